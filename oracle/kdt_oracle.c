@@ -1,0 +1,841 @@
+/*
+ * kdt_oracle.c -- plain, slow, single-threaded CPU oracle for the k-d tree
+ * hot path (test infrastructure only).
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  It shares no code with the HIP path and must never
+ * be called by it.
+ *
+ * What it computes, and where each piece comes from:
+ *   - squared Euclidean distance (Eq. 1 with p = 2) in IEEE float32, summed
+ *     left to right over the axes, every operation rounded on its own
+ *     (build with -ffp-contract=off so that no multiply-add is fused);
+ *   - brute-force kNN, ball counts/lists and friends-of-friends groups: the
+ *     plain definitions, O(N^2);
+ *   - the sliding-midpoint k-d tree of Sec. 2.1 (Algorithm 1, serial);
+ *   - best-first kNN over that tree with a node min-heap and a candidate
+ *     max-heap (Algorithm 2), results sorted at the end (Sec. 2.3);
+ *   - recursive ball query with whole-node acceptance (Algorithm 3);
+ *   - friends-of-friends grouping by union-find over ball queries (Sec. 4.1);
+ *   - adaptive SPH particle-to-mesh deposit with the M4 cubic spline and
+ *     per-particle normalisation (Sec. 4.2), and its adjoint, in float64.
+ *
+ * Readings of the paper taken here (it is silent or self-contradictory):
+ *   - ties in squared distance are broken by the lower point index, so a kNN
+ *     result is the k smallest (d2, index) keys in ascending order; rows are
+ *     padded with (index -1, d2 +inf) when k exceeds n; a query that is itself
+ *     a data point finds itself at distance 0;
+ *   - the ball is closed: a point at squared distance exactly fl(r*r) is in;
+ *     Algorithm 3 takes all points of a node whose farthest corner is inside
+ *     and then stops descending that node (the listing omits the return);
+ *   - Algorithm 2 reads the worst candidate before k candidates exist: the
+ *     candidate heap starts filled with (+inf, INT32_MAX) sentinels;
+ *   - a node is a leaf when it holds at most N_leaf points (Algorithm 1 uses
+ *     "<=");  the split axis is the longest side of the node's tight point
+ *     bounding box (ties: lowest axis); a node whose points all coincide is a
+ *     leaf whatever its size;  when the midpoint leaves one side empty, the
+ *     single extreme point nearest the plane (ties: lowest original index) is
+ *     moved to the empty side;
+ *   - friends-of-friends links i != j when d2(i, j) <= fl(l*l); the group
+ *     label is the smallest point index of the connected component;
+ *   - deposit: q = 2 r / H_i with H_i = max(h_i, cell), M4 profile
+ *     w(q) = 1 - 1.5 q^2 + 0.75 q^3 (q < 1), 0.25 (2 - q)^3 (1 <= q < 2),
+ *     0 beyond; cells outside the grid are dropped and the weights of each
+ *     particle are normalised over the in-grid cells, so mass is conserved;
+ *     cell (i, j, k) is centred at lo + (i + 1/2, j + 1/2, k + 1/2) * cell and
+ *     the grid is stored x slowest, z fastest.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+
+/* ------------------------------------------------------------------------ */
+/* Distances (Eq. 1, p = 2), float32, fixed order, no contraction.          */
+/* ------------------------------------------------------------------------ */
+
+static float sq_dist(const float *p, const float *q, int d)
+{
+    float s = 0.0f;
+    for (int a = 0; a < d; ++a) {
+        float t = p[a] - q[a];
+        float t2 = t * t;
+        s = s + t2;
+    }
+    return s;
+}
+
+/* Smallest squared distance from q to any point of the box [lo, hi]. */
+static float box_min_dist(const float *q, const float *lo, const float *hi, int d)
+{
+    float s = 0.0f;
+    for (int a = 0; a < d; ++a) {
+        float t = 0.0f;
+        if (q[a] < lo[a]) t = lo[a] - q[a];
+        else if (q[a] > hi[a]) t = q[a] - hi[a];
+        float t2 = t * t;
+        s = s + t2;
+    }
+    return s;
+}
+
+/* Largest squared distance from q to any point of the box [lo, hi]. */
+static float box_max_dist(const float *q, const float *lo, const float *hi, int d)
+{
+    float s = 0.0f;
+    for (int a = 0; a < d; ++a) {
+        float t1 = fabsf(q[a] - lo[a]);
+        float t2 = fabsf(q[a] - hi[a]);
+        float t = t1 > t2 ? t1 : t2;
+        float tt = t * t;
+        s = s + tt;
+    }
+    return s;
+}
+
+/* (d2, index) keys, compared lexicographically. */
+typedef struct {
+    float d2;
+    int32_t idx;
+} key_t;
+
+static int key_less(key_t a, key_t b)
+{
+    return a.d2 < b.d2 || (a.d2 == b.d2 && a.idx < b.idx);
+}
+
+static int key_cmp(const void *pa, const void *pb)
+{
+    key_t a = *(const key_t *)pa, b = *(const key_t *)pb;
+    if (key_less(a, b)) return -1;
+    if (key_less(b, a)) return 1;
+    return 0;
+}
+
+static int idx_cmp(const void *pa, const void *pb)
+{
+    int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
+    return (a > b) - (a < b);
+}
+
+static void write_knn_row(const key_t *sorted, int k, int32_t *oi, float *od)
+{
+    for (int j = 0; j < k; ++j) {
+        if (sorted[j].idx == INT32_MAX) {
+            oi[j] = -1;
+            od[j] = INFINITY;
+        } else {
+            oi[j] = sorted[j].idx;
+            od[j] = sorted[j].d2;
+        }
+    }
+}
+
+float orc_sq_dist(const float *p, const float *q, int d) { return sq_dist(p, q, d); }
+
+/* ------------------------------------------------------------------------ */
+/* Brute force: the plain definitions.                                      */
+/* ------------------------------------------------------------------------ */
+
+/* k smallest (d2, idx) keys over all n points, ascending. */
+int orc_knn_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq,
+                  int k, int32_t *out_idx, float *out_d2)
+{
+    if (!pts || !q || !out_idx || !out_d2 || n < 0 || nq < 0 || k < 1 || d < 1)
+        return ORC_EINVAL;
+    key_t *best = (key_t *)malloc(sizeof(key_t) * (size_t)k);
+    if (!best) return ORC_ENOMEM;
+    for (int64_t t = 0; t < nq; ++t) {
+        const float *qt = q + t * d;
+        for (int j = 0; j < k; ++j) {
+            best[j].d2 = INFINITY;
+            best[j].idx = INT32_MAX;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            key_t c = {sq_dist(pts + i * d, qt, d), (int32_t)i};
+            if (!key_less(c, best[k - 1])) continue;
+            int j = k - 1;
+            while (j > 0 && key_less(c, best[j - 1])) {
+                best[j] = best[j - 1];
+                --j;
+            }
+            best[j] = c;
+        }
+        write_knn_row(best, k, out_idx + t * k, out_d2 + t * k);
+    }
+    free(best);
+    return ORC_OK;
+}
+
+/* Number of points with d2 <= fl(r*r), and optionally their indices (ascending). */
+int orc_range_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq,
+                    float r, int64_t *out_count, int64_t *offsets, int32_t *out_idx)
+{
+    if (!pts || !q || !out_count || n < 0 || nq < 0 || d < 1 || !(r >= 0.0f))
+        return ORC_EINVAL;
+    float r2 = r * r;
+    int64_t pos = 0;
+    for (int64_t t = 0; t < nq; ++t) {
+        const float *qt = q + t * d;
+        int64_t c = 0;
+        if (offsets) offsets[t] = pos;
+        for (int64_t i = 0; i < n; ++i) {
+            if (sq_dist(pts + i * d, qt, d) <= r2) {
+                if (out_idx) out_idx[pos] = (int32_t)i;
+                ++pos;
+                ++c;
+            }
+        }
+        out_count[t] = c;
+    }
+    if (offsets) offsets[nq] = pos;
+    return ORC_OK;
+}
+
+/* Friends-of-friends by breadth-first search over all pairs. */
+int orc_fof_brute(const float *pts, int64_t n, int d, float l, int32_t *labels)
+{
+    if (!pts || !labels || n < 0 || d < 1 || !(l >= 0.0f)) return ORC_EINVAL;
+    float l2 = l * l;
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) labels[i] = -1;
+    for (int64_t s = 0; s < n; ++s) {
+        if (labels[s] >= 0) continue;
+        /* every smaller index is already labelled, so s is the component minimum */
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        labels[s] = (int32_t)s;
+        while (head < tail) {
+            int64_t u = queue[head++];
+            for (int64_t v = 0; v < n; ++v) {
+                if (labels[v] >= 0 || v == u) continue;
+                if (sq_dist(pts + u * d, pts + v * d, d) <= l2) {
+                    labels[v] = (int32_t)s;
+                    queue[tail++] = v;
+                }
+            }
+        }
+    }
+    free(queue);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sliding-midpoint k-d tree (Sec. 2.1, Algorithm 1).                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct orc_tree {
+    int d;
+    int leaf_size;
+    int64_t n;
+    float *pts;      /* tree-ordered copy of the points, [n][d] */
+    int32_t *idx;    /* original index of each copied point */
+    int64_t n_nodes, cap;
+    int64_t *begin, *end;   /* point range [begin, end) of each node */
+    int64_t *left, *right;  /* children, -1 for a leaf */
+    int32_t *axis;          /* split axis, -1 for a leaf */
+    float *split;           /* split value (the plane after any slide) */
+    float *lo, *hi;         /* tight bounding box, [n_nodes][d] each */
+    int32_t depth;          /* number of edges on the longest root-leaf path */
+} orc_tree;
+
+static int tree_grow(orc_tree *t)
+{
+    int64_t c = t->cap ? 2 * t->cap : 64;
+    int d = t->d;
+#define GROW(ptr, type, per)                                                    \
+    do {                                                                        \
+        type *p_ = (type *)realloc(t->ptr, sizeof(type) * (size_t)(c * (per))); \
+        if (!p_) return ORC_ENOMEM;                                             \
+        t->ptr = p_;                                                            \
+    } while (0)
+    GROW(begin, int64_t, 1);
+    GROW(end, int64_t, 1);
+    GROW(left, int64_t, 1);
+    GROW(right, int64_t, 1);
+    GROW(axis, int32_t, 1);
+    GROW(split, float, 1);
+    GROW(lo, float, d);
+    GROW(hi, float, d);
+#undef GROW
+    t->cap = c;
+    return ORC_OK;
+}
+
+static int64_t tree_new_node(orc_tree *t, int64_t b, int64_t e)
+{
+    if (t->n_nodes == t->cap && tree_grow(t) != ORC_OK) return -1;
+    int64_t id = t->n_nodes++;
+    int d = t->d;
+    t->begin[id] = b;
+    t->end[id] = e;
+    t->left[id] = t->right[id] = -1;
+    t->axis[id] = -1;
+    t->split[id] = 0.0f;
+    float *lo = t->lo + id * d, *hi = t->hi + id * d;
+    for (int a = 0; a < d; ++a) {
+        lo[a] = INFINITY;
+        hi[a] = -INFINITY;
+    }
+    for (int64_t i = b; i < e; ++i) {
+        const float *p = t->pts + i * d;
+        for (int a = 0; a < d; ++a) {
+            if (p[a] < lo[a]) lo[a] = p[a];
+            if (p[a] > hi[a]) hi[a] = p[a];
+        }
+    }
+    return id;
+}
+
+void orc_tree_free(orc_tree *t)
+{
+    if (!t) return;
+    free(t->pts);
+    free(t->idx);
+    free(t->begin);
+    free(t->end);
+    free(t->left);
+    free(t->right);
+    free(t->axis);
+    free(t->split);
+    free(t->lo);
+    free(t->hi);
+    free(t);
+}
+
+/* Moves the points of [b, e) whose flag is set to the front, keeping order. */
+static int stable_split(orc_tree *t, int64_t b, int64_t e, const unsigned char *go_left,
+                        float *tmp_p, int32_t *tmp_i)
+{
+    int d = t->d;
+    int64_t w = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int64_t i = b; i < e; ++i)
+            if ((go_left[i - b] != 0) == (pass == 0)) {
+                memcpy(tmp_p + w * d, t->pts + i * d, sizeof(float) * (size_t)d);
+                tmp_i[w] = t->idx[i];
+                ++w;
+            }
+    memcpy(t->pts + b * d, tmp_p, sizeof(float) * (size_t)((e - b) * d));
+    memcpy(t->idx + b, tmp_i, sizeof(int32_t) * (size_t)(e - b));
+    return ORC_OK;
+}
+
+int orc_tree_build(const float *pts, int64_t n, int d, int leaf_size, orc_tree **out)
+{
+    if (!pts || !out || n < 0 || d < 1 || leaf_size < 1) return ORC_EINVAL;
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!isfinite(pts[i])) return ORC_EINVAL;
+    orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
+    if (!t) return ORC_ENOMEM;
+    t->d = d;
+    t->leaf_size = leaf_size;
+    t->n = n;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    t->pts = (float *)malloc(sizeof(float) * nn * (size_t)d);
+    t->idx = (int32_t *)malloc(sizeof(int32_t) * nn);
+    float *tmp_p = (float *)malloc(sizeof(float) * nn * (size_t)d);
+    int32_t *tmp_i = (int32_t *)malloc(sizeof(int32_t) * nn);
+    unsigned char *flag = (unsigned char *)malloc(nn);
+    int64_t *stack = (int64_t *)malloc(sizeof(int64_t) * 2 * nn + 16);
+    int32_t *level = (int32_t *)malloc(sizeof(int32_t) * 2 * nn + 16);
+    if (!t->pts || !t->idx || !tmp_p || !tmp_i || !flag || !stack || !level) goto nomem;
+    memcpy(t->pts, pts, sizeof(float) * (size_t)(n * d));
+    for (int64_t i = 0; i < n; ++i) t->idx[i] = (int32_t)i;
+
+    if (tree_new_node(t, 0, n) < 0) goto nomem;
+    int64_t sp = 0;
+    stack[sp] = 0;
+    level[sp] = 0;
+    ++sp;
+    while (sp > 0) {
+        --sp;
+        int64_t id = stack[sp];
+        int32_t lev = level[sp];
+        if (lev > t->depth) t->depth = lev;
+        int64_t b = t->begin[id], e = t->end[id], m = e - b;
+        if (m <= leaf_size) continue;                      /* leaf (Alg. 1) */
+        const float *lo = t->lo + id * d, *hi = t->hi + id * d;
+        int ax = 0;
+        float ext = hi[0] - lo[0];
+        for (int a = 1; a < d; ++a)
+            if (hi[a] - lo[a] > ext) {
+                ext = hi[a] - lo[a];
+                ax = a;
+            }
+        if (!(ext > 0.0f)) continue;                       /* all points coincide */
+        float split = lo[ax] + (hi[ax] - lo[ax]) * 0.5f;   /* box midpoint */
+        int64_t n_left = 0;
+        for (int64_t i = b; i < e; ++i) {
+            flag[i - b] = t->pts[i * d + ax] < split;
+            n_left += flag[i - b];
+        }
+        if (n_left == 0 || n_left == m) {
+            /* slide: the extreme point nearest the plane moves to the empty side */
+            int want_min = (n_left == 0);
+            int64_t pick = -1;
+            for (int64_t i = b; i < e; ++i) {
+                float v = t->pts[i * d + ax];
+                if (pick < 0) { pick = i; continue; }
+                float pv = t->pts[pick * d + ax];
+                int better = want_min ? (v < pv) : (v > pv);
+                if (better || (v == pv && t->idx[i] < t->idx[pick])) pick = i;
+            }
+            split = t->pts[pick * d + ax];
+            for (int64_t i = b; i < e; ++i) flag[i - b] = want_min ? (i == pick) : (i != pick);
+            n_left = want_min ? 1 : m - 1;
+        }
+        stable_split(t, b, e, flag, tmp_p, tmp_i);
+        int64_t l = tree_new_node(t, b, b + n_left);
+        if (l < 0) goto nomem;
+        int64_t r = tree_new_node(t, b + n_left, e);
+        if (r < 0) goto nomem;
+        t->left[id] = l;
+        t->right[id] = r;
+        t->axis[id] = ax;
+        t->split[id] = split;
+        stack[sp] = r;
+        level[sp] = lev + 1;
+        ++sp;
+        stack[sp] = l;
+        level[sp] = lev + 1;
+        ++sp;
+    }
+    free(tmp_p);
+    free(tmp_i);
+    free(flag);
+    free(stack);
+    free(level);
+    *out = t;
+    return ORC_OK;
+nomem:
+    free(tmp_p);
+    free(tmp_i);
+    free(flag);
+    free(stack);
+    free(level);
+    orc_tree_free(t);
+    return ORC_ENOMEM;
+}
+
+/* Read-only views used by the invariant tests. */
+int64_t orc_tree_n_nodes(const orc_tree *t) { return t->n_nodes; }
+int32_t orc_tree_depth(const orc_tree *t) { return t->depth; }
+
+int orc_tree_export(const orc_tree *t, float *pts, int32_t *idx, int64_t *begin, int64_t *end,
+                    int64_t *left, int64_t *right, int32_t *axis, float *split, float *lo,
+                    float *hi)
+{
+    int64_t m = t->n_nodes;
+    int d = t->d;
+    if (pts) memcpy(pts, t->pts, sizeof(float) * (size_t)(t->n * d));
+    if (idx) memcpy(idx, t->idx, sizeof(int32_t) * (size_t)t->n);
+    if (begin) memcpy(begin, t->begin, sizeof(int64_t) * (size_t)m);
+    if (end) memcpy(end, t->end, sizeof(int64_t) * (size_t)m);
+    if (left) memcpy(left, t->left, sizeof(int64_t) * (size_t)m);
+    if (right) memcpy(right, t->right, sizeof(int64_t) * (size_t)m);
+    if (axis) memcpy(axis, t->axis, sizeof(int32_t) * (size_t)m);
+    if (split) memcpy(split, t->split, sizeof(float) * (size_t)m);
+    if (lo) memcpy(lo, t->lo, sizeof(float) * (size_t)(m * d));
+    if (hi) memcpy(hi, t->hi, sizeof(float) * (size_t)(m * d));
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* kNN query (Algorithm 2): best-first over a node min-heap, candidates in a */
+/* max-heap, results sorted at the end.                                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    float dist;
+    int64_t node;
+} qitem_t;
+
+static void qheap_push(qitem_t *h, int64_t *nh, qitem_t it)
+{
+    int64_t i = (*nh)++;
+    h[i] = it;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].dist <= h[i].dist) break;
+        qitem_t s = h[p];
+        h[p] = h[i];
+        h[i] = s;
+        i = p;
+    }
+}
+
+static qitem_t qheap_pop(qitem_t *h, int64_t *nh)
+{
+    qitem_t top = h[0];
+    h[0] = h[--(*nh)];
+    int64_t i = 0, m = *nh;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, s = i;
+        if (l < m && h[l].dist < h[s].dist) s = l;
+        if (r < m && h[r].dist < h[s].dist) s = r;
+        if (s == i) break;
+        qitem_t x = h[s];
+        h[s] = h[i];
+        h[i] = x;
+        i = s;
+    }
+    return top;
+}
+
+/* replace the largest key of a max-heap and restore the heap property */
+static void kheap_replace_top(key_t *h, int k, key_t c)
+{
+    h[0] = c;
+    int i = 0;
+    for (;;) {
+        int l = 2 * i + 1, r = l + 1, s = i;
+        if (l < k && key_less(h[s], h[l])) s = l;
+        if (r < k && key_less(h[s], h[r])) s = r;
+        if (s == i) break;
+        key_t x = h[s];
+        h[s] = h[i];
+        h[i] = x;
+        i = s;
+    }
+}
+
+int orc_knn_tree(const orc_tree *t, const float *q, int64_t nq, int k, int32_t *out_idx,
+                 float *out_d2)
+{
+    if (!t || !q || !out_idx || !out_d2 || nq < 0 || k < 1) return ORC_EINVAL;
+    int d = t->d;
+    key_t *K = (key_t *)malloc(sizeof(key_t) * (size_t)k);
+    qitem_t *Q = (qitem_t *)malloc(sizeof(qitem_t) * (size_t)(t->n_nodes + 1));
+    if (!K || !Q) {
+        free(K);
+        free(Q);
+        return ORC_ENOMEM;
+    }
+    for (int64_t s = 0; s < nq; ++s) {
+        const float *p = q + s * d;
+        for (int j = 0; j < k; ++j) {
+            K[j].d2 = INFINITY;
+            K[j].idx = INT32_MAX;
+        }
+        int64_t nh = 0;
+        qitem_t root = {box_min_dist(p, t->lo, t->hi, d), 0};
+        qheap_push(Q, &nh, root);
+        while (nh > 0) {
+            qitem_t it = qheap_pop(Q, &nh);
+            if (it.dist > K[0].d2) continue;
+            int64_t id = it.node;
+            if (t->left[id] < 0) {
+                for (int64_t i = t->begin[id]; i < t->end[id]; ++i) {
+                    key_t c = {sq_dist(t->pts + i * d, p, d), t->idx[i]};
+                    if (key_less(c, K[0])) kheap_replace_top(K, k, c);
+                }
+            } else {
+                int64_t ch[2] = {t->left[id], t->right[id]};
+                for (int c = 0; c < 2; ++c) {
+                    float md = box_min_dist(p, t->lo + ch[c] * d, t->hi + ch[c] * d, d);
+                    if (md <= K[0].d2) {
+                        qitem_t ci = {md, ch[c]};
+                        qheap_push(Q, &nh, ci);
+                    }
+                }
+            }
+        }
+        qsort(K, (size_t)k, sizeof(key_t), key_cmp);
+        write_knn_row(K, k, out_idx + s * k, out_d2 + s * k);
+    }
+    free(K);
+    free(Q);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ball query (Algorithm 3).                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t *buf;
+    int64_t n, cap;
+} ivec_t;
+
+static int ivec_push(ivec_t *v, int32_t x)
+{
+    if (v->n == v->cap) {
+        int64_t c = v->cap ? 2 * v->cap : 256;
+        int32_t *b = (int32_t *)realloc(v->buf, sizeof(int32_t) * (size_t)c);
+        if (!b) return ORC_ENOMEM;
+        v->buf = b;
+        v->cap = c;
+    }
+    v->buf[v->n++] = x;
+    return ORC_OK;
+}
+
+/* Collects the original indices of all points with d2 <= r2 (unsorted). */
+static int ball_collect(const orc_tree *t, int64_t id, const float *p, float r2, ivec_t *out)
+{
+    int d = t->d;
+    const float *lo = t->lo + id * d, *hi = t->hi + id * d;
+    if (box_min_dist(p, lo, hi, d) > r2) return ORC_OK;
+    if (box_max_dist(p, lo, hi, d) <= r2) {
+        for (int64_t i = t->begin[id]; i < t->end[id]; ++i)
+            if (ivec_push(out, t->idx[i]) != ORC_OK) return ORC_ENOMEM;
+        return ORC_OK;
+    }
+    if (t->left[id] < 0) {
+        for (int64_t i = t->begin[id]; i < t->end[id]; ++i)
+            if (sq_dist(t->pts + i * d, p, d) <= r2)
+                if (ivec_push(out, t->idx[i]) != ORC_OK) return ORC_ENOMEM;
+        return ORC_OK;
+    }
+    if (ball_collect(t, t->left[id], p, r2, out) != ORC_OK) return ORC_ENOMEM;
+    return ball_collect(t, t->right[id], p, r2, out);
+}
+
+/*
+ * Ball query for nq points.  out_count[s] is the number of points within r.
+ * When out_idx is given, offsets[nq+1] must be given too and the lists are
+ * written in ascending index order; capacity bounds out_idx.
+ */
+int orc_range_tree(const orc_tree *t, const float *q, int64_t nq, float r, int64_t *out_count,
+                   int64_t *offsets, int32_t *out_idx, int64_t capacity)
+{
+    if (!t || !q || !out_count || nq < 0 || !(r >= 0.0f)) return ORC_EINVAL;
+    float r2 = r * r;
+    ivec_t v = {0, 0, 0};
+    int64_t pos = 0;
+    for (int64_t s = 0; s < nq; ++s) {
+        v.n = 0;
+        if (t->n > 0 && ball_collect(t, 0, q + s * t->d, r2, &v) != ORC_OK) {
+            free(v.buf);
+            return ORC_ENOMEM;
+        }
+        out_count[s] = v.n;
+        if (offsets) offsets[s] = pos;
+        if (out_idx) {
+            if (pos + v.n > capacity) {
+                free(v.buf);
+                return ORC_EINVAL;
+            }
+            qsort(v.buf, (size_t)v.n, sizeof(int32_t), idx_cmp);
+            memcpy(out_idx + pos, v.buf, sizeof(int32_t) * (size_t)v.n);
+        }
+        pos += v.n;
+    }
+    if (offsets) offsets[nq] = pos;
+    free(v.buf);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Friends-of-friends (Sec. 4.1): union-find over ball queries.             */
+/* ------------------------------------------------------------------------ */
+
+static int32_t uf_find(int32_t *parent, int32_t x)
+{
+    while (parent[x] != x) x = parent[x];
+    return x;
+}
+
+int orc_fof_tree(const orc_tree *t, const float *pts, float l, int32_t *labels)
+{
+    if (!t || !pts || !labels || !(l >= 0.0f)) return ORC_EINVAL;
+    int64_t n = t->n;
+    int d = t->d;
+    float l2 = l * l;
+    for (int64_t i = 0; i < n; ++i) labels[i] = (int32_t)i;
+    ivec_t v = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        v.n = 0;
+        if (ball_collect(t, 0, pts + i * d, l2, &v) != ORC_OK) {
+            free(v.buf);
+            return ORC_ENOMEM;
+        }
+        for (int64_t j = 0; j < v.n; ++j) {
+            /* union: the larger root is hung under the smaller one, so every
+               root is the smallest index of its set */
+            int32_t a = uf_find(labels, (int32_t)i), b = uf_find(labels, v.buf[j]);
+            if (a < b) labels[b] = a;
+            else if (b < a) labels[a] = b;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) labels[i] = uf_find(labels, (int32_t)i);
+    free(v.buf);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive SPH particle-to-mesh deposit (Sec. 4.2), float64.               */
+/* ------------------------------------------------------------------------ */
+
+/* M4 cubic spline profile on q in [0, 2] and its derivative. */
+double orc_m4_w(double q)
+{
+    if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+    if (q < 2.0) {
+        double u = 2.0 - q;
+        return 0.25 * u * u * u;
+    }
+    return 0.0;
+}
+
+double orc_m4_dw(double q)
+{
+    if (q < 1.0) return -3.0 * q + 2.25 * q * q;
+    if (q < 2.0) {
+        double u = 2.0 - q;
+        return -0.75 * u * u;
+    }
+    return 0.0;
+}
+
+typedef struct {
+    double lo[3];
+    double cell;
+    int32_t n[3];
+} orc_grid;
+
+static int grid_ok(const orc_grid *g)
+{
+    return g && g->cell > 0.0 && g->n[0] > 0 && g->n[1] > 0 && g->n[2] > 0;
+}
+
+static int inside_grid(const orc_grid *g, const double *x)
+{
+    for (int a = 0; a < 3; ++a) {
+        double top = g->lo[a] + g->cell * g->n[a];
+        if (!(x[a] >= g->lo[a] && x[a] < top)) return 0;
+    }
+    return 1;
+}
+
+/* Cell index range [c0, c1] per axis that can hold centres within H of x.
+   brute != 0 returns the whole grid instead. */
+static void cell_box(const orc_grid *g, const double *x, double H, int brute, int32_t *c0,
+                     int32_t *c1)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (brute) {
+            c0[a] = 0;
+            c1[a] = g->n[a] - 1;
+            continue;
+        }
+        double f0 = (x[a] - H - g->lo[a]) / g->cell - 0.5;
+        double f1 = (x[a] + H - g->lo[a]) / g->cell - 0.5;
+        int64_t i0 = (int64_t)floor(f0) - 1, i1 = (int64_t)ceil(f1) + 1;
+        if (i0 < 0) i0 = 0;
+        if (i1 > g->n[a] - 1) i1 = g->n[a] - 1;
+        c0[a] = (int32_t)i0;
+        c1[a] = (int32_t)i1;
+    }
+}
+
+static double cell_centre(const orc_grid *g, int a, int32_t c)
+{
+    return g->lo[a] + ((double)c + 0.5) * g->cell;
+}
+
+/*
+ * rho[c] = sum_i m_i w(2 |x_i - x_c| / H_i) / S_i,  S_i = sum over in-grid c.
+ * x is [n][3], rho has n[0]*n[1]*n[2] entries and is overwritten.
+ */
+static int p2m_forward(const double *x, const double *m, const double *h, int64_t n,
+                       const orc_grid *g, double *rho, int brute)
+{
+    if (!x || !m || !h || !rho || n < 0 || !grid_ok(g)) return ORC_EINVAL;
+    int64_t ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    for (int64_t c = 0; c < ncell; ++c) rho[c] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *xi = x + 3 * i;
+        if (!inside_grid(g, xi) || !(h[i] >= 0.0)) return ORC_EINVAL;
+        double H = h[i] > g->cell ? h[i] : g->cell;
+        int32_t c0[3], c1[3];
+        cell_box(g, xi, H, brute, c0, c1);
+        double S = 0.0;
+        for (int32_t a = c0[0]; a <= c1[0]; ++a)
+            for (int32_t b = c0[1]; b <= c1[1]; ++b)
+                for (int32_t c = c0[2]; c <= c1[2]; ++c) {
+                    double dx = xi[0] - cell_centre(g, 0, a);
+                    double dy = xi[1] - cell_centre(g, 1, b);
+                    double dz = xi[2] - cell_centre(g, 2, c);
+                    double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    S += orc_m4_w(2.0 * r / H);
+                }
+        if (!(S > 0.0)) return ORC_EINVAL;
+        for (int32_t a = c0[0]; a <= c1[0]; ++a)
+            for (int32_t b = c0[1]; b <= c1[1]; ++b)
+                for (int32_t c = c0[2]; c <= c1[2]; ++c) {
+                    double dx = xi[0] - cell_centre(g, 0, a);
+                    double dy = xi[1] - cell_centre(g, 1, b);
+                    double dz = xi[2] - cell_centre(g, 2, c);
+                    double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    double w = orc_m4_w(2.0 * r / H);
+                    if (w != 0.0)
+                        rho[((int64_t)a * g->n[1] + b) * g->n[2] + c] += m[i] * w / S;
+                }
+    }
+    return ORC_OK;
+}
+
+int orc_p2m(const double *x, const double *m, const double *h, int64_t n, const orc_grid *g,
+            double *rho)
+{
+    return p2m_forward(x, m, h, n, g, rho, 0);
+}
+
+int orc_p2m_brute(const double *x, const double *m, const double *h, int64_t n,
+                  const orc_grid *g, double *rho)
+{
+    return p2m_forward(x, m, h, n, g, rho, 1);
+}
+
+/*
+ * Adjoint of orc_p2m for L = sum_c g_c rho_c with h held fixed:
+ *   dL/dm_i = A_i / S_i,
+ *   dL/dx_i = (m_i / S_i) (C_i - (A_i / S_i) B_i),
+ * with S = sum w, A = sum g w, B = sum grad w, C = sum g grad w over the
+ * particle's in-grid cells and grad w = w'(q) (2 / H) (x_i - x_c) / r.
+ */
+int orc_p2m_backward(const double *x, const double *m, const double *h, int64_t n,
+                     const orc_grid *g, const double *gg, double *dm, double *dx)
+{
+    if (!x || !m || !h || !gg || n < 0 || !grid_ok(g)) return ORC_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *xi = x + 3 * i;
+        if (!inside_grid(g, xi) || !(h[i] >= 0.0)) return ORC_EINVAL;
+        double H = h[i] > g->cell ? h[i] : g->cell;
+        int32_t c0[3], c1[3];
+        cell_box(g, xi, H, 0, c0, c1);
+        double S = 0.0, A = 0.0, B[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+        for (int32_t a = c0[0]; a <= c1[0]; ++a)
+            for (int32_t b = c0[1]; b <= c1[1]; ++b)
+                for (int32_t c = c0[2]; c <= c1[2]; ++c) {
+                    double v[3] = {xi[0] - cell_centre(g, 0, a), xi[1] - cell_centre(g, 1, b),
+                                   xi[2] - cell_centre(g, 2, c)};
+                    double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                    double q = 2.0 * r / H;
+                    double w = orc_m4_w(q);
+                    double gc = gg[((int64_t)a * g->n[1] + b) * g->n[2] + c];
+                    S += w;
+                    A += gc * w;
+                    if (r > 0.0) {
+                        double f = orc_m4_dw(q) * (2.0 / H) / r;
+                        for (int e = 0; e < 3; ++e) {
+                            B[e] += f * v[e];
+                            C[e] += gc * f * v[e];
+                        }
+                    }
+                }
+        if (!(S > 0.0)) return ORC_EINVAL;
+        double G = A / S;
+        if (dm) dm[i] = G;
+        if (dx)
+            for (int e = 0; e < 3; ++e) dx[3 * i + e] = (m[i] / S) * (C[e] - G * B[e]);
+    }
+    return ORC_OK;
+}
