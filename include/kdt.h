@@ -1,0 +1,261 @@
+/*
+ * kdt.h -- C ABI of the MI355X (gfx950) k-d tree library.
+ *
+ * The library builds k-d trees on the GPU and answers batched k-nearest-
+ * neighbour and fixed-radius (ball) queries over them, then uses those queries
+ * for friends-of-friends grouping and for an adaptive SPH particle-to-mesh
+ * deposit with its adjoint.  The method is the one of "cosmokdtree: a flexible
+ * OpenMP-parallelized k-d tree for computational astrophysics applications"
+ * (tree construction Sec. 2.1 and Algorithm 1, queries Sec. 2.3 and
+ * Algorithms 2-3, applications Sec. 4.1-4.2); the GPU design differs from the
+ * paper's CPU one (balanced median splits, level-synchronous build).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers on the current HIP device; the
+ *     caller owns them.  Pointers named h_* or documented as "host" are host
+ *     memory.  Points are float32 rows, row-major [n][d].
+ *   - Every call is asynchronous on `stream` unless it documents a wait.
+ *     A call never frees or reallocates caller memory.
+ *   - Nothing throws.  Each call returns a kdt_status; on anything but KDT_OK
+ *     the calling thread's kdt_last_error() describes the failure and no
+ *     output may be relied on.
+ *   - Indices in results are int32 and refer to the caller's input order.
+ *   - Distances are squared Euclidean distances (Eq. 1 with p = 2) in float32,
+ *     summed over axes 0..d-1 left to right with every operation rounded on
+ *     its own (no fused multiply-add).  Equal distances are ordered by the
+ *     lower index.  These rules make kNN, ball and grouping results exact and
+ *     reproducible, independent of the tree's shape.
+ */
+#ifndef KDT_H
+#define KDT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KDT_OK = 0,
+    KDT_EINVAL = 1,       /* bad argument, or non-finite input coordinates */
+    KDT_EUNSUPPORTED = 2, /* dimension or k outside what the kernels are built for */
+    KDT_ENOMEM = 3,       /* a device or host allocation failed */
+    KDT_ECAPACITY = 4,    /* an output buffer is too small; see `required` */
+    KDT_EDEVICE = 5       /* a HIP runtime call failed */
+} kdt_status;
+
+/* Supported dimensions and the largest k of one kNN call. */
+#define KDT_MAX_K 64
+/* d must be one of 2, 3, 4, 8, 16. */
+
+typedef struct kdt_tree kdt_tree;             /* device-resident tree, library-owned */
+typedef struct kdt_batch_plan kdt_batch_plan; /* many trees, fixed shapes, library-owned */
+
+typedef struct {
+    int32_t leaf_size;    /* N_leaf: a node with <= leaf_size points is a leaf
+                             (Sec. 2.1 step 4).  0 selects the default, 32. */
+    int32_t check_finite; /* 1 (default when opts is NULL): kdt_build waits for its
+                             first pass and rejects NaN/Inf coordinates with
+                             KDT_EINVAL.  0: no wait, no check. */
+} kdt_build_opts;
+
+typedef struct {
+    int32_t sort_queries; /* 1: reorder external queries along the tree before the
+                             traversal (more coherent waves); 0: input order.
+                             Results are identical either way. */
+    int32_t reserved;
+} kdt_query_opts;
+
+/* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side
+   `cell`, cell (i,j,k) centred at lo + (i+1/2, j+1/2, k+1/2)*cell, stored with
+   x slowest and z fastest. */
+typedef struct {
+    float lo[3];
+    float cell;
+    int32_t n[3];
+} kdt_grid;
+
+/* Shape of a built tree, for diagnostics and the structural tests. */
+typedef struct {
+    int64_t n;          /* points */
+    int32_t d;          /* dimension */
+    int32_t leaf_size;  /* N_leaf used */
+    int32_t levels;     /* L: splits on every root-to-leaf path; leaves = 2^L */
+    int32_t stride;     /* floats per point record in tree order */
+    int64_t n_nodes;    /* 2^(L+1) - 1 */
+} kdt_tree_info;
+
+/*
+ * kdt_build -- build a k-d tree over n points (Sec. 2.1, Algorithm 1).
+ *
+ * d_pts  [n][d] float32, device.  Only read; it may be freed or overwritten once
+ *        the work queued on `stream` by this call has run: the tree keeps its own
+ *        copy of positions and indices (the tree is self-contained, Sec. 3.4).
+ * n      1 <= n <= 2^31 - 1.     d in {2, 3, 4, 8, 16}.
+ * opts   may be NULL (leaf_size 32, finiteness check on).
+ * out    receives the tree handle; release it with kdt_free.
+ *
+ * Splits are balanced: node (l, j) owns points [floor(j n / 2^l),
+ * floor((j+1) n / 2^l)) of the tree order and is split along the longest side
+ * of its tight bounding box (lowest axis on ties) at the median, so that the
+ * depth is L = ceil(log2(ceil(n / leaf_size))) for every leaf.  The paper's
+ * sliding-midpoint rule (Sec. 2.1 step 1) is not used: the median rule gives a
+ * depth known from n alone, which fixes the launch schedule.  Query results do
+ * not depend on the split rule.
+ *
+ * Errors: KDT_EINVAL (NULL pointer, n out of range, non-finite coordinate when
+ * checked), KDT_EUNSUPPORTED (d), KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_build(const float *d_pts, int64_t n, int32_t d, const kdt_build_opts *opts,
+                     hipStream_t stream, kdt_tree **out);
+
+/* Releases a tree.  Waits for the tree's build stream; the caller must have
+   finished (or ordered before this call) every query that uses the tree. */
+kdt_status kdt_free(kdt_tree *tree);
+
+/* Fills *info (host). */
+kdt_status kdt_tree_get_info(const kdt_tree *tree, kdt_tree_info *info);
+
+/*
+ * Copies the tree to host memory for inspection (waits on `stream`).
+ * h_pts [n][d] tree-ordered positions, h_perm [n] original index of each,
+ * h_lo / h_hi [n_nodes][d] tight bounding box of each node in heap order
+ * (node (l, j) at 2^l - 1 + j), h_axis [n_nodes] split axis (-1 for leaves),
+ * h_split [n_nodes] split coordinate.  Any pointer may be NULL.
+ */
+kdt_status kdt_tree_export(const kdt_tree *tree, float *h_pts, int32_t *h_perm, float *h_lo,
+                           float *h_hi, int32_t *h_axis, float *h_split, hipStream_t stream);
+
+/*
+ * kdt_knn -- k nearest neighbours of nq query points (Sec. 2.3, Algorithm 2).
+ *
+ * d_q    [nq][d] float32 queries, or NULL to query every point of the tree
+ *        itself (then nq must equal n and row i belongs to input point i).
+ *        A query that is a data point finds itself at distance 0.
+ * k      1 <= k <= KDT_MAX_K.
+ * kth_only 0: write k results per row, ascending by (d2, index):
+ *             d_idx [nq][k] int32 (may be NULL), d_d2 [nq][k] float32.
+ *          1: write only the k-th squared distance, d_d2 [nq].
+ *          2: write only the k-th distance sqrt(d2_k), d_d2 [nq] (an SPH
+ *             smoothing length, Sec. 4.2).
+ * Rows of a tree with fewer than k points are padded with (-1, +inf).
+ * opts   may be NULL (sort_queries = 1).
+ *
+ * Errors: KDT_EINVAL, KDT_EUNSUPPORTED (k), KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_knn(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t k,
+                   int32_t *d_idx, float *d_d2, int32_t kth_only, const kdt_query_opts *opts,
+                   hipStream_t stream);
+
+/*
+ * kdt_range -- ball query: the points within distance r of each query
+ * (Sec. 2.3, Algorithm 3).  The ball is closed: a point is in when
+ * d2 <= fl32(r * r).
+ *
+ * d_q       [nq][d] float32, or NULL for the tree's own points (nq == n).
+ * r         finite, >= 0.
+ * d_count   [nq] int32: number of points in each ball (required).
+ * d_offsets [nq + 1] int64, or NULL.  When given together with d_idx the call
+ *           also returns the lists in CSR form: row i is
+ *           d_idx[d_offsets[i] .. d_offsets[i+1]) in ascending index order.
+ *           This mode waits on `stream` once to learn the total size.
+ * capacity  number of int32 slots in d_idx.
+ * required  host, may be NULL: receives the total list length (list mode).
+ *
+ * Errors: KDT_EINVAL, KDT_ECAPACITY (total > capacity; *required is set and
+ * d_count / d_offsets are valid), KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_range(const kdt_tree *tree, const float *d_q, int64_t nq, float r,
+                     int32_t *d_count, int64_t *d_offsets, int32_t *d_idx, int64_t capacity,
+                     int64_t *required, const kdt_query_opts *opts, hipStream_t stream);
+
+/*
+ * kdt_fof -- friends-of-friends groups of the tree's points (Sec. 4.1).
+ *
+ * Points i != j are friends when d2(i, j) <= fl32(l * l); groups are the
+ * connected components of that relation.  d_labels [n] int32 receives, for
+ * every input point, the smallest input index of its group, so labels are
+ * canonical and independent of scheduling.  n_groups (host, may be NULL)
+ * receives the number of groups; asking for it waits on `stream`.
+ *
+ * Errors: KDT_EINVAL (l negative or non-finite), KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_fof(const kdt_tree *tree, float l, int32_t *d_labels, int64_t *n_groups,
+                   hipStream_t stream);
+
+/*
+ * kdt_p2m -- adaptive SPH particle-to-mesh deposit (Sec. 4.2).
+ *
+ * d_x [n][3], d_m [n], d_h [n] float32 device: positions, masses and
+ * smoothing lengths (h_i = distance to the k-th neighbour, e.g. from
+ * kdt_knn with kth_only = 2).  Every position must lie in the grid box.
+ * Each particle spreads m_i over the cells whose centres lie within
+ * H_i = max(h_i, cell) with the M4 cubic spline w(q), q = 2 r / H_i,
+ * normalised over its in-grid cells, so the deposit conserves mass:
+ *   rho_c = sum_i m_i w(q_ic) / S_i,   S_i = sum_c w(q_ic).
+ * d_order [n] int32 or NULL: visiting order of the particles (for example the
+ * tree order from kdt_tree_perm); it only changes speed and rounding order.
+ * d_grid [n0*n1*n2] float32: overwritten with the mass per cell.  The sums are
+ * accumulated in float64 and rounded once.
+ *
+ * Errors: KDT_EINVAL (NULL pointer, bad grid, particle outside the box -- the
+ * latter is detected on the device and reported by a wait at the end),
+ * KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_p2m(const float *d_x, const float *d_m, const float *d_h, int64_t n,
+                   const kdt_grid *grid, const int32_t *d_order, float *d_grid,
+                   hipStream_t stream);
+
+/*
+ * kdt_p2m_backward -- adjoint of kdt_p2m for a loss L = sum_c g_c rho_c with
+ * the smoothing lengths held fixed:
+ *   dL/dm_i = A_i / S_i,   dL/dx_i = (m_i / S_i) (C_i - (A_i / S_i) B_i),
+ * S = sum w, A = sum g w, B = sum grad w, C = sum g grad w over the particle's
+ * in-grid cells, grad w = w'(q) (2 / H_i) (x_i - x_c) / r.  The weights are
+ * recomputed, nothing per (particle, cell) is stored.
+ * d_ggrid [cells] float32 upstream gradient.  d_gm [n], d_gx [n][3] float32
+ * outputs, either may be NULL.  Other arguments as kdt_p2m.
+ */
+kdt_status kdt_p2m_backward(const float *d_x, const float *d_m, const float *d_h, int64_t n,
+                            const kdt_grid *grid, const int32_t *d_order,
+                            const float *d_ggrid, float *d_gm, float *d_gx,
+                            hipStream_t stream);
+
+/* Device pointer to the tree order: perm[t] is the input index of the point at
+   tree position t (n int32, owned by the tree).  NULL on error. */
+const int32_t *kdt_tree_perm(const kdt_tree *tree);
+
+/*
+ * Batched mode: many independent point sets of uneven size, concatenated.
+ *
+ * kdt_batch_plan_create fixes the shapes on the host: h_offsets [n_sets+1]
+ * (host, int64, set s owns rows h_offsets[s] .. h_offsets[s+1]), d, k, and the
+ * options.  It allocates every buffer the pipeline needs, so a launch
+ * allocates nothing.
+ *
+ * kdt_batch_launch builds one tree per set and runs, per set, kNN of every
+ * point of the set (k from the plan) and friends-of-friends with the set's
+ * linking length d_l[s] (device, float32 [n_sets]).  Outputs use set-local
+ * indices: d_idx / d_d2 [total][k], d_labels [total].  Results are identical
+ * to kdt_build + kdt_knn(NULL) + kdt_fof on each set.  With use_graph = 1 the
+ * whole pipeline is captured once into a hipGraph and replayed.
+ *
+ * Errors: KDT_EINVAL, KDT_EUNSUPPORTED, KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_batch_plan_create(const int64_t *h_offsets, int32_t n_sets, int32_t d,
+                                 int32_t k, const kdt_build_opts *bopts,
+                                 const kdt_query_opts *qopts, kdt_batch_plan **out);
+kdt_status kdt_batch_launch(kdt_batch_plan *plan, const float *d_pts, const float *d_l,
+                            int32_t *d_idx, float *d_d2, int32_t *d_labels, int32_t use_graph,
+                            hipStream_t stream);
+kdt_status kdt_batch_plan_free(kdt_batch_plan *plan);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *kdt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDT_H */

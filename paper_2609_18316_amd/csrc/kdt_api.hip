@@ -1,0 +1,256 @@
+// kdt_api.hip -- C ABI entry points for tree construction and inspection,
+// error reporting and the cache of device-resident build schedules.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <string>
+
+#include "kdt_internal.h"
+
+static thread_local std::string g_error;
+
+void kdt_set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+}
+
+void kdt_clear_error() { g_error.clear(); }
+
+extern "C" const char* kdt_last_error(void) { return g_error.c_str(); }
+
+namespace kdt {
+
+// Build schedules depend only on (device, n, d, leaf); repeated builds of the
+// same shape reuse the uploaded tables.
+struct CachedPlan {
+  int device;
+  int64_t n;
+  int d, leaf;
+  Plan plan;
+  PlanDev dev;
+};
+
+static std::mutex g_plan_mu;
+static std::list<std::shared_ptr<CachedPlan>> g_plans;
+constexpr size_t kPlanCache = 8;
+
+static kdt_status get_plan(int device, int64_t n, int d, int leaf, hipStream_t stream,
+                           std::shared_ptr<CachedPlan>& out) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
+    if ((*it)->device == device && (*it)->n == n && (*it)->d == d && (*it)->leaf == leaf) {
+      out = *it;
+      g_plans.splice(g_plans.begin(), g_plans, it);
+      return KDT_OK;
+    }
+  }
+  auto cp = std::make_shared<CachedPlan>();
+  cp->device = device;
+  cp->n = n;
+  cp->d = d;
+  cp->leaf = leaf;
+  int64_t offs[2] = {0, n};
+  std::string err;
+  if (!make_plan(offs, 1, d, leaf, cp->plan, err)) {
+    kdt_set_error("%s", err.c_str());
+    return KDT_EINVAL;
+  }
+  kdt_status st = plan_upload(cp->plan, cp->dev, stream);
+  if (st != KDT_OK) return st;
+  g_plans.push_front(cp);
+  while (g_plans.size() > kPlanCache) {
+    // a plan still referenced by a running build stays alive through `out`
+    std::shared_ptr<CachedPlan> victim = g_plans.back();
+    g_plans.pop_back();
+    if (victim.use_count() == 1) {
+      (void)hipDeviceSynchronize();
+      plan_release(victim->dev);
+    }
+  }
+  out = cp;
+  return KDT_OK;
+}
+
+static bool dim_ok(int d) { return d == 2 || d == 3 || d == 4 || d == 8 || d == 16; }
+
+}  // namespace kdt
+
+using namespace kdt;
+
+extern "C" kdt_status kdt_build(const float* d_pts, int64_t n, int32_t d,
+                                const kdt_build_opts* opts, hipStream_t stream, kdt_tree** out) {
+  kdt_clear_error();
+  if (!out) {
+    kdt_set_error("kdt_build: out is NULL");
+    return KDT_EINVAL;
+  }
+  *out = nullptr;
+  if (!d_pts || n < 1 || n > INT32_MAX) {
+    kdt_set_error("kdt_build: NULL points or n=%lld outside [1, 2^31-1]", (long long)n);
+    return KDT_EINVAL;
+  }
+  if (!dim_ok(d)) {
+    kdt_set_error("kdt_build: dimension %d is not one of 2, 3, 4, 8, 16", d);
+    return KDT_EUNSUPPORTED;
+  }
+  int leaf = 32, check = 1;
+  if (opts) {
+    if (opts->leaf_size) leaf = opts->leaf_size;
+    check = opts->check_finite;
+  }
+  if (leaf < 2 || leaf > 256) {
+    kdt_set_error("kdt_build: leaf_size %d outside [2, 256]", leaf);
+    return KDT_EINVAL;
+  }
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) {
+    kdt_set_error("kdt_build: no HIP device");
+    return KDT_EDEVICE;
+  }
+  std::shared_ptr<CachedPlan> cp;
+  kdt_status st = get_plan(device, n, d, leaf, stream, cp);
+  if (st != KDT_OK) return st;
+  const Plan& plan = cp->plan;
+
+  kdt_tree* t = new (std::nothrow) kdt_tree();
+  if (!t) {
+    kdt_set_error("kdt_build: out of host memory");
+    return KDT_ENOMEM;
+  }
+  t->device = device;
+  t->stream = stream;
+  t->n = n;
+  t->d = d;
+  t->leaf = leaf;
+  t->levels = plan.sets[0].levels;
+  t->stride = rec_stride(d);
+  t->n_nodes = plan.n_nodes;
+  const size_t b_rec = sizeof(float) * (size_t)n * t->stride;
+  const size_t b_box = sizeof(float) * (size_t)t->n_nodes * 2 * pad4(d);
+  const size_t b_perm = sizeof(int32_t) * (size_t)n;
+  const size_t b_axis = sizeof(int32_t) * (size_t)t->n_nodes;
+  const size_t b_split = sizeof(float) * (size_t)t->n_nodes;
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  void* block = nullptr;
+  if (dev_alloc(&block, up(b_rec) + up(b_box) + up(b_perm) + up(b_axis) + up(b_split), stream) !=
+      hipSuccess) {
+    delete t;
+    kdt_set_error("kdt_build: cannot allocate the tree (%lld points)", (long long)n);
+    return KDT_ENOMEM;
+  }
+  unsigned char* bp = static_cast<unsigned char*>(block);
+  t->rec = reinterpret_cast<float*>(bp);
+  t->box = reinterpret_cast<float*>(bp + up(b_rec));
+  t->perm = reinterpret_cast<int32_t*>(bp + up(b_rec) + up(b_box));
+  t->axis = reinterpret_cast<int32_t*>(bp + up(b_rec) + up(b_box) + up(b_perm));
+  t->split = reinterpret_cast<float*>(bp + up(b_rec) + up(b_box) + up(b_perm) + up(b_axis));
+
+  BuildScratch w;
+  st = build_scratch_alloc(plan, cp->dev, w, stream);
+  if (st != KDT_OK) {
+    (void)hipFreeAsync(block, stream);
+    delete t;
+    return st;
+  }
+  BuildOut o{t->rec, t->box, t->perm, t->axis, t->split};
+  st = build_launch(plan, cp->dev, d_pts, w, o, 0, stream);
+  if (st == KDT_OK && check) {
+    int32_t bad = 0;
+    if (hipMemcpyAsync(&bad, w.bad, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      kdt_set_error("kdt_build: reading the input check failed");
+      st = KDT_EDEVICE;
+    } else if (bad) {
+      kdt_set_error("kdt_build: the points contain NaN or infinite coordinates");
+      st = KDT_EINVAL;
+    }
+  }
+  if (st == KDT_OK) st = build_launch(plan, cp->dev, d_pts, w, o, 1, stream);
+  build_scratch_free(w, stream);
+  if (st != KDT_OK) {
+    (void)hipFreeAsync(block, stream);
+    delete t;
+    return st;
+  }
+  *out = t;
+  return KDT_OK;
+}
+
+extern "C" kdt_status kdt_free(kdt_tree* tree) {
+  kdt_clear_error();
+  if (!tree) return KDT_OK;
+  hipError_t e = hipStreamSynchronize(tree->stream);
+  if (tree->rec) (void)hipFreeAsync(tree->rec, tree->stream);
+  delete tree;
+  if (e != hipSuccess) {
+    kdt_set_error("kdt_free: waiting for the tree's stream failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+extern "C" kdt_status kdt_tree_get_info(const kdt_tree* tree, kdt_tree_info* info) {
+  kdt_clear_error();
+  if (!tree || !info) {
+    kdt_set_error("kdt_tree_get_info: NULL argument");
+    return KDT_EINVAL;
+  }
+  info->n = tree->n;
+  info->d = tree->d;
+  info->leaf_size = tree->leaf;
+  info->levels = tree->levels;
+  info->stride = tree->stride;
+  info->n_nodes = tree->n_nodes;
+  return KDT_OK;
+}
+
+extern "C" const int32_t* kdt_tree_perm(const kdt_tree* tree) { return tree ? tree->perm : nullptr; }
+
+extern "C" kdt_status kdt_tree_export(const kdt_tree* tree, float* h_pts, int32_t* h_perm,
+                                      float* h_lo, float* h_hi, int32_t* h_axis, float* h_split,
+                                      hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree) {
+    kdt_set_error("kdt_tree_export: NULL tree");
+    return KDT_EINVAL;
+  }
+  const int d = tree->d, S = tree->stride, P = pad4(d);
+  std::vector<float> rec((size_t)tree->n * S);
+  std::vector<float> box((size_t)tree->n_nodes * 2 * P);
+  hipError_t e = hipMemcpyAsync(rec.data(), tree->rec, sizeof(float) * rec.size(),
+                                hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(box.data(), tree->box, sizeof(float) * box.size(), hipMemcpyDeviceToHost,
+                       stream);
+  if (e == hipSuccess && h_perm)
+    e = hipMemcpyAsync(h_perm, tree->perm, sizeof(int32_t) * tree->n, hipMemcpyDeviceToHost,
+                       stream);
+  if (e == hipSuccess && h_axis)
+    e = hipMemcpyAsync(h_axis, tree->axis, sizeof(int32_t) * tree->n_nodes,
+                       hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && h_split)
+    e = hipMemcpyAsync(h_split, tree->split, sizeof(float) * tree->n_nodes,
+                       hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    kdt_set_error("kdt_tree_export: copy failed: %s", hipGetErrorString(e));
+    return KDT_EDEVICE;
+  }
+  for (int64_t i = 0; h_pts && i < tree->n; ++i)
+    for (int a = 0; a < d; ++a) h_pts[i * d + a] = rec[(size_t)i * S + a];
+  for (int64_t v = 0; v < tree->n_nodes; ++v)
+    for (int a = 0; a < d; ++a) {
+      if (h_lo) h_lo[v * d + a] = box[(size_t)v * 2 * P + a];
+      if (h_hi) h_hi[v * d + a] = box[(size_t)v * 2 * P + P + a];
+    }
+  return KDT_OK;
+}

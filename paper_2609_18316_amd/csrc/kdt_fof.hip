@@ -1,0 +1,177 @@
+// kdt_fof.hip -- friends-of-friends grouping (Sec. 4.1) on gfx950.
+//
+// Every point runs a ball query of radius l over the tree (in tree order, so
+// the lanes of a wave search neighbouring space) and links itself to every
+// friend with a larger input index through a lock-free union-find: roots
+// always hang under the smaller root (compare-and-swap), so the root of each
+// component is its smallest input index.  Finding a root halves the path as
+// it goes.  A final pass points every element at its root, which is the
+// canonical group label.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "kdt_query.h"
+
+namespace kdt {
+
+constexpr int kFBlock = 128;
+
+__device__ __forceinline__ int32_t ld_rel(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x.  parent[y] <= y always holds, and only roots change owner, so
+// shortcutting a non-root to any of its ancestors is always valid.
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+  int32_t cur = ld_rel(parent + x);
+  if (cur == x) return x;
+  int32_t prev = x;
+  for (;;) {
+    const int32_t next = ld_rel(parent + cur);
+    if (next >= cur) break;
+    st_rel(parent + prev, next);
+    prev = cur;
+    cur = next;
+  }
+  return cur;
+}
+
+// Joins the sets of a and b: the larger root is hooked under the smaller.
+__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+  int32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+  while (ra != rb) {
+    if (ra < rb) {
+      const int32_t old = atomicCAS(parent + rb, rb, ra);
+      if (old == rb) break;
+      rb = old;
+    } else {
+      const int32_t old = atomicCAS(parent + ra, ra, rb);
+      if (old == ra) break;
+      ra = old;
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kFBlock) void k_fof_link(TreeView t, float l2,
+                                                      int32_t* __restrict__ parent) {
+  __shared__ uint32_t stk[kMaxDepth][kFBlock];
+  const int64_t s = (int64_t)blockIdx.x * kFBlock + threadIdx.x;
+  if (s >= t.n) return;
+  float p[D];
+  int32_t me = 0;
+  load_rec<D>(t.rec, s, p, me);
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int sp = 0;
+  stk[sp++][threadIdx.x] = 0;
+  while (sp > 0) {
+    const uint32_t node = stk[--sp][threadIdx.x];
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (box_mindist<D>(lo, hi, p) > l2) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    const bool all_in = box_maxdist<D>(lo, hi, p) <= l2;
+    if (all_in || node >= first_leaf) {
+      for (int64_t i = b; i < e; ++i) {
+        float x[D];
+        int32_t id = 0;
+        load_rec<D>(t.rec, i, x, id);
+        if (id > me && (all_in || sq_dist<D>(x, p) <= l2)) uf_union(parent, me, id);
+      }
+      continue;
+    }
+    stk[sp++][threadIdx.x] = 2 * node + 2;
+    stk[sp++][threadIdx.x] = 2 * node + 1;
+  }
+}
+
+__global__ void k_fof_init(int32_t* __restrict__ parent, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) parent[i] = (int32_t)i;
+}
+
+__global__ void k_fof_final(int32_t* __restrict__ parent, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int32_t r = uf_find(parent, (int32_t)i);
+    st_rel(parent + i, r);
+  }
+}
+
+struct IsRoot {
+  const int32_t* lab;
+  __host__ __device__ int64_t operator()(int64_t i) const { return lab[i] == (int32_t)i ? 1 : 0; }
+};
+
+static TreeView view_of(const kdt_tree* t) {
+  TreeView v;
+  v.rec = t->rec;
+  v.box = t->box;
+  v.n = t->n;
+  v.levels = t->levels;
+  return v;
+}
+
+}  // namespace kdt
+
+using namespace kdt;
+
+extern "C" kdt_status kdt_fof(const kdt_tree* tree, float l, int32_t* d_labels, int64_t* n_groups,
+                              hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree || !d_labels || !(l >= 0.0f) || !std::isfinite(l)) {
+    kdt_set_error("kdt_fof: NULL tree or labels, or linking length not finite and >= 0");
+    return KDT_EINVAL;
+  }
+  const int64_t n = tree->n;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  k_fof_init<<<g, 256, 0, stream>>>(d_labels, n);
+  const TreeView v = view_of(tree);
+  const float l2 = l * l;
+  const unsigned gl = (unsigned)((n + kFBlock - 1) / kFBlock);
+  switch (tree->d) {
+    case 2: k_fof_link<2><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
+    case 3: k_fof_link<3><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
+    case 4: k_fof_link<4><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
+    case 8: k_fof_link<8><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
+    case 16: k_fof_link<16><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
+    default:
+      kdt_set_error("kdt_fof: unsupported dimension %d", tree->d);
+      return KDT_EUNSUPPORTED;
+  }
+  k_fof_final<<<g, 256, 0, stream>>>(d_labels, n);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_fof: kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  if (n_groups) {
+    hipcub::CountingInputIterator<int64_t> ci(0);
+    hipcub::TransformInputIterator<int64_t, IsRoot, hipcub::CountingInputIterator<int64_t>> roots(
+        ci, IsRoot{d_labels});
+    int64_t* d_out = nullptr;
+    void* tmp = nullptr;
+    size_t tb = 0;
+    hipcub::DeviceReduce::Sum(nullptr, tb, roots, d_out, (int)n, stream);
+    if (hipMallocAsync((void**)&d_out, sizeof(int64_t), stream) != hipSuccess ||
+        hipMallocAsync(&tmp, tb > 0 ? tb : 16, stream) != hipSuccess) {
+      kdt_set_error("kdt_fof: device allocation failed");
+      return KDT_ENOMEM;
+    }
+    hipcub::DeviceReduce::Sum(tmp, tb, roots, d_out, (int)n, stream);
+    int64_t h = 0;
+    hipError_t e1 = hipMemcpyAsync(&h, d_out, sizeof(h), hipMemcpyDeviceToHost, stream);
+    (void)hipFreeAsync(tmp, stream);
+    (void)hipFreeAsync(d_out, stream);
+    if (e1 != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+      kdt_set_error("kdt_fof: counting groups failed");
+      return KDT_EDEVICE;
+    }
+    *n_groups = h;
+  }
+  return KDT_OK;
+}

@@ -1,0 +1,192 @@
+// kdt_internal.h -- shared device helpers and host-side structures of the
+// HIP k-d tree library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "kdt.h"
+
+namespace kdt {
+
+constexpr int kWave = 64;
+
+// Floats per node bounding-box half (lo or hi), padded so a node's box is
+// two aligned runs of float4.
+__host__ __device__ constexpr int pad4(int d) { return (d + 3) & ~3; }
+// Floats per tree-ordered point record: d coordinates, then the original index
+// (int32 bits), padded to a multiple of 4 so records load as float4.
+__host__ __device__ constexpr int rec_stride(int d) { return (d + 1 + 3) & ~3; }
+
+// Order-preserving map of float32 onto uint32 (total order; -0 sorts below +0).
+__device__ __forceinline__ uint32_t fkey(float f) {
+  uint32_t b = __float_as_uint(f);
+  return b ^ ((b & 0x80000000u) ? 0xFFFFFFFFu : 0x80000000u);
+}
+__device__ __forceinline__ float fkey_inv(uint32_t u) {
+  uint32_t b = u ^ ((u & 0x80000000u) ? 0x80000000u : 0xFFFFFFFFu);
+  return __uint_as_float(b);
+}
+
+// Point range [begin, end) of node (level, j) of a balanced tree over n points.
+__host__ __device__ __forceinline__ int64_t node_begin(int64_t n, int level, int64_t j) {
+  return (j * n) >> level;
+}
+
+// Level of heap node id v (root 0, children 2v+1, 2v+2).
+__device__ __forceinline__ int node_level(uint32_t v) { return 31 - __clz(v + 1); }
+
+// Memory-model helpers for data written by other workgroups in the same launch.
+__device__ __forceinline__ uint32_t ld_acquire_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_agent_i32(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Orders LDS traffic between the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set lanes of `mask` below the calling lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+// ---------------------------------------------------------------------------
+// Host-side structures
+// ---------------------------------------------------------------------------
+
+// One tree of a forest (a single tree is a forest of one set).
+struct SetDesc {
+  int64_t off;        // first row of the set in the concatenated point array
+  int64_t n;          // points in the set
+  int64_t node_base;  // first node id of the set
+  int32_t levels;     // L
+  int32_t glevels;    // levels split by the multi-workgroup path
+};
+
+// A node split by the multi-workgroup path at one level.
+struct SegEntry {
+  int64_t b, e, m;      // global rows [b, e), first right row m
+  int64_t node;         // global node id
+  int64_t child;        // global node id of the left child (right = child + 1)
+  int32_t first_chunk;  // chunk ids [first_chunk, first_chunk + n_chunks)
+  int32_t n_chunks;
+};
+
+struct ChunkEntry {
+  int64_t b, e;  // rows
+  int32_t seg;   // segment index within the level (or set index for the root pass)
+  int32_t pad;
+};
+
+// A node finished inside one workgroup's LDS, with its whole subtree.
+struct SubEntry {
+  int64_t j;      // index of the node within its level
+  int32_t set;
+  int32_t level;
+};
+
+// Selection state of one segment during the radix-select passes.
+struct SegState {
+  uint32_t prefix;   // resolved high bits of the pivot key
+  int32_t rank;      // rank of the pivot among the keys that match prefix
+  int32_t hb;        // highest unresolved bit, -1 when the pivot is known
+  int32_t axis;
+  int32_t n_eq_left; // keys equal to the pivot that go left
+  int32_t pad[3];
+};
+
+struct Plan {
+  int d = 0, leaf = 0;
+  int64_t total = 0;
+  std::vector<SetDesc> sets;
+  int64_t n_nodes = 0;
+  int n_glevels = 0;
+  // per global level: segment and chunk tables
+  std::vector<std::vector<SegEntry>> segs;
+  std::vector<std::vector<ChunkEntry>> chunks;
+  std::vector<ChunkEntry> root_chunks;  // seg field = set index
+  std::vector<SubEntry> subs;
+  int lds_cap = 0;  // largest node finished in LDS
+};
+
+// Builds the static schedule of a forest from host-known sizes.
+bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& plan, std::string& err);
+
+int levels_for(int64_t n, int leaf);
+int lds_capacity(int d);
+
+// Device copies of a plan's tables (one allocation).
+struct PlanDev {
+  SetDesc* sets = nullptr;
+  ChunkEntry* root_chunks = nullptr;
+  std::vector<SegEntry*> segs;
+  std::vector<ChunkEntry*> chunks;
+  SubEntry* subs = nullptr;
+  void* block = nullptr;
+  size_t max_segs = 0, max_chunks = 0;
+};
+
+// Scratch of one build (stream-ordered allocations).
+struct BuildScratch {
+  float* x[2] = {nullptr, nullptr};
+  int32_t* p[2] = {nullptr, nullptr};
+  uint32_t* ubox = nullptr;
+  SegState* st = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t* ctr = nullptr;
+  int32_t* cnt = nullptr;
+  int32_t* pref = nullptr;
+  int32_t* bad = nullptr;
+};
+
+// Where a build writes the tree.
+struct BuildOut {
+  float* rec;
+  float* box;
+  int32_t* perm;
+  int32_t* axis;
+  float* split;
+};
+
+kdt_status plan_upload(const Plan& p, PlanDev& pd, hipStream_t stream);
+void plan_release(PlanDev& pd);
+kdt_status build_scratch_alloc(const Plan& p, const PlanDev& pd, BuildScratch& w,
+                               hipStream_t stream);
+void build_scratch_free(BuildScratch& w, hipStream_t stream);
+// phase 0: ingest and root boxes; phase 1: everything after.
+kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
+                        const BuildScratch& w, const BuildOut& o, int phase, hipStream_t stream);
+// Stream-ordered device allocation from the default pool (kept cached).
+hipError_t dev_alloc(void** ptr, size_t bytes, hipStream_t stream);
+
+}  // namespace kdt
+
+// Library-owned tree.
+struct kdt_tree {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t n = 0;
+  int d = 0, leaf = 0, levels = 0, stride = 0;
+  int64_t n_nodes = 0;
+  float* rec = nullptr;      // [n][stride]
+  float* box = nullptr;      // [n_nodes][2 * pad4(d)]
+  int32_t* perm = nullptr;   // [n]
+  int32_t* axis = nullptr;   // [n_nodes]
+  float* split = nullptr;    // [n_nodes]
+};
+
+// Error reporting shared by every entry point.
+void kdt_set_error(const char* fmt, ...);
+void kdt_clear_error();

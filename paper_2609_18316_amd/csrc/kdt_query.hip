@@ -1,0 +1,455 @@
+// kdt_query.hip -- batched kNN (Sec. 2.3, Algorithm 2) and ball queries
+// (Algorithm 3) over a balanced k-d tree on gfx950.
+//
+// One lane per query.  The paper's best-first node queue is replaced by a
+// depth-first stack that descends into the nearer child first and prunes a
+// node when its box is farther than the current k-th candidate (strict '>').
+// Candidates live in a sorted register list keyed by (d2, index), so the
+// result -- the k smallest keys -- is exactly the one the best-first order
+// gives.  Queries of one wave are made spatially coherent either by running
+// in tree order (self queries) or by sorting external queries by the leaf
+// they fall in.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+
+#include "kdt_query.h"
+
+namespace kdt {
+
+constexpr int kQBlock = 128;
+
+// ---------------------------------------------------------------------------
+// kNN
+// ---------------------------------------------------------------------------
+
+template <int D, int KC>
+__global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* __restrict__ q,
+                                                      int64_t nq, int k,
+                                                      const int32_t* __restrict__ order, int mode,
+                                                      int32_t* __restrict__ oidx,
+                                                      float* __restrict__ od2) {
+  __shared__ uint64_t stk[kMaxDepth][kQBlock];
+  constexpr int S = rec_stride(D);
+  const int64_t s = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
+  if (s >= nq) return;
+  float p[D];
+  int64_t row;
+  if (q == nullptr) {
+    int32_t id = 0;
+    load_rec<D>(t.rec, s, p, id);
+    row = id;
+  } else {
+    row = order ? order[s] : s;
+#pragma unroll
+    for (int a = 0; a < D; ++a) p[a] = q[row * D + a];
+  }
+  TopK<KC> best;
+  best.init(k);
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  float lo[D], hi[D];
+  load_box<D>(t.box, 0, lo, hi);
+  uint32_t node = 0;
+  float nd = box_mindist<D>(lo, hi, p);
+  int sp = 0;
+  for (;;) {
+    if (nd <= best.worst_d2()) {
+      if (node >= first_leaf) {
+        const int64_t j = node - first_leaf;
+        const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
+        for (int64_t i = b; i < e; ++i) {
+          float x[D];
+          int32_t id = 0;
+          load_rec<D>(t.rec, i, x, id);
+          const uint64_t key = make_key(sq_dist<D>(x, p), id);
+          if (key < best.worst()) best.insert(key);
+        }
+      } else {
+        const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
+        load_box<D>(t.box, c0, lo, hi);
+        const float d0 = box_mindist<D>(lo, hi, p);
+        load_box<D>(t.box, c1, lo, hi);
+        const float d1 = box_mindist<D>(lo, hi, p);
+        const bool first0 = d0 <= d1;
+        const uint32_t nn = first0 ? c0 : c1, ff = first0 ? c1 : c0;
+        const float dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
+        if (df <= best.worst_d2()) {
+          stk[sp][threadIdx.x] = ((uint64_t)ff << 32) | __float_as_uint(df);
+          ++sp;
+        }
+        node = nn;
+        nd = dn;
+        continue;
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    const uint64_t e = stk[sp][threadIdx.x];
+    node = (uint32_t)(e >> 32);
+    nd = __uint_as_float((uint32_t)e);
+  }
+  if (mode == 0) {
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+      if (j < KC - k) continue;
+      const uint64_t key = best.a[j];
+      const bool empty = key == kEmptyKey;
+      const int64_t o = row * k + (j - (KC - k));
+      if (oidx) oidx[o] = empty ? -1 : (int32_t)(uint32_t)key;
+      od2[o] = empty ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
+    }
+  } else {
+    const uint64_t key = best.a[KC - 1];
+    float d2 = key == kEmptyKey ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
+    od2[row] = mode == 2 ? sqrtf(d2) : d2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Ball queries: counts, then CSR lists
+// ---------------------------------------------------------------------------
+
+template <int D, bool FILL>
+__global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __restrict__ q,
+                                                   int64_t nq, float r2,
+                                                   const int32_t* __restrict__ order,
+                                                   int32_t* __restrict__ count,
+                                                   const int64_t* __restrict__ offsets,
+                                                   int32_t* __restrict__ out) {
+  __shared__ uint32_t stk[kMaxDepth][kQBlock];
+  const int64_t s = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
+  if (s >= nq) return;
+  float p[D];
+  int64_t row;
+  if (q == nullptr) {
+    int32_t id = 0;
+    load_rec<D>(t.rec, s, p, id);
+    row = id;
+  } else {
+    row = order ? order[s] : s;
+#pragma unroll
+    for (int a = 0; a < D; ++a) p[a] = q[row * D + a];
+  }
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int64_t c = 0;
+  int64_t pos = FILL ? offsets[row] : 0;
+  int sp = 0;
+  stk[sp++][threadIdx.x] = 0;
+  while (sp > 0) {
+    const uint32_t node = stk[--sp][threadIdx.x];
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (box_mindist<D>(lo, hi, p) > r2) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    if (box_maxdist<D>(lo, hi, p) <= r2) {
+      if (FILL) {
+        for (int64_t i = b; i < e; ++i) {
+          float x[D];
+          int32_t id = 0;
+          load_rec<D>(t.rec, i, x, id);
+          out[pos++] = id;
+        }
+      }
+      c += e - b;
+      continue;
+    }
+    if (node >= first_leaf) {
+      for (int64_t i = b; i < e; ++i) {
+        float x[D];
+        int32_t id = 0;
+        load_rec<D>(t.rec, i, x, id);
+        if (sq_dist<D>(x, p) <= r2) {
+          if (FILL) out[pos++] = id;
+          ++c;
+        }
+      }
+      continue;
+    }
+    stk[sp++][threadIdx.x] = 2 * node + 2;
+    stk[sp++][threadIdx.x] = 2 * node + 1;
+  }
+  if (!FILL) count[row] = (int32_t)c;
+}
+
+// ---------------------------------------------------------------------------
+// Query ordering: leaf reached by descending towards the nearer child.
+// ---------------------------------------------------------------------------
+
+template <int D>
+__global__ void k_query_leaf(TreeView t, const float* __restrict__ q, int64_t nq,
+                             uint32_t* __restrict__ key, int32_t* __restrict__ val) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nq) return;
+  float p[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) p[a] = q[s * D + a];
+  uint32_t node = 0;
+  for (int l = 0; l < t.levels; ++l) {
+    float lo[D], hi[D];
+    load_box<D>(t.box, 2 * node + 1, lo, hi);
+    const float d0 = box_mindist<D>(lo, hi, p);
+    load_box<D>(t.box, 2 * node + 2, lo, hi);
+    const float d1 = box_mindist<D>(lo, hi, p);
+    node = d0 <= d1 ? 2 * node + 1 : 2 * node + 2;
+  }
+  key[s] = node;
+  val[s] = (int32_t)s;
+}
+
+__global__ void k_iota(int32_t* v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (int32_t)i;
+}
+
+struct ToI64 {
+  __host__ __device__ int64_t operator()(int32_t v) const { return v; }
+};
+
+__global__ void k_range_offsets_fix(int64_t* off, const int32_t* count, int64_t nq) {
+  // off holds the exclusive scan of count over [0, nq); write off[nq]
+  if (blockIdx.x == 0 && threadIdx.x == 0) off[nq] = nq > 0 ? off[nq - 1] + count[nq - 1] : 0;
+}
+
+#define KDT_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      kdt_set_error("%s failed: %s", #call, hipGetErrorString(e_));          \
+      return KDT_EDEVICE;                                                    \
+    }                                                                        \
+  } while (0)
+
+static TreeView view_of(const kdt_tree* t) {
+  TreeView v;
+  v.rec = t->rec;
+  v.box = t->box;
+  v.n = t->n;
+  v.levels = t->levels;
+  return v;
+}
+
+// Sorts external queries by the leaf they fall in; returns the order array
+// (caller frees with hipFreeAsync).
+template <int D>
+static kdt_status order_queries(const kdt_tree* t, const float* d_q, int64_t nq, int32_t** out,
+                                hipStream_t stream) {
+  *out = nullptr;
+  if (nq > INT32_MAX) {
+    kdt_set_error("query reordering supports at most 2^31-1 queries");
+    return KDT_EINVAL;
+  }
+  uint32_t *k0 = nullptr, *k1 = nullptr;
+  int32_t *v0 = nullptr, *v1 = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  const int end_bit = std::max(1, t->levels + 1);
+  hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k0, k1, v0, v1, (int)nq, 0, end_bit, stream);
+  const size_t nb = sizeof(uint32_t) * (size_t)nq;
+  if (hipMallocAsync((void**)&k0, nb, stream) != hipSuccess ||
+      hipMallocAsync((void**)&k1, nb, stream) != hipSuccess ||
+      hipMallocAsync((void**)&v0, nb, stream) != hipSuccess ||
+      hipMallocAsync((void**)&v1, nb, stream) != hipSuccess ||
+      hipMallocAsync(&tmp, std::max<size_t>(tmp_bytes, 16), stream) != hipSuccess) {
+    kdt_set_error("device allocation failed for query ordering");
+    return KDT_ENOMEM;
+  }
+  k_query_leaf<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq, k0, v0);
+  KDT_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k0, k1, v0, v1, (int)nq, 0, end_bit,
+                                             stream));
+  (void)hipFreeAsync(k0, stream);
+  (void)hipFreeAsync(k1, stream);
+  (void)hipFreeAsync(v0, stream);
+  (void)hipFreeAsync(tmp, stream);
+  *out = v1;
+  return KDT_OK;
+}
+
+template <int D>
+static kdt_status knn_dispatch(const kdt_tree* t, const float* d_q, int64_t nq, int k,
+                               int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
+                               hipStream_t stream) {
+  const TreeView v = view_of(t);
+  const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
+  if (k <= 8)
+    k_knn_lane<D, 8><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+  else if (k <= 16)
+    k_knn_lane<D, 16><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+  else if (k <= 32)
+    k_knn_lane<D, 32><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+  else
+    k_knn_lane<D, 64><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+  KDT_HIP(hipGetLastError());
+  return KDT_OK;
+}
+
+template <int D>
+static kdt_status knn_impl(const kdt_tree* t, const float* d_q, int64_t nq, int k, int32_t* d_idx,
+                           float* d_d2, int mode, bool sort_q, hipStream_t stream) {
+  int32_t* order = nullptr;
+  if (d_q && sort_q && nq > 1) {
+    kdt_status st = order_queries<D>(t, d_q, nq, &order, stream);
+    if (st != KDT_OK) return st;
+  }
+  kdt_status st = knn_dispatch<D>(t, d_q, nq, k, d_idx, d_d2, mode, order, stream);
+  if (order) (void)hipFreeAsync(order, stream);
+  return st;
+}
+
+template <int D>
+static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, float r,
+                             int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
+                             int64_t* required, bool sort_q, hipStream_t stream) {
+  int32_t* order = nullptr;
+  if (d_q && sort_q && nq > 1) {
+    kdt_status st = order_queries<D>(t, d_q, nq, &order, stream);
+    if (st != KDT_OK) return st;
+  }
+  const TreeView v = view_of(t);
+  const float r2 = r * r;
+  const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
+  k_range<D, false><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
+  kdt_status st = KDT_OK;
+  if (d_off) {
+    void* tmp = nullptr;
+    size_t tb = 0;
+    hipcub::TransformInputIterator<int64_t, ToI64, const int32_t*> cnt64(d_count, ToI64());
+    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt64, d_off, (int)nq, stream);
+    if (hipMallocAsync(&tmp, std::max<size_t>(tb, 16), stream) != hipSuccess) {
+      kdt_set_error("device allocation failed for the list offsets");
+      st = KDT_ENOMEM;
+    } else {
+      hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt64, d_off, (int)nq, stream);
+      k_range_offsets_fix<<<1, 1, 0, stream>>>(d_off, d_count, nq);
+      (void)hipFreeAsync(tmp, stream);
+      int64_t total = 0;
+      if (hipMemcpyAsync(&total, d_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, stream) !=
+              hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess) {
+        kdt_set_error("reading the list size failed");
+        st = KDT_EDEVICE;
+      } else {
+        if (required) *required = total;
+        if (d_idx) {
+          if (total > capacity) {
+            kdt_set_error("list capacity %lld is below the %lld entries needed",
+                          (long long)capacity, (long long)total);
+            st = KDT_ECAPACITY;
+          } else if (total > INT32_MAX) {
+            kdt_set_error("lists above 2^31-1 entries are not supported");
+            st = KDT_EUNSUPPORTED;
+          } else if (total > 0) {
+            int32_t* unsorted = nullptr;
+            if (hipMallocAsync((void**)&unsorted, sizeof(int32_t) * total, stream) != hipSuccess) {
+              kdt_set_error("device allocation failed for the lists");
+              st = KDT_ENOMEM;
+            } else {
+              k_range<D, true><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, r2, order, d_count, d_off,
+                                                             unsorted);
+              size_t sb = 0;
+              hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total,
+                                                    (int)nq, d_off, d_off + 1, stream);
+              void* stmp = nullptr;
+              if (hipMallocAsync(&stmp, std::max<size_t>(sb, 16), stream) != hipSuccess) {
+                kdt_set_error("device allocation failed for sorting the lists");
+                st = KDT_ENOMEM;
+              } else {
+                hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total,
+                                                      (int)nq, d_off, d_off + 1, stream);
+                (void)hipFreeAsync(stmp, stream);
+              }
+              (void)hipFreeAsync(unsorted, stream);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (order) (void)hipFreeAsync(order, stream);
+  if (st == KDT_OK) KDT_HIP(hipGetLastError());
+  return st;
+}
+
+}  // namespace kdt
+
+using namespace kdt;
+
+extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq, int32_t k,
+                              int32_t* d_idx, float* d_d2, int32_t kth_only,
+                              const kdt_query_opts* opts, hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree || !d_d2 || nq < 0) {
+    kdt_set_error("kdt_knn: NULL tree or output, or negative nq");
+    return KDT_EINVAL;
+  }
+  if (k < 1 || k > KDT_MAX_K) {
+    kdt_set_error("kdt_knn: k=%d outside [1, %d]", k, KDT_MAX_K);
+    return k < 1 ? KDT_EINVAL : KDT_EUNSUPPORTED;
+  }
+  if (kth_only < 0 || kth_only > 2) {
+    kdt_set_error("kdt_knn: kth_only must be 0, 1 or 2");
+    return KDT_EINVAL;
+  }
+  if (!d_q && nq != tree->n) {
+    kdt_set_error("kdt_knn: self queries need nq == n (%lld)", (long long)tree->n);
+    return KDT_EINVAL;
+  }
+  if (nq == 0) return KDT_OK;
+  const bool sort_q = opts ? opts->sort_queries != 0 : true;
+  switch (tree->d) {
+    case 2: return knn_impl<2>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
+    case 3: return knn_impl<3>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
+    case 4: return knn_impl<4>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
+    case 8: return knn_impl<8>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
+    case 16: return knn_impl<16>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
+  }
+  kdt_set_error("kdt_knn: unsupported dimension %d", tree->d);
+  return KDT_EUNSUPPORTED;
+}
+
+extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t nq, float r,
+                                int32_t* d_count, int64_t* d_offsets, int32_t* d_idx,
+                                int64_t capacity, int64_t* required, const kdt_query_opts* opts,
+                                hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree || !d_count || nq < 0 || !(r >= 0.0f) || !std::isfinite(r)) {
+    kdt_set_error("kdt_range: NULL tree or count, negative nq, or r not finite and >= 0");
+    return KDT_EINVAL;
+  }
+  if (!d_q && nq != tree->n) {
+    kdt_set_error("kdt_range: self queries need nq == n (%lld)", (long long)tree->n);
+    return KDT_EINVAL;
+  }
+  if (d_idx && !d_offsets) {
+    kdt_set_error("kdt_range: lists need d_offsets");
+    return KDT_EINVAL;
+  }
+  if (nq > INT32_MAX && d_offsets) {
+    kdt_set_error("kdt_range: list mode supports at most 2^31-1 queries");
+    return KDT_EUNSUPPORTED;
+  }
+  if (nq == 0) {
+    if (required) *required = 0;
+    if (d_offsets) {
+      int64_t z = 0;
+      if (hipMemcpyAsync(d_offsets, &z, sizeof(z), hipMemcpyHostToDevice, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess) {
+        kdt_set_error("kdt_range: writing empty offsets failed");
+        return KDT_EDEVICE;
+      }
+    }
+    return KDT_OK;
+  }
+  const bool sort_q = opts ? opts->sort_queries != 0 : true;
+  switch (tree->d) {
+    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
+    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
+    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
+    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
+    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
+  }
+  kdt_set_error("kdt_range: unsupported dimension %d", tree->d);
+  return KDT_EUNSUPPORTED;
+}

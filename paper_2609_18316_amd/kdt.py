@@ -1,0 +1,330 @@
+"""Thin ctypes binding of ``libkdt.so`` (the C ABI declared in include/kdt.h).
+
+Argument marshalling only: tensors must already live on the GPU, every step
+runs in the library's HIP kernels on torch's current stream, and a missing or
+unloadable library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkdt.so")
+
+KDT_OK, KDT_EINVAL, KDT_EUNSUPPORTED, KDT_ENOMEM, KDT_ECAPACITY, KDT_EDEVICE = range(6)
+STATUS_NAMES = {0: "KDT_OK", 1: "KDT_EINVAL", 2: "KDT_EUNSUPPORTED", 3: "KDT_ENOMEM",
+                4: "KDT_ECAPACITY", 5: "KDT_EDEVICE"}
+MAX_K = 64
+DIMS = (2, 3, 4, 8, 16)
+
+# Every exported entry point of include/kdt.h.
+EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt_knn",
+           "kdt_range", "kdt_fof", "kdt_p2m", "kdt_p2m_backward", "kdt_tree_perm",
+           "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_last_error")
+
+
+class KdtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("check_finite", C.c_int32)]
+
+
+class QueryOpts(C.Structure):
+    _fields_ = [("sort_queries", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("lo", C.c_float * 3), ("cell", C.c_float), ("n", C.c_int32 * 3)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("leaf_size", C.c_int32),
+                ("levels", C.c_int32), ("stride", C.c_int32), ("n_nodes", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2609_18316_amd.build_lib")
+    lib = C.CDLL(path)
+    vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+    lib.kdt_build.argtypes = [vp, i64, i32, C.POINTER(BuildOpts), vp, C.POINTER(vp)]
+    lib.kdt_free.argtypes = [vp]
+    lib.kdt_tree_get_info.argtypes = [vp, C.POINTER(TreeInfo)]
+    lib.kdt_tree_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.kdt_knn.argtypes = [vp, vp, i64, i32, vp, vp, i32, C.POINTER(QueryOpts), vp]
+    lib.kdt_range.argtypes = [vp, vp, i64, f32, vp, vp, vp, i64, C.POINTER(C.c_int64),
+                              C.POINTER(QueryOpts), vp]
+    lib.kdt_fof.argtypes = [vp, f32, vp, C.POINTER(C.c_int64), vp]
+    lib.kdt_p2m.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp]
+    lib.kdt_p2m_backward.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp, vp, vp]
+    lib.kdt_tree_perm.argtypes = [vp]
+    lib.kdt_tree_perm.restype = vp
+    if hasattr(lib, "kdt_batch_plan_create"):
+        lib.kdt_batch_plan_create.argtypes = [vp, i32, i32, i32, C.POINTER(BuildOpts),
+                                              C.POINTER(QueryOpts), C.POINTER(vp)]
+        lib.kdt_batch_launch.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp]
+        lib.kdt_batch_plan_free.argtypes = [vp]
+    lib.kdt_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("kdt_last_error", "kdt_tree_perm") and hasattr(lib, name):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != KDT_OK:
+        raise KdtError(rc, load().kdt_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+@dataclass
+class Info:
+    n: int
+    d: int
+    leaf_size: int
+    levels: int
+    stride: int
+    n_nodes: int
+
+
+class Tree:
+    """A device-resident k-d tree (library-owned; freed with the object)."""
+
+    def __init__(self, points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
+                 stream=None):
+        lib = load()
+        points = _dev(points, torch.float32, "points")
+        if points.dim() != 2:
+            raise ValueError("points must be [n][d]")
+        self._h = C.c_void_p()
+        opts = BuildOpts(leaf_size, 1 if check_finite else 0)
+        _check(lib.kdt_build(_ptr(points), points.shape[0], points.shape[1], C.byref(opts),
+                             _stream(stream), C.byref(self._h)))
+        info = TreeInfo()
+        _check(lib.kdt_tree_get_info(self._h, C.byref(info)))
+        self.info = Info(info.n, info.d, info.leaf_size, info.levels, info.stride, info.n_nodes)
+        self.n, self.d = info.n, info.d
+        self.device = points.device
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.kdt_free(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def perm_ptr(self) -> int:
+        """Device address of the tree order (n int32, owned by the tree)."""
+        return int(load().kdt_tree_perm(self._h))
+
+    def knn(self, queries: torch.Tensor | None, k: int, kth_only: int = 0,
+            sort_queries: bool = True, stream=None):
+        """k nearest neighbours, ascending by (d2, index): (idx [nq][k], d2 [nq][k]).
+
+        ``queries=None`` queries every point of the tree (row i = input point i).
+        ``kth_only=1`` returns only d2 of the k-th neighbour, ``2`` its distance.
+        """
+        nq = self.n if queries is None else queries.shape[0]
+        if queries is not None:
+            queries = _dev(queries, torch.float32, "queries", (nq, self.d))
+        opts = QueryOpts(1 if sort_queries else 0, 0)
+        if kth_only:
+            d2 = torch.empty(nq, dtype=torch.float32, device=self.device)
+            _check(load().kdt_knn(self._h, _ptr(queries), nq, k, None, _ptr(d2), kth_only,
+                                  C.byref(opts), _stream(stream)))
+            return d2
+        idx = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        _check(load().kdt_knn(self._h, _ptr(queries), nq, k, _ptr(idx), _ptr(d2), 0,
+                              C.byref(opts), _stream(stream)))
+        return idx, d2
+
+    def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
+              sort_queries: bool = True, stream=None):
+        """Closed-ball counts; with ``lists`` also CSR (offsets int64, idx int32)."""
+        nq = self.n if queries is None else queries.shape[0]
+        if queries is not None:
+            queries = _dev(queries, torch.float32, "queries", (nq, self.d))
+        opts = QueryOpts(1 if sort_queries else 0, 0)
+        count = torch.empty(nq, dtype=torch.int32, device=self.device)
+        lib = load()
+        if not lists:
+            _check(lib.kdt_range(self._h, _ptr(queries), nq, float(r), _ptr(count), None, None, 0,
+                                 None, C.byref(opts), _stream(stream)))
+            return count
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
+        req = C.c_int64(0)
+        _check(lib.kdt_range(self._h, _ptr(queries), nq, float(r), _ptr(count), _ptr(offsets),
+                             None, 0, C.byref(req), C.byref(opts), _stream(stream)))
+        idx = torch.empty(max(req.value, 1), dtype=torch.int32, device=self.device)
+        _check(lib.kdt_range(self._h, _ptr(queries), nq, float(r), _ptr(count), _ptr(offsets),
+                             _ptr(idx), idx.numel(), C.byref(req), C.byref(opts),
+                             _stream(stream)))
+        return count, offsets, idx[:req.value]
+
+    def fof(self, linking_length: float, count_groups: bool = False, stream=None):
+        """Friends-of-friends labels (smallest input index of each group)."""
+        labels = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        ng = C.c_int64(0)
+        _check(load().kdt_fof(self._h, float(linking_length), _ptr(labels),
+                              C.byref(ng) if count_groups else None, _stream(stream)))
+        return (labels, ng.value) if count_groups else labels
+
+    def export(self, stream=None) -> dict:
+        """Copies the tree to host numpy arrays (for inspection and tests)."""
+        import numpy as np
+        i = self.info
+        out = dict(pts=np.empty((i.n, i.d), np.float32), perm=np.empty(i.n, np.int32),
+                   lo=np.empty((i.n_nodes, i.d), np.float32),
+                   hi=np.empty((i.n_nodes, i.d), np.float32),
+                   axis=np.empty(i.n_nodes, np.int32), split=np.empty(i.n_nodes, np.float32))
+        _check(load().kdt_tree_export(self._h, out["pts"].ctypes.data, out["perm"].ctypes.data,
+                                      out["lo"].ctypes.data, out["hi"].ctypes.data,
+                                      out["axis"].ctypes.data, out["split"].ctypes.data,
+                                      _stream(stream)))
+        return out
+
+
+def build(points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
+          stream=None) -> Tree:
+    return Tree(points, leaf_size, check_finite, stream)
+
+
+def make_grid(lo, cell: float, shape) -> Grid:
+    g = Grid()
+    for a in range(3):
+        g.lo[a] = float(lo[a])
+        g.n[a] = int(shape[a])
+    g.cell = float(cell)
+    return g
+
+
+def p2m(x: torch.Tensor, m: torch.Tensor, h: torch.Tensor, lo, cell: float, shape,
+        order_ptr: int | None = None, out: torch.Tensor | None = None, stream=None):
+    """Adaptive SPH deposit: float32 mass per cell, shape ``shape``."""
+    n = x.shape[0]
+    x = _dev(x, torch.float32, "x", (n, 3))
+    m = _dev(m, torch.float32, "m", (n,))
+    h = _dev(h, torch.float32, "h", (n,))
+    if out is None:
+        out = torch.empty(tuple(shape), dtype=torch.float32, device=x.device)
+    g = make_grid(lo, cell, shape)
+    _check(load().kdt_p2m(_ptr(x), _ptr(m), _ptr(h), n, C.byref(g), order_ptr, _ptr(out),
+                          _stream(stream)))
+    return out
+
+
+def p2m_backward(x, m, h, lo, cell, shape, grad, order_ptr=None, need_m=True, need_x=True,
+                 stream=None):
+    """(dL/dm, dL/dx) of L = sum(grad * p2m(x, m, h)), h held fixed."""
+    n = x.shape[0]
+    x = _dev(x, torch.float32, "x", (n, 3))
+    m = _dev(m, torch.float32, "m", (n,))
+    h = _dev(h, torch.float32, "h", (n,))
+    grad = _dev(grad.contiguous(), torch.float32, "grad")
+    gm = torch.empty(n, dtype=torch.float32, device=x.device) if need_m else None
+    gx = torch.empty((n, 3), dtype=torch.float32, device=x.device) if need_x else None
+    g = make_grid(lo, cell, shape)
+    _check(load().kdt_p2m_backward(_ptr(x), _ptr(m), _ptr(h), n, C.byref(g), order_ptr,
+                                   _ptr(grad), _ptr(gm), _ptr(gx), _stream(stream)))
+    return gm, gx
+
+
+class P2M(torch.autograd.Function):
+    """Differentiable deposit: gradients for masses and positions, h held fixed."""
+
+    @staticmethod
+    def forward(ctx, x, m, h, grid):
+        lo, cell, shape, order_ptr = grid
+        ctx.save_for_backward(x, m, h)
+        ctx.grid = grid
+        return p2m(x.detach(), m.detach(), h.detach(), lo, cell, shape, order_ptr)
+
+    @staticmethod
+    def backward(ctx, g):
+        x, m, h = ctx.saved_tensors
+        lo, cell, shape, order_ptr = ctx.grid
+        gm, gx = p2m_backward(x.detach(), m.detach(), h.detach(), lo, cell, shape, g,
+                              order_ptr, need_m=ctx.needs_input_grad[1],
+                              need_x=ctx.needs_input_grad[0])
+        return gx, gm, None, None
+
+
+class BatchPlan:
+    """Many point sets of uneven size: fixed shapes, one launch per batch."""
+
+    def __init__(self, offsets, d: int, k: int, leaf_size: int = 32):
+        import numpy as np
+        lib = load()
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.offsets = off
+        self.n_sets = len(off) - 1
+        self.total = int(off[-1])
+        self.d, self.k = d, k
+        self._h = C.c_void_p()
+        bo = BuildOpts(leaf_size, 0)
+        qo = QueryOpts(1, 0)
+        _check(lib.kdt_batch_plan_create(off.ctypes.data, self.n_sets, d, k, C.byref(bo),
+                                         C.byref(qo), C.byref(self._h)))
+
+    def launch(self, points: torch.Tensor, linking: torch.Tensor, use_graph: bool = True,
+               out=None, stream=None):
+        points = _dev(points, torch.float32, "points", (self.total, self.d))
+        linking = _dev(linking, torch.float32, "linking", (self.n_sets,))
+        if out is None:
+            dev = points.device
+            out = (torch.empty((self.total, self.k), dtype=torch.int32, device=dev),
+                   torch.empty((self.total, self.k), dtype=torch.float32, device=dev),
+                   torch.empty(self.total, dtype=torch.int32, device=dev))
+        idx, d2, labels = out
+        _check(load().kdt_batch_launch(self._h, _ptr(points), _ptr(linking), _ptr(idx), _ptr(d2),
+                                       _ptr(labels), 1 if use_graph else 0, _stream(stream)))
+        return idx, d2, labels
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.kdt_batch_plan_free(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

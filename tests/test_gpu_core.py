@@ -1,0 +1,215 @@
+"""GPU parity: tree build, kNN, ball queries and friends-of-friends through the
+C ABI, against the CPU oracle on the same seeded inputs (bit-exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_18316_amd import kdt, workloads
+from tests import cases
+from tests.gpu_util import dev, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SIZES = (1, 2, 33, 1000, 5000, 20011)
+
+
+def check_tree_invariants(tree, x):
+    e = tree.export()
+    info = tree.info
+    n, d = x.shape
+    # levels = ceil(log2(ceil(n / leaf)))
+    L = 0
+    while -(-n // (1 << L)) > info.leaf_size:
+        L += 1
+    assert info.levels == L and info.n_nodes == (2 << L) - 1
+    assert np.array_equal(np.sort(e["perm"]), np.arange(n))
+    np.testing.assert_array_equal(e["pts"], x[e["perm"]])
+    for lev in range(L + 1):
+        for j in range(1 << lev):
+            v = (1 << lev) - 1 + j
+            b, en = (j * n) >> lev, ((j + 1) * n) >> lev
+            p = e["pts"][b:en]
+            assert en > b
+            np.testing.assert_array_equal(e["lo"][v], p.min(axis=0))
+            np.testing.assert_array_equal(e["hi"][v], p.max(axis=0))
+            if lev == L:
+                assert en - b <= info.leaf_size
+                continue
+            ext = e["hi"][v] - e["lo"][v]
+            ax = e["axis"][v]
+            assert ax == int(np.argmax(ext))
+            m = ((2 * j + 1) * n) >> (lev + 1)
+            assert p[: m - b, ax].max() <= e["split"][v] <= p[m - b:, ax].min()
+
+
+@pytest.mark.parametrize("d", kdt.DIMS)
+@pytest.mark.parametrize("kind", ("uniform", "duplicates", "lattice", "identical"))
+def test_build_invariants(d, kind):
+    dev()
+    for n in SIZES:
+        say(f"build invariants d={d} kind={kind} n={n}")
+        x = cases.points(kind, n, d, seed=n + 7 * d)
+        t = kdt.build(to_dev(x), leaf_size=8 if n < 100 else 32)
+        check_tree_invariants(t, x)
+
+
+@pytest.mark.parametrize("d", kdt.DIMS)
+@pytest.mark.parametrize("kind", ("uniform", "duplicates", "lattice", "normal"))
+def test_knn_matches_oracle(d, kind):
+    dev()
+    for n in SIZES if d <= 4 else SIZES[:-1]:
+        x = cases.points(kind, n, d, seed=3 * n + d)
+        q = cases.points(kind, 300, d, seed=11 * n + d)
+        t = kdt.build(to_dev(x), leaf_size=16)
+        ot = oracle.Tree(x, 16)
+        ks = (1, 8, 32, 64, min(n + 3, 64)) if n <= 1000 else (8, 64)
+        for k in sorted(set(ks)):
+            say(f"knn d={d} kind={kind} n={n} k={k}")
+            gi, gd = t.knn(to_dev(q), k)
+            oi, od = ot.knn(q, k)
+            np.testing.assert_array_equal(to_host(gi), oi)
+            np.testing.assert_array_equal(to_host(gd), od)
+            si, sd = t.knn(None, k)
+            oi, od = ot.knn(x, k)
+            np.testing.assert_array_equal(to_host(si), oi)
+            np.testing.assert_array_equal(to_host(sd), od)
+            kth = to_host(t.knn(None, k, kth_only=1))
+            np.testing.assert_array_equal(kth, od[:, -1])
+            h = to_host(t.knn(None, k, kth_only=2))
+            np.testing.assert_array_equal(h, np.sqrt(od[:, -1]))
+
+
+def test_unsorted_queries_give_the_same_answer():
+    dev()
+    x = workloads.clustered(50000, seed=5)
+    q = workloads.uniform(4000, 3, seed=6)
+    t = kdt.build(to_dev(x))
+    a = t.knn(to_dev(q), 16, sort_queries=True)
+    b = t.knn(to_dev(q), 16, sort_queries=False)
+    np.testing.assert_array_equal(to_host(a[0]), to_host(b[0]))
+    np.testing.assert_array_equal(to_host(a[1]), to_host(b[1]))
+
+
+def test_knn_full_small_config():
+    """65536 uniform points in [0,1)^3, leaf 32, k = 8 for every point, plus
+    radius-0.02 counts: every row bit-exact."""
+    dev()
+    x = workloads.uniform(65536, 3, seed=1)
+    say("knn C1 full")
+    t = kdt.build(to_dev(x), leaf_size=32)
+    ot = oracle.Tree(x, 32)
+    gi, gd = t.knn(None, 8)
+    oi, od = ot.knn(x, 8)
+    np.testing.assert_array_equal(to_host(gi), oi)
+    np.testing.assert_array_equal(to_host(gd), od)
+    c = to_host(t.range(None, 0.02))
+    np.testing.assert_array_equal(c, ot.range(x, 0.02))
+    check_tree_invariants(t, x)
+
+
+@pytest.mark.parametrize("d", kdt.DIMS)
+def test_range_counts_and_lists(d):
+    dev()
+    for kind in ("uniform", "lattice", "duplicates"):
+        for n in (1, 33, 5000, 20011):
+            x = cases.points(kind, n, d, seed=n + d)
+            q = cases.points(kind, 257, d, seed=2 * n + d)
+            t = kdt.build(to_dev(x), leaf_size=16)
+            ot = oracle.Tree(x, 16)
+            for r in (0.0, 0.05, 0.3):
+                say(f"range d={d} kind={kind} n={n} r={r}")
+                c, off, lst = t.range(to_dev(q), r, lists=True)
+                oc, ooff, olst = ot.range(q, r, lists=True)
+                np.testing.assert_array_equal(to_host(c), oc)
+                np.testing.assert_array_equal(to_host(off), ooff)
+                np.testing.assert_array_equal(to_host(lst), olst)
+                np.testing.assert_array_equal(to_host(t.range(None, r)), ot.range(x, r))
+
+
+def test_range_capacity_error_reports_required():
+    dev()
+    x = cases.points("uniform", 3000, 3, seed=1)
+    t = kdt.build(to_dev(x))
+    q = to_dev(x[:100])
+    count = to_dev(np.zeros(100, np.int32))
+    off = to_dev(np.zeros(101, np.int64))
+    small = to_dev(np.zeros(5, np.int32))
+    import ctypes as C
+    req = C.c_int64(0)
+    rc = kdt.load().kdt_range(t._h, q.data_ptr(), 100, 0.1, count.data_ptr(), off.data_ptr(),
+                              small.data_ptr(), 5, C.byref(req), None, None)
+    assert rc == kdt.KDT_ECAPACITY
+    assert req.value == int(oracle.Tree(x, 16).range(x[:100], 0.1).sum())
+
+
+@pytest.mark.parametrize("d", (2, 3, 8))
+def test_fof_matches_oracle(d):
+    dev()
+    for kind in ("uniform", "duplicates", "lattice"):
+        for n in (1, 2, 700, 20011):
+            x = cases.points(kind, n, d, seed=5 * n + d)
+            t = kdt.build(to_dev(x), leaf_size=16)
+            ot = oracle.Tree(x, 16)
+            for l in (0.0, 0.02, 0.1):
+                say(f"fof d={d} kind={kind} n={n} l={l}")
+                lab, ng = t.fof(l, count_groups=True)
+                ol = ot.fof(l)
+                np.testing.assert_array_equal(to_host(lab), ol)
+                assert ng == len(np.unique(ol))
+
+
+def test_fof_clustered_mock():
+    dev()
+    n = 200000
+    x = workloads.clustered(n, seed=41)
+    l = float(np.float32(0.2 * (1.0 / n) ** (1.0 / 3.0)))
+    say("fof clustered 2e5")
+    lab = to_host(kdt.build(to_dev(x)).fof(l))
+    np.testing.assert_array_equal(lab, oracle.Tree(x, 32).fof(l))
+
+
+def test_repeated_runs_are_identical():
+    dev()
+    x = workloads.clustered(100000, seed=9)
+    a = kdt.build(to_dev(x))
+    b = kdt.build(to_dev(x))
+    ea, eb = a.export(), b.export()
+    for key in ea:
+        np.testing.assert_array_equal(ea[key], eb[key])
+    np.testing.assert_array_equal(to_host(a.knn(None, 32)[0]), to_host(b.knn(None, 32)[0]))
+    np.testing.assert_array_equal(to_host(a.fof(0.003)), to_host(b.fof(0.003)))
+
+
+def test_error_paths():
+    dev()
+    import torch
+    x = cases.points("uniform", 100, 3, seed=1)
+    bad = x.copy()
+    bad[17, 1] = np.nan
+    with pytest.raises(kdt.KdtError) as e:
+        kdt.build(to_dev(bad))
+    assert e.value.status == kdt.KDT_EINVAL
+    bad[17, 1] = np.inf
+    with pytest.raises(kdt.KdtError) as e:
+        kdt.build(to_dev(bad))
+    assert e.value.status == kdt.KDT_EINVAL
+    with pytest.raises(kdt.KdtError) as e:
+        kdt.build(to_dev(cases.points("uniform", 100, 5, seed=1)))
+    assert e.value.status == kdt.KDT_EUNSUPPORTED
+    t = kdt.build(to_dev(x))
+    with pytest.raises(kdt.KdtError) as e:
+        t.knn(None, 65)
+    assert e.value.status == kdt.KDT_EUNSUPPORTED
+    with pytest.raises(kdt.KdtError) as e:
+        t.knn(None, 0)
+    assert e.value.status == kdt.KDT_EINVAL
+    with pytest.raises(kdt.KdtError) as e:
+        t.range(None, -1.0)
+    assert e.value.status == kdt.KDT_EINVAL
+    with pytest.raises(kdt.KdtError) as e:
+        t.fof(float("nan"))
+    assert e.value.status == kdt.KDT_EINVAL
+    with pytest.raises(kdt.KdtError) as e:
+        kdt.build(to_dev(x), leaf_size=1)
+    assert e.value.status == kdt.KDT_EINVAL
+    assert torch.cuda.is_available()
