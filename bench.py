@@ -1,0 +1,213 @@
+"""Benchmark of the k-d tree hot path on one MI355X.
+
+One step runs every stage of the path on the clustered workload: a tree over
+2^24 clustered 3-D points (2000 Gaussian halos + 20 % uniform background),
+kNN (k = 32) of 2^22 uniform query points, closed-ball counts (r = 0.01) of the
+same queries, friends-of-friends of the 2^24 points (b = 0.2), SPH smoothing
+lengths (distance to the 32nd neighbour of every point), the particle-to-mesh
+deposit onto a 256^3 mesh and its adjoint, and -- when the batched plan is
+available -- the batched forest of 256 clustered sets (kNN k = 8 + FoF).
+
+Inputs are generated on the host and copied to the GPU before timing.  Each
+stage is timed with HIP events on the stream that runs it; the headline value
+is kNN queries per second of the k = 32 stage.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_POINTS = 1 << 24
+N_QUERIES = 1 << 22
+K = 32
+RADIUS = 0.01
+FOF_B = 0.2
+GRID = 256
+LEAF = 32
+HBM_PEAK_GBS = 8000.0
+BATCH_SETS = 256
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--cpu-queries", type=int, default=1 << 14)
+    return ap.parse_args()
+
+
+def linking_length(n: int) -> float:
+    return float(np.float32(FOF_B * (1.0 / n) ** (1.0 / 3.0)))
+
+
+def cpu_baseline(x, q, n_q):
+    """The CPU oracle (single thread): tree build over all points, then kNN of
+    a bounded sample of the queries."""
+    import oracle
+    t0 = time.perf_counter()
+    tree = oracle.Tree(x, LEAF)
+    t1 = time.perf_counter()
+    tree.knn(q[:n_q], K)
+    t2 = time.perf_counter()
+    return {"value": n_q / (t2 - t1), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle tree over all {x.shape[0]} points (build {t1 - t0:.1f} s, "
+                      f"{x.shape[0] / (t1 - t0) / 1e6:.2f} Mpts/s), kNN k={K} of the first "
+                      f"{n_q} of the {q.shape[0]} queries",
+            "build_mpts_s": x.shape[0] / (t1 - t0) / 1e6}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2609_18316_amd import kdt, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    kdt.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    t_gen = time.perf_counter()
+    x = workloads.clustered(N_POINTS, seed=2)
+    q = workloads.uniform(N_QUERIES, 3, seed=102)
+    m = workloads.masses(N_POINTS, seed=5)
+    print(f"[bench] inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
+          flush=True)
+    xt = torch.from_numpy(x).to(dev)
+    qt = torch.from_numpy(q).to(dev)
+    mt = torch.from_numpy(m).to(dev)
+    gen = torch.Generator(device=dev).manual_seed(7)
+    gg = torch.randn((GRID,) * 3, device=dev, generator=gen)
+    lo, cell, shape = (0.0, 0.0, 0.0), 1.0 / GRID, (GRID,) * 3
+    l_fof = linking_length(N_POINTS)
+
+    batch = None
+    if not args.no_batch and hasattr(kdt.load(), "kdt_batch_plan_create"):
+        sizes = workloads.batch_sizes(BATCH_SETS, 3.0, 6.0, seed=4)
+        bx, boff = workloads.batched_clustered(sizes, seed_base=40000)
+        bl = np.array([linking_length(int(s)) for s in sizes], np.float32)
+        plan = kdt.BatchPlan(boff, 3, 8, LEAF)
+        bxt = torch.from_numpy(bx).to(dev)
+        blt = torch.from_numpy(bl).to(dev)
+        bout = (torch.empty((int(boff[-1]), 8), dtype=torch.int32, device=dev),
+                torch.empty((int(boff[-1]), 8), dtype=torch.float32, device=dev),
+                torch.empty(int(boff[-1]), dtype=torch.int32, device=dev))
+        batch = (plan, bxt, blt, bout, int(boff[-1]))
+
+    phases = ["build", "knn", "range", "fof", "hsml", "p2m_fwd", "p2m_bwd"]
+    if batch:
+        phases += ["batch_graph", "batch_eager"]
+    ev = {p: [] for p in phases}
+    torch.cuda.synchronize()
+
+    def step(record):
+        marks = {}
+
+        def mark(name):
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            marks[name] = e
+
+        mark("start")
+        tree = kdt.build(xt, leaf_size=LEAF, check_finite=True)
+        mark("build")
+        idx, d2 = tree.knn(qt, K)
+        mark("knn")
+        cnt = tree.range(qt, RADIUS)
+        mark("range")
+        lab = tree.fof(l_fof)
+        mark("fof")
+        h = tree.knn(None, K, kth_only=2)
+        mark("hsml")
+        rho = kdt.p2m(xt, mt, h, lo, cell, shape, order_ptr=tree.perm_ptr)
+        mark("p2m_fwd")
+        gm, gx = kdt.p2m_backward(xt, mt, h, lo, cell, shape, gg, order_ptr=tree.perm_ptr)
+        mark("p2m_bwd")
+        if batch:
+            plan, bxt, blt, bout, _ = batch
+            plan.launch(bxt, blt, use_graph=True, out=bout)
+            mark("batch_graph")
+            plan.launch(bxt, blt, use_graph=False, out=bout)
+            mark("batch_eager")
+        if record:
+            order = ["start"] + phases
+            torch.cuda.synchronize()
+            for a, b in zip(order[:-1], order[1:]):
+                ev[b].append(marks[a].elapsed_time(marks[b]))
+        return tree, (idx, d2, cnt, lab, rho, gm, gx)
+
+    for _ in range(args.warmup):
+        keep = step(False)
+        del keep
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        keep = step(True)
+        del keep
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed * 1e3 / args.steps
+    avg = {p: float(np.mean(ev[p])) for p in phases}
+
+    knn_qps = N_QUERIES / (avg["knn"] * 1e-3)
+    # Roofline of the kNN stage: compulsory bytes per query are the query
+    # coordinates in (4 d) plus k (index, d2) pairs out (8 k).
+    knn_bytes = N_QUERIES * (4 * 3 + 8 * K)
+    achieved = knn_bytes / (avg["knn"] * 1e-3) / 1e9
+    out = {
+        "metric": "kNN queries/s (k=32, 2^24 pts) + build Mpts/s; batched speedup; P2M bwd/fwd",
+        "value": knn_qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "clustered 3-D, 2^24 points (2000 Gaussian halos + 20% uniform), "
+                        "2^22 uniform queries, kNN k=32, ball r=0.01, FoF b=0.2, "
+                        "SPH P2M 256^3 with adjoint, batched 256 clustered sets",
+            "n_points": N_POINTS, "n_queries": N_QUERIES, "k": K, "radius": RADIUS,
+            "leaf_size": LEAF, "grid": GRID, "fof_linking_length": l_fof,
+        },
+        "phases_ms": avg,
+        "build_mpts_s": N_POINTS / (avg["build"] * 1e-3) / 1e6,
+        "knn_queries_s": knn_qps,
+        "range_queries_s": N_QUERIES / (avg["range"] * 1e-3),
+        "fof_mpts_s": N_POINTS / (avg["fof"] * 1e-3) / 1e6,
+        "p2m_bwd_over_fwd": avg["p2m_bwd"] / avg["p2m_fwd"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "kNN stage (k=32), compulsory bytes 4d + 8k per query"},
+    }
+    if batch:
+        out["batched_speedup"] = avg["batch_eager"] / avg["batch_graph"]
+        out["batched_points"] = batch[4]
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(x, q, args.cpu_queries)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

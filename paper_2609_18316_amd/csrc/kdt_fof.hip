@@ -95,11 +95,19 @@ __global__ void k_fof_init(int32_t* __restrict__ parent, int64_t n) {
   if (i < n) parent[i] = (int32_t)i;
 }
 
+// Points every element at its root.  No path shortcuts here: each element is
+// written by its own lane only, so no lane can overwrite a finished label with
+// an intermediate ancestor.
 __global__ void k_fof_final(int32_t* __restrict__ parent, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    const int32_t r = uf_find(parent, (int32_t)i);
-    st_rel(parent + i, r);
+    int32_t cur = (int32_t)i;
+    for (;;) {
+      const int32_t next = ld_rel(parent + cur);
+      if (next >= cur) break;
+      cur = next;
+    }
+    st_rel(parent + i, cur);
   }
 }
 
