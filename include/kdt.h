@@ -238,8 +238,14 @@ const int32_t *kdt_tree_perm(const kdt_tree *tree);
  * point of the set (k from the plan) and friends-of-friends with the set's
  * linking length d_l[s] (device, float32 [n_sets]).  Outputs use set-local
  * indices: d_idx / d_d2 [total][k], d_labels [total].  Results are identical
- * to kdt_build + kdt_knn(NULL) + kdt_fof on each set.  With use_graph = 1 the
- * whole pipeline is captured once into a hipGraph and replayed.
+ * to kdt_build + kdt_knn(NULL) + kdt_fof on each set.
+ * use_graph = 1: the batched pipeline (forest build whose level kernels cover
+ *   every set, persistent work-queue kNN and grouping kernels) is captured into
+ *   a hipGraph on the first call and replayed; a call with different pointers
+ *   captures again.  Nothing is allocated per call.
+ * use_graph = 2: the same batched kernels launched eagerly (no graph).
+ * use_graph = 0: the per-set baseline -- kdt_build, kdt_knn and kdt_fof called
+ *   once per set, eagerly (waits on `stream` to read d_l).
  *
  * Errors: KDT_EINVAL, KDT_EUNSUPPORTED, KDT_ENOMEM, KDT_EDEVICE.
  */

@@ -41,7 +41,7 @@ struct CachedPlan {
 
 static std::mutex g_plan_mu;
 static std::list<std::shared_ptr<CachedPlan>> g_plans;
-constexpr size_t kPlanCache = 8;
+constexpr size_t kPlanCache = 512;
 
 static kdt_status get_plan(int device, int64_t n, int d, int leaf, hipStream_t stream,
                            std::shared_ptr<CachedPlan>& out) {

@@ -827,6 +827,7 @@ kdt_status build_scratch_alloc(const Plan& p, const PlanDev& pd, BuildScratch& w
   const int64_t tot = p.total;
   const int d = p.d;
   auto A = [&](void** ptr, size_t bytes) -> bool {
+    if (stream == kPlainAlloc) return hipMalloc(ptr, std::max<size_t>(bytes, 256)) == hipSuccess;
     return dev_alloc(ptr, bytes, stream) == hipSuccess;
   };
   bool ok = A((void**)&w.x[0], sizeof(float) * d * tot) && A((void**)&w.x[1], sizeof(float) * d * tot) &&
@@ -848,7 +849,7 @@ kdt_status build_scratch_alloc(const Plan& p, const PlanDev& pd, BuildScratch& w
 void build_scratch_free(BuildScratch& w, hipStream_t stream) {
   void* ptrs[] = {w.x[0], w.x[1], w.p[0], w.p[1], w.ubox, w.st, w.hist, w.ctr, w.cnt, w.pref, w.bad};
   for (void* q : ptrs)
-    if (q) (void)hipFreeAsync(q, stream);
+    if (q) (void)(stream == kPlainAlloc ? hipFree(q) : hipFreeAsync(q, stream));
   w = BuildScratch();
 }
 
@@ -862,13 +863,7 @@ static void zero_u32(uint32_t* p, int64_t n, hipStream_t stream) {
   k_zero_u32<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(p, n);
 }
 
-kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
-                        const BuildScratch& w, const BuildOut& o, int phase, hipStream_t stream) {
-  if (phase == 0) {
-    zero_u32(w.hist, 256 * (int64_t)pd.max_segs, stream);
-    zero_u32(w.ctr, (int64_t)pd.max_segs, stream);
-    zero_u32(reinterpret_cast<uint32_t*>(w.bad), 1, stream);
-  }
+void build_init_once() {
   static std::once_flag attr_once;
   std::call_once(attr_once, [] {
     set_smem_attr<2>(lds_capacity(2));
@@ -877,6 +872,16 @@ kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
     set_smem_attr<8>(lds_capacity(8));
     set_smem_attr<16>(lds_capacity(16));
   });
+}
+
+kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
+                        const BuildScratch& w, const BuildOut& o, int phase, hipStream_t stream) {
+  if (phase == 0) {
+    zero_u32(w.hist, 256 * (int64_t)pd.max_segs, stream);
+    zero_u32(w.ctr, (int64_t)pd.max_segs, stream);
+    zero_u32(reinterpret_cast<uint32_t*>(w.bad), 1, stream);
+  }
+  build_init_once();
   switch (p.d) {
     case 2: return run_build<2>(p, pd, d_pts, w, o, phase, stream);
     case 3: return run_build<3>(p, pd, d_pts, w, o, phase, stream);

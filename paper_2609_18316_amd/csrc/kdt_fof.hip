@@ -16,45 +16,6 @@ namespace kdt {
 
 constexpr int kFBlock = 128;
 
-__device__ __forceinline__ int32_t ld_rel(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Root of x.  parent[y] <= y always holds, and only roots change owner, so
-// shortcutting a non-root to any of its ancestors is always valid.
-__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
-  int32_t cur = ld_rel(parent + x);
-  if (cur == x) return x;
-  int32_t prev = x;
-  for (;;) {
-    const int32_t next = ld_rel(parent + cur);
-    if (next >= cur) break;
-    st_rel(parent + prev, next);
-    prev = cur;
-    cur = next;
-  }
-  return cur;
-}
-
-// Joins the sets of a and b: the larger root is hooked under the smaller.
-__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
-  int32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
-  while (ra != rb) {
-    if (ra < rb) {
-      const int32_t old = atomicCAS(parent + rb, rb, ra);
-      if (old == rb) break;
-      rb = old;
-    } else {
-      const int32_t old = atomicCAS(parent + ra, ra, rb);
-      if (old == ra) break;
-      ra = old;
-    }
-  }
-}
-
 template <int D>
 __global__ __launch_bounds__(kFBlock) void k_fof_link(TreeView t, float l2,
                                                       int32_t* __restrict__ parent) {
@@ -64,30 +25,8 @@ __global__ __launch_bounds__(kFBlock) void k_fof_link(TreeView t, float l2,
   float p[D];
   int32_t me = 0;
   load_rec<D>(t.rec, s, p, me);
-  const uint32_t first_leaf = (1u << t.levels) - 1u;
-  int sp = 0;
-  stk[sp++][threadIdx.x] = 0;
-  while (sp > 0) {
-    const uint32_t node = stk[--sp][threadIdx.x];
-    float lo[D], hi[D];
-    load_box<D>(t.box, node, lo, hi);
-    if (box_mindist<D>(lo, hi, p) > l2) continue;
-    const int lev = node_level(node);
-    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
-    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
-    const bool all_in = box_maxdist<D>(lo, hi, p) <= l2;
-    if (all_in || node >= first_leaf) {
-      for (int64_t i = b; i < e; ++i) {
-        float x[D];
-        int32_t id = 0;
-        load_rec<D>(t.rec, i, x, id);
-        if (id > me && (all_in || sq_dist<D>(x, p) <= l2)) uf_union(parent, me, id);
-      }
-      continue;
-    }
-    stk[sp++][threadIdx.x] = 2 * node + 2;
-    stk[sp++][threadIdx.x] = 2 * node + 1;
-  }
+  fof_one<D>(t, p, me, l2, &stk[0][threadIdx.x], kFBlock,
+             [&](int32_t id) { uf_union(parent, me, id); });
 }
 
 __global__ void k_fof_init(int32_t* __restrict__ parent, int64_t n) {
@@ -101,13 +40,7 @@ __global__ void k_fof_init(int32_t* __restrict__ parent, int64_t n) {
 __global__ void k_fof_final(int32_t* __restrict__ parent, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    int32_t cur = (int32_t)i;
-    for (;;) {
-      const int32_t next = ld_rel(parent + cur);
-      if (next >= cur) break;
-      cur = next;
-    }
-    st_rel(parent + i, cur);
+    uf_st(parent + i, uf_root(parent, (int32_t)i));
   }
 }
 

@@ -162,8 +162,13 @@ struct BuildOut {
 
 kdt_status plan_upload(const Plan& p, PlanDev& pd, hipStream_t stream);
 void plan_release(PlanDev& pd);
+// Passing kPlainAlloc as the stream allocates with hipMalloc instead of the
+// stream-ordered pool (used by batch plans, whose buffers live in a graph).
+static const hipStream_t kPlainAlloc = reinterpret_cast<hipStream_t>(~uintptr_t(0));
 kdt_status build_scratch_alloc(const Plan& p, const PlanDev& pd, BuildScratch& w,
                                hipStream_t stream);
+// Sets kernel attributes once (must run outside any graph capture).
+void build_init_once();
 void build_scratch_free(BuildScratch& w, hipStream_t stream);
 // phase 0: ingest and root boxes; phase 1: everything after.
 kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,

@@ -133,4 +133,160 @@ __device__ __forceinline__ uint64_t make_key(float d2, int32_t idx) {
   return ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)idx;
 }
 
+// kNN of one query p over tree t (Algorithm 2 semantics): depth-first, nearer
+// child first, a node is skipped when its box is farther than the current
+// k-th candidate.  `stk` is this lane's column of an LDS stack with stride
+// `ld` entries.
+template <int D, int KC>
+__device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], TopK<KC>& best,
+                                        uint64_t* stk, int ld) {
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  float lo[D], hi[D];
+  load_box<D>(t.box, 0, lo, hi);
+  uint32_t node = 0;
+  float nd = box_mindist<D>(lo, hi, p);
+  int sp = 0;
+  for (;;) {
+    if (nd <= best.worst_d2()) {
+      if (node >= first_leaf) {
+        const int64_t j = node - first_leaf;
+        const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
+        for (int64_t i = b; i < e; ++i) {
+          float x[D];
+          int32_t id = 0;
+          load_rec<D>(t.rec, i, x, id);
+          const uint64_t key = make_key(sq_dist<D>(x, p), id);
+          if (key < best.worst()) best.insert(key);
+        }
+      } else {
+        const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
+        load_box<D>(t.box, c0, lo, hi);
+        const float d0 = box_mindist<D>(lo, hi, p);
+        load_box<D>(t.box, c1, lo, hi);
+        const float d1 = box_mindist<D>(lo, hi, p);
+        const bool first0 = d0 <= d1;
+        const uint32_t nn = first0 ? c0 : c1, ff = first0 ? c1 : c0;
+        const float dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
+        if (df <= best.worst_d2()) {
+          stk[sp * ld] = ((uint64_t)ff << 32) | __float_as_uint(df);
+          ++sp;
+        }
+        node = nn;
+        nd = dn;
+        continue;
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    const uint64_t e = stk[sp * ld];
+    node = (uint32_t)(e >> 32);
+    nd = __uint_as_float((uint32_t)e);
+  }
+}
+
+// Writes one kNN row: mode 0 -> k (index, d2) pairs, 1 -> d2 of the k-th,
+// 2 -> distance of the k-th.
+template <int KC>
+__device__ __forceinline__ void knn_write(const TopK<KC>& best, int k, int mode, int64_t row,
+                                          int32_t* __restrict__ oidx, float* __restrict__ od2) {
+  if (mode == 0) {
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+      if (j < KC - k) continue;
+      const uint64_t key = best.a[j];
+      const bool empty = key == kEmptyKey;
+      const int64_t o = row * k + (j - (KC - k));
+      if (oidx) oidx[o] = empty ? -1 : (int32_t)(uint32_t)key;
+      od2[o] = empty ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
+    }
+  } else {
+    const uint64_t key = best.a[KC - 1];
+    const float d2 = key == kEmptyKey ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
+    od2[row] = mode == 2 ? sqrtf(d2) : d2;
+  }
+}
+
+// Friends-of-friends links of the point at tree position s (index `me`):
+// every friend with a larger index is passed to `link(friend_index)`.
+template <int D, typename F>
+__device__ __forceinline__ void fof_one(const TreeView& t, const float p[D], int32_t me, float l2,
+                                        uint32_t* stk, int ld, F&& link) {
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int sp = 0;
+  stk[0] = 0;
+  sp = 1;
+  while (sp > 0) {
+    const uint32_t node = stk[--sp * ld];
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (box_mindist<D>(lo, hi, p) > l2) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    const bool all_in = box_maxdist<D>(lo, hi, p) <= l2;
+    if (all_in || node >= first_leaf) {
+      for (int64_t i = b; i < e; ++i) {
+        float x[D];
+        int32_t id = 0;
+        load_rec<D>(t.rec, i, x, id);
+        if (id > me && (all_in || sq_dist<D>(x, p) <= l2)) link(id);
+      }
+      continue;
+    }
+    stk[sp++ * ld] = 2 * node + 2;
+    stk[sp++ * ld] = 2 * node + 1;
+  }
+}
+
+// Lock-free union-find on int32 parents with parent[y] <= y.
+__device__ __forceinline__ int32_t uf_ld(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void uf_st(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x.  Only roots change owner, so shortcutting a non-root to any of
+// its ancestors is always valid.
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+  int32_t cur = uf_ld(parent + x);
+  if (cur == x) return x;
+  int32_t prev = x;
+  for (;;) {
+    const int32_t next = uf_ld(parent + cur);
+    if (next >= cur) break;
+    uf_st(parent + prev, next);
+    prev = cur;
+    cur = next;
+  }
+  return cur;
+}
+
+// Joins the sets of a and b: the larger root is hooked under the smaller, so
+// every root is the smallest index of its set.
+__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+  int32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+  while (ra != rb) {
+    if (ra < rb) {
+      const int32_t old = atomicCAS(parent + rb, rb, ra);
+      if (old == rb) break;
+      rb = old;
+    } else {
+      const int32_t old = atomicCAS(parent + ra, ra, rb);
+      if (old == ra) break;
+      ra = old;
+    }
+  }
+}
+
+// Root of x without shortcuts (safe while other lanes write final labels).
+__device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
+  int32_t cur = x;
+  for (;;) {
+    const int32_t next = uf_ld(parent + cur);
+    if (next >= cur) return cur;
+    cur = next;
+  }
+}
+
 }  // namespace kdt

@@ -47,63 +47,8 @@ __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* _
   }
   TopK<KC> best;
   best.init(k);
-  const uint32_t first_leaf = (1u << t.levels) - 1u;
-  float lo[D], hi[D];
-  load_box<D>(t.box, 0, lo, hi);
-  uint32_t node = 0;
-  float nd = box_mindist<D>(lo, hi, p);
-  int sp = 0;
-  for (;;) {
-    if (nd <= best.worst_d2()) {
-      if (node >= first_leaf) {
-        const int64_t j = node - first_leaf;
-        const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
-        for (int64_t i = b; i < e; ++i) {
-          float x[D];
-          int32_t id = 0;
-          load_rec<D>(t.rec, i, x, id);
-          const uint64_t key = make_key(sq_dist<D>(x, p), id);
-          if (key < best.worst()) best.insert(key);
-        }
-      } else {
-        const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
-        load_box<D>(t.box, c0, lo, hi);
-        const float d0 = box_mindist<D>(lo, hi, p);
-        load_box<D>(t.box, c1, lo, hi);
-        const float d1 = box_mindist<D>(lo, hi, p);
-        const bool first0 = d0 <= d1;
-        const uint32_t nn = first0 ? c0 : c1, ff = first0 ? c1 : c0;
-        const float dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
-        if (df <= best.worst_d2()) {
-          stk[sp][threadIdx.x] = ((uint64_t)ff << 32) | __float_as_uint(df);
-          ++sp;
-        }
-        node = nn;
-        nd = dn;
-        continue;
-      }
-    }
-    if (sp == 0) break;
-    --sp;
-    const uint64_t e = stk[sp][threadIdx.x];
-    node = (uint32_t)(e >> 32);
-    nd = __uint_as_float((uint32_t)e);
-  }
-  if (mode == 0) {
-#pragma unroll
-    for (int j = 0; j < KC; ++j) {
-      if (j < KC - k) continue;
-      const uint64_t key = best.a[j];
-      const bool empty = key == kEmptyKey;
-      const int64_t o = row * k + (j - (KC - k));
-      if (oidx) oidx[o] = empty ? -1 : (int32_t)(uint32_t)key;
-      od2[o] = empty ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
-    }
-  } else {
-    const uint64_t key = best.a[KC - 1];
-    float d2 = key == kEmptyKey ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
-    od2[row] = mode == 2 ? sqrtf(d2) : d2;
-  }
+  knn_one<D, KC>(t, p, best, &stk[0][threadIdx.x], kQBlock);
+  knn_write<KC>(best, k, mode, row, oidx, od2);
 }
 
 // ---------------------------------------------------------------------------

@@ -306,8 +306,13 @@ class BatchPlan:
         _check(lib.kdt_batch_plan_create(off.ctypes.data, self.n_sets, d, k, C.byref(bo),
                                          C.byref(qo), C.byref(self._h)))
 
-    def launch(self, points: torch.Tensor, linking: torch.Tensor, use_graph: bool = True,
+    def launch(self, points: torch.Tensor, linking: torch.Tensor, use_graph: int = 1,
                out=None, stream=None):
+        """Builds every set and runs kNN (k from the plan) and friends-of-friends.
+
+        use_graph: 1 batched kernels replayed from a hipGraph, 2 the same kernels
+        launched eagerly, 0 the per-set baseline (single-tree calls per set).
+        """
         points = _dev(points, torch.float32, "points", (self.total, self.d))
         linking = _dev(linking, torch.float32, "linking", (self.n_sets,))
         if out is None:
@@ -317,7 +322,7 @@ class BatchPlan:
                    torch.empty(self.total, dtype=torch.int32, device=dev))
         idx, d2, labels = out
         _check(load().kdt_batch_launch(self._h, _ptr(points), _ptr(linking), _ptr(idx), _ptr(d2),
-                                       _ptr(labels), 1 if use_graph else 0, _stream(stream)))
+                                       _ptr(labels), int(use_graph), _stream(stream)))
         return idx, d2, labels
 
     def close(self):
