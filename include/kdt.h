@@ -64,7 +64,11 @@ typedef struct {
     int32_t sort_queries; /* 1: reorder external queries along the tree before the
                              traversal (more coherent waves); 0: input order.
                              Results are identical either way. */
-    int32_t reserved;
+    int32_t traversal;    /* kNN only.  0: default (2).  1: one independent
+                             traversal per lane.  2: one traversal shared by the
+                             64 queries of a wave, leaves staged in LDS (trees
+                             with leaf_size <= 64; larger leaves use 1).
+                             Results are identical either way. */
 } kdt_query_opts;
 
 /* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side

@@ -88,11 +88,42 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 }
 
 template <int D>
+__global__ void k_fof_forest_mark(const SetDesc* __restrict__ sets, int n_sets,
+                                  const float* __restrict__ box, int64_t n_nodes,
+                                  const float* __restrict__ lengths, uint32_t* __restrict__ conn) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_nodes) return;
+  int lo = 0, hi = n_sets - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sets[mid].node_base <= v) lo = mid;
+    else hi = mid - 1;
+  }
+  const float l = lengths[lo];
+  fof_mark_clique<D>(box, v, l * l, conn);
+}
+
+template <int D>
+__global__ void k_fof_forest_join(const SetDesc* __restrict__ sets, int n_sets,
+                                  const float* __restrict__ rec, const float* __restrict__ box,
+                                  int64_t total, int32_t* __restrict__ parent,
+                                  const uint32_t* __restrict__ conn) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= total) return;
+  const SetDesc sd = sets[find_set(sets, n_sets, row)];
+  const TreeView t = set_view<D>(sd, rec, box);
+  const int64_t pos = row - sd.off;
+  fof_join_clique<D>(t, pos, __float_as_int(t.rec[pos * rec_stride(D) + D]), (int32_t)sd.off,
+                     parent, conn + sd.node_base);
+}
+
+template <int D>
 __global__ __launch_bounds__(kBQ) void k_fof_forest(const SetDesc* __restrict__ sets, int n_sets,
                                                     const float* __restrict__ rec,
                                                     const float* __restrict__ box, int64_t total,
                                                     const float* __restrict__ lengths,
                                                     int32_t* __restrict__ parent,
+                                                    uint32_t* __restrict__ conn,
                                                     unsigned long long* __restrict__ ctr) {
   __shared__ uint32_t stk[kMaxDepth][kBQ];
   __shared__ int64_t slot;
@@ -109,10 +140,10 @@ __global__ __launch_bounds__(kBQ) void k_fof_forest(const SetDesc* __restrict__ 
       const float l2 = l * l;
       float q[D];
       int32_t me = 0;
-      load_rec<D>(t.rec, row - sd.off, q, me);
-      const int32_t base = (int32_t)sd.off;
-      fof_one<D>(t, q, me, l2, &stk[0][threadIdx.x], kBQ,
-                 [&](int32_t id) { uf_union(parent, base + me, base + id); });
+      const int64_t pos = row - sd.off;
+      load_rec<D>(t.rec, pos, q, me);
+      fof_point<D>(t, q, pos, me, l2, (int32_t)sd.off, parent, conn + sd.node_base,
+                   &stk[0][threadIdx.x], kBQ);
     }
   }
 }
@@ -139,6 +170,7 @@ struct kdt_batch_plan {
   void* tree_block = nullptr;
   BuildOut out{};
   int32_t* parent = nullptr;
+  uint32_t* conn = nullptr;
   unsigned long long* ctr = nullptr;
   int knn_blocks = 0, fof_blocks = 0;
   hipStream_t cap = nullptr;
@@ -178,8 +210,12 @@ static kdt_status forest_queries(kdt_batch_plan* bp, const float* d_l, int32_t* 
                                                        tot, k, d_idx, d_d2, bp->ctr);
   const unsigned g = (unsigned)((tot + 255) / 256);
   k_iota_i32<<<g, 256, 0, s>>>(bp->parent, tot);
+  const unsigned gn = (unsigned)((p.n_nodes + 255) / 256);
+  k_fof_forest_mark<D><<<gn, 256, 0, s>>>(bp->dev.sets, ns, bp->out.box, p.n_nodes, d_l, bp->conn);
+  k_fof_forest_join<D><<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box, tot,
+                                         bp->parent, bp->conn);
   k_fof_forest<D><<<bp->fof_blocks, kBQ, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box, tot,
-                                                 d_l, bp->parent, bp->ctr + 1);
+                                                 d_l, bp->parent, bp->conn, bp->ctr + 1);
   k_fof_forest_final<<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->parent, tot, d_labels);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_batch_launch: kernel launch failed");
@@ -221,6 +257,7 @@ static void release(kdt_batch_plan* bp) {
   build_scratch_free(bp->w, kPlainAlloc);
   if (bp->tree_block) (void)hipFree(bp->tree_block);
   if (bp->parent) (void)hipFree(bp->parent);
+  if (bp->conn) (void)hipFree(bp->conn);
   if (bp->ctr) (void)hipFree(bp->ctr);
   plan_release(bp->dev);
 }
@@ -280,6 +317,8 @@ extern "C" kdt_status kdt_batch_plan_create(const int64_t* h_offsets, int32_t n_
       (hipMalloc(&bp->tree_block, up(b_rec) + up(b_box) + up(b_perm) + up(b_axis) + up(b_split)) !=
            hipSuccess ||
        hipMalloc((void**)&bp->parent, sizeof(int32_t) * std::max<int64_t>(tot, 1)) != hipSuccess ||
+       hipMalloc((void**)&bp->conn, sizeof(uint32_t) * std::max<int64_t>(bp->plan.n_nodes, 1)) !=
+           hipSuccess ||
        hipMalloc((void**)&bp->ctr, 256) != hipSuccess)) {
     kdt_set_error("kdt_batch_plan_create: device allocation failed (%lld points)", (long long)tot);
     st = KDT_ENOMEM;

@@ -278,8 +278,15 @@ __global__ void k_level_init(const SegEntry* __restrict__ segs, int nseg, SegSta
   }
 }
 
-// One 8-bit radix-select pass.  The last workgroup of each segment scans the
-// merged histogram and narrows the pivot.
+// One radix-select pass over 11-bit digits (three passes resolve a 32-bit
+// key).  Lanes of a wave that fall in the same bin as the wave's first lane
+// add their count with one LDS atomic (clustered data puts most keys of a
+// node in few bins).  The last workgroup of each segment scans the merged
+// histogram and narrows the pivot.
+constexpr int kDigitBits = 11;
+constexpr int kBins = 1 << kDigitBits;
+constexpr int kRadixPasses = (32 + kDigitBits - 1) / kDigitBits;
+
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void k_radix_pass(const ChunkEntry* __restrict__ chunks,
                                                             const SegEntry* __restrict__ segs,
@@ -287,44 +294,78 @@ __global__ __launch_bounds__(kBuildBlock) void k_radix_pass(const ChunkEntry* __
                                                             uint32_t* __restrict__ hist,
                                                             uint32_t* __restrict__ ctr,
                                                             const float* __restrict__ x, int64_t tot) {
-  __shared__ uint32_t h[256];
+  __shared__ uint32_t h[kBins];
   __shared__ uint32_t tmp[4];
   __shared__ int is_last;
   const ChunkEntry ch = chunks[blockIdx.x];
   const SegState s = st[ch.seg];
   if (s.hb < 0) return;
-  const int tid = threadIdx.x;
-  h[tid] = 0;
+  const int tid = threadIdx.x, lane = lane_id();
+  for (int b = tid; b < kBins; b += kBuildBlock) h[b] = 0;
   __syncthreads();
-  const int sh = s.hb >= 7 ? s.hb - 7 : 0;
+  const int sh = s.hb >= kDigitBits - 1 ? s.hb - (kDigitBits - 1) : 0;
   const uint32_t dmask = (1u << (s.hb - sh + 1)) - 1u;
   const uint64_t want = (uint64_t)s.prefix >> (s.hb + 1);
   const float* kx = x + (int64_t)s.axis * tot;
-  for (int64_t i = ch.b + tid; i < ch.e; i += kBuildBlock) {
-    uint32_t k = fkey(kx[i]);
-    if (((uint64_t)k >> (s.hb + 1)) == want) atomicAdd(&h[(k >> sh) & dmask], 1u);
+  for (int64_t base = ch.b; base < ch.e; base += kBuildBlock) {
+    const int64_t i = base + tid;
+    bool ok = false;
+    uint32_t bin = 0;
+    if (i < ch.e) {
+      const uint32_t k = fkey(kx[i]);
+      ok = ((uint64_t)k >> (s.hb + 1)) == want;
+      bin = (k >> sh) & dmask;
+    }
+    const uint64_t m_ok = __ballot(ok);
+    if (m_ok == 0) continue;
+    const uint32_t lead = (uint32_t)__builtin_amdgcn_readlane((int)bin, __ffsll((unsigned long long)m_ok) - 1);
+    const bool same = ok && bin == lead;
+    const uint64_t m = __ballot(same);
+    if (same) {
+      if (lanes_below(m) == 0) atomicAdd(&h[lead], (uint32_t)__popcll(m));
+    } else if (ok) {
+      atomicAdd(&h[bin], 1u);
+    }
   }
   __syncthreads();
-  uint32_t* gh = hist + (int64_t)ch.seg * 256;
-  if (h[tid]) atomicAdd(gh + tid, h[tid]);
+  uint32_t* gh = hist + (int64_t)ch.seg * kBins;
+  for (int b = tid; b < kBins; b += kBuildBlock)
+    if (h[b]) atomicAdd(gh + b, h[b]);
   __threadfence();
   __syncthreads();
   if (tid == 0) is_last = atomicAdd(ctr + ch.seg, 1u) == (uint32_t)(segs[ch.seg].n_chunks - 1);
   __syncthreads();
   if (!is_last) return;
   __threadfence();
-  uint32_t c = ld_acquire_u32(gh + tid);
-  uint32_t inc = block_incl_scan(c, tmp);
-  uint32_t exc = inc - c;
-  uint32_t r = (uint32_t)s.rank;
+  constexpr int per = kBins / kBuildBlock;
+  uint32_t c[per];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    c[q] = ld_acquire_u32(gh + tid * per + q);
+    sum += c[q];
+  }
+  const uint32_t inc = block_incl_scan(sum, tmp);
+  const uint32_t exc = inc - sum;
+  const uint32_t r = (uint32_t)s.rank;
   if (exc <= r && r < inc) {
+    uint32_t rr = r - exc;
+    int b = 0;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+      if (b == q && rr >= c[q]) {
+        rr -= c[q];
+        b = q + 1;
+      }
+    }
     SegState ns = s;
-    ns.prefix = s.prefix | ((uint32_t)tid << sh);
-    ns.rank = (int32_t)(r - exc);
+    ns.prefix = s.prefix | ((uint32_t)(tid * per + b) << sh);
+    ns.rank = (int32_t)rr;
     ns.hb = sh - 1;
     st[ch.seg] = ns;
   }
-  gh[tid] = 0;
+#pragma unroll
+  for (int q = 0; q < per; ++q) gh[tid * per + q] = 0;
   if (tid == 0) ctr[ch.seg] = 0;
 }
 
@@ -402,7 +443,10 @@ __global__ __launch_bounds__(kBuildBlock) void k_count(const ChunkEntry* __restr
 }
 
 // Stable partition of each segment around its pivot into the other buffer,
-// accumulating the children's tight boxes.
+// accumulating the children's tight boxes.  Each wave owns a contiguous
+// quarter of the chunk: it first counts its keys below / equal to the pivot,
+// one barrier publishes the per-wave counts, then every wave scatters its rows
+// in order with wave ballots only.
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __restrict__ chunks,
                                                          const SegEntry* __restrict__ segs,
@@ -414,18 +458,36 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
                                                          int32_t* __restrict__ pout, int64_t tot,
                                                          uint32_t* __restrict__ ubox,
                                                          int32_t* __restrict__ bad) {
-  __shared__ uint32_t wsum[2][4];
+  __shared__ uint32_t wcnt[2][4];
   const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
   const ChunkEntry ch = chunks[blockIdx.x];
   const SegEntry se = segs[ch.seg];
   const SegState s = st[ch.seg];
   const uint32_t pivot = s.prefix;
   const int64_t n_eq_left = (int64_t)s.rank + 1;
-  const int64_t less_before = pref[2 * blockIdx.x];
-  const int64_t eq_before = pref[2 * blockIdx.x + 1];
-  const int64_t left_before = less_before + min(eq_before, n_eq_left);
-  const int64_t right_before = (ch.b - se.b) - left_before;
   const float* kx = xin + (int64_t)s.axis * tot;
+  const int64_t len = ch.e - ch.b;
+  const int64_t wb = ch.b + len * wave / 4, we = ch.b + len * (wave + 1) / 4;
+  uint32_t nl = 0, ne = 0;
+  for (int64_t i = wb + lane; i < we; i += kWave) {
+    const uint32_t k = fkey(kx[i]);
+    nl += k < pivot;
+    ne += k == pivot;
+  }
+  nl = wave_sum(nl);
+  ne = wave_sum(ne);
+  if (lane == 0) {
+    wcnt[0][wave] = nl;
+    wcnt[1][wave] = ne;
+  }
+  __syncthreads();
+  int64_t less_before = pref[2 * blockIdx.x], eq_before = pref[2 * blockIdx.x + 1];
+  for (int w = 0; w < wave; ++w) {
+    less_before += wcnt[0][w];
+    eq_before += wcnt[1][w];
+  }
+  const int64_t left_before = less_before + min(eq_before, n_eq_left);
+  const int64_t right_before = (wb - se.b) - left_before;
   uint32_t lmin[D], lmax[D], rmin[D], rmax[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -433,48 +495,29 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
     lmax[a] = rmax[a] = 0u;
   }
   int64_t run_left = 0, run_right = 0, run_eq = 0;
-  for (int64_t base = ch.b; base < ch.e; base += kBuildBlock) {
-    const int64_t i = base + tid;
-    const bool valid = i < ch.e;
+  for (int64_t base = wb; base < we; base += kWave) {
+    const int64_t i = base + lane;
+    const bool valid = i < we;
     const uint32_t k = valid ? fkey(kx[i]) : 0xFFFFFFFFu;
     const bool less = valid && k < pivot;
     const bool eq = valid && k == pivot;
     const uint64_t be = __ballot(eq);
-    if (lane == 0) wsum[0][wave] = __popcll(be);
-    __syncthreads();
-    uint32_t e_before = 0, e_tot = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      uint32_t v = wsum[0][w];
-      e_before += w < wave ? v : 0u;
-      e_tot += v;
-    }
-    const int64_t eq_rank = eq_before + run_eq + e_before + lanes_below(be);
+    const int64_t eq_rank = eq_before + run_eq + lanes_below(be);
     const bool left = less || (eq && eq_rank < n_eq_left);
     const uint64_t bl = __ballot(left);
-    if (lane == 0) wsum[1][wave] = __popcll(bl);
-    __syncthreads();
-    uint32_t l_before = 0, l_tot = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      uint32_t v = wsum[1][w];
-      l_before += w < wave ? v : 0u;
-      l_tot += v;
-    }
+    const int lpos = lanes_below(bl);
     if (valid) {
-      const int64_t lpos = l_before + lanes_below(bl);
-      const int64_t rpos = tid - lpos;
       int64_t dst = left ? se.b + left_before + run_left + lpos
-                         : se.m + right_before + run_right + rpos;
+                         : se.m + right_before + run_right + (lane - lpos);
       if (dst < se.b || dst >= se.e) {  // cannot happen; keeps a logic slip in bounds
         atomicOr(bad, 2);
         dst = se.b;
       }
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        float v = xin[a * tot + i];
+        const float v = xin[a * tot + i];
         xout[a * tot + dst] = v;
-        uint32_t kv = fkey(v);
+        const uint32_t kv = fkey(v);
         if (left) {
           lmin[a] = min(lmin[a], kv);
           lmax[a] = max(lmax[a], kv);
@@ -485,17 +528,17 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
       }
       pout[dst] = pin[i];
     }
-    const int64_t nvalid = min((int64_t)kBuildBlock, ch.e - base);
-    run_eq += e_tot;
-    run_left += l_tot;
-    run_right += nvalid - l_tot;
+    const int64_t nvalid = min((int64_t)kWave, we - base);
+    run_eq += __popcll(be);
+    run_left += __popcll(bl);
+    run_right += nvalid - __popcll(bl);
   }
   if (se.child >= 0) {
     uint32_t* c = ubox + se.child * 2 * D;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      uint32_t v0 = wave_umin(lmin[a]), v1 = wave_umax(lmax[a]);
-      uint32_t v2 = wave_umin(rmin[a]), v3 = wave_umax(rmax[a]);
+      const uint32_t v0 = wave_umin(lmin[a]), v1 = wave_umax(lmax[a]);
+      const uint32_t v2 = wave_umin(rmin[a]), v3 = wave_umax(rmax[a]);
       if (lane == 0) {
         if (v0 != 0xFFFFFFFFu) atomicMin(c + a, v0);
         if (v1 != 0u) atomicMax(c + D + a, v1);
@@ -785,7 +828,7 @@ static kdt_status run_build(const Plan& p, const PlanDev& pd, const float* d_pts
     const int src = l & 1, dst = src ^ 1;
     k_level_init<D><<<(nseg + 127) / 128, 128, 0, stream>>>(pd.segs[l], nseg, w.st, w.ubox, o.box,
                                                             o.axis);
-    for (int pass = 0; pass < 4; ++pass)
+    for (int pass = 0; pass < kRadixPasses; ++pass)
       k_radix_pass<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], pd.segs[l], w.st, w.hist,
                                                        w.ctr, w.x[src], tot);
     k_count<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], pd.segs[l], w.st, w.x[src], tot,
@@ -834,7 +877,7 @@ kdt_status build_scratch_alloc(const Plan& p, const PlanDev& pd, BuildScratch& w
             A((void**)&w.p[0], sizeof(int32_t) * tot) && A((void**)&w.p[1], sizeof(int32_t) * tot) &&
             A((void**)&w.ubox, sizeof(uint32_t) * 2 * d * p.n_nodes) &&
             A((void**)&w.st, sizeof(SegState) * pd.max_segs) &&
-            A((void**)&w.hist, sizeof(uint32_t) * 256 * pd.max_segs) &&
+            A((void**)&w.hist, sizeof(uint32_t) * kBins * pd.max_segs) &&
             A((void**)&w.ctr, sizeof(uint32_t) * pd.max_segs) &&
             A((void**)&w.cnt, sizeof(int32_t) * 2 * pd.max_chunks) &&
             A((void**)&w.pref, sizeof(int32_t) * 2 * pd.max_chunks) && A((void**)&w.bad, 256);
@@ -877,7 +920,7 @@ void build_init_once() {
 kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
                         const BuildScratch& w, const BuildOut& o, int phase, hipStream_t stream) {
   if (phase == 0) {
-    zero_u32(w.hist, 256 * (int64_t)pd.max_segs, stream);
+    zero_u32(w.hist, kBins * (int64_t)pd.max_segs, stream);
     zero_u32(w.ctr, (int64_t)pd.max_segs, stream);
     zero_u32(reinterpret_cast<uint32_t*>(w.bad), 1, stream);
   }

@@ -17,16 +17,43 @@ namespace kdt {
 constexpr int kFBlock = 128;
 
 template <int D>
+__global__ void k_fof_clique_mark(const float* __restrict__ box, int64_t n_nodes, float l2,
+                                  uint32_t* __restrict__ conn) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n_nodes) fof_mark_clique<D>(box, v, l2, conn);
+}
+
+template <int D>
+__global__ void k_fof_clique_join(TreeView t, int32_t* __restrict__ parent,
+                                  const uint32_t* __restrict__ conn) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= t.n) return;
+  constexpr int S = rec_stride(D);
+  fof_join_clique<D>(t, s, __float_as_int(t.rec[s * S + D]), 0, parent, conn);
+}
+
+template <int D>
 __global__ __launch_bounds__(kFBlock) void k_fof_link(TreeView t, float l2,
-                                                      int32_t* __restrict__ parent) {
+                                                      int32_t* __restrict__ parent,
+                                                      uint32_t* __restrict__ conn) {
   __shared__ uint32_t stk[kMaxDepth][kFBlock];
   const int64_t s = (int64_t)blockIdx.x * kFBlock + threadIdx.x;
   if (s >= t.n) return;
   float p[D];
   int32_t me = 0;
   load_rec<D>(t.rec, s, p, me);
-  fof_one<D>(t, p, me, l2, &stk[0][threadIdx.x], kFBlock,
-             [&](int32_t id) { uf_union(parent, me, id); });
+  fof_point<D>(t, p, s, me, l2, 0, parent, conn, &stk[0][threadIdx.x], kFBlock);
+}
+
+template <int D>
+static void fof_launch(const TreeView& v, int64_t n_nodes, float l2, int32_t* labels,
+                       uint32_t* conn, hipStream_t stream) {
+  const unsigned gn = (unsigned)((n_nodes + 255) / 256);
+  const unsigned gp = (unsigned)((v.n + 255) / 256);
+  const unsigned gl = (unsigned)((v.n + kFBlock - 1) / kFBlock);
+  k_fof_clique_mark<D><<<gn, 256, 0, stream>>>(v.box, n_nodes, l2, conn);
+  k_fof_clique_join<D><<<gp, 256, 0, stream>>>(v, labels, conn);
+  k_fof_link<D><<<gl, kFBlock, 0, stream>>>(v, l2, labels, conn);
 }
 
 __global__ void k_fof_init(int32_t* __restrict__ parent, int64_t n) {
@@ -74,17 +101,23 @@ extern "C" kdt_status kdt_fof(const kdt_tree* tree, float l, int32_t* d_labels, 
   k_fof_init<<<g, 256, 0, stream>>>(d_labels, n);
   const TreeView v = view_of(tree);
   const float l2 = l * l;
-  const unsigned gl = (unsigned)((n + kFBlock - 1) / kFBlock);
+  uint32_t* conn = nullptr;
+  if (dev_alloc((void**)&conn, sizeof(uint32_t) * tree->n_nodes, stream) != hipSuccess) {
+    kdt_set_error("kdt_fof: device allocation failed");
+    return KDT_ENOMEM;
+  }
   switch (tree->d) {
-    case 2: k_fof_link<2><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
-    case 3: k_fof_link<3><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
-    case 4: k_fof_link<4><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
-    case 8: k_fof_link<8><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
-    case 16: k_fof_link<16><<<gl, kFBlock, 0, stream>>>(v, l2, d_labels); break;
+    case 2: fof_launch<2>(v, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 3: fof_launch<3>(v, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 4: fof_launch<4>(v, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 8: fof_launch<8>(v, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 16: fof_launch<16>(v, tree->n_nodes, l2, d_labels, conn, stream); break;
     default:
+      (void)hipFreeAsync(conn, stream);
       kdt_set_error("kdt_fof: unsupported dimension %d", tree->d);
       return KDT_EUNSUPPORTED;
   }
+  (void)hipFreeAsync(conn, stream);
   k_fof_final<<<g, 256, 0, stream>>>(d_labels, n);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_fof: kernel launch failed");

@@ -106,26 +106,39 @@ constexpr uint64_t kEmptyKey = 0x7F800000FFFFFFFFull;
 
 // Sorted register list of the KC smallest 64-bit keys (d2 bits << 32 | index).
 // Only the last k slots are live: the first KC - k hold 0 and never move.
+//
+// The keys are stored as float64 bit patterns: for d2 >= 0 (never NaN) the
+// key's sign bit is 0 and its exponent field can never be all ones, so the
+// float64 order of the patterns is exactly the unsigned order of the keys
+// (keys below 2^52 are subnormal doubles, which the float64 min/max keep
+// exact because float64 subnormals are not flushed).  That turns each
+// compare-and-carry step into one v_min_f64 and one v_max_f64.
 template <int KC>
 struct TopK {
-  uint64_t a[KC];
+  double a[KC];
   __device__ __forceinline__ void init(int k) {
 #pragma unroll
-    for (int i = 0; i < KC; ++i) a[i] = (i < KC - k) ? 0ull : kEmptyKey;
+    for (int i = 0; i < KC; ++i) a[i] = (i < KC - k) ? 0.0 : __longlong_as_double((long long)kEmptyKey);
   }
-  __device__ __forceinline__ uint64_t worst() const { return a[KC - 1]; }
+  __device__ __forceinline__ uint64_t key(int i) const {
+    return (uint64_t)__double_as_longlong(a[i]);
+  }
+  __device__ __forceinline__ uint64_t worst() const { return key(KC - 1); }
   __device__ __forceinline__ float worst_d2() const {
-    return __uint_as_float((uint32_t)(a[KC - 1] >> 32));
+    return __uint_as_float((uint32_t)(worst() >> 32));
   }
-  // requires x < worst()
+  // Inserts x if it is below worst(), otherwise leaves the list unchanged
+  // (no branch, so it can run on every lane of a wave).  One bottom-up pass
+  // of compare-and-carry: each slot keeps the smaller of itself and the carry
+  // and hands the larger upwards; the largest key falls off the top.
   __device__ __forceinline__ void insert(uint64_t x) {
+    double carry = __longlong_as_double((long long)x);
 #pragma unroll
-    for (int i = KC - 1; i > 0; --i) {
-      const uint64_t lo = a[i - 1];
-      const uint64_t cur = a[i];
-      a[i] = (x < lo) ? lo : ((x < cur) ? x : cur);
+    for (int i = 0; i < KC; ++i) {
+      const double up = fmax(a[i], carry);
+      a[i] = fmin(a[i], carry);
+      carry = up;
     }
-    a[0] = (x < a[0]) ? x : a[0];
   }
 };
 
@@ -193,48 +206,16 @@ __device__ __forceinline__ void knn_write(const TopK<KC>& best, int k, int mode,
 #pragma unroll
     for (int j = 0; j < KC; ++j) {
       if (j < KC - k) continue;
-      const uint64_t key = best.a[j];
+      const uint64_t key = best.key(j);
       const bool empty = key == kEmptyKey;
       const int64_t o = row * k + (j - (KC - k));
       if (oidx) oidx[o] = empty ? -1 : (int32_t)(uint32_t)key;
       od2[o] = empty ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
     }
   } else {
-    const uint64_t key = best.a[KC - 1];
+    const uint64_t key = best.key(KC - 1);
     const float d2 = key == kEmptyKey ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
     od2[row] = mode == 2 ? sqrtf(d2) : d2;
-  }
-}
-
-// Friends-of-friends links of the point at tree position s (index `me`):
-// every friend with a larger index is passed to `link(friend_index)`.
-template <int D, typename F>
-__device__ __forceinline__ void fof_one(const TreeView& t, const float p[D], int32_t me, float l2,
-                                        uint32_t* stk, int ld, F&& link) {
-  const uint32_t first_leaf = (1u << t.levels) - 1u;
-  int sp = 0;
-  stk[0] = 0;
-  sp = 1;
-  while (sp > 0) {
-    const uint32_t node = stk[--sp * ld];
-    float lo[D], hi[D];
-    load_box<D>(t.box, node, lo, hi);
-    if (box_mindist<D>(lo, hi, p) > l2) continue;
-    const int lev = node_level(node);
-    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
-    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
-    const bool all_in = box_maxdist<D>(lo, hi, p) <= l2;
-    if (all_in || node >= first_leaf) {
-      for (int64_t i = b; i < e; ++i) {
-        float x[D];
-        int32_t id = 0;
-        load_rec<D>(t.rec, i, x, id);
-        if (id > me && (all_in || sq_dist<D>(x, p) <= l2)) link(id);
-      }
-      continue;
-    }
-    stk[sp++ * ld] = 2 * node + 2;
-    stk[sp++ * ld] = 2 * node + 1;
   }
 }
 
@@ -279,6 +260,123 @@ __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) 
   }
 }
 
+// Squared diagonal of a box: every pair of points inside is at most this far
+// apart (same operation order as the point distance).
+template <int D>
+__device__ __forceinline__ float box_diag2(const float lo[D], const float hi[D]) {
+  float s = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float t = hi[a] - lo[a];
+    float t2 = t * t;
+    s = s + t2;
+  }
+  return s;
+}
+
+__device__ __forceinline__ uint32_t flag_ld(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_st(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Friends-of-friends links of the point p at tree position `pos` (index me)
+// of tree t.  Union-find indices are base + index.  conn[v] != 0 records that
+// every point of node v is already (or will be, once the running unions land)
+// in one component; such a node needs a single link to p, and once one friend
+// is found inside it the rest of its subtree is skipped.
+template <int D>
+__device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], int64_t pos,
+                                          int32_t me, float l2, int32_t base,
+                                          int32_t* __restrict__ parent,
+                                          uint32_t* __restrict__ conn, uint32_t* stk, int ld) {
+  constexpr int S = rec_stride(D);
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int sp = 1;
+  stk[0] = 0;
+  int guard = -1;  // stack depth where the current one-component region began
+  while (sp > 0) {
+    --sp;
+    if (guard >= 0 && sp < guard) guard = -1;
+    const uint32_t node = stk[sp * ld];
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (box_mindist<D>(lo, hi, p) > l2) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    const bool in_region = guard >= 0;
+    const bool one = in_region || flag_ld(conn + node) != 0;
+    if (one && pos >= b && pos < e) continue;  // p is already in this component
+    if (box_maxdist<D>(lo, hi, p) <= l2) {
+      if (one) {
+        uf_union(parent, base + me, base + __float_as_int(t.rec[b * S + D]));
+        if (in_region) {
+          sp = guard;
+          guard = -1;
+        }
+      } else {
+        for (int64_t i = b; i < e; ++i) uf_union(parent, base + me, base + __float_as_int(t.rec[i * S + D]));
+        flag_st(conn + node, 1u);
+      }
+      continue;
+    }
+    if (node >= first_leaf) {
+      for (int64_t i = b; i < e; ++i) {
+        float x[D];
+        int32_t id = 0;
+        load_rec<D>(t.rec, i, x, id);
+        if (sq_dist<D>(x, p) > l2) continue;
+        if (one) {
+          uf_union(parent, base + me, base + id);
+          if (in_region) {
+            sp = guard;
+            guard = -1;
+          }
+          break;
+        }
+        if (id > me) uf_union(parent, base + me, base + id);
+      }
+      continue;
+    }
+    if (one && !in_region) guard = sp;
+    stk[sp++ * ld] = 2 * node + 2;
+    stk[sp++ * ld] = 2 * node + 1;
+  }
+}
+
+// Marks nodes whose box diagonal is within the linking length: all their
+// points are mutual friends.
+template <int D>
+__device__ __forceinline__ void fof_mark_clique(const float* __restrict__ box, int64_t node,
+                                                float l2, uint32_t* __restrict__ conn) {
+  float lo[D], hi[D];
+  load_box<D>(box, (uint32_t)node, lo, hi);
+  conn[node] = box_diag2<D>(lo, hi) <= l2 ? 1u : 0u;
+}
+
+// Joins the point at tree position pos with the first point of the largest
+// clique node above it (so every maximal clique becomes one component).
+template <int D>
+__device__ __forceinline__ void fof_join_clique(const TreeView& t, int64_t pos, int32_t me,
+                                                int32_t base, int32_t* __restrict__ parent,
+                                                const uint32_t* __restrict__ conn) {
+  constexpr int S = rec_stride(D);
+  const int64_t first_leaf = (int64_t(1) << t.levels) - 1;
+  // leaf holding pos: largest j with node_begin(n, L, j) <= pos
+  int64_t j = ((pos + 1) << t.levels) / t.n;
+  while (j > 0 && node_begin(t.n, t.levels, j) > pos) --j;
+  while (node_begin(t.n, t.levels, j + 1) <= pos) ++j;
+  int64_t v = first_leaf + j;
+  if (!conn[v]) return;
+  while (v > 0 && conn[(v - 1) >> 1]) v = (v - 1) >> 1;
+  const int lev = node_level((uint32_t)v);
+  const int64_t b = node_begin(t.n, lev, v - ((int64_t(1) << lev) - 1));
+  const int32_t first = __float_as_int(t.rec[b * S + D]);
+  if (first != me) uf_union(parent, base + me, base + first);
+}
+
 // Root of x without shortcuts (safe while other lanes write final labels).
 __device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
   int32_t cur = x;
@@ -288,5 +386,10 @@ __device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
     cur = next;
   }
 }
+
+template <int D>
+kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, int k,
+                             int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
+                             hipStream_t stream);
 
 }  // namespace kdt

@@ -232,13 +232,17 @@ static kdt_status knn_dispatch(const kdt_tree* t, const float* d_q, int64_t nq, 
 
 template <int D>
 static kdt_status knn_impl(const kdt_tree* t, const float* d_q, int64_t nq, int k, int32_t* d_idx,
-                           float* d_d2, int mode, bool sort_q, hipStream_t stream) {
+                           float* d_d2, int mode, bool sort_q, int traversal, hipStream_t stream) {
   int32_t* order = nullptr;
   if (d_q && sort_q && nq > 1) {
     kdt_status st = order_queries<D>(t, d_q, nq, &order, stream);
     if (st != KDT_OK) return st;
   }
-  kdt_status st = knn_dispatch<D>(t, d_q, nq, k, d_idx, d_d2, mode, order, stream);
+  if (t->leaf > 64) traversal = 1;  // the wave kernel marks at most 64 points per leaf
+  kdt_status st = traversal == 1
+                      ? knn_dispatch<D>(t, d_q, nq, k, d_idx, d_d2, mode, order, stream)
+                      : knn_packet_launch<D>(view_of(t), t->leaf, d_q, nq, k, d_idx, d_d2, mode,
+                                             order, stream);
   if (order) (void)hipFreeAsync(order, stream);
   return st;
 }
@@ -343,12 +347,17 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
   }
   if (nq == 0) return KDT_OK;
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
+  const int trav = opts ? opts->traversal : 0;
+  if (trav < 0 || trav > 2) {
+    kdt_set_error("kdt_knn: traversal must be 0, 1 or 2");
+    return KDT_EINVAL;
+  }
   switch (tree->d) {
-    case 2: return knn_impl<2>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
-    case 3: return knn_impl<3>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
-    case 4: return knn_impl<4>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
-    case 8: return knn_impl<8>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
-    case 16: return knn_impl<16>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, stream);
+    case 2: return knn_impl<2>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
+    case 3: return knn_impl<3>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
+    case 4: return knn_impl<4>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
+    case 8: return knn_impl<8>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
+    case 16: return knn_impl<16>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
   }
   kdt_set_error("kdt_knn: unsupported dimension %d", tree->d);
   return KDT_EUNSUPPORTED;

@@ -38,7 +38,7 @@ class BuildOpts(C.Structure):
 
 
 class QueryOpts(C.Structure):
-    _fields_ = [("sort_queries", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("sort_queries", C.c_int32), ("traversal", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -157,7 +157,7 @@ class Tree:
         return int(load().kdt_tree_perm(self._h))
 
     def knn(self, queries: torch.Tensor | None, k: int, kth_only: int = 0,
-            sort_queries: bool = True, stream=None):
+            sort_queries: bool = True, traversal: int = 0, stream=None):
         """k nearest neighbours, ascending by (d2, index): (idx [nq][k], d2 [nq][k]).
 
         ``queries=None`` queries every point of the tree (row i = input point i).
@@ -166,7 +166,7 @@ class Tree:
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, 0)
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal))
         if kth_only:
             d2 = torch.empty(nq, dtype=torch.float32, device=self.device)
             _check(load().kdt_knn(self._h, _ptr(queries), nq, k, None, _ptr(d2), kth_only,

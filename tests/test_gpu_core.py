@@ -79,6 +79,22 @@ def test_knn_matches_oracle(d, kind):
             np.testing.assert_array_equal(h, np.sqrt(od[:, -1]))
 
 
+@pytest.mark.parametrize("d", kdt.DIMS)
+def test_lane_and_wave_traversals_agree_with_oracle(d):
+    dev()
+    x = cases.points("normal", 12000, d, seed=d)
+    q = cases.points("normal", 3000, d, seed=100 + d)
+    t = kdt.build(to_dev(x), leaf_size=24)
+    ot = oracle.Tree(x, 24)
+    for k in (5, 16, 40):
+        say(f"traversals d={d} k={k}")
+        oi, od = ot.knn(q, k)
+        for trav in (1, 2):
+            gi, gd = t.knn(to_dev(q), k, traversal=trav)
+            np.testing.assert_array_equal(to_host(gi), oi)
+            np.testing.assert_array_equal(to_host(gd), od)
+
+
 def test_unsorted_queries_give_the_same_answer():
     dev()
     x = workloads.clustered(50000, seed=5)
