@@ -10,12 +10,16 @@
 //
 // Two phases:
 //  * global levels -- nodes too large for one workgroup's LDS are split by
-//    multi-workgroup kernels: per level an init pass (box, axis), up to four
-//    8-bit radix-select passes over order-preserving uint32 keys of the split
-//    coordinate (histograms merged by the last workgroup of each node), a
-//    count pass and a stable scatter of the SoA coordinates and indices into
-//    the other ping-pong buffer, which also accumulates the children's tight
-//    boxes;
+//    multi-workgroup kernels.  Workgroups never talk to each other inside a
+//    launch (no device-scope fences or counters, which are expensive across
+//    the chip's XCDs): every cross-workgroup sum goes through a kernel
+//    boundary.  Per level: an init pass (one wave per node reduces the partial
+//    boxes its points left behind, picks the axis), four 8-bit radix-select
+//    passes over order-preserving uint32 keys of the split coordinate (each a
+//    per-chunk histogram kernel plus a per-node select kernel), a per-chunk
+//    count of keys below / equal to the pivot, and a stable scatter that
+//    partitions each chunk in LDS and writes whole runs of the other
+//    ping-pong buffer, leaving partial child boxes per chunk;
 //  * LDS subtrees -- each node small enough to fit is loaded once into one
 //    workgroup's LDS, which finishes all remaining levels there (one wave per
 //    node; radix select or, for <= 64 points, rank counting) and writes the
@@ -30,7 +34,7 @@
 
 namespace kdt {
 
-constexpr int kChunk = 4096;  // rows per workgroup in the global-level passes
+constexpr int kChunk = 16384;  // rows per workgroup in the global-level passes
 constexpr int kBuildBlock = 256;
 
 int levels_for(int64_t n, int leaf) {
@@ -86,11 +90,18 @@ bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std
     }
     return (int32_t)nch;
   };
-  for (int s = 0; s < n_sets; ++s) add_chunks(p.root_chunks, p.sets[s].off, p.sets[s].off + p.sets[s].n, s);
+  std::vector<int32_t> root_first(n_sets), root_count(n_sets);
+  for (int s = 0; s < n_sets; ++s) {
+    root_first[s] = (int32_t)p.root_chunks.size();
+    root_count[s] = add_chunks(p.root_chunks, p.sets[s].off, p.sets[s].off + p.sets[s].n, s);
+  }
+  // index of each set's first segment in the previous level (for box sources)
+  std::vector<int64_t> prev_first(n_sets, -1), cur_first(n_sets, -1);
   for (int l = 0; l < p.n_glevels; ++l) {
     for (int s = 0; s < n_sets; ++s) {
       const SetDesc& sd = p.sets[s];
       if (sd.glevels <= l) continue;
+      cur_first[s] = (int64_t)p.segs[l].size();
       for (int64_t j = 0; j < (int64_t(1) << l); ++j) {
         SegEntry se;
         se.b = sd.off + node_begin(sd.n, l, j);
@@ -100,9 +111,21 @@ bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std
         se.child = (l + 1 < sd.glevels) ? sd.node_base + (int64_t(2) << l) - 1 + 2 * j : -1;
         se.first_chunk = (int32_t)p.chunks[l].size();
         se.n_chunks = add_chunks(p.chunks[l], se.b, se.e, (int32_t)p.segs[l].size());
+        if (l == 0) {
+          se.src_first = root_first[s];
+          se.src_count = root_count[s];
+          se.src_side = -1;
+        } else {
+          const SegEntry& par = p.segs[l - 1][prev_first[s] + (j >> 1)];
+          se.src_first = par.first_chunk;
+          se.src_count = par.n_chunks;
+          se.src_side = (int32_t)(j & 1);
+        }
+        se.pad = 0;
         p.segs[l].push_back(se);
       }
     }
+    prev_first = cur_first;
   }
   for (int s = 0; s < n_sets; ++s) {
     const SetDesc& sd = p.sets[s];
@@ -172,15 +195,40 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* tmp) {
 // Kernels
 // ---------------------------------------------------------------------------
 
+constexpr int kBins = 256;       // 8-bit digits
+constexpr int kRadixPasses = 4;  // 4 x 8 bits resolve a 32-bit key
+
+// Rows of one scatter tile: coordinates and index of the tile fit in 32 KiB.
 template <int D>
-__global__ void k_init_roots(const SetDesc* __restrict__ sets, int n_sets, uint32_t* __restrict__ ubox) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_sets) return;
-  uint32_t* u = ubox + sets[s].node_base * 2 * D;
+__host__ __device__ constexpr int scatter_tile() {
+  return (8192 / (D + 1)) / kBuildBlock * kBuildBlock > 0 ? (8192 / (D + 1)) / kBuildBlock * kBuildBlock
+                                                          : kBuildBlock;
+}
+
+// Block-wide min/max of per-thread key boxes; the result lands in out[0..2D).
+template <int D>
+__device__ __forceinline__ void block_box(const uint32_t lo[D], const uint32_t hi[D],
+                                          uint32_t* red /*[4][2D]*/, uint32_t* out) {
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+#pragma unroll
   for (int a = 0; a < D; ++a) {
-    u[a] = 0xFFFFFFFFu;
-    u[D + a] = 0u;
+    const uint32_t l = wave_umin(lo[a]), h = wave_umax(hi[a]);
+    if (lane == 0) {
+      red[wave * 2 * D + a] = l;
+      red[wave * 2 * D + D + a] = h;
+    }
   }
+  __syncthreads();
+  if (threadIdx.x < 2 * D) {
+    const int a = threadIdx.x;
+    uint32_t v = red[a];
+    for (int w = 1; w < 4; ++w) {
+      const uint32_t u = red[w * 2 * D + a];
+      v = a < D ? min(v, u) : max(v, u);
+    }
+    out[a] = v;
+  }
+  __syncthreads();
 }
 
 template <int D>
@@ -189,8 +237,9 @@ __global__ __launch_bounds__(kBuildBlock) void k_ingest(const ChunkEntry* __rest
                                                         const float* __restrict__ in,
                                                         float* __restrict__ x,
                                                         int32_t* __restrict__ perm, int64_t tot,
-                                                        uint32_t* __restrict__ ubox,
+                                                        uint32_t* __restrict__ pbox,
                                                         int32_t* __restrict__ bad) {
+  __shared__ uint32_t red[4 * 2 * D];
   const ChunkEntry ch = chunks[blockIdx.x];
   const SetDesc sd = sets[ch.seg];
   uint32_t lo[D], hi[D];
@@ -203,107 +252,102 @@ __global__ __launch_bounds__(kBuildBlock) void k_ingest(const ChunkEntry* __rest
   for (int64_t i = ch.b + threadIdx.x; i < ch.e; i += kBuildBlock) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      float v = in[i * D + a];
+      const float v = in[i * D + a];
       nonfinite |= !isfinite(v);
       x[a * tot + i] = v;
-      uint32_t k = fkey(v);
+      const uint32_t k = fkey(v);
       lo[a] = min(lo[a], k);
       hi[a] = max(hi[a], k);
     }
     perm[i] = (int32_t)(i - sd.off);
   }
   if (__any(nonfinite) && lane_id() == 0) atomicOr(bad, 1);
-  uint32_t* u = ubox + sd.node_base * 2 * D;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    uint32_t l = wave_umin(lo[a]), h = wave_umax(hi[a]);
-    if (lane_id() == 0) {
-      atomicMin(u + a, l);
-      atomicMax(u + D + a, h);
-    }
-  }
+  block_box<D>(lo, hi, red, pbox + (int64_t)blockIdx.x * 2 * D);
 }
 
+// One wave per node: reduce the partial boxes of the node's points, write the
+// node's box and split axis, and start its pivot selection.
 template <int D>
-__global__ void k_level_init(const SegEntry* __restrict__ segs, int nseg, SegState* __restrict__ st,
-                             uint32_t* __restrict__ ubox, float* __restrict__ box,
-                             int32_t* __restrict__ axis_out) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
+__global__ __launch_bounds__(kBuildBlock) void k_level_init(const SegEntry* __restrict__ segs,
+                                                            int nseg, SegState* __restrict__ st,
+                                                            const uint32_t* __restrict__ pbox,
+                                                            const uint32_t* __restrict__ cbox,
+                                                            float* __restrict__ box,
+                                                            int32_t* __restrict__ axis_out) {
   constexpr int P = pad4(D);
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int s = blockIdx.x * 4 + wave;
+  if (s >= nseg) return;
   const SegEntry se = segs[s];
-  const uint32_t* u = ubox + se.node * 2 * D;
-  float lo[D], hi[D];
-  uint32_t klo = 0, khi = 0;
-  int ax = 0;
-  float ext = -1.0f;
+  uint32_t ulo[D], uhi[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    lo[a] = fkey_inv(u[a]);
-    hi[a] = fkey_inv(u[D + a]);
-    float e = hi[a] - lo[a];
+    ulo[a] = 0xFFFFFFFFu;
+    uhi[a] = 0u;
+  }
+  for (int c = lane; c < se.src_count; c += kWave) {
+    const uint32_t* src = se.src_side < 0 ? pbox + (int64_t)(se.src_first + c) * 2 * D
+                                          : cbox + ((int64_t)(se.src_first + c) * 2 + se.src_side) * 2 * D;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      ulo[a] = min(ulo[a], src[a]);
+      uhi[a] = max(uhi[a], src[D + a]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    ulo[a] = wave_umin(ulo[a]);
+    uhi[a] = wave_umax(uhi[a]);
+  }
+  int ax = 0;
+  float ext = -1.0f;
+  uint32_t klo = 0, khi = 0;
+  float wv = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float lo = fkey_inv(ulo[a]), hi = fkey_inv(uhi[a]);
+    const float e = hi - lo;
     if (e > ext) {
       ext = e;
       ax = a;
-      klo = u[a];
-      khi = u[D + a];
+      klo = ulo[a];
+      khi = uhi[a];
     }
+    if (lane == a) wv = lo;
+    if (lane == P + a) wv = hi;
   }
-  float* bx = box + se.node * 2 * P;
-#pragma unroll
-  for (int a = 0; a < P; ++a) {
-    bx[a] = a < D ? lo[a] : 0.0f;
-    bx[P + a] = a < D ? hi[a] : 0.0f;
-  }
-  axis_out[se.node] = ax;
-  uint32_t xr = klo ^ khi;
-  SegState ss;
-  ss.hb = xr ? 31 - __clz(xr) : -1;
-  ss.prefix = ss.hb >= 0 ? (klo & ~((2u << ss.hb) - 1u)) : klo;
-  ss.rank = (int32_t)(se.m - se.b) - 1;
-  ss.axis = ax;
-  ss.n_eq_left = 0;
-  ss.pad[0] = ss.pad[1] = ss.pad[2] = 0;
-  st[s] = ss;
-  if (se.child >= 0) {
-    uint32_t* c = ubox + se.child * 2 * D;
-    for (int a = 0; a < 2 * D; ++a) {
-      c[a] = 0xFFFFFFFFu;             // left child lo
-      c[2 * D + a] = 0xFFFFFFFFu;     // right child lo
-    }
-    for (int a = 0; a < D; ++a) {
-      c[D + a] = 0u;                  // left child hi
-      c[3 * D + a] = 0u;              // right child hi
-    }
+  if (lane < 2 * P) box[se.node * 2 * P + lane] = wv;
+  if (lane == 0) {
+    axis_out[se.node] = ax;
+    const uint32_t xr = klo ^ khi;
+    SegState ss;
+    ss.hb = xr ? 31 - __clz(xr) : -1;
+    ss.prefix = ss.hb >= 0 ? (klo & ~((2u << ss.hb) - 1u)) : klo;
+    ss.rank = (int32_t)(se.m - se.b) - 1;
+    ss.axis = ax;
+    ss.n_eq_left = 0;
+    ss.pad[0] = ss.pad[1] = ss.pad[2] = 0;
+    st[s] = ss;
   }
 }
 
-// One radix-select pass over 11-bit digits (three passes resolve a 32-bit
-// key).  Lanes of a wave that fall in the same bin as the wave's first lane
-// add their count with one LDS atomic (clustered data puts most keys of a
-// node in few bins).  The last workgroup of each segment scans the merged
-// histogram and narrows the pivot.
-constexpr int kDigitBits = 11;
-constexpr int kBins = 1 << kDigitBits;
-constexpr int kRadixPasses = (32 + kDigitBits - 1) / kDigitBits;
-
+// Histogram of the next 8-bit digit over one chunk (keys that match the
+// resolved prefix only), written densely per chunk.  Lanes of a wave whose bin
+// equals that of the wave's first valid lane add their count with one LDS
+// atomic (clustered data puts most keys of a node in few bins).
 template <int D>
-__global__ __launch_bounds__(kBuildBlock) void k_radix_pass(const ChunkEntry* __restrict__ chunks,
-                                                            const SegEntry* __restrict__ segs,
-                                                            SegState* __restrict__ st,
-                                                            uint32_t* __restrict__ hist,
-                                                            uint32_t* __restrict__ ctr,
-                                                            const float* __restrict__ x, int64_t tot) {
+__global__ __launch_bounds__(kBuildBlock) void k_hist(const ChunkEntry* __restrict__ chunks,
+                                                      const SegState* __restrict__ st,
+                                                      const float* __restrict__ x, int64_t tot,
+                                                      uint32_t* __restrict__ chist) {
   __shared__ uint32_t h[kBins];
-  __shared__ uint32_t tmp[4];
-  __shared__ int is_last;
   const ChunkEntry ch = chunks[blockIdx.x];
   const SegState s = st[ch.seg];
   if (s.hb < 0) return;
-  const int tid = threadIdx.x, lane = lane_id();
-  for (int b = tid; b < kBins; b += kBuildBlock) h[b] = 0;
+  const int tid = threadIdx.x;
+  h[tid] = 0;
   __syncthreads();
-  const int sh = s.hb >= kDigitBits - 1 ? s.hb - (kDigitBits - 1) : 0;
+  const int sh = s.hb >= 7 ? s.hb - 7 : 0;
   const uint32_t dmask = (1u << (s.hb - sh + 1)) - 1u;
   const uint64_t want = (uint64_t)s.prefix >> (s.hb + 1);
   const float* kx = x + (int64_t)s.axis * tot;
@@ -318,7 +362,8 @@ __global__ __launch_bounds__(kBuildBlock) void k_radix_pass(const ChunkEntry* __
     }
     const uint64_t m_ok = __ballot(ok);
     if (m_ok == 0) continue;
-    const uint32_t lead = (uint32_t)__builtin_amdgcn_readlane((int)bin, __ffsll((unsigned long long)m_ok) - 1);
+    const uint32_t lead =
+        (uint32_t)__builtin_amdgcn_readlane((int)bin, __ffsll((unsigned long long)m_ok) - 1);
     const bool same = ok && bin == lead;
     const uint64_t m = __ballot(same);
     if (same) {
@@ -328,61 +373,52 @@ __global__ __launch_bounds__(kBuildBlock) void k_radix_pass(const ChunkEntry* __
     }
   }
   __syncthreads();
-  uint32_t* gh = hist + (int64_t)ch.seg * kBins;
-  for (int b = tid; b < kBins; b += kBuildBlock)
-    if (h[b]) atomicAdd(gh + b, h[b]);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) is_last = atomicAdd(ctr + ch.seg, 1u) == (uint32_t)(segs[ch.seg].n_chunks - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  constexpr int per = kBins / kBuildBlock;
-  uint32_t c[per];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int q = 0; q < per; ++q) {
-    c[q] = ld_acquire_u32(gh + tid * per + q);
-    sum += c[q];
-  }
-  const uint32_t inc = block_incl_scan(sum, tmp);
-  const uint32_t exc = inc - sum;
-  const uint32_t r = (uint32_t)s.rank;
-  if (exc <= r && r < inc) {
-    uint32_t rr = r - exc;
-    int b = 0;
-#pragma unroll
-    for (int q = 0; q < per; ++q) {
-      if (b == q && rr >= c[q]) {
-        rr -= c[q];
-        b = q + 1;
-      }
-    }
-    SegState ns = s;
-    ns.prefix = s.prefix | ((uint32_t)(tid * per + b) << sh);
-    ns.rank = (int32_t)rr;
-    ns.hb = sh - 1;
-    st[ch.seg] = ns;
-  }
-#pragma unroll
-  for (int q = 0; q < per; ++q) gh[tid * per + q] = 0;
-  if (tid == 0) ctr[ch.seg] = 0;
+  chist[(int64_t)blockIdx.x * kBins + tid] = h[tid];
 }
 
-// Counts keys below / equal to the pivot per chunk; the last workgroup of the
-// segment turns the counts into exclusive prefixes.
+// One workgroup per node: sum the chunk histograms, find the digit bin that
+// holds the pivot's rank and narrow the selection state.
+__global__ __launch_bounds__(kBuildBlock) void k_select(const SegEntry* __restrict__ segs,
+                                                        SegState* __restrict__ st,
+                                                        const uint32_t* __restrict__ chist) {
+  __shared__ uint32_t tmp[4];
+  const int tid = threadIdx.x;
+  const SegState s = st[blockIdx.x];
+  if (s.hb < 0) return;
+  const SegEntry se = segs[blockIdx.x];
+  const uint32_t* hp = chist + (int64_t)se.first_chunk * kBins + tid;
+  uint32_t c = 0;
+  int q = 0;
+  for (; q + 8 <= se.n_chunks; q += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = hp[(int64_t)(q + u) * kBins];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c += v[u];
+  }
+  for (; q < se.n_chunks; ++q) c += hp[(int64_t)q * kBins];
+  const uint32_t inc = block_incl_scan(c, tmp);
+  const uint32_t exc = inc - c;
+  const uint32_t r = (uint32_t)s.rank;
+  if (exc <= r && r < inc) {
+    const int sh = s.hb >= 7 ? s.hb - 7 : 0;
+    SegState ns = s;
+    ns.prefix = s.prefix | ((uint32_t)tid << sh);
+    ns.rank = (int32_t)(r - exc);
+    ns.hb = sh - 1;
+    st[blockIdx.x] = ns;
+  }
+}
+
+// Keys below / equal to the pivot in each chunk.
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void k_count(const ChunkEntry* __restrict__ chunks,
                                                        const SegEntry* __restrict__ segs,
                                                        const SegState* __restrict__ st,
                                                        const float* __restrict__ x, int64_t tot,
                                                        int32_t* __restrict__ cnt,
-                                                       int32_t* __restrict__ pref,
-                                                       uint32_t* __restrict__ ctr,
                                                        float* __restrict__ split_out) {
-  __shared__ uint32_t tmp[4];
   __shared__ uint32_t red[2][4];
-  __shared__ int is_last;
   const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
   const ChunkEntry ch = chunks[blockIdx.x];
   const SegState s = st[ch.seg];
@@ -390,7 +426,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_count(const ChunkEntry* __restr
   const float* kx = x + (int64_t)s.axis * tot;
   uint32_t nl = 0, ne = 0;
   for (int64_t i = ch.b + tid; i < ch.e; i += kBuildBlock) {
-    uint32_t k = fkey(kx[i]);
+    const uint32_t k = fkey(kx[i]);
     nl += k < pivot;
     ne += k == pivot;
   }
@@ -404,90 +440,59 @@ __global__ __launch_bounds__(kBuildBlock) void k_count(const ChunkEntry* __restr
   if (tid == 0) {
     cnt[2 * blockIdx.x] = (int32_t)(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
     cnt[2 * blockIdx.x + 1] = (int32_t)(red[1][0] + red[1][1] + red[1][2] + red[1][3]);
-  }
-  __threadfence();
-  __syncthreads();
-  const SegEntry se = segs[ch.seg];
-  if (tid == 0) is_last = atomicAdd(ctr + ch.seg, 1u) == (uint32_t)(se.n_chunks - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  uint32_t run_l = 0, run_e = 0;
-  for (int base = 0; base < se.n_chunks; base += kBuildBlock) {
-    int c = base + tid;
-    uint32_t vl = 0, ve = 0;
-    if (c < se.n_chunks) {
-      vl = (uint32_t)ld_agent_i32(cnt + 2 * (se.first_chunk + c));
-      ve = (uint32_t)ld_agent_i32(cnt + 2 * (se.first_chunk + c) + 1);
-    }
-    uint32_t il = block_incl_scan(vl, tmp);
-    uint32_t ie = block_incl_scan(ve, tmp);
-    if (c < se.n_chunks) {
-      pref[2 * (se.first_chunk + c)] = (int32_t)(run_l + il - vl);
-      pref[2 * (se.first_chunk + c) + 1] = (int32_t)(run_e + ie - ve);
-    }
-    __shared__ uint32_t last_l, last_e;
-    if (tid == kBuildBlock - 1) {
-      last_l = il;
-      last_e = ie;
-    }
-    __syncthreads();
-    run_l += last_l;
-    run_e += last_e;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    split_out[se.node] = fkey_inv(pivot);
-    ctr[ch.seg] = 0;
+    const SegEntry se = segs[ch.seg];
+    if (blockIdx.x == (unsigned)se.first_chunk) split_out[se.node] = fkey_inv(pivot);
   }
 }
 
-// Stable partition of each segment around its pivot into the other buffer,
-// accumulating the children's tight boxes.  Each wave owns a contiguous
-// quarter of the chunk: it first counts its keys below / equal to the pivot,
-// one barrier publishes the per-wave counts, then every wave scatters its rows
-// in order with wave ballots only.
+// Stable partition of each chunk around its node's pivot.  A tile of rows is
+// partitioned inside LDS (left rows first, both in input order) and then
+// written as two contiguous runs per coordinate array, so every global store
+// is coalesced.  The chunk's left and right boxes are left in cbox.
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __restrict__ chunks,
                                                          const SegEntry* __restrict__ segs,
                                                          const SegState* __restrict__ st,
-                                                         const int32_t* __restrict__ pref,
+                                                         const int32_t* __restrict__ cnt,
                                                          const float* __restrict__ xin,
                                                          const int32_t* __restrict__ pin,
                                                          float* __restrict__ xout,
                                                          int32_t* __restrict__ pout, int64_t tot,
-                                                         uint32_t* __restrict__ ubox,
+                                                         uint32_t* __restrict__ cbox,
                                                          int32_t* __restrict__ bad) {
-  __shared__ uint32_t wcnt[2][4];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+  constexpr int T = scatter_tile<D>();
+  constexpr int R = T / kBuildBlock;  // rows per thread in a tile
+  __shared__ float sx[D][T];
+  __shared__ int32_t sp[T];
+  __shared__ uint32_t tmp[4];
+  __shared__ uint32_t red[4 * 2 * D];
+  __shared__ uint32_t tot_eq, tot_left;
+  __shared__ int64_t pre[2];
+  const int tid = threadIdx.x, lane = lane_id();
   const ChunkEntry ch = chunks[blockIdx.x];
   const SegEntry se = segs[ch.seg];
   const SegState s = st[ch.seg];
   const uint32_t pivot = s.prefix;
   const int64_t n_eq_left = (int64_t)s.rank + 1;
   const float* kx = xin + (int64_t)s.axis * tot;
-  const int64_t len = ch.e - ch.b;
-  const int64_t wb = ch.b + len * wave / 4, we = ch.b + len * (wave + 1) / 4;
-  uint32_t nl = 0, ne = 0;
-  for (int64_t i = wb + lane; i < we; i += kWave) {
-    const uint32_t k = fkey(kx[i]);
-    nl += k < pivot;
-    ne += k == pivot;
+  // keys below / equal to the pivot in the earlier chunks of this node
+  {
+    uint32_t nl = 0, ne = 0;
+    for (int c = se.first_chunk + tid; c < (int)blockIdx.x; c += kBuildBlock) {
+      nl += (uint32_t)cnt[2 * c];
+      ne += (uint32_t)cnt[2 * c + 1];
+    }
+    const uint32_t il = block_incl_scan(nl, tmp);
+    const uint32_t ie = block_incl_scan(ne, tmp);
+    if (tid == kBuildBlock - 1) {
+      pre[0] = il;
+      pre[1] = ie;
+    }
+    __syncthreads();
   }
-  nl = wave_sum(nl);
-  ne = wave_sum(ne);
-  if (lane == 0) {
-    wcnt[0][wave] = nl;
-    wcnt[1][wave] = ne;
-  }
-  __syncthreads();
-  int64_t less_before = pref[2 * blockIdx.x], eq_before = pref[2 * blockIdx.x + 1];
-  for (int w = 0; w < wave; ++w) {
-    less_before += wcnt[0][w];
-    eq_before += wcnt[1][w];
-  }
+  const int64_t less_before = pre[0], eq_before = pre[1];
   const int64_t left_before = less_before + min(eq_before, n_eq_left);
-  const int64_t right_before = (wb - se.b) - left_before;
+  const int64_t right_before = (ch.b - se.b) - left_before;
   uint32_t lmin[D], lmax[D], rmin[D], rmax[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -495,28 +500,45 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
     lmax[a] = rmax[a] = 0u;
   }
   int64_t run_left = 0, run_right = 0, run_eq = 0;
-  for (int64_t base = wb; base < we; base += kWave) {
-    const int64_t i = base + lane;
-    const bool valid = i < we;
-    const uint32_t k = valid ? fkey(kx[i]) : 0xFFFFFFFFu;
-    const bool less = valid && k < pivot;
-    const bool eq = valid && k == pivot;
-    const uint64_t be = __ballot(eq);
-    const int64_t eq_rank = eq_before + run_eq + lanes_below(be);
-    const bool left = less || (eq && eq_rank < n_eq_left);
-    const uint64_t bl = __ballot(left);
-    const int lpos = lanes_below(bl);
-    if (valid) {
-      int64_t dst = left ? se.b + left_before + run_left + lpos
-                         : se.m + right_before + run_right + (lane - lpos);
-      if (dst < se.b || dst >= se.e) {  // cannot happen; keeps a logic slip in bounds
-        atomicOr(bad, 2);
-        dst = se.b;
-      }
+  for (int64_t base = ch.b; base < ch.e; base += T) {
+    const int nt = (int)min((int64_t)T, ch.e - base);
+    const int r0 = tid * R;  // this thread's first row in the tile
+    uint32_t key[R];
+    uint32_t my_eq = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      key[r] = r0 + r < nt ? fkey(kx[base + r0 + r]) : 0xFFFFFFFFu;
+      my_eq += (r0 + r < nt) && key[r] == pivot;
+    }
+    const uint32_t eq_inc = block_incl_scan(my_eq, tmp);
+    if (tid == kBuildBlock - 1) tot_eq = eq_inc;
+    uint32_t eq_rank = (uint32_t)(eq_before + run_eq) + eq_inc - my_eq;
+    uint32_t left_bits = 0, my_left = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool valid = r0 + r < nt;
+      const bool eq = valid && key[r] == pivot;
+      const bool left = valid && (key[r] < pivot || (eq && (int64_t)eq_rank < n_eq_left));
+      eq_rank += eq;
+      left_bits |= (uint32_t)left << r;
+      my_left += left;
+    }
+    const uint32_t left_inc = block_incl_scan(my_left, tmp);
+    if (tid == kBuildBlock - 1) tot_left = left_inc;
+    __syncthreads();
+    const int tl = (int)tot_left;
+    uint32_t lpos = left_inc - my_left;  // left rows before this thread's rows
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r0 + r >= nt) break;
+      const int64_t row = base + r0 + r;
+      const bool left = (left_bits >> r) & 1u;
+      const int dst = left ? (int)lpos : tl + (r0 + r - (int)lpos);
+      lpos += left;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const float v = xin[a * tot + i];
-        xout[a * tot + dst] = v;
+        const float v = xin[a * tot + row];
+        sx[a][dst] = v;
         const uint32_t kv = fkey(v);
         if (left) {
           lmin[a] = min(lmin[a], kv);
@@ -526,27 +548,30 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
           rmax[a] = max(rmax[a], kv);
         }
       }
-      pout[dst] = pin[i];
+      sp[dst] = pin[row];
     }
-    const int64_t nvalid = min((int64_t)kWave, we - base);
-    run_eq += __popcll(be);
-    run_left += __popcll(bl);
-    run_right += nvalid - __popcll(bl);
+    __syncthreads();
+    for (int i = tid; i < nt; i += kBuildBlock) {
+      int64_t g = i < tl ? se.b + left_before + run_left + i : se.m + right_before + run_right + (i - tl);
+      if (g < se.b || g >= se.e) {  // cannot happen; keeps a logic slip in bounds
+        atomicOr(bad, 2);
+        g = se.b;
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) xout[a * tot + g] = sx[a][i];
+      pout[g] = sp[i];
+    }
+    run_eq += tot_eq;
+    run_left += tl;
+    run_right += nt - tl;
+    __syncthreads();
   }
   if (se.child >= 0) {
-    uint32_t* c = ubox + se.child * 2 * D;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const uint32_t v0 = wave_umin(lmin[a]), v1 = wave_umax(lmax[a]);
-      const uint32_t v2 = wave_umin(rmin[a]), v3 = wave_umax(rmax[a]);
-      if (lane == 0) {
-        if (v0 != 0xFFFFFFFFu) atomicMin(c + a, v0);
-        if (v1 != 0u) atomicMax(c + D + a, v1);
-        if (v2 != 0xFFFFFFFFu) atomicMin(c + 2 * D + a, v2);
-        if (v3 != 0u) atomicMax(c + 3 * D + a, v3);
-      }
-    }
+    uint32_t* c = cbox + (int64_t)blockIdx.x * 4 * D;
+    block_box<D>(lmin, lmax, red, c);
+    block_box<D>(rmin, rmax, red, c + 2 * D);
   }
+  (void)lane;
 }
 
 // Finishes every level below a node inside one workgroup's LDS and writes the
@@ -814,11 +839,9 @@ static kdt_status run_build(const Plan& p, const PlanDev& pd, const float* d_pts
                             const BuildScratch& w, const BuildOut& o, int phase,
                             hipStream_t stream) {
   const int64_t tot = p.total;
-  const int ns = (int)p.sets.size();
   if (phase == 0) {
-    k_init_roots<D><<<(ns + 127) / 128, 128, 0, stream>>>(pd.sets, ns, w.ubox);
     k_ingest<D><<<(unsigned)p.root_chunks.size(), kBuildBlock, 0, stream>>>(
-        pd.root_chunks, pd.sets, d_pts, w.x[0], w.p[0], tot, w.ubox, w.bad);
+        pd.root_chunks, pd.sets, d_pts, w.x[0], w.p[0], tot, w.pbox, w.bad);
     KDT_HIP(hipGetLastError());
     return KDT_OK;
   }
@@ -826,16 +849,17 @@ static kdt_status run_build(const Plan& p, const PlanDev& pd, const float* d_pts
     const int nseg = (int)p.segs[l].size();
     const unsigned nch = (unsigned)p.chunks[l].size();
     const int src = l & 1, dst = src ^ 1;
-    k_level_init<D><<<(nseg + 127) / 128, 128, 0, stream>>>(pd.segs[l], nseg, w.st, w.ubox, o.box,
-                                                            o.axis);
-    for (int pass = 0; pass < kRadixPasses; ++pass)
-      k_radix_pass<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], pd.segs[l], w.st, w.hist,
-                                                       w.ctr, w.x[src], tot);
+    k_level_init<D><<<(nseg + 3) / 4, kBuildBlock, 0, stream>>>(pd.segs[l], nseg, w.st, w.pbox,
+                                                                w.cbox, o.box, o.axis);
+    for (int pass = 0; pass < kRadixPasses; ++pass) {
+      k_hist<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], w.st, w.x[src], tot, w.chist);
+      k_select<<<nseg, kBuildBlock, 0, stream>>>(pd.segs[l], w.st, w.chist);
+    }
     k_count<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], pd.segs[l], w.st, w.x[src], tot,
-                                                w.cnt, w.pref, w.ctr, o.split);
-    k_scatter<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], pd.segs[l], w.st, w.pref,
+                                                w.cnt, o.split);
+    k_scatter<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], pd.segs[l], w.st, w.cnt,
                                                   w.x[src], w.p[src], w.x[dst], w.p[dst], tot,
-                                                  w.ubox, w.bad);
+                                                  w.cbox, w.bad);
   }
   const size_t smem = lds_bytes(D, p.lds_cap);
   k_lds_subtree<D><<<(unsigned)p.subs.size(), kBuildBlock, smem, stream>>>(
@@ -873,14 +897,14 @@ kdt_status build_scratch_alloc(const Plan& p, const PlanDev& pd, BuildScratch& w
     if (stream == kPlainAlloc) return hipMalloc(ptr, std::max<size_t>(bytes, 256)) == hipSuccess;
     return dev_alloc(ptr, bytes, stream) == hipSuccess;
   };
+  const int64_t nroot = (int64_t)p.root_chunks.size();
   bool ok = A((void**)&w.x[0], sizeof(float) * d * tot) && A((void**)&w.x[1], sizeof(float) * d * tot) &&
             A((void**)&w.p[0], sizeof(int32_t) * tot) && A((void**)&w.p[1], sizeof(int32_t) * tot) &&
-            A((void**)&w.ubox, sizeof(uint32_t) * 2 * d * p.n_nodes) &&
+            A((void**)&w.pbox, sizeof(uint32_t) * 2 * d * nroot) &&
+            A((void**)&w.cbox, sizeof(uint32_t) * 4 * d * pd.max_chunks) &&
             A((void**)&w.st, sizeof(SegState) * pd.max_segs) &&
-            A((void**)&w.hist, sizeof(uint32_t) * kBins * pd.max_segs) &&
-            A((void**)&w.ctr, sizeof(uint32_t) * pd.max_segs) &&
-            A((void**)&w.cnt, sizeof(int32_t) * 2 * pd.max_chunks) &&
-            A((void**)&w.pref, sizeof(int32_t) * 2 * pd.max_chunks) && A((void**)&w.bad, 256);
+            A((void**)&w.chist, sizeof(uint32_t) * kBins * pd.max_chunks) &&
+            A((void**)&w.cnt, sizeof(int32_t) * 2 * pd.max_chunks) && A((void**)&w.bad, 256);
   if (!ok) {
     build_scratch_free(w, stream);
     kdt_set_error("device allocation failed for the build scratch (%lld points)", (long long)tot);
@@ -890,7 +914,7 @@ kdt_status build_scratch_alloc(const Plan& p, const PlanDev& pd, BuildScratch& w
 }
 
 void build_scratch_free(BuildScratch& w, hipStream_t stream) {
-  void* ptrs[] = {w.x[0], w.x[1], w.p[0], w.p[1], w.ubox, w.st, w.hist, w.ctr, w.cnt, w.pref, w.bad};
+  void* ptrs[] = {w.x[0], w.x[1], w.p[0], w.p[1], w.pbox, w.cbox, w.st, w.chist, w.cnt, w.bad};
   for (void* q : ptrs)
     if (q) (void)(stream == kPlainAlloc ? hipFree(q) : hipFreeAsync(q, stream));
   w = BuildScratch();
@@ -919,11 +943,7 @@ void build_init_once() {
 
 kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
                         const BuildScratch& w, const BuildOut& o, int phase, hipStream_t stream) {
-  if (phase == 0) {
-    zero_u32(w.hist, kBins * (int64_t)pd.max_segs, stream);
-    zero_u32(w.ctr, (int64_t)pd.max_segs, stream);
-    zero_u32(reinterpret_cast<uint32_t*>(w.bad), 1, stream);
-  }
+  if (phase == 0) zero_u32(reinterpret_cast<uint32_t*>(w.bad), 1, stream);
   build_init_once();
   switch (p.d) {
     case 2: return run_build<2>(p, pd, d_pts, w, o, phase, stream);

@@ -82,6 +82,13 @@ struct SegEntry {
   int64_t child;        // global node id of the left child (right = child + 1)
   int32_t first_chunk;  // chunk ids [first_chunk, first_chunk + n_chunks)
   int32_t n_chunks;
+  // Where the partial boxes of this node's points were left: the root pass
+  // chunks [src_first, src_first + src_count) (src_side < 0) or the chunks of
+  // the parent at the previous level, left (0) or right (1) side.
+  int32_t src_first;
+  int32_t src_count;
+  int32_t src_side;
+  int32_t pad;
 };
 
 struct ChunkEntry {
@@ -142,12 +149,11 @@ struct PlanDev {
 struct BuildScratch {
   float* x[2] = {nullptr, nullptr};
   int32_t* p[2] = {nullptr, nullptr};
-  uint32_t* ubox = nullptr;
+  uint32_t* pbox = nullptr;   // partial boxes of the root pass, [root chunk][2][d]
+  uint32_t* cbox = nullptr;   // partial child boxes, [chunk][side][2][d]
   SegState* st = nullptr;
-  uint32_t* hist = nullptr;
-  uint32_t* ctr = nullptr;
-  int32_t* cnt = nullptr;
-  int32_t* pref = nullptr;
+  uint32_t* chist = nullptr;  // per-chunk digit histograms, [chunk][256]
+  int32_t* cnt = nullptr;     // per-chunk (below, equal) pivot counts
   int32_t* bad = nullptr;
 };
 
