@@ -15,7 +15,7 @@
 #include <cstring>
 #include <vector>
 
-#include "kdt_query.h"
+#include "kdt_packet.h"
 
 namespace kdt {
 
@@ -74,6 +74,48 @@ __global__ __launch_bounds__(kBQ) void k_knn_forest(const SetDesc* __restrict__ 
       knn_one<D, KC>(t, q, best, &stk[0][threadIdx.x], kBQ);
       knn_write<KC>(best, k, 0, sd.off + id, oidx, od2);
     }
+  }
+}
+
+// Persistent wave-level work queue over packets of 64 consecutive points of
+// one set (packets never straddle sets, so a wave always walks one tree).
+template <int D, int KC>
+__global__ __launch_bounds__(256) void k_knn_forest_packet(
+    const SetDesc* __restrict__ sets, int n_sets, const int64_t* __restrict__ pbase,
+    const float* __restrict__ rec, const float* __restrict__ box, int k, int leaf_cap,
+    int32_t* __restrict__ oidx, float* __restrict__ od2, unsigned long long* __restrict__ ctr) {
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  float* leafbuf = lds + (size_t)wave * leaf_cap * rec_stride(D);
+  const int64_t n_packets = pbase[n_sets];
+  for (;;) {
+    unsigned long long got = 0;
+    if (lane == 0) got = atomicAdd(ctr, 1ull);
+    const int64_t pk = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(got >> 32)) << 32) |
+                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)got));
+    if (pk >= n_packets) break;
+    int lo = 0, hi = n_sets - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pbase[mid] <= pk) lo = mid;
+      else hi = mid - 1;
+    }
+    const SetDesc sd = sets[lo];
+    const TreeView t = set_view<D>(sd, rec, box);
+    const int64_t pos = (pk - pbase[lo]) * 64 + lane;
+    const bool active = pos < sd.n;
+    float q[D];
+    int32_t id = 0;
+    if (active) {
+      load_rec<D>(t.rec, pos, q, id);
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) q[a] = 0.0f;
+    }
+    TopK<KC> best;
+    best.init(k);
+    packet_knn<D, KC>(t, q, active, best, leafbuf);
+    if (active) knn_write<KC>(best, k, 0, sd.off + id, oidx, od2);
   }
 }
 
@@ -171,6 +213,7 @@ struct kdt_batch_plan {
   BuildOut out{};
   int32_t* parent = nullptr;
   uint32_t* conn = nullptr;
+  int64_t* pbase = nullptr;  // first packet of each set, [n_sets + 1]
   unsigned long long* ctr = nullptr;
   int knn_blocks = 0, fof_blocks = 0;
   hipStream_t cap = nullptr;
@@ -180,11 +223,11 @@ struct kdt_batch_plan {
 };
 
 template <int D, int KC>
-static int occupancy_blocks(const void* fn, size_t smem) {
+static int occupancy_blocks(const void* fn, size_t smem, int block) {
   int per_cu = 0, dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBQ, smem);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, smem);
   return std::max(1, per_cu) * std::max(1, cus);
 }
 
@@ -196,7 +239,18 @@ static kdt_status forest_queries(kdt_batch_plan* bp, const float* d_l, int32_t* 
   const int64_t tot = p.total;
   k_zero_u64<<<1, 64, 0, s>>>(bp->ctr, 2);
   const int k = bp->k;
-  if (k <= 8)
+  if (bp->leaf <= 64) {
+    const size_t smem = sizeof(float) * (size_t)bp->leaf * rec_stride(D) * 4;
+    const unsigned g = (unsigned)bp->knn_blocks;
+    if (k <= 8)
+      k_knn_forest_packet<D, 8><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
+    else if (k <= 16)
+      k_knn_forest_packet<D, 16><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
+    else if (k <= 32)
+      k_knn_forest_packet<D, 32><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
+    else
+      k_knn_forest_packet<D, 64><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
+  } else if (k <= 8)
     k_knn_forest<D, 8><<<bp->knn_blocks, kBQ, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box,
                                                       tot, k, d_idx, d_d2, bp->ctr);
   else if (k <= 16)
@@ -242,12 +296,22 @@ static kdt_status forest_pipeline(kdt_batch_plan* bp, const float* d_pts, const 
 template <int D>
 static void size_grids(kdt_batch_plan* bp) {
   const void* kf = nullptr;
-  if (bp->k <= 8) kf = reinterpret_cast<const void*>(&k_knn_forest<D, 8>);
-  else if (bp->k <= 16) kf = reinterpret_cast<const void*>(&k_knn_forest<D, 16>);
-  else if (bp->k <= 32) kf = reinterpret_cast<const void*>(&k_knn_forest<D, 32>);
-  else kf = reinterpret_cast<const void*>(&k_knn_forest<D, 64>);
-  bp->knn_blocks = occupancy_blocks<D, 0>(kf, 0);
-  bp->fof_blocks = occupancy_blocks<D, 0>(reinterpret_cast<const void*>(&k_fof_forest<D>), 0);
+  size_t smem = 0;
+  if (bp->leaf <= 64) {
+    smem = sizeof(float) * (size_t)bp->leaf * rec_stride(D) * 4;
+    if (bp->k <= 8) kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 8>);
+    else if (bp->k <= 16) kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 16>);
+    else if (bp->k <= 32) kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 32>);
+    else kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 64>);
+    bp->knn_blocks = occupancy_blocks<D, 0>(kf, smem, 256);
+  } else {
+    if (bp->k <= 8) kf = reinterpret_cast<const void*>(&k_knn_forest<D, 8>);
+    else if (bp->k <= 16) kf = reinterpret_cast<const void*>(&k_knn_forest<D, 16>);
+    else if (bp->k <= 32) kf = reinterpret_cast<const void*>(&k_knn_forest<D, 32>);
+    else kf = reinterpret_cast<const void*>(&k_knn_forest<D, 64>);
+    bp->knn_blocks = occupancy_blocks<D, 0>(kf, 0, kBQ);
+  }
+  bp->fof_blocks = occupancy_blocks<D, 0>(reinterpret_cast<const void*>(&k_fof_forest<D>), 0, kBQ);
 }
 
 static void release(kdt_batch_plan* bp) {
@@ -258,6 +322,7 @@ static void release(kdt_batch_plan* bp) {
   if (bp->tree_block) (void)hipFree(bp->tree_block);
   if (bp->parent) (void)hipFree(bp->parent);
   if (bp->conn) (void)hipFree(bp->conn);
+  if (bp->pbase) (void)hipFree(bp->pbase);
   if (bp->ctr) (void)hipFree(bp->ctr);
   plan_release(bp->dev);
 }
@@ -322,6 +387,16 @@ extern "C" kdt_status kdt_batch_plan_create(const int64_t* h_offsets, int32_t n_
        hipMalloc((void**)&bp->ctr, 256) != hipSuccess)) {
     kdt_set_error("kdt_batch_plan_create: device allocation failed (%lld points)", (long long)tot);
     st = KDT_ENOMEM;
+  }
+  if (st == KDT_OK) {
+    std::vector<int64_t> pb(n_sets + 1, 0);
+    for (int i = 0; i < n_sets; ++i) pb[i + 1] = pb[i] + (h_offsets[i + 1] - h_offsets[i] + 63) / 64;
+    if (hipMalloc((void**)&bp->pbase, sizeof(int64_t) * (n_sets + 1)) != hipSuccess ||
+        hipMemcpy(bp->pbase, pb.data(), sizeof(int64_t) * (n_sets + 1), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+      kdt_set_error("kdt_batch_plan_create: cannot upload the packet table");
+      st = KDT_ENOMEM;
+    }
   }
   if (st == KDT_OK && hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking) != hipSuccess) {
     kdt_set_error("kdt_batch_plan_create: cannot create the capture stream");

@@ -1,0 +1,168 @@
+// kdt_packet.h -- wave-coherent traversals shared by the single-tree and the
+// batched kernels (gfx950, wave64).
+//
+// A wave of 64 spatially coherent queries walks one tree together.  The node
+// stack is held in the wave's lane registers (entry i lives in lane i, popped
+// with readlane), so it costs no memory.  A node is entered when at least one
+// lane needs it (wave ballot); a visited leaf is copied once into the wave's
+// LDS slice and its points are read back as broadcasts, so one coalesced load
+// serves 64 queries.
+#pragma once
+
+#include "kdt_query.h"
+
+namespace kdt {
+
+// kNN of the 64 queries of a wave (Algorithm 2 semantics).  Each lane keeps its
+// own register top-k keyed by (d2, index), so the result is exactly the k
+// smallest keys, the same as any exact traversal.  Leaves must hold at most 64
+// points; leafbuf is the wave's LDS slice of leaf_size * rec_stride(D) floats.
+template <int D, int KC>
+__device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], bool active,
+                                           TopK<KC>& best, float* leafbuf) {
+  constexpr int S = rec_stride(D);
+  const int lane = lane_id();
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  uint32_t stackv = 0;  // lane i holds stack entry i
+  int sp = 1;
+  uint64_t mask = 0;    // this lane's pending candidates in the staged leaf
+  // One flat loop (the candidate list is then live across a single loop
+  // header): a round either inserts one pending candidate per lane, or pops
+  // and visits the next node.
+  for (;;) {
+    if (__any(mask != 0)) {
+      const bool has = mask != 0;
+      const int i = has ? __ffsll((unsigned long long)mask) - 1 : 0;
+      mask &= mask - 1;
+      const float* r = leafbuf + i * S;
+      float x[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) x[a] = r[a];
+      const uint64_t key = make_key(sq_dist<D>(x, p), __float_as_int(r[D]));
+      best.insert(has ? key : kEmptyKey);
+      continue;
+    }
+    if (sp == 0) break;
+    --sp;
+    const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)stackv, sp);
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    const bool need = active && box_mindist<D>(lo, hi, p) <= best.worst_d2();
+    if (!__any(need)) continue;
+    if (node >= first_leaf) {
+      const int64_t j = node - first_leaf;
+      const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
+      const int cnt = (int)(e - b);
+      wave_sync();  // every lane is done with the previous leaf
+      const float4* src = reinterpret_cast<const float4*>(t.rec + b * S);
+      float4* dst = reinterpret_cast<float4*>(leafbuf);
+      for (int i = lane; i < cnt * (S / 4); i += 64) dst[i] = src[i];
+      wave_sync();
+      // Mark the leaf points (at most 64) that beat this lane's current k-th
+      // candidate; the rounds above then insert them, so the wave pays for
+      // the largest per-lane count of insertions rather than for every point
+      // some lane wants.
+      const uint64_t w = best.worst();
+#pragma unroll 1
+      for (int i = 0; i < cnt; ++i) {
+        const float* r = leafbuf + i * S;
+        float x[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = r[a];
+        const uint64_t key = make_key(sq_dist<D>(x, p), __float_as_int(r[D]));
+        mask |= (uint64_t)(key < w) << i;
+      }
+      if (!active) mask = 0;
+    } else {
+      const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
+      load_box<D>(t.box, c0, lo, hi);
+      const float d0 = box_mindist<D>(lo, hi, p);
+      load_box<D>(t.box, c1, lo, hi);
+      const float d1 = box_mindist<D>(lo, hi, p);
+      const float wd = best.worst_d2();
+      const bool n0 = active && d0 <= wd, n1 = active && d1 <= wd;
+      const uint64_t b0 = __ballot(n0), b1 = __ballot(n1);
+      const int pref0 = __popcll(__ballot(n0 && d0 <= d1));
+      const int pref1 = __popcll(__ballot(n1 && d1 < d0));
+      const bool first0 = pref0 >= pref1;
+      const uint32_t nn = first0 ? c0 : c1, ff = first0 ? c1 : c0;
+      const bool need_n = first0 ? b0 != 0 : b1 != 0;
+      const bool need_f = first0 ? b1 != 0 : b0 != 0;
+      if (need_f) {
+        stackv = lane == sp ? ff : stackv;
+        ++sp;
+      }
+      if (need_n) {
+        stackv = lane == sp ? nn : stackv;
+        ++sp;
+      }
+    }
+  }
+}
+
+// Closed-ball counts of the 64 queries of a wave (Algorithm 3 semantics): a
+// node farther than r from every lane is skipped, a node entirely inside a
+// lane's ball adds its size to that lane, and leaves are scanned only for the
+// lanes whose ball cuts them.  Each stack entry carries the mask of lanes that
+// still need that subtree, so a lane that has counted a whole node never
+// counts its descendants again.  Leaves must hold at most 64 points.
+template <int D>
+__device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const float p[D],
+                                                      bool active, float r2, float* leafbuf) {
+  constexpr int S = rec_stride(D);
+  const int lane = lane_id();
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int64_t count = 0;
+  uint32_t stackv = 0;                              // lane i: node of entry i
+  uint32_t stk_lo = 0xFFFFFFFFu, stk_hi = 0xFFFFFFFFu;  // lane i: lane mask of entry i
+  int sp = 1;
+  while (sp > 0) {
+    --sp;
+    const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)stackv, sp);
+    const uint64_t live = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)stk_hi, sp) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)stk_lo, sp);
+    const bool mine = active && ((live >> lane) & 1ull);
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    const bool touch = mine && box_mindist<D>(lo, hi, p) <= r2;
+    if (!__any(touch)) continue;
+    const bool full = touch && box_maxdist<D>(lo, hi, p) <= r2;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    if (full) count += e - b;
+    const bool part = touch && !full;
+    const uint64_t pm = __ballot(part);
+    if (pm == 0) continue;
+    if (node >= first_leaf) {
+      const int cnt = (int)(e - b);
+      wave_sync();
+      const float4* src = reinterpret_cast<const float4*>(t.rec + b * S);
+      float4* dst = reinterpret_cast<float4*>(leafbuf);
+      for (int i = lane; i < cnt * (S / 4); i += 64) dst[i] = src[i];
+      wave_sync();
+      int c = 0;
+#pragma unroll 1
+      for (int i = 0; i < cnt; ++i) {
+        const float* r = leafbuf + i * S;
+        float x[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = r[a];
+        c += sq_dist<D>(x, p) <= r2;
+      }
+      if (part) count += c;
+    } else {
+      const uint32_t mlo = (uint32_t)pm, mhi = (uint32_t)(pm >> 32);
+#pragma unroll
+      for (int c = 2; c >= 1; --c) {
+        stackv = lane == sp ? 2 * node + c : stackv;
+        stk_lo = lane == sp ? mlo : stk_lo;
+        stk_hi = lane == sp ? mhi : stk_hi;
+        ++sp;
+      }
+    }
+  }
+  return count;
+}
+
+}  // namespace kdt

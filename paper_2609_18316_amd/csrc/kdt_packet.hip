@@ -1,0 +1,114 @@
+// kdt_packet.hip -- single-tree kernels of the wave-coherent traversals
+// (kNN, Sec. 2.3 / Algorithm 2; ball counts, Algorithm 3) for gfx950.
+#include <hip/hip_runtime.h>
+
+#include "kdt_packet.h"
+
+namespace kdt {
+
+constexpr int kPWaves = 4;  // waves per workgroup (independent packets)
+
+template <int D>
+__device__ __forceinline__ bool load_query(const TreeView& t, const float* __restrict__ q,
+                                           int64_t nq, const int32_t* __restrict__ order,
+                                           int64_t s, float p[D], int64_t& row) {
+  if (s >= nq) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) p[a] = 0.0f;
+    return false;
+  }
+  if (q == nullptr) {
+    int32_t id = 0;
+    load_rec<D>(t.rec, s, p, id);
+    row = id;
+  } else {
+    row = order ? order[s] : s;
+#pragma unroll
+    for (int a = 0; a < D; ++a) p[a] = q[row * D + a];
+  }
+  return true;
+}
+
+template <int D, int KC>
+__global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const float* __restrict__ q,
+                                                             int64_t nq, int k,
+                                                             const int32_t* __restrict__ order,
+                                                             int mode, int32_t* __restrict__ oidx,
+                                                             float* __restrict__ od2, int leaf_cap) {
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t s0 = ((int64_t)blockIdx.x * kPWaves + wave) * 64;
+  if (s0 >= nq) return;  // whole wave idle
+  float p[D];
+  int64_t row = 0;
+  const bool active = load_query<D>(t, q, nq, order, s0 + lane, p, row);
+  TopK<KC> best;
+  best.init(k);
+  packet_knn<D, KC>(t, p, active, best, lds + (size_t)wave * leaf_cap * rec_stride(D));
+  if (active) knn_write<KC>(best, k, mode, row, oidx, od2);
+}
+
+template <int D>
+__global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const float* __restrict__ q,
+                                                               int64_t nq, float r2,
+                                                               const int32_t* __restrict__ order,
+                                                               int32_t* __restrict__ count,
+                                                               int leaf_cap) {
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t s0 = ((int64_t)blockIdx.x * kPWaves + wave) * 64;
+  if (s0 >= nq) return;
+  float p[D];
+  int64_t row = 0;
+  const bool active = load_query<D>(t, q, nq, order, s0 + lane, p, row);
+  const int64_t c = packet_range_count<D>(t, p, active, r2, lds + (size_t)wave * leaf_cap * rec_stride(D));
+  if (active) count[row] = (int32_t)c;
+}
+
+template <int D>
+kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, int k,
+                             int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
+                             hipStream_t stream) {
+  const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
+  const size_t smem = sizeof(float) * (size_t)leaf * rec_stride(D) * kPWaves;
+  if (k <= 8)
+    k_knn_packet<D, 8><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2, leaf);
+  else if (k <= 16)
+    k_knn_packet<D, 16><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2, leaf);
+  else if (k <= 32)
+    k_knn_packet<D, 32><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2, leaf);
+  else
+    k_knn_packet<D, 64><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2, leaf);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_knn: packet kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+template <int D>
+kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
+                               const int32_t* order, int32_t* d_count, hipStream_t stream) {
+  const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
+  const size_t smem = sizeof(float) * (size_t)leaf * rec_stride(D) * kPWaves;
+  k_range_packet<D><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, r2, order, d_count, leaf);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_range: packet kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+#define KDT_INST(D)                                                                                \
+  template kdt_status knn_packet_launch<D>(const TreeView&, int, const float*, int64_t, int,       \
+                                           int32_t*, float*, int, const int32_t*, hipStream_t);    \
+  template kdt_status range_packet_launch<D>(const TreeView&, int, const float*, int64_t, float,   \
+                                             const int32_t*, int32_t*, hipStream_t);
+KDT_INST(2)
+KDT_INST(3)
+KDT_INST(4)
+KDT_INST(8)
+KDT_INST(16)
+#undef KDT_INST
+
+}  // namespace kdt

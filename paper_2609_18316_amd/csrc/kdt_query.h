@@ -391,5 +391,8 @@ template <int D>
 kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, int k,
                              int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
                              hipStream_t stream);
+template <int D>
+kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
+                               const int32_t* order, int32_t* d_count, hipStream_t stream);
 
 }  // namespace kdt

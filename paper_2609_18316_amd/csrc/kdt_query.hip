@@ -259,8 +259,15 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
   const TreeView v = view_of(t);
   const float r2 = r * r;
   const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
-  k_range<D, false><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
   kdt_status st = KDT_OK;
+  if (t->leaf <= 64)
+    st = range_packet_launch<D>(v, t->leaf, d_q, nq, r2, order, d_count, stream);
+  else
+    k_range<D, false><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
+  if (st != KDT_OK) {
+    if (order) (void)hipFreeAsync(order, stream);
+    return st;
+  }
   if (d_off) {
     void* tmp = nullptr;
     size_t tb = 0;
