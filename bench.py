@@ -110,7 +110,7 @@ def main():
                 torch.empty(int(boff[-1]), dtype=torch.int32, device=dev))
         batch = (plan, bxt, blt, bout, int(boff[-1]))
 
-    phases = ["build", "knn", "range", "fof", "hsml", "p2m_fwd", "p2m_bwd"]
+    phases = ["build", "knn_order", "knn", "range", "fof", "hsml", "p2m_fwd", "p2m_bwd"]
     if batch:
         phases += ["batch_graph"]
     ev = {p: [] for p in phases}
@@ -127,9 +127,11 @@ def main():
         mark("start")
         tree = kdt.build(xt, leaf_size=LEAF, check_finite=True)
         mark("build")
-        idx, d2 = tree.knn(qt, K)
+        order = tree.query_order(qt)
+        mark("knn_order")
+        idx, d2 = tree.knn(qt, K, order=order)
         mark("knn")
-        cnt = tree.range(qt, RADIUS)
+        cnt = tree.range(qt, RADIUS, order=order)
         mark("range")
         lab = tree.fof(l_fof)
         mark("fof")
@@ -163,9 +165,12 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     avg = {p: float(np.mean(ev[p])) for p in phases}
 
-    knn_qps = N_QUERIES / (avg["knn"] * 1e-3)
-    # Roofline of the kNN stage: compulsory bytes per query are the query
-    # coordinates in (4 d) plus k (index, d2) pairs out (8 k).
+    # Headline: the whole kNN call as a user makes it (ordering the queries
+    # along the tree, then the traversal kernel).
+    knn_qps = N_QUERIES / ((avg["knn_order"] + avg["knn"]) * 1e-3)
+    # Roofline of the traversal kernel (one launch, timed alone): compulsory
+    # bytes per query are the query coordinates in (4 d) plus k (index, d2)
+    # pairs out (8 k).
     knn_bytes = N_QUERIES * (4 * 3 + 8 * K)
     achieved = knn_bytes / (avg["knn"] * 1e-3) / 1e9
     out = {
@@ -196,7 +201,8 @@ def main():
         "p2m_bwd_over_fwd": avg["p2m_bwd"] / avg["p2m_fwd"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "kNN stage (k=32), compulsory bytes 4d + 8k per query"},
+                     "kernel": "k_knn_packet<3,32,0> (kNN traversal, k=32): compulsory bytes "
+                               "4d + 8k = 268 per query"},
     }
     if batch:
         # The baseline (the single-tree entry points once per set, eager) is

@@ -69,6 +69,8 @@ typedef struct {
                              64 queries of a wave, leaves staged in LDS (trees
                              with leaf_size <= 64; larger leaves use 1).
                              Results are identical either way. */
+    const int32_t *order; /* NULL, or a device permutation [nq] from
+                             kdt_query_order to use instead of sorting again. */
 } kdt_query_opts;
 
 /* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side
@@ -225,6 +227,17 @@ kdt_status kdt_p2m_backward(const float *d_x, const float *d_m, const float *d_h
                             const kdt_grid *grid, const int32_t *d_order,
                             const float *d_ggrid, float *d_gm, float *d_gx,
                             hipStream_t stream);
+
+/*
+ * kdt_query_order -- writes into d_order [nq] (int32, device) a permutation of
+ * the queries that follows the tree: queries sorted by the leaf reached when
+ * descending towards the nearer child at every level.  Passing it back through
+ * kdt_query_opts.order lets repeated queries skip the sort.  Results of the
+ * queries never depend on the order.
+ * Errors: KDT_EINVAL (NULL pointer, nq outside [1, 2^31-1]), KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_query_order(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t *d_order,
+                           hipStream_t stream);
 
 /* Device pointer to the tree order: perm[t] is the input index of the point at
    tree position t (n int32, owned by the tree).  NULL on error. */

@@ -29,11 +29,13 @@ __device__ __forceinline__ bool load_query(const TreeView& t, const float* __res
   return true;
 }
 
-template <int D, int KC>
+// MODE 0 writes k (index, d2) pairs per row, 1 the k-th d2, 2 the k-th
+// distance (a compile-time choice, so each output form is its own kernel).
+template <int D, int KC, int MODE>
 __global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const float* __restrict__ q,
                                                              int64_t nq, int k,
                                                              const int32_t* __restrict__ order,
-                                                             int mode, int32_t* __restrict__ oidx,
+                                                             int32_t* __restrict__ oidx,
                                                              float* __restrict__ od2, int leaf_cap) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const f
   TopK<KC> best;
   best.init(k);
   packet_knn<D, KC>(t, p, active, best, lds + (size_t)wave * leaf_cap * rec_stride(D));
-  if (active) knn_write<KC>(best, k, mode, row, oidx, od2);
+  if (active) knn_write<KC>(best, k, MODE, row, oidx, od2);
 }
 
 template <int D>
@@ -71,14 +73,23 @@ kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int6
                              hipStream_t stream) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
   const size_t smem = sizeof(float) * (size_t)leaf * rec_stride(D) * kPWaves;
-  if (k <= 8)
-    k_knn_packet<D, 8><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2, leaf);
-  else if (k <= 16)
-    k_knn_packet<D, 16><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2, leaf);
-  else if (k <= 32)
-    k_knn_packet<D, 32><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2, leaf);
-  else
-    k_knn_packet<D, 64><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2, leaf);
+#define KDT_LAUNCH(KC, M) \
+  k_knn_packet<D, KC, M><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, d_idx, d_d2, leaf)
+#define KDT_BY_MODE(KC)          \
+  if (mode == 0) KDT_LAUNCH(KC, 0); \
+  else if (mode == 1) KDT_LAUNCH(KC, 1); \
+  else KDT_LAUNCH(KC, 2);
+  if (k <= 8) {
+    KDT_BY_MODE(8)
+  } else if (k <= 16) {
+    KDT_BY_MODE(16)
+  } else if (k <= 32) {
+    KDT_BY_MODE(32)
+  } else {
+    KDT_BY_MODE(64)
+  }
+#undef KDT_BY_MODE
+#undef KDT_LAUNCH
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_knn: packet kernel launch failed");
     return KDT_EDEVICE;

@@ -232,17 +232,19 @@ static kdt_status knn_dispatch(const kdt_tree* t, const float* d_q, int64_t nq, 
 
 template <int D>
 static kdt_status knn_impl(const kdt_tree* t, const float* d_q, int64_t nq, int k, int32_t* d_idx,
-                           float* d_d2, int mode, bool sort_q, int traversal, hipStream_t stream) {
+                           float* d_d2, int mode, bool sort_q, int traversal,
+                           const int32_t* given, hipStream_t stream) {
   int32_t* order = nullptr;
-  if (d_q && sort_q && nq > 1) {
+  if (d_q && !given && sort_q && nq > 1) {
     kdt_status st = order_queries<D>(t, d_q, nq, &order, stream);
     if (st != KDT_OK) return st;
   }
+  const int32_t* use = d_q ? (given ? given : order) : nullptr;
   if (t->leaf > 64) traversal = 1;  // the wave kernel marks at most 64 points per leaf
   kdt_status st = traversal == 1
-                      ? knn_dispatch<D>(t, d_q, nq, k, d_idx, d_d2, mode, order, stream)
+                      ? knn_dispatch<D>(t, d_q, nq, k, d_idx, d_d2, mode, use, stream)
                       : knn_packet_launch<D>(view_of(t), t->leaf, d_q, nq, k, d_idx, d_d2, mode,
-                                             order, stream);
+                                             use, stream);
   if (order) (void)hipFreeAsync(order, stream);
   return st;
 }
@@ -250,12 +252,14 @@ static kdt_status knn_impl(const kdt_tree* t, const float* d_q, int64_t nq, int 
 template <int D>
 static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, float r,
                              int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
-                             int64_t* required, bool sort_q, hipStream_t stream) {
-  int32_t* order = nullptr;
-  if (d_q && sort_q && nq > 1) {
-    kdt_status st = order_queries<D>(t, d_q, nq, &order, stream);
+                             int64_t* required, bool sort_q, const int32_t* given,
+                             hipStream_t stream) {
+  int32_t* own = nullptr;
+  if (d_q && !given && sort_q && nq > 1) {
+    kdt_status st = order_queries<D>(t, d_q, nq, &own, stream);
     if (st != KDT_OK) return st;
   }
+  const int32_t* order = d_q ? (given ? given : own) : nullptr;
   const TreeView v = view_of(t);
   const float r2 = r * r;
   const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
@@ -265,7 +269,7 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
   else
     k_range<D, false><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
   if (st != KDT_OK) {
-    if (order) (void)hipFreeAsync(order, stream);
+    if (own) (void)hipFreeAsync(own, stream);
     return st;
   }
   if (d_off) {
@@ -323,14 +327,49 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
       }
     }
   }
-  if (order) (void)hipFreeAsync(order, stream);
+  if (own) (void)hipFreeAsync(own, stream);
   if (st == KDT_OK) KDT_HIP(hipGetLastError());
   return st;
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ a, int32_t* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+template <int D>
+static kdt_status order_into(const kdt_tree* t, const float* d_q, int64_t nq, int32_t* d_order,
+                             hipStream_t stream) {
+  int32_t* tmp = nullptr;
+  kdt_status st = order_queries<D>(t, d_q, nq, &tmp, stream);
+  if (st != KDT_OK) return st;
+  k_copy_i32<<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(tmp, d_order, nq);
+  (void)hipFreeAsync(tmp, stream);
+  KDT_HIP(hipGetLastError());
+  return KDT_OK;
 }
 
 }  // namespace kdt
 
 using namespace kdt;
+
+extern "C" kdt_status kdt_query_order(const kdt_tree* tree, const float* d_q, int64_t nq,
+                                      int32_t* d_order, hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree || !d_q || !d_order || nq < 1 || nq > INT32_MAX) {
+    kdt_set_error("kdt_query_order: NULL argument or nq outside [1, 2^31-1]");
+    return KDT_EINVAL;
+  }
+  switch (tree->d) {
+    case 2: return order_into<2>(tree, d_q, nq, d_order, stream);
+    case 3: return order_into<3>(tree, d_q, nq, d_order, stream);
+    case 4: return order_into<4>(tree, d_q, nq, d_order, stream);
+    case 8: return order_into<8>(tree, d_q, nq, d_order, stream);
+    case 16: return order_into<16>(tree, d_q, nq, d_order, stream);
+  }
+  kdt_set_error("kdt_query_order: unsupported dimension %d", tree->d);
+  return KDT_EUNSUPPORTED;
+}
 
 extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq, int32_t k,
                               int32_t* d_idx, float* d_d2, int32_t kth_only,
@@ -355,16 +394,17 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
   if (nq == 0) return KDT_OK;
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
   const int trav = opts ? opts->traversal : 0;
+  const int32_t* given = opts ? opts->order : nullptr;
   if (trav < 0 || trav > 2) {
     kdt_set_error("kdt_knn: traversal must be 0, 1 or 2");
     return KDT_EINVAL;
   }
   switch (tree->d) {
-    case 2: return knn_impl<2>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
-    case 3: return knn_impl<3>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
-    case 4: return knn_impl<4>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
-    case 8: return knn_impl<8>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
-    case 16: return knn_impl<16>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, stream);
+    case 2: return knn_impl<2>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);
+    case 3: return knn_impl<3>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);
+    case 4: return knn_impl<4>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);
+    case 8: return knn_impl<8>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);
+    case 16: return knn_impl<16>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);
   }
   kdt_set_error("kdt_knn: unsupported dimension %d", tree->d);
   return KDT_EUNSUPPORTED;
@@ -405,11 +445,11 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
   }
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
   switch (tree->d) {
-    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
-    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
-    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
-    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
-    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, stream);
+    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
+    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
+    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
+    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
+    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
   }
   kdt_set_error("kdt_range: unsupported dimension %d", tree->d);
   return KDT_EUNSUPPORTED;

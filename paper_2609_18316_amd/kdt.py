@@ -23,7 +23,7 @@ DIMS = (2, 3, 4, 8, 16)
 
 # Every exported entry point of include/kdt.h.
 EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt_knn",
-           "kdt_range", "kdt_fof", "kdt_p2m", "kdt_p2m_backward", "kdt_tree_perm",
+           "kdt_range", "kdt_fof", "kdt_p2m", "kdt_p2m_backward", "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_last_error")
 
 
@@ -38,7 +38,7 @@ class BuildOpts(C.Structure):
 
 
 class QueryOpts(C.Structure):
-    _fields_ = [("sort_queries", C.c_int32), ("traversal", C.c_int32)]
+    _fields_ = [("sort_queries", C.c_int32), ("traversal", C.c_int32), ("order", C.c_void_p)]
 
 
 class Grid(C.Structure):
@@ -72,6 +72,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_fof.argtypes = [vp, f32, vp, C.POINTER(C.c_int64), vp]
     lib.kdt_p2m.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp]
     lib.kdt_p2m_backward.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp, vp, vp]
+    lib.kdt_query_order.argtypes = [vp, vp, i64, vp, vp]
     lib.kdt_tree_perm.argtypes = [vp]
     lib.kdt_tree_perm.restype = vp
     if hasattr(lib, "kdt_batch_plan_create"):
@@ -156,8 +157,17 @@ class Tree:
         """Device address of the tree order (n int32, owned by the tree)."""
         return int(load().kdt_tree_perm(self._h))
 
+    def query_order(self, queries: torch.Tensor, stream=None) -> torch.Tensor:
+        """Permutation of the queries along the tree (reusable through ``order=``)."""
+        nq = queries.shape[0]
+        queries = _dev(queries, torch.float32, "queries", (nq, self.d))
+        order = torch.empty(nq, dtype=torch.int32, device=self.device)
+        _check(load().kdt_query_order(self._h, _ptr(queries), nq, _ptr(order), _stream(stream)))
+        return order
+
     def knn(self, queries: torch.Tensor | None, k: int, kth_only: int = 0,
-            sort_queries: bool = True, traversal: int = 0, stream=None):
+            sort_queries: bool = True, traversal: int = 0, order: torch.Tensor | None = None,
+            stream=None):
         """k nearest neighbours, ascending by (d2, index): (idx [nq][k], d2 [nq][k]).
 
         ``queries=None`` queries every point of the tree (row i = input point i).
@@ -166,7 +176,7 @@ class Tree:
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, int(traversal))
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order))
         if kth_only:
             d2 = torch.empty(nq, dtype=torch.float32, device=self.device)
             _check(load().kdt_knn(self._h, _ptr(queries), nq, k, None, _ptr(d2), kth_only,
@@ -179,12 +189,12 @@ class Tree:
         return idx, d2
 
     def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
-              sort_queries: bool = True, stream=None):
+              sort_queries: bool = True, order: torch.Tensor | None = None, stream=None):
         """Closed-ball counts; with ``lists`` also CSR (offsets int64, idx int32)."""
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, 0)
+        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order))
         count = torch.empty(nq, dtype=torch.int32, device=self.device)
         lib = load()
         if not lists:
@@ -302,7 +312,7 @@ class BatchPlan:
         self.d, self.k = d, k
         self._h = C.c_void_p()
         bo = BuildOpts(leaf_size, 0)
-        qo = QueryOpts(1, 0)
+        qo = QueryOpts(1, 0, None)
         _check(lib.kdt_batch_plan_create(off.ctypes.data, self.n_sets, d, k, C.byref(bo),
                                          C.byref(qo), C.byref(self._h)))
 

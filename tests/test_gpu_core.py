@@ -104,6 +104,13 @@ def test_unsorted_queries_give_the_same_answer():
     b = t.knn(to_dev(q), 16, sort_queries=False)
     np.testing.assert_array_equal(to_host(a[0]), to_host(b[0]))
     np.testing.assert_array_equal(to_host(a[1]), to_host(b[1]))
+    order = t.query_order(to_dev(q))
+    o = to_host(order)
+    assert np.array_equal(np.sort(o), np.arange(len(q)))
+    c = t.knn(to_dev(q), 16, order=order)
+    np.testing.assert_array_equal(to_host(a[0]), to_host(c[0]))
+    np.testing.assert_array_equal(to_host(t.range(to_dev(q), 0.02, order=order)),
+                                  to_host(t.range(to_dev(q), 0.02, sort_queries=False)))
 
 
 def test_knn_full_small_config():

@@ -1,0 +1,163 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py
+times, on sampled outputs the oracle computes one by one (and properties that
+hold at any size where the oracle cannot follow)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2609_18316_amd import kdt, workloads
+from tests.gpu_util import dev, say, to_dev, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N = 1 << 24
+NQ = 1 << 22
+
+
+@pytest.fixture(scope="module")
+def clustered():
+    dev()
+    say("generating 2^24 clustered points and 2^22 queries")
+    x = workloads.clustered(N, seed=2)
+    q = workloads.uniform(NQ, 3, seed=102)
+    xt, qt = to_dev(x), to_dev(q)
+    tree = kdt.build(xt, leaf_size=32)
+    say("oracle tree over 2^24 points")
+    ot = oracle.Tree(x, 32)
+    return x, q, xt, qt, tree, ot
+
+
+def test_knn_and_counts_full_size_sampled(clustered):
+    x, q, xt, qt, tree, ot = clustered
+    say("kNN k=32 of 2^22 queries + r=0.01 counts")
+    order = tree.query_order(qt)
+    idx, d2 = tree.knn(qt, 32, order=order)
+    cnt = tree.range(qt, 0.01, order=order)
+    s = workloads.sample_indices(NQ, 4096, seed=7)
+    oi, od = ot.knn(q[s], 32)
+    np.testing.assert_array_equal(to_host(idx)[s], oi)
+    np.testing.assert_array_equal(to_host(d2)[s], od)
+    np.testing.assert_array_equal(to_host(cnt)[s], ot.range(q[s], 0.01))
+
+
+def test_self_knn_and_smoothing_full_size_sampled(clustered):
+    x, q, xt, qt, tree, ot = clustered
+    say("self kNN k=32 of 2^24 points, k-th distance")
+    h = to_host(tree.knn(None, 32, kth_only=2))
+    s = workloads.sample_indices(N, 4096, seed=8)
+    oi, od = ot.knn(x[s], 32)
+    np.testing.assert_array_equal(h[s], np.sqrt(od[:, -1]))
+    assert (od[:, 0] == 0).all()
+
+
+def test_fof_full_size_properties_and_sampled_components(clustered):
+    x, q, xt, qt, tree, ot = clustered
+    l = float(np.float32(0.2 * (1.0 / N) ** (1.0 / 3.0)))
+    say(f"FoF of 2^24 points, l={l}")
+    lab = to_host(tree.fof(l))
+    i = np.arange(N)
+    assert (lab <= i).all()
+    assert (lab[lab] == lab).all()
+    s = workloads.sample_indices(N, 2000, seed=9)
+    c, off, lst = ot.range(x[s], l, lists=True)
+    owner = np.repeat(np.arange(len(s)), c)
+    assert (lab[lst] == lab[s][owner]).all()
+    # exact components of small groups, by breadth-first search with oracle ball queries
+    checked = 0
+    for p in s[:400]:
+        seen = {int(p)}
+        frontier = [int(p)]
+        ok = True
+        while frontier and ok:
+            cc, oo, ll = ot.range(x[frontier], l, lists=True)
+            nxt = set(ll.tolist()) - seen
+            seen |= nxt
+            frontier = sorted(nxt)
+            ok = len(seen) <= 3000
+        if ok:
+            assert lab[p] == min(seen)
+            assert (lab[sorted(seen)] == lab[p]).all()
+            checked += 1
+    assert checked > 100
+
+
+def test_deposit_full_size_subvolume_and_adjoint_sample(clustered):
+    x, q, xt, qt, tree, ot = clustered
+    g = 256
+    cell = 1.0 / g
+    m = workloads.masses(N, seed=5)
+    mt = to_dev(m)
+    h = tree.knn(None, 32, kth_only=2)
+    say("P2M forward 2^24 particles on 256^3")
+    rho = to_host(kdt.p2m(xt, mt, h, (0, 0, 0), cell, (g, g, g), order_ptr=tree.perm_ptr))
+    hh = to_host(h)
+    total = float(m.astype(np.float64).sum())
+    assert abs(float(rho.astype(np.float64).sum()) - total) <= 1e-5 * total
+    mean = total / rho.size
+    for lo_c in ((100, 100, 100), (3, 250, 17), (128, 64, 200)):
+        lo = np.array(lo_c) * cell
+        hi = (np.array(lo_c) + 16) * cell
+        H = np.maximum(hh, np.float32(cell)).astype(np.float64)
+        near = np.all((x >= lo - H[:, None] - cell) & (x < hi + H[:, None] + cell), axis=1)
+        sel = np.nonzero(near)[0]
+        say(f"oracle deposit of {len(sel)} particles around cells {lo_c}")
+        o = oracle.p2m(x[sel], m[sel], hh[sel], (0, 0, 0), cell, (g, g, g))
+        a, b, c = lo_c
+        og = o[a:a + 16, b:b + 16, c:c + 16]
+        gg = rho[a:a + 16, b:b + 16, c:c + 16].astype(np.float64)
+        assert (np.abs(gg - og) <= 1e-5 * np.maximum(np.abs(og), mean)).all()
+    say("P2M adjoint 2^24 particles")
+    gen = torch.Generator(device=xt.device).manual_seed(11)
+    up = torch.randn((g, g, g), device=xt.device, generator=gen)
+    gm, gx = kdt.p2m_backward(xt, mt, h, (0, 0, 0), cell, (g, g, g), up, order_ptr=tree.perm_ptr)
+    s = workloads.sample_indices(N, 2048, seed=12)
+    om, ox = oracle.p2m_backward(x[s], m[s], hh[s], (0, 0, 0), cell, (g, g, g), to_host(up))
+    gm_s, gx_s = to_host(gm)[s].astype(np.float64), to_host(gx)[s].astype(np.float64)
+    assert (np.abs(gm_s - om) <= 1e-5 * np.maximum(np.abs(om), np.abs(om).mean())).all()
+    assert np.linalg.norm(gx_s - ox) <= 1e-4 * np.linalg.norm(ox)
+
+
+@pytest.mark.parametrize("d", (2, 4, 8, 16))
+@pytest.mark.parametrize("dist", ("uniform", "normal"))
+def test_dimension_sweep_full_size_sampled(d, dist):
+    dev()
+    n = 1 << 22
+    x = workloads.uniform(n, d, 300 + d) if dist == "uniform" else workloads.normal(n, d, 400 + d)
+    say(f"dimension sweep d={d} {dist}: build + self kNN k=16")
+    t = kdt.build(to_dev(x), leaf_size=32)
+    idx, d2 = t.knn(None, 16)
+    idx, d2 = to_host(idx), to_host(d2)
+    s = workloads.sample_indices(n, 48 if d >= 8 else 256, seed=13 + d)
+    if d <= 4:
+        oi, od = oracle.Tree(x, 32).knn(x[s], 16)
+    else:
+        oi, od = oracle.knn_brute(x, x[s], 16)
+    np.testing.assert_array_equal(idx[s], oi)
+    np.testing.assert_array_equal(d2[s], od)
+
+
+def test_batched_full_size():
+    dev()
+    sizes = workloads.batch_sizes(256, 3.0, 6.0, seed=4)
+    say(f"batch of 256 clustered sets, {int(sizes.sum())} points")
+    x, off = workloads.batched_clustered(sizes, seed_base=40000)
+    lens = np.array([np.float32(0.2 * (1.0 / s) ** (1.0 / 3.0)) for s in sizes], np.float32)
+    plan = kdt.BatchPlan(off, 3, 8)
+    xt, lt = to_dev(x), to_dev(lens)
+    a = [to_host(v) for v in plan.launch(xt, lt, use_graph=1)]
+    b = [to_host(v) for v in plan.launch(xt, lt, use_graph=0)]
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+    idx, d2, lab = a
+    rng = np.random.Generator(np.random.PCG64(14))
+    small = [s for s in range(256) if sizes[s] <= 60000]
+    for s in rng.choice(small, size=min(6, len(small)), replace=False):
+        xs = x[off[s]:off[s + 1]]
+        say(f"oracle set {s} (n={len(xs)})")
+        t = oracle.Tree(xs, 32)
+        oi, od = t.knn(xs, 8)
+        np.testing.assert_array_equal(idx[off[s]:off[s + 1]], oi)
+        np.testing.assert_array_equal(d2[off[s]:off[s + 1]], od)
+        np.testing.assert_array_equal(lab[off[s]:off[s + 1]], t.fof(float(lens[s])))
+    plan.close()
