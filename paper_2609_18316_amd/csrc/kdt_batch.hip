@@ -119,6 +119,48 @@ __global__ __launch_bounds__(256) void k_knn_forest_packet(
   }
 }
 
+// Friends-of-friends links over the same wave-level packet queue.
+template <int D>
+__global__ __launch_bounds__(256) void k_fof_forest_packet(
+    const SetDesc* __restrict__ sets, int n_sets, const int64_t* __restrict__ pbase,
+    const float* __restrict__ rec, const float* __restrict__ box,
+    const float* __restrict__ lengths, int leaf_cap, int32_t* __restrict__ parent,
+    uint32_t* __restrict__ conn, unsigned long long* __restrict__ ctr) {
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  float* leafbuf = lds + (size_t)wave * leaf_cap * rec_stride(D);
+  const int64_t n_packets = pbase[n_sets];
+  for (;;) {
+    unsigned long long got = 0;
+    if (lane == 0) got = atomicAdd(ctr, 1ull);
+    const int64_t pk = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(got >> 32)) << 32) |
+                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)got));
+    if (pk >= n_packets) break;
+    int lo = 0, hi = n_sets - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pbase[mid] <= pk) lo = mid;
+      else hi = mid - 1;
+    }
+    const SetDesc sd = sets[lo];
+    const TreeView t = set_view<D>(sd, rec, box);
+    const float l = lengths[lo];
+    const float l2 = l * l;
+    const int64_t pos = (pk - pbase[lo]) * 64 + lane;
+    const bool active = pos < sd.n;
+    float q[D];
+    int32_t me = 0;
+    if (active) {
+      load_rec<D>(t.rec, pos, q, me);
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) q[a] = 0.0f;
+    }
+    packet_fof<D>(t, q, pos, me, active, l2, (int32_t)sd.off, parent, conn + sd.node_base,
+                  leafbuf);
+  }
+}
+
 __global__ void k_iota_i32(int32_t* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = (int32_t)i;
@@ -268,8 +310,15 @@ static kdt_status forest_queries(kdt_batch_plan* bp, const float* d_l, int32_t* 
   k_fof_forest_mark<D><<<gn, 256, 0, s>>>(bp->dev.sets, ns, bp->out.box, p.n_nodes, d_l, bp->conn);
   k_fof_forest_join<D><<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box, tot,
                                          bp->parent, bp->conn);
-  k_fof_forest<D><<<bp->fof_blocks, kBQ, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box, tot,
-                                                 d_l, bp->parent, bp->conn, bp->ctr + 1);
+  if (bp->leaf <= 64) {
+    const size_t smem = sizeof(float) * (size_t)bp->leaf * rec_stride(D) * 4;
+    k_fof_forest_packet<D><<<bp->fof_blocks, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase,
+                                                            bp->out.rec, bp->out.box, d_l, bp->leaf,
+                                                            bp->parent, bp->conn, bp->ctr + 1);
+  } else {
+    k_fof_forest<D><<<bp->fof_blocks, kBQ, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box, tot,
+                                                   d_l, bp->parent, bp->conn, bp->ctr + 1);
+  }
   k_fof_forest_final<<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->parent, tot, d_labels);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_batch_launch: kernel launch failed");
@@ -311,7 +360,10 @@ static void size_grids(kdt_batch_plan* bp) {
     else kf = reinterpret_cast<const void*>(&k_knn_forest<D, 64>);
     bp->knn_blocks = occupancy_blocks<D, 0>(kf, 0, kBQ);
   }
-  bp->fof_blocks = occupancy_blocks<D, 0>(reinterpret_cast<const void*>(&k_fof_forest<D>), 0, kBQ);
+  if (bp->leaf <= 64)
+    bp->fof_blocks = occupancy_blocks<D, 0>(reinterpret_cast<const void*>(&k_fof_forest_packet<D>), smem, 256);
+  else
+    bp->fof_blocks = occupancy_blocks<D, 0>(reinterpret_cast<const void*>(&k_fof_forest<D>), 0, kBQ);
 }
 
 static void release(kdt_batch_plan* bp) {

@@ -39,7 +39,7 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
 #pragma unroll
       for (int a = 0; a < D; ++a) x[a] = r[a];
       const uint64_t key = make_key(sq_dist<D>(x, p), __float_as_int(r[D]));
-      best.insert(has ? key : kEmptyKey);
+      best.insert(has && key < best.worst() ? key : kEmptyKey);
       continue;
     }
     if (sp == 0) break;
@@ -62,15 +62,17 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       // candidate; the rounds above then insert them, so the wave pays for
       // the largest per-lane count of insertions rather than for every point
       // some lane wants.
-      const uint64_t w = best.worst();
+      // A float compare on d2 alone marks a superset of the candidates (it
+      // keeps ties with the current k-th); the exact key test is repeated
+      // before insertion.
+      const float wd = best.worst_d2();
 #pragma unroll 1
       for (int i = 0; i < cnt; ++i) {
         const float* r = leafbuf + i * S;
         float x[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) x[a] = r[a];
-        const uint64_t key = make_key(sq_dist<D>(x, p), __float_as_int(r[D]));
-        mask |= (uint64_t)(key < w) << i;
+        mask |= (uint64_t)(sq_dist<D>(x, p) <= wd) << i;
       }
       if (!active) mask = 0;
     } else {
@@ -163,6 +165,99 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
     }
   }
   return count;
+}
+
+// Friends-of-friends links of the 64 points of a wave (tree positions pos,
+// indices me; union-find indices base + index).  A node whose points are known
+// to form one component (conn flag) is skipped by every lane whose own root is
+// already that component's, needs a single link when it lies entirely within l
+// of the lane, and otherwise only its first friend.  A node entirely within l
+// of several lanes is joined point by point by the lowest such lane, which then
+// flags it; the others link to its first point.  Elsewhere each pair i < j
+// within l is linked by i.  Leaves must hold at most 64 points.
+template <int D>
+__device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], int64_t pos,
+                                           int32_t me, bool active, float l2, int32_t base,
+                                           int32_t* __restrict__ parent,
+                                           uint32_t* __restrict__ conn, float* leafbuf) {
+  constexpr int S = rec_stride(D);
+  const int lane = lane_id();
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  const int32_t gme = base + me;
+  uint32_t stackv = 0;
+  uint32_t stk_lo = 0xFFFFFFFFu, stk_hi = 0xFFFFFFFFu;
+  int sp = 1;
+  while (sp > 0) {
+    --sp;
+    const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)stackv, sp);
+    const uint64_t live = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)stk_hi, sp) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)stk_lo, sp);
+    const bool mine = active && ((live >> lane) & 1ull);
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    bool touch = mine && box_mindist<D>(lo, hi, p) <= l2;
+    if (!__any(touch)) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    const int32_t gfirst = base + __float_as_int(t.rec[b * S + D]);
+    const bool one = flag_ld(conn + node) != 0;
+    if (one && touch) {
+      const bool inside = pos >= b && pos < e;
+      touch = !inside && uf_find(parent, gme) != uf_find(parent, gfirst);
+    }
+    if (!__any(touch)) continue;
+    const bool full = touch && box_maxdist<D>(lo, hi, p) <= l2;
+    if (one) {
+      if (full) uf_union(parent, gme, gfirst);
+    } else {
+      const uint64_t fm = __ballot(full);
+      if (fm != 0) {
+        const int leader = __ffsll((unsigned long long)fm) - 1;
+        if (lane == leader) {
+          for (int64_t i = b; i < e; ++i) uf_union(parent, gme, base + __float_as_int(t.rec[i * S + D]));
+          flag_st(conn + node, 1u);
+        } else if (full) {
+          uf_union(parent, gme, gfirst);
+        }
+      }
+    }
+    const bool part = touch && !full;
+    const uint64_t pm = __ballot(part);
+    if (pm == 0) continue;
+    if (node >= first_leaf) {
+      const int cnt = (int)(e - b);
+      wave_sync();
+      const float4* src = reinterpret_cast<const float4*>(t.rec + b * S);
+      float4* dst = reinterpret_cast<float4*>(leafbuf);
+      for (int i = lane; i < cnt * (S / 4); i += 64) dst[i] = src[i];
+      wave_sync();
+      if (part) {
+        for (int i = 0; i < cnt; ++i) {
+          const float* r = leafbuf + i * S;
+          float x[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) x[a] = r[a];
+          if (sq_dist<D>(x, p) > l2) continue;
+          const int32_t id = __float_as_int(r[D]);
+          if (one) {
+            uf_union(parent, gme, base + id);
+            break;
+          }
+          if (id > me) uf_union(parent, gme, base + id);
+        }
+      }
+    } else {
+      const uint32_t mlo = (uint32_t)pm, mhi = (uint32_t)(pm >> 32);
+#pragma unroll
+      for (int c = 2; c >= 1; --c) {
+        stackv = lane == sp ? 2 * node + c : stackv;
+        stk_lo = lane == sp ? mlo : stk_lo;
+        stk_hi = lane == sp ? mhi : stk_hi;
+        ++sp;
+      }
+    }
+  }
 }
 
 }  // namespace kdt

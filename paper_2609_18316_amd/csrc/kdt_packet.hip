@@ -68,6 +68,42 @@ __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const
 }
 
 template <int D>
+__global__ __launch_bounds__(64 * kPWaves) void k_fof_packet(TreeView t, float l2,
+                                                             int32_t* __restrict__ parent,
+                                                             uint32_t* __restrict__ conn,
+                                                             int leaf_cap) {
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t s0 = ((int64_t)blockIdx.x * kPWaves + wave) * 64;
+  if (s0 >= t.n) return;
+  const int64_t pos = s0 + lane;
+  const bool active = pos < t.n;
+  float p[D];
+  int32_t me = 0;
+  if (active) {
+    load_rec<D>(t.rec, pos, p, me);
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) p[a] = 0.0f;
+  }
+  packet_fof<D>(t, p, pos, me, active, l2, 0, parent, conn,
+                lds + (size_t)wave * leaf_cap * rec_stride(D));
+}
+
+template <int D>
+kdt_status fof_packet_launch(const TreeView& v, int leaf, float l2, int32_t* parent, uint32_t* conn,
+                             hipStream_t stream) {
+  const unsigned grid = (unsigned)((v.n + 64 * kPWaves - 1) / (64 * kPWaves));
+  const size_t smem = sizeof(float) * (size_t)leaf * rec_stride(D) * kPWaves;
+  k_fof_packet<D><<<grid, 64 * kPWaves, smem, stream>>>(v, l2, parent, conn, leaf);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_fof: packet kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+template <int D>
 kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, int k,
                              int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
                              hipStream_t stream) {
@@ -114,7 +150,9 @@ kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, in
   template kdt_status knn_packet_launch<D>(const TreeView&, int, const float*, int64_t, int,       \
                                            int32_t*, float*, int, const int32_t*, hipStream_t);    \
   template kdt_status range_packet_launch<D>(const TreeView&, int, const float*, int64_t, float,   \
-                                             const int32_t*, int32_t*, hipStream_t);
+                                             const int32_t*, int32_t*, hipStream_t);             \
+  template kdt_status fof_packet_launch<D>(const TreeView&, int, float, int32_t*, uint32_t*,       \
+                                           hipStream_t);
 KDT_INST(2)
 KDT_INST(3)
 KDT_INST(4)
