@@ -64,11 +64,13 @@ typedef struct {
     int32_t sort_queries; /* 1: reorder external queries along the tree before the
                              traversal (more coherent waves); 0: input order.
                              Results are identical either way. */
-    int32_t traversal;    /* kNN only.  0: default (2).  1: one independent
-                             traversal per lane.  2: one traversal shared by the
-                             64 queries of a wave, leaves staged in LDS (trees
-                             with leaf_size <= 64; larger leaves use 1).
-                             Results are identical either way. */
+    int32_t traversal;    /* kNN and ball counts.  0: default.  1: one
+                             independent traversal per lane.  2: one traversal
+                             shared by the 64 queries of a wave, leaves staged
+                             in LDS (trees with leaf_size <= 64; larger leaves
+                             use 1).  The default is 1 for kNN in d <= 8 and 2
+                             otherwise, and 2 for ball counts.  Results are
+                             identical either way. */
     const int32_t *order; /* NULL, or a device permutation [nq] from
                              kdt_query_order to use instead of sorting again. */
 } kdt_query_opts;

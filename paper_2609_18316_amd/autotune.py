@@ -1,0 +1,133 @@
+"""Autotuner for the tree and traversal parameters.
+
+The paper tunes the leaf size by hand (Sec. 2.1 and App. A: 10-20 is best on
+its CPUs, 16 by default, and the optimum moves with N and D).  Here the choice
+is measured on the GPU for a given workload shape:
+
+* leaf size (N_leaf) -- trades build time against leaf scanning in queries;
+* queries per wave -- 1 (one independent traversal per lane) or 64 (one
+  traversal shared by a wave of spatially coherent queries);
+* traversal stack depth -- not tuned: with median splits it is exactly the
+  tree depth L = ceil(log2(ceil(n / N_leaf))), known from n.
+
+`tune()` times build + query for every candidate and returns the fastest;
+`lookup()` reads results stored by earlier tuning runs (a JSON table next to
+this file, keyed by workload shape), falling back to the paper's regime.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import asdict, dataclass
+
+import torch
+
+from . import kdt
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table.json")
+LEAF_CANDIDATES = (8, 12, 16, 24, 32, 48, 64)
+
+
+@dataclass
+class Choice:
+    leaf_size: int
+    queries_per_wave: int  # 1 or 64
+    stack_depth: int
+    build_ms: float
+    query_ms: float
+
+
+def key(n: int, d: int, k: int, kind: str) -> str:
+    """Table key: log2 of n rounded, dimension, k and the query kind."""
+    return f"n2^{int(round(math.log2(max(n, 1))))}-d{d}-k{k}-{kind}"
+
+
+def _time(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        s.record()
+        fn()
+        e.record()
+        torch.cuda.synchronize()
+        best = min(best, s.elapsed_time(e))
+    return best
+
+
+def tune(points: torch.Tensor, k: int, queries: torch.Tensor | None = None,
+         leaf_sizes=LEAF_CANDIDATES, reps: int = 3, query_weight: float = 1.0) -> Choice:
+    """Measures build + kNN (k) for each candidate; minimises build + weight * query."""
+    n, d = points.shape
+    best: Choice | None = None
+    for leaf in leaf_sizes:
+        build_ms = _time(lambda: kdt.build(points, leaf_size=leaf, check_finite=False), reps)
+        tree = kdt.build(points, leaf_size=leaf, check_finite=False)
+        order = tree.query_order(queries) if queries is not None else None
+        for trav in ((1, 2) if leaf <= 64 else (1,)):
+            q_ms = _time(lambda: tree.knn(queries, k, order=order, traversal=trav), reps)
+            c = Choice(leaf, 64 if trav == 2 else 1, tree.info.levels + 1, build_ms, q_ms)
+            score = build_ms + query_weight * q_ms
+            if best is None or score < best.build_ms + query_weight * best.query_ms:
+                best = c
+        tree.close()
+    assert best is not None
+    return best
+
+
+def load_table(path: str = TABLE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def store(entries: dict, path: str = TABLE) -> None:
+    table = load_table(path)
+    table.update({k: asdict(v) if isinstance(v, Choice) else v for k, v in entries.items()})
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+
+
+def lookup(n: int, d: int, k: int, kind: str, path: str = TABLE) -> Choice:
+    """Stored choice for the workload shape, else the default (leaf 32, wave packets)."""
+    entry = load_table(path).get(key(n, d, k, kind))
+    if entry:
+        return Choice(**entry)
+    leaf = 32
+    levels = 0
+    while -(-n // (1 << levels)) > leaf:
+        levels += 1
+    return Choice(leaf, 64, levels + 1, float("nan"), float("nan"))
+
+
+def _standard_workloads():
+    """The workload shapes the benchmark and the parity configurations use."""
+    from . import workloads
+    dev = torch.device("cuda:0")
+    gen = torch.Generator().manual_seed(0)
+    x = torch.from_numpy(workloads.clustered(1 << 24, seed=2)).to(dev)
+    q = torch.from_numpy(workloads.uniform(1 << 22, 3, seed=102)).to(dev)
+    yield key(1 << 24, 3, 32, "uniform-queries"), x, q, 32
+    sel = torch.randperm(x.shape[0], generator=gen)[: 1 << 20].to(dev)
+    yield key(1 << 24, 3, 32, "self"), x, x[sel].contiguous(), 32
+    for d in (2, 4, 8, 16):
+        for dist in ("uniform", "normal"):
+            pts = workloads.uniform(1 << 22, d, 300 + d) if dist == "uniform" else \
+                workloads.normal(1 << 22, d, 400 + d)
+            xt = torch.from_numpy(pts).to(dev)
+            sel = torch.randperm(xt.shape[0], generator=gen)[: 1 << 16].to(dev)
+            yield key(1 << 22, d, 16, f"self-{dist}"), xt, xt[sel].contiguous(), 16
+
+
+if __name__ == "__main__":
+    import sys
+    out = sys.argv[1] if len(sys.argv) > 1 else TABLE
+    results = {}
+    for name, pts, qs, kk in _standard_workloads():
+        c = tune(pts, kk, qs)
+        results[name] = c
+        print(name, asdict(c), flush=True)
+    store(results, out)

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBQ) void k_knn_forest(const SetDesc* __restrict__ 
                                                     int k, int32_t* __restrict__ oidx,
                                                     float* __restrict__ od2,
                                                     unsigned long long* __restrict__ ctr) {
-  __shared__ uint64_t stk[kMaxDepth][kBQ];
+  __shared__ uint32_t stk[kMaxDepth][kBQ];
   __shared__ int64_t slot;
   const int64_t n_packets = (total + kBQ - 1) / kBQ;
   for (;;) {

@@ -152,7 +152,7 @@ __device__ __forceinline__ uint64_t make_key(float d2, int32_t idx) {
 // `ld` entries.
 template <int D, int KC>
 __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], TopK<KC>& best,
-                                        uint64_t* stk, int ld) {
+                                        uint32_t* stk, int ld) {
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   float lo[D], hi[D];
   load_box<D>(t.box, 0, lo, hi);
@@ -180,20 +180,18 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Top
         const bool first0 = d0 <= d1;
         const uint32_t nn = first0 ? c0 : c1, ff = first0 ? c1 : c0;
         const float dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
-        if (df <= best.worst_d2()) {
-          stk[sp * ld] = ((uint64_t)ff << 32) | __float_as_uint(df);
-          ++sp;
-        }
+        if (df <= best.worst_d2()) stk[sp++ * ld] = ff;
         node = nn;
         nd = dn;
         continue;
       }
     }
     if (sp == 0) break;
-    --sp;
-    const uint64_t e = stk[sp * ld];
-    node = (uint32_t)(e >> 32);
-    nd = __uint_as_float((uint32_t)e);
+    // only the node id is kept on the stack; its box distance is recomputed
+    // (the box is cache-resident), halving the stack's LDS footprint
+    node = stk[--sp * ld];
+    load_box<D>(t.box, node, lo, hi);
+    nd = box_mindist<D>(lo, hi, p);
   }
 }
 

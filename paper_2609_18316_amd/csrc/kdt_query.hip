@@ -24,13 +24,15 @@ constexpr int kQBlock = 128;
 // kNN
 // ---------------------------------------------------------------------------
 
+// The per-lane stack lives in LDS, (levels + 1) entries per lane (the tree
+// depth bounds it: one pending sibling per level), sized at launch.
 template <int D, int KC>
 __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* __restrict__ q,
                                                       int64_t nq, int k,
                                                       const int32_t* __restrict__ order, int mode,
                                                       int32_t* __restrict__ oidx,
                                                       float* __restrict__ od2) {
-  __shared__ uint64_t stk[kMaxDepth][kQBlock];
+  extern __shared__ uint32_t stk_dyn[];
   constexpr int S = rec_stride(D);
   const int64_t s = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
   if (s >= nq) return;
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* _
   }
   TopK<KC> best;
   best.init(k);
-  knn_one<D, KC>(t, p, best, &stk[0][threadIdx.x], kQBlock);
+  knn_one<D, KC>(t, p, best, stk_dyn + threadIdx.x, kQBlock);
   knn_write<KC>(best, k, mode, row, oidx, od2);
 }
 
@@ -62,7 +64,8 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
                                                    int32_t* __restrict__ count,
                                                    const int64_t* __restrict__ offsets,
                                                    int32_t* __restrict__ out) {
-  __shared__ uint32_t stk[kMaxDepth][kQBlock];
+  extern __shared__ uint32_t stk_dyn32[];
+  uint32_t* col = stk_dyn32 + threadIdx.x;
   const int64_t s = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
   if (s >= nq) return;
   float p[D];
@@ -80,9 +83,9 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
   int64_t c = 0;
   int64_t pos = FILL ? offsets[row] : 0;
   int sp = 0;
-  stk[sp++][threadIdx.x] = 0;
+  col[kQBlock * sp++] = 0;
   while (sp > 0) {
-    const uint32_t node = stk[--sp][threadIdx.x];
+    const uint32_t node = col[kQBlock * --sp];
     float lo[D], hi[D];
     load_box<D>(t.box, node, lo, hi);
     if (box_mindist<D>(lo, hi, p) > r2) continue;
@@ -113,8 +116,8 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
       }
       continue;
     }
-    stk[sp++][threadIdx.x] = 2 * node + 2;
-    stk[sp++][threadIdx.x] = 2 * node + 1;
+    col[kQBlock * sp++] = 2 * node + 2;
+    col[kQBlock * sp++] = 2 * node + 1;
   }
   if (!FILL) count[row] = (int32_t)c;
 }
@@ -218,14 +221,15 @@ static kdt_status knn_dispatch(const kdt_tree* t, const float* d_q, int64_t nq, 
                                hipStream_t stream) {
   const TreeView v = view_of(t);
   const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
+  const size_t smem = sizeof(uint32_t) * (size_t)(t->levels + 1) * kQBlock;
   if (k <= 8)
-    k_knn_lane<D, 8><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+    k_knn_lane<D, 8><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
   else if (k <= 16)
-    k_knn_lane<D, 16><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+    k_knn_lane<D, 16><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
   else if (k <= 32)
-    k_knn_lane<D, 32><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+    k_knn_lane<D, 32><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
   else
-    k_knn_lane<D, 64><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+    k_knn_lane<D, 64><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
   KDT_HIP(hipGetLastError());
   return KDT_OK;
 }
@@ -240,6 +244,7 @@ static kdt_status knn_impl(const kdt_tree* t, const float* d_q, int64_t nq, int 
     if (st != KDT_OK) return st;
   }
   const int32_t* use = d_q ? (given ? given : order) : nullptr;
+  if (traversal == 0) traversal = D <= 8 ? 1 : 2;  // measured defaults
   if (t->leaf > 64) traversal = 1;  // the wave kernel marks at most 64 points per leaf
   kdt_status st = traversal == 1
                       ? knn_dispatch<D>(t, d_q, nq, k, d_idx, d_d2, mode, use, stream)
@@ -253,7 +258,7 @@ template <int D>
 static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, float r,
                              int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
                              int64_t* required, bool sort_q, const int32_t* given,
-                             hipStream_t stream) {
+                             int traversal, hipStream_t stream) {
   int32_t* own = nullptr;
   if (d_q && !given && sort_q && nq > 1) {
     kdt_status st = order_queries<D>(t, d_q, nq, &own, stream);
@@ -263,11 +268,13 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
   const TreeView v = view_of(t);
   const float r2 = r * r;
   const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
+  // both children are pushed: at most levels + 2 entries
+  const size_t rsmem = sizeof(uint32_t) * (size_t)(t->levels + 2) * kQBlock;
   kdt_status st = KDT_OK;
-  if (t->leaf <= 64)
+  if (t->leaf <= 64 && traversal != 1)
     st = range_packet_launch<D>(v, t->leaf, d_q, nq, r2, order, d_count, stream);
   else
-    k_range<D, false><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
+    k_range<D, false><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
   if (st != KDT_OK) {
     if (own) (void)hipFreeAsync(own, stream);
     return st;
@@ -306,8 +313,8 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
               kdt_set_error("device allocation failed for the lists");
               st = KDT_ENOMEM;
             } else {
-              k_range<D, true><<<grid, kQBlock, 0, stream>>>(v, d_q, nq, r2, order, d_count, d_off,
-                                                             unsorted);
+              k_range<D, true><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count,
+                                                                 d_off, unsorted);
               size_t sb = 0;
               hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total,
                                                     (int)nq, d_off, d_off + 1, stream);
@@ -445,11 +452,11 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
   }
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
   switch (tree->d) {
-    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
-    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
-    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
-    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
-    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, stream);
+    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
+    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
+    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
+    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
+    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
   }
   kdt_set_error("kdt_range: unsupported dimension %d", tree->d);
   return KDT_EUNSUPPORTED;

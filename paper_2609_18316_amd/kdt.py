@@ -189,12 +189,13 @@ class Tree:
         return idx, d2
 
     def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
-              sort_queries: bool = True, order: torch.Tensor | None = None, stream=None):
+              sort_queries: bool = True, order: torch.Tensor | None = None, traversal: int = 0,
+              stream=None):
         """Closed-ball counts; with ``lists`` also CSR (offsets int64, idx int32)."""
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order))
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order))
         count = torch.empty(nq, dtype=torch.int32, device=self.device)
         lib = load()
         if not lists:
