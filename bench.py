@@ -201,8 +201,8 @@ def main():
         "p2m_bwd_over_fwd": avg["p2m_bwd"] / avg["p2m_fwd"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_knn_packet<3,32,0> (kNN traversal, k=32): compulsory bytes "
-                               "4d + 8k = 268 per query"},
+                     "kernel": "k_knn_lane<3,32> (kNN traversal, k=32, one query per lane): "
+                               "compulsory bytes 4d + 8k = 268 per query"},
     }
     if batch:
         # The baseline (the single-tree entry points once per set, eager) is

@@ -265,6 +265,11 @@ const int32_t *kdt_tree_perm(const kdt_tree *tree);
  * use_graph = 2: the same batched kernels launched eagerly (no graph).
  * use_graph = 0: the per-set baseline -- kdt_build, kdt_knn and kdt_fof called
  *   once per set, eagerly (waits on `stream` to read d_l).
+ * bopts->leaf_size sets N_leaf for every set (0 or NULL: 32); qopts->traversal
+ * picks the batched kNN kernel (0 and 2: wave packets, the measured default
+ * for all-points queries; 1: one query per lane; leaf_size > 64 always uses
+ * 1); qopts may be NULL and its other fields are unused.  Results are
+ * identical either way.
  *
  * Errors: KDT_EINVAL, KDT_EUNSUPPORTED, KDT_ENOMEM, KDT_EDEVICE.
  */

@@ -44,10 +44,14 @@ def key(n: int, d: int, k: int, kind: str) -> str:
 
 
 def _time(fn, reps: int) -> float:
-    fn()
-    torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    best = float("inf")
+    s.record()
+    fn()
+    e.record()
+    torch.cuda.synchronize()
+    best = s.elapsed_time(e)
+    if best > 200.0:  # slow candidates (high d): the first run is representative enough
+        reps = 1
     for _ in range(reps):
         s.record()
         fn()
@@ -58,7 +62,8 @@ def _time(fn, reps: int) -> float:
 
 
 def tune(points: torch.Tensor, k: int, queries: torch.Tensor | None = None,
-         leaf_sizes=LEAF_CANDIDATES, reps: int = 3, query_weight: float = 1.0) -> Choice:
+         leaf_sizes=LEAF_CANDIDATES, reps: int = 3, query_weight: float = 1.0,
+         verbose: bool = False) -> Choice:
     """Measures build + kNN (k) for each candidate; minimises build + weight * query."""
     n, d = points.shape
     best: Choice | None = None
@@ -69,6 +74,9 @@ def tune(points: torch.Tensor, k: int, queries: torch.Tensor | None = None,
         for trav in ((1, 2) if leaf <= 64 else (1,)):
             q_ms = _time(lambda: tree.knn(queries, k, order=order, traversal=trav), reps)
             c = Choice(leaf, 64 if trav == 2 else 1, tree.info.levels + 1, build_ms, q_ms)
+            if verbose:
+                print(f"  leaf {leaf} traversal {trav}: build {build_ms:.3f} ms, "
+                      f"query {q_ms:.3f} ms", flush=True)
             score = build_ms + query_weight * q_ms
             if best is None or score < best.build_ms + query_weight * best.query_ms:
                 best = c
@@ -127,7 +135,8 @@ if __name__ == "__main__":
     out = sys.argv[1] if len(sys.argv) > 1 else TABLE
     results = {}
     for name, pts, qs, kk in _standard_workloads():
-        c = tune(pts, kk, qs)
+        print(name, flush=True)
+        c = tune(pts, kk, qs, verbose=True)
         results[name] = c
         print(name, asdict(c), flush=True)
     store(results, out)

@@ -131,12 +131,20 @@ struct TopK {
   // (no branch, so it can run on every lane of a wave).  One bottom-up pass
   // of compare-and-carry: each slot keeps the smaller of itself and the carry
   // and hands the larger upwards; the largest key falls off the top.
+  //
+  // Every key read as a float64 is finite and non-negative (the high word is
+  // a non-negative float32, so the float64 exponent stays below 0x7FF), so
+  // the hardware min/max order keys exactly.  They are issued directly: the
+  // library fmin/fmax would first canonicalise both operands of every slot
+  // (IEEE mode), half as many instructions again.
   __device__ __forceinline__ void insert(uint64_t x) {
     double carry = __longlong_as_double((long long)x);
 #pragma unroll
     for (int i = 0; i < KC; ++i) {
-      const double up = fmax(a[i], carry);
-      a[i] = fmin(a[i], carry);
+      double up;
+      asm("v_max_f64 %1, %0, %2\n\tv_min_f64 %0, %0, %2"
+          : "+v"(a[i]), "=&v"(up)
+          : "v"(carry));
       carry = up;
     }
   }
@@ -164,12 +172,33 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Top
       if (node >= first_leaf) {
         const int64_t j = node - first_leaf;
         const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
-        for (int64_t i = b; i < e; ++i) {
-          float x[D];
-          int32_t id = 0;
-          load_rec<D>(t.rec, i, x, id);
-          const uint64_t key = make_key(sq_dist<D>(x, p), id);
-          if (key < best.worst()) best.insert(key);
+        // Two passes per block of up to 64 leaf points.  The first computes
+        // every distance and marks the points that can enter the list (float
+        // test against the current k-th distance, ties kept); the second
+        // inserts the marked points, recomputing their distances.  The
+        // insertion is the expensive step and runs for the whole wave when
+        // any lane inserts, so marking first makes the wave pay for the
+        // largest number of insertions of one lane in this leaf, not for
+        // every position at which some lane inserts.
+        for (int64_t c = b; c < e; c += 64) {
+          const int m = (int)((e - c) < 64 ? (e - c) : 64);
+          const float w = best.worst_d2();
+          uint64_t mask = 0;
+          for (int i = 0; i < m; ++i) {
+            float x[D];
+            int32_t id = 0;
+            load_rec<D>(t.rec, c + i, x, id);
+            if (sq_dist<D>(x, p) <= w) mask |= 1ull << i;
+          }
+          while (mask) {
+            const int i = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            float x[D];
+            int32_t id = 0;
+            load_rec<D>(t.rec, c + i, x, id);
+            const uint64_t key = make_key(sq_dist<D>(x, p), id);
+            if (key < best.worst()) best.insert(key);
+          }
         }
       } else {
         const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;

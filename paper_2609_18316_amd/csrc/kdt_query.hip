@@ -33,7 +33,6 @@ __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* _
                                                       int32_t* __restrict__ oidx,
                                                       float* __restrict__ od2) {
   extern __shared__ uint32_t stk_dyn[];
-  constexpr int S = rec_stride(D);
   const int64_t s = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
   if (s >= nq) return;
   float p[D];

@@ -303,7 +303,8 @@ class P2M(torch.autograd.Function):
 class BatchPlan:
     """Many point sets of uneven size: fixed shapes, one launch per batch."""
 
-    def __init__(self, offsets, d: int, k: int, leaf_size: int = 32):
+    def __init__(self, offsets, d: int, k: int, leaf_size: int = 32, traversal: int = 0):
+        """traversal: 0 measured default, 1 one query per lane, 2 wave packets."""
         import numpy as np
         lib = load()
         off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -313,7 +314,7 @@ class BatchPlan:
         self.d, self.k = d, k
         self._h = C.c_void_p()
         bo = BuildOpts(leaf_size, 0)
-        qo = QueryOpts(1, 0, None)
+        qo = QueryOpts(1, int(traversal), None)
         _check(lib.kdt_batch_plan_create(off.ctypes.data, self.n_sets, d, k, C.byref(bo),
                                          C.byref(qo), C.byref(self._h)))
 

@@ -22,13 +22,13 @@ def _batch(sizes, seed_base, d=3):
     return x, off, lens
 
 
-@pytest.mark.parametrize("d", (3, 2, 8))
-def test_batch_matches_per_set_and_oracle(d):
+@pytest.mark.parametrize("d,traversal", ((3, 0), (3, 1), (2, 0), (8, 0), (8, 1)))
+def test_batch_matches_per_set_and_oracle(d, traversal):
     dev()
     sizes = [1, 2, 33, 700, 5000, 20011, 64, 3, 12000, 257]
     x, off, lens = _batch(sizes, 900, d)
-    say(f"batch d={d} sets={len(sizes)} total={off[-1]}")
-    plan = kdt.BatchPlan(off, d, 8)
+    say(f"batch d={d} traversal={traversal} sets={len(sizes)} total={off[-1]}")
+    plan = kdt.BatchPlan(off, d, 8, traversal=traversal)
     xt, lt = to_dev(x), to_dev(lens)
     outs = {}
     for mode in (1, 2, 0, 1):
