@@ -4,24 +4,38 @@
 // Each particle i spreads its mass over the cells whose centres lie within
 // H_i = max(h_i, cell) with the M4 cubic spline w(q), q = 2 r / H_i, and the
 // weights are normalised over the particle's in-grid cells (S_i), so the
-// deposit conserves mass.  Forward: one workgroup takes 256 consecutive
-// particles of the visiting order (tree order keeps them spatially compact),
-// accumulates their deposits in a float64 LDS tile covering the union of their
-// supports and flushes the tile into a float64 mesh with one atomic add per
-// touched cell; a last pass rounds the mesh to float32.  Chunks whose union
-// box does not fit the tile deposit with global float64 atomics.  Backward:
-// one lane per particle gathers S, A = sum g w, B = sum grad w and
-// C = sum g grad w (weights recomputed, float64 sums) -- no atomics.
+// deposit conserves mass.
+//
+// Forward, as a binned deposit into LDS tiles of 16^3 cells:
+//  1. one lane per particle sums S_i over its support, keeps m_i / S_i and
+//     counts, per tile, the particles whose support box overlaps it
+//     (wave-aggregated atomics: the lanes of a wave hold nearby particles);
+//  2. the host reads the per-tile counts, lays out the (tile, particle) lists
+//     and cuts them into chunks of at most kChunk particles;
+//  3. the particles are scattered into their tiles' lists;
+//  4. one workgroup per chunk accumulates its particles' deposits inside its
+//     tile in a float64 LDS tile and writes the tile out once: rounded to
+//     float32 straight into the mesh when the tile is a single chunk, else as
+//     a float64 partial;
+//  5. tiles cut into several chunks sum their partials in chunk order.
+// Every mesh cell is written exactly once and no global atomics touch the
+// mesh.  Backward: one lane per particle gathers S, A = sum g w,
+// B = sum grad w and C = sum g grad w (weights recomputed, float64 sums) --
+// no atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "kdt_internal.h"
 
 namespace kdt {
 
 constexpr int kPBlock = 256;
-constexpr int kTile = 8192;  // float64 cells in the LDS tile (64 KiB)
+constexpr int kT = 16;                      // tile edge in cells
+constexpr int kTileCells = kT * kT * kT;    // float64 LDS tile: 32 KiB
+constexpr int64_t kChunk = 4096;            // particles per deposit work item
 
 struct GridDev {
   float lo[3];
@@ -94,17 +108,34 @@ __device__ __forceinline__ void load_particle(const GridDev& g, const float* __r
   }
 }
 
-// Visits every cell of the particle's support box with (flat index, w, dr, r).
+// Visits every cell of the box [b0, b1] (a part of the particle's support
+// box) whose centre lies within the support, with (flat index, ix, iy, iz, q,
+// dx, dy, dz, r).  The same float operations for every cell, whichever part
+// of the support box is visited, so a cell's weight does not depend on it.
+//
+// Rows are clipped to the support sphere before the exact test: a z-row is
+// walked only over the cells within a chord of half-length
+// sqrt(H^2 (1 + 2e-4) - dx^2 - dy^2) + 1e-3 cell, a margin far above the
+// float rounding of q, so every cell with q < 2 is still visited (and the
+// test q < 2 decides, as before); rows and planes farther than H are skipped.
 template <typename F>
-__device__ __forceinline__ void for_cells(const GridDev& g, const Particle& p, F&& f) {
+__device__ __forceinline__ void for_cells_in(const GridDev& g, const Particle& p, const int b0[3],
+                                             const int b1[3], F&& f) {
   const float inv2h = 2.0f / p.H;
-  for (int ix = p.c0[0]; ix <= p.c1[0]; ++ix) {
+  const float H2 = p.H * p.H * 1.0002f;
+  const float inv = 1.0f / g.cell;
+  for (int ix = b0[0]; ix <= b1[0]; ++ix) {
     const float dx = p.x[0] - (g.lo[0] + ((float)ix + 0.5f) * g.cell);
-    for (int iy = p.c0[1]; iy <= p.c1[1]; ++iy) {
+    if (dx * dx > H2) continue;
+    for (int iy = b0[1]; iy <= b1[1]; ++iy) {
       const float dy = p.x[1] - (g.lo[1] + ((float)iy + 0.5f) * g.cell);
       const float dxy = dx * dx + dy * dy;
+      if (dxy > H2) continue;
+      const float zr = sqrtf(H2 - dxy) + 1e-3f * g.cell;
+      const int z0 = max(b0[2], (int)ceilf((p.x[2] - zr - g.lo[2]) * inv - 0.5f));
+      const int z1 = min(b1[2], (int)floorf((p.x[2] + zr - g.lo[2]) * inv - 0.5f));
       const int64_t rowb = ((int64_t)ix * g.n[1] + iy) * g.n[2];
-      for (int iz = p.c0[2]; iz <= p.c1[2]; ++iz) {
+      for (int iz = z0; iz <= z1; ++iz) {
         const float dz = p.x[2] - (g.lo[2] + ((float)iz + 0.5f) * g.cell);
         const float r2 = dxy + dz * dz;
         const float r = sqrtf(r2);
@@ -115,89 +146,203 @@ __device__ __forceinline__ void for_cells(const GridDev& g, const Particle& p, F
   }
 }
 
+template <typename F>
+__device__ __forceinline__ void for_cells(const GridDev& g, const Particle& p, F&& f) {
+  for_cells_in(g, p, p.c0, p.c1, f);
+}
+
 __global__ void k_zero_f64(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
 }
 
-__global__ void k_round_f32(const double* __restrict__ a, float* __restrict__ out, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (float)a[i];
+
+struct TileGrid {
+  int nt[3];  // tiles per axis
+};
+
+// Next tile of a lane's support box in x-major order; false past the last.
+__device__ __forceinline__ bool next_tile(int c[3], const int t0[3], const int t1[3]) {
+  if (++c[2] <= t1[2]) return true;
+  c[2] = t0[2];
+  if (++c[1] <= t1[1]) return true;
+  c[1] = t0[1];
+  return ++c[0] <= t1[0];
 }
 
-__global__ __launch_bounds__(kPBlock) void k_p2m_fwd(GridDev g, const float* __restrict__ x,
-                                                     const float* __restrict__ m,
-                                                     const float* __restrict__ h, int64_t n,
-                                                     const int32_t* __restrict__ order,
-                                                     double* __restrict__ acc,
-                                                     int32_t* __restrict__ bad) {
-  __shared__ double tile[kTile];
-  __shared__ int bmin[3], bmax[3];
+// Walks every lane's list of overlapped tiles in step: each round takes the
+// current tile of the first unfinished lane and hands it, with the set of
+// lanes currently at that tile, to `f` (called by the whole wave; the
+// leader is the lowest such lane), then moves those lanes on.  Lanes of a
+// wave hold nearby particles, so a wave needs few rounds.
+template <typename F>
+__device__ __forceinline__ void for_tiles_aggregated(const TileGrid& tg, const int t0[3],
+                                                     const int t1[3], bool has, F&& f) {
+  int c[3] = {t0[0], t0[1], t0[2]};
+  bool more = has;
+  for (;;) {
+    const uint64_t act = __ballot(more);
+    if (act == 0) break;
+    const int tile = more ? (c[0] * tg.nt[1] + c[1]) * tg.nt[2] + c[2] : -1;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const int lt = __shfl(tile, leader);
+    const bool mine = more && tile == lt;
+    const uint64_t same = __ballot(mine);
+    f(lt, same, leader, mine);
+    if (mine) more = next_tile(c, t0, t1);
+  }
+}
+
+// Tiles overlapped by a valid particle's support box; false (no tiles) for
+// an invalid particle or an empty box.  The prep and scatter passes decide
+// this identically, so the lists hold exactly the counted entries.
+__device__ __forceinline__ bool tile_range(const Particle& p, int t0[3], int t1[3]) {
+  bool has = p.ok;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    has &= p.c0[a] <= p.c1[a];
+    t0[a] = p.c0[a] / kT;
+    t1[a] = p.c1[a] / kT;
+  }
+  return has;
+}
+
+// Step 1: per particle (visiting position t), f = m / S and the per-tile
+// particle counts.
+__global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
+                                                      const float* __restrict__ x,
+                                                      const float* __restrict__ m,
+                                                      const float* __restrict__ h, int64_t n,
+                                                      const int32_t* __restrict__ order,
+                                                      float* __restrict__ fbuf,
+                                                      uint32_t* __restrict__ tcount,
+                                                      int32_t* __restrict__ bad) {
   const int64_t t = (int64_t)blockIdx.x * kPBlock + threadIdx.x;
-  Particle p;
-  const bool live = t < n;
-  if (live) {
+  int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
+  bool has = false;
+  if (t < n) {
     const int64_t i = order ? order[t] : t;
+    Particle p;
     load_particle(g, x, m, h, i, p);
     if (!p.ok) atomicOr(bad, 1);
-  } else {
-    p.ok = false;
-    for (int a = 0; a < 3; ++a) {
-      p.c0[a] = 0;
-      p.c1[a] = -1;
-    }
-  }
-  if (threadIdx.x < 3) {
-    bmin[threadIdx.x] = INT32_MAX;
-    bmax[threadIdx.x] = INT32_MIN;
-  }
-  __syncthreads();
-  if (p.ok) {
-    for (int a = 0; a < 3; ++a) {
-      atomicMin(&bmin[a], p.c0[a]);
-      atomicMax(&bmax[a], p.c1[a]);
-    }
-  }
-  __syncthreads();
-  const int ex = bmax[0] - bmin[0] + 1, ey = bmax[1] - bmin[1] + 1, ez = bmax[2] - bmin[2] + 1;
-  const bool any = bmax[0] >= bmin[0];
-  const bool use_tile = any && (int64_t)ex * ey * ez <= kTile;
-  if (use_tile) {
-    for (int c = threadIdx.x; c < ex * ey * ez; c += kPBlock) tile[c] = 0.0;
-    __syncthreads();
-  }
-  if (p.ok) {
     float S = 0.0f;
     for_cells(g, p, [&](int64_t, int, int, int, float q, float, float, float, float) {
       S += m4_w(q);
     });
-    const float f = p.m / S;
-    if (use_tile) {
-      for_cells(g, p, [&](int64_t, int ix, int iy, int iz, float q, float, float, float, float) {
-        const float w = m4_w(q);
-        if (w > 0.0f) {
-          const int c = ((ix - bmin[0]) * ey + (iy - bmin[1])) * ez + (iz - bmin[2]);
-          atomicAdd(&tile[c], (double)(f * w));
-        }
-      });
-    } else {
-      for_cells(g, p, [&](int64_t cidx, int, int, int, float q, float, float, float, float) {
-        const float w = m4_w(q);
-        if (w > 0.0f) unsafeAtomicAdd(acc + cidx, (double)(f * w));
-      });
+    // a particle inside the mesh has its own cell centre within
+    // sqrt(3)/2 cell <= H, so S > 0
+    has = tile_range(p, t0, t1);
+    fbuf[t] = has ? p.m / S : 0.0f;
+  }
+  for_tiles_aggregated(tg, t0, t1, has, [&](int tile, uint64_t same, int leader, bool) {
+    if (lane_id() == leader) atomicAdd(tcount + tile, (uint32_t)__popcll(same));
+  });
+}
+
+// Step 3: every particle appends its visiting position to the lists of the
+// tiles its support box overlaps.
+__global__ __launch_bounds__(kPBlock) void k_p2m_scatter(GridDev g, TileGrid tg,
+                                                         const float* __restrict__ x,
+                                                         const float* __restrict__ h, int64_t n,
+                                                         const int32_t* __restrict__ order,
+                                                         const int64_t* __restrict__ toff,
+                                                         uint32_t* __restrict__ tfill,
+                                                         int32_t* __restrict__ pairs) {
+  const int64_t t = (int64_t)blockIdx.x * kPBlock + threadIdx.x;
+  int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
+  bool has = false;
+  if (t < n) {
+    const int64_t i = order ? order[t] : t;
+    Particle p;
+    load_particle(g, x, nullptr, h, i, p);
+    has = tile_range(p, t0, t1);
+  }
+  for_tiles_aggregated(tg, t0, t1, has, [&](int tile, uint64_t same, int leader, bool mine) {
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(tfill + tile, (uint32_t)__popcll(same));
+    base = (uint32_t)__shfl((int)base, leader);
+    const int64_t at = toff[tile] + base + lanes_below(same);
+    if (mine && at < toff[tile + 1]) pairs[at] = (int32_t)t;
+  });
+}
+
+struct DepositChunk {
+  int32_t tile;
+  int32_t slot;  // -1: the tile's only chunk, written to the mesh; else its partial
+  int64_t begin, end;
+};
+
+// Step 4: one workgroup per chunk of one tile's particle list.
+__global__ __launch_bounds__(kPBlock) void k_p2m_tile(GridDev g, TileGrid tg,
+                                                      const float* __restrict__ x,
+                                                      const float* __restrict__ h,
+                                                      const int32_t* __restrict__ order,
+                                                      int64_t n, const float* __restrict__ fbuf,
+                                                      const int32_t* __restrict__ pairs,
+                                                      const DepositChunk* __restrict__ chunks,
+                                                      float* __restrict__ mesh,
+                                                      double* __restrict__ partial) {
+  __shared__ double tile[kTileCells];
+  const DepositChunk ck = chunks[blockIdx.x];
+  const int tz = ck.tile % tg.nt[2], ty = (ck.tile / tg.nt[2]) % tg.nt[1],
+            tx = ck.tile / (tg.nt[2] * tg.nt[1]);
+  const int lo[3] = {tx * kT, ty * kT, tz * kT};
+  const int hi[3] = {min(lo[0] + kT, g.n[0]) - 1, min(lo[1] + kT, g.n[1]) - 1,
+                     min(lo[2] + kT, g.n[2]) - 1};
+  for (int c = threadIdx.x; c < kTileCells; c += kPBlock) tile[c] = 0.0;
+  __syncthreads();
+  for (int64_t e = ck.begin + threadIdx.x; e < ck.end; e += kPBlock) {
+    const int64_t t = pairs[e];
+    if ((uint64_t)t >= (uint64_t)n) continue;
+    const int64_t i = order ? order[t] : t;
+    Particle p;
+    load_particle(g, x, nullptr, h, i, p);
+    const float f = fbuf[t];
+    int b0[3], b1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      b0[a] = max(p.c0[a], lo[a]);
+      b1[a] = min(p.c1[a], hi[a]);
+    }
+    for_cells_in(g, p, b0, b1, [&](int64_t, int ix, int iy, int iz, float q, float, float, float, float) {
+      const float w = m4_w(q);
+      if (w > 0.0f)
+        atomicAdd(&tile[((ix - lo[0]) * kT + (iy - lo[1])) * kT + (iz - lo[2])], (double)(f * w));
+    });
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < kTileCells; c += kPBlock) {
+    const int lz = c % kT, ly = (c / kT) % kT, lx = c / (kT * kT);
+    if (ck.slot >= 0) {
+      partial[(int64_t)ck.slot * kTileCells + c] = tile[c];
+    } else if (lo[0] + lx <= hi[0] && lo[1] + ly <= hi[1] && lo[2] + lz <= hi[2]) {
+      mesh[((int64_t)(lo[0] + lx) * g.n[1] + (lo[1] + ly)) * g.n[2] + (lo[2] + lz)] = (float)tile[c];
     }
   }
-  if (use_tile) {
-    __syncthreads();
-    for (int c = threadIdx.x; c < ex * ey * ez; c += kPBlock) {
-      const double v = tile[c];
-      if (v != 0.0) {
-        const int iz = c % ez, iy = (c / ez) % ey, ix = c / (ez * ey);
-        const int64_t cidx = ((int64_t)(ix + bmin[0]) * g.n[1] + (iy + bmin[1])) * g.n[2] + (iz + bmin[2]);
-        unsafeAtomicAdd(acc + cidx, v);
-      }
-    }
-  }
+}
+
+struct SplitTile {
+  int32_t tile;
+  int32_t first_slot, n_slots;
+};
+
+// Step 5: tiles cut into several chunks add their partials in chunk order.
+// Grid (split tiles, kTileCells / kPBlock): one thread per cell.
+__global__ __launch_bounds__(kPBlock) void k_p2m_reduce(GridDev g, TileGrid tg,
+                                                        const SplitTile* __restrict__ split,
+                                                        const double* __restrict__ partial,
+                                                        float* __restrict__ mesh) {
+  const SplitTile st = split[blockIdx.x];
+  const int tz = st.tile % tg.nt[2], ty = (st.tile / tg.nt[2]) % tg.nt[1],
+            tx = st.tile / (tg.nt[2] * tg.nt[1]);
+  const int c = blockIdx.y * kPBlock + threadIdx.x;
+  const int lz = c % kT, ly = (c / kT) % kT, lx = c / (kT * kT);
+  const int ix = tx * kT + lx, iy = ty * kT + ly, iz = tz * kT + lz;
+  if (ix >= g.n[0] || iy >= g.n[1] || iz >= g.n[2]) return;
+  const double* src = partial + (int64_t)st.first_slot * kTileCells + c;
+  double v = 0.0;
+  for (int s = 0; s < st.n_slots; ++s) v += src[(int64_t)s * kTileCells];
+  mesh[((int64_t)ix * g.n[1] + iy) * g.n[2] + iz] = (float)v;
 }
 
 __global__ __launch_bounds__(kPBlock) void k_p2m_bwd(GridDev g, const float* __restrict__ x,
@@ -280,6 +425,33 @@ static kdt_status finish_bad_check(int32_t* d_bad, hipStream_t stream, const cha
   return KDT_OK;
 }
 
+namespace {
+
+// Device buffers of one forward call, released in stream order.
+struct FwdBuffers {
+  hipStream_t stream;
+  std::vector<void*> held;
+  explicit FwdBuffers(hipStream_t s) : stream(s) {}
+  template <typename T>
+  bool get(T** p, size_t count) {
+    void* q = nullptr;
+    if (hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), stream) != hipSuccess) return false;
+    held.push_back(q);
+    *p = static_cast<T*>(q);
+    return true;
+  }
+  ~FwdBuffers() {
+    for (void* q : held) (void)hipFreeAsync(q, stream);
+  }
+};
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
 extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d_h, int64_t n,
                               const kdt_grid* grid, const int32_t* d_order, float* d_grid,
                               hipStream_t stream) {
@@ -288,27 +460,130 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
     kdt_set_error("kdt_p2m: NULL pointer, negative n or invalid grid");
     return KDT_EINVAL;
   }
-  const int64_t cells = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
-  double* acc = nullptr;
+  if (n > INT32_MAX) {
+    kdt_set_error("kdt_p2m: n = %lld above 2^31 - 1", (long long)n);
+    return KDT_EUNSUPPORTED;
+  }
+  const GridDev g = to_dev(grid);
+  TileGrid tg;
+  int64_t n_tiles = 1;
+  for (int a = 0; a < 3; ++a) {
+    tg.nt[a] = (grid->n[a] + kT - 1) / kT;
+    n_tiles *= tg.nt[a];
+  }
+  if (n_tiles > INT32_MAX / 2) {
+    kdt_set_error("kdt_p2m: mesh too large (%lld tiles of %d^3 cells)", (long long)n_tiles, kT);
+    return KDT_EUNSUPPORTED;
+  }
+  FwdBuffers buf(stream);
+  float* fbuf = nullptr;
+  uint32_t* tcount = nullptr;
   int32_t* bad = nullptr;
-  if (hipMallocAsync((void**)&acc, sizeof(double) * cells, stream) != hipSuccess ||
-      hipMallocAsync((void**)&bad, 256, stream) != hipSuccess) {
-    kdt_set_error("kdt_p2m: cannot allocate the float64 accumulation mesh");
+  if (!buf.get(&fbuf, (size_t)n) || !buf.get(&tcount, (size_t)n_tiles + 64)) {
+    kdt_set_error("kdt_p2m: device allocation failed");
     return KDT_ENOMEM;
   }
-  const unsigned gc = (unsigned)((cells + 255) / 256);
-  k_zero_f64<<<gc, 256, 0, stream>>>(acc, cells);
-  k_zero_f64<<<1, 32, 0, stream>>>(reinterpret_cast<double*>(bad), 1);
+  bad = reinterpret_cast<int32_t*>(tcount + n_tiles);
+  const unsigned gt = (unsigned)((n_tiles + 64 + 255) / 256);
+  k_fill_u32<<<gt, 256, 0, stream>>>(tcount, n_tiles + 64, 0u);
+  const unsigned gp = (unsigned)((n + kPBlock - 1) / kPBlock);
   if (n > 0)
-    k_p2m_fwd<<<(unsigned)((n + kPBlock - 1) / kPBlock), kPBlock, 0, stream>>>(
-        to_dev(grid), d_x, d_m, d_h, n, d_order, acc, bad);
-  k_round_f32<<<gc, 256, 0, stream>>>(acc, d_grid, cells);
-  (void)hipFreeAsync(acc, stream);
+    k_p2m_prep<<<gp, kPBlock, 0, stream>>>(g, tg, d_x, d_m, d_h, n, d_order, fbuf, tcount, bad);
+  // the per-tile counts size the lists: read them back (with the check flag)
+  std::vector<uint32_t> cnt((size_t)n_tiles + 1);
+  hipError_t e = hipMemcpyAsync(cnt.data(), tcount, sizeof(uint32_t) * (n_tiles + 1),
+                                hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    kdt_set_error("kdt_p2m: %s", hipGetErrorString(e));
+    return KDT_EDEVICE;
+  }
+  if (cnt[n_tiles] != 0) {
+    kdt_set_error("kdt_p2m: a particle lies outside the grid or has an invalid smoothing length");
+    return KDT_EINVAL;
+  }
+  // lay out the lists and cut them into chunks; tiles of several chunks get
+  // consecutive partial slots (the chunk grows if the partials would pass 1 GiB)
+  std::vector<int64_t> toff((size_t)n_tiles + 1);
+  int64_t total = 0;
+  for (int64_t t = 0; t < n_tiles; ++t) {
+    toff[t] = total;
+    total += cnt[t];
+  }
+  toff[n_tiles] = total;
+  int64_t chunk = kChunk;
+  auto slots_for = [&](int64_t c) {
+    int64_t s = 0;
+    for (int64_t t = 0; t < n_tiles; ++t) {
+      const int64_t k = (cnt[t] + c - 1) / c;
+      if (k > 1) s += k;
+    }
+    return s;
+  };
+  while (slots_for(chunk) * (int64_t)sizeof(double) * kTileCells > (int64_t(1) << 30)) chunk *= 2;
+  std::vector<DepositChunk> chunks;
+  std::vector<SplitTile> split;
+  int32_t slots = 0;
+  chunks.reserve((size_t)n_tiles);
+  for (int64_t t = 0; t < n_tiles; ++t) {
+    const int64_t k = std::max<int64_t>(1, (cnt[t] + chunk - 1) / chunk);
+    if (k == 1) {
+      chunks.push_back({(int32_t)t, -1, toff[t], toff[t] + cnt[t]});
+      continue;
+    }
+    split.push_back({(int32_t)t, slots, (int32_t)k});
+    for (int64_t c = 0; c < k; ++c) {
+      const int64_t b = toff[t] + c * chunk;
+      chunks.push_back({(int32_t)t, slots++, b, std::min<int64_t>(b + chunk, toff[t] + cnt[t])});
+    }
+  }
+  // largest chunks first, so the long ones do not form the tail of the launch
+  // (the launch order changes nothing in the results: slots are fixed above)
+  std::stable_sort(chunks.begin(), chunks.end(), [](const DepositChunk& a, const DepositChunk& b) {
+    return a.end - a.begin > b.end - b.begin;
+  });
+  int32_t* pairs = nullptr;
+  int64_t* d_toff = nullptr;
+  DepositChunk* d_chunks = nullptr;
+  SplitTile* d_split = nullptr;
+  double* partial = nullptr;
+  if (!buf.get(&pairs, (size_t)total) || !buf.get(&d_toff, (size_t)n_tiles + 1) ||
+      !buf.get(&d_chunks, chunks.size()) || !buf.get(&d_split, split.size()) ||
+      !buf.get(&partial, (size_t)slots * kTileCells)) {
+    kdt_set_error("kdt_p2m: device allocation failed (%lld particle-tile pairs)", (long long)total);
+    return KDT_ENOMEM;
+  }
+  e = hipMemcpyAsync(d_toff, toff.data(), sizeof(int64_t) * (n_tiles + 1), hipMemcpyHostToDevice,
+                     stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_chunks, chunks.data(), sizeof(DepositChunk) * chunks.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && !split.empty())
+    e = hipMemcpyAsync(d_split, split.data(), sizeof(SplitTile) * split.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) {
+    kdt_set_error("kdt_p2m: %s", hipGetErrorString(e));
+    return KDT_EDEVICE;
+  }
+  k_fill_u32<<<gt, 256, 0, stream>>>(tcount, n_tiles, 0u);  // reused as list fill counters
+  if (n > 0)
+    k_p2m_scatter<<<gp, kPBlock, 0, stream>>>(g, tg, d_x, d_h, n, d_order, d_toff, tcount, pairs);
+  k_p2m_tile<<<(unsigned)chunks.size(), kPBlock, 0, stream>>>(g, tg, d_x, d_h, d_order, n, fbuf,
+                                                              pairs, d_chunks, d_grid, partial);
+  if (!split.empty())
+    k_p2m_reduce<<<dim3((unsigned)split.size(), kTileCells / kPBlock), kPBlock, 0, stream>>>(
+        g, tg, d_split, partial, d_grid);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_p2m: kernel launch failed");
     return KDT_EDEVICE;
   }
-  return finish_bad_check(bad, stream, "kdt_p2m");
+  // the host tables above must outlive their copies
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    kdt_set_error("kdt_p2m: %s", hipGetErrorString(e));
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
 }
 
 extern "C" kdt_status kdt_p2m_backward(const float* d_x, const float* d_m, const float* d_h,
