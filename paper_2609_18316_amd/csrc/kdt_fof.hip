@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kFBlock) void k_fof_link(TreeView t, float l2,
                                                       int32_t* __restrict__ parent,
                                                       uint32_t* __restrict__ conn) {
   __shared__ uint32_t stk[kMaxDepth][kFBlock];
-  const int64_t s = (int64_t)blockIdx.x * kFBlock + threadIdx.x;
+  const int64_t s = xcd_block<kXcdRunFof>() * kFBlock + threadIdx.x;
   if (s >= t.n) return;
   float p[D];
   int32_t me = 0;

@@ -56,6 +56,35 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroups are handed to the 8 XCDs round robin (workgroup b to XCD b % 8),
+// and each XCD has its own L2.  Kernels whose neighbouring workgroups touch
+// the same data (queries sorted along the tree) renumber themselves so that
+// runs of R consecutive logical workgroups go to one XCD: neighbours then
+// share an L2, while work that varies in space still spreads over all XCDs
+// every 8 R workgroups.  R = 0 gives each XCD one contiguous eighth of the
+// grid.  A bijection of [0, gridDim.x) for any grid size.
+template <int R>
+__device__ __forceinline__ int64_t xcd_block() {
+  constexpr int64_t kXcd = 8;
+  const int64_t g = gridDim.x, b = blockIdx.x;
+  const int64_t span = R > 0 ? kXcd * R : g;
+  const int64_t base = b / span * span, r = b - base;
+  const int64_t size = g - base < span ? g - base : span;
+  const int64_t per = size / kXcd, rem = size % kXcd, x = r % kXcd;
+  return base + x * per + (x < rem ? x : rem) + r / kXcd;
+}
+
+// Run lengths per kernel family, measured on 2^24 clustered points (R = 1 is
+// the plain round robin).  Per-lane kNN gains most from whole eighths
+// (9.4 -> 8.3 ms for 2^22 queries, 26.3 -> 21.6 ms for all points, k = 32);
+// grouping, whose cost is concentrated in the halos, balances better with
+// runs of 16 (19.5 -> 18.4 ms; whole eighths: 27 ms); wave-packet ball
+// counts gain nothing.
+constexpr int kXcdRunLane = 0;    // per-lane kNN and ball queries
+constexpr int kXcdRunPacket = 1;  // wave-packet kNN and ball queries
+constexpr int kXcdRunFof = 16;    // grouping
+constexpr int kXcdRunP2M = 64;    // particle passes of the deposit and its adjoint
+
 // Number of set lanes of `mask` below the calling lane.
 __device__ __forceinline__ int lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

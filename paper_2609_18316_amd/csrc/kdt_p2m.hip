@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
                                                       float* __restrict__ fbuf,
                                                       uint32_t* __restrict__ tcount,
                                                       int32_t* __restrict__ bad) {
-  const int64_t t = (int64_t)blockIdx.x * kPBlock + threadIdx.x;
+  const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
   int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
   bool has = false;
   if (t < n) {
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_scatter(GridDev g, TileGrid tg,
                                                          const int64_t* __restrict__ toff,
                                                          uint32_t* __restrict__ tfill,
                                                          int32_t* __restrict__ pairs) {
-  const int64_t t = (int64_t)blockIdx.x * kPBlock + threadIdx.x;
+  const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
   int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
   bool has = false;
   if (t < n) {
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_bwd(GridDev g, const float* __r
                                                      float* __restrict__ gm,
                                                      float* __restrict__ gx,
                                                      int32_t* __restrict__ bad) {
-  const int64_t t = (int64_t)blockIdx.x * kPBlock + threadIdx.x;
+  const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
   if (t >= n) return;
   const int64_t i = order ? order[t] : t;
   Particle p;

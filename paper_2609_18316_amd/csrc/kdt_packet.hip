@@ -39,7 +39,7 @@ __global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const f
                                                              float* __restrict__ od2, int leaf_cap) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t s0 = ((int64_t)blockIdx.x * kPWaves + wave) * 64;
+  const int64_t s0 = (xcd_block<kXcdRunPacket>() * kPWaves + wave) * 64;
   if (s0 >= nq) return;  // whole wave idle
   float p[D];
   int64_t row = 0;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const
                                                                int leaf_cap) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t s0 = ((int64_t)blockIdx.x * kPWaves + wave) * 64;
+  const int64_t s0 = (xcd_block<kXcdRunPacket>() * kPWaves + wave) * 64;
   if (s0 >= nq) return;
   float p[D];
   int64_t row = 0;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(64 * kPWaves) void k_fof_packet(TreeView t, float l
                                                              int leaf_cap) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t s0 = ((int64_t)blockIdx.x * kPWaves + wave) * 64;
+  const int64_t s0 = (xcd_block<kXcdRunFof>() * kPWaves + wave) * 64;
   if (s0 >= t.n) return;
   const int64_t pos = s0 + lane;
   const bool active = pos < t.n;

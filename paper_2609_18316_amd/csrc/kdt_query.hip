@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* _
                                                       int32_t* __restrict__ oidx,
                                                       float* __restrict__ od2) {
   extern __shared__ uint32_t stk_dyn[];
-  const int64_t s = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
+  const int64_t s = xcd_block<kXcdRunLane>() * kQBlock + threadIdx.x;
   if (s >= nq) return;
   float p[D];
   int64_t row;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
                                                    int32_t* __restrict__ out) {
   extern __shared__ uint32_t stk_dyn32[];
   uint32_t* col = stk_dyn32 + threadIdx.x;
-  const int64_t s = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
+  const int64_t s = xcd_block<kXcdRunLane>() * kQBlock + threadIdx.x;
   if (s >= nq) return;
   float p[D];
   int64_t row;
