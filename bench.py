@@ -131,7 +131,7 @@ def main():
         mark("knn_order")
         idx, d2 = tree.knn(qt, K, order=order)
         mark("knn")
-        cnt = tree.range(qt, RADIUS, order=order)
+        cnt = tree.range(qt, RADIUS)  # sorts its queries in tree-leaf order itself
         mark("range")
         lab = tree.fof(l_fof)
         mark("fof")

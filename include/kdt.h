@@ -231,15 +231,21 @@ kdt_status kdt_p2m_backward(const float *d_x, const float *d_m, const float *d_h
                             hipStream_t stream);
 
 /*
- * kdt_query_order -- writes into d_order [nq] (int32, device) a permutation of
- * the queries that follows the tree: queries sorted by the leaf reached when
- * descending towards the nearer child at every level.  Passing it back through
- * kdt_query_opts.order lets repeated queries skip the sort.  Results of the
- * queries never depend on the order.
- * Errors: KDT_EINVAL (NULL pointer, nq outside [1, 2^31-1]), KDT_ENOMEM, KDT_EDEVICE.
+ * kdt_query_order -- writes into d_order [nq] (int32, device) a deterministic
+ * permutation of the queries that follows the tree's space, for reuse
+ * through kdt_query_opts.order (the queries calls then skip their own sort).
+ * kind 0: for d <= 4 the order of a Hilbert curve over the root bounding box
+ *   (30 / d bits per axis), computed without touching the tree -- the order
+ *   kdt_knn uses with one traversal per lane; above d = 4 as kind 1.
+ * kind 1: queries sorted by the leaf reached when descending towards the
+ *   nearer child at every level -- the order the wave-shared traversals (ball
+ *   counts, wave-packet kNN) use.
+ * Results of the queries never depend on the order, only their speed.
+ * Errors: KDT_EINVAL (NULL pointer, nq outside [1, 2^31-1], other kind),
+ * KDT_ENOMEM, KDT_EDEVICE.
  */
-kdt_status kdt_query_order(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t *d_order,
-                           hipStream_t stream);
+kdt_status kdt_query_order(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t kind,
+                           int32_t *d_order, hipStream_t stream);
 
 /* Device pointer to the tree order: perm[t] is the input index of the point at
    tree position t (n int32, owned by the tree).  NULL on error. */

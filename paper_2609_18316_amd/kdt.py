@@ -72,7 +72,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_fof.argtypes = [vp, f32, vp, C.POINTER(C.c_int64), vp]
     lib.kdt_p2m.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp]
     lib.kdt_p2m_backward.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp, vp, vp]
-    lib.kdt_query_order.argtypes = [vp, vp, i64, vp, vp]
+    lib.kdt_query_order.argtypes = [vp, vp, i64, C.c_int32, vp, vp]
     lib.kdt_tree_perm.argtypes = [vp]
     lib.kdt_tree_perm.restype = vp
     if hasattr(lib, "kdt_batch_plan_create"):
@@ -157,12 +157,17 @@ class Tree:
         """Device address of the tree order (n int32, owned by the tree)."""
         return int(load().kdt_tree_perm(self._h))
 
-    def query_order(self, queries: torch.Tensor, stream=None) -> torch.Tensor:
-        """Permutation of the queries along the tree (reusable through ``order=``)."""
+    def query_order(self, queries: torch.Tensor, kind: int = 0, stream=None) -> torch.Tensor:
+        """Permutation of the queries along the tree (reusable through ``order=``).
+
+        kind 0: Hilbert curve over the root box (d <= 4), the order of per-lane
+        kNN; kind 1: tree-leaf order, the order of ball counts and wave packets.
+        """
         nq = queries.shape[0]
         queries = _dev(queries, torch.float32, "queries", (nq, self.d))
         order = torch.empty(nq, dtype=torch.int32, device=self.device)
-        _check(load().kdt_query_order(self._h, _ptr(queries), nq, _ptr(order), _stream(stream)))
+        _check(load().kdt_query_order(self._h, _ptr(queries), nq, int(kind), _ptr(order),
+                                      _stream(stream)))
         return order
 
     def knn(self, queries: torch.Tensor | None, k: int, kth_only: int = 0,

@@ -104,13 +104,41 @@ def test_unsorted_queries_give_the_same_answer():
     b = t.knn(to_dev(q), 16, sort_queries=False)
     np.testing.assert_array_equal(to_host(a[0]), to_host(b[0]))
     np.testing.assert_array_equal(to_host(a[1]), to_host(b[1]))
-    order = t.query_order(to_dev(q))
-    o = to_host(order)
+    for kind in (0, 1):
+        order = t.query_order(to_dev(q), kind=kind)
+        o = to_host(order)
+        assert np.array_equal(np.sort(o), np.arange(len(q)))
+        assert np.array_equal(o, to_host(t.query_order(to_dev(q), kind=kind)))  # deterministic
+        for trav in (1, 2):
+            c = t.knn(to_dev(q), 16, order=order, traversal=trav)
+            np.testing.assert_array_equal(to_host(a[0]), to_host(c[0]))
+            np.testing.assert_array_equal(to_host(a[1]), to_host(c[1]))
+        np.testing.assert_array_equal(to_host(t.range(to_dev(q), 0.02, order=order)),
+                                      to_host(t.range(to_dev(q), 0.02, sort_queries=False)))
+    with pytest.raises(kdt.KdtError):
+        t.query_order(to_dev(q), kind=2)
+
+
+@pytest.mark.parametrize("d,levels", ((2, 4), (3, 3), (4, 2)))
+def test_query_order_walks_a_block_lattice_with_unit_steps(d, levels):
+    """For d <= 4 the order follows a Hilbert curve over the root box: one
+    query at the centre of every block of a 2^levels lattice over the box,
+    given in a shuffled order, comes back as a walk whose consecutive blocks
+    share a face (a Z curve would jump), and each block once."""
+    dev()
+    x = workloads.uniform(20000, d, seed=15)
+    x[0], x[1] = 0.0, 1.0  # root box exactly [0, 1]^d
+    t = kdt.build(to_dev(x))
+    ex = t.export()
+    assert (ex["lo"][0] == 0).all() and (ex["hi"][0] == 1).all()
+    m = 1 << levels
+    blocks = np.array(np.meshgrid(*[np.arange(m)] * d, indexing="ij")).reshape(d, -1).T
+    perm = np.random.default_rng(17).permutation(len(blocks))
+    q = ((blocks[perm] + 0.5) / m).astype(np.float32)
+    o = to_host(t.query_order(to_dev(q)))
     assert np.array_equal(np.sort(o), np.arange(len(q)))
-    c = t.knn(to_dev(q), 16, order=order)
-    np.testing.assert_array_equal(to_host(a[0]), to_host(c[0]))
-    np.testing.assert_array_equal(to_host(t.range(to_dev(q), 0.02, order=order)),
-                                  to_host(t.range(to_dev(q), 0.02, sort_queries=False)))
+    walk = blocks[perm][o]
+    assert (np.abs(np.diff(walk, axis=0)).sum(1) == 1).all()
 
 
 def test_knn_full_small_config():

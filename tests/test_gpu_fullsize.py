@@ -33,7 +33,7 @@ def test_knn_and_counts_full_size_sampled(clustered):
     say("kNN k=32 of 2^22 queries + r=0.01 counts")
     order = tree.query_order(qt)
     idx, d2 = tree.knn(qt, 32, order=order)
-    cnt = tree.range(qt, 0.01, order=order)
+    cnt = tree.range(qt, 0.01)
     s = workloads.sample_indices(NQ, 4096, seed=7)
     oi, od = ot.knn(q[s], 32)
     np.testing.assert_array_equal(to_host(idx)[s], oi)
