@@ -4,9 +4,9 @@
 // A wave of 64 spatially coherent queries walks one tree together.  The node
 // stack is held in the wave's lane registers (entry i lives in lane i, popped
 // with readlane), so it costs no memory.  A node is entered when at least one
-// lane needs it (wave ballot); a visited leaf is copied once into the wave's
-// LDS slice and its points are read back as broadcasts, so one coalesced load
-// serves 64 queries.
+// lane needs it (wave ballot); the boxes and the points of a visited leaf sit
+// at wave-uniform addresses and are read with scalar loads, one load serving
+// 64 queries, several points in flight at a time.
 #pragma once
 
 #include "kdt_query.h"
@@ -16,16 +16,16 @@ namespace kdt {
 // kNN of the 64 queries of a wave (Algorithm 2 semantics).  Each lane keeps its
 // own register top-k keyed by (d2, index), so the result is exactly the k
 // smallest keys, the same as any exact traversal.  Leaves must hold at most 64
-// points; leafbuf is the wave's LDS slice of leaf_size * rec_stride(D) floats.
+// points.
 template <int D, int KC>
 __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], bool active,
-                                           TopK<KC>& best, float* leafbuf) {
-  constexpr int S = rec_stride(D);
+                                           TopK<KC>& best) {
   const int lane = lane_id();
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   uint32_t stackv = 0;  // lane i holds stack entry i
   int sp = 1;
-  uint64_t mask = 0;    // this lane's pending candidates in the staged leaf
+  uint64_t mask = 0;    // this lane's pending candidates in the current leaf
+  int64_t leaf_b = 0;   // first record of the current leaf (wave-uniform)
   // One flat loop (the candidate list is then live across a single loop
   // header): a round either inserts one pending candidate per lane, or pops
   // and visits the next node.
@@ -34,11 +34,10 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       const bool has = mask != 0;
       const int i = has ? __ffsll((unsigned long long)mask) - 1 : 0;
       mask &= mask - 1;
-      const float* r = leafbuf + i * S;
       float x[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a) x[a] = r[a];
-      const uint64_t key = make_key(sq_dist<D>(x, p), __float_as_int(r[D]));
+      int32_t id = 0;
+      load_rec<D>(t.rec, leaf_b + i, x, id);
+      const uint64_t key = make_key(sq_dist<D>(x, p), id);
       best.insert(has && key < best.worst() ? key : kEmptyKey);
       continue;
     }
@@ -46,18 +45,14 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
     --sp;
     const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)stackv, sp);
     float lo[D], hi[D];
-    load_box<D>(t.box, node, lo, hi);
+    load_box_uniform<D>(t.box, node, lo, hi);
     const bool need = active && box_mindist<D>(lo, hi, p) <= best.worst_d2();
     if (!__any(need)) continue;
     if (node >= first_leaf) {
       const int64_t j = node - first_leaf;
       const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
       const int cnt = (int)(e - b);
-      wave_sync();  // every lane is done with the previous leaf
-      const float4* src = reinterpret_cast<const float4*>(t.rec + b * S);
-      float4* dst = reinterpret_cast<float4*>(leafbuf);
-      for (int i = lane; i < cnt * (S / 4); i += 64) dst[i] = src[i];
-      wave_sync();
+      leaf_b = b;
       // Mark the leaf points (at most 64) that beat this lane's current k-th
       // candidate; the rounds above then insert them, so the wave pays for
       // the largest per-lane count of insertions rather than for every point
@@ -65,21 +60,21 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       // A float compare on d2 alone marks a superset of the candidates (it
       // keeps ties with the current k-th); the exact key test is repeated
       // before insertion.
+      // The points are read at wave-uniform addresses (scalar loads,
+      // broadcast to every lane), several in flight at a time.
       const float wd = best.worst_d2();
-#pragma unroll 1
+#pragma unroll 8
       for (int i = 0; i < cnt; ++i) {
-        const float* r = leafbuf + i * S;
         float x[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) x[a] = r[a];
+        load_rec_uniform<D>(t.rec, b + i, x);
         mask |= (uint64_t)(sq_dist<D>(x, p) <= wd) << i;
       }
       if (!active) mask = 0;
     } else {
       const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
-      load_box<D>(t.box, c0, lo, hi);
+      load_box_uniform<D>(t.box, c0, lo, hi);
       const float d0 = box_mindist<D>(lo, hi, p);
-      load_box<D>(t.box, c1, lo, hi);
+      load_box_uniform<D>(t.box, c1, lo, hi);
       const float d1 = box_mindist<D>(lo, hi, p);
       const float wd = best.worst_d2();
       const bool n0 = active && d0 <= wd, n1 = active && d1 <= wd;
@@ -110,8 +105,7 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
 // counts its descendants again.  Leaves must hold at most 64 points.
 template <int D>
 __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const float p[D],
-                                                      bool active, float r2, float* leafbuf) {
-  constexpr int S = rec_stride(D);
+                                                      bool active, float r2) {
   const int lane = lane_id();
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   int64_t count = 0;
@@ -125,7 +119,7 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
                           (uint32_t)__builtin_amdgcn_readlane((int)stk_lo, sp);
     const bool mine = active && ((live >> lane) & 1ull);
     float lo[D], hi[D];
-    load_box<D>(t.box, node, lo, hi);
+    load_box_uniform<D>(t.box, node, lo, hi);
     const bool touch = mine && box_mindist<D>(lo, hi, p) <= r2;
     if (!__any(touch)) continue;
     const bool full = touch && box_maxdist<D>(lo, hi, p) <= r2;
@@ -137,19 +131,14 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
     const uint64_t pm = __ballot(part);
     if (pm == 0) continue;
     if (node >= first_leaf) {
+      // the leaf's points are read at wave-uniform addresses (scalar loads,
+      // broadcast to every lane), several points in flight at a time
       const int cnt = (int)(e - b);
-      wave_sync();
-      const float4* src = reinterpret_cast<const float4*>(t.rec + b * S);
-      float4* dst = reinterpret_cast<float4*>(leafbuf);
-      for (int i = lane; i < cnt * (S / 4); i += 64) dst[i] = src[i];
-      wave_sync();
       int c = 0;
-#pragma unroll 1
+#pragma unroll 8
       for (int i = 0; i < cnt; ++i) {
-        const float* r = leafbuf + i * S;
         float x[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) x[a] = r[a];
+        load_rec_uniform<D>(t.rec, b + i, x);
         c += sq_dist<D>(x, p) <= r2;
       }
       if (part) count += c;
@@ -179,7 +168,7 @@ template <int D>
 __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], int64_t pos,
                                            int32_t me, bool active, float l2, int32_t base,
                                            int32_t* __restrict__ parent,
-                                           uint32_t* __restrict__ conn, float* leafbuf) {
+                                           uint32_t* __restrict__ conn) {
   constexpr int S = rec_stride(D);
   const int lane = lane_id();
   const uint32_t first_leaf = (1u << t.levels) - 1u;
@@ -194,7 +183,7 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
                           (uint32_t)__builtin_amdgcn_readlane((int)stk_lo, sp);
     const bool mine = active && ((live >> lane) & 1ull);
     float lo[D], hi[D];
-    load_box<D>(t.box, node, lo, hi);
+    load_box_uniform<D>(t.box, node, lo, hi);
     bool touch = mine && box_mindist<D>(lo, hi, p) <= l2;
     if (!__any(touch)) continue;
     const int lev = node_level(node);
@@ -226,26 +215,27 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
     const uint64_t pm = __ballot(part);
     if (pm == 0) continue;
     if (node >= first_leaf) {
+      // Friends in the leaf: distances for every lane at wave-uniform
+      // addresses (scalar loads, several in flight), then each lane links
+      // its own friends.
       const int cnt = (int)(e - b);
-      wave_sync();
-      const float4* src = reinterpret_cast<const float4*>(t.rec + b * S);
-      float4* dst = reinterpret_cast<float4*>(leafbuf);
-      for (int i = lane; i < cnt * (S / 4); i += 64) dst[i] = src[i];
-      wave_sync();
-      if (part) {
-        for (int i = 0; i < cnt; ++i) {
-          const float* r = leafbuf + i * S;
-          float x[D];
-#pragma unroll
-          for (int a = 0; a < D; ++a) x[a] = r[a];
-          if (sq_dist<D>(x, p) > l2) continue;
-          const int32_t id = __float_as_int(r[D]);
-          if (one) {
-            uf_union(parent, gme, base + id);
-            break;
-          }
-          if (id > me) uf_union(parent, gme, base + id);
+      uint64_t fr = 0;
+#pragma unroll 8
+      for (int i = 0; i < cnt; ++i) {
+        float x[D];
+        load_rec_uniform<D>(t.rec, b + i, x);
+        fr |= (uint64_t)(sq_dist<D>(x, p) <= l2) << i;
+      }
+      if (!part) fr = 0;
+      while (fr) {
+        const int i = __ffsll((unsigned long long)fr) - 1;
+        fr &= fr - 1;
+        const int32_t id = __float_as_int(t.rec[(b + i) * S + D]);
+        if (one) {
+          uf_union(parent, gme, base + id);
+          break;
         }
+        if (id > me) uf_union(parent, gme, base + id);
       }
     } else {
       const uint32_t mlo = (uint32_t)pm, mhi = (uint32_t)(pm >> 32);

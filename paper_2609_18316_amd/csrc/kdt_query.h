@@ -38,14 +38,14 @@ __device__ __forceinline__ void load_box(const float* __restrict__ box, uint32_t
 // Smallest squared distance from p to the box: the same float32 operations,
 // in the same axis order, as the point distance, so it never exceeds the
 // rounded distance of any point inside the box.
+// The axis gap max(lo - p, p - hi, 0) is exactly lo - p below the box, p - hi
+// above it and 0 inside (a max does not round), taken without branches.
 template <int D>
 __device__ __forceinline__ float box_mindist(const float lo[D], const float hi[D], const float p[D]) {
   float s = 0.0f;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    float t = 0.0f;
-    if (p[a] < lo[a]) t = lo[a] - p[a];
-    else if (p[a] > hi[a]) t = p[a] - hi[a];
+    const float t = fmaxf(fmaxf(lo[a] - p[a], p[a] - hi[a]), 0.0f);
     float t2 = t * t;
     s = s + t2;
   }
@@ -98,6 +98,35 @@ __device__ __forceinline__ void load_rec(const float* __restrict__ rec, int64_t 
       if (a == D) idx = __float_as_int(w[c]);
     }
   }
+}
+
+// Reads of wave-uniform addresses in data that no kernel writes while it
+// runs (tree records and boxes): through the constant address space, so
+// the compiler issues scalar loads, several in flight and shared by the wave.
+typedef const __attribute__((address_space(4))) float cfloat;
+__device__ __forceinline__ const cfloat* as_uniform(const float* p) {
+  return (const cfloat*)p;
+}
+
+// Box of a node whose index is wave-uniform.
+template <int D>
+__device__ __forceinline__ void load_box_uniform(const float* box, uint32_t node, float lo[D],
+                                                 float hi[D]) {
+  constexpr int P = pad4(D);
+  const cfloat* b = as_uniform(box) + (size_t)node * 2 * P;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = b[a];
+    hi[a] = b[P + a];
+  }
+}
+
+// Coordinates of tree record i read at a wave-uniform address.
+template <int D>
+__device__ __forceinline__ void load_rec_uniform(const float* rec, int64_t i, float x[D]) {
+  const cfloat* r = as_uniform(rec) + i * rec_stride(D);
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = r[a];
 }
 
 // Key of an empty candidate slot: squared distance +inf, index 0xFFFFFFFF, so
