@@ -10,7 +10,11 @@ available -- the batched forest of 256 clustered sets (kNN k = 8 + FoF).
 
 Inputs are generated on the host and copied to the GPU before timing.  Each
 stage is timed with HIP events on the stream that runs it; the headline value
-is kNN queries per second of the k = 32 stage.  Prints ONE JSON line.
+is kNN queries per second of the k = 32 stage.  After the timed steps, outside
+them: the per-set baseline of the batched mode, the dimensionality sweep
+(build and k = 16 kNN over 2^22 points in d = 2, 4, 8, 16, uniform and normal,
+autotuned leaf size) and the CPU oracle on a bounded sample.  Prints ONE JSON
+line.
 """
 from __future__ import annotations
 
@@ -36,6 +40,32 @@ HBM_PEAK_GBS = 8000.0
 BATCH_SETS = 256
 
 
+# Hardware counters of the kNN traversal kernel (k_knn_lane<3,32>, one launch
+# over the 2^22 queries), taken with rocprofv3 --pmc on MI355X: FETCH_SIZE
+# and WRITE_SIZE (KiB per dispatch) in two runs, FETCH_SIZE scaled by 2.0 and
+# WRITE_SIZE by 1.0 -- the factors that turn the same counters of a plain
+# 1 GiB read + 1 GiB write kernel into its bytes -- and TCC_HIT / TCC_MISS,
+# SQ_INSTS_VALU.  They describe the kernel built from the sources whose hash
+# is given; for any other source they are not reported.
+KNN_COUNTERS = {
+    "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
+                "paper_2609_18316_amd/csrc/kdt_internal.h"],
+    "sha256": None,
+    "hbm_bytes": None,
+    "l2_hit_rate": None,
+    "valu_issue_frac": None,
+}
+
+
+def sources_hash(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +74,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=1 << 14)
+    ap.add_argument("--no-dsweep", action="store_true")
     return ap.parse_args()
 
 
@@ -65,6 +96,46 @@ def cpu_baseline(x, q, n_q):
                       f"{x.shape[0] / (t1 - t0) / 1e6:.2f} Mpts/s), kNN k={K} of the first "
                       f"{n_q} of the {q.shape[0]} queries",
             "build_mpts_s": x.shape[0] / (t1 - t0) / 1e6}
+
+
+def dimension_sweep(torch, kdt, workloads, dev):
+    """Build and kNN (k = 16, the points themselves as queries) over 2^22
+    points in d = 2, 4, 8, 16, uniform and standard normal, with the leaf size
+    and traversal the autotuner stored for each shape.  Every point queries
+    up to d = 8; at d = 16 (near brute force) the first 2^16 points do."""
+    from paper_2609_18316_amd import autotune
+    n, k = 1 << 22, 16
+    rows = []
+    for d in (2, 4, 8, 16):
+        for dist in ("uniform", "normal"):
+            pts = workloads.uniform(n, d, 300 + d) if dist == "uniform" else \
+                workloads.normal(n, d, 400 + d)
+            xt = torch.from_numpy(pts).to(dev)
+            c = autotune.lookup(n, d, k, f"self-{dist}")
+            trav = 2 if c.queries_per_wave == 64 else 1
+            kdt.build(xt, leaf_size=c.leaf_size, check_finite=False).close()  # warm-up
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            t = kdt.build(xt, leaf_size=c.leaf_size, check_finite=False)
+            e.record()
+            torch.cuda.synchronize()
+            build_ms = s.elapsed_time(e)
+            nq = n if d <= 8 else 1 << 16
+            qs = None if nq == n else xt[:nq].contiguous()
+            s.record()
+            t.knn(qs, k, traversal=trav)
+            e.record()
+            torch.cuda.synchronize()
+            knn_ms = s.elapsed_time(e)
+            rows.append({"d": d, "dist": dist, "n": n, "leaf_size": c.leaf_size,
+                         "traversal": "lane" if trav == 1 else "wave", "build_ms": build_ms,
+                         "build_mpts_s": n / (build_ms * 1e-3) / 1e6, "queries": nq,
+                         "knn_ms": knn_ms, "knn_queries_s": nq / (knn_ms * 1e-3)})
+            t.close()
+            del xt
+            print(f"[bench] d={d} {dist}: build {build_ms:.2f} ms, kNN {knn_ms:.2f} ms "
+                  f"({nq} queries)", file=sys.stderr, flush=True)
+    return rows
 
 
 def main():
@@ -204,6 +275,12 @@ def main():
                      "kernel": "k_knn_lane<3,32> (kNN traversal, k=32, one query per lane): "
                                "compulsory bytes 4d + 8k = 268 per query"},
     }
+    if KNN_COUNTERS["sha256"] and sources_hash(KNN_COUNTERS["sources"]) == KNN_COUNTERS["sha256"]:
+        rf = out["roofline"]
+        rf["traffic"] = KNN_COUNTERS["hbm_bytes"]
+        rf["traffic_gbs"] = KNN_COUNTERS["hbm_bytes"] / (avg["knn"] * 1e-3) / 1e9
+        rf["l2_hit_rate"] = KNN_COUNTERS["l2_hit_rate"]
+        rf["valu_issue_frac"] = KNN_COUNTERS["valu_issue_frac"]
     if batch:
         # The baseline (the single-tree entry points once per set, eager) is
         # timed outside the timed steps: it is a comparison, not the path.
@@ -219,6 +296,8 @@ def main():
         out["batch_per_set_eager_ms"] = float(np.mean(reps))
         out["batched_speedup"] = out["batch_per_set_eager_ms"] / avg["batch_graph"]
         out["batched_points"] = batch[4]
+    if not args.no_dsweep:
+        out["dsweep"] = dimension_sweep(torch, kdt, workloads, dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(x, q, args.cpu_queries)

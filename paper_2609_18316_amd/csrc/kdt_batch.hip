@@ -82,9 +82,11 @@ __global__ __launch_bounds__(kBQ) void k_knn_forest(const SetDesc* __restrict__ 
 template <int D, int KC>
 __global__ __launch_bounds__(256) void k_knn_forest_packet(
     const SetDesc* __restrict__ sets, int n_sets, const int64_t* __restrict__ pbase,
-    const float* __restrict__ rec, const float* __restrict__ box, int k,
+    const float* __restrict__ rec, const float* __restrict__ box, int k, int leaf_cap,
     int32_t* __restrict__ oidx, float* __restrict__ od2, unsigned long long* __restrict__ ctr) {
-  const int lane = lane_id();
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  float* slice = LeafReader<D>::kStaged ? lds + (size_t)wave * leaf_cap * rec_stride(D) : nullptr;
   const int64_t n_packets = pbase[n_sets];
   for (;;) {
     unsigned long long got = 0;
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(256) void k_knn_forest_packet(
     }
     TopK<KC> best;
     best.init(k);
-    packet_knn<D, KC>(t, q, active, best);
+    packet_knn<D, KC>(t, q, active, best, slice);
     if (active) knn_write<KC>(best, k, 0, sd.off + id, oidx, od2);
   }
 }
@@ -122,9 +124,11 @@ template <int D>
 __global__ __launch_bounds__(256) void k_fof_forest_packet(
     const SetDesc* __restrict__ sets, int n_sets, const int64_t* __restrict__ pbase,
     const float* __restrict__ rec, const float* __restrict__ box,
-    const float* __restrict__ lengths, int32_t* __restrict__ parent,
+    const float* __restrict__ lengths, int leaf_cap, int32_t* __restrict__ parent,
     uint32_t* __restrict__ conn, unsigned long long* __restrict__ ctr) {
-  const int lane = lane_id();
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  float* slice = LeafReader<D>::kStaged ? lds + (size_t)wave * leaf_cap * rec_stride(D) : nullptr;
   const int64_t n_packets = pbase[n_sets];
   for (;;) {
     unsigned long long got = 0;
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(256) void k_fof_forest_packet(
 #pragma unroll
       for (int a = 0; a < D; ++a) q[a] = 0.0f;
     }
-    packet_fof<D>(t, q, pos, me, active, l2, (int32_t)sd.off, parent, conn + sd.node_base);
+    packet_fof<D>(t, q, pos, me, active, l2, (int32_t)sd.off, parent, conn + sd.node_base, slice);
   }
 }
 
@@ -260,6 +264,13 @@ struct kdt_batch_plan {
   const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
+// LDS of a 4-wave workgroup of the forest packet kernels (leaf slices where
+// leaves are staged).
+template <int D>
+static size_t forest_lds_bytes(int leaf) {
+  return LeafReader<D>::kStaged ? sizeof(float) * (size_t)leaf * rec_stride(D) * 4 : 0;
+}
+
 template <int D, int KC>
 static int occupancy_blocks(const void* fn, size_t smem, int block) {
   int per_cu = 0, dev = 0, cus = 0;
@@ -279,14 +290,15 @@ static kdt_status forest_queries(kdt_batch_plan* bp, const float* d_l, int32_t* 
   const int k = bp->k;
   if (bp->knn_packets) {
     const unsigned g = (unsigned)bp->knn_blocks;
+    const size_t smem = forest_lds_bytes<D>(bp->leaf);
     if (k <= 8)
-      k_knn_forest_packet<D, 8><<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, d_idx, d_d2, bp->ctr);
+      k_knn_forest_packet<D, 8><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
     else if (k <= 16)
-      k_knn_forest_packet<D, 16><<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, d_idx, d_d2, bp->ctr);
+      k_knn_forest_packet<D, 16><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
     else if (k <= 32)
-      k_knn_forest_packet<D, 32><<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, d_idx, d_d2, bp->ctr);
+      k_knn_forest_packet<D, 32><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
     else
-      k_knn_forest_packet<D, 64><<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, d_idx, d_d2, bp->ctr);
+      k_knn_forest_packet<D, 64><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
   } else if (k <= 8)
     k_knn_forest<D, 8><<<bp->knn_blocks, kBQ, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box,
                                                       tot, k, d_idx, d_d2, bp->ctr);
@@ -306,9 +318,9 @@ static kdt_status forest_queries(kdt_batch_plan* bp, const float* d_l, int32_t* 
   k_fof_forest_join<D><<<g, 256, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box, tot,
                                          bp->parent, bp->conn);
   if (bp->leaf <= 64) {
-    k_fof_forest_packet<D><<<bp->fof_blocks, 256, 0, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec,
-                                                          bp->out.box, d_l, bp->parent, bp->conn,
-                                                          bp->ctr + 1);
+    k_fof_forest_packet<D><<<bp->fof_blocks, 256, forest_lds_bytes<D>(bp->leaf), s>>>(
+        bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, d_l, bp->leaf, bp->parent, bp->conn,
+        bp->ctr + 1);
   } else {
     k_fof_forest<D><<<bp->fof_blocks, kBQ, 0, s>>>(bp->dev.sets, ns, bp->out.rec, bp->out.box, tot,
                                                    d_l, bp->parent, bp->conn, bp->ctr + 1);
@@ -339,7 +351,7 @@ static kdt_status forest_pipeline(kdt_batch_plan* bp, const float* d_pts, const 
 template <int D>
 static void size_grids(kdt_batch_plan* bp) {
   const void* kf = nullptr;
-  const size_t smem = 0;
+  const size_t smem = bp->leaf <= 64 ? forest_lds_bytes<D>(bp->leaf) : 0;
   if (bp->knn_packets) {
     if (bp->k <= 8) kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 8>);
     else if (bp->k <= 16) kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 16>);

@@ -4,14 +4,59 @@
 // A wave of 64 spatially coherent queries walks one tree together.  The node
 // stack is held in the wave's lane registers (entry i lives in lane i, popped
 // with readlane), so it costs no memory.  A node is entered when at least one
-// lane needs it (wave ballot); the boxes and the points of a visited leaf sit
-// at wave-uniform addresses and are read with scalar loads, one load serving
-// 64 queries, several points in flight at a time.
+// lane needs it (wave ballot); its box sits at a wave-uniform address and is
+// read with scalar loads, one load serving 64 queries.
 #pragma once
 
 #include "kdt_query.h"
 
 namespace kdt {
+
+// Where a wave reads the points of the leaf it visits.  Up to d = 4 straight
+// from the tree records at wave-uniform addresses: scalar loads broadcast to
+// every lane, several points in flight.  From d = 8 a leaf (up to 64 records
+// of rec_stride(d) floats) no longer fits the scalar cache with the other
+// waves' leaves, so it is copied once into the wave's LDS slice (`lds`, at
+// least 64 records) and read back as LDS broadcasts.
+template <int D>
+struct LeafReader {
+  static constexpr bool kStaged = D > 4;
+  static constexpr int S = rec_stride(D);
+  const float* rec;
+  float* lds;
+  int64_t b = 0;  // first record of the open leaf
+  __device__ __forceinline__ LeafReader(const float* r, float* l) : rec(r), lds(l) {}
+  // Called by the whole wave with a wave-uniform leaf.
+  __device__ __forceinline__ void open(int64_t first, int cnt) {
+    b = first;
+    if constexpr (kStaged) {
+      wave_sync();  // every lane is done with the previous leaf
+      const float4* src = reinterpret_cast<const float4*>(rec + first * S);
+      float4* dst = reinterpret_cast<float4*>(lds);
+      for (int i = lane_id(); i < cnt * (S / 4); i += 64) dst[i] = src[i];
+      wave_sync();
+    }
+  }
+  // Point i of the open leaf, i wave-uniform.
+  __device__ __forceinline__ void point(int i, float x[D]) const {
+    if constexpr (kStaged) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) x[a] = lds[i * S + a];
+    } else {
+      load_rec_uniform<D>(rec, b + i, x);
+    }
+  }
+  // Point i of the open leaf and its index, i per lane.
+  __device__ __forceinline__ void lane_point(int i, float x[D], int32_t& id) const {
+    if constexpr (kStaged) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) x[a] = lds[i * S + a];
+      id = __float_as_int(lds[i * S + D]);
+    } else {
+      load_rec<D>(rec, b + i, x, id);
+    }
+  }
+};
 
 // kNN of the 64 queries of a wave (Algorithm 2 semantics).  Each lane keeps its
 // own register top-k keyed by (d2, index), so the result is exactly the k
@@ -19,13 +64,13 @@ namespace kdt {
 // points.
 template <int D, int KC>
 __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], bool active,
-                                           TopK<KC>& best) {
+                                           TopK<KC>& best, float* lds) {
   const int lane = lane_id();
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   uint32_t stackv = 0;  // lane i holds stack entry i
   int sp = 1;
-  uint64_t mask = 0;    // this lane's pending candidates in the current leaf
-  int64_t leaf_b = 0;   // first record of the current leaf (wave-uniform)
+  uint64_t mask = 0;    // this lane's pending candidates in the open leaf
+  LeafReader<D> leaf(t.rec, lds);
   // One flat loop (the candidate list is then live across a single loop
   // header): a round either inserts one pending candidate per lane, or pops
   // and visits the next node.
@@ -36,7 +81,7 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       mask &= mask - 1;
       float x[D];
       int32_t id = 0;
-      load_rec<D>(t.rec, leaf_b + i, x, id);
+      leaf.lane_point(i, x, id);
       const uint64_t key = make_key(sq_dist<D>(x, p), id);
       best.insert(has && key < best.worst() ? key : kEmptyKey);
       continue;
@@ -52,7 +97,7 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       const int64_t j = node - first_leaf;
       const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
       const int cnt = (int)(e - b);
-      leaf_b = b;
+      leaf.open(b, cnt);
       // Mark the leaf points (at most 64) that beat this lane's current k-th
       // candidate; the rounds above then insert them, so the wave pays for
       // the largest per-lane count of insertions rather than for every point
@@ -60,13 +105,11 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       // A float compare on d2 alone marks a superset of the candidates (it
       // keeps ties with the current k-th); the exact key test is repeated
       // before insertion.
-      // The points are read at wave-uniform addresses (scalar loads,
-      // broadcast to every lane), several in flight at a time.
       const float wd = best.worst_d2();
-#pragma unroll 8
+#pragma unroll uniform_batch<D>()
       for (int i = 0; i < cnt; ++i) {
         float x[D];
-        load_rec_uniform<D>(t.rec, b + i, x);
+        leaf.point(i, x);
         mask |= (uint64_t)(sq_dist<D>(x, p) <= wd) << i;
       }
       if (!active) mask = 0;
@@ -105,8 +148,9 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
 // counts its descendants again.  Leaves must hold at most 64 points.
 template <int D>
 __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const float p[D],
-                                                      bool active, float r2) {
+                                                      bool active, float r2, float* lds) {
   const int lane = lane_id();
+  LeafReader<D> leaf(t.rec, lds);
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   int64_t count = 0;
   uint32_t stackv = 0;                              // lane i: node of entry i
@@ -131,14 +175,13 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
     const uint64_t pm = __ballot(part);
     if (pm == 0) continue;
     if (node >= first_leaf) {
-      // the leaf's points are read at wave-uniform addresses (scalar loads,
-      // broadcast to every lane), several points in flight at a time
       const int cnt = (int)(e - b);
+      leaf.open(b, cnt);
       int c = 0;
-#pragma unroll 8
+#pragma unroll uniform_batch<D>()
       for (int i = 0; i < cnt; ++i) {
         float x[D];
-        load_rec_uniform<D>(t.rec, b + i, x);
+        leaf.point(i, x);
         c += sq_dist<D>(x, p) <= r2;
       }
       if (part) count += c;
@@ -168,11 +211,12 @@ template <int D>
 __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], int64_t pos,
                                            int32_t me, bool active, float l2, int32_t base,
                                            int32_t* __restrict__ parent,
-                                           uint32_t* __restrict__ conn) {
+                                           uint32_t* __restrict__ conn, float* lds) {
   constexpr int S = rec_stride(D);
   const int lane = lane_id();
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   const int32_t gme = base + me;
+  LeafReader<D> leaf(t.rec, lds);
   uint32_t stackv = 0;
   uint32_t stk_lo = 0xFFFFFFFFu, stk_hi = 0xFFFFFFFFu;
   int sp = 1;
@@ -215,15 +259,15 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
     const uint64_t pm = __ballot(part);
     if (pm == 0) continue;
     if (node >= first_leaf) {
-      // Friends in the leaf: distances for every lane at wave-uniform
-      // addresses (scalar loads, several in flight), then each lane links
-      // its own friends.
+      // Friends in the leaf: distances for every lane first, then each
+      // lane links its own friends.
       const int cnt = (int)(e - b);
+      leaf.open(b, cnt);
       uint64_t fr = 0;
-#pragma unroll 8
+#pragma unroll uniform_batch<D>()
       for (int i = 0; i < cnt; ++i) {
         float x[D];
-        load_rec_uniform<D>(t.rec, b + i, x);
+        leaf.point(i, x);
         fr |= (uint64_t)(sq_dist<D>(x, p) <= l2) << i;
       }
       if (!part) fr = 0;

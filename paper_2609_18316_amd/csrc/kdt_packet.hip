@@ -8,6 +8,17 @@ namespace kdt {
 
 constexpr int kPWaves = 4;  // waves per workgroup (independent packets)
 
+// LDS of a workgroup: a leaf slice per wave where leaves are staged.
+template <int D>
+size_t packet_lds_bytes(int leaf) {
+  return LeafReader<D>::kStaged ? sizeof(float) * (size_t)leaf * rec_stride(D) * kPWaves : 0;
+}
+
+template <int D>
+__device__ __forceinline__ float* wave_slice(float* lds, int wave, int leaf_cap) {
+  return LeafReader<D>::kStaged ? lds + (size_t)wave * leaf_cap * rec_stride(D) : nullptr;
+}
+
 template <int D>
 __device__ __forceinline__ bool load_query(const TreeView& t, const float* __restrict__ q,
                                            int64_t nq, const int32_t* __restrict__ order,
@@ -36,7 +47,8 @@ __global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const f
                                                              int64_t nq, int k,
                                                              const int32_t* __restrict__ order,
                                                              int32_t* __restrict__ oidx,
-                                                             float* __restrict__ od2) {
+                                                             float* __restrict__ od2, int leaf_cap) {
+  extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s0 = (xcd_block<kXcdRunPacket>() * kPWaves + wave) * 64;
   if (s0 >= nq) return;  // whole wave idle
@@ -45,7 +57,7 @@ __global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const f
   const bool active = load_query<D>(t, q, nq, order, s0 + lane, p, row);
   TopK<KC> best;
   best.init(k);
-  packet_knn<D, KC>(t, p, active, best);
+  packet_knn<D, KC>(t, p, active, best, wave_slice<D>(lds, wave, leaf_cap));
   if (active) knn_write<KC>(best, k, MODE, row, oidx, od2);
 }
 
@@ -53,21 +65,25 @@ template <int D>
 __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const float* __restrict__ q,
                                                                int64_t nq, float r2,
                                                                const int32_t* __restrict__ order,
-                                                               int32_t* __restrict__ count) {
+                                                               int32_t* __restrict__ count,
+                                                               int leaf_cap) {
+  extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s0 = (xcd_block<kXcdRunPacket>() * kPWaves + wave) * 64;
   if (s0 >= nq) return;
   float p[D];
   int64_t row = 0;
   const bool active = load_query<D>(t, q, nq, order, s0 + lane, p, row);
-  const int64_t c = packet_range_count<D>(t, p, active, r2);
+  const int64_t c = packet_range_count<D>(t, p, active, r2, wave_slice<D>(lds, wave, leaf_cap));
   if (active) count[row] = (int32_t)c;
 }
 
 template <int D>
 __global__ __launch_bounds__(64 * kPWaves) void k_fof_packet(TreeView t, float l2,
                                                              int32_t* __restrict__ parent,
-                                                             uint32_t* __restrict__ conn) {
+                                                             uint32_t* __restrict__ conn,
+                                                             int leaf_cap) {
+  extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s0 = (xcd_block<kXcdRunFof>() * kPWaves + wave) * 64;
   if (s0 >= t.n) return;
@@ -81,15 +97,15 @@ __global__ __launch_bounds__(64 * kPWaves) void k_fof_packet(TreeView t, float l
 #pragma unroll
     for (int a = 0; a < D; ++a) p[a] = 0.0f;
   }
-  packet_fof<D>(t, p, pos, me, active, l2, 0, parent, conn);
+  packet_fof<D>(t, p, pos, me, active, l2, 0, parent, conn, wave_slice<D>(lds, wave, leaf_cap));
 }
 
 template <int D>
 kdt_status fof_packet_launch(const TreeView& v, int leaf, float l2, int32_t* parent, uint32_t* conn,
                              hipStream_t stream) {
   const unsigned grid = (unsigned)((v.n + 64 * kPWaves - 1) / (64 * kPWaves));
-  (void)leaf;
-  k_fof_packet<D><<<grid, 64 * kPWaves, 0, stream>>>(v, l2, parent, conn);
+  k_fof_packet<D><<<grid, 64 * kPWaves, packet_lds_bytes<D>(leaf), stream>>>(v, l2, parent, conn,
+                                                                            leaf);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_fof: packet kernel launch failed");
     return KDT_EDEVICE;
@@ -102,9 +118,10 @@ kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int6
                              int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
                              hipStream_t stream) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
-  (void)leaf;
-#define KDT_LAUNCH(KC, M) \
-  k_knn_packet<D, KC, M><<<grid, 64 * kPWaves, 0, stream>>>(v, d_q, nq, k, order, d_idx, d_d2)
+  const size_t smem = packet_lds_bytes<D>(leaf);
+#define KDT_LAUNCH(KC, M)                                                                      \
+  k_knn_packet<D, KC, M><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, d_idx, d_d2, \
+                                                               leaf)
 #define KDT_BY_MODE(KC)          \
   if (mode == 0) KDT_LAUNCH(KC, 0); \
   else if (mode == 1) KDT_LAUNCH(KC, 1); \
@@ -131,8 +148,8 @@ template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
                                const int32_t* order, int32_t* d_count, hipStream_t stream) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
-  (void)leaf;
-  k_range_packet<D><<<grid, 64 * kPWaves, 0, stream>>>(v, d_q, nq, r2, order, d_count);
+  k_range_packet<D><<<grid, 64 * kPWaves, packet_lds_bytes<D>(leaf), stream>>>(v, d_q, nq, r2,
+                                                                              order, d_count, leaf);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_range: packet kernel launch failed");
     return KDT_EDEVICE;

@@ -121,6 +121,13 @@ __device__ __forceinline__ void load_box_uniform(const float* box, uint32_t node
   }
 }
 
+// Leaf points a wave-uniform scan keeps in flight: their coordinates live in
+// scalar registers, about 32 of them.
+template <int D>
+constexpr int uniform_batch() {
+  return D <= 4 ? 8 : (32 / D > 0 ? 32 / D : 1);
+}
+
 // Coordinates of tree record i read at a wave-uniform address.
 template <int D>
 __device__ __forceinline__ void load_rec_uniform(const float* rec, int64_t i, float x[D]) {
