@@ -49,11 +49,11 @@ BATCH_SETS = 256
 # is given; for any other source they are not reported.
 KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
-                "paper_2609_18316_amd/csrc/kdt_internal.h"],
-    "sha256": None,
-    "hbm_bytes": None,
-    "l2_hit_rate": None,
-    "valu_issue_frac": None,
+                "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
+    "sha256": "720f33e128f2e831bdc3073d07018af3ee771334490b2e96a14af8222f88125f",
+    "hbm_bytes": 2.1446e+09,
+    "l2_hit_rate": 0.964,
+    "valu_issue_frac": 0.76,
 }
 
 
@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=1 << 14)
     ap.add_argument("--no-dsweep", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy of 1 GiB (read once, written once), the "
+                         "reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes")
     return ap.parse_args()
 
 
@@ -150,6 +153,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
+        return
     kdt.load()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
