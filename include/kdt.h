@@ -148,6 +148,8 @@ kdt_status kdt_tree_export(const kdt_tree *tree, float *h_pts, int32_t *h_perm, 
  *          2: write only the k-th distance sqrt(d2_k), d_d2 [nq] (an SPH
  *             smoothing length, Sec. 4.2).
  * Rows of a tree with fewer than k points are padded with (-1, +inf).
+ * nq = 0 is an empty query set: nothing is read or written and every
+ * pointer may be NULL (k and kth_only are still checked).
  * opts   may be NULL (sort_queries = 1).
  *
  * Errors: KDT_EINVAL, KDT_EUNSUPPORTED (k), KDT_ENOMEM, KDT_EDEVICE.
@@ -170,6 +172,8 @@ kdt_status kdt_knn(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t k
  *           This mode waits on `stream` once to learn the total size.
  * capacity  number of int32 slots in d_idx.
  * required  host, may be NULL: receives the total list length (list mode).
+ * nq = 0 is an empty query set: d_q and d_count may be NULL; d_offsets, if
+ * given, receives its single 0 and *required 0.
  *
  * Errors: KDT_EINVAL, KDT_ECAPACITY (total > capacity; *required is set and
  * d_count / d_offsets are valid), KDT_ENOMEM, KDT_EDEVICE.
@@ -205,11 +209,16 @@ kdt_status kdt_fof(const kdt_tree *tree, float l, int32_t *d_labels, int64_t *n_
  * d_order [n] int32 or NULL: visiting order of the particles (for example the
  * tree order from kdt_tree_perm); it only changes speed and rounding order.
  * d_grid [n0*n1*n2] float32: overwritten with the mass per cell.  The sums are
- * accumulated in float64 and rounded once.
+ * accumulated in float64 and rounded once (the float64 summation order
+ * follows the scheduling, a difference far below the float32 rounding).
+ * n = 0 writes an all-zero mesh (the particle pointers may then be NULL).
+ * The call waits on `stream` once, after the first pass, to read the
+ * per-tile particle counts that size its lists (and the validity flag), and
+ * again at the end; its buffers come from the stream-ordered pool.
  *
- * Errors: KDT_EINVAL (NULL pointer, bad grid, particle outside the box -- the
- * latter is detected on the device and reported by a wait at the end),
- * KDT_ENOMEM, KDT_EDEVICE.
+ * Errors: KDT_EINVAL (NULL pointer, bad grid, particle outside the box or an
+ * invalid h -- detected on the device), KDT_EUNSUPPORTED (n >= 2^31 or a mesh
+ * of more than 2^30 tiles of 16^3 cells), KDT_ENOMEM, KDT_EDEVICE.
  */
 kdt_status kdt_p2m(const float *d_x, const float *d_m, const float *d_h, int64_t n,
                    const kdt_grid *grid, const int32_t *d_order, float *d_grid,
@@ -223,7 +232,10 @@ kdt_status kdt_p2m(const float *d_x, const float *d_m, const float *d_h, int64_t
  * in-grid cells, grad w = w'(q) (2 / H_i) (x_i - x_c) / r.  The weights are
  * recomputed, nothing per (particle, cell) is stored.
  * d_ggrid [cells] float32 upstream gradient.  d_gm [n], d_gx [n][3] float32
- * outputs, either may be NULL.  Other arguments as kdt_p2m.
+ * outputs, either may be NULL.  One lane per particle gathers in a fixed
+ * order, so the result is reproducible.  Other arguments as kdt_p2m (n = 0:
+ * nothing to do, pointers may be NULL); waits on `stream` at the end for the
+ * validity flag.
  */
 kdt_status kdt_p2m_backward(const float *d_x, const float *d_m, const float *d_h, int64_t n,
                             const kdt_grid *grid, const int32_t *d_order,
@@ -241,7 +253,8 @@ kdt_status kdt_p2m_backward(const float *d_x, const float *d_m, const float *d_h
  *   nearer child at every level -- the order the wave-shared traversals (ball
  *   counts, wave-packet kNN) use.
  * Results of the queries never depend on the order, only their speed.
- * Errors: KDT_EINVAL (NULL pointer, nq outside [1, 2^31-1], other kind),
+ * nq = 0 does nothing (pointers may be NULL).
+ * Errors: KDT_EINVAL (NULL pointer, nq outside [0, 2^31-1], other kind),
  * KDT_ENOMEM, KDT_EDEVICE.
  */
 kdt_status kdt_query_order(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t kind,
@@ -255,7 +268,8 @@ const int32_t *kdt_tree_perm(const kdt_tree *tree);
  * Batched mode: many independent point sets of uneven size, concatenated.
  *
  * kdt_batch_plan_create fixes the shapes on the host: h_offsets [n_sets+1]
- * (host, int64, set s owns rows h_offsets[s] .. h_offsets[s+1]), d, k, and the
+ * (host, int64, set s owns rows h_offsets[s] .. h_offsets[s+1], every set at
+ * least one point, KDT_EINVAL otherwise), d, k, and the
  * options.  It allocates every buffer the pipeline needs, so a launch
  * allocates nothing.
  *

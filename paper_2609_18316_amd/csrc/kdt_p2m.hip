@@ -456,7 +456,7 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
                               const kdt_grid* grid, const int32_t* d_order, float* d_grid,
                               hipStream_t stream) {
   kdt_clear_error();
-  if (!d_x || !d_m || !d_h || !d_grid || n < 0 || !grid_ok(grid)) {
+  if (!d_grid || n < 0 || !grid_ok(grid) || (n > 0 && (!d_x || !d_m || !d_h))) {
     kdt_set_error("kdt_p2m: NULL pointer, negative n or invalid grid");
     return KDT_EINVAL;
   }
@@ -591,7 +591,7 @@ extern "C" kdt_status kdt_p2m_backward(const float* d_x, const float* d_m, const
                                        const float* d_ggrid, float* d_gm, float* d_gx,
                                        hipStream_t stream) {
   kdt_clear_error();
-  if (!d_x || !d_m || !d_h || !d_ggrid || n < 0 || !grid_ok(grid)) {
+  if (n < 0 || !grid_ok(grid) || (n > 0 && (!d_x || !d_m || !d_h || !d_ggrid))) {
     kdt_set_error("kdt_p2m_backward: NULL pointer, negative n or invalid grid");
     return KDT_EINVAL;
   }

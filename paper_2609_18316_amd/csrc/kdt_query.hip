@@ -416,8 +416,13 @@ using namespace kdt;
 extern "C" kdt_status kdt_query_order(const kdt_tree* tree, const float* d_q, int64_t nq,
                                       int32_t kind, int32_t* d_order, hipStream_t stream) {
   kdt_clear_error();
-  if (!tree || !d_q || !d_order || nq < 1 || nq > INT32_MAX || (kind != 0 && kind != 1)) {
-    kdt_set_error("kdt_query_order: NULL argument, nq outside [1, 2^31-1] or kind not 0 or 1");
+  if (!tree || nq < 0 || nq > INT32_MAX || (kind != 0 && kind != 1)) {
+    kdt_set_error("kdt_query_order: NULL tree, nq outside [0, 2^31-1] or kind not 0 or 1");
+    return KDT_EINVAL;
+  }
+  if (nq == 0) return KDT_OK;
+  if (!d_q || !d_order) {
+    kdt_set_error("kdt_query_order: NULL queries or order");
     return KDT_EINVAL;
   }
   switch (tree->d) {
@@ -435,8 +440,8 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
                               int32_t* d_idx, float* d_d2, int32_t kth_only,
                               const kdt_query_opts* opts, hipStream_t stream) {
   kdt_clear_error();
-  if (!tree || !d_d2 || nq < 0) {
-    kdt_set_error("kdt_knn: NULL tree or output, or negative nq");
+  if (!tree || nq < 0) {
+    kdt_set_error("kdt_knn: NULL tree or negative nq");
     return KDT_EINVAL;
   }
   if (k < 1 || k > KDT_MAX_K) {
@@ -447,11 +452,15 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
     kdt_set_error("kdt_knn: kth_only must be 0, 1 or 2");
     return KDT_EINVAL;
   }
+  if (nq == 0) return KDT_OK;  // no queries: nothing is read or written
+  if (!d_d2) {
+    kdt_set_error("kdt_knn: NULL d_d2");
+    return KDT_EINVAL;
+  }
   if (!d_q && nq != tree->n) {
     kdt_set_error("kdt_knn: self queries need nq == n (%lld)", (long long)tree->n);
     return KDT_EINVAL;
   }
-  if (nq == 0) return KDT_OK;
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
   const int trav = opts ? opts->traversal : 0;
   const int32_t* given = opts ? opts->order : nullptr;
@@ -475,11 +484,15 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
                                 int64_t capacity, int64_t* required, const kdt_query_opts* opts,
                                 hipStream_t stream) {
   kdt_clear_error();
-  if (!tree || !d_count || nq < 0 || !(r >= 0.0f) || !std::isfinite(r)) {
-    kdt_set_error("kdt_range: NULL tree or count, negative nq, or r not finite and >= 0");
+  if (!tree || nq < 0 || !(r >= 0.0f) || !std::isfinite(r)) {
+    kdt_set_error("kdt_range: NULL tree, negative nq, or r not finite and >= 0");
     return KDT_EINVAL;
   }
-  if (!d_q && nq != tree->n) {
+  if (!d_count && nq > 0) {
+    kdt_set_error("kdt_range: NULL d_count");
+    return KDT_EINVAL;
+  }
+  if (!d_q && nq > 0 && nq != tree->n) {
     kdt_set_error("kdt_range: self queries need nq == n (%lld)", (long long)tree->n);
     return KDT_EINVAL;
   }
