@@ -121,12 +121,18 @@ def test_deposit_full_size_subvolume_and_adjoint_sample(clustered):
 @pytest.mark.parametrize("d", (2, 4, 8, 16))
 @pytest.mark.parametrize("dist", ("uniform", "normal"))
 def test_dimension_sweep_full_size_sampled(d, dist):
+    """The bench's configuration: leaf size and traversal from the autotuner's
+    table, every point as a query."""
+    from paper_2609_18316_amd import autotune
     dev()
     n = 1 << 22
     x = workloads.uniform(n, d, 300 + d) if dist == "uniform" else workloads.normal(n, d, 400 + d)
-    say(f"dimension sweep d={d} {dist}: build + self kNN k=16")
-    t = kdt.build(to_dev(x), leaf_size=32)
-    idx, d2 = t.knn(None, 16)
+    c = autotune.lookup(n, d, 16, f"self-{dist}")
+    trav = 2 if c.queries_per_wave == 64 else 1
+    say(f"dimension sweep d={d} {dist}: leaf {c.leaf_size}, traversal {trav}, kNN k=16")
+    xt = to_dev(x)
+    t = kdt.build(xt, leaf_size=c.leaf_size)
+    idx, d2 = t.knn(None, 16, traversal=trav)
     idx, d2 = to_host(idx), to_host(d2)
     s = workloads.sample_indices(n, 48 if d >= 8 else 256, seed=13 + d)
     if d <= 4:
