@@ -216,6 +216,7 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
   const int lane = lane_id();
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   const int32_t gme = base + me;
+  int32_t myroot = gme;  // an ancestor of this lane's point (see uf_union_from)
   LeafReader<D> leaf(t.rec, lds);
   uint32_t stackv = 0;
   uint32_t stk_lo = 0xFFFFFFFFu, stk_hi = 0xFFFFFFFFu;
@@ -237,21 +238,23 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
     const bool one = flag_ld(conn + node) != 0;
     if (one && touch) {
       const bool inside = pos >= b && pos < e;
-      touch = !inside && uf_find(parent, gme) != uf_find(parent, gfirst);
+      if (!inside) myroot = uf_find(parent, myroot);
+      touch = !inside && myroot != uf_find(parent, gfirst);
     }
     if (!__any(touch)) continue;
     const bool full = touch && box_maxdist<D>(lo, hi, p) <= l2;
     if (one) {
-      if (full) uf_union(parent, gme, gfirst);
+      if (full) uf_union_from(parent, myroot, gfirst);
     } else {
       const uint64_t fm = __ballot(full);
       if (fm != 0) {
         const int leader = __ffsll((unsigned long long)fm) - 1;
         if (lane == leader) {
-          for (int64_t i = b; i < e; ++i) uf_union(parent, gme, base + __float_as_int(t.rec[i * S + D]));
+          for (int64_t i = b; i < e; ++i)
+            uf_union_from(parent, myroot, base + __float_as_int(t.rec[i * S + D]));
           flag_st(conn + node, 1u);
         } else if (full) {
-          uf_union(parent, gme, gfirst);
+          uf_union_from(parent, myroot, gfirst);
         }
       }
     }
@@ -276,10 +279,10 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
         fr &= fr - 1;
         const int32_t id = __float_as_int(t.rec[(b + i) * S + D]);
         if (one) {
-          uf_union(parent, gme, base + id);
+          uf_union_from(parent, myroot, base + id);
           break;
         }
-        if (id > me) uf_union(parent, gme, base + id);
+        if (id > me) uf_union_from(parent, myroot, base + id);
       }
     } else {
       const uint32_t mlo = (uint32_t)pm, mhi = (uint32_t)(pm >> 32);

@@ -306,10 +306,21 @@ __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
   return cur;
 }
 
-// Joins the sets of a and b: the larger root is hooked under the smaller, so
-// every root is the smallest index of its set.
-__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
-  int32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+// Joins the set of the element whose known ancestor is `a` (updated to an
+// ancestor of the joined set's root) with the set of b: the larger root is
+// hooked under the smaller, so every root is the smallest index of its set.
+// A root found once stays an ancestor of its elements after it is hooked
+// (only roots change parent), so a lane that links one point many times
+// keeps its last root in `a` and starts every search there.
+//
+// Two elements that share any ancestor are in one set, so when b is a or b's
+// parent is a (the usual case once paths are compressed) nothing is left to
+// do after a single load.
+__device__ __forceinline__ void uf_union_from(int32_t* parent, int32_t& a, int32_t b) {
+  if (b == a) return;
+  const int32_t pb = uf_ld(parent + b);
+  if (pb == a) return;
+  int32_t ra = uf_find(parent, a), rb = pb == b ? b : uf_find(parent, pb);
   while (ra != rb) {
     if (ra < rb) {
       const int32_t old = atomicCAS(parent + rb, rb, ra);
@@ -317,10 +328,19 @@ __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) 
       rb = old;
     } else {
       const int32_t old = atomicCAS(parent + ra, ra, rb);
-      if (old == ra) break;
+      if (old == ra) {
+        ra = rb;
+        break;
+      }
       ra = old;
     }
   }
+  a = ra;
+}
+
+// Joins the sets of a and b.
+__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+  uf_union_from(parent, a, b);
 }
 
 // Squared diagonal of a box: every pair of points inside is at most this far
@@ -358,6 +378,7 @@ __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], i
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   int sp = 1;
   stk[0] = 0;
+  int32_t myroot = base + me;  // an ancestor of p's set root (see uf_union_from)
   int guard = -1;  // stack depth where the current one-component region began
   while (sp > 0) {
     --sp;
@@ -374,13 +395,14 @@ __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], i
     if (one && pos >= b && pos < e) continue;  // p is already in this component
     if (box_maxdist<D>(lo, hi, p) <= l2) {
       if (one) {
-        uf_union(parent, base + me, base + __float_as_int(t.rec[b * S + D]));
+        uf_union_from(parent, myroot, base + __float_as_int(t.rec[b * S + D]));
         if (in_region) {
           sp = guard;
           guard = -1;
         }
       } else {
-        for (int64_t i = b; i < e; ++i) uf_union(parent, base + me, base + __float_as_int(t.rec[i * S + D]));
+        for (int64_t i = b; i < e; ++i)
+          uf_union_from(parent, myroot, base + __float_as_int(t.rec[i * S + D]));
         flag_st(conn + node, 1u);
       }
       continue;
@@ -392,14 +414,14 @@ __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], i
         load_rec<D>(t.rec, i, x, id);
         if (sq_dist<D>(x, p) > l2) continue;
         if (one) {
-          uf_union(parent, base + me, base + id);
+          uf_union_from(parent, myroot, base + id);
           if (in_region) {
             sp = guard;
             guard = -1;
           }
           break;
         }
-        if (id > me) uf_union(parent, base + me, base + id);
+        if (id > me) uf_union_from(parent, myroot, base + id);
       }
       continue;
     }
