@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_knn_forest_packet(
     int32_t* __restrict__ oidx, float* __restrict__ od2, unsigned long long* __restrict__ ctr) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  float* slice = LeafReader<D>::kStaged ? lds + (size_t)wave * leaf_cap * rec_stride(D) : nullptr;
+  float* slice = lds + (size_t)wave * leaf_cap * rec_stride(D);
   const int64_t n_packets = pbase[n_sets];
   for (;;) {
     unsigned long long got = 0;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_fof_forest_packet(
     uint32_t* __restrict__ conn, unsigned long long* __restrict__ ctr) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  float* slice = LeafReader<D>::kStaged ? lds + (size_t)wave * leaf_cap * rec_stride(D) : nullptr;
+  float* slice = lds + (size_t)wave * leaf_cap * rec_stride(D);
   const int64_t n_packets = pbase[n_sets];
   for (;;) {
     unsigned long long got = 0;
@@ -264,11 +264,11 @@ struct kdt_batch_plan {
   const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
-// LDS of a 4-wave workgroup of the forest packet kernels (leaf slices where
-// leaves are staged).
+// LDS of a 4-wave workgroup of the forest packet kernels (a leaf slice per
+// wave).
 template <int D>
 static size_t forest_lds_bytes(int leaf) {
-  return LeafReader<D>::kStaged ? sizeof(float) * (size_t)leaf * rec_stride(D) * 4 : 0;
+  return sizeof(float) * (size_t)leaf * rec_stride(D) * 4;
 }
 
 template <int D, int KC>

@@ -8,15 +8,15 @@ namespace kdt {
 
 constexpr int kPWaves = 4;  // waves per workgroup (independent packets)
 
-// LDS of a workgroup: a leaf slice per wave where leaves are staged.
+// LDS of a workgroup: a leaf slice per wave.
 template <int D>
 size_t packet_lds_bytes(int leaf) {
-  return LeafReader<D>::kStaged ? sizeof(float) * (size_t)leaf * rec_stride(D) * kPWaves : 0;
+  return sizeof(float) * (size_t)leaf * rec_stride(D) * kPWaves;
 }
 
 template <int D>
 __device__ __forceinline__ float* wave_slice(float* lds, int wave, int leaf_cap) {
-  return LeafReader<D>::kStaged ? lds + (size_t)wave * leaf_cap * rec_stride(D) : nullptr;
+  return lds + (size_t)wave * leaf_cap * rec_stride(D);
 }
 
 template <int D>

@@ -101,8 +101,8 @@ __device__ __forceinline__ void load_rec(const float* __restrict__ rec, int64_t 
 }
 
 // Reads of wave-uniform addresses in data that no kernel writes while it
-// runs (tree records and boxes): through the constant address space, so
-// the compiler issues scalar loads, several in flight and shared by the wave.
+// runs (node boxes): through the constant address space, so the compiler
+// issues scalar loads, one per wave.
 typedef const __attribute__((address_space(4))) float cfloat;
 __device__ __forceinline__ const cfloat* as_uniform(const float* p) {
   return (const cfloat*)p;
@@ -121,19 +121,10 @@ __device__ __forceinline__ void load_box_uniform(const float* box, uint32_t node
   }
 }
 
-// Leaf points a wave-uniform scan keeps in flight: their coordinates live in
-// scalar registers, about 32 of them.
+// Leaf points a wave-uniform scan keeps in flight (a loop unroll factor).
 template <int D>
 constexpr int uniform_batch() {
   return D <= 4 ? 8 : (32 / D > 0 ? 32 / D : 1);
-}
-
-// Coordinates of tree record i read at a wave-uniform address.
-template <int D>
-__device__ __forceinline__ void load_rec_uniform(const float* rec, int64_t i, float x[D]) {
-  const cfloat* r = as_uniform(rec) + i * rec_stride(D);
-#pragma unroll
-  for (int a = 0; a < D; ++a) x[a] = r[a];
 }
 
 // Key of an empty candidate slot: squared distance +inf, index 0xFFFFFFFF, so
