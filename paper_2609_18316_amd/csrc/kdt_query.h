@@ -189,6 +189,9 @@ template <int D, int KC>
 __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], TopK<KC>& best,
                                         uint32_t* stk, int ld) {
   const uint32_t first_leaf = (1u << t.levels) - 1u;
+  // leaf sizes: floor(n / 2^L) or one more
+  const int lmin = (int)(t.n >> t.levels);
+  const int lmax = (int)((t.n + (int64_t(1) << t.levels) - 1) >> t.levels);
   float lo[D], hi[D];
   load_box<D>(t.box, 0, lo, hi);
   uint32_t node = 0;
@@ -208,14 +211,35 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Top
         // largest number of insertions of one lane in this leaf, not for
         // every position at which some lane inserts.
         for (int64_t c = b; c < e; c += 64) {
-          const int m = (int)((e - c) < 64 ? (e - c) : 64);
           const float w = best.worst_d2();
           uint64_t mask = 0;
-          for (int i = 0; i < m; ++i) {
-            float x[D];
-            int32_t id = 0;
-            load_rec<D>(t.rec, c + i, x, id);
-            if (sq_dist<D>(x, p) <= w) mask |= 1ull << i;
+          if (lmax <= 32) {
+            // Every leaf holds lmin or lmin + 1 points: the first lmin are
+            // scanned with a wave-uniform trip count, the possible last one
+            // on its own (one block: e - b <= 32).
+            uint32_t m32 = 0;
+#pragma unroll 1  // unrolling costs occupancy (measured slower at k = 32)
+            for (int i = 0; i < lmin; ++i) {
+              float x[D];
+              int32_t id = 0;
+              load_rec<D>(t.rec, b + i, x, id);
+              m32 |= (uint32_t)(sq_dist<D>(x, p) <= w) << i;
+            }
+            if (e - b > lmin) {
+              float x[D];
+              int32_t id = 0;
+              load_rec<D>(t.rec, b + lmin, x, id);
+              m32 |= (uint32_t)(sq_dist<D>(x, p) <= w) << lmin;
+            }
+            mask = m32;
+          } else {
+            const int m = (int)((e - c) < 64 ? (e - c) : 64);
+            for (int i = 0; i < m; ++i) {
+              float x[D];
+              int32_t id = 0;
+              load_rec<D>(t.rec, c + i, x, id);
+              if (sq_dist<D>(x, p) <= w) mask |= 1ull << i;
+            }
           }
           while (mask) {
             const int i = __builtin_ctzll(mask);
