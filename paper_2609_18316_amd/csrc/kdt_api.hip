@@ -31,16 +31,25 @@ namespace kdt {
 
 // Build schedules depend only on (device, n, d, leaf); repeated builds of the
 // same shape reuse the uploaded tables.
+// The device tables are released with the last reference (hipFree waits for
+// the device, so a build still reading them finishes first).
 struct CachedPlan {
   int device;
   int64_t n;
   int d, leaf;
   Plan plan;
   PlanDev dev;
+  CachedPlan() = default;
+  CachedPlan(const CachedPlan&) = delete;
+  CachedPlan& operator=(const CachedPlan&) = delete;
+  ~CachedPlan() { plan_release(dev); }
 };
 
 static std::mutex g_plan_mu;
-static std::list<std::shared_ptr<CachedPlan>> g_plans;
+// Never destroyed: releasing device memory from static destructors at process
+// exit could run after the HIP runtime has shut down.
+static std::list<std::shared_ptr<CachedPlan>>& g_plans =
+    *new std::list<std::shared_ptr<CachedPlan>>();
 constexpr size_t kPlanCache = 512;
 
 static kdt_status get_plan(int device, int64_t n, int d, int leaf, hipStream_t stream,
@@ -67,15 +76,9 @@ static kdt_status get_plan(int device, int64_t n, int d, int leaf, hipStream_t s
   kdt_status st = plan_upload(cp->plan, cp->dev, stream);
   if (st != KDT_OK) return st;
   g_plans.push_front(cp);
-  while (g_plans.size() > kPlanCache) {
-    // a plan still referenced by a running build stays alive through `out`
-    std::shared_ptr<CachedPlan> victim = g_plans.back();
-    g_plans.pop_back();
-    if (victim.use_count() == 1) {
-      (void)hipDeviceSynchronize();
-      plan_release(victim->dev);
-    }
-  }
+  // the oldest plans leave the cache; one still held by a running build is
+  // released when that build drops it
+  while (g_plans.size() > kPlanCache) g_plans.pop_back();
   out = cp;
   return KDT_OK;
 }

@@ -130,21 +130,22 @@ extern "C" kdt_status kdt_fof(const kdt_tree* tree, float l, int32_t* d_labels, 
     hipcub::CountingInputIterator<int64_t> ci(0);
     hipcub::TransformInputIterator<int64_t, IsRoot, hipcub::CountingInputIterator<int64_t>> roots(
         ci, IsRoot{d_labels});
+    PoolBuffers buf(stream);
     int64_t* d_out = nullptr;
-    void* tmp = nullptr;
+    char* tmp = nullptr;
     size_t tb = 0;
-    hipcub::DeviceReduce::Sum(nullptr, tb, roots, d_out, (int)n, stream);
-    if (hipMallocAsync((void**)&d_out, sizeof(int64_t), stream) != hipSuccess ||
-        hipMallocAsync(&tmp, tb > 0 ? tb : 16, stream) != hipSuccess) {
+    if (hipcub::DeviceReduce::Sum(nullptr, tb, roots, d_out, (int)n, stream) != hipSuccess) {
+      kdt_set_error("kdt_fof: group count setup failed");
+      return KDT_EDEVICE;
+    }
+    if (!buf.get(&d_out, 1) || !buf.get(&tmp, tb)) {
       kdt_set_error("kdt_fof: device allocation failed");
       return KDT_ENOMEM;
     }
-    hipcub::DeviceReduce::Sum(tmp, tb, roots, d_out, (int)n, stream);
     int64_t h = 0;
-    hipError_t e1 = hipMemcpyAsync(&h, d_out, sizeof(h), hipMemcpyDeviceToHost, stream);
-    (void)hipFreeAsync(tmp, stream);
-    (void)hipFreeAsync(d_out, stream);
-    if (e1 != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+    if (hipcub::DeviceReduce::Sum(tmp, tb, roots, d_out, (int)n, stream) != hipSuccess ||
+        hipMemcpyAsync(&h, d_out, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
       kdt_set_error("kdt_fof: counting groups failed");
       return KDT_EDEVICE;
     }

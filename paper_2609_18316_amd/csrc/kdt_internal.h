@@ -211,6 +211,37 @@ kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
 // Stream-ordered device allocation from the default pool (kept cached).
 hipError_t dev_alloc(void** ptr, size_t bytes, hipStream_t stream);
 
+// Stream-ordered scratch buffers of one call, released in stream order when
+// the holder goes out of scope -- on every return path, errors included.
+class PoolBuffers {
+ public:
+  explicit PoolBuffers(hipStream_t s) : stream_(s) {}
+  PoolBuffers(const PoolBuffers&) = delete;
+  PoolBuffers& operator=(const PoolBuffers&) = delete;
+  ~PoolBuffers() {
+    for (void* q : held_)
+      if (q) (void)hipFreeAsync(q, stream_);
+  }
+  // count elements of T (at least one); false if the pool is exhausted
+  template <typename T>
+  bool get(T** p, size_t count) {
+    void* q = nullptr;
+    if (dev_alloc(&q, (count > 0 ? count : 1) * sizeof(T), stream_) != hipSuccess) return false;
+    held_.push_back(q);
+    *p = static_cast<T*>(q);
+    return true;
+  }
+  // Hands a buffer over to the caller: it is no longer released here.
+  void keep(const void* p) {
+    for (void*& q : held_)
+      if (q == p) q = nullptr;
+  }
+
+ private:
+  hipStream_t stream_;
+  std::vector<void*> held_;
+};
+
 }  // namespace kdt
 
 // Library-owned tree.

@@ -409,11 +409,11 @@ static GridDev to_dev(const kdt_grid* g) {
 
 using namespace kdt;
 
-static kdt_status finish_bad_check(int32_t* d_bad, hipStream_t stream, const char* who) {
+// Waits for the stream and reports the device-side validity flag.
+static kdt_status read_bad_flag(const int32_t* d_bad, hipStream_t stream, const char* who) {
   int32_t bad = 0;
   hipError_t e = hipMemcpyAsync(&bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  (void)hipFreeAsync(d_bad, stream);
   if (e != hipSuccess) {
     kdt_set_error("%s: %s", who, hipGetErrorString(e));
     return KDT_EDEVICE;
@@ -426,24 +426,6 @@ static kdt_status finish_bad_check(int32_t* d_bad, hipStream_t stream, const cha
 }
 
 namespace {
-
-// Device buffers of one forward call, released in stream order.
-struct FwdBuffers {
-  hipStream_t stream;
-  std::vector<void*> held;
-  explicit FwdBuffers(hipStream_t s) : stream(s) {}
-  template <typename T>
-  bool get(T** p, size_t count) {
-    void* q = nullptr;
-    if (hipMallocAsync(&q, std::max<size_t>(count, 1) * sizeof(T), stream) != hipSuccess) return false;
-    held.push_back(q);
-    *p = static_cast<T*>(q);
-    return true;
-  }
-  ~FwdBuffers() {
-    for (void* q : held) (void)hipFreeAsync(q, stream);
-  }
-};
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -475,7 +457,7 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
     kdt_set_error("kdt_p2m: mesh too large (%lld tiles of %d^3 cells)", (long long)n_tiles, kT);
     return KDT_EUNSUPPORTED;
   }
-  FwdBuffers buf(stream);
+  PoolBuffers buf(stream);
   float* fbuf = nullptr;
   uint32_t* tcount = nullptr;
   int32_t* bad = nullptr;
@@ -595,18 +577,19 @@ extern "C" kdt_status kdt_p2m_backward(const float* d_x, const float* d_m, const
     kdt_set_error("kdt_p2m_backward: NULL pointer, negative n or invalid grid");
     return KDT_EINVAL;
   }
+  if (n == 0 || (!d_gm && !d_gx)) return KDT_OK;
+  PoolBuffers buf(stream);
   int32_t* bad = nullptr;
-  if (hipMallocAsync((void**)&bad, 256, stream) != hipSuccess) {
+  if (!buf.get(&bad, 64)) {
     kdt_set_error("kdt_p2m_backward: allocation failed");
     return KDT_ENOMEM;
   }
   k_zero_f64<<<1, 32, 0, stream>>>(reinterpret_cast<double*>(bad), 1);
-  if (n > 0 && (d_gm || d_gx))
-    k_p2m_bwd<<<(unsigned)((n + kPBlock - 1) / kPBlock), kPBlock, 0, stream>>>(
-        to_dev(grid), d_x, d_m, d_h, n, d_order, d_ggrid, d_gm, d_gx, bad);
+  k_p2m_bwd<<<(unsigned)((n + kPBlock - 1) / kPBlock), kPBlock, 0, stream>>>(
+      to_dev(grid), d_x, d_m, d_h, n, d_order, d_ggrid, d_gm, d_gx, bad);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_p2m_backward: kernel launch failed");
     return KDT_EDEVICE;
   }
-  return finish_bad_check(bad, stream, "kdt_p2m_backward");
+  return read_bad_flag(bad, stream, "kdt_p2m_backward");
 }

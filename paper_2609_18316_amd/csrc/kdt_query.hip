@@ -244,36 +244,33 @@ static kdt_status order_queries(const kdt_tree* t, const float* d_q, int64_t nq,
     kdt_set_error("query reordering supports at most 2^31-1 queries");
     return KDT_EINVAL;
   }
+  PoolBuffers buf(stream);
   uint32_t *k0 = nullptr, *k1 = nullptr;
-  int32_t *v0 = nullptr, *v1 = nullptr;
+  int32_t *v0 = nullptr, *v1 = dst;
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
   // up to 4 dimensions a Hilbert key over the root box; above, the leaf
   // reached by descending towards the nearer child
   const bool hilbert = D <= 4 && kind == 0;
   const int end_bit = hilbert ? (30 / D) * D : std::max(1, t->levels + 1);
-  hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k0, k1, v0, v1, (int)nq, 0, end_bit, stream);
-  const size_t nb = sizeof(uint32_t) * (size_t)nq;
-  if (hipMallocAsync((void**)&k0, nb, stream) != hipSuccess ||
-      hipMallocAsync((void**)&k1, nb, stream) != hipSuccess ||
-      hipMallocAsync((void**)&v0, nb, stream) != hipSuccess ||
-      (!dst && hipMallocAsync((void**)&v1, nb, stream) != hipSuccess) ||
-      hipMallocAsync(&tmp, std::max<size_t>(tmp_bytes, 16), stream) != hipSuccess) {
+  KDT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k0, k1, v0, v1, (int)nq, 0,
+                                             end_bit, stream));
+  if (!buf.get(&k0, (size_t)nq) || !buf.get(&k1, (size_t)nq) || !buf.get(&v0, (size_t)nq) ||
+      (!dst && !buf.get(&v1, (size_t)nq)) || !buf.get((char**)&tmp, tmp_bytes)) {
     kdt_set_error("device allocation failed for query ordering");
     return KDT_ENOMEM;
   }
-  if (dst) v1 = dst;
   if (hilbert)
     k_query_hilbert<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq, k0, v0);
   else
     k_query_leaf<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq, k0, v0);
+  KDT_HIP(hipGetLastError());
   KDT_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k0, k1, v0, v1, (int)nq, 0, end_bit,
                                              stream));
-  (void)hipFreeAsync(k0, stream);
-  (void)hipFreeAsync(k1, stream);
-  (void)hipFreeAsync(v0, stream);
-  (void)hipFreeAsync(tmp, stream);
-  if (!dst) *out = v1;
+  if (!dst) {
+    buf.keep(v1);
+    *out = v1;
+  }
   return KDT_OK;
 }
 
@@ -342,55 +339,62 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
     return st;
   }
   if (d_off) {
+    PoolBuffers buf(stream);
     void* tmp = nullptr;
     size_t tb = 0;
     hipcub::TransformInputIterator<int64_t, ToI64, const int32_t*> cnt64(d_count, ToI64());
-    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt64, d_off, (int)nq, stream);
-    if (hipMallocAsync(&tmp, std::max<size_t>(tb, 16), stream) != hipSuccess) {
+    int64_t total = 0;
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt64, d_off, (int)nq, stream) != hipSuccess) {
+      kdt_set_error("kdt_range: offset scan setup failed");
+      st = KDT_EDEVICE;
+    } else if (!buf.get((char**)&tmp, tb)) {
       kdt_set_error("device allocation failed for the list offsets");
       st = KDT_ENOMEM;
+    } else if (hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt64, d_off, (int)nq, stream) !=
+               hipSuccess) {
+      kdt_set_error("kdt_range: offset scan failed");
+      st = KDT_EDEVICE;
     } else {
-      hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt64, d_off, (int)nq, stream);
       k_range_offsets_fix<<<1, 1, 0, stream>>>(d_off, d_count, nq);
-      (void)hipFreeAsync(tmp, stream);
-      int64_t total = 0;
       if (hipMemcpyAsync(&total, d_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, stream) !=
               hipSuccess ||
           hipStreamSynchronize(stream) != hipSuccess) {
         kdt_set_error("reading the list size failed");
         st = KDT_EDEVICE;
-      } else {
-        if (required) *required = total;
-        if (d_idx) {
-          if (total > capacity) {
-            kdt_set_error("list capacity %lld is below the %lld entries needed",
-                          (long long)capacity, (long long)total);
-            st = KDT_ECAPACITY;
-          } else if (total > INT32_MAX) {
-            kdt_set_error("lists above 2^31-1 entries are not supported");
-            st = KDT_EUNSUPPORTED;
-          } else if (total > 0) {
-            int32_t* unsorted = nullptr;
-            if (hipMallocAsync((void**)&unsorted, sizeof(int32_t) * total, stream) != hipSuccess) {
-              kdt_set_error("device allocation failed for the lists");
-              st = KDT_ENOMEM;
-            } else {
-              k_range<D, true><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count,
-                                                                 d_off, unsorted);
-              size_t sb = 0;
-              hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total,
-                                                    (int)nq, d_off, d_off + 1, stream);
-              void* stmp = nullptr;
-              if (hipMallocAsync(&stmp, std::max<size_t>(sb, 16), stream) != hipSuccess) {
-                kdt_set_error("device allocation failed for sorting the lists");
-                st = KDT_ENOMEM;
-              } else {
-                hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total,
-                                                      (int)nq, d_off, d_off + 1, stream);
-                (void)hipFreeAsync(stmp, stream);
-              }
-              (void)hipFreeAsync(unsorted, stream);
-            }
+      }
+    }
+    if (st == KDT_OK) {
+      if (required) *required = total;
+      if (d_idx && total > capacity) {
+        kdt_set_error("list capacity %lld is below the %lld entries needed",
+                      (long long)capacity, (long long)total);
+        st = KDT_ECAPACITY;
+      } else if (d_idx && total > INT32_MAX) {
+        kdt_set_error("lists above 2^31-1 entries are not supported");
+        st = KDT_EUNSUPPORTED;
+      } else if (d_idx && total > 0) {
+        int32_t* unsorted = nullptr;
+        void* stmp = nullptr;
+        size_t sb = 0;
+        if (!buf.get(&unsorted, (size_t)total)) {
+          kdt_set_error("device allocation failed for the lists");
+          st = KDT_ENOMEM;
+        } else {
+          k_range<D, true><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count,
+                                                             d_off, unsorted);
+          if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total,
+                                                    (int)nq, d_off, d_off + 1, stream) !=
+              hipSuccess) {
+            kdt_set_error("kdt_range: list sort setup failed");
+            st = KDT_EDEVICE;
+          } else if (!buf.get((char**)&stmp, sb)) {
+            kdt_set_error("device allocation failed for sorting the lists");
+            st = KDT_ENOMEM;
+          } else if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total,
+                                                           (int)nq, d_off, d_off + 1, stream) !=
+                     hipSuccess) {
+            kdt_set_error("kdt_range: list sort failed");
+            st = KDT_EDEVICE;
           }
         }
       }
