@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_knn_forest_packet(
     int32_t* __restrict__ oidx, float* __restrict__ od2, unsigned long long* __restrict__ ctr) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  float* slice = lds + (size_t)wave * leaf_cap * rec_stride(D);
+  float* slice = lds + (size_t)wave * knn_wave_floats<D>(leaf_cap);
   const int64_t n_packets = pbase[n_sets];
   for (;;) {
     unsigned long long got = 0;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_knn_forest_packet(
     }
     TopK<KC> best;
     best.init(k);
-    packet_knn<D, KC>(t, q, active, best, slice);
+    packet_knn<D, KC>(t, q, active, best, slice, leaf_cap);
     if (active) knn_write<KC>(best, k, 0, sd.off + id, oidx, od2);
   }
 }
@@ -290,7 +290,7 @@ static kdt_status forest_queries(kdt_batch_plan* bp, const float* d_l, int32_t* 
   const int k = bp->k;
   if (bp->knn_packets) {
     const unsigned g = (unsigned)bp->knn_blocks;
-    const size_t smem = forest_lds_bytes<D>(bp->leaf);
+    const size_t smem = sizeof(float) * knn_wave_floats<D>(bp->leaf) * 4;
     if (k <= 8)
       k_knn_forest_packet<D, 8><<<g, 256, smem, s>>>(bp->dev.sets, ns, bp->pbase, bp->out.rec, bp->out.box, k, bp->leaf, d_idx, d_d2, bp->ctr);
     else if (k <= 16)
@@ -352,12 +352,13 @@ template <int D>
 static void size_grids(kdt_batch_plan* bp) {
   const void* kf = nullptr;
   const size_t smem = bp->leaf <= 64 ? forest_lds_bytes<D>(bp->leaf) : 0;
+  const size_t knn_smem = bp->leaf <= 64 ? sizeof(float) * knn_wave_floats<D>(bp->leaf) * 4 : 0;
   if (bp->knn_packets) {
     if (bp->k <= 8) kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 8>);
     else if (bp->k <= 16) kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 16>);
     else if (bp->k <= 32) kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 32>);
     else kf = reinterpret_cast<const void*>(&k_knn_forest_packet<D, 64>);
-    bp->knn_blocks = occupancy_blocks<D, 0>(kf, smem, 256);
+    bp->knn_blocks = occupancy_blocks<D, 0>(kf, knn_smem, 256);
   } else {
     if (bp->k <= 8) kf = reinterpret_cast<const void*>(&k_knn_forest<D, 8>);
     else if (bp->k <= 16) kf = reinterpret_cast<const void*>(&k_knn_forest<D, 16>);

@@ -47,19 +47,146 @@ struct LeafReader {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Matrix-core filter for the leaf scan of the wave kNN (d = 8, 16)
+// ---------------------------------------------------------------------------
+//
+// In high dimension almost every leaf is visited and the scan -- 64 queries
+// against up to 64 points -- is a dense contraction.  The filter computes
+// every query-point dot product with fp32 MFMA (v_mfma_f32_16x16x4f32: 16
+// blocks of 16 x 16, d/4 steps each) and marks point i for query q when
+//   (1 - 2^-16) (|q|^2 + |p_i|^2) - 2 q.p_i  <=  (1 + 2^-16) worst_q + 2^-100,
+// worst_q being the query's current k-th squared distance.  Rounding bound:
+// the dot product (d products and sums in fp32), the two norms and the
+// combination stay within (3d + 8) u (|q|^2 + |p|^2) of the real squared
+// distance, and the exact float32 distance of the insertion pass is within
+// (d + 2) u of it (u = 2^-24); the relative margins above are 256 u, and the
+// absolute term covers denormal products the matrix core may flush.  So every
+// point that can enter the list is marked, and the insertion pass, which
+// recomputes the exact distance and key, keeps the results bit-identical.
+//
+// MFMA lane layout (16x16x4 f32): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[4 (l / 16) + r][l % 16] in register r.
+// Rows are leaf points, columns queries.
+
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+template <int D>
+struct DotFilter {
+  static constexpr bool kOn = D >= 8 && D % 4 == 0;
+  static constexpr int KS = D / 4 > 0 ? D / 4 : 1;  // MFMA k-steps
+  float bq[4][KS];  // B operands: coordinate 4 s + l / 16 of query 16 qj + l % 16
+  float nq[4];      // |q|^2 of query 16 qj + l % 16
+  float* np;        // LDS [64]: |p|^2 of the open leaf's points
+  uint64_t* mb;     // LDS [4][4][16]: partial marks on their way to the query's lane
+
+  // LDS of one wave: the leaf slice (also the query staging area), then np
+  // and mb.  `leaf` is the tree's leaf size.
+  __host__ __device__ static constexpr size_t slice_floats(int leaf) {
+    return ((size_t)((leaf + 15) / 16 * 16) * rec_stride(D) > (size_t)64 * D
+                ? (size_t)((leaf + 15) / 16 * 16) * rec_stride(D)
+                : (size_t)64 * D);
+  }
+  __host__ __device__ static constexpr size_t wave_floats(int leaf) {
+    return slice_floats(leaf) + 64 + 2 * 4 * 4 * 16;
+  }
+
+  // Called by the whole wave before any leaf is opened.
+  __device__ __forceinline__ void init(const float p[D], bool active, float* lds, int leaf) {
+    const int l = lane_id();
+    float* stage = lds;
+    np = lds + slice_floats(leaf);
+    mb = reinterpret_cast<uint64_t*>(np + 64);
+    float n2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) n2 += p[a] * p[a];
+    wave_sync();
+#pragma unroll
+    for (int a = 0; a < D; ++a) stage[l * D + a] = active ? p[a] : 0.0f;
+    np[l] = active ? n2 : 0.0f;
+    wave_sync();
+#pragma unroll
+    for (int qj = 0; qj < 4; ++qj) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) bq[qj][s] = stage[(16 * qj + (l & 15)) * D + 4 * s + (l >> 4)];
+      nq[qj] = np[16 * qj + (l & 15)];
+    }
+    wave_sync();
+  }
+
+  // Marks of the open leaf (`leaf`: its LDS copy, `cnt` points) for this
+  // lane's query, whose own threshold is `worst`.  Whole wave.
+  __device__ __forceinline__ uint64_t marks(const float* leaf, int cnt, float worst) const {
+    constexpr int S = rec_stride(D);
+    const int l = lane_id();
+    const float thr_own = worst * (1.0f + 0x1p-16f) + 0x1p-100f;
+    float thr[4];
+#pragma unroll
+    for (int qj = 0; qj < 4; ++qj) thr[qj] = __shfl(thr_own, 16 * qj + (l & 15));
+    float n2 = 0.0f;
+    if (l < cnt) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) n2 += leaf[l * S + a] * leaf[l * S + a];
+    }
+    np[l] = n2;
+    wave_sync();
+    uint64_t m[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int pi = 0; pi < 4; ++pi) {
+      if (16 * pi >= cnt) break;
+      float ap[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) ap[s] = leaf[(16 * pi + (l & 15)) * S + 4 * s + (l >> 4)];
+      const int row0 = 16 * pi + 4 * (l >> 4);
+      float npv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) npv[r] = np[row0 + r];
+#pragma unroll
+      for (int qj = 0; qj < 4; ++qj) {
+        v4f_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[s], bq[qj][s], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float lhs = (nq[qj] + npv[r]) * (1.0f - 0x1p-16f) - 2.0f * acc[r];
+          m[qj] |= (uint64_t)(lhs <= thr[qj]) << (row0 + r);
+        }
+      }
+    }
+#pragma unroll
+    for (int qj = 0; qj < 4; ++qj) mb[(qj * 4 + (l >> 4)) * 16 + (l & 15)] = m[qj];
+    wave_sync();
+    uint64_t mine = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) mine |= mb[((l >> 4) * 4 + t) * 16 + (l & 15)];
+    wave_sync();  // np and mb are rewritten by the next leaf
+    return cnt < 64 ? mine & ((1ull << cnt) - 1) : mine;
+  }
+};
+
+// LDS floats of one wave of the wave kNN.
+template <int D>
+__host__ __device__ constexpr size_t knn_wave_floats(int leaf) {
+  return DotFilter<D>::kOn ? DotFilter<D>::wave_floats(leaf) : (size_t)leaf * rec_stride(D);
+}
+
 // kNN of the 64 queries of a wave (Algorithm 2 semantics).  Each lane keeps its
 // own register top-k keyed by (d2, index), so the result is exactly the k
 // smallest keys, the same as any exact traversal.  Leaves must hold at most 64
 // points.
+// `lds` is the wave's slice of DotFilter<D>::wave_floats(leaf_cap) floats
+// (leaf_cap * rec_stride(D) below d = 8).
 template <int D, int KC>
 __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], bool active,
-                                           TopK<KC>& best, float* lds) {
+                                           TopK<KC>& best, float* lds, int leaf_cap) {
   const int lane = lane_id();
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   uint32_t stackv = 0;  // lane i holds stack entry i
   int sp = 1;
   uint64_t mask = 0;    // this lane's pending candidates in the open leaf
   LeafReader<D> leaf(t.rec, lds);
+  DotFilter<D> filt;
+  if constexpr (DotFilter<D>::kOn) filt.init(p, active, lds, leaf_cap);
   // One flat loop (the candidate list is then live across a single loop
   // header): a round either inserts one pending candidate per lane, or pops
   // and visits the next node.
@@ -95,11 +222,15 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       // keeps ties with the current k-th); the exact key test is repeated
       // before insertion.
       const float wd = best.worst_d2();
+      if constexpr (DotFilter<D>::kOn) {
+        mask = filt.marks(lds, cnt, wd);
+      } else {
 #pragma unroll uniform_batch<D>()
-      for (int i = 0; i < cnt; ++i) {
-        float x[D];
-        leaf.point(i, x);
-        mask |= (uint64_t)(sq_dist<D>(x, p) <= wd) << i;
+        for (int i = 0; i < cnt; ++i) {
+          float x[D];
+          leaf.point(i, x);
+          mask |= (uint64_t)(sq_dist<D>(x, p) <= wd) << i;
+        }
       }
       if (!active) mask = 0;
     } else {

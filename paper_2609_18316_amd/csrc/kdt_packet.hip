@@ -57,7 +57,8 @@ __global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const f
   const bool active = load_query<D>(t, q, nq, order, s0 + lane, p, row);
   TopK<KC> best;
   best.init(k);
-  packet_knn<D, KC>(t, p, active, best, wave_slice<D>(lds, wave, leaf_cap));
+  packet_knn<D, KC>(t, p, active, best, lds + (size_t)wave * knn_wave_floats<D>(leaf_cap),
+                    leaf_cap);
   if (active) knn_write<KC>(best, k, MODE, row, oidx, od2);
 }
 
@@ -118,7 +119,7 @@ kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int6
                              int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
                              hipStream_t stream) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
-  const size_t smem = packet_lds_bytes<D>(leaf);
+  const size_t smem = sizeof(float) * knn_wave_floats<D>(leaf) * kPWaves;
 #define KDT_LAUNCH(KC, M)                                                                      \
   k_knn_packet<D, KC, M><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, k, order, d_idx, d_d2, \
                                                                leaf)
