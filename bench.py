@@ -50,10 +50,10 @@ BATCH_SETS = 256
 KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
                 "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
-    "sha256": "720f33e128f2e831bdc3073d07018af3ee771334490b2e96a14af8222f88125f",
-    "hbm_bytes": 2.1446e+09,
+    "sha256": "f5d4738d977d353db2fb80538794c1a9583d729f4e2421d7af3cee600efbc81b",
+    "hbm_bytes": 2.1447e+09,
     "l2_hit_rate": 0.964,
-    "valu_issue_frac": 0.76,
+    "valu_issue_frac": 0.71,
 }
 
 
