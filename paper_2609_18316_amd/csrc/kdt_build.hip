@@ -466,15 +466,14 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
   __shared__ int32_t sp[T];
   __shared__ uint32_t tmp[4];
   __shared__ uint32_t red[4 * 2 * D];
-  __shared__ uint32_t tot_eq, tot_left;
+  __shared__ uint4 wcnt[2][R];  // per round of rows: counts of the four waves (equal, left)
   __shared__ int64_t pre[2];
-  const int tid = threadIdx.x, lane = lane_id();
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const ChunkEntry ch = chunks[blockIdx.x];
   const SegEntry se = segs[ch.seg];
   const SegState s = st[ch.seg];
   const uint32_t pivot = s.prefix;
   const int64_t n_eq_left = (int64_t)s.rank + 1;
-  const float* kx = xin + (int64_t)s.axis * tot;
   // keys below / equal to the pivot in the earlier chunks of this node
   {
     uint32_t nl = 0, ne = 0;
@@ -499,47 +498,75 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
     lmin[a] = rmin[a] = 0xFFFFFFFFu;
     lmax[a] = rmax[a] = 0u;
   }
+  // Rows of a tile are dealt out round by round (row r * 256 + tid), so every
+  // load is coalesced; ballots give each row its rank in input order.
   int64_t run_left = 0, run_right = 0, run_eq = 0;
   for (int64_t base = ch.b; base < ch.e; base += T) {
     const int nt = (int)min((int64_t)T, ch.e - base);
-    const int r0 = tid * R;  // this thread's first row in the tile
+    float v[R][D];
+    int32_t p[R];
     uint32_t key[R];
-    uint32_t my_eq = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      key[r] = r0 + r < nt ? fkey(kx[base + r0 + r]) : 0xFFFFFFFFu;
-      my_eq += (r0 + r < nt) && key[r] == pivot;
+      const int i = r * kBuildBlock + tid;
+      const int64_t row = base + (i < nt ? i : 0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) v[r][a] = xin[a * tot + row];
+      p[r] = pin[row];
     }
-    const uint32_t eq_inc = block_incl_scan(my_eq, tmp);
-    if (tid == kBuildBlock - 1) tot_eq = eq_inc;
-    uint32_t eq_rank = (uint32_t)(eq_before + run_eq) + eq_inc - my_eq;
-    uint32_t left_bits = 0, my_left = 0;
+    uint32_t below_eq[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const bool valid = r0 + r < nt;
-      const bool eq = valid && key[r] == pivot;
-      const bool left = valid && (key[r] < pivot || (eq && (int64_t)eq_rank < n_eq_left));
-      eq_rank += eq;
-      left_bits |= (uint32_t)left << r;
-      my_left += left;
+      float kv = v[r][0];
+#pragma unroll
+      for (int a = 1; a < D; ++a) kv = a == s.axis ? v[r][a] : kv;
+      key[r] = fkey(kv);
+      const bool eq = r * kBuildBlock + tid < nt && key[r] == pivot;
+      const uint64_t b = __ballot(eq);
+      below_eq[r] = (uint32_t)lanes_below(b);
+      if (lane == 0) (&wcnt[0][r].x)[wave] = (uint32_t)__popcll(b);
     }
-    const uint32_t left_inc = block_incl_scan(my_left, tmp);
-    if (tid == kBuildBlock - 1) tot_left = left_inc;
     __syncthreads();
-    const int tl = (int)tot_left;
-    uint32_t lpos = left_inc - my_left;  // left rows before this thread's rows
+    uint32_t acc = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (r0 + r >= nt) break;
-      const int64_t row = base + r0 + r;
+      const uint4 c = wcnt[0][r];
+      below_eq[r] += acc + (wave > 0 ? c.x : 0) + (wave > 1 ? c.y : 0) + (wave > 2 ? c.z : 0);
+      acc += c.x + c.y + c.z + c.w;
+    }
+    const uint32_t tile_eq = acc;
+    uint32_t below_left[R];
+    uint32_t left_bits = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool valid = r * kBuildBlock + tid < nt;
+      const bool eq = valid && key[r] == pivot;
+      const bool left =
+          valid && (key[r] < pivot || (eq && eq_before + run_eq + (int64_t)below_eq[r] < n_eq_left));
+      left_bits |= (uint32_t)left << r;
+      const uint64_t b = __ballot(left);
+      below_left[r] = (uint32_t)lanes_below(b);
+      if (lane == 0) (&wcnt[1][r].x)[wave] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    acc = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint4 c = wcnt[1][r];
+      below_left[r] += acc + (wave > 0 ? c.x : 0) + (wave > 1 ? c.y : 0) + (wave > 2 ? c.z : 0);
+      acc += c.x + c.y + c.z + c.w;
+    }
+    const int tl = (int)acc;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = r * kBuildBlock + tid;
+      if (i >= nt) break;
       const bool left = (left_bits >> r) & 1u;
-      const int dst = left ? (int)lpos : tl + (r0 + r - (int)lpos);
-      lpos += left;
+      const int dst = left ? (int)below_left[r] : tl + (i - (int)below_left[r]);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const float v = xin[a * tot + row];
-        sx[a][dst] = v;
-        const uint32_t kv = fkey(v);
+        sx[a][dst] = v[r][a];
+        const uint32_t kv = fkey(v[r][a]);
         if (left) {
           lmin[a] = min(lmin[a], kv);
           lmax[a] = max(lmax[a], kv);
@@ -548,7 +575,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
           rmax[a] = max(rmax[a], kv);
         }
       }
-      sp[dst] = pin[row];
+      sp[dst] = p[r];
     }
     __syncthreads();
     for (int i = tid; i < nt; i += kBuildBlock) {
@@ -561,7 +588,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
       for (int a = 0; a < D; ++a) xout[a * tot + g] = sx[a][i];
       pout[g] = sp[i];
     }
-    run_eq += tot_eq;
+    run_eq += tile_eq;
     run_left += tl;
     run_right += nt - tl;
     __syncthreads();
@@ -571,7 +598,6 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(const ChunkEntry* __res
     block_box<D>(lmin, lmax, red, c);
     block_box<D>(rmin, rmax, red, c + 2 * D);
   }
-  (void)lane;
 }
 
 // Finishes every level below a node inside one workgroup's LDS and writes the
