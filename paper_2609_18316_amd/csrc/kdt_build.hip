@@ -43,12 +43,13 @@ int levels_for(int64_t n, int leaf) {
   return L;
 }
 
-// Largest node handled inside one workgroup: coordinates, index and two
-// uint16 ping-pong index arrays must fit in ~60 KiB of LDS.
-int lds_capacity(int d) { return (61440) / (4 * d + 8); }
+// Largest node handled inside one workgroup: coordinates and two uint16
+// ping-pong index arrays must fit in ~60 KiB of LDS.
+int lds_capacity(int d) { return (61440) / (4 * d + 4); }
 
+// LDS of a subtree workgroup whose largest node holds `cap` points.
 static size_t lds_bytes(int d, int cap) {
-  return (size_t)cap * (4 * d + 4) + 4 * 256 * 4 + (size_t)cap * 2 * 2;
+  return (size_t)cap * 4 * d + 4 * 256 * 4 + (size_t)cap * 2 * 2;
 }
 
 bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std::string& err) {
@@ -135,6 +136,8 @@ bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std
       e.set = s;
       e.level = sd.glevels;
       p.subs.push_back(e);
+      p.sub_max = std::max<int>(p.sub_max, (int)(node_begin(sd.n, sd.glevels, j + 1) -
+                                                 node_begin(sd.n, sd.glevels, j)));
     }
   }
   return true;
@@ -613,8 +616,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_lds_subtree(
   constexpr int P = pad4(D);
   constexpr int S = rec_stride(D);
   float* lx = reinterpret_cast<float*>(smem);
-  int32_t* lperm = reinterpret_cast<int32_t*>(lx + (size_t)D * cap);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(lperm + cap);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(lx + (size_t)D * cap);
   uint16_t* lpa = reinterpret_cast<uint16_t*>(hist + 4 * 256);
   uint16_t* lpb = lpa + cap;
 
@@ -627,7 +629,6 @@ __global__ __launch_bounds__(kBuildBlock) void k_lds_subtree(
   for (int i = threadIdx.x; i < m; i += kBuildBlock) {
 #pragma unroll
     for (int a = 0; a < D; ++a) lx[a * cap + i] = xin[a * tot + g0 + i];
-    lperm[i] = pin[g0 + i];
     lpa[i] = (uint16_t)i;
   }
   __syncthreads();
@@ -711,7 +712,17 @@ __global__ __launch_bounds__(kBuildBlock) void k_lds_subtree(
           const uint64_t want = (uint64_t)prefix >> (hb + 1);
           for (int b = lane; b < 256; b += kWave) h[b] = 0;
           wave_sync();
-          for (int i = lb + lane; i < le; i += kWave) {
+          // four rounds of loads before their atomics
+          int i = lb + lane;
+          for (; i + 3 * kWave < le; i += 4 * kWave) {
+            uint32_t k[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) k[u] = fkey(kx[cur[i + u * kWave]]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (((uint64_t)k[u] >> (hb + 1)) == want) atomicAdd(&h[(k[u] >> sh) & dmask], 1u);
+          }
+          for (; i < le; i += kWave) {
             uint32_t k = fkey(kx[cur[i]]);
             if (((uint64_t)k >> (hb + 1)) == want) atomicAdd(&h[(k >> sh) & dmask], 1u);
           }
@@ -789,11 +800,12 @@ __global__ __launch_bounds__(kBuildBlock) void k_lds_subtree(
     for (int a = 0; a < S; ++a) r[a] = 0.0f;
 #pragma unroll
     for (int a = 0; a < D; ++a) r[a] = lx[a * cap + s];
-    r[D] = __int_as_float(lperm[s]);
+    const int32_t id = pin[g0 + s];
+    r[D] = __int_as_float(id);
     float4* dst = reinterpret_cast<float4*>(rec + row * S);
 #pragma unroll
     for (int q = 0; q < S / 4; ++q) dst[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
-    perm_out[row] = lperm[s];
+    perm_out[row] = id;
   }
 }
 
@@ -887,9 +899,9 @@ static kdt_status run_build(const Plan& p, const PlanDev& pd, const float* d_pts
                                                   w.x[src], w.p[src], w.x[dst], w.p[dst], tot,
                                                   w.cbox, w.bad);
   }
-  const size_t smem = lds_bytes(D, p.lds_cap);
+  const size_t smem = lds_bytes(D, p.sub_max);
   k_lds_subtree<D><<<(unsigned)p.subs.size(), kBuildBlock, smem, stream>>>(
-      pd.subs, pd.sets, w.x[0], w.p[0], w.x[1], w.p[1], tot, p.lds_cap, o.box, o.axis, o.split,
+      pd.subs, pd.sets, w.x[0], w.p[0], w.x[1], w.p[1], tot, p.sub_max, o.box, o.axis, o.split,
       o.rec, o.perm);
   KDT_HIP(hipGetLastError());
   return KDT_OK;

@@ -155,6 +155,7 @@ struct Plan {
   std::vector<ChunkEntry> root_chunks;  // seg field = set index
   std::vector<SubEntry> subs;
   int lds_cap = 0;  // largest node finished in LDS
+  int sub_max = 1;  // largest node that is finished in LDS in this plan
 };
 
 // Builds the static schedule of a forest from host-known sizes.
