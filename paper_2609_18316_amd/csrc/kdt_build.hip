@@ -78,6 +78,7 @@ bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std
   }
   p.n_nodes = nb;
   p.segs.resize(p.n_glevels);
+  p.multi_chunk.assign(p.n_glevels, 0);
   p.chunks.resize(p.n_glevels);
   auto add_chunks = [](std::vector<ChunkEntry>& out, int64_t b, int64_t e, int32_t seg) {
     int64_t nch = std::max<int64_t>(1, (e - b + kChunk - 1) / kChunk);
@@ -86,7 +87,7 @@ bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std
       ce.b = b + (e - b) * c / nch;
       ce.e = b + (e - b) * (c + 1) / nch;
       ce.seg = seg;
-      ce.pad = 0;
+      ce.sole = nch == 1;
       out.push_back(ce);
     }
     return (int32_t)nch;
@@ -112,6 +113,7 @@ bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std
         se.child = (l + 1 < sd.glevels) ? sd.node_base + (int64_t(2) << l) - 1 + 2 * j : -1;
         se.first_chunk = (int32_t)p.chunks[l].size();
         se.n_chunks = add_chunks(p.chunks[l], se.b, se.e, (int32_t)p.segs[l].size());
+        if (se.n_chunks > 1) p.multi_chunk[l] = 1;
         if (l == 0) {
           se.src_first = root_first[s];
           se.src_count = root_count[s];
@@ -200,6 +202,7 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* tmp) {
 
 constexpr int kBins = 256;       // 8-bit digits
 constexpr int kRadixPasses = 4;  // 4 x 8 bits resolve a 32-bit key
+constexpr int kPassUnroll = 8;   // rows per thread whose loads are in flight together
 
 // Rows of one scatter tile: coordinates and index of the tile fit in 32 KiB.
 template <int D>
@@ -340,10 +343,11 @@ __global__ __launch_bounds__(kBuildBlock) void k_level_init(const SegEntry* __re
 // atomic (clustered data puts most keys of a node in few bins).
 template <int D>
 __global__ __launch_bounds__(kBuildBlock) void k_hist(const ChunkEntry* __restrict__ chunks,
-                                                      const SegState* __restrict__ st,
+                                                      SegState* __restrict__ st,
                                                       const float* __restrict__ x, int64_t tot,
                                                       uint32_t* __restrict__ chist) {
   __shared__ uint32_t h[kBins];
+  __shared__ uint32_t tmp[4];
   const ChunkEntry ch = chunks[blockIdx.x];
   const SegState s = st[ch.seg];
   if (s.hb < 0) return;
@@ -353,63 +357,113 @@ __global__ __launch_bounds__(kBuildBlock) void k_hist(const ChunkEntry* __restri
   const int sh = s.hb >= 7 ? s.hb - 7 : 0;
   const uint32_t dmask = (1u << (s.hb - sh + 1)) - 1u;
   const uint64_t want = (uint64_t)s.prefix >> (s.hb + 1);
-  const float* kx = x + (int64_t)s.axis * tot;
-  for (int64_t base = ch.b; base < ch.e; base += kBuildBlock) {
-    const int64_t i = base + tid;
-    bool ok = false;
-    uint32_t bin = 0;
-    if (i < ch.e) {
-      const uint32_t k = fkey(kx[i]);
-      ok = ((uint64_t)k >> (s.hb + 1)) == want;
-      bin = (k >> sh) & dmask;
-    }
-    const uint64_t m_ok = __ballot(ok);
-    if (m_ok == 0) continue;
-    const uint32_t lead =
-        (uint32_t)__builtin_amdgcn_readlane((int)bin, __ffsll((unsigned long long)m_ok) - 1);
-    const bool same = ok && bin == lead;
-    const uint64_t m = __ballot(same);
-    if (same) {
-      if (lanes_below(m) == 0) atomicAdd(&h[lead], (uint32_t)__popcll(m));
-    } else if (ok) {
-      atomicAdd(&h[bin], 1u);
+  const float* kx = x + (int64_t)s.axis * tot + ch.b;
+  const int nr = (int)(ch.e - ch.b);
+  for (int base = 0; base < nr; base += kBuildBlock * kPassUnroll) {
+    // every load of the round is issued before the first is used (indexes
+    // clamped into the chunk; rows past its end are masked afterwards)
+    float v[kPassUnroll];
+#pragma unroll
+    for (int u = 0; u < kPassUnroll; ++u) v[u] = kx[min(base + u * kBuildBlock + tid, nr - 1)];
+#pragma unroll
+    for (int u = 0; u < kPassUnroll; ++u) {
+      const uint32_t k = fkey(v[u]);
+      const bool ok = base + u * kBuildBlock + tid < nr && ((uint64_t)k >> (s.hb + 1)) == want;
+      const uint32_t bin = (k >> sh) & dmask;
+      const uint64_t m_ok = __ballot(ok);
+      if (m_ok == 0) continue;
+      const uint32_t lead =
+          (uint32_t)__builtin_amdgcn_readlane((int)bin, __ffsll((unsigned long long)m_ok) - 1);
+      const bool same = ok && bin == lead;
+      const uint64_t m = __ballot(same);
+      if (same) {
+        if (lanes_below(m) == 0) atomicAdd(&h[lead], (uint32_t)__popcll(m));
+      } else if (ok) {
+        atomicAdd(&h[bin], 1u);
+      }
     }
   }
   __syncthreads();
+  if (ch.sole) {
+    // the node's only chunk: narrow its selection state here
+    const uint32_t c = h[tid];
+    const uint32_t inc = block_incl_scan(c, tmp);
+    const uint32_t exc = inc - c;
+    const uint32_t r = (uint32_t)s.rank;
+    if (exc <= r && r < inc) {
+      SegState* o = st + ch.seg;
+      o->prefix = s.prefix | ((uint32_t)tid << sh);
+      o->rank = (int32_t)(r - exc);
+      o->hb = sh - 1;
+    }
+    return;
+  }
   chist[(int64_t)blockIdx.x * kBins + tid] = h[tid];
 }
 
-// One workgroup per node: sum the chunk histograms, find the digit bin that
-// holds the pivot's rank and narrow the selection state.
-__global__ __launch_bounds__(kBuildBlock) void k_select(const SegEntry* __restrict__ segs,
-                                                        SegState* __restrict__ st,
-                                                        const uint32_t* __restrict__ chist) {
-  __shared__ uint32_t tmp[4];
+// One workgroup per node of more than one chunk: sum the chunk histograms,
+// find the digit bin that holds the pivot's rank and narrow the selection
+// state.  Top-level nodes own hundreds of chunks: each wave reads whole chunk
+// histograms as 16-byte quads of bins, kSelUnroll chunks in flight.
+constexpr int kSelBlock = 1024;
+constexpr int kSelQuads = kBins / 4;
+constexpr int kSelGroups = kSelBlock / kSelQuads;
+constexpr int kSelUnroll = 8;
+__global__ __launch_bounds__(kSelBlock) void k_select(const SegEntry* __restrict__ segs,
+                                                      SegState* __restrict__ st,
+                                                      const uint32_t* __restrict__ chist) {
+  __shared__ uint4 part[kSelGroups][kSelQuads];
+  __shared__ uint32_t tmp[kBins / kWave];
   const int tid = threadIdx.x;
+  const SegEntry se = segs[blockIdx.x];
+  if (se.n_chunks == 1) return;  // resolved by its histogram pass
   const SegState s = st[blockIdx.x];
   if (s.hb < 0) return;
-  const SegEntry se = segs[blockIdx.x];
-  const uint32_t* hp = chist + (int64_t)se.first_chunk * kBins + tid;
-  uint32_t c = 0;
-  int q = 0;
-  for (; q + 8 <= se.n_chunks; q += 8) {
-    uint32_t v[8];
+  const int quad = tid % kSelQuads, grp = tid / kSelQuads;
+  const uint4* hp = reinterpret_cast<const uint4*>(chist + (int64_t)se.first_chunk * kBins) + quad;
+  uint4 c = make_uint4(0, 0, 0, 0);
+  int q = grp;
+  for (; q + kSelGroups * (kSelUnroll - 1) < se.n_chunks; q += kSelGroups * kSelUnroll) {
+    uint4 v[kSelUnroll];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = hp[(int64_t)(q + u) * kBins];
+    for (int u = 0; u < kSelUnroll; ++u) v[u] = hp[(int64_t)(q + u * kSelGroups) * kSelQuads];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c += v[u];
+    for (int u = 0; u < kSelUnroll; ++u) {
+      c.x += v[u].x;
+      c.y += v[u].y;
+      c.z += v[u].z;
+      c.w += v[u].w;
+    }
   }
-  for (; q < se.n_chunks; ++q) c += hp[(int64_t)q * kBins];
-  const uint32_t inc = block_incl_scan(c, tmp);
-  const uint32_t exc = inc - c;
-  const uint32_t r = (uint32_t)s.rank;
-  if (exc <= r && r < inc) {
-    const int sh = s.hb >= 7 ? s.hb - 7 : 0;
-    SegState ns = s;
-    ns.prefix = s.prefix | ((uint32_t)tid << sh);
-    ns.rank = (int32_t)(r - exc);
-    ns.hb = sh - 1;
-    st[blockIdx.x] = ns;
+  for (; q < se.n_chunks; q += kSelGroups) {
+    const uint4 v = hp[(int64_t)q * kSelQuads];
+    c.x += v.x;
+    c.y += v.y;
+    c.z += v.z;
+    c.w += v.w;
+  }
+  part[grp][quad] = c;
+  __syncthreads();
+  const int wave = tid >> 6, lane = lane_id();
+  uint32_t sum = 0, inc = 0;
+  if (tid < kBins) {
+#pragma unroll
+    for (int g = 0; g < kSelGroups; ++g) sum += reinterpret_cast<const uint32_t*>(part[g])[tid];
+    inc = wave_incl_scan(sum);
+    if (lane == kWave - 1) tmp[wave] = inc;
+  }
+  __syncthreads();
+  if (tid < kBins) {
+    for (int w = 0; w < wave; ++w) inc += tmp[w];
+    const uint32_t exc = inc - sum;
+    const uint32_t r = (uint32_t)s.rank;
+    if (exc <= r && r < inc) {
+      const int sh = s.hb >= 7 ? s.hb - 7 : 0;
+      SegState* o = st + blockIdx.x;
+      o->prefix = s.prefix | ((uint32_t)tid << sh);
+      o->rank = (int32_t)(r - exc);
+      o->hb = sh - 1;
+    }
   }
 }
 
@@ -426,12 +480,20 @@ __global__ __launch_bounds__(kBuildBlock) void k_count(const ChunkEntry* __restr
   const ChunkEntry ch = chunks[blockIdx.x];
   const SegState s = st[ch.seg];
   const uint32_t pivot = s.prefix;
-  const float* kx = x + (int64_t)s.axis * tot;
+  const float* kx = x + (int64_t)s.axis * tot + ch.b;
+  const int nr = (int)(ch.e - ch.b);
   uint32_t nl = 0, ne = 0;
-  for (int64_t i = ch.b + tid; i < ch.e; i += kBuildBlock) {
-    const uint32_t k = fkey(kx[i]);
-    nl += k < pivot;
-    ne += k == pivot;
+  for (int base = 0; base < nr; base += kBuildBlock * kPassUnroll) {
+    float v[kPassUnroll];
+#pragma unroll
+    for (int u = 0; u < kPassUnroll; ++u) v[u] = kx[min(base + u * kBuildBlock + tid, nr - 1)];
+#pragma unroll
+    for (int u = 0; u < kPassUnroll; ++u) {
+      const uint32_t k = fkey(v[u]);
+      const bool valid = base + u * kBuildBlock + tid < nr;
+      nl += valid && k < pivot;
+      ne += valid && k == pivot;
+    }
   }
   nl = wave_sum(nl);
   ne = wave_sum(ne);
@@ -891,7 +953,8 @@ static kdt_status run_build(const Plan& p, const PlanDev& pd, const float* d_pts
                                                                 w.cbox, o.box, o.axis);
     for (int pass = 0; pass < kRadixPasses; ++pass) {
       k_hist<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], w.st, w.x[src], tot, w.chist);
-      k_select<<<nseg, kBuildBlock, 0, stream>>>(pd.segs[l], w.st, w.chist);
+      if (p.multi_chunk[l])
+        k_select<<<nseg, kSelBlock, 0, stream>>>(pd.segs[l], w.st, w.chist);
     }
     k_count<D><<<nch, kBuildBlock, 0, stream>>>(pd.chunks[l], pd.segs[l], w.st, w.x[src], tot,
                                                 w.cnt, o.split);

@@ -123,7 +123,7 @@ struct SegEntry {
 struct ChunkEntry {
   int64_t b, e;  // rows
   int32_t seg;   // segment index within the level (or set index for the root pass)
-  int32_t pad;
+  int32_t sole;  // 1 when the chunk is its segment's only one
 };
 
 // A node finished inside one workgroup's LDS, with its whole subtree.
@@ -153,6 +153,7 @@ struct Plan {
   std::vector<std::vector<SegEntry>> segs;
   std::vector<std::vector<ChunkEntry>> chunks;
   std::vector<ChunkEntry> root_chunks;  // seg field = set index
+  std::vector<char> multi_chunk;        // per global level: some node owns several chunks
   std::vector<SubEntry> subs;
   int lds_cap = 0;  // largest node finished in LDS
   int sub_max = 1;  // largest node that is finished in LDS in this plan
