@@ -2,7 +2,9 @@
 //
 // Every point runs a ball query of radius l over the tree (in tree order, so
 // the lanes of a wave search neighbouring space) and links itself to every
-// friend with a larger input index through a lock-free union-find: roots
+// friend at a later tree position (nodes that end at or before its own are
+// never entered: the other end of each such pair links it) through a
+// lock-free union-find: roots
 // always hang under the smaller root (compare-and-swap), so the root of each
 // component is its smallest input index.  Finding a root halves the path as
 // it goes.  A final pass points every element at its root, which is the

@@ -325,8 +325,10 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
 // already that component's, needs a single link when it lies entirely within l
 // of the lane, and otherwise only its first friend.  A node entirely within l
 // of several lanes is joined point by point by the lowest such lane, which then
-// flags it; the others link to its first point.  Elsewhere each pair i < j
-// within l is linked by i.  Leaves must hold at most 64 points.
+// flags it; the others link to its first point.  Elsewhere each pair within l
+// is linked by the point that comes first in tree order: a lane never enters a
+// node that ends at or before its own position, so the search of a ball costs
+// about half.  Leaves must hold at most 64 points.
 template <int D>
 __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], int64_t pos,
                                            int32_t me, bool active, float l2, int32_t base,
@@ -346,14 +348,16 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
     const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)stackv, sp);
     const uint64_t live = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)stk_hi, sp) << 32) |
                           (uint32_t)__builtin_amdgcn_readlane((int)stk_lo, sp);
-    const bool mine = active && ((live >> lane) & 1ull);
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    // a lane links only towards later tree positions: a node that ends at or
+    // before its own position is left to the points inside it
+    const bool mine = active && ((live >> lane) & 1ull) && e > pos;
     float lo[D], hi[D];
     load_box_uniform<D>(t.box, node, lo, hi);
     bool touch = mine && box_mindist<D>(lo, hi, p) <= l2;
     if (!__any(touch)) continue;
-    const int lev = node_level(node);
-    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
-    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
     const int32_t gfirst = base + __float_as_int(t.rec[b * S + D]);
     const bool one = flag_ld(conn + node) != 0;
     if (one && touch) {
@@ -402,7 +406,7 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
           uf_union_from(parent, myroot, base + id);
           break;
         }
-        if (id > me) uf_union_from(parent, myroot, base + id);
+        if (b + i > pos) uf_union_from(parent, myroot, base + id);
       }
     } else {
       const uint32_t mlo = (uint32_t)pm, mhi = (uint32_t)(pm >> 32);

@@ -399,12 +399,15 @@ __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], i
     --sp;
     if (guard >= 0 && sp < guard) guard = -1;
     const uint32_t node = stk[sp * ld];
-    float lo[D], hi[D];
-    load_box<D>(t.box, node, lo, hi);
-    if (box_mindist<D>(lo, hi, p) > l2) continue;
     const int lev = node_level(node);
     const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
     const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    // links go towards later tree positions only: a node that ends at or
+    // before p's position is left to the points inside it
+    if (e <= pos) continue;
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (box_mindist<D>(lo, hi, p) > l2) continue;
     const bool in_region = guard >= 0;
     const bool one = in_region || flag_ld(conn + node) != 0;
     if (one && pos >= b && pos < e) continue;  // p is already in this component
@@ -436,7 +439,7 @@ __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], i
           }
           break;
         }
-        if (id > me) uf_union_from(parent, myroot, base + id);
+        if (i > pos) uf_union_from(parent, myroot, base + id);
       }
       continue;
     }

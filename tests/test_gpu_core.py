@@ -194,15 +194,16 @@ def test_range_capacity_error_reports_required():
 
 
 @pytest.mark.parametrize("d", (2, 3, 8))
-def test_fof_matches_oracle(d):
+@pytest.mark.parametrize("leaf", (16, 100))  # wave packets / one traversal per lane
+def test_fof_matches_oracle(d, leaf):
     dev()
     for kind in ("uniform", "duplicates", "lattice"):
         for n in (1, 2, 700, 20011):
             x = cases.points(kind, n, d, seed=5 * n + d)
-            t = kdt.build(to_dev(x), leaf_size=16)
+            t = kdt.build(to_dev(x), leaf_size=leaf)
             ot = oracle.Tree(x, 16)
             for l in (0.0, 0.02, 0.1):
-                say(f"fof d={d} kind={kind} n={n} l={l}")
+                say(f"fof d={d} leaf={leaf} kind={kind} n={n} l={l}")
                 lab, ng = t.fof(l, count_groups=True)
                 ol = ot.fof(l)
                 np.testing.assert_array_equal(to_host(lab), ol)
