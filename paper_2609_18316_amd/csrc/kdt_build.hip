@@ -44,8 +44,9 @@ int levels_for(int64_t n, int leaf) {
 }
 
 // Largest node handled inside one workgroup: coordinates and two uint16
-// ping-pong index arrays must fit in ~60 KiB of LDS.
-int lds_capacity(int d) { return (61440) / (4 * d + 4); }
+// ping-pong index arrays fit in 32 KiB of LDS, so four workgroups share a CU
+// (the subtree finish is bound by LDS latency, not by its instruction count).
+int lds_capacity(int d) { return 32768 / (4 * d + 4); }
 
 // LDS of a subtree workgroup whose largest node holds `cap` points.
 static size_t lds_bytes(int d, int cap) {
