@@ -260,17 +260,35 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
   }
 }
 
+// LDS floats of one wave of the ball count: the open leaf, then the packed
+// queries [64][D] and their counts [64].
+template <int D>
+__host__ __device__ constexpr size_t range_wave_floats(int leaf) {
+  return (size_t)leaf * rec_stride(D) + 64 * (D + 1);
+}
+
 // Closed-ball counts of the 64 queries of a wave (Algorithm 3 semantics): a
 // node farther than r from every lane is skipped, a node entirely inside a
 // lane's ball adds its size to that lane, and leaves are scanned only for the
 // lanes whose ball cuts them.  Each stack entry carries the mask of lanes that
 // still need that subtree, so a lane that has counted a whole node never
 // counts its descendants again.  Leaves must hold at most 64 points.
+//
+// Where the balls of a wave overlap a dense region, a leaf often cuts the
+// surface of only a few of them.  Then the queries that need the leaf are
+// packed into LDS and the wave tests (query, point) pairs instead: 64 / W
+// queries per step, W the leaf size rounded up to a power of two, each lane
+// holding one point; a query's count is the population of its lanes' ballot.
+// The distances are the same float32 expressions either way.
 template <int D>
 __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const float p[D],
-                                                      bool active, float r2, float* lds) {
+                                                      bool active, float r2, float* lds,
+                                                      int leaf_cap) {
+  constexpr int S = rec_stride(D);
   const int lane = lane_id();
   LeafReader<D> leaf(t.rec, lds);
+  float* cq = lds + (size_t)leaf_cap * S;                  // packed queries [64][D]
+  int32_t* cc = reinterpret_cast<int32_t*>(cq + 64 * D);  // their counts [64]
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   int64_t count = 0;
   uint32_t stackv = 0;                              // lane i: node of entry i
@@ -297,14 +315,43 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
     if (node >= first_leaf) {
       const int cnt = (int)(e - b);
       leaf.open(b, cnt);
-      int c = 0;
-#pragma unroll uniform_batch<D>()
-      for (int i = 0; i < cnt; ++i) {
+      const int na = __popcll(pm);
+      const int W = cnt <= 8 ? 8 : cnt <= 16 ? 16 : cnt <= 32 ? 32 : 64;
+      const int G = 64 / W;
+      const int steps = (na + G - 1) / G;
+      if (2 * steps <= cnt) {  // a packed step costs about two broadcast steps
+        const int me = lanes_below(pm);
+        if (part) {
+#pragma unroll
+          for (int a = 0; a < D; ++a) cq[me * D + a] = p[a];
+        }
+        wave_sync();
+        const int slot = lane / W, i = lane % W;
+        const uint64_t wmask = ~0ull >> (64 - W);
         float x[D];
-        leaf.point(i, x);
-        c += sq_dist<D>(x, p) <= r2;
+        leaf.point(min(i, cnt - 1), x);
+        for (int s = 0; s < steps; ++s) {
+          const int a = s * G + slot;
+          const int ac = min(a, na - 1);
+          float qv[D];
+#pragma unroll
+          for (int u = 0; u < D; ++u) qv[u] = cq[ac * D + u];
+          const bool hit = i < cnt && a < na && sq_dist<D>(x, qv) <= r2;
+          const uint64_t hm = __ballot(hit);
+          if (i == 0 && a < na) cc[a] = __popcll((hm >> (slot * W)) & wmask);
+        }
+        wave_sync();
+        if (part) count += cc[me];
+      } else {
+        int c = 0;
+#pragma unroll uniform_batch<D>()
+        for (int i = 0; i < cnt; ++i) {
+          float x[D];
+          leaf.point(i, x);
+          c += sq_dist<D>(x, p) <= r2;
+        }
+        if (part) count += c;
       }
-      if (part) count += c;
     } else {
       const uint32_t mlo = (uint32_t)pm, mhi = (uint32_t)(pm >> 32);
 #pragma unroll

@@ -75,7 +75,9 @@ __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const
   float p[D];
   int64_t row = 0;
   const bool active = load_query<D>(t, q, nq, order, s0 + lane, p, row);
-  const int64_t c = packet_range_count<D>(t, p, active, r2, wave_slice<D>(lds, wave, leaf_cap));
+  const int64_t c = packet_range_count<D>(t, p, active, r2,
+                                          lds + (size_t)wave * range_wave_floats<D>(leaf_cap),
+                                          leaf_cap);
   if (active) count[row] = (int32_t)c;
 }
 
@@ -149,8 +151,8 @@ template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
                                const int32_t* order, int32_t* d_count, hipStream_t stream) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
-  k_range_packet<D><<<grid, 64 * kPWaves, packet_lds_bytes<D>(leaf), stream>>>(v, d_q, nq, r2,
-                                                                              order, d_count, leaf);
+  const size_t smem = sizeof(float) * range_wave_floats<D>(leaf) * kPWaves;
+  k_range_packet<D><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, r2, order, d_count, leaf);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_range: packet kernel launch failed");
     return KDT_EDEVICE;

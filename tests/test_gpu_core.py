@@ -265,3 +265,19 @@ def test_error_paths():
         kdt.build(to_dev(x), leaf_size=1)
     assert e.value.status == kdt.KDT_EINVAL
     assert torch.cuda.is_available()
+
+
+@pytest.mark.parametrize("leaf", (8, 24, 32, 64))
+def test_range_counts_clustered_overlapping_balls(leaf):
+    """Ball counts where many balls of a wave overlap dense halos, so that
+    leaves cut by few of them take the packed-query scan (slot widths 8, 32,
+    32 and 64 points)."""
+    dev()
+    x = workloads.clustered(100000, seed=43)
+    q = workloads.uniform(8192, 3, seed=44)
+    t = kdt.build(to_dev(x), leaf_size=leaf)
+    ot = oracle.Tree(x, 32)
+    for r in (0.004, 0.02):
+        say(f"clustered range leaf={leaf} r={r}")
+        np.testing.assert_array_equal(to_host(t.range(to_dev(q), r)), ot.range(q, r))
+        np.testing.assert_array_equal(to_host(t.range(None, r)), ot.range(x, r))
