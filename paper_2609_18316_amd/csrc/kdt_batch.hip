@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBQ) void k_knn_forest(const SetDesc* __restrict__ 
       load_rec<D>(t.rec, row - sd.off, q, id);
       TopK<KC> best;
       best.init(k);
-      knn_one<D, KC>(t, q, best, &stk[0][threadIdx.x], kBQ);
+      knn_one<D>(t, q, best, &stk[0][threadIdx.x], kBQ);
       knn_write<KC>(best, k, 0, sd.off + id, oidx, od2);
     }
   }

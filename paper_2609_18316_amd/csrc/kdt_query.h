@@ -175,18 +175,53 @@ struct TopK {
       carry = up;
     }
   }
+  __device__ __forceinline__ void offer(float d2, int32_t id);
 };
 
 __device__ __forceinline__ uint64_t make_key(float d2, int32_t idx) {
   return ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)idx;
 }
 
+template <int KC>
+__device__ __forceinline__ void TopK<KC>::offer(float d2, int32_t id) {
+  const uint64_t key = make_key(d2, id);
+  if (key < worst()) insert(key);
+}
+
+// The k smallest squared distances alone, for queries that want only the
+// k-th distance: its value does not depend on how equal distances are
+// ordered, so no index is kept and the list takes half the registers of
+// TopK.  Entries are the bit patterns of non-negative float32 values (or
+// +inf), which order like the values, so integer min/max keep the list
+// sorted without any float rounding or denormal handling.
+template <int KC>
+struct TopD {
+  uint32_t a[KC];
+  __device__ __forceinline__ void init(int k) {
+#pragma unroll
+    for (int i = 0; i < KC; ++i) a[i] = (i < KC - k) ? 0u : 0x7F800000u;
+  }
+  __device__ __forceinline__ float worst_d2() const { return __uint_as_float(a[KC - 1]); }
+  __device__ __forceinline__ void offer(float d2, int32_t) {
+    const uint32_t x = __float_as_uint(d2);
+    if (x < a[KC - 1]) {
+      uint32_t carry = x;
+#pragma unroll
+      for (int i = 0; i < KC; ++i) {
+        const uint32_t up = max(a[i], carry);
+        a[i] = min(a[i], carry);
+        carry = up;
+      }
+    }
+  }
+};
+
 // kNN of one query p over tree t (Algorithm 2 semantics): depth-first, nearer
 // child first, a node is skipped when its box is farther than the current
 // k-th candidate.  `stk` is this lane's column of an LDS stack with stride
 // `ld` entries.
-template <int D, int KC>
-__device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], TopK<KC>& best,
+template <int D, class List>
+__device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], List& best,
                                         uint32_t* stk, int ld) {
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   // leaf sizes: floor(n / 2^L) or one more
@@ -247,8 +282,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Top
             float x[D];
             int32_t id = 0;
             load_rec<D>(t.rec, c + i, x, id);
-            const uint64_t key = make_key(sq_dist<D>(x, p), id);
-            if (key < best.worst()) best.insert(key);
+            best.offer(sq_dist<D>(x, p), id);
           }
         }
       } else {
@@ -295,6 +329,14 @@ __device__ __forceinline__ void knn_write(const TopK<KC>& best, int k, int mode,
     const float d2 = key == kEmptyKey ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
     od2[row] = mode == 2 ? sqrtf(d2) : d2;
   }
+}
+
+// The k-th squared distance (mode 1) or distance (mode 2) of a TopD list.
+template <int KC>
+__device__ __forceinline__ void knn_write_kth(const TopD<KC>& best, int mode, int64_t row,
+                                              float* __restrict__ od2) {
+  const float d2 = best.worst_d2();
+  od2[row] = mode == 2 ? sqrtf(d2) : d2;
 }
 
 // Lock-free union-find on int32 parents with parent[y] <= y.

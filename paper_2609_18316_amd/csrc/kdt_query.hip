@@ -25,8 +25,9 @@ constexpr int kQBlock = 128;
 // ---------------------------------------------------------------------------
 
 // The per-lane stack lives in LDS, (levels + 1) entries per lane (the tree
-// depth bounds it: one pending sibling per level), sized at launch.
-template <int D, int KC>
+// depth bounds it: one pending sibling per level), sized at launch.  KTH:
+// only the k-th distance is written (modes 1 and 2), kept in a TopD list.
+template <int D, int KC, bool KTH>
 __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* __restrict__ q,
                                                       int64_t nq, int k,
                                                       const int32_t* __restrict__ order, int mode,
@@ -46,10 +47,17 @@ __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* _
 #pragma unroll
     for (int a = 0; a < D; ++a) p[a] = q[row * D + a];
   }
-  TopK<KC> best;
-  best.init(k);
-  knn_one<D, KC>(t, p, best, stk_dyn + threadIdx.x, kQBlock);
-  knn_write<KC>(best, k, mode, row, oidx, od2);
+  if constexpr (KTH) {
+    TopD<KC> best;
+    best.init(k);
+    knn_one<D>(t, p, best, stk_dyn + threadIdx.x, kQBlock);
+    knn_write_kth<KC>(best, mode, row, od2);
+  } else {
+    TopK<KC> best;
+    best.init(k);
+    knn_one<D>(t, p, best, stk_dyn + threadIdx.x, kQBlock);
+    knn_write<KC>(best, k, mode, row, oidx, od2);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -281,14 +289,23 @@ static kdt_status knn_dispatch(const kdt_tree* t, const float* d_q, int64_t nq, 
   const TreeView v = view_of(t);
   const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(t->levels + 1) * kQBlock;
-  if (k <= 8)
-    k_knn_lane<D, 8><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
-  else if (k <= 16)
-    k_knn_lane<D, 16><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
-  else if (k <= 32)
-    k_knn_lane<D, 32><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
-  else
-    k_knn_lane<D, 64><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, d_idx, d_d2);
+#define KDT_LANE(KC)                                                                      \
+  if (mode == 0)                                                                          \
+    k_knn_lane<D, KC, false><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, \
+                                                              d_idx, d_d2);               \
+  else                                                                                    \
+    k_knn_lane<D, KC, true><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode,  \
+                                                             d_idx, d_d2);
+  if (k <= 8) {
+    KDT_LANE(8)
+  } else if (k <= 16) {
+    KDT_LANE(16)
+  } else if (k <= 32) {
+    KDT_LANE(32)
+  } else {
+    KDT_LANE(64)
+  }
+#undef KDT_LANE
   KDT_HIP(hipGetLastError());
   return KDT_OK;
 }

@@ -62,13 +62,14 @@ def test_knn_matches_oracle(d, kind):
         q = cases.points(kind, 300, d, seed=11 * n + d)
         t = kdt.build(to_dev(x), leaf_size=16)
         ot = oracle.Tree(x, 16)
-        ks = (1, 8, 32, 64, min(n + 3, 64)) if n <= 1000 else (8, 64)
+        ks = (1, 8, 16, 32, 64, min(n + 3, 64)) if n <= 1000 else (8, 64)
         for k in sorted(set(ks)):
             say(f"knn d={d} kind={kind} n={n} k={k}")
             gi, gd = t.knn(to_dev(q), k)
             oi, od = ot.knn(q, k)
             np.testing.assert_array_equal(to_host(gi), oi)
             np.testing.assert_array_equal(to_host(gd), od)
+            np.testing.assert_array_equal(to_host(t.knn(to_dev(q), k, kth_only=1)), od[:, -1])
             si, sd = t.knn(None, k)
             oi, od = ot.knn(x, k)
             np.testing.assert_array_equal(to_host(si), oi)
