@@ -167,15 +167,23 @@ struct DotFilter {
 // LDS floats of one wave of the wave kNN.
 template <int D>
 __host__ __device__ constexpr size_t knn_wave_floats(int leaf) {
-  return DotFilter<D>::kOn ? DotFilter<D>::wave_floats(leaf) : (size_t)leaf * rec_stride(D);
+  // without the filter: the open leaf, then packed queries [64][D + 1]
+  return DotFilter<D>::kOn ? DotFilter<D>::wave_floats(leaf)
+                           : (size_t)leaf * rec_stride(D) + 64 * (D + 1);
 }
 
 // kNN of the 64 queries of a wave (Algorithm 2 semantics).  Each lane keeps its
 // own register top-k keyed by (d2, index), so the result is exactly the k
 // smallest keys, the same as any exact traversal.  Leaves must hold at most 64
 // points.
-// `lds` is the wave's slice of DotFilter<D>::wave_floats(leaf_cap) floats
-// (leaf_cap * rec_stride(D) below d = 8).
+// `lds` is the wave's slice of knn_wave_floats<D>(leaf_cap) floats.
+//
+// Below d = 8, a leaf that only a few lanes need (box within their k-th
+// distance) is marked as (query, point) pairs of those lanes, packed in LDS
+// as in the ball count; each lane's marks come back to it from the ballot of
+// its slot.  A lane whose box test fails has no point within its k-th
+// distance (the float box distance never exceeds a point's), so the marks are
+// those of the scan over all lanes.
 template <int D, int KC>
 __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], bool active,
                                            TopK<KC>& best, float* lds, int leaf_cap) {
@@ -224,15 +232,53 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       const float wd = best.worst_d2();
       if constexpr (DotFilter<D>::kOn) {
         mask = filt.marks(lds, cnt, wd);
+        if (!active) mask = 0;
       } else {
-#pragma unroll uniform_batch<D>()
-        for (int i = 0; i < cnt; ++i) {
+        const uint64_t nm = __ballot(need);
+        const int na = __popcll(nm);
+        const int W = cnt <= 8 ? 8 : cnt <= 16 ? 16 : cnt <= 32 ? 32 : 64;
+        const int G = 64 / W;
+        const int steps = (na + G - 1) / G;
+        if (2 * steps <= cnt) {  // a packed step costs about two broadcast steps
+          float* cq = lds + (size_t)leaf_cap * rec_stride(D);  // [64][D + 1]: query, k-th d2
+          const int me = lanes_below(nm);
+          if (need) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) cq[me * (D + 1) + a] = p[a];
+            cq[me * (D + 1) + D] = wd;
+          }
+          wave_sync();
+          const int slot = lane / W, i = lane % W;
+          const uint64_t wmask = ~0ull >> (64 - W);
           float x[D];
-          leaf.point(i, x);
-          mask |= (uint64_t)(sq_dist<D>(x, p) <= wd) << i;
+          leaf.point(min(i, cnt - 1), x);
+          uint64_t rem = nm;  // owners of the slots still to come, lowest first
+          for (int s = 0; s < steps; ++s) {
+            const int a = s * G + slot;
+            const int ac = min(a, na - 1);
+            float qv[D];
+#pragma unroll
+            for (int u = 0; u < D; ++u) qv[u] = cq[ac * (D + 1) + u];
+            const float qw = cq[ac * (D + 1) + D];
+            const uint64_t hm = __ballot(i < cnt && a < na && sq_dist<D>(x, qv) <= qw);
+            for (int g = 0; g < G && rem != 0; ++g) {
+              const int owner = __ffsll((unsigned long long)rem) - 1;
+              rem &= rem - 1;
+              const uint64_t bits = (hm >> (g * W)) & wmask;
+              mask = lane == owner ? bits : mask;
+            }
+          }
+          wave_sync();
+        } else {
+#pragma unroll uniform_batch<D>()
+          for (int i = 0; i < cnt; ++i) {
+            float x[D];
+            leaf.point(i, x);
+            mask |= (uint64_t)(sq_dist<D>(x, p) <= wd) << i;
+          }
+          if (!active) mask = 0;
         }
       }
-      if (!active) mask = 0;
     } else {
       const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
       load_box_uniform<D>(t.box, c0, lo, hi);
