@@ -417,8 +417,9 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
 // to form one component (conn flag) is skipped by every lane whose own root is
 // already that component's, needs a single link when it lies entirely within l
 // of the lane, and otherwise only its first friend.  A node entirely within l
-// of several lanes is joined point by point by the lowest such lane, which then
-// flags it; the others link to its first point.  Elsewhere each pair within l
+// of several lanes is joined to the lowest such lane's point by the whole wave
+// (64 links at a time), and that lane flags it; the others link to its first
+// point.  Elsewhere each pair within l
 // is linked by the point that comes first in tree order: a lane never enters a
 // node that ends at or before its own position, so the search of a ball costs
 // about half.  Leaves must hold at most 64 points.
@@ -465,10 +466,15 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
     } else {
       const uint64_t fm = __ballot(full);
       if (fm != 0) {
+        // every point of the node is a friend of the leader's point: the
+        // whole wave links them to it, 64 at a time
         const int leader = __ffsll((unsigned long long)fm) - 1;
+        const int32_t lroot = __builtin_amdgcn_readlane(myroot, leader);
+        for (int64_t i = b + lane; i < e; i += 64) {
+          int32_t r = lroot;
+          uf_union_from(parent, r, base + __float_as_int(t.rec[i * S + D]));
+        }
         if (lane == leader) {
-          for (int64_t i = b; i < e; ++i)
-            uf_union_from(parent, myroot, base + __float_as_int(t.rec[i * S + D]));
           flag_st(conn + node, 1u);
         } else if (full) {
           uf_union_from(parent, myroot, gfirst);
