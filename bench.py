@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 BATCH_SETS = 256
 
 
-# Hardware counters of the kNN traversal kernel (k_knn_lane<3,32>, one launch
+# Hardware counters of the kNN traversal kernel (k_knn_lane<3,32,false>, one launch
 # over the 2^22 queries), taken with rocprofv3 --pmc on MI355X: FETCH_SIZE
 # and WRITE_SIZE (KiB per dispatch) in two runs, FETCH_SIZE scaled by 2.0 and
 # WRITE_SIZE by 1.0 -- the factors that turn the same counters of a plain
@@ -50,8 +50,8 @@ BATCH_SETS = 256
 KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
                 "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
-    "sha256": "f5d4738d977d353db2fb80538794c1a9583d729f4e2421d7af3cee600efbc81b",
-    "hbm_bytes": 2.1447e+09,
+    "sha256": "42b30de2de1895a4785badc0171d247d39213628ac90c0a579adf41741e19396",
+    "hbm_bytes": 2.1444e+09,
     "l2_hit_rate": 0.964,
     "valu_issue_frac": 0.71,
 }
@@ -282,7 +282,7 @@ def main():
         "p2m_bwd_over_fwd": avg["p2m_bwd"] / avg["p2m_fwd"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_knn_lane<3,32> (kNN traversal, k=32, one query per lane): "
+                     "kernel": "k_knn_lane<3,32,false> (kNN traversal, k=32, one query per lane): "
                                "compulsory bytes 4d + 8k = 268 per query"},
     }
     if KNN_COUNTERS["sha256"] and sources_hash(KNN_COUNTERS["sources"]) == KNN_COUNTERS["sha256"]:
