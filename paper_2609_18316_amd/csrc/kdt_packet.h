@@ -306,6 +306,28 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
   }
 }
 
+// A subtree of the ball count handed from one wave to a later pass: the
+// 64-query group, the subtree's root and the lanes whose ball cuts it.
+struct RangeTask {
+  uint32_t group, node, lo, hi;
+};
+constexpr uint32_t kNoNode = 0xFFFFFFFFu;  // a reserved task slot left empty
+constexpr uint32_t kRangeSplitLevels = 4;  // subtrees of fewer leaves are never handed on
+
+// Where a traversal that exceeds its budget of node visits leaves the rest of
+// its stack (buf == nullptr: no budget).  With `done` set, it hands work on
+// only once *done >= tail_from: while enough waves are still to start, a
+// heavy wave costs no time at the end of the launch, and a hand-off (its
+// atomics and the extra passes) would.
+struct RangeSpill {
+  RangeTask* buf;
+  uint32_t* count;  // tasks reserved so far (may exceed cap: the excess is not written)
+  uint32_t cap;
+  uint32_t budget;
+  const uint32_t* done;  // waves of the launch that have finished, or nullptr
+  uint32_t tail_from;
+};
+
 // LDS floats of one wave of the ball count: the open leaf, then the packed
 // queries [64][D] and their counts [64].
 template <int D>
@@ -326,10 +348,20 @@ __host__ __device__ constexpr size_t range_wave_floats(int leaf) {
 // queries per step, W the leaf size rounded up to a power of two, each lane
 // holding one point; a query's count is the population of its lanes' ballot.
 // The distances are the same float32 expressions either way.
+//
+// The traversal starts at `start` for the lanes of `start_mask`.  In a dense
+// halo the balls of one wave can hold millions of points while most waves
+// finish within a few hundred node visits, and that one wave would set the
+// length of the whole launch.  So a wave that has visited `budget` nodes
+// writes its remaining stack entries (entry i sits in lane i) as tasks for a
+// later pass and returns its partial counts; the later passes add theirs, so
+// every count is the same integer sum.
 template <int D>
 __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const float p[D],
                                                       bool active, float r2, float* lds,
-                                                      int leaf_cap) {
+                                                      int leaf_cap, uint32_t start,
+                                                      uint64_t start_mask, uint32_t group,
+                                                      const RangeSpill& spill) {
   constexpr int S = rec_stride(D);
   const int lane = lane_id();
   LeafReader<D> leaf(t.rec, lds);
@@ -337,10 +369,44 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
   int32_t* cc = reinterpret_cast<int32_t*>(cq + 64 * D);  // their counts [64]
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   int64_t count = 0;
-  uint32_t stackv = 0;                              // lane i: node of entry i
-  uint32_t stk_lo = 0xFFFFFFFFu, stk_hi = 0xFFFFFFFFu;  // lane i: lane mask of entry i
+  uint32_t stackv = start;                         // lane i: node of entry i
+  uint32_t stk_lo = (uint32_t)start_mask;          // lane i: lane mask of entry i
+  uint32_t stk_hi = (uint32_t)(start_mask >> 32);
   int sp = 1;
+  uint32_t left = spill.buf ? spill.budget : 0xFFFFFFFFu;  // node visits before handing off
   while (sp > 0) {
+    if (left == 0) {
+      // Entries deepen from the bottom of the stack to its top; hand on the
+      // bottom ones whose subtrees span at least 2^kRangeSplitLevels leaves
+      // and keep the small ones here.
+      const int big_level = t.levels - (int)kRangeSplitLevels;
+      const bool tail = spill.done == nullptr ||
+                        __hip_atomic_load(spill.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                            spill.tail_from;
+      const int nbig =
+          tail ? __popcll(__ballot(lane < sp && node_level(stackv) <= big_level)) : 0;
+      left = spill.budget;
+      if (nbig > 0) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(spill.count, (uint32_t)nbig);
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+        if ((uint64_t)base + (uint32_t)nbig <= spill.cap) {
+          if (lane < nbig) spill.buf[base + lane] = RangeTask{group, stackv, stk_lo, stk_hi};
+          if (nbig == sp) return count;
+          const int from = min(lane + nbig, 63);
+          stackv = (uint32_t)__shfl((int)stackv, from);
+          stk_lo = (uint32_t)__shfl((int)stk_lo, from);
+          stk_hi = (uint32_t)__shfl((int)stk_hi, from);
+          sp -= nbig;
+        } else {
+          // no room: leave the reserved slots empty and finish here
+          if (lane < nbig && (uint64_t)base + lane < spill.cap)
+            spill.buf[base + lane] = RangeTask{group, kNoNode, 0u, 0u};
+          left = 0xFFFFFFFFu;
+        }
+      }
+    }
+    --left;
     --sp;
     const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)stackv, sp);
     const uint64_t live = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)stk_hi, sp) << 32) |

@@ -7,6 +7,18 @@
 namespace kdt {
 
 constexpr int kPWaves = 4;  // waves per workgroup (independent packets)
+// Ball-count work splitting: passes; node visits per wave before it hands the
+// rest of its stack on, in the first pass (where most waves are light and a
+// hand-off costs atomics) and in the later ones; task slots per pass;
+// workgroups of a task pass.
+constexpr int kRangePasses = 8;
+constexpr uint32_t kRangeBudgetFirst = 512;
+constexpr uint32_t kRangeBudget = 512;
+constexpr uint32_t kRangeTaskCap = 1u << 20;
+constexpr unsigned kRangeTaskBlocks = 8192;
+// The first pass hands work on only once fewer than this many of its waves
+// are left (about what the chip holds at once).
+constexpr int64_t kRangeTailWaves = 8192;
 
 // LDS of a workgroup: a leaf slice per wave.
 template <int D>
@@ -62,12 +74,14 @@ __global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const f
   if (active) knn_write<KC>(best, k, MODE, row, oidx, od2);
 }
 
+// First pass of the ball counts: one 64-query group per wave from the root;
+// writes each count (partial if the wave handed subtrees on).
 template <int D>
 __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const float* __restrict__ q,
                                                                int64_t nq, float r2,
                                                                const int32_t* __restrict__ order,
                                                                int32_t* __restrict__ count,
-                                                               int leaf_cap) {
+                                                               int leaf_cap, RangeSpill spill) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s0 = (xcd_block<kXcdRunPacket>() * kPWaves + wave) * 64;
@@ -77,8 +91,38 @@ __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const
   const bool active = load_query<D>(t, q, nq, order, s0 + lane, p, row);
   const int64_t c = packet_range_count<D>(t, p, active, r2,
                                           lds + (size_t)wave * range_wave_floats<D>(leaf_cap),
-                                          leaf_cap);
+                                          leaf_cap, 0u, ~0ull, (uint32_t)(s0 / 64), spill);
   if (active) count[row] = (int32_t)c;
+  if (lane == 0) atomicAdd(const_cast<uint32_t*>(spill.done), 1u);
+}
+
+// A later pass: each wave takes tasks left by the previous pass (a fixed
+// count, read at start, so every wave's loop ends) and adds its counts.
+template <int D>
+__global__ __launch_bounds__(64 * kPWaves) void k_range_tasks(
+    TreeView t, const float* __restrict__ q, int64_t nq, float r2,
+    const int32_t* __restrict__ order, int32_t* __restrict__ count, int leaf_cap,
+    const RangeTask* __restrict__ in, const uint32_t* __restrict__ in_count, uint32_t in_cap,
+    RangeSpill spill) {
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t n = min(*in_count, in_cap);
+  float* slice = lds + (size_t)wave * range_wave_floats<D>(leaf_cap);
+  for (uint32_t k = blockIdx.x * kPWaves + wave; k < n; k += gridDim.x * kPWaves) {
+    const RangeTask task = in[k];
+    if (task.node == kNoNode) continue;
+    float p[D];
+    int64_t row = 0;
+    const bool active = load_query<D>(t, q, nq, order, (int64_t)task.group * 64 + lane, p, row);
+    const uint64_t mask = ((uint64_t)task.hi << 32) | task.lo;
+    const int64_t c = packet_range_count<D>(t, p, active, r2, slice, leaf_cap, task.node, mask,
+                                            task.group, spill);
+    if (active && c != 0) atomicAdd(count + row, (int32_t)c);
+  }
+}
+
+__global__ void k_zero_tasks(uint32_t* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
 }
 
 template <int D>
@@ -152,7 +196,33 @@ kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, in
                                const int32_t* order, int32_t* d_count, hipStream_t stream) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
   const size_t smem = sizeof(float) * range_wave_floats<D>(leaf) * kPWaves;
-  k_range_packet<D><<<grid, 64 * kPWaves, smem, stream>>>(v, d_q, nq, r2, order, d_count, leaf);
+  // Heavy traversals are split over kRangePasses launches: the first kRangePasses - 1
+  // hand off what exceeds kRangeBudget node visits, the last finishes everything.
+  PoolBuffers buf(stream);
+  RangeTask* tasks = nullptr;
+  uint32_t* counts = nullptr;
+  // counts[0 .. kRangePasses - 1): tasks per pass; counts[kRangePasses]: finished
+  // waves of the first pass
+  if (!buf.get(&tasks, (size_t)kRangeTaskCap * (kRangePasses - 1)) ||
+      !buf.get(&counts, kRangePasses + 1)) {
+    kdt_set_error("device allocation failed for the ball-count task lists");
+    return KDT_ENOMEM;
+  }
+  k_zero_tasks<<<1, 64, 0, stream>>>(counts, kRangePasses + 1);
+  const int64_t waves = (nq + 63) / 64;
+  const uint32_t tail_from = waves > kRangeTailWaves ? (uint32_t)(waves - kRangeTailWaves) : 0u;
+  k_range_packet<D><<<grid, 64 * kPWaves, smem, stream>>>(
+      v, d_q, nq, r2, order, d_count, leaf,
+      RangeSpill{tasks, counts, kRangeTaskCap, kRangeBudgetFirst, counts + kRangePasses, tail_from});
+  for (int pass = 1; pass < kRangePasses; ++pass) {
+    const bool last = pass == kRangePasses - 1;
+    const RangeSpill out = last ? RangeSpill{nullptr, nullptr, 0u, 0u, nullptr, 0u}
+                                : RangeSpill{tasks + (size_t)pass * kRangeTaskCap, counts + pass,
+                                             kRangeTaskCap, kRangeBudget, nullptr, 0u};
+    k_range_tasks<D><<<kRangeTaskBlocks, 64 * kPWaves, smem, stream>>>(
+        v, d_q, nq, r2, order, d_count, leaf, tasks + (size_t)(pass - 1) * kRangeTaskCap,
+        counts + pass - 1, kRangeTaskCap, out);
+  }
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_range: packet kernel launch failed");
     return KDT_EDEVICE;

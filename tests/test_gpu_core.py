@@ -282,3 +282,23 @@ def test_range_counts_clustered_overlapping_balls(leaf):
         say(f"clustered range leaf={leaf} r={r}")
         np.testing.assert_array_equal(to_host(t.range(to_dev(q), r)), ot.range(q, r))
         np.testing.assert_array_equal(to_host(t.range(None, r)), ot.range(x, r))
+
+
+def test_range_counts_dense_cluster_split_traversals():
+    """Balls of a wave inside one dense cluster cut thousands of leaves, so
+    waves exceed their node-visit budget and hand subtrees to later passes:
+    every count must still be the exact integer sum."""
+    dev()
+    rng = np.random.Generator(np.random.PCG64(45))
+    x = (0.5 + 0.01 * rng.standard_normal((300000, 3))).astype(np.float32)
+    q = (0.5 + 0.03 * (rng.random((8192, 3)) - 0.5)).astype(np.float32)
+    t = kdt.build(to_dev(x), leaf_size=32)
+    ot = oracle.Tree(x, 32)
+    for r in (0.002, 0.004):
+        say(f"dense-cluster range r={r}")
+        np.testing.assert_array_equal(to_host(t.range(to_dev(q), r)), ot.range(q, r))
+        np.testing.assert_array_equal(to_host(t.range(None, r)), ot.range(x, r))
+        c, off, lst = t.range(to_dev(q[:512]), r, lists=True)
+        oc, ooff, olst = ot.range(q[:512], r, lists=True)
+        np.testing.assert_array_equal(to_host(c), oc)
+        np.testing.assert_array_equal(to_host(lst), olst)
