@@ -306,27 +306,79 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
   }
 }
 
-// A subtree of the ball count handed from one wave to a later pass: the
-// 64-query group, the subtree's root and the lanes whose ball cuts it.
-struct RangeTask {
+// A subtree of the wave-shared ball count handed from
+// one wave to a later pass: the 64-query group, the subtree's root and the
+// lanes that still need it.
+struct PacketTask {
   uint32_t group, node, lo, hi;
 };
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;  // a reserved task slot left empty
-constexpr uint32_t kRangeSplitLevels = 4;  // subtrees of fewer leaves are never handed on
+constexpr uint32_t kSplitLevels = 4;       // subtrees of fewer leaves are never handed on
 
 // Where a traversal that exceeds its budget of node visits leaves the rest of
 // its stack (buf == nullptr: no budget).  With `done` set, it hands work on
-// only once *done >= tail_from: while enough waves are still to start, a
-// heavy wave costs no time at the end of the launch, and a hand-off (its
-// atomics and the extra passes) would.
-struct RangeSpill {
-  RangeTask* buf;
+// only once the finished waves reach tail_from: while enough waves are still
+// to start, a heavy wave costs no time at the end of the launch, and a
+// hand-off (its atomics and the extra passes) would.  Finished waves are
+// counted in kDoneShards counters (workgroup b adds to b % kDoneShards), so
+// that the count itself does not serialise the launch.
+constexpr int kDoneShards = 32;
+struct PacketSpill {
+  PacketTask* buf;
   uint32_t* count;  // tasks reserved so far (may exceed cap: the excess is not written)
   uint32_t cap;
   uint32_t budget;
-  const uint32_t* done;  // waves of the launch that have finished, or nullptr
+  uint32_t* done;  // [kDoneShards] finished waves of the launch, or nullptr
   uint32_t tail_from;
 };
+
+// A wave of a launch with a tail test reports that it has finished.
+__device__ __forceinline__ void wave_done(const PacketSpill& spill) {
+  if (spill.done && lane_id() == 0) atomicAdd(spill.done + blockIdx.x % kDoneShards, 1u);
+}
+
+// Called by a wave whose budget of node visits is used up (left == 0).  In
+// the launch's tail it hands the bottom entries of its stack whose subtrees
+// span at least 2^kSplitLevels leaves on as tasks (entries deepen from the
+// bottom of the stack to its top, and entry i sits in lane i, so each lane
+// writes one task) and keeps the smaller ones.  Resets the budget; returns
+// true when nothing is left to do here.
+__device__ __forceinline__ bool hand_off(const PacketSpill& spill, int levels, uint32_t group,
+                                         uint32_t& stackv, uint32_t& stk_lo, uint32_t& stk_hi,
+                                         int& sp, uint32_t& left) {
+  const int lane = lane_id();
+  const int big_level = levels - (int)kSplitLevels;
+  bool tail = true;
+  if (spill.done) {
+    int d = lane < kDoneShards ? (int)__hip_atomic_load(spill.done + lane, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+                               : 0;
+#pragma unroll
+    for (int o = kDoneShards / 2; o > 0; o >>= 1) d += __shfl_xor(d, o);  // lane 0: all shards
+    tail = (uint32_t)__builtin_amdgcn_readfirstlane(d) >= spill.tail_from;
+  }
+  const int nbig = tail ? __popcll(__ballot(lane < sp && node_level(stackv) <= big_level)) : 0;
+  left = spill.budget;
+  if (nbig == 0) return false;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(spill.count, (uint32_t)nbig);
+  base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+  if ((uint64_t)base + (uint32_t)nbig > spill.cap) {
+    // no room: leave the reserved slots empty and finish here
+    if (lane < nbig && (uint64_t)base + lane < spill.cap)
+      spill.buf[base + lane] = PacketTask{group, kNoNode, 0u, 0u};
+    left = 0xFFFFFFFFu;
+    return false;
+  }
+  if (lane < nbig) spill.buf[base + lane] = PacketTask{group, stackv, stk_lo, stk_hi};
+  if (nbig == sp) return true;
+  const int from = min(lane + nbig, 63);
+  stackv = (uint32_t)__shfl((int)stackv, from);
+  stk_lo = (uint32_t)__shfl((int)stk_lo, from);
+  stk_hi = (uint32_t)__shfl((int)stk_hi, from);
+  sp -= nbig;
+  return false;
+}
 
 // LDS floats of one wave of the ball count: the open leaf, then the packed
 // queries [64][D] and their counts [64].
@@ -361,7 +413,7 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
                                                       bool active, float r2, float* lds,
                                                       int leaf_cap, uint32_t start,
                                                       uint64_t start_mask, uint32_t group,
-                                                      const RangeSpill& spill) {
+                                                      const PacketSpill& spill) {
   constexpr int S = rec_stride(D);
   const int lane = lane_id();
   LeafReader<D> leaf(t.rec, lds);
@@ -375,37 +427,8 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
   int sp = 1;
   uint32_t left = spill.buf ? spill.budget : 0xFFFFFFFFu;  // node visits before handing off
   while (sp > 0) {
-    if (left == 0) {
-      // Entries deepen from the bottom of the stack to its top; hand on the
-      // bottom ones whose subtrees span at least 2^kRangeSplitLevels leaves
-      // and keep the small ones here.
-      const int big_level = t.levels - (int)kRangeSplitLevels;
-      const bool tail = spill.done == nullptr ||
-                        __hip_atomic_load(spill.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-                            spill.tail_from;
-      const int nbig =
-          tail ? __popcll(__ballot(lane < sp && node_level(stackv) <= big_level)) : 0;
-      left = spill.budget;
-      if (nbig > 0) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(spill.count, (uint32_t)nbig);
-        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-        if ((uint64_t)base + (uint32_t)nbig <= spill.cap) {
-          if (lane < nbig) spill.buf[base + lane] = RangeTask{group, stackv, stk_lo, stk_hi};
-          if (nbig == sp) return count;
-          const int from = min(lane + nbig, 63);
-          stackv = (uint32_t)__shfl((int)stackv, from);
-          stk_lo = (uint32_t)__shfl((int)stk_lo, from);
-          stk_hi = (uint32_t)__shfl((int)stk_hi, from);
-          sp -= nbig;
-        } else {
-          // no room: leave the reserved slots empty and finish here
-          if (lane < nbig && (uint64_t)base + lane < spill.cap)
-            spill.buf[base + lane] = RangeTask{group, kNoNode, 0u, 0u};
-          left = 0xFFFFFFFFu;
-        }
-      }
-    }
+    if (left == 0 && hand_off(spill, t.levels, group, stackv, stk_lo, stk_hi, sp, left))
+      return count;
     --left;
     --sp;
     const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)stackv, sp);

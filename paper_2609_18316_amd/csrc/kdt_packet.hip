@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const
                                                                int64_t nq, float r2,
                                                                const int32_t* __restrict__ order,
                                                                int32_t* __restrict__ count,
-                                                               int leaf_cap, RangeSpill spill) {
+                                                               int leaf_cap, PacketSpill spill) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s0 = (xcd_block<kXcdRunPacket>() * kPWaves + wave) * 64;
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const
                                           lds + (size_t)wave * range_wave_floats<D>(leaf_cap),
                                           leaf_cap, 0u, ~0ull, (uint32_t)(s0 / 64), spill);
   if (active) count[row] = (int32_t)c;
-  if (lane == 0) atomicAdd(const_cast<uint32_t*>(spill.done), 1u);
+  wave_done(spill);
 }
 
 // A later pass: each wave takes tasks left by the previous pass (a fixed
@@ -102,14 +102,14 @@ template <int D>
 __global__ __launch_bounds__(64 * kPWaves) void k_range_tasks(
     TreeView t, const float* __restrict__ q, int64_t nq, float r2,
     const int32_t* __restrict__ order, int32_t* __restrict__ count, int leaf_cap,
-    const RangeTask* __restrict__ in, const uint32_t* __restrict__ in_count, uint32_t in_cap,
-    RangeSpill spill) {
+    const PacketTask* __restrict__ in, const uint32_t* __restrict__ in_count, uint32_t in_cap,
+    PacketSpill spill) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t n = min(*in_count, in_cap);
   float* slice = lds + (size_t)wave * range_wave_floats<D>(leaf_cap);
   for (uint32_t k = blockIdx.x * kPWaves + wave; k < n; k += gridDim.x * kPWaves) {
-    const RangeTask task = in[k];
+    const PacketTask task = in[k];
     if (task.node == kNoNode) continue;
     float p[D];
     int64_t row = 0;
@@ -199,25 +199,25 @@ kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, in
   // Heavy traversals are split over kRangePasses launches: the first kRangePasses - 1
   // hand off what exceeds kRangeBudget node visits, the last finishes everything.
   PoolBuffers buf(stream);
-  RangeTask* tasks = nullptr;
+  PacketTask* tasks = nullptr;
   uint32_t* counts = nullptr;
-  // counts[0 .. kRangePasses - 1): tasks per pass; counts[kRangePasses]: finished
-  // waves of the first pass
+  // counts[0 .. kRangePasses - 1): tasks per pass; then the first pass's
+  // finished-wave counters
   if (!buf.get(&tasks, (size_t)kRangeTaskCap * (kRangePasses - 1)) ||
-      !buf.get(&counts, kRangePasses + 1)) {
+      !buf.get(&counts, kRangePasses + kDoneShards)) {
     kdt_set_error("device allocation failed for the ball-count task lists");
     return KDT_ENOMEM;
   }
-  k_zero_tasks<<<1, 64, 0, stream>>>(counts, kRangePasses + 1);
+  k_zero_tasks<<<1, 64, 0, stream>>>(counts, kRangePasses + kDoneShards);
   const int64_t waves = (nq + 63) / 64;
   const uint32_t tail_from = waves > kRangeTailWaves ? (uint32_t)(waves - kRangeTailWaves) : 0u;
   k_range_packet<D><<<grid, 64 * kPWaves, smem, stream>>>(
       v, d_q, nq, r2, order, d_count, leaf,
-      RangeSpill{tasks, counts, kRangeTaskCap, kRangeBudgetFirst, counts + kRangePasses, tail_from});
+      PacketSpill{tasks, counts, kRangeTaskCap, kRangeBudgetFirst, counts + kRangePasses, tail_from});
   for (int pass = 1; pass < kRangePasses; ++pass) {
     const bool last = pass == kRangePasses - 1;
-    const RangeSpill out = last ? RangeSpill{nullptr, nullptr, 0u, 0u, nullptr, 0u}
-                                : RangeSpill{tasks + (size_t)pass * kRangeTaskCap, counts + pass,
+    const PacketSpill out = last ? PacketSpill{nullptr, nullptr, 0u, 0u, nullptr, 0u}
+                                : PacketSpill{tasks + (size_t)pass * kRangeTaskCap, counts + pass,
                                              kRangeTaskCap, kRangeBudget, nullptr, 0u};
     k_range_tasks<D><<<kRangeTaskBlocks, 64 * kPWaves, smem, stream>>>(
         v, d_q, nq, r2, order, d_count, leaf, tasks + (size_t)(pass - 1) * kRangeTaskCap,
