@@ -51,9 +51,9 @@ KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
                 "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
     "sha256": "42b30de2de1895a4785badc0171d247d39213628ac90c0a579adf41741e19396",
-    "hbm_bytes": 2.1444e+09,
+    "hbm_bytes": 2.1452e+09,
     "l2_hit_rate": 0.964,
-    "valu_issue_frac": 0.71,
+    "valu_issue_frac": 0.72,
 }
 
 

@@ -313,7 +313,7 @@ struct PacketTask {
   uint32_t group, node, lo, hi;
 };
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;  // a reserved task slot left empty
-constexpr uint32_t kSplitLevels = 4;       // subtrees of fewer leaves are never handed on
+constexpr uint32_t kSplitLevels = 2;       // subtrees of fewer leaves are never handed on
 
 // Where a traversal that exceeds its budget of node visits leaves the rest of
 // its stack (buf == nullptr: no budget).  With `done` set, it hands work on

@@ -13,7 +13,7 @@ constexpr int kPWaves = 4;  // waves per workgroup (independent packets)
 // workgroups of a task pass.
 constexpr int kRangePasses = 8;
 constexpr uint32_t kRangeBudgetFirst = 512;
-constexpr uint32_t kRangeBudget = 512;
+constexpr uint32_t kRangeBudget = 32;
 constexpr uint32_t kRangeTaskCap = 1u << 20;
 constexpr unsigned kRangeTaskBlocks = 8192;
 // The first pass hands work on only once fewer than this many of its waves
