@@ -174,6 +174,10 @@ kdt_status kdt_knn(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t k
  * required  host, may be NULL: receives the total list length (list mode).
  * nq = 0 is an empty query set: d_q and d_count may be NULL; d_offsets, if
  * given, receives its single 0 and *required 0.
+ * Scratch (the query order, and about 120 MB of task lists through which
+ * heavy traversals are split over several launches) comes from the
+ * stream-ordered pool and is released in stream order.  Counts are exact
+ * integers however the work was split.
  *
  * Errors: KDT_EINVAL, KDT_ECAPACITY (total > capacity; *required is set and
  * d_count / d_offsets are valid), KDT_ENOMEM, KDT_EDEVICE.
