@@ -252,10 +252,10 @@ kdt_status kdt_p2m_backward(const float *d_x, const float *d_m, const float *d_h
  * through kdt_query_opts.order (the queries calls then skip their own sort).
  * kind 0: for d <= 4 the order of a Hilbert curve over the root bounding box
  *   (30 / d bits per axis), computed without touching the tree -- the order
- *   kdt_knn uses with one traversal per lane; above d = 4 as kind 1.
+ *   kdt_knn uses with one traversal per lane, and kdt_range; above d = 4 as
+ *   kind 1.
  * kind 1: queries sorted by the leaf reached when descending towards the
- *   nearer child at every level -- the order the wave-shared traversals (ball
- *   counts, wave-packet kNN) use.
+ *   nearer child at every level -- the order the wave-packet kNN uses.
  * Results of the queries never depend on the order, only their speed.
  * nq = 0 does nothing (pointers may be NULL).
  * Errors: KDT_EINVAL (NULL pointer, nq outside [0, 2^31-1], other kind),

@@ -238,11 +238,13 @@ static TreeView view_of(const kdt_tree* t) {
 // Sorts external queries along the tree's space (a Hilbert key for D <= 4,
 // else the leaf they fall in); returns the order array (caller frees with
 // hipFreeAsync).
-// kind 0: a Hilbert key over the root box for D <= 4 (cheap; what one
-// traversal per lane needs), else the tree leaf; kind 1: the tree leaf (what
-// wave-shared traversals need: a wave's queries then sit in one subtree --
-// for ball counts on the clustered workload 25.5 ms against 48 ms with a
-// Hilbert or Morton order, while per-lane kNN runs equally fast on both).
+// kind 0: a Hilbert key over the root box for D <= 4 (cheap: no tree walk;
+// what one traversal per lane and the ball counts use), else the tree leaf;
+// kind 1: the tree leaf (a wave's queries then sit in one subtree; what the
+// wave-packet kNN uses).  Ball counts on the clustered workload took 25.5 ms
+// in leaf order against 48 ms in Hilbert order before heavy traversals were
+// split over several launches; with that splitting Hilbert order is the
+// faster one (3.3 against 4.1 ms, and its key costs 0.24 against 0.69 ms).
 // Writes the permutation to `dst` if given, else to a new buffer *out.
 template <int D>
 static kdt_status order_queries(const kdt_tree* t, const float* d_q, int64_t nq, int kind,
@@ -337,7 +339,7 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
                              int traversal, hipStream_t stream) {
   int32_t* own = nullptr;
   if (d_q && !given && sort_q && nq > 1) {
-    kdt_status st = order_queries<D>(t, d_q, nq, 1, &own, stream);
+    kdt_status st = order_queries<D>(t, d_q, nq, 0, &own, stream);
     if (st != KDT_OK) return st;
   }
   const int32_t* order = d_q ? (given ? given : own) : nullptr;

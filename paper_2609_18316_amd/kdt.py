@@ -161,7 +161,7 @@ class Tree:
         """Permutation of the queries along the tree (reusable through ``order=``).
 
         kind 0: Hilbert curve over the root box (d <= 4), the order of per-lane
-        kNN; kind 1: tree-leaf order, the order of ball counts and wave packets.
+        kNN and ball counts; kind 1: tree-leaf order, the order of wave-packet kNN.
         """
         nq = queries.shape[0]
         queries = _dev(queries, torch.float32, "queries", (nq, self.d))
