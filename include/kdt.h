@@ -73,6 +73,14 @@ typedef struct {
                              identical either way. */
     const int32_t *order; /* NULL, or a device permutation [nq] from
                              kdt_query_order to use instead of sorting again. */
+    int32_t split_budget; /* Ball counts with traversal 2.  0: default (a wave
+                             still running in the launch's tail hands the big
+                             subtrees of its stack on to later launches after
+                             512 node visits, then every 32).  > 0: every wave
+                             hands subtrees on after this many visits, in
+                             every launch.  Results are identical either way;
+                             it exists for tuning and for testing the
+                             hand-off.  Negative: KDT_EINVAL. */
 } kdt_query_opts;
 
 /* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side

@@ -193,7 +193,8 @@ kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int6
 
 template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
-                               const int32_t* order, int32_t* d_count, hipStream_t stream) {
+                               const int32_t* order, int32_t* d_count, uint32_t split_budget,
+                               hipStream_t stream) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
   const size_t smem = sizeof(float) * range_wave_floats<D>(leaf) * kPWaves;
   // Heavy traversals are split over kRangePasses launches: the first kRangePasses - 1
@@ -209,16 +210,21 @@ kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, in
     return KDT_ENOMEM;
   }
   k_zero_tasks<<<1, 64, 0, stream>>>(counts, kRangePasses + kDoneShards);
+  // a caller's budget applies to every wave of every launch
+  const uint32_t first = split_budget ? split_budget : kRangeBudgetFirst;
+  const uint32_t later = split_budget ? split_budget : kRangeBudget;
   const int64_t waves = (nq + 63) / 64;
-  const uint32_t tail_from = waves > kRangeTailWaves ? (uint32_t)(waves - kRangeTailWaves) : 0u;
+  const uint32_t tail_from = split_budget                ? 0u
+                             : waves > kRangeTailWaves ? (uint32_t)(waves - kRangeTailWaves)
+                                                       : 0u;
   k_range_packet<D><<<grid, 64 * kPWaves, smem, stream>>>(
       v, d_q, nq, r2, order, d_count, leaf,
-      PacketSpill{tasks, counts, kRangeTaskCap, kRangeBudgetFirst, counts + kRangePasses, tail_from});
+      PacketSpill{tasks, counts, kRangeTaskCap, first, counts + kRangePasses, tail_from});
   for (int pass = 1; pass < kRangePasses; ++pass) {
     const bool last = pass == kRangePasses - 1;
     const PacketSpill out = last ? PacketSpill{nullptr, nullptr, 0u, 0u, nullptr, 0u}
                                 : PacketSpill{tasks + (size_t)pass * kRangeTaskCap, counts + pass,
-                                             kRangeTaskCap, kRangeBudget, nullptr, 0u};
+                                             kRangeTaskCap, later, nullptr, 0u};
     k_range_tasks<D><<<kRangeTaskBlocks, 64 * kPWaves, smem, stream>>>(
         v, d_q, nq, r2, order, d_count, leaf, tasks + (size_t)(pass - 1) * kRangeTaskCap,
         counts + pass - 1, kRangeTaskCap, out);
@@ -234,7 +240,7 @@ kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, in
   template kdt_status knn_packet_launch<D>(const TreeView&, int, const float*, int64_t, int,       \
                                            int32_t*, float*, int, const int32_t*, hipStream_t);    \
   template kdt_status range_packet_launch<D>(const TreeView&, int, const float*, int64_t, float,   \
-                                             const int32_t*, int32_t*, hipStream_t);             \
+                                             const int32_t*, int32_t*, uint32_t, hipStream_t);   \
   template kdt_status fof_packet_launch<D>(const TreeView&, int, float, int32_t*, uint32_t*,       \
                                            hipStream_t);
 KDT_INST(2)

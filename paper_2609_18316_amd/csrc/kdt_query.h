@@ -538,7 +538,8 @@ kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int6
                              hipStream_t stream);
 template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
-                               const int32_t* order, int32_t* d_count, hipStream_t stream);
+                               const int32_t* order, int32_t* d_count, uint32_t split_budget,
+                               hipStream_t stream);
 template <int D>
 kdt_status fof_packet_launch(const TreeView& v, int leaf, float l2, int32_t* parent, uint32_t* conn,
                              hipStream_t stream);

@@ -336,7 +336,7 @@ template <int D>
 static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, float r,
                              int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
                              int64_t* required, bool sort_q, const int32_t* given,
-                             int traversal, hipStream_t stream) {
+                             int traversal, uint32_t split_budget, hipStream_t stream) {
   int32_t* own = nullptr;
   if (d_q && !given && sort_q && nq > 1) {
     kdt_status st = order_queries<D>(t, d_q, nq, 0, &own, stream);
@@ -350,7 +350,7 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
   const size_t rsmem = sizeof(uint32_t) * (size_t)(t->levels + 2) * kQBlock;
   kdt_status st = KDT_OK;
   if (t->leaf <= 64 && traversal != 1)
-    st = range_packet_launch<D>(v, t->leaf, d_q, nq, r2, order, d_count, stream);
+    st = range_packet_launch<D>(v, t->leaf, d_q, nq, r2, order, d_count, split_budget, stream);
   else
     k_range<D, false><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
   if (st != KDT_OK) {
@@ -523,6 +523,11 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
     kdt_set_error("kdt_range: lists need d_offsets");
     return KDT_EINVAL;
   }
+  if (opts && opts->split_budget < 0) {
+    kdt_set_error("kdt_range: split_budget must be >= 0");
+    return KDT_EINVAL;
+  }
+  const uint32_t budget = opts ? (uint32_t)opts->split_budget : 0u;
   if (nq > INT32_MAX && d_offsets) {
     kdt_set_error("kdt_range: list mode supports at most 2^31-1 queries");
     return KDT_EUNSUPPORTED;
@@ -541,11 +546,11 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
   }
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
   switch (tree->d) {
-    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
-    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
-    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
-    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
-    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, stream);
+    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
+    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
+    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
+    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
+    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
   }
   kdt_set_error("kdt_range: unsupported dimension %d", tree->d);
   return KDT_EUNSUPPORTED;

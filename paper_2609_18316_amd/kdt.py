@@ -38,7 +38,8 @@ class BuildOpts(C.Structure):
 
 
 class QueryOpts(C.Structure):
-    _fields_ = [("sort_queries", C.c_int32), ("traversal", C.c_int32), ("order", C.c_void_p)]
+    _fields_ = [("sort_queries", C.c_int32), ("traversal", C.c_int32), ("order", C.c_void_p),
+                ("split_budget", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -195,12 +196,17 @@ class Tree:
 
     def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
               sort_queries: bool = True, order: torch.Tensor | None = None, traversal: int = 0,
-              stream=None):
-        """Closed-ball counts; with ``lists`` also CSR (offsets int64, idx int32)."""
+              split_budget: int = 0, stream=None):
+        """Closed-ball counts; with ``lists`` also CSR (offsets int64, idx int32).
+
+        ``split_budget`` > 0 makes every wave of the wave-shared count hand
+        subtrees on to later launches after that many node visits (results are
+        identical; 0 keeps the default schedule).
+        """
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order))
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), int(split_budget))
         count = torch.empty(nq, dtype=torch.int32, device=self.device)
         lib = load()
         if not lists:

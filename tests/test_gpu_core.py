@@ -118,6 +118,8 @@ def test_unsorted_queries_give_the_same_answer():
                                       to_host(t.range(to_dev(q), 0.02, sort_queries=False)))
     with pytest.raises(kdt.KdtError):
         t.query_order(to_dev(q), kind=2)
+    with pytest.raises(kdt.KdtError):
+        t.range(to_dev(q), 0.02, split_budget=-1)
 
 
 @pytest.mark.parametrize("d,levels", ((2, 4), (3, 3), (4, 2)))
@@ -176,6 +178,10 @@ def test_range_counts_and_lists(d):
                 np.testing.assert_array_equal(to_host(off), ooff)
                 np.testing.assert_array_equal(to_host(lst), olst)
                 np.testing.assert_array_equal(to_host(t.range(None, r)), ot.range(x, r))
+                if n == 20011:  # the same with every traversal handed on after 4 visits
+                    c, off, lst = t.range(to_dev(q), r, lists=True, split_budget=4)
+                    np.testing.assert_array_equal(to_host(c), oc)
+                    np.testing.assert_array_equal(to_host(lst), olst)
 
 
 def test_range_capacity_error_reports_required():
@@ -296,8 +302,12 @@ def test_range_counts_dense_cluster_split_traversals():
     ot = oracle.Tree(x, 32)
     for r in (0.002, 0.004):
         say(f"dense-cluster range r={r}")
-        np.testing.assert_array_equal(to_host(t.range(to_dev(q), r)), ot.range(q, r))
-        np.testing.assert_array_equal(to_host(t.range(None, r)), ot.range(x, r))
+        oq, ox = ot.range(q, r), ot.range(x, r)
+        np.testing.assert_array_equal(to_host(t.range(to_dev(q), r)), oq)
+        np.testing.assert_array_equal(to_host(t.range(None, r)), ox)
+        for budget in (1, 16, 100):  # every wave hands subtrees on, many times over
+            np.testing.assert_array_equal(to_host(t.range(to_dev(q), r, split_budget=budget)), oq)
+            np.testing.assert_array_equal(to_host(t.range(None, r, split_budget=budget)), ox)
         c, off, lst = t.range(to_dev(q[:512]), r, lists=True)
         oc, ooff, olst = ot.range(q[:512], r, lists=True)
         np.testing.assert_array_equal(to_host(c), oc)
