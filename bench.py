@@ -50,10 +50,10 @@ BATCH_SETS = 256
 KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
                 "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
-    "sha256": "e090725d951663ab850a69f9766c8a00b23b2ae81468565e3d7fe724dc322eec",
-    "hbm_bytes": 2.1434e+09,
+    "sha256": "cdec93fb39035b668859ab58156c046add96cb2dace928ccac6edfb9fa257ed8",
+    "hbm_bytes": 2.1460e+09,
     "l2_hit_rate": 0.964,
-    "valu_issue_frac": 0.71,
+    "valu_issue_frac": 0.72,
 }
 
 
