@@ -6,7 +6,8 @@ its Python binding) never calls it and shares no code with it.
 
 The arithmetic lives in ``kdt_oracle.c`` (plain single-threaded C, float32
 distances with no fused multiply-add, float64 particle-to-mesh).  This module
-only marshals numpy arrays through ctypes.
+marshals numpy arrays through ctypes; the box query, which has no arithmetic
+(coordinate comparisons only), is written out here with numpy.
 """
 from __future__ import annotations
 
@@ -113,6 +114,29 @@ def range_brute(pts, queries, r: float, lists: bool = False):
     _check(lib.orc_range_brute(pts, n, d, queries, nq, np.float32(r), count,
                                offsets.ctypes.data, idx.ctypes.data), "range_brute")
     return count, offsets, idx[:int(count.sum())]
+
+
+def box_brute(pts, lo, hi, lists: bool = False):
+    """Points inside closed axis-aligned boxes (the rectangular ranges of
+    Sec. 2.3): point x is in box i when lo[i][a] <= x[a] <= hi[i][a] on every
+    axis a.  A box with lo > hi on some axis, or with a NaN bound, holds no
+    point.  With ``lists`` also CSR (offsets int64, ascending input indices).
+    The definition written out, one box at a time; comparisons only."""
+    pts, lo, hi = _pts(pts), _pts(lo), _pts(hi)
+    nq = lo.shape[0]
+    counts = np.empty(nq, np.int64)
+    rows = []
+    for i in range(nq):
+        inside = np.all((pts >= lo[i]) & (pts <= hi[i]), axis=1)
+        idx = np.nonzero(inside)[0].astype(np.int32)
+        counts[i] = idx.size
+        if lists:
+            rows.append(idx)
+    if not lists:
+        return counts
+    offsets = np.zeros(nq + 1, np.int64)
+    offsets[1:] = np.cumsum(counts)
+    return counts, offsets, (np.concatenate(rows) if rows else np.empty(0, np.int32))
 
 
 def fof_brute(pts, l: float) -> np.ndarray:
