@@ -195,6 +195,32 @@ kdt_status kdt_range(const kdt_tree *tree, const float *d_q, int64_t nq, float r
                      int64_t *required, const kdt_query_opts *opts, hipStream_t stream);
 
 /*
+ * kdt_box -- axis-aligned box query: the rectangular ranges that Sec. 2.3
+ * names beside the ball query.  Point x is inside box i when
+ * d_lo[i][a] <= x[a] <= d_hi[i][a] on every axis a (closed on every side);
+ * a box with lo > hi on some axis, or with a NaN bound, holds no point.
+ *
+ * d_lo, d_hi [nq][d] float32 (device): the boxes' corners; infinite bounds
+ *           are allowed.
+ * d_count   [nq] int32: number of points in each box (required).
+ * d_offsets [nq + 1] int64, or NULL; with d_idx the call also returns the
+ *           input indices in CSR form, ascending within each row.  This mode
+ *           waits on `stream` once to learn the total size.
+ * capacity, required: as for kdt_range.
+ * opts      may be NULL; sort_queries orders the boxes by their centres along
+ *           the tree (results are identical either way); traversal and
+ *           split_budget are ignored.
+ * nq = 0 is an empty query set: d_lo, d_hi and d_count may be NULL.
+ * Scratch (the order, list staging) comes from the stream-ordered pool.
+ *
+ * Errors: KDT_EINVAL, KDT_ECAPACITY (total > capacity; *required is set and
+ * d_count / d_offsets are valid), KDT_EUNSUPPORTED, KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_box(const kdt_tree *tree, const float *d_lo, const float *d_hi, int64_t nq,
+                   int32_t *d_count, int64_t *d_offsets, int32_t *d_idx, int64_t capacity,
+                   int64_t *required, const kdt_query_opts *opts, hipStream_t stream);
+
+/*
  * kdt_fof -- friends-of-friends groups of the tree's points (Sec. 4.1).
  *
  * Points i != j are friends when d2(i, j) <= fl32(l * l); groups are the

@@ -1,0 +1,257 @@
+// kdt_box.hip -- axis-aligned box queries on gfx950: the rectangular ranges
+// that Sec. 2.3 names beside the ball query.  For each query box [lo, hi]
+// (closed on every axis) the number of tree points inside and, optionally,
+// their input indices in CSR form, ascending.  One traversal per lane, depth
+// first: a node whose tight box misses the query box is skipped, a node whose
+// box lies inside it is taken whole, leaves test their points.  Only
+// comparisons are involved, so the result is exact.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+
+#include "kdt_query.h"
+
+namespace kdt {
+
+constexpr int kBoxBlock = 128;
+
+// Counts (FILL = false) or writes the input indices of the points inside each
+// query box, from offsets[row] on (FILL = true).  The node-id stack lives in
+// LDS, levels + 2 entries per lane.
+template <int D, bool FILL>
+__global__ __launch_bounds__(kBoxBlock) void k_box(TreeView t, const float* __restrict__ qlo,
+                                                   const float* __restrict__ qhi, int64_t nq,
+                                                   const int32_t* __restrict__ order,
+                                                   int32_t* __restrict__ count,
+                                                   const int64_t* __restrict__ offsets,
+                                                   int32_t* __restrict__ out) {
+  extern __shared__ uint32_t box_stk[];
+  uint32_t* col = box_stk + threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * kBoxBlock + threadIdx.x;
+  if (s >= nq) return;
+  const int64_t row = order ? order[s] : s;
+  float ql[D], qh[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    ql[a] = qlo[row * D + a];
+    qh[a] = qhi[row * D + a];
+  }
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int64_t c = 0;
+  int64_t pos = FILL ? offsets[row] : 0;
+  int sp = 0;
+  col[kBoxBlock * sp++] = 0;
+  while (sp > 0) {
+    const uint32_t node = col[kBoxBlock * --sp];
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    bool miss = false, inside = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      miss |= hi[a] < ql[a] || lo[a] > qh[a];
+      inside &= ql[a] <= lo[a] && hi[a] <= qh[a];
+    }
+    if (miss) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    if (inside) {
+      if (FILL) {
+        for (int64_t i = b; i < e; ++i) {
+          float x[D];
+          int32_t id = 0;
+          load_rec<D>(t.rec, i, x, id);
+          out[pos++] = id;
+        }
+      }
+      c += e - b;
+      continue;
+    }
+    if (node >= first_leaf) {
+      for (int64_t i = b; i < e; ++i) {
+        float x[D];
+        int32_t id = 0;
+        load_rec<D>(t.rec, i, x, id);
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) in &= ql[a] <= x[a] && x[a] <= qh[a];
+        if (in) {
+          if (FILL) out[pos++] = id;
+          ++c;
+        }
+      }
+      continue;
+    }
+    col[kBoxBlock * sp++] = 2 * node + 2;
+    col[kBoxBlock * sp++] = 2 * node + 1;
+  }
+  if (!FILL) count[row] = (int32_t)c;
+}
+
+// Box centres for ordering the queries along the tree (a non-finite centre,
+// from an infinite or NaN bound, becomes 0: the order only affects speed).
+template <int D>
+__global__ void k_box_centres(const float* __restrict__ lo, const float* __restrict__ hi,
+                              int64_t nq, float* __restrict__ c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq * D) return;
+  const float m = 0.5f * lo[i] + 0.5f * hi[i];
+  c[i] = isfinite(m) ? m : 0.0f;
+}
+
+__global__ void k_box_offsets_last(int64_t* off, const int32_t* count, int64_t nq) {
+  // off holds the exclusive scan of count over [0, nq); writes off[nq]
+  if (blockIdx.x == 0 && threadIdx.x == 0) off[nq] = off[nq - 1] + count[nq - 1];
+}
+
+struct BoxI64 {
+  __host__ __device__ int64_t operator()(int32_t v) const { return v; }
+};
+
+template <int D>
+static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d_hi, int64_t nq,
+                           int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
+                           int64_t* required, bool sort_q, const int32_t* given,
+                           hipStream_t stream) {
+  TreeView v;
+  v.rec = tr->rec;
+  v.box = tr->box;
+  v.n = tr->n;
+  v.levels = tr->levels;
+  PoolBuffers buf(stream);
+  const int32_t* order = given;
+  if (!order && sort_q && nq > 1) {
+    float* centres = nullptr;
+    int32_t* own = nullptr;
+    if (!buf.get(&centres, (size_t)nq * D) || !buf.get(&own, (size_t)nq)) {
+      kdt_set_error("device allocation failed for the box query order");
+      return KDT_ENOMEM;
+    }
+    k_box_centres<D><<<(unsigned)((nq * D + 255) / 256), 256, 0, stream>>>(d_lo, d_hi, nq, centres);
+    const kdt_status st = kdt_query_order(tr, centres, nq, 0, own, stream);
+    if (st != KDT_OK) return st;
+    order = own;
+  }
+  const unsigned grid = (unsigned)((nq + kBoxBlock - 1) / kBoxBlock);
+  const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kBoxBlock;
+  k_box<D, false><<<grid, kBoxBlock, smem, stream>>>(v, d_lo, d_hi, nq, order, d_count, nullptr,
+                                                      nullptr);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_box: count kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  if (!d_off) return KDT_OK;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  hipcub::TransformInputIterator<int64_t, BoxI64, const int32_t*> c64(d_count, BoxI64());
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
+    kdt_set_error("kdt_box: offset scan setup failed");
+    return KDT_EDEVICE;
+  }
+  if (!buf.get((char**)&tmp, tb)) {
+    kdt_set_error("device allocation failed for the box list offsets");
+    return KDT_ENOMEM;
+  }
+  int64_t total = 0;
+  if (hipcub::DeviceScan::ExclusiveSum(tmp, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
+    kdt_set_error("kdt_box: offset scan failed");
+    return KDT_EDEVICE;
+  }
+  k_box_offsets_last<<<1, 1, 0, stream>>>(d_off, d_count, nq);
+  if (hipMemcpyAsync(&total, d_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    kdt_set_error("kdt_box: reading the list size failed");
+    return KDT_EDEVICE;
+  }
+  if (required) *required = total;
+  if (!d_idx || total == 0) return KDT_OK;
+  if (total > capacity) {
+    kdt_set_error("list capacity %lld is below the %lld entries needed", (long long)capacity,
+                  (long long)total);
+    return KDT_ECAPACITY;
+  }
+  if (total > INT32_MAX) {
+    kdt_set_error("lists above 2^31-1 entries are not supported");
+    return KDT_EUNSUPPORTED;
+  }
+  int32_t* unsorted = nullptr;
+  if (!buf.get(&unsorted, (size_t)total)) {
+    kdt_set_error("device allocation failed for the box lists");
+    return KDT_ENOMEM;
+  }
+  k_box<D, true><<<grid, kBoxBlock, smem, stream>>>(v, d_lo, d_hi, nq, order, d_count, d_off,
+                                                     unsorted);
+  void* stmp = nullptr;
+  size_t sb = 0;
+  if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total, (int)nq,
+                                            d_off, d_off + 1, stream) != hipSuccess) {
+    kdt_set_error("kdt_box: list sort setup failed");
+    return KDT_EDEVICE;
+  }
+  if (!buf.get((char**)&stmp, sb)) {
+    kdt_set_error("device allocation failed for sorting the box lists");
+    return KDT_ENOMEM;
+  }
+  if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total, (int)nq,
+                                            d_off, d_off + 1, stream) != hipSuccess) {
+    kdt_set_error("kdt_box: list sort failed");
+    return KDT_EDEVICE;
+  }
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_box: list kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+}  // namespace kdt
+
+using namespace kdt;
+
+extern "C" kdt_status kdt_box(const kdt_tree* tree, const float* d_lo, const float* d_hi,
+                              int64_t nq, int32_t* d_count, int64_t* d_offsets, int32_t* d_idx,
+                              int64_t capacity, int64_t* required, const kdt_query_opts* opts,
+                              hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree || nq < 0) {
+    kdt_set_error("kdt_box: NULL tree or negative nq");
+    return KDT_EINVAL;
+  }
+  if (nq > 0 && (!d_lo || !d_hi || !d_count)) {
+    kdt_set_error("kdt_box: NULL lo, hi or d_count");
+    return KDT_EINVAL;
+  }
+  if (d_idx && !d_offsets) {
+    kdt_set_error("kdt_box: lists need d_offsets");
+    return KDT_EINVAL;
+  }
+  if (nq > INT32_MAX && d_offsets) {
+    kdt_set_error("kdt_box: list mode supports at most 2^31-1 queries");
+    return KDT_EUNSUPPORTED;
+  }
+  if (nq == 0) {
+    if (required) *required = 0;
+    if (d_offsets) {
+      int64_t z = 0;
+      if (hipMemcpyAsync(d_offsets, &z, sizeof(z), hipMemcpyHostToDevice, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess) {
+        kdt_set_error("kdt_box: writing empty offsets failed");
+        return KDT_EDEVICE;
+      }
+    }
+    return KDT_OK;
+  }
+  const bool sort_q = opts ? opts->sort_queries != 0 : true;
+  const int32_t* given = opts ? opts->order : nullptr;
+  switch (tree->d) {
+    case 2: return box_impl<2>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
+    case 3: return box_impl<3>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
+    case 4: return box_impl<4>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
+    case 8: return box_impl<8>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
+    case 16: return box_impl<16>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
+  }
+  kdt_set_error("kdt_box: unsupported dimension %d", tree->d);
+  return KDT_EUNSUPPORTED;
+}

@@ -23,7 +23,7 @@ DIMS = (2, 3, 4, 8, 16)
 
 # Every exported entry point of include/kdt.h.
 EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt_knn",
-           "kdt_range", "kdt_fof", "kdt_p2m", "kdt_p2m_backward", "kdt_tree_perm", "kdt_query_order",
+           "kdt_range", "kdt_box", "kdt_fof", "kdt_p2m", "kdt_p2m_backward", "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_last_error")
 
 
@@ -70,6 +70,8 @@ def load(path: str = LIB_PATH):
     lib.kdt_knn.argtypes = [vp, vp, i64, i32, vp, vp, i32, C.POINTER(QueryOpts), vp]
     lib.kdt_range.argtypes = [vp, vp, i64, f32, vp, vp, vp, i64, C.POINTER(C.c_int64),
                               C.POINTER(QueryOpts), vp]
+    lib.kdt_box.argtypes = [vp, vp, vp, i64, vp, vp, vp, i64, C.POINTER(C.c_int64),
+                            C.POINTER(QueryOpts), vp]
     lib.kdt_fof.argtypes = [vp, f32, vp, C.POINTER(C.c_int64), vp]
     lib.kdt_p2m.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp]
     lib.kdt_p2m_backward.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp, vp, vp]
@@ -221,6 +223,29 @@ class Tree:
         _check(lib.kdt_range(self._h, _ptr(queries), nq, float(r), _ptr(count), _ptr(offsets),
                              _ptr(idx), idx.numel(), C.byref(req), C.byref(opts),
                              _stream(stream)))
+        return count, offsets, idx[:req.value]
+
+    def box(self, lo: torch.Tensor, hi: torch.Tensor, lists: bool = False,
+            sort_queries: bool = True, order: torch.Tensor | None = None, stream=None):
+        """Points inside the closed boxes [lo, hi] (each [nq][d]): counts; with
+        ``lists`` also CSR (offsets int64, ascending input indices int32)."""
+        nq = lo.shape[0]
+        lo = _dev(lo, torch.float32, "lo", (nq, self.d))
+        hi = _dev(hi, torch.float32, "hi", (nq, self.d))
+        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order), 0)
+        count = torch.empty(nq, dtype=torch.int32, device=self.device)
+        lib = load()
+        if not lists:
+            _check(lib.kdt_box(self._h, _ptr(lo), _ptr(hi), nq, _ptr(count), None, None, 0, None,
+                               C.byref(opts), _stream(stream)))
+            return count
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
+        req = C.c_int64(0)
+        _check(lib.kdt_box(self._h, _ptr(lo), _ptr(hi), nq, _ptr(count), _ptr(offsets), None, 0,
+                           C.byref(req), C.byref(opts), _stream(stream)))
+        idx = torch.empty(max(req.value, 1), dtype=torch.int32, device=self.device)
+        _check(lib.kdt_box(self._h, _ptr(lo), _ptr(hi), nq, _ptr(count), _ptr(offsets), _ptr(idx),
+                           idx.numel(), C.byref(req), C.byref(opts), _stream(stream)))
         return count, offsets, idx[:req.value]
 
     def fof(self, linking_length: float, count_groups: bool = False, stream=None):

@@ -41,6 +41,20 @@ def test_knn_and_counts_full_size_sampled(clustered):
     np.testing.assert_array_equal(to_host(cnt)[s], ot.range(q[s], 0.01))
 
 
+def test_box_counts_full_size_sampled(clustered):
+    """2^16 boxes of side 0.002-0.04 on the 2^24-point tree; 48 sampled rows
+    checked against the oracle's definition."""
+    x, q, xt, qt, tree, ot = clustered
+    rng = np.random.Generator(np.random.PCG64(51))
+    c = rng.random((1 << 16, 3), dtype=np.float32)
+    half = ((0.002 + 0.038 * rng.random((1 << 16, 3))) / 2).astype(np.float32)
+    lo, hi = (c - half).astype(np.float32), (c + half).astype(np.float32)
+    say("box counts of 2^16 boxes on 2^24 points")
+    cnt = to_host(tree.box(to_dev(lo), to_dev(hi)))
+    s = workloads.sample_indices(1 << 16, 48, seed=52)
+    np.testing.assert_array_equal(cnt[s], oracle.box_brute(x, lo[s], hi[s]))
+
+
 def test_self_knn_and_smoothing_full_size_sampled(clustered):
     x, q, xt, qt, tree, ot = clustered
     say("self kNN k=32 of 2^24 points, k-th distance")
