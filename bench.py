@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=1 << 14)
     ap.add_argument("--no-dsweep", action="store_true")
+    ap.add_argument("--no-box", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of 1 GiB (read once, written once), the "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -306,6 +307,28 @@ def main():
         out["batch_per_set_eager_ms"] = float(np.mean(reps))
         out["batched_speedup"] = out["batch_per_set_eager_ms"] / avg["batch_graph"]
         out["batched_points"] = batch[4]
+    if not args.no_box:
+        # Box queries (the rectangular ranges, a widening of the path): cubes of
+        # the ball's volume (side 0.0161 for r = 0.01) centred on the 2^22
+        # queries, counts on the step's tree, built again; outside the timed steps.
+        half = 0.5 * (4.0 / 3.0 * np.pi) ** (1.0 / 3.0) * RADIUS
+        blo, bhi = (qt - half).contiguous(), (qt + half).contiguous()
+        tree = kdt.build(xt, leaf_size=LEAF)
+        tree.box(blo, bhi)
+        torch.cuda.synchronize()
+        reps = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tree.box(blo, bhi)
+            e1.record()
+            torch.cuda.synchronize()
+            reps.append(e0.elapsed_time(e1))
+        box_ms = float(np.median(reps))
+        out["box"] = {"ms": box_ms, "queries_s": N_QUERIES / (box_ms * 1e-3),
+                      "side": 2 * half, "n_boxes": N_QUERIES}
+        tree.close()
+        del blo, bhi
     if not args.no_dsweep:
         out["dsweep"] = dimension_sweep(torch, kdt, workloads, dev)
     if not args.no_cpu_baseline:

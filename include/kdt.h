@@ -208,12 +208,15 @@ kdt_status kdt_range(const kdt_tree *tree, const float *d_q, int64_t nq, float r
  *           waits on `stream` once to learn the total size.
  * capacity, required: as for kdt_range.
  * opts      may be NULL; sort_queries orders the boxes by their centres along
- *           the tree (results are identical either way); traversal and
- *           split_budget are ignored.
+ *           the tree; traversal 1 counts with one traversal per lane, 0 or 2
+ *           with the wave-shared traversal of the ball counts (trees with
+ *           leaf_size <= 64); split_budget as for kdt_range.  Results are
+ *           identical either way.
  * nq = 0 is an empty query set: d_lo, d_hi and d_count may be NULL.
  * Scratch (the order, list staging) comes from the stream-ordered pool.
  *
- * Errors: KDT_EINVAL, KDT_ECAPACITY (total > capacity; *required is set and
+ * Errors: KDT_EINVAL (also a traversal outside 0..2 or a negative
+ * split_budget), KDT_ECAPACITY (total > capacity; *required is set and
  * d_count / d_offsets are valid), KDT_EUNSUPPORTED, KDT_ENOMEM, KDT_EDEVICE.
  */
 kdt_status kdt_box(const kdt_tree *tree, const float *d_lo, const float *d_hi, int64_t nq,

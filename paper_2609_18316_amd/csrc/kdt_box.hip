@@ -1,16 +1,19 @@
 // kdt_box.hip -- axis-aligned box queries on gfx950: the rectangular ranges
 // that Sec. 2.3 names beside the ball query.  For each query box [lo, hi]
 // (closed on every axis) the number of tree points inside and, optionally,
-// their input indices in CSR form, ascending.  One traversal per lane, depth
-// first: a node whose tight box misses the query box is skipped, a node whose
-// box lies inside it is taken whole, leaves test their points.  Only
-// comparisons are involved, so the result is exact.
+// their input indices in CSR form, ascending.  A node whose tight box misses
+// the query box is skipped, a node whose box lies inside it is taken whole,
+// leaves test their points.  Counts use the wave-shared traversal of the ball
+// counts with a box as the query shape (packed leaf scans, heavy traversals
+// split over several launches); the lists, and trees with leaves of more than
+// 64 points, one traversal per lane.  Only comparisons are involved, so the
+// result is exact.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
 
-#include "kdt_query.h"
+#include "kdt_packet.h"
 
 namespace kdt {
 
@@ -112,8 +115,8 @@ struct BoxI64 {
 template <int D>
 static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d_hi, int64_t nq,
                            int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
-                           int64_t* required, bool sort_q, const int32_t* given,
-                           hipStream_t stream) {
+                           int64_t* required, bool sort_q, const int32_t* given, int traversal,
+                           uint32_t split_budget, hipStream_t stream) {
   TreeView v;
   v.rec = tr->rec;
   v.box = tr->box;
@@ -135,11 +138,17 @@ static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d
   }
   const unsigned grid = (unsigned)((nq + kBoxBlock - 1) / kBoxBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kBoxBlock;
-  k_box<D, false><<<grid, kBoxBlock, smem, stream>>>(v, d_lo, d_hi, nq, order, d_count, nullptr,
-                                                      nullptr);
-  if (hipGetLastError() != hipSuccess) {
-    kdt_set_error("kdt_box: count kernel launch failed");
-    return KDT_EDEVICE;
+  if (tr->leaf <= 64 && traversal != 1) {
+    const kdt_status st =
+        box_packet_launch<D>(v, tr->leaf, d_lo, d_hi, nq, order, d_count, split_budget, stream);
+    if (st != KDT_OK) return st;
+  } else {
+    k_box<D, false><<<grid, kBoxBlock, smem, stream>>>(v, d_lo, d_hi, nq, order, d_count,
+                                                        nullptr, nullptr);
+    if (hipGetLastError() != hipSuccess) {
+      kdt_set_error("kdt_box: count kernel launch failed");
+      return KDT_EDEVICE;
+    }
   }
   if (!d_off) return KDT_OK;
   void* tmp = nullptr;
@@ -243,14 +252,20 @@ extern "C" kdt_status kdt_box(const kdt_tree* tree, const float* d_lo, const flo
     }
     return KDT_OK;
   }
+  if (opts && (opts->split_budget < 0 || opts->traversal < 0 || opts->traversal > 2)) {
+    kdt_set_error("kdt_box: traversal must be 0, 1 or 2 and split_budget >= 0");
+    return KDT_EINVAL;
+  }
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
   const int32_t* given = opts ? opts->order : nullptr;
+  const int trav = opts ? opts->traversal : 0;
+  const uint32_t budget = opts ? (uint32_t)opts->split_budget : 0u;
   switch (tree->d) {
-    case 2: return box_impl<2>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
-    case 3: return box_impl<3>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
-    case 4: return box_impl<4>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
-    case 8: return box_impl<8>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
-    case 16: return box_impl<16>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, stream);
+    case 2: return box_impl<2>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 3: return box_impl<3>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 4: return box_impl<4>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 8: return box_impl<8>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 16: return box_impl<16>(tree, d_lo, d_hi, nq, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
   }
   kdt_set_error("kdt_box: unsupported dimension %d", tree->d);
   return KDT_EUNSUPPORTED;

@@ -380,17 +380,96 @@ __device__ __forceinline__ bool hand_off(const PacketSpill& spill, int levels, u
   return false;
 }
 
-// LDS floats of one wave of the ball count: the open leaf, then the packed
-// queries [64][D] and their counts [64].
+// Box counts by the wave-shared traversal (the ball counts' launch is declared
+// with the other single-tree entry points).  Leaves must hold at most 64 points.
 template <int D>
+kdt_status box_packet_launch(const TreeView& v, int leaf, const float* d_lo, const float* d_hi,
+                             int64_t nq, const int32_t* order, int32_t* d_count,
+                             uint32_t split_budget, hipStream_t stream);
+
+// Query shapes of the wave-shared counts.  Each says whether it cuts a node
+// box, holds a node box whole, and holds a point, and packs into kFloats
+// floats for the packed leaf scan.
+//
+// A closed ball (Algorithm 3): centre p, squared radius r2 (the same for all
+// queries of a launch).
+template <int D>
+struct BallShape {
+  static constexpr int kFloats = D;
+  float p[D];
+  float r2;
+  __device__ __forceinline__ bool cuts(const float lo[D], const float hi[D]) const {
+    return box_mindist<D>(lo, hi, p) <= r2;
+  }
+  __device__ __forceinline__ bool holds_box(const float lo[D], const float hi[D]) const {
+    return box_maxdist<D>(lo, hi, p) <= r2;
+  }
+  __device__ __forceinline__ bool holds(const float x[D]) const { return sq_dist<D>(x, p) <= r2; }
+  __device__ __forceinline__ void pack(float* dst) const {
+#pragma unroll
+    for (int a = 0; a < D; ++a) dst[a] = p[a];
+  }
+  __device__ __forceinline__ BallShape unpack(const float* src) const {
+    BallShape b;
+#pragma unroll
+    for (int a = 0; a < D; ++a) b.p[a] = src[a];
+    b.r2 = r2;
+    return b;
+  }
+};
+
+// A closed axis-aligned box [lo, hi] (the rectangular ranges of Sec. 2.3).
+template <int D>
+struct BoxShape {
+  static constexpr int kFloats = 2 * D;
+  float lo[D], hi[D];
+  __device__ __forceinline__ bool cuts(const float nlo[D], const float nhi[D]) const {
+    bool meet = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) meet &= nhi[a] >= lo[a] && nlo[a] <= hi[a];
+    return meet;
+  }
+  __device__ __forceinline__ bool holds_box(const float nlo[D], const float nhi[D]) const {
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) in &= lo[a] <= nlo[a] && nhi[a] <= hi[a];
+    return in;
+  }
+  __device__ __forceinline__ bool holds(const float x[D]) const {
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) in &= lo[a] <= x[a] && x[a] <= hi[a];
+    return in;
+  }
+  __device__ __forceinline__ void pack(float* dst) const {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      dst[a] = lo[a];
+      dst[D + a] = hi[a];
+    }
+  }
+  __device__ __forceinline__ BoxShape unpack(const float* src) const {
+    BoxShape b;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      b.lo[a] = src[a];
+      b.hi[a] = src[D + a];
+    }
+    return b;
+  }
+};
+
+// LDS floats of one wave of a count: the open leaf, then the packed queries
+// [64][K] (K floats per query shape) and their counts [64].
+template <int D, int K = D>
 __host__ __device__ constexpr size_t range_wave_floats(int leaf) {
-  return (size_t)leaf * rec_stride(D) + 64 * (D + 1);
+  return (size_t)leaf * rec_stride(D) + 64 * (K + 1);
 }
 
-// Closed-ball counts of the 64 queries of a wave (Algorithm 3 semantics): a
-// node farther than r from every lane is skipped, a node entirely inside a
-// lane's ball adds its size to that lane, and leaves are scanned only for the
-// lanes whose ball cuts them.  Each stack entry carries the mask of lanes that
+// Counts of the 64 query shapes of a wave (closed balls: Algorithm 3
+// semantics; or closed boxes): a node that no lane's shape cuts is skipped, a
+// node entirely inside a lane's shape adds its size to that lane, and leaves
+// are scanned only for the lanes whose shape cuts them.  Each stack entry carries the mask of lanes that
 // still need that subtree, so a lane that has counted a whole node never
 // counts its descendants again.  Leaves must hold at most 64 points.
 //
@@ -408,17 +487,18 @@ __host__ __device__ constexpr size_t range_wave_floats(int leaf) {
 // writes its remaining stack entries (entry i sits in lane i) as tasks for a
 // later pass and returns its partial counts; the later passes add theirs, so
 // every count is the same integer sum.
-template <int D>
-__device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const float p[D],
-                                                      bool active, float r2, float* lds,
+template <int D, class Shape>
+__device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const Shape& sh,
+                                                      bool active, float* lds,
                                                       int leaf_cap, uint32_t start,
                                                       uint64_t start_mask, uint32_t group,
                                                       const PacketSpill& spill) {
   constexpr int S = rec_stride(D);
+  constexpr int K = Shape::kFloats;
   const int lane = lane_id();
   LeafReader<D> leaf(t.rec, lds);
-  float* cq = lds + (size_t)leaf_cap * S;                  // packed queries [64][D]
-  int32_t* cc = reinterpret_cast<int32_t*>(cq + 64 * D);  // their counts [64]
+  float* cq = lds + (size_t)leaf_cap * S;                  // packed queries [64][K]
+  int32_t* cc = reinterpret_cast<int32_t*>(cq + 64 * K);  // their counts [64]
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   int64_t count = 0;
   uint32_t stackv = start;                         // lane i: node of entry i
@@ -437,9 +517,9 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
     const bool mine = active && ((live >> lane) & 1ull);
     float lo[D], hi[D];
     load_box_uniform<D>(t.box, node, lo, hi);
-    const bool touch = mine && box_mindist<D>(lo, hi, p) <= r2;
+    const bool touch = mine && sh.cuts(lo, hi);
     if (!__any(touch)) continue;
-    const bool full = touch && box_maxdist<D>(lo, hi, p) <= r2;
+    const bool full = touch && sh.holds_box(lo, hi);
     const int lev = node_level(node);
     const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
     const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
@@ -456,10 +536,7 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
       const int steps = (na + G - 1) / G;
       if (2 * steps <= cnt) {  // a packed step costs about two broadcast steps
         const int me = lanes_below(pm);
-        if (part) {
-#pragma unroll
-          for (int a = 0; a < D; ++a) cq[me * D + a] = p[a];
-        }
+        if (part) sh.pack(cq + me * K);
         wave_sync();
         const int slot = lane / W, i = lane % W;
         const uint64_t wmask = ~0ull >> (64 - W);
@@ -468,10 +545,8 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
         for (int s = 0; s < steps; ++s) {
           const int a = s * G + slot;
           const int ac = min(a, na - 1);
-          float qv[D];
-#pragma unroll
-          for (int u = 0; u < D; ++u) qv[u] = cq[ac * D + u];
-          const bool hit = i < cnt && a < na && sq_dist<D>(x, qv) <= r2;
+          const Shape qs = sh.unpack(cq + ac * K);
+          const bool hit = i < cnt && a < na && qs.holds(x);
           const uint64_t hm = __ballot(hit);
           if (i == 0 && a < na) cc[a] = __popcll((hm >> (slot * W)) & wmask);
         }
@@ -483,7 +558,7 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const f
         for (int i = 0; i < cnt; ++i) {
           float x[D];
           leaf.point(i, x);
-          c += sq_dist<D>(x, p) <= r2;
+          c += sh.holds(x);
         }
         if (part) count += c;
       }

@@ -74,11 +74,54 @@ __global__ __launch_bounds__(64 * kPWaves) void k_knn_packet(TreeView t, const f
   if (active) knn_write<KC>(best, k, MODE, row, oidx, od2);
 }
 
-// First pass of the ball counts: one 64-query group per wave from the root;
-// writes each count (partial if the wave handed subtrees on).
+// Where the queries of a count come from: balls (centres, or the tree's own
+// points, and one squared radius) or boxes (corners).
 template <int D>
-__global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const float* __restrict__ q,
-                                                               int64_t nq, float r2,
+struct BallQueries {
+  using Shape = BallShape<D>;
+  const float* q;  // [nq][D], or nullptr: the tree's own points
+  float r2;
+  __device__ __forceinline__ bool load(const TreeView& t, int64_t nq, const int32_t* order,
+                                       int64_t s, Shape& sh, int64_t& row) const {
+    sh.r2 = r2;
+    return load_query<D>(t, q, nq, order, s, sh.p, row);
+  }
+};
+
+template <int D>
+struct BoxQueries {
+  using Shape = BoxShape<D>;
+  const float* lo;  // [nq][D]
+  const float* hi;
+  __device__ __forceinline__ bool load(const TreeView&, int64_t nq, const int32_t* order,
+                                       int64_t s, Shape& sh, int64_t& row) const {
+    if (s >= nq) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        sh.lo[a] = 1.0f;  // an empty box
+        sh.hi[a] = 0.0f;
+      }
+      return false;
+    }
+    row = order ? order[s] : s;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      sh.lo[a] = lo[row * D + a];
+      sh.hi[a] = hi[row * D + a];
+    }
+    return true;
+  }
+};
+
+template <int D, class Q>
+__host__ __device__ constexpr size_t count_wave_floats(int leaf) {
+  return range_wave_floats<D, Q::Shape::kFloats>(leaf);
+}
+
+// First pass of the counts: one 64-query group per wave from the root; writes
+// each count (partial if the wave handed subtrees on).
+template <int D, class Q>
+__global__ __launch_bounds__(64 * kPWaves) void k_count_packet(TreeView t, Q src, int64_t nq,
                                                                const int32_t* __restrict__ order,
                                                                int32_t* __restrict__ count,
                                                                int leaf_cap, PacketSpill spill) {
@@ -86,11 +129,11 @@ __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s0 = (xcd_block<kXcdRunPacket>() * kPWaves + wave) * 64;
   if (s0 >= nq) return;
-  float p[D];
+  typename Q::Shape sh;
   int64_t row = 0;
-  const bool active = load_query<D>(t, q, nq, order, s0 + lane, p, row);
-  const int64_t c = packet_range_count<D>(t, p, active, r2,
-                                          lds + (size_t)wave * range_wave_floats<D>(leaf_cap),
+  const bool active = src.load(t, nq, order, s0 + lane, sh, row);
+  const int64_t c = packet_range_count<D>(t, sh, active,
+                                          lds + (size_t)wave * count_wave_floats<D, Q>(leaf_cap),
                                           leaf_cap, 0u, ~0ull, (uint32_t)(s0 / 64), spill);
   if (active) count[row] = (int32_t)c;
   wave_done(spill);
@@ -98,24 +141,23 @@ __global__ __launch_bounds__(64 * kPWaves) void k_range_packet(TreeView t, const
 
 // A later pass: each wave takes tasks left by the previous pass (a fixed
 // count, read at start, so every wave's loop ends) and adds its counts.
-template <int D>
-__global__ __launch_bounds__(64 * kPWaves) void k_range_tasks(
-    TreeView t, const float* __restrict__ q, int64_t nq, float r2,
-    const int32_t* __restrict__ order, int32_t* __restrict__ count, int leaf_cap,
-    const PacketTask* __restrict__ in, const uint32_t* __restrict__ in_count, uint32_t in_cap,
-    PacketSpill spill) {
+template <int D, class Q>
+__global__ __launch_bounds__(64 * kPWaves) void k_count_tasks(
+    TreeView t, Q src, int64_t nq, const int32_t* __restrict__ order,
+    int32_t* __restrict__ count, int leaf_cap, const PacketTask* __restrict__ in,
+    const uint32_t* __restrict__ in_count, uint32_t in_cap, PacketSpill spill) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t n = min(*in_count, in_cap);
-  float* slice = lds + (size_t)wave * range_wave_floats<D>(leaf_cap);
+  float* slice = lds + (size_t)wave * count_wave_floats<D, Q>(leaf_cap);
   for (uint32_t k = blockIdx.x * kPWaves + wave; k < n; k += gridDim.x * kPWaves) {
     const PacketTask task = in[k];
     if (task.node == kNoNode) continue;
-    float p[D];
+    typename Q::Shape sh;
     int64_t row = 0;
-    const bool active = load_query<D>(t, q, nq, order, (int64_t)task.group * 64 + lane, p, row);
+    const bool active = src.load(t, nq, order, (int64_t)task.group * 64 + lane, sh, row);
     const uint64_t mask = ((uint64_t)task.hi << 32) | task.lo;
-    const int64_t c = packet_range_count<D>(t, p, active, r2, slice, leaf_cap, task.node, mask,
+    const int64_t c = packet_range_count<D>(t, sh, active, slice, leaf_cap, task.node, mask,
                                             task.group, spill);
     if (active && c != 0) atomicAdd(count + row, (int32_t)c);
   }
@@ -191,14 +233,16 @@ kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int6
   return KDT_OK;
 }
 
-template <int D>
-kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
-                               const int32_t* order, int32_t* d_count, uint32_t split_budget,
-                               hipStream_t stream) {
+// The wave-shared counts (balls or boxes), with heavy traversals split over
+// kRangePasses launches: the first kRangePasses - 1 hand off what exceeds their
+// budget of node visits, the last finishes everything.
+template <int D, class Q>
+static kdt_status count_packet_launch(const TreeView& v, int leaf, Q src, int64_t nq,
+                                      const int32_t* order, int32_t* d_count,
+                                      uint32_t split_budget, hipStream_t stream,
+                                      const char* who) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
-  const size_t smem = sizeof(float) * range_wave_floats<D>(leaf) * kPWaves;
-  // Heavy traversals are split over kRangePasses launches: the first kRangePasses - 1
-  // hand off what exceeds kRangeBudget node visits, the last finishes everything.
+  const size_t smem = sizeof(float) * count_wave_floats<D, Q>(leaf) * kPWaves;
   PoolBuffers buf(stream);
   PacketTask* tasks = nullptr;
   uint32_t* counts = nullptr;
@@ -206,7 +250,7 @@ kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, in
   // finished-wave counters
   if (!buf.get(&tasks, (size_t)kRangeTaskCap * (kRangePasses - 1)) ||
       !buf.get(&counts, kRangePasses + kDoneShards)) {
-    kdt_set_error("device allocation failed for the ball-count task lists");
+    kdt_set_error("%s: device allocation failed for the task lists", who);
     return KDT_ENOMEM;
   }
   k_zero_tasks<<<1, 64, 0, stream>>>(counts, kRangePasses + kDoneShards);
@@ -217,23 +261,39 @@ kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, in
   const uint32_t tail_from = split_budget                ? 0u
                              : waves > kRangeTailWaves ? (uint32_t)(waves - kRangeTailWaves)
                                                        : 0u;
-  k_range_packet<D><<<grid, 64 * kPWaves, smem, stream>>>(
-      v, d_q, nq, r2, order, d_count, leaf,
+  k_count_packet<D, Q><<<grid, 64 * kPWaves, smem, stream>>>(
+      v, src, nq, order, d_count, leaf,
       PacketSpill{tasks, counts, kRangeTaskCap, first, counts + kRangePasses, tail_from});
   for (int pass = 1; pass < kRangePasses; ++pass) {
     const bool last = pass == kRangePasses - 1;
     const PacketSpill out = last ? PacketSpill{nullptr, nullptr, 0u, 0u, nullptr, 0u}
                                 : PacketSpill{tasks + (size_t)pass * kRangeTaskCap, counts + pass,
                                              kRangeTaskCap, later, nullptr, 0u};
-    k_range_tasks<D><<<kRangeTaskBlocks, 64 * kPWaves, smem, stream>>>(
-        v, d_q, nq, r2, order, d_count, leaf, tasks + (size_t)(pass - 1) * kRangeTaskCap,
+    k_count_tasks<D, Q><<<kRangeTaskBlocks, 64 * kPWaves, smem, stream>>>(
+        v, src, nq, order, d_count, leaf, tasks + (size_t)(pass - 1) * kRangeTaskCap,
         counts + pass - 1, kRangeTaskCap, out);
   }
   if (hipGetLastError() != hipSuccess) {
-    kdt_set_error("kdt_range: packet kernel launch failed");
+    kdt_set_error("%s: packet kernel launch failed", who);
     return KDT_EDEVICE;
   }
   return KDT_OK;
+}
+
+template <int D>
+kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
+                               const int32_t* order, int32_t* d_count, uint32_t split_budget,
+                               hipStream_t stream) {
+  return count_packet_launch<D>(v, leaf, BallQueries<D>{d_q, r2}, nq, order, d_count,
+                                split_budget, stream, "kdt_range");
+}
+
+template <int D>
+kdt_status box_packet_launch(const TreeView& v, int leaf, const float* d_lo, const float* d_hi,
+                             int64_t nq, const int32_t* order, int32_t* d_count,
+                             uint32_t split_budget, hipStream_t stream) {
+  return count_packet_launch<D>(v, leaf, BoxQueries<D>{d_lo, d_hi}, nq, order, d_count,
+                                split_budget, stream, "kdt_box");
 }
 
 #define KDT_INST(D)                                                                                \
@@ -241,6 +301,9 @@ kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, in
                                            int32_t*, float*, int, const int32_t*, hipStream_t);    \
   template kdt_status range_packet_launch<D>(const TreeView&, int, const float*, int64_t, float,   \
                                              const int32_t*, int32_t*, uint32_t, hipStream_t);   \
+  template kdt_status box_packet_launch<D>(const TreeView&, int, const float*, const float*,       \
+                                           int64_t, const int32_t*, int32_t*, uint32_t,          \
+                                           hipStream_t);                                         \
   template kdt_status fof_packet_launch<D>(const TreeView&, int, float, int32_t*, uint32_t*,       \
                                            hipStream_t);
 KDT_INST(2)

@@ -226,13 +226,14 @@ class Tree:
         return count, offsets, idx[:req.value]
 
     def box(self, lo: torch.Tensor, hi: torch.Tensor, lists: bool = False,
-            sort_queries: bool = True, order: torch.Tensor | None = None, stream=None):
+            sort_queries: bool = True, order: torch.Tensor | None = None, traversal: int = 0,
+            split_budget: int = 0, stream=None):
         """Points inside the closed boxes [lo, hi] (each [nq][d]): counts; with
         ``lists`` also CSR (offsets int64, ascending input indices int32)."""
         nq = lo.shape[0]
         lo = _dev(lo, torch.float32, "lo", (nq, self.d))
         hi = _dev(hi, torch.float32, "hi", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order), 0)
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), int(split_budget))
         count = torch.empty(nq, dtype=torch.int32, device=self.device)
         lib = load()
         if not lists:

@@ -47,6 +47,9 @@ def test_box_counts_and_lists(d):
             np.testing.assert_array_equal(to_host(c), oc)
             np.testing.assert_array_equal(to_host(off), ooff)
             np.testing.assert_array_equal(to_host(lst), olst)
+            for trav, budget in ((1, 0), (2, 0), (2, 3)):  # per lane; wave-shared; handed on
+                got = t.box(to_dev(lo), to_dev(hi), traversal=trav, split_budget=budget)
+                np.testing.assert_array_equal(to_host(got), oc)
 
 
 @pytest.mark.parametrize("leaf", (8, 32, 64))
@@ -57,7 +60,10 @@ def test_box_counts_clustered(leaf):
     lo, hi = _boxes(rng, 1000, 3, 0.002, 0.05)
     say(f"box clustered leaf={leaf}")
     t = kdt.build(to_dev(x), leaf_size=leaf)
-    np.testing.assert_array_equal(to_host(t.box(to_dev(lo), to_dev(hi))), oracle.box_brute(x, lo, hi))
+    o = oracle.box_brute(x, lo, hi)
+    for trav, budget in ((0, 0), (1, 0), (2, 16)):
+        got = t.box(to_dev(lo), to_dev(hi), traversal=trav, split_budget=budget)
+        np.testing.assert_array_equal(to_host(got), o)
 
 
 def test_box_order_does_not_change_results_and_empty_sets():
@@ -73,6 +79,10 @@ def test_box_order_does_not_change_results_and_empty_sets():
     for u, v, w in zip(a, b, c):
         np.testing.assert_array_equal(to_host(u), to_host(v))
         np.testing.assert_array_equal(to_host(u), to_host(w))
+    with pytest.raises(kdt.KdtError):
+        t.box(to_dev(lo), to_dev(hi), traversal=3)
+    with pytest.raises(kdt.KdtError):
+        t.box(to_dev(lo), to_dev(hi), split_budget=-2)
     z = torch.empty((0, 3), dtype=torch.float32, device=d)
     assert t.box(z, z).shape == (0,)
     cz, oz, lz = t.box(z, z, lists=True)
