@@ -50,10 +50,10 @@ BATCH_SETS = 256
 KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
                 "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
-    "sha256": "cdec93fb39035b668859ab58156c046add96cb2dace928ccac6edfb9fa257ed8",
-    "hbm_bytes": 2.1460e+09,
+    "sha256": "23f47c65ae287309229b41f795eb5dc49379a7ff1f87b8f878dc0dccbd2148fa",
+    "hbm_bytes": 2.1450e+09,
     "l2_hit_rate": 0.964,
-    "valu_issue_frac": 0.72,
+    "valu_issue_frac": 0.71,
 }
 
 
