@@ -45,8 +45,11 @@ typedef enum {
     KDT_EDEVICE = 5       /* a HIP runtime call failed */
 } kdt_status;
 
-/* Supported dimensions and the largest k of one kNN call. */
+/* The largest k that kdt_knn keeps in registers (the batched forest's limit
+   too), and the largest k it accepts: above KDT_MAX_K it switches to a
+   per-query ball and sort (Sec. 3.3 measures k up to 10^4). */
 #define KDT_MAX_K 64
+#define KDT_MAX_K_SORTED (1 << 20)
 /* d must be one of 2, 3, 4, 8, 16. */
 
 typedef struct kdt_tree kdt_tree;             /* device-resident tree, library-owned */
@@ -149,7 +152,16 @@ kdt_status kdt_tree_export(const kdt_tree *tree, float *h_pts, int32_t *h_perm, 
  * d_q    [nq][d] float32 queries, or NULL to query every point of the tree
  *        itself (then nq must equal n and row i belongs to input point i).
  *        A query that is a data point finds itself at distance 0.
- * k      1 <= k <= KDT_MAX_K.
+ * k      1 <= k <= KDT_MAX_K_SORTED.  Up to KDT_MAX_K the neighbour lists live
+ *        in registers.  Above it each query first takes its 64th neighbour,
+ *        scales that squared distance by 1.1 (k/64)^(2/d), grows it (from
+ *        the density its count shows) until its closed ball holds at least
+ *        k points, writes the
+ *        (d2, index) keys of that ball and sorts them per query; results are
+ *        the same as the register path's.  This mode waits on `stream` a few
+ *        times, takes scratch of 16 bytes per candidate (queries are taken in
+ *        chunks of at most 2^27 candidates, 2 GiB) from the stream-ordered
+ *        pool, and fails with KDT_EUNSUPPORTED above 2^31-1 queries.
  * kth_only 0: write k results per row, ascending by (d2, index):
  *             d_idx [nq][k] int32 (may be NULL), d_d2 [nq][k] float32.
  *          1: write only the k-th squared distance, d_d2 [nq].

@@ -1,0 +1,416 @@
+// kdt_bigk.hip -- k nearest neighbours for k above the 64 entries a register
+// list holds (Sec. 3.3 measures k up to 10^4) on gfx950.  Exact, in three
+// steps:
+//   1. a squared radius per query whose closed ball holds at least k points:
+//      the 64th neighbour's d2 (the register path) scaled by (k/64)^(2/d),
+//      grown from the density a count shows where it falls short;
+//   2. the (d2, index) keys of every point in that ball, one wave per query;
+//   3. a segmented sort of the keys: the first k of each row are the answer,
+//      since every point outside the ball is farther than the k-th key.
+// Keys are (d2 bits << 32 | index) with the same float32 distances as the
+// register path, so results are identical to it wherever both apply.  Queries
+// are processed in chunks whose keys fit a bounded buffer.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <vector>
+
+#include "kdt_query.h"
+
+namespace kdt {
+
+constexpr int kLBlock = 128;
+constexpr int64_t kBigKeysPerChunk = int64_t(1) << 27;  // 1 GiB of keys
+constexpr int kBigGrowRounds = 24;  // then the radius becomes infinite
+// Margin on estimated squared radii (x 1.1^(d/2) expected points), the least
+// growth of a radius that fell short, and the cap of that least growth for
+// stuck rows.
+constexpr float kBigMargin = 1.1f;
+constexpr float kBigGrowMin = 1.1f;
+constexpr float kBigGrowCap = 64.0f;
+
+// Queries in a spatially coherent order, pos -> row: the tree's own points
+// in tree order (self queries) or the given queries gathered through `order`.
+template <int D>
+__global__ void k_gather_self(const float* __restrict__ rec, int64_t n, float* __restrict__ qs,
+                              int32_t* __restrict__ rowof) {
+  constexpr int S = rec_stride(D);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int a = 0; a < D; ++a) qs[i * D + a] = rec[i * S + a];
+  rowof[i] = __float_as_int(rec[i * S + D]);
+}
+
+template <int D>
+__global__ void k_gather_queries(const float* __restrict__ q, const int32_t* __restrict__ order,
+                                 int64_t nq, float* __restrict__ qs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const int64_t r = order[i];
+#pragma unroll
+  for (int a = 0; a < D; ++a) qs[i * D + a] = q[r * D + a];
+}
+
+// r2 <- 64th neighbour's d2 x scale (+inf when the tree holds at most k
+// points); also clears the growth state and the first offset.
+__global__ void k_start_radius(float* __restrict__ r2, int64_t nq, float scale, int all,
+                               int32_t* __restrict__ prev, int32_t* __restrict__ stuck,
+                               int32_t* __restrict__ again, int rounds,
+                               int64_t* __restrict__ off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nq) {
+    r2[i] = all ? INFINITY : r2[i] * scale;
+    prev[i] = 0;
+    stuck[i] = 0;
+  }
+  if (i < rounds) again[i] = 0;
+  if (i == 0) off[0] = 0;
+}
+
+// Per query, one lane each: the number of points of the closed ball of
+// squared radius r2[s] around it.  A node inside the ball counts whole, a
+// leaf that straddles it tests its points.  With `only_marked`, rows whose
+// count is not negative (not grown since they were counted) are skipped.
+template <int D>
+__global__ __launch_bounds__(kLBlock) void k_ball_count(TreeView t, const float* __restrict__ q,
+                                                        int64_t nq, const float* __restrict__ r2v,
+                                                        int32_t* __restrict__ count,
+                                                        int only_marked) {
+  extern __shared__ uint32_t var_stk[];
+  uint32_t* col = var_stk + threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * kLBlock + threadIdx.x;
+  if (s >= nq || (only_marked && count[s] >= 0)) return;
+  float p[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) p[a] = q[s * D + a];
+  const float r2 = r2v[s];
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int64_t c = 0;
+  int sp = 0;
+  col[kLBlock * sp++] = 0;
+  while (sp > 0) {
+    const uint32_t node = col[kLBlock * --sp];
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (box_mindist<D>(lo, hi, p) > r2) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    if (box_maxdist<D>(lo, hi, p) <= r2) {
+      c += e - b;
+      continue;
+    }
+    if (node >= first_leaf) {
+      for (int64_t i = b; i < e; ++i) {
+        float x[D];
+        int32_t id = 0;
+        load_rec<D>(t.rec, i, x, id);
+        c += sq_dist<D>(x, p) <= r2;
+      }
+      continue;
+    }
+    col[kLBlock * sp++] = 2 * node + 2;
+    col[kLBlock * sp++] = 2 * node + 1;
+  }
+  count[s] = (int32_t)c;
+}
+
+// Per query, one wave each: the keys of the points k_ball_count counted,
+// written from offsets[s] - base on.  The wave walks the tree together and
+// scans a node's points 64 at a time with coalesced loads; lanes holding a
+// point append its key at their rank in the wave's ballot.  The node tests
+// are those of k_ball_count, so exactly count[s] keys are written.
+constexpr int kFillWaves = 4;
+template <int D>
+__global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
+    TreeView t, const float* __restrict__ q, int64_t s0, int64_t s1,
+    const float* __restrict__ r2v, const int64_t* __restrict__ offsets, int64_t base,
+    uint64_t* __restrict__ keys, int stack_len) {
+  extern __shared__ uint32_t fill_stk[];
+  const int lane = threadIdx.x & 63;
+  uint32_t* stk = fill_stk + (threadIdx.x >> 6) * stack_len;
+  const int64_t s = s0 + (int64_t)blockIdx.x * kFillWaves + (threadIdx.x >> 6);
+  if (s >= s1) return;  // uniform over the wave
+  float p[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) p[a] = q[s * D + a];
+  const float r2 = r2v[s];
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  const uint64_t below = (1ull << lane) - 1ull;
+  int64_t pos = offsets[s] - base;
+  // every lane writes the same entries, so each reads back its own writes
+  int sp = 0;
+  stk[sp++] = 0;
+  while (sp > 0) {
+    const uint32_t node = stk[--sp];
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (box_mindist<D>(lo, hi, p) > r2) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    const bool whole = box_maxdist<D>(lo, hi, p) <= r2;
+    if (whole || node >= first_leaf) {
+      for (int64_t c = b; c < e; c += 64) {
+        const int64_t i = c + lane;
+        bool in = false;
+        uint64_t key = 0;
+        if (i < e) {
+          float x[D];
+          int32_t id = 0;
+          load_rec<D>(t.rec, i, x, id);
+          const float d2 = sq_dist<D>(x, p);
+          in = whole || d2 <= r2;
+          key = make_key(d2, id);
+        }
+        const uint64_t m = __ballot(in);
+        if (in) keys[pos + __popcll(m & below)] = key;
+        pos += __popcll(m);
+      }
+      continue;
+    }
+    stk[sp++] = 2 * node + 2;
+    stk[sp++] = 2 * node + 1;
+  }
+}
+
+// Rows whose ball holds fewer than k points get a larger radius, from the
+// density the count shows: r2 x kBigMargin (k / count)^(2/d), at least
+// x kBigGrowMin (a zero radius restarts from `floor`); the row is marked for
+// recounting.  A row whose count grew by less than an eighth since its last
+// round is stuck (its ball is crossing empty space, e.g. around a small
+// isolated clump): each time, its least growth is multiplied by four, up to
+// kBigGrowCap.  In the last round the radius becomes infinite.
+__global__ void k_grow_radius(float* __restrict__ r2, int32_t* __restrict__ count,
+                              int32_t* __restrict__ prev, int32_t* __restrict__ stuck, int64_t nq,
+                              int k, float two_over_d, float floor, int last,
+                              int32_t* __restrict__ again) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq || count[i] >= k || isinf(r2[i])) return;
+  const int c = count[i], p = prev[i];
+  const int l = stuck[i] + (p > 0 && c - p < (p >> 3) ? 1 : 0);
+  stuck[i] = l;
+  prev[i] = c;
+  const float least = fminf(kBigGrowCap, kBigGrowMin * exp2f(2.0f * (float)l));
+  const float f = c > 0 ? fmaxf(least, kBigMargin * powf((float)k / (float)c, two_over_d)) : least;
+  r2[i] = last ? INFINITY : (r2[i] > 0.0f ? r2[i] * f : floor);
+  count[i] = -1;
+  again[0] = 1;
+}
+
+struct BigI64 {
+  __host__ __device__ int64_t operator()(int32_t v) const { return v; }
+};
+
+__global__ void k_chunk_offsets(const int64_t* __restrict__ off, int64_t s0, int64_t m,
+                                int32_t* __restrict__ rel) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= m) rel[i] = (int32_t)(off[s0 + i] - off[s0]);
+}
+
+// The first k sorted keys of each query of the chunk: (index, d2) pairs, or
+// the k-th d2 / distance.  Rows with fewer than k keys are padded (-1, +inf).
+__global__ void k_take_first(const uint64_t* __restrict__ keys, const int32_t* __restrict__ rel,
+                             const int32_t* __restrict__ rowof, int64_t s0, int64_t m, int k,
+                             int mode, int32_t* __restrict__ oidx, float* __restrict__ od2) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = mode == 0 ? k : 1;
+  if (t >= m * per) return;
+  const int64_t i = t / per;
+  const int j = mode == 0 ? (int)(t % per) : k - 1;
+  const int have = rel[i + 1] - rel[i];
+  const int64_t row = rowof ? (int64_t)rowof[s0 + i] : s0 + i;
+  const bool empty = j >= have;
+  const uint64_t key = empty ? 0ull : keys[rel[i] + j];
+  const float d2 = empty ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
+  if (mode == 0) {
+    if (oidx) oidx[row * k + j] = empty ? -1 : (int32_t)(uint32_t)key;
+    od2[row * k + j] = d2;
+  } else {
+    od2[row] = mode == 2 ? sqrtf(d2) : d2;
+  }
+}
+
+template <int D>
+static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t nq, int k,
+                                 int32_t* d_idx, float* d_d2, int mode, bool sort_q,
+                                 const int32_t* given, hipStream_t stream) {
+  TreeView v;
+  v.rec = tr->rec;
+  v.box = tr->box;
+  v.n = tr->n;
+  v.levels = tr->levels;
+  PoolBuffers buf(stream);
+  const unsigned gq = (unsigned)((nq + 255) / 256);
+  // 0. queries in a coherent order (pos), rowof[pos] their output row
+  const float* q = d_q;
+  const int32_t* rowof = nullptr;
+  if (!d_q || given || (sort_q && nq > 1)) {
+    float* qs = nullptr;
+    int32_t* rows = nullptr;
+    if (!buf.get(&qs, (size_t)nq * D) || (!given && !buf.get(&rows, (size_t)nq))) {
+      kdt_set_error("kdt_knn: device allocation failed for the large-k query order");
+      return KDT_ENOMEM;
+    }
+    if (!d_q) {
+      k_gather_self<D><<<gq, 256, 0, stream>>>(tr->rec, nq, qs, rows);
+      rowof = rows;
+    } else {
+      if (!given) {
+        const kdt_status st = kdt_query_order(tr, d_q, nq, 0, rows, stream);
+        if (st != KDT_OK) return st;
+      }
+      rowof = given ? given : rows;
+      k_gather_queries<D><<<gq, 256, 0, stream>>>(d_q, rowof, nq, qs);
+    }
+    q = qs;
+  }
+  float* r2 = nullptr;
+  int32_t* count = nullptr;
+  int64_t* off = nullptr;
+  int32_t* again = nullptr;
+  int32_t* prev = nullptr;
+  int32_t* stuck = nullptr;
+  if (!buf.get(&r2, (size_t)nq) || !buf.get(&count, (size_t)nq) || !buf.get(&prev, (size_t)nq) ||
+      !buf.get(&stuck, (size_t)nq) ||
+      !buf.get(&off, (size_t)nq + 1) || !buf.get(&again, (size_t)kBigGrowRounds)) {
+    kdt_set_error("kdt_knn: device allocation failed for the large-k radii");
+    return KDT_ENOMEM;
+  }
+  // 1. start from the 64th neighbour (the register path), scaled to hold k
+  kdt_query_opts in_order{};
+  in_order.sort_queries = 0;
+  kdt_status st = kdt_knn(tr, q, nq, KDT_MAX_K, nullptr, r2, 1, &in_order, stream);
+  if (st != KDT_OK) return st;
+  const float scale = kBigMargin * std::pow((float)k / (float)KDT_MAX_K, 2.0f / (float)D);
+  k_start_radius<<<gq, 256, 0, stream>>>(r2, nq, scale, tr->n <= k ? 1 : 0, prev, stuck, again,
+                                         kBigGrowRounds, off);
+  float root_lo[D], root_hi[D];
+  if (hipMemcpyAsync(root_lo, tr->box, sizeof(float) * D, hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(root_hi, tr->box + pad4(D), sizeof(float) * D, hipMemcpyDeviceToHost,
+                     stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    kdt_set_error("kdt_knn: reading the root box failed");
+    return KDT_EDEVICE;
+  }
+  float diag2 = 0.0f;
+  for (int a = 0; a < D; ++a) diag2 += (root_hi[a] - root_lo[a]) * (root_hi[a] - root_lo[a]);
+  const float floor = diag2 > 0.0f ? std::ldexp(diag2, -24) : 1e-30f;
+  const int stack_len = tr->levels + 2;
+  const size_t smem = sizeof(uint32_t) * (size_t)stack_len * kLBlock;
+  const unsigned gl = (unsigned)((nq + kLBlock - 1) / kLBlock);
+  for (int round = 0; round < kBigGrowRounds; ++round) {
+    k_ball_count<D><<<gl, kLBlock, smem, stream>>>(v, q, nq, r2, count, round > 0 ? 1 : 0);
+    k_grow_radius<<<gq, 256, 0, stream>>>(r2, count, prev, stuck, nq, k, 2.0f / (float)D, floor,
+                                          round + 2 >= kBigGrowRounds ? 1 : 0, again + round);
+    int32_t h_again = 0;
+    if (hipMemcpyAsync(&h_again, again + round, sizeof(int32_t), hipMemcpyDeviceToHost,
+                       stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      kdt_set_error("kdt_knn: reading the growth flag failed");
+      return KDT_EDEVICE;
+    }
+    if (!h_again) break;
+  }
+  // 2. offsets of each query's keys; chunks of at most kBigKeysPerChunk keys
+  {
+    void* tmp = nullptr;
+    size_t tb = 0;
+    hipcub::TransformInputIterator<int64_t, BigI64, const int32_t*> c64(count, BigI64());
+    if (hipcub::DeviceScan::InclusiveSum(nullptr, tb, c64, off + 1, (int)nq, stream) !=
+            hipSuccess ||
+        !buf.get((char**)&tmp, tb) ||
+        hipcub::DeviceScan::InclusiveSum(tmp, tb, c64, off + 1, (int)nq, stream) != hipSuccess) {
+      kdt_set_error("kdt_knn: large-k offsets failed");
+      return KDT_EDEVICE;
+    }
+  }
+  std::vector<int64_t> h_off((size_t)nq + 1);
+  if (hipMemcpyAsync(h_off.data(), off, sizeof(int64_t) * (nq + 1), hipMemcpyDeviceToHost,
+                     stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    kdt_set_error("kdt_knn: reading the large-k offsets failed");
+    return KDT_EDEVICE;
+  }
+  int64_t max_row = 0;
+  for (int64_t i = 0; i < nq; ++i) max_row = std::max(max_row, h_off[i + 1] - h_off[i]);
+  const int64_t cap = std::max(kBigKeysPerChunk, max_row);
+  if (cap > INT32_MAX) {
+    kdt_set_error("kdt_knn: a query's candidate ball holds more than 2^31-1 points");
+    return KDT_EUNSUPPORTED;
+  }
+  uint64_t* keys = nullptr;
+  uint64_t* sorted = nullptr;
+  int32_t* rel = nullptr;
+  const int64_t biggest = std::min(cap, h_off[nq]);
+  if (!buf.get(&keys, (size_t)std::max<int64_t>(biggest, 1)) ||
+      !buf.get(&sorted, (size_t)std::max<int64_t>(biggest, 1)) ||
+      !buf.get(&rel, (size_t)nq + 1)) {
+    kdt_set_error("kdt_knn: device allocation failed for the large-k keys");
+    return KDT_ENOMEM;
+  }
+  // 3. per chunk: keys, segmented sort, first k
+  void* stmp = nullptr;
+  size_t stmp_bytes = 0;
+  for (int64_t s0 = 0; s0 < nq;) {
+    int64_t s1 = s0 + 1;
+    while (s1 < nq && h_off[s1 + 1] - h_off[s0] <= cap) ++s1;
+    const int64_t m = s1 - s0, total = h_off[s1] - h_off[s0];
+    k_chunk_offsets<<<(unsigned)((m + 256) / 256), 256, 0, stream>>>(off, s0, m, rel);
+    if (total > 0) {
+      k_ball_fill<D><<<(unsigned)((m + kFillWaves - 1) / kFillWaves), 64 * kFillWaves,
+                       sizeof(uint32_t) * (size_t)stack_len * kFillWaves, stream>>>(
+          v, q, s0, s1, r2, off, h_off[s0], keys, stack_len);
+      size_t sb = 0;
+      if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, keys, sorted, (int)total, (int)m,
+                                                rel, rel + 1, stream) != hipSuccess) {
+        kdt_set_error("kdt_knn: large-k sort setup failed");
+        return KDT_EDEVICE;
+      }
+      if (sb > stmp_bytes) {
+        if (!buf.get((char**)&stmp, sb)) {
+          kdt_set_error("kdt_knn: device allocation failed for the large-k sort");
+          return KDT_ENOMEM;
+        }
+        stmp_bytes = sb;
+      }
+      if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, keys, sorted, (int)total, (int)m, rel,
+                                                rel + 1, stream) != hipSuccess) {
+        kdt_set_error("kdt_knn: large-k sort failed");
+        return KDT_EDEVICE;
+      }
+    }
+    const int64_t outs = m * (mode == 0 ? k : 1);
+    k_take_first<<<(unsigned)((outs + 255) / 256), 256, 0, stream>>>(sorted, rel, rowof, s0, m,
+                                                                   k, mode, d_idx, d_d2);
+    s0 = s1;
+  }
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_knn: a large-k kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+kdt_status knn_large(const kdt_tree* tr, const float* d_q, int64_t nq, int k, int32_t* d_idx,
+                     float* d_d2, int mode, bool sort_q, const int32_t* given,
+                     hipStream_t stream) {
+  if (nq > INT32_MAX) {
+    kdt_set_error("kdt_knn: k above %d supports at most 2^31-1 queries", KDT_MAX_K);
+    return KDT_EUNSUPPORTED;
+  }
+  switch (tr->d) {
+    case 2: return knn_large_impl<2>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
+    case 3: return knn_large_impl<3>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
+    case 4: return knn_large_impl<4>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
+    case 8: return knn_large_impl<8>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
+    case 16: return knn_large_impl<16>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
+  }
+  kdt_set_error("kdt_knn: unsupported dimension %d", tr->d);
+  return KDT_EUNSUPPORTED;
+}
+
+}  // namespace kdt

@@ -536,6 +536,12 @@ template <int D>
 kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, int k,
                              int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
                              hipStream_t stream);
+// k above KDT_MAX_K: exact neighbours from a per-query ball that holds at
+// least k points, its keys sorted per query (arguments as kdt_knn).
+kdt_status knn_large(const kdt_tree* tr, const float* d_q, int64_t nq, int k, int32_t* d_idx,
+                     float* d_d2, int mode, bool sort_q, const int32_t* given,
+                     hipStream_t stream);
+
 template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
                                const int32_t* order, int32_t* d_count, uint32_t split_budget,

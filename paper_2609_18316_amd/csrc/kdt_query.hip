@@ -467,8 +467,8 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
     kdt_set_error("kdt_knn: NULL tree or negative nq");
     return KDT_EINVAL;
   }
-  if (k < 1 || k > KDT_MAX_K) {
-    kdt_set_error("kdt_knn: k=%d outside [1, %d]", k, KDT_MAX_K);
+  if (k < 1 || k > KDT_MAX_K_SORTED) {
+    kdt_set_error("kdt_knn: k=%d outside [1, %d]", k, KDT_MAX_K_SORTED);
     return k < 1 ? KDT_EINVAL : KDT_EUNSUPPORTED;
   }
   if (kth_only < 0 || kth_only > 2) {
@@ -491,6 +491,8 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
     kdt_set_error("kdt_knn: traversal must be 0, 1 or 2");
     return KDT_EINVAL;
   }
+  if (k > KDT_MAX_K)
+    return knn_large(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, given, stream);
   switch (tree->d) {
     case 2: return knn_impl<2>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);
     case 3: return knn_impl<3>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);

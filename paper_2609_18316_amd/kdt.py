@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libkdt.so")
 KDT_OK, KDT_EINVAL, KDT_EUNSUPPORTED, KDT_ENOMEM, KDT_ECAPACITY, KDT_EDEVICE = range(6)
 STATUS_NAMES = {0: "KDT_OK", 1: "KDT_EINVAL", 2: "KDT_EUNSUPPORTED", 3: "KDT_ENOMEM",
                 4: "KDT_ECAPACITY", 5: "KDT_EDEVICE"}
-MAX_K = 64
+MAX_K = 64          # register lists (and the batched forest)
+MAX_K_SORTED = 1 << 20  # kdt_knn above MAX_K: ball and sort
 DIMS = (2, 3, 4, 8, 16)
 
 # Every exported entry point of include/kdt.h.

@@ -257,7 +257,7 @@ def test_error_paths():
     assert e.value.status == kdt.KDT_EUNSUPPORTED
     t = kdt.build(to_dev(x))
     with pytest.raises(kdt.KdtError) as e:
-        t.knn(None, 65)
+        t.knn(None, kdt.MAX_K_SORTED + 1)
     assert e.value.status == kdt.KDT_EUNSUPPORTED
     with pytest.raises(kdt.KdtError) as e:
         t.knn(None, 0)
