@@ -36,6 +36,8 @@ RADIUS = 0.01
 FOF_B = 0.2
 GRID = 256
 LEAF = 32
+LARGE_K_QUERIES = 100_000
+LARGE_KS = (100, 1000, 10_000)
 HBM_PEAK_GBS = 8000.0
 BATCH_SETS = 256
 
@@ -50,8 +52,8 @@ BATCH_SETS = 256
 KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
                 "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
-    "sha256": "23f47c65ae287309229b41f795eb5dc49379a7ff1f87b8f878dc0dccbd2148fa",
-    "hbm_bytes": 2.1450e+09,
+    "sha256": "b6c5c4b299fbfc3080844f55c4f44436882c2a3aa943b681eaac47964a6faaff",
+    "hbm_bytes": 2.1458e+09,
     "l2_hit_rate": 0.964,
     "valu_issue_frac": 0.71,
 }
@@ -76,6 +78,7 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=1 << 14)
     ap.add_argument("--no-dsweep", action="store_true")
     ap.add_argument("--no-box", action="store_true")
+    ap.add_argument("--no-large-k", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of 1 GiB (read once, written once), the "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -329,6 +332,28 @@ def main():
                       "side": 2 * half, "n_boxes": N_QUERIES}
         tree.close()
         del blo, bhi
+    if not args.no_large_k:
+        # kNN with k above the 64 register entries (the ball-and-sort path, a
+        # widening of the path): 10^5 of the queries, k = 100 (the paper's
+        # parallel test), 1000 and 10^4 (the top of its k sweep), full lists,
+        # on the step's tree built again; outside the timed steps.
+        tree = kdt.build(xt, leaf_size=LEAF)
+        qk = qt[:LARGE_K_QUERIES].contiguous()
+        out["large_k"] = {"n_queries": LARGE_K_QUERIES}
+        for kk in LARGE_KS:
+            r = tree.knn(qk, kk)
+            del r
+            torch.cuda.synchronize()
+            reps = []
+            for _ in range(2):
+                t_k = time.perf_counter()
+                r = tree.knn(qk, kk)
+                torch.cuda.synchronize()
+                reps.append((time.perf_counter() - t_k) * 1e3)
+                del r
+            ms = float(np.min(reps))
+            out["large_k"][str(kk)] = {"ms": ms, "queries_s": LARGE_K_QUERIES / (ms * 1e-3)}
+        tree.close()
     if not args.no_dsweep:
         out["dsweep"] = dimension_sweep(torch, kdt, workloads, dev)
     if not args.no_cpu_baseline:

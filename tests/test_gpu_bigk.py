@@ -120,3 +120,19 @@ def test_large_k_limits_and_empty():
     q = torch.empty((0, 3), dtype=torch.float32, device="cuda")
     gi, gd = t.knn(q, 1000)
     assert gi.shape == (0, 1000) and gd.shape == (0, 1000)
+
+
+def test_large_k_lattice_ties():
+    """A coarse lattice where most distances tie: ties at and across the k-th
+    place are broken by index, as in the oracle."""
+    dev()
+    rng = np.random.Generator(np.random.PCG64(8))
+    x = (rng.integers(0, 8, (20000, 3)) / 8.0).astype(np.float32)
+    q = (rng.integers(0, 8, (500, 3)) / 8.0).astype(np.float32)
+    t = kdt.build(to_dev(x), leaf_size=32)
+    for k in (65, 1000, 5000):
+        say(f"large k lattice ties k={k}")
+        oi, od = oracle.knn_brute(x, q, k)
+        gi, gd = t.knn(to_dev(q), k)
+        np.testing.assert_array_equal(to_host(gi), oi)
+        np.testing.assert_array_equal(to_host(gd), od)

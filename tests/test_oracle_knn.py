@@ -93,3 +93,22 @@ def test_invariants_on_clustered_points():
     ib, db = oracle.knn_brute(x, q[:50], k)
     np.testing.assert_array_equal(idx[:50], ib)
     np.testing.assert_array_equal(d2[:50], db)
+
+
+def test_large_k_lattice_ties_match_integer_arithmetic():
+    """k well above 64 on a coarse 1/8 lattice, where most distances tie: the
+    order is (exact integer d2, index), as the definition fixes."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    xi = rng.integers(0, 8, (900, 3))
+    qi = rng.integers(0, 8, (30, 3))
+    x = (xi / 8.0).astype(np.float32)
+    q = (qi / 8.0).astype(np.float32)
+    for k in (65, 300, 900, 905):
+        idx, d2 = oracle.knn_brute(x, q, k)
+        for s in range(q.shape[0]):
+            di = ((xi - qi[s]) ** 2).sum(axis=1)
+            order = np.lexsort((np.arange(len(di)), di))[:k]
+            m = len(order)
+            np.testing.assert_array_equal(idx[s, :m], order)
+            np.testing.assert_array_equal(d2[s, :m].astype(np.float64) * 64.0, di[order])
+            assert np.all(idx[s, m:] == -1) and np.all(np.isinf(d2[s, m:]))
