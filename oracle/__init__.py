@@ -43,6 +43,8 @@ def _load():
     lib.orc_sq_dist.restype = f32
     lib.orc_knn_brute.argtypes = [_f32p, i64, i32, _f32p, i64, i32, _i32p, _f32p]
     lib.orc_range_brute.argtypes = [_f32p, i64, i32, _f32p, i64, f32, _i64p, vp, vp]
+    lib.orc_knn_brute_torus.argtypes = [_f32p, i64, i32, _f32p, i64, i32, _f32p, _i32p, _f32p]
+    lib.orc_range_brute_torus.argtypes = [_f32p, i64, i32, _f32p, i64, f32, _f32p, _i64p, vp, vp]
     lib.orc_fof_brute.argtypes = [_f32p, i64, i32, f32, _i32p]
     lib.orc_tree_build.argtypes = [_f32p, i64, i32, i32, C.POINTER(vp)]
     lib.orc_tree_free.argtypes = [vp]
@@ -87,32 +89,54 @@ def sq_dist(p, q) -> np.float32:
 # brute force (the plain definitions)
 # --------------------------------------------------------------------------
 
-def knn_brute(pts, queries, k: int):
-    """k smallest (d2, index) keys of every query, ascending: (idx, d2)."""
+def _period(period, d: int):
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(period, np.float32), (d,)))
+    return L
+
+
+def knn_brute(pts, queries, k: int, period=None):
+    """k smallest (d2, index) keys of every query, ascending: (idx, d2).
+
+    ``period`` (a length or one per axis): distances on the D-torus of those
+    periods (Sec. 2.1, Sec. 2.4), every coordinate in [0, period).
+    """
     pts, queries = _pts(pts), _pts(queries)
     nq = queries.shape[0]
     idx = np.empty((nq, k), np.int32)
     d2 = np.empty((nq, k), np.float32)
-    _check(_load().orc_knn_brute(pts, pts.shape[0], pts.shape[1], queries, nq, k, idx, d2),
-           "knn_brute")
+    lib = _load()
+    if period is None:
+        rc = lib.orc_knn_brute(pts, pts.shape[0], pts.shape[1], queries, nq, k, idx, d2)
+    else:
+        rc = lib.orc_knn_brute_torus(pts, pts.shape[0], pts.shape[1], queries, nq, k,
+                                     _period(period, pts.shape[1]), idx, d2)
+    _check(rc, "knn_brute")
     return idx, d2
 
 
-def range_brute(pts, queries, r: float, lists: bool = False):
-    """Counts of points with d2 <= fl(r*r); with ``lists`` also CSR (offsets, idx)."""
+def range_brute(pts, queries, r: float, lists: bool = False, period=None):
+    """Counts of points with d2 <= fl(r*r); with ``lists`` also CSR (offsets, idx).
+
+    ``period``: distances on the D-torus, as in ``knn_brute``.
+    """
     pts, queries = _pts(pts), _pts(queries)
     n, d = pts.shape
     nq = queries.shape[0]
     lib = _load()
+
+    def call(count, offsets, idx):
+        if period is None:
+            return lib.orc_range_brute(pts, n, d, queries, nq, np.float32(r), count, offsets, idx)
+        return lib.orc_range_brute_torus(pts, n, d, queries, nq, np.float32(r),
+                                         _period(period, d), count, offsets, idx)
+
     count = np.empty(nq, np.int64)
-    _check(lib.orc_range_brute(pts, n, d, queries, nq, np.float32(r), count, None, None),
-           "range_brute")
+    _check(call(count, None, None), "range_brute")
     if not lists:
         return count
     offsets = np.empty(nq + 1, np.int64)
     idx = np.empty(max(int(count.sum()), 1), np.int32)
-    _check(lib.orc_range_brute(pts, n, d, queries, nq, np.float32(r), count,
-                               offsets.ctypes.data, idx.ctypes.data), "range_brute")
+    _check(call(count, offsets.ctypes.data, idx.ctypes.data), "range_brute")
     return count, offsets, idx[:int(count.sum())]
 
 

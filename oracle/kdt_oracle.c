@@ -10,8 +10,11 @@
  *   - squared Euclidean distance (Eq. 1 with p = 2) in IEEE float32, summed
  *     left to right over the axes, every operation rounded on its own
  *     (build with -ffp-contract=off so that no multiply-add is fused);
+ *   - the same distance on the D-torus of periods L_a (the periodic boundary
+ *     conditions of Sec. 2.1 and Sec. 2.4): per axis the shorter way round,
+ *     min(|x - q|, L - |x - q|), for coordinates in [0, L);
  *   - brute-force kNN, ball counts/lists and friends-of-friends groups: the
- *     plain definitions, O(N^2);
+ *     plain definitions, O(N^2) (kNN and balls also on the torus);
  *   - the sliding-midpoint k-d tree of Sec. 2.1 (Algorithm 1, serial);
  *   - best-first kNN over that tree with a node min-heap and a candidate
  *     max-heap (Algorithm 2), results sorted at the end (Sec. 2.3);
@@ -67,6 +70,38 @@ static float sq_dist(const float *p, const float *q, int d)
         s = s + t2;
     }
     return s;
+}
+
+/* Squared distance on the D-torus with periods L[a] (Sec. 2.1: the metric of
+ * a D-toroid; Sec. 2.4: periodic boundary conditions), for coordinates in
+ * [0, L[a]): along each axis the gap |p - q| or the way round, L - |p - q|,
+ * whichever is shorter; then squares summed as in sq_dist. */
+static float torus_sq_dist(const float *p, const float *q, int d, const float *L)
+{
+    float s = 0.0f;
+    for (int a = 0; a < d; ++a) {
+        float g = fabsf(p[a] - q[a]);
+        float w = L[a] - g;
+        float t = w < g ? w : g;
+        float t2 = t * t;
+        s = s + t2;
+    }
+    return s;
+}
+
+/* Open boundaries (L == NULL) or the torus. */
+static float metric_sq_dist(const float *p, const float *q, int d, const float *L)
+{
+    return L ? torus_sq_dist(p, q, d, L) : sq_dist(p, q, d);
+}
+
+/* Every coordinate of the n x d array inside [0, L[a]). */
+static int inside_period(const float *x, int64_t n, int d, const float *L)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < d; ++a)
+            if (!(x[i * d + a] >= 0.0f && x[i * d + a] < L[a])) return 0;
+    return 1;
 }
 
 /* Smallest squared distance from q to any point of the box [lo, hi]. */
@@ -141,11 +176,14 @@ float orc_sq_dist(const float *p, const float *q, int d) { return sq_dist(p, q, 
 /* Brute force: the plain definitions.                                      */
 /* ------------------------------------------------------------------------ */
 
-/* k smallest (d2, idx) keys over all n points, ascending. */
-int orc_knn_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq,
-                  int k, int32_t *out_idx, float *out_d2)
+/* k smallest (d2, idx) keys over all n points, ascending; on the torus of
+ * periods L when L is not NULL. */
+static int knn_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq,
+                     int k, const float *L, int32_t *out_idx, float *out_d2)
 {
     if (!pts || !q || !out_idx || !out_d2 || n < 0 || nq < 0 || k < 1 || d < 1)
+        return ORC_EINVAL;
+    if (L && (!inside_period(pts, n, d, L) || !inside_period(q, nq, d, L)))
         return ORC_EINVAL;
     key_t *best = (key_t *)malloc(sizeof(key_t) * (size_t)k);
     if (!best) return ORC_ENOMEM;
@@ -156,7 +194,7 @@ int orc_knn_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq
             best[j].idx = INT32_MAX;
         }
         for (int64_t i = 0; i < n; ++i) {
-            key_t c = {sq_dist(pts + i * d, qt, d), (int32_t)i};
+            key_t c = {metric_sq_dist(pts + i * d, qt, d, L), (int32_t)i};
             if (!key_less(c, best[k - 1])) continue;
             int j = k - 1;
             while (j > 0 && key_less(c, best[j - 1])) {
@@ -171,11 +209,28 @@ int orc_knn_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq
     return ORC_OK;
 }
 
-/* Number of points with d2 <= fl(r*r), and optionally their indices (ascending). */
-int orc_range_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq,
-                    float r, int64_t *out_count, int64_t *offsets, int32_t *out_idx)
+int orc_knn_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq,
+                  int k, int32_t *out_idx, float *out_d2)
+{
+    return knn_brute(pts, n, d, q, nq, k, NULL, out_idx, out_d2);
+}
+
+int orc_knn_brute_torus(const float *pts, int64_t n, int d, const float *q, int64_t nq,
+                        int k, const float *L, int32_t *out_idx, float *out_d2)
+{
+    if (!L) return ORC_EINVAL;
+    return knn_brute(pts, n, d, q, nq, k, L, out_idx, out_d2);
+}
+
+/* Number of points with d2 <= fl(r*r), and optionally their indices
+ * (ascending); on the torus of periods L when L is not NULL. */
+static int range_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq,
+                       float r, const float *L, int64_t *out_count, int64_t *offsets,
+                       int32_t *out_idx)
 {
     if (!pts || !q || !out_count || n < 0 || nq < 0 || d < 1 || !(r >= 0.0f))
+        return ORC_EINVAL;
+    if (L && (!inside_period(pts, n, d, L) || !inside_period(q, nq, d, L)))
         return ORC_EINVAL;
     float r2 = r * r;
     int64_t pos = 0;
@@ -184,7 +239,7 @@ int orc_range_brute(const float *pts, int64_t n, int d, const float *q, int64_t 
         int64_t c = 0;
         if (offsets) offsets[t] = pos;
         for (int64_t i = 0; i < n; ++i) {
-            if (sq_dist(pts + i * d, qt, d) <= r2) {
+            if (metric_sq_dist(pts + i * d, qt, d, L) <= r2) {
                 if (out_idx) out_idx[pos] = (int32_t)i;
                 ++pos;
                 ++c;
@@ -194,6 +249,20 @@ int orc_range_brute(const float *pts, int64_t n, int d, const float *q, int64_t 
     }
     if (offsets) offsets[nq] = pos;
     return ORC_OK;
+}
+
+int orc_range_brute(const float *pts, int64_t n, int d, const float *q, int64_t nq,
+                    float r, int64_t *out_count, int64_t *offsets, int32_t *out_idx)
+{
+    return range_brute(pts, n, d, q, nq, r, NULL, out_count, offsets, out_idx);
+}
+
+int orc_range_brute_torus(const float *pts, int64_t n, int d, const float *q, int64_t nq,
+                          float r, const float *L, int64_t *out_count, int64_t *offsets,
+                          int32_t *out_idx)
+{
+    if (!L) return ORC_EINVAL;
+    return range_brute(pts, n, d, q, nq, r, L, out_count, offsets, out_idx);
 }
 
 /* Friends-of-friends by breadth-first search over all pairs. */
