@@ -84,6 +84,18 @@ typedef struct {
                              every launch.  Results are identical either way;
                              it exists for tuning and for testing the
                              hand-off.  Negative: KDT_EINVAL. */
+    const float *period;  /* NULL: open boundaries.  Else a host array of d
+                             periods L_a (finite, > 0): kdt_knn (k <= KDT_MAX_K)
+                             and kdt_range measure distances on the D-torus
+                             (the periodic boundary conditions of Sec. 2.1 and
+                             Sec. 2.4): per axis the shorter way round,
+                             min(|x - q|, L - |x - q|), squared and summed in
+                             float32 like the open distance.  Every tree point
+                             and query must lie in [0, L_a) (KDT_EINVAL
+                             otherwise; the call waits on its stream to check).
+                             One traversal per lane (traversal and
+                             split_budget are ignored).  kdt_box, and kdt_knn
+                             with k > KDT_MAX_K, return KDT_EUNSUPPORTED. */
 } kdt_query_opts;
 
 /* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side

@@ -256,6 +256,10 @@ extern "C" kdt_status kdt_box(const kdt_tree* tree, const float* d_lo, const flo
     kdt_set_error("kdt_box: traversal must be 0, 1 or 2 and split_budget >= 0");
     return KDT_EINVAL;
   }
+  if (opts && opts->period) {
+    kdt_set_error("kdt_box: periodic boundaries are not supported for box queries");
+    return KDT_EUNSUPPORTED;
+  }
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
   const int32_t* given = opts ? opts->order : nullptr;
   const int trav = opts ? opts->traversal : 0;

@@ -536,6 +536,16 @@ template <int D>
 kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, int k,
                              int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
                              hipStream_t stream);
+// Periodic boundaries (opts->period): kNN (k <= KDT_MAX_K) and ball queries
+// on the D-torus, arguments as kdt_knn / kdt_range.
+kdt_status knn_torus(const kdt_tree* tr, const float* d_q, int64_t nq, int k, int32_t* d_idx,
+                     float* d_d2, int mode, bool sort_q, const int32_t* given,
+                     const float* period, hipStream_t stream);
+kdt_status range_torus(const kdt_tree* tr, const float* d_q, int64_t nq, float r,
+                       int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
+                       int64_t* required, bool sort_q, const int32_t* given, const float* period,
+                       hipStream_t stream);
+
 // k above KDT_MAX_K: exact neighbours from a per-query ball that holds at
 // least k points, its keys sorted per query (arguments as kdt_knn).
 kdt_status knn_large(const kdt_tree* tr, const float* d_q, int64_t nq, int k, int32_t* d_idx,

@@ -491,6 +491,14 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
     kdt_set_error("kdt_knn: traversal must be 0, 1 or 2");
     return KDT_EINVAL;
   }
+  if (opts && opts->period) {
+    if (k > KDT_MAX_K) {
+      kdt_set_error("kdt_knn: k above %d is not supported with periodic boundaries", KDT_MAX_K);
+      return KDT_EUNSUPPORTED;
+    }
+    return knn_torus(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, given, opts->period,
+                     stream);
+  }
   if (k > KDT_MAX_K)
     return knn_large(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, given, stream);
   switch (tree->d) {
@@ -547,6 +555,9 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
     return KDT_OK;
   }
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
+  if (opts && opts->period)
+    return range_torus(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q,
+                       opts->order, opts->period, stream);
   switch (tree->d) {
     case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
     case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);

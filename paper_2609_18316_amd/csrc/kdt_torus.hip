@@ -1,0 +1,446 @@
+// kdt_torus.hip -- kNN and ball queries on the D-torus: the periodic boundary
+// conditions of Sec. 2.1 (the metric replaced by that of a D-toroid) and
+// Sec. 2.4 (a compile-time option there, a template here), on gfx950.
+//
+// Every coordinate lies in [0, L_a).  Along each axis the distance goes the
+// shorter way round, min(|x - q|, L - |x - q|), squared and summed in axis
+// order in float32 without contraction, so results are exact against the
+// oracle's definition.  The tree is the ordinary one: a node is skipped when
+// even the shorter way round to its box is too far, and a node counts whole
+// for a ball when its open-space farthest corner is inside (the torus
+// distance never exceeds the open one).  One traversal per lane.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+
+#include "kdt_query.h"
+
+namespace kdt {
+
+constexpr int kTBlock = 128;
+
+template <int D>
+struct Torus {
+  float L[D];
+};
+
+// Squared torus distance: per axis g = |x - p|, the way round L - g, the
+// shorter of the two squared; summed left to right.
+template <int D>
+__device__ __forceinline__ float torus_sq_dist(const float* __restrict__ x, const float p[D],
+                                               const Torus<D>& T) {
+  float s = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float g = fabsf(x[a] - p[a]);
+    const float w = T.L[a] - g;
+    const float t = w < g ? w : g;
+    const float t2 = t * t;
+    s = s + t2;
+  }
+  return s;
+}
+
+// Lower bound of torus_sq_dist over the points of the box [lo, hi].  Below
+// the box (lo > p) a point's gap lies between lo - p and hi - p, so its way
+// round is at least L - (hi - p); above it, symmetrically.  Every step is a
+// rounded operation that is monotone in the point's coordinate, so the bound
+// never exceeds the rounded distance of any point inside.
+template <int D>
+__device__ __forceinline__ float torus_box_mindist(const float lo[D], const float hi[D],
+                                                   const float p[D], const Torus<D>& T) {
+  float s = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float below = lo[a] - p[a];
+    const float above = p[a] - hi[a];
+    float t = 0.0f;
+    if (below > 0.0f) {
+      const float w = T.L[a] - (hi[a] - p[a]);
+      t = w < below ? w : below;
+    } else if (above > 0.0f) {
+      const float w = T.L[a] - (p[a] - lo[a]);
+      t = w < above ? w : above;
+    }
+    const float t2 = t * t;
+    s = s + t2;
+  }
+  return s;
+}
+
+// kNN of one query on the torus: depth-first, nearer child first, a node
+// skipped when its bound exceeds the current k-th candidate (ties kept).
+// `stk` is this lane's column of an LDS stack with stride `ld`.
+template <int D, class List>
+__device__ __forceinline__ void torus_knn_one(const TreeView& t, const float p[D],
+                                              const Torus<D>& T, List& best, uint32_t* stk,
+                                              int ld) {
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  float lo[D], hi[D];
+  load_box<D>(t.box, 0, lo, hi);
+  uint32_t node = 0;
+  float nd = torus_box_mindist<D>(lo, hi, p, T);
+  int sp = 0;
+  for (;;) {
+    if (nd <= best.worst_d2()) {
+      if (node >= first_leaf) {
+        const int64_t j = node - first_leaf;
+        const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
+        for (int64_t i = b; i < e; ++i) {
+          float x[D];
+          int32_t id = 0;
+          load_rec<D>(t.rec, i, x, id);
+          const float d2 = torus_sq_dist<D>(x, p, T);
+          if (d2 <= best.worst_d2()) best.offer(d2, id);
+        }
+      } else {
+        const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
+        load_box<D>(t.box, c0, lo, hi);
+        const float d0 = torus_box_mindist<D>(lo, hi, p, T);
+        load_box<D>(t.box, c1, lo, hi);
+        const float d1 = torus_box_mindist<D>(lo, hi, p, T);
+        const bool first0 = d0 <= d1;
+        const uint32_t nn = first0 ? c0 : c1, ff = first0 ? c1 : c0;
+        const float dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
+        if (df <= best.worst_d2()) stk[sp++ * ld] = ff;
+        node = nn;
+        nd = dn;
+        continue;
+      }
+    }
+    if (sp == 0) break;
+    node = stk[--sp * ld];
+    load_box<D>(t.box, node, lo, hi);
+    nd = torus_box_mindist<D>(lo, hi, p, T);
+  }
+}
+
+// One query per lane: the tree's own points (q == NULL, row = input index)
+// or q[order[s]] (q[s] without an order).
+template <int D>
+__device__ __forceinline__ int64_t torus_query(const TreeView& t, const float* __restrict__ q,
+                                               const int32_t* __restrict__ order, int64_t s,
+                                               float p[D]) {
+  if (q == nullptr) {
+    int32_t id = 0;
+    load_rec<D>(t.rec, s, p, id);
+    return id;
+  }
+  const int64_t row = order ? order[s] : s;
+#pragma unroll
+  for (int a = 0; a < D; ++a) p[a] = q[row * D + a];
+  return row;
+}
+
+template <int D, int KC, bool KTH>
+__global__ __launch_bounds__(kTBlock) void k_torus_knn(TreeView t, const float* __restrict__ q,
+                                                       int64_t nq, int k,
+                                                       const int32_t* __restrict__ order,
+                                                       Torus<D> T, int mode,
+                                                       int32_t* __restrict__ oidx,
+                                                       float* __restrict__ od2) {
+  extern __shared__ uint32_t torus_stk[];
+  const int64_t s = (int64_t)blockIdx.x * kTBlock + threadIdx.x;
+  if (s >= nq) return;
+  float p[D];
+  const int64_t row = torus_query<D>(t, q, order, s, p);
+  if constexpr (KTH) {
+    TopD<KC> best;
+    best.init(k);
+    torus_knn_one<D>(t, p, T, best, torus_stk + threadIdx.x, kTBlock);
+    knn_write_kth<KC>(best, mode, row, od2);
+  } else {
+    TopK<KC> best;
+    best.init(k);
+    torus_knn_one<D>(t, p, T, best, torus_stk + threadIdx.x, kTBlock);
+    knn_write<KC>(best, k, mode, row, oidx, od2);
+  }
+}
+
+// Closed torus balls: counts (FILL = false) or the input indices of the
+// points inside, from offsets[row] on (FILL = true).  Both children are
+// pushed: at most levels + 2 stack entries.
+template <int D, bool FILL>
+__global__ __launch_bounds__(kTBlock) void k_torus_range(TreeView t, const float* __restrict__ q,
+                                                         int64_t nq, float r2,
+                                                         const int32_t* __restrict__ order,
+                                                         Torus<D> T, int32_t* __restrict__ count,
+                                                         const int64_t* __restrict__ offsets,
+                                                         int32_t* __restrict__ out) {
+  extern __shared__ uint32_t torus_col[];
+  uint32_t* col = torus_col + threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * kTBlock + threadIdx.x;
+  if (s >= nq) return;
+  float p[D];
+  const int64_t row = torus_query<D>(t, q, order, s, p);
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int64_t c = 0;
+  int64_t pos = FILL ? offsets[row] : 0;
+  int sp = 0;
+  col[kTBlock * sp++] = 0;
+  while (sp > 0) {
+    const uint32_t node = col[kTBlock * --sp];
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (torus_box_mindist<D>(lo, hi, p, T) > r2) continue;
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    const bool whole = box_maxdist<D>(lo, hi, p) <= r2;
+    if (whole || node >= first_leaf) {
+      if (whole && !FILL) {
+        c += e - b;
+        continue;
+      }
+      for (int64_t i = b; i < e; ++i) {
+        float x[D];
+        int32_t id = 0;
+        load_rec<D>(t.rec, i, x, id);
+        if (whole || torus_sq_dist<D>(x, p, T) <= r2) {
+          if (FILL) out[pos++] = id;
+          ++c;
+        }
+      }
+      continue;
+    }
+    col[kTBlock * sp++] = 2 * node + 2;
+    col[kTBlock * sp++] = 2 * node + 1;
+  }
+  if (!FILL) count[row] = (int32_t)c;
+}
+
+// flag[0] <- 1 if some query coordinate lies outside [0, L_a).
+template <int D>
+__global__ void k_torus_check(const float* __restrict__ q, int64_t nq, Torus<D> T,
+                              int32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  bool bad = false;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float v = q[i * D + a];
+    bad |= !(v >= 0.0f && v < T.L[a]);
+  }
+  if (bad) flag[0] = 1;
+}
+
+__global__ void k_torus_flag_clear(int32_t* flag) { flag[0] = 0; }
+
+__global__ void k_torus_offsets_last(int64_t* off, const int32_t* count, int64_t nq) {
+  off[nq] = off[nq - 1] + count[nq - 1];
+}
+
+struct TorusI64 {
+  __host__ __device__ int64_t operator()(int32_t v) const { return v; }
+};
+
+// Periods finite and positive, every tree point (its root box) and every
+// query inside [0, L).  Waits on the stream.
+template <int D>
+static kdt_status torus_setup(const kdt_tree* tr, const float* d_q, int64_t nq,
+                              const float* period, PoolBuffers& buf, Torus<D>* T,
+                              hipStream_t stream, const char* who) {
+  for (int a = 0; a < D; ++a) {
+    if (!(period[a] > 0.0f) || !std::isfinite(period[a])) {
+      kdt_set_error("%s: period %d is not finite and > 0", who, a);
+      return KDT_EINVAL;
+    }
+    T->L[a] = period[a];
+  }
+  float root[2 * pad4(D)];
+  int32_t bad = 0;
+  int32_t* flag = nullptr;
+  if (d_q && !buf.get(&flag, 1)) {
+    kdt_set_error("%s: device allocation failed for the period check", who);
+    return KDT_ENOMEM;
+  }
+  if (d_q) {
+    k_torus_flag_clear<<<1, 1, 0, stream>>>(flag);
+    k_torus_check<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(d_q, nq, *T, flag);
+  }
+  if (hipMemcpyAsync(root, tr->box, sizeof(root), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      (d_q && hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream) !=
+                  hipSuccess) ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    kdt_set_error("%s: reading the period check failed", who);
+    return KDT_EDEVICE;
+  }
+  for (int a = 0; a < D; ++a)
+    if (!(root[a] >= 0.0f && root[pad4(D) + a] < T->L[a])) {
+      kdt_set_error("%s: tree points outside [0, period) on axis %d", who, a);
+      return KDT_EINVAL;
+    }
+  if (bad) {
+    kdt_set_error("%s: a query lies outside [0, period)", who);
+    return KDT_EINVAL;
+  }
+  return KDT_OK;
+}
+
+template <int D>
+static kdt_status torus_knn_impl(const kdt_tree* tr, const float* d_q, int64_t nq, int k,
+                                 int32_t* d_idx, float* d_d2, int mode, bool sort_q,
+                                 const int32_t* given, const float* period, hipStream_t stream) {
+  PoolBuffers buf(stream);
+  Torus<D> T;
+  kdt_status st = torus_setup<D>(tr, d_q, nq, period, buf, &T, stream, "kdt_knn");
+  if (st != KDT_OK) return st;
+  TreeView v;
+  v.rec = tr->rec;
+  v.box = tr->box;
+  v.n = tr->n;
+  v.levels = tr->levels;
+  const int32_t* order = given;
+  if (d_q && !given && sort_q && nq > 1) {
+    int32_t* own = nullptr;
+    if (!buf.get(&own, (size_t)nq)) {
+      kdt_set_error("kdt_knn: device allocation failed for the query order");
+      return KDT_ENOMEM;
+    }
+    st = kdt_query_order(tr, d_q, nq, 0, own, stream);
+    if (st != KDT_OK) return st;
+    order = own;
+  }
+  if (!d_q) order = nullptr;
+  const unsigned grid = (unsigned)((nq + kTBlock - 1) / kTBlock);
+  const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 1) * kTBlock;
+#define KDT_TORUS(KC)                                                                          \
+  if (mode == 0)                                                                               \
+    k_torus_knn<D, KC, false><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, k, order, T, mode, \
+                                                               d_idx, d_d2);                   \
+  else                                                                                         \
+    k_torus_knn<D, KC, true><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, k, order, T, mode,  \
+                                                              d_idx, d_d2);
+  if (k <= 8) {
+    KDT_TORUS(8)
+  } else if (k <= 16) {
+    KDT_TORUS(16)
+  } else if (k <= 32) {
+    KDT_TORUS(32)
+  } else {
+    KDT_TORUS(64)
+  }
+#undef KDT_TORUS
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_knn: torus kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+template <int D>
+static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t nq, float r,
+                                   int32_t* d_count, int64_t* d_off, int32_t* d_idx,
+                                   int64_t capacity, int64_t* required, bool sort_q,
+                                   const int32_t* given, const float* period,
+                                   hipStream_t stream) {
+  PoolBuffers buf(stream);
+  Torus<D> T;
+  kdt_status st = torus_setup<D>(tr, d_q, nq, period, buf, &T, stream, "kdt_range");
+  if (st != KDT_OK) return st;
+  TreeView v;
+  v.rec = tr->rec;
+  v.box = tr->box;
+  v.n = tr->n;
+  v.levels = tr->levels;
+  const int32_t* order = given;
+  if (d_q && !given && sort_q && nq > 1) {
+    int32_t* own = nullptr;
+    if (!buf.get(&own, (size_t)nq)) {
+      kdt_set_error("kdt_range: device allocation failed for the query order");
+      return KDT_ENOMEM;
+    }
+    st = kdt_query_order(tr, d_q, nq, 0, own, stream);
+    if (st != KDT_OK) return st;
+    order = own;
+  }
+  if (!d_q) order = nullptr;
+  const float r2 = r * r;
+  const unsigned grid = (unsigned)((nq + kTBlock - 1) / kTBlock);
+  const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;
+  k_torus_range<D, false><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, r2, order, T, d_count,
+                                                            nullptr, nullptr);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_range: torus count kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  if (!d_off) return KDT_OK;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  hipcub::TransformInputIterator<int64_t, TorusI64, const int32_t*> c64(d_count, TorusI64());
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, c64, d_off, (int)nq, stream) != hipSuccess ||
+      !buf.get((char**)&tmp, tb) ||
+      hipcub::DeviceScan::ExclusiveSum(tmp, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
+    kdt_set_error("kdt_range: torus offset scan failed");
+    return KDT_EDEVICE;
+  }
+  k_torus_offsets_last<<<1, 1, 0, stream>>>(d_off, d_count, nq);
+  int64_t total = 0;
+  if (hipMemcpyAsync(&total, d_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    kdt_set_error("kdt_range: reading the list size failed");
+    return KDT_EDEVICE;
+  }
+  if (required) *required = total;
+  if (!d_idx || total == 0) return KDT_OK;
+  if (total > capacity) {
+    kdt_set_error("list capacity %lld is below the %lld entries needed", (long long)capacity,
+                  (long long)total);
+    return KDT_ECAPACITY;
+  }
+  if (total > INT32_MAX) {
+    kdt_set_error("lists above 2^31-1 entries are not supported");
+    return KDT_EUNSUPPORTED;
+  }
+  int32_t* unsorted = nullptr;
+  if (!buf.get(&unsorted, (size_t)total)) {
+    kdt_set_error("device allocation failed for the lists");
+    return KDT_ENOMEM;
+  }
+  k_torus_range<D, true><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, r2, order, T, d_count, d_off,
+                                                           unsorted);
+  void* stmp = nullptr;
+  size_t sb = 0;
+  if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total, (int)nq,
+                                            d_off, d_off + 1, stream) != hipSuccess ||
+      !buf.get((char**)&stmp, sb) ||
+      hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total, (int)nq, d_off,
+                                            d_off + 1, stream) != hipSuccess) {
+    kdt_set_error("kdt_range: torus list sort failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+kdt_status knn_torus(const kdt_tree* tr, const float* d_q, int64_t nq, int k, int32_t* d_idx,
+                     float* d_d2, int mode, bool sort_q, const int32_t* given,
+                     const float* period, hipStream_t stream) {
+  switch (tr->d) {
+    case 2: return torus_knn_impl<2>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+    case 3: return torus_knn_impl<3>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+    case 4: return torus_knn_impl<4>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+    case 8: return torus_knn_impl<8>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+    case 16: return torus_knn_impl<16>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+  }
+  kdt_set_error("kdt_knn: unsupported dimension %d", tr->d);
+  return KDT_EUNSUPPORTED;
+}
+
+kdt_status range_torus(const kdt_tree* tr, const float* d_q, int64_t nq, float r,
+                       int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
+                       int64_t* required, bool sort_q, const int32_t* given, const float* period,
+                       hipStream_t stream) {
+  switch (tr->d) {
+    case 2: return torus_range_impl<2>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
+    case 3: return torus_range_impl<3>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
+    case 4: return torus_range_impl<4>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
+    case 8: return torus_range_impl<8>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
+    case 16: return torus_range_impl<16>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
+  }
+  kdt_set_error("kdt_range: unsupported dimension %d", tr->d);
+  return KDT_EUNSUPPORTED;
+}
+
+}  // namespace kdt

@@ -38,9 +38,19 @@ class BuildOpts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("check_finite", C.c_int32)]
 
 
+def _periods(period, d: int):
+    """ctypes float[d] of the torus periods (one value or one per axis), or None."""
+    if period is None:
+        return None
+    vals = [float(v) for v in period] if hasattr(period, "__len__") else [float(period)] * d
+    if len(vals) != d:
+        raise ValueError(f"period needs 1 or {d} values, got {len(vals)}")
+    return (C.c_float * d)(*vals)
+
+
 class QueryOpts(C.Structure):
     _fields_ = [("sort_queries", C.c_int32), ("traversal", C.c_int32), ("order", C.c_void_p),
-                ("split_budget", C.c_int32)]
+                ("split_budget", C.c_int32), ("period", C.POINTER(C.c_float))]
 
 
 class Grid(C.Structure):
@@ -176,16 +186,19 @@ class Tree:
 
     def knn(self, queries: torch.Tensor | None, k: int, kth_only: int = 0,
             sort_queries: bool = True, traversal: int = 0, order: torch.Tensor | None = None,
-            stream=None):
+            period=None, stream=None):
         """k nearest neighbours, ascending by (d2, index): (idx [nq][k], d2 [nq][k]).
 
         ``queries=None`` queries every point of the tree (row i = input point i).
         ``kth_only=1`` returns only d2 of the k-th neighbour, ``2`` its distance.
+        ``period`` (one value or one per axis): distances on the D-torus, every
+        point and query in [0, period).
         """
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order))
+        per = _periods(period, self.d)
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), 0, per)
         if kth_only:
             d2 = torch.empty(nq, dtype=torch.float32, device=self.device)
             _check(load().kdt_knn(self._h, _ptr(queries), nq, k, None, _ptr(d2), kth_only,
@@ -199,17 +212,20 @@ class Tree:
 
     def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
               sort_queries: bool = True, order: torch.Tensor | None = None, traversal: int = 0,
-              split_budget: int = 0, stream=None):
+              split_budget: int = 0, period=None, stream=None):
         """Closed-ball counts; with ``lists`` also CSR (offsets int64, idx int32).
 
         ``split_budget`` > 0 makes every wave of the wave-shared count hand
         subtrees on to later launches after that many node visits (results are
-        identical; 0 keeps the default schedule).
+        identical; 0 keeps the default schedule).  ``period``: balls on the
+        D-torus, as in ``knn``.
         """
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), int(split_budget))
+        per = _periods(period, self.d)
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), int(split_budget),
+                         per)
         count = torch.empty(nq, dtype=torch.int32, device=self.device)
         lib = load()
         if not lists:

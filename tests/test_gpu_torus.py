@@ -1,0 +1,160 @@
+"""GPU parity for periodic boundaries (kNN and ball queries on the D-torus,
+Sec. 2.1 and Sec. 2.4) against the oracle's brute force on the same seeded
+inputs, bit-exact: every dimension, several point kinds wrapped into the
+period, per-axis periods, self and external queries, all k-th modes, counts
+and CSR lists, the full-size clustered workload (sampled rows) and the error
+paths."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2609_18316_amd import kdt, workloads
+from tests import cases
+from tests.gpu_util import dev, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ("uniform", "duplicates", "lattice", "normal", "collinear")
+
+
+def wrap(x: np.ndarray, L) -> np.ndarray:
+    """Coordinates folded into [0, L) per axis (float32, never equal to L)."""
+    L = np.broadcast_to(np.asarray(L, np.float64), (x.shape[1],))
+    y = np.mod(x.astype(np.float64), L).astype(np.float32)
+    top = np.nextafter(L.astype(np.float32), np.float32(0))
+    return np.minimum(y, top).astype(np.float32)
+
+
+def _periods(d):
+    return np.array([1.0, 2.0, 0.5, 1.0] * 4, np.float32)[:d]
+
+
+@pytest.mark.parametrize("d", kdt.DIMS)
+@pytest.mark.parametrize("kind", KINDS)
+def test_torus_knn_equals_brute_force(kind, d):
+    dev()
+    L = _periods(d)
+    for n in (1, 33, 1000, 5000):
+        x = wrap(cases.points(kind, n, d, seed=5 * n + d) * 1.7 - 0.3, L)
+        q = wrap(cases.points(kind, 200, d, seed=9 * n + d) * 1.7 - 0.3, L)
+        t = kdt.build(to_dev(x), leaf_size=16)
+        for k in sorted({1, 8, 32, 64, min(n + 3, 64)}):
+            say(f"torus knn d={d} kind={kind} n={n} k={k}")
+            oi, od = oracle.knn_brute(x, q, k, period=L)
+            gi, gd = t.knn(to_dev(q), k, period=L)
+            np.testing.assert_array_equal(to_host(gi), oi)
+            np.testing.assert_array_equal(to_host(gd), od)
+            np.testing.assert_array_equal(to_host(t.knn(to_dev(q), k, kth_only=1, period=L)),
+                                          od[:, -1])
+            if n <= 1000:
+                oi, od = oracle.knn_brute(x, x, k, period=L)
+                si, sd = t.knn(None, k, period=L)
+                np.testing.assert_array_equal(to_host(si), oi)
+                np.testing.assert_array_equal(to_host(sd), od)
+                np.testing.assert_array_equal(to_host(t.knn(None, k, kth_only=2, period=L)),
+                                              np.sqrt(od[:, -1]))
+
+
+@pytest.mark.parametrize("d", kdt.DIMS)
+def test_torus_range_counts_and_lists(d):
+    dev()
+    L = _periods(d)
+    x = wrap(workloads.normal(6000, d, seed=d) * 0.4 + 0.1, L)
+    q = wrap(workloads.uniform(400, d, seed=50 + d) * 1.3, L)
+    for leaf in (8, 32, 100):
+        t = kdt.build(to_dev(x), leaf_size=leaf)
+        for r in (0.0, 0.05, 0.2, 0.6, 3.0):
+            say(f"torus range d={d} leaf={leaf} r={r}")
+            oc, oo, ol = oracle.range_brute(x, q, r, lists=True, period=L)
+            gc, go, gl = t.range(to_dev(q), r, lists=True, period=L)
+            np.testing.assert_array_equal(to_host(gc), oc)
+            np.testing.assert_array_equal(to_host(go), oo)
+            np.testing.assert_array_equal(to_host(gl), ol)
+        sc = oracle.range_brute(x, x, 0.1, period=L)
+        np.testing.assert_array_equal(to_host(t.range(None, 0.1, period=L)), sc)
+
+
+def test_torus_clustered_orders_and_lattice_ties():
+    """Clustered catalogue points across the faces of the unit box, reused and
+    unsorted query orders; a coarse lattice where most distances tie."""
+    dev()
+    x = workloads.clustered(60000, seed=8)
+    q = workloads.uniform(3000, 3, seed=9)
+    t = kdt.build(to_dev(x), leaf_size=32)
+    qd = to_dev(q)
+    oi, od = oracle.knn_brute(x, q, 32, period=1.0)
+    order = t.query_order(qd, kind=0)
+    for kw in ({}, {"sort_queries": False}, {"order": order}):
+        say(f"torus clustered {list(kw)}")
+        gi, gd = t.knn(qd, 32, period=1.0, **kw)
+        np.testing.assert_array_equal(to_host(gi), oi)
+        np.testing.assert_array_equal(to_host(gd), od)
+    np.testing.assert_array_equal(to_host(t.range(qd, 0.02, period=1.0)),
+                                  oracle.range_brute(x, q, 0.02, period=1.0))
+    rng = np.random.Generator(np.random.PCG64(3))
+    xl = (rng.integers(0, 8, (5000, 3)) / 8.0).astype(np.float32)
+    ql = (rng.integers(0, 8, (300, 3)) / 8.0).astype(np.float32)
+    tl = kdt.build(to_dev(xl), leaf_size=16)
+    for k in (10, 64):
+        say(f"torus lattice ties k={k}")
+        oi, od = oracle.knn_brute(xl, ql, k, period=1.0)
+        gi, gd = tl.knn(to_dev(ql), k, period=1.0)
+        np.testing.assert_array_equal(to_host(gi), oi)
+        np.testing.assert_array_equal(to_host(gd), od)
+
+
+def test_torus_full_size_sampled():
+    """The 2^24-point clustered workload in the unit box, k = 32 for 2^22
+    uniform queries and r = 0.01 counts, on the torus; sampled rows against
+    brute force."""
+    dev()
+    x = workloads.clustered(1 << 24, seed=2)
+    q = workloads.uniform(1 << 22, 3, seed=102)
+    t = kdt.build(to_dev(x), leaf_size=32)
+    qd = to_dev(q)
+    say("torus full size knn")
+    gi, gd = t.knn(qd, 32, period=1.0)
+    gc = t.range(qd, 0.01, period=1.0)
+    rows = workloads.sample_indices(1 << 22, 48, seed=11)
+    # rows near the faces, where the way round matters
+    edge = np.nonzero((q.min(axis=1) < 0.01) | (q.max(axis=1) > 0.99))[0][:16]
+    rows = np.concatenate([rows, edge])
+    oi, od = oracle.knn_brute(x, q[rows], 32, period=1.0)
+    np.testing.assert_array_equal(to_host(gi)[rows], oi)
+    np.testing.assert_array_equal(to_host(gd)[rows], od)
+    np.testing.assert_array_equal(to_host(gc)[rows],
+                                  oracle.range_brute(x, q[rows], 0.01, period=1.0))
+
+
+def test_torus_errors():
+    dev()
+    x = workloads.uniform(500, 3, seed=4)
+    t = kdt.build(to_dev(x))
+    q = workloads.uniform(10, 3, seed=5)
+    for bad_period in (0.0, -1.0, float("nan"), float("inf"), 0.5):
+        with pytest.raises(kdt.KdtError) as e:
+            t.knn(to_dev(q), 4, period=bad_period)
+        assert e.value.status == kdt.KDT_EINVAL
+    qo = q.copy()
+    qo[3, 1] = 1.0
+    with pytest.raises(kdt.KdtError) as e:
+        t.knn(to_dev(qo), 4, period=1.0)
+    assert e.value.status == kdt.KDT_EINVAL
+    with pytest.raises(kdt.KdtError) as e:
+        t.range(to_dev(qo), 0.1, period=1.0)
+    assert e.value.status == kdt.KDT_EINVAL
+    with pytest.raises(kdt.KdtError) as e:
+        t.knn(to_dev(q), kdt.MAX_K + 1, period=1.0)
+    assert e.value.status == kdt.KDT_EUNSUPPORTED
+    with pytest.raises(kdt.KdtError) as e:
+        opts_lo = torch.zeros((2, 3), dtype=torch.float32, device="cuda")
+        opts = kdt.QueryOpts(1, 0, None, 0, kdt._periods(1.0, 3))
+        st = kdt.load().kdt_box(t._h, kdt._ptr(opts_lo), kdt._ptr(opts_lo), 2,
+                                kdt._ptr(torch.empty(2, dtype=torch.int32, device="cuda")),
+                                None, None, 0, None, kdt.C.byref(opts), None)
+        kdt._check(st)
+    assert e.value.status == kdt.KDT_EUNSUPPORTED
+    # an empty query set is fine with a period
+    gi, gd = t.knn(torch.empty((0, 3), dtype=torch.float32, device="cuda"), 4, period=1.0)
+    assert gi.shape == (0, 4)
