@@ -46,6 +46,7 @@ def _load():
     lib.orc_knn_brute_torus.argtypes = [_f32p, i64, i32, _f32p, i64, i32, _f32p, _i32p, _f32p]
     lib.orc_range_brute_torus.argtypes = [_f32p, i64, i32, _f32p, i64, f32, _f32p, _i64p, vp, vp]
     lib.orc_fof_brute.argtypes = [_f32p, i64, i32, f32, _i32p]
+    lib.orc_fof_brute_torus.argtypes = [_f32p, i64, i32, f32, _f32p, _i32p]
     lib.orc_tree_build.argtypes = [_f32p, i64, i32, i32, C.POINTER(vp)]
     lib.orc_tree_free.argtypes = [vp]
     lib.orc_tree_free.restype = None
@@ -163,11 +164,18 @@ def box_brute(pts, lo, hi, lists: bool = False):
     return counts, offsets, (np.concatenate(rows) if rows else np.empty(0, np.int32))
 
 
-def fof_brute(pts, l: float) -> np.ndarray:
+def fof_brute(pts, l: float, period=None) -> np.ndarray:
+    """Group label (smallest input index of the group) of every point;
+    ``period``: friends on the D-torus, as in ``knn_brute``."""
     pts = _pts(pts)
     labels = np.empty(pts.shape[0], np.int32)
-    _check(_load().orc_fof_brute(pts, pts.shape[0], pts.shape[1], np.float32(l), labels),
-           "fof_brute")
+    lib = _load()
+    if period is None:
+        rc = lib.orc_fof_brute(pts, pts.shape[0], pts.shape[1], np.float32(l), labels)
+    else:
+        rc = lib.orc_fof_brute_torus(pts, pts.shape[0], pts.shape[1], np.float32(l),
+                                     _period(period, pts.shape[1]), labels)
+    _check(rc, "fof_brute")
     return labels
 
 

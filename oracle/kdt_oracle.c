@@ -14,7 +14,7 @@
  *     conditions of Sec. 2.1 and Sec. 2.4): per axis the shorter way round,
  *     min(|x - q|, L - |x - q|), for coordinates in [0, L);
  *   - brute-force kNN, ball counts/lists and friends-of-friends groups: the
- *     plain definitions, O(N^2) (kNN and balls also on the torus);
+ *     plain definitions, O(N^2) (also on the torus);
  *   - the sliding-midpoint k-d tree of Sec. 2.1 (Algorithm 1, serial);
  *   - best-first kNN over that tree with a node min-heap and a candidate
  *     max-heap (Algorithm 2), results sorted at the end (Sec. 2.3);
@@ -265,10 +265,13 @@ int orc_range_brute_torus(const float *pts, int64_t n, int d, const float *q, in
     return range_brute(pts, n, d, q, nq, r, L, out_count, offsets, out_idx);
 }
 
-/* Friends-of-friends by breadth-first search over all pairs. */
-int orc_fof_brute(const float *pts, int64_t n, int d, float l, int32_t *labels)
+/* Friends-of-friends by breadth-first search over all pairs; on the torus of
+ * periods L when L is not NULL. */
+static int fof_brute(const float *pts, int64_t n, int d, float l, const float *L,
+                     int32_t *labels)
 {
     if (!pts || !labels || n < 0 || d < 1 || !(l >= 0.0f)) return ORC_EINVAL;
+    if (L && !inside_period(pts, n, d, L)) return ORC_EINVAL;
     float l2 = l * l;
     int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     if (!queue) return ORC_ENOMEM;
@@ -283,7 +286,7 @@ int orc_fof_brute(const float *pts, int64_t n, int d, float l, int32_t *labels)
             int64_t u = queue[head++];
             for (int64_t v = 0; v < n; ++v) {
                 if (labels[v] >= 0 || v == u) continue;
-                if (sq_dist(pts + u * d, pts + v * d, d) <= l2) {
+                if (metric_sq_dist(pts + u * d, pts + v * d, d, L) <= l2) {
                     labels[v] = (int32_t)s;
                     queue[tail++] = v;
                 }
@@ -292,6 +295,18 @@ int orc_fof_brute(const float *pts, int64_t n, int d, float l, int32_t *labels)
     }
     free(queue);
     return ORC_OK;
+}
+
+int orc_fof_brute(const float *pts, int64_t n, int d, float l, int32_t *labels)
+{
+    return fof_brute(pts, n, d, l, NULL, labels);
+}
+
+int orc_fof_brute_torus(const float *pts, int64_t n, int d, float l, const float *L,
+                        int32_t *labels)
+{
+    if (!L) return ORC_EINVAL;
+    return fof_brute(pts, n, d, l, L, labels);
 }
 
 /* ------------------------------------------------------------------------ */

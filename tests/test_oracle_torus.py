@@ -120,3 +120,52 @@ def test_torus_rejects_coordinates_outside_the_period():
         oracle.knn_brute(x, x[:1], 1, period=1.0)
     with pytest.raises(ValueError):
         oracle.range_brute(x[:1], np.array([[-0.1, 0.2]], np.float32), 0.1, period=1.0)
+
+
+def _groups_by_union(edges_ok, n):
+    """Smallest-index labels of the components of a boolean adjacency matrix."""
+    parent = list(range(n))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    ii, jj = np.nonzero(edges_ok)
+    for a, b in zip(ii.tolist(), jj.tolist()):
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            parent[max(ra, rb)] = min(ra, rb)
+    return np.array([find(i) for i in range(n)], np.int32)
+
+
+@pytest.mark.parametrize("d", (2, 3, 8))
+def test_torus_fof_lattice_matches_integer_images(d):
+    """Groups on a 1/16 lattice with per-axis periods equal the components of
+    the integer image-distance graph (union-find over all pairs)."""
+    rng = np.random.Generator(np.random.PCG64(60 + d))
+    per = np.array([16, 32, 8, 16] * 4)[:d]
+    xi = rng.integers(0, per, (300, d))
+    x = (xi / 16.0).astype(np.float32)
+    L = (per / 16.0).astype(np.float32)
+    for l16 in (0, 1, 2.5, 4):
+        got = oracle.fof_brute(x, l16 / 16.0, period=L)
+        d2 = np.stack([_image_d2(xi, xi[s], per) for s in range(len(xi))])
+        want = _groups_by_union(d2 <= l16 * l16, len(xi))
+        np.testing.assert_array_equal(got, want)
+
+
+def test_torus_fof_reduces_and_translates():
+    """Inside half a period FoF on the torus equals the open one; a lattice
+    shift modulo the period leaves the groups unchanged."""
+    x = cases.points("normal", 800, 3, seed=3)
+    xs = ((x - x.min()) * (np.float32(0.49) / (x.max() - x.min()))).astype(np.float32)
+    for l in (0.005, 0.02):
+        np.testing.assert_array_equal(oracle.fof_brute(xs, l, period=1.0), oracle.fof_brute(xs, l))
+    rng = np.random.Generator(np.random.PCG64(2))
+    xi = rng.integers(0, 16, (500, 3))
+    base = oracle.fof_brute((xi / 16.0).astype(np.float32), 1.5 / 16, period=1.0)
+    moved = oracle.fof_brute((((xi + (7, 15, 3)) % 16) / 16.0).astype(np.float32), 1.5 / 16,
+                             period=1.0)
+    np.testing.assert_array_equal(moved, base)
