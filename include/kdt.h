@@ -262,6 +262,19 @@ kdt_status kdt_fof(const kdt_tree *tree, float l, int32_t *d_labels, int64_t *n_
                    hipStream_t stream);
 
 /*
+ * kdt_fof_torus -- friends-of-friends groups on the D-torus (Sec. 4.1 with the
+ * periodic boundary conditions of Sec. 2.1 and Sec. 2.4): as kdt_fof, with
+ * the distance of kdt_query_opts.period.  period: host array of d periods
+ * L_a (finite, > 0); every tree point must lie in [0, L_a) (KDT_EINVAL
+ * otherwise).  The call waits on `stream` once to check the periods against
+ * the tree's bounding box.  One search per point and lane.
+ *
+ * Errors: KDT_EINVAL (l, period, points outside), KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_fof_torus(const kdt_tree *tree, float l, const float *period, int32_t *d_labels,
+                         int64_t *n_groups, hipStream_t stream);
+
+/*
  * kdt_p2m -- adaptive SPH particle-to-mesh deposit (Sec. 4.2).
  *
  * d_x [n][3], d_m [n], d_h [n] float32 device: positions, masses and

@@ -8,7 +8,8 @@
 // oracle's definition.  The tree is the ordinary one: a node is skipped when
 // even the shorter way round to its box is too far, and a node counts whole
 // for a ball when its open-space farthest corner is inside (the torus
-// distance never exceeds the open one).  One traversal per lane.
+// distance never exceeds the open one).  One traversal per lane.  Also
+// friends-of-friends groups on the torus (kdt_fof_torus).
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -414,6 +415,108 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   return KDT_OK;
 }
 
+// Friends-of-friends on the torus (Sec. 4.1 with the periodic metric): one
+// lane per point in tree order searches its ball of radius l and links every
+// friend at a later tree position (nodes ending at or before its own are not
+// entered: the other end of each such pair links it), through the same
+// lock-free union-find as the open grouping, whose roots are the smallest
+// input indices.  Both children are pushed: at most levels + 2 entries.
+template <int D>
+__global__ __launch_bounds__(kTBlock) void k_torus_fof_link(TreeView t, float l2, Torus<D> T,
+                                                            int32_t* __restrict__ parent) {
+  extern __shared__ uint32_t torus_fcol[];
+  uint32_t* col = torus_fcol + threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * kTBlock + threadIdx.x;
+  if (s >= t.n) return;
+  float p[D];
+  int32_t me = 0;
+  load_rec<D>(t.rec, s, p, me);
+  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  int sp = 0;
+  col[kTBlock * sp++] = 0;
+  while (sp > 0) {
+    const uint32_t node = col[kTBlock * --sp];
+    const int lev = node_level(node);
+    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
+    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    if (e <= s + 1) continue;  // every point at or before this one
+    float lo[D], hi[D];
+    load_box<D>(t.box, node, lo, hi);
+    if (torus_box_mindist<D>(lo, hi, p, T) > l2) continue;
+    const bool whole = box_maxdist<D>(lo, hi, p) <= l2;
+    if (whole || node >= first_leaf) {
+      for (int64_t i = b > s ? b : s + 1; i < e; ++i) {
+        float x[D];
+        int32_t id = 0;
+        load_rec<D>(t.rec, i, x, id);
+        if (whole || torus_sq_dist<D>(x, p, T) <= l2) uf_union(parent, me, id);
+      }
+      continue;
+    }
+    col[kTBlock * sp++] = 2 * node + 2;
+    col[kTBlock * sp++] = 2 * node + 1;
+  }
+}
+
+__global__ void k_torus_fof_init(int32_t* __restrict__ parent, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) parent[i] = (int32_t)i;
+}
+
+// Every element pointed at its root (written by its own lane only).
+__global__ void k_torus_fof_final(int32_t* __restrict__ parent, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) uf_st(parent + i, uf_root(parent, (int32_t)i));
+}
+
+struct TorusIsRoot {
+  const int32_t* lab;
+  __host__ __device__ int64_t operator()(int64_t i) const { return lab[i] == (int32_t)i ? 1 : 0; }
+};
+
+template <int D>
+static kdt_status torus_fof_impl(const kdt_tree* tr, float l, const float* period,
+                                 int32_t* d_labels, int64_t* n_groups, hipStream_t stream) {
+  PoolBuffers buf(stream);
+  Torus<D> T;
+  kdt_status st = torus_setup<D>(tr, nullptr, 0, period, buf, &T, stream, "kdt_fof_torus");
+  if (st != KDT_OK) return st;
+  TreeView v;
+  v.rec = tr->rec;
+  v.box = tr->box;
+  v.n = tr->n;
+  v.levels = tr->levels;
+  const int64_t n = tr->n;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  k_torus_fof_init<<<g, 256, 0, stream>>>(d_labels, n);
+  const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;
+  k_torus_fof_link<D><<<(unsigned)((n + kTBlock - 1) / kTBlock), kTBlock, smem, stream>>>(
+      v, l * l, T, d_labels);
+  k_torus_fof_final<<<g, 256, 0, stream>>>(d_labels, n);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_fof_torus: kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  if (!n_groups) return KDT_OK;
+  hipcub::CountingInputIterator<int64_t> ci(0);
+  hipcub::TransformInputIterator<int64_t, TorusIsRoot, hipcub::CountingInputIterator<int64_t>>
+      roots(ci, TorusIsRoot{d_labels});
+  int64_t* d_out = nullptr;
+  char* tmp = nullptr;
+  size_t tb = 0;
+  int64_t h = 0;
+  if (hipcub::DeviceReduce::Sum(nullptr, tb, roots, d_out, (int)n, stream) != hipSuccess ||
+      !buf.get(&d_out, 1) || !buf.get(&tmp, tb) ||
+      hipcub::DeviceReduce::Sum(tmp, tb, roots, d_out, (int)n, stream) != hipSuccess ||
+      hipMemcpyAsync(&h, d_out, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    kdt_set_error("kdt_fof_torus: counting groups failed");
+    return KDT_EDEVICE;
+  }
+  *n_groups = h;
+  return KDT_OK;
+}
+
 kdt_status knn_torus(const kdt_tree* tr, const float* d_q, int64_t nq, int k, int32_t* d_idx,
                      float* d_d2, int mode, bool sort_q, const int32_t* given,
                      const float* period, hipStream_t stream) {
@@ -444,3 +547,23 @@ kdt_status range_torus(const kdt_tree* tr, const float* d_q, int64_t nq, float r
 }
 
 }  // namespace kdt
+
+using namespace kdt;
+
+extern "C" kdt_status kdt_fof_torus(const kdt_tree* tree, float l, const float* period,
+                                    int32_t* d_labels, int64_t* n_groups, hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree || !d_labels || !period || !(l >= 0.0f) || !std::isfinite(l)) {
+    kdt_set_error("kdt_fof_torus: NULL tree, labels or period, or l not finite and >= 0");
+    return KDT_EINVAL;
+  }
+  switch (tree->d) {
+    case 2: return torus_fof_impl<2>(tree, l, period, d_labels, n_groups, stream);
+    case 3: return torus_fof_impl<3>(tree, l, period, d_labels, n_groups, stream);
+    case 4: return torus_fof_impl<4>(tree, l, period, d_labels, n_groups, stream);
+    case 8: return torus_fof_impl<8>(tree, l, period, d_labels, n_groups, stream);
+    case 16: return torus_fof_impl<16>(tree, l, period, d_labels, n_groups, stream);
+  }
+  kdt_set_error("kdt_fof_torus: unsupported dimension %d", tree->d);
+  return KDT_EUNSUPPORTED;
+}

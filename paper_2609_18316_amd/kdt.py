@@ -24,7 +24,8 @@ DIMS = (2, 3, 4, 8, 16)
 
 # Every exported entry point of include/kdt.h.
 EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt_knn",
-           "kdt_range", "kdt_box", "kdt_fof", "kdt_p2m", "kdt_p2m_backward", "kdt_tree_perm", "kdt_query_order",
+           "kdt_range", "kdt_box", "kdt_fof", "kdt_fof_torus", "kdt_p2m", "kdt_p2m_backward",
+           "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_last_error")
 
 
@@ -84,6 +85,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_box.argtypes = [vp, vp, vp, i64, vp, vp, vp, i64, C.POINTER(C.c_int64),
                             C.POINTER(QueryOpts), vp]
     lib.kdt_fof.argtypes = [vp, f32, vp, C.POINTER(C.c_int64), vp]
+    lib.kdt_fof_torus.argtypes = [vp, f32, C.POINTER(C.c_float), vp, C.POINTER(C.c_int64), vp]
     lib.kdt_p2m.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp]
     lib.kdt_p2m_backward.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp, vp, vp]
     lib.kdt_query_order.argtypes = [vp, vp, i64, C.c_int32, vp, vp]
@@ -266,10 +268,18 @@ class Tree:
                            idx.numel(), C.byref(req), C.byref(opts), _stream(stream)))
         return count, offsets, idx[:req.value]
 
-    def fof(self, linking_length: float, count_groups: bool = False, stream=None):
-        """Friends-of-friends labels (smallest input index of each group)."""
+    def fof(self, linking_length: float, count_groups: bool = False, period=None, stream=None):
+        """Friends-of-friends labels (smallest input index of each group).
+
+        ``period``: groups on the D-torus, as in ``knn``.
+        """
         labels = torch.empty(self.n, dtype=torch.int32, device=self.device)
         ng = C.c_int64(0)
+        if period is not None:
+            _check(load().kdt_fof_torus(self._h, float(linking_length), _periods(period, self.d),
+                                        _ptr(labels), C.byref(ng) if count_groups else None,
+                                        _stream(stream)))
+            return (labels, ng.value) if count_groups else labels
         _check(load().kdt_fof(self._h, float(linking_length), _ptr(labels),
                               C.byref(ng) if count_groups else None, _stream(stream)))
         return (labels, ng.value) if count_groups else labels

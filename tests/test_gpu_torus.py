@@ -1,5 +1,5 @@
-"""GPU parity for periodic boundaries (kNN and ball queries on the D-torus,
-Sec. 2.1 and Sec. 2.4) against the oracle's brute force on the same seeded
+"""GPU parity for periodic boundaries (kNN, ball queries and friends-of-friends
+on the D-torus, Sec. 2.1 and Sec. 2.4) against the oracle's brute force on the same seeded
 inputs, bit-exact: every dimension, several point kinds wrapped into the
 period, per-axis periods, self and external queries, all k-th modes, counts
 and CSR lists, the full-size clustered workload (sampled rows) and the error
@@ -73,6 +73,38 @@ def test_torus_range_counts_and_lists(d):
             np.testing.assert_array_equal(to_host(gl), ol)
         sc = oracle.range_brute(x, x, 0.1, period=L)
         np.testing.assert_array_equal(to_host(t.range(None, 0.1, period=L)), sc)
+
+
+@pytest.mark.parametrize("d", kdt.DIMS)
+@pytest.mark.parametrize("kind", ("uniform", "duplicates", "lattice", "normal"))
+def test_torus_fof_equals_brute_force(kind, d):
+    dev()
+    L = _periods(d)
+    for n in (1, 33, 2000):
+        x = wrap(cases.points(kind, n, d, seed=3 * n + d) * 1.7 - 0.3, L)
+        for leaf in (4, 32):
+            t = kdt.build(to_dev(x), leaf_size=leaf)
+            for l in (0.0, 0.03, 0.1, 0.4):
+                say(f"torus fof d={d} kind={kind} n={n} leaf={leaf} l={l}")
+                want = oracle.fof_brute(x, l, period=L)
+                got, ng = t.fof(l, count_groups=True, period=L)
+                np.testing.assert_array_equal(to_host(got), want)
+                assert ng == len(np.unique(want))
+
+
+def test_torus_fof_clustered_joins_across_faces():
+    """Clustered catalogue points whose halos wrap across the faces: the torus
+    groups equal brute force and join pieces that the open grouping keeps apart."""
+    dev()
+    x = workloads.clustered(20000, seed=12)
+    t = kdt.build(to_dev(x), leaf_size=32)
+    for l in (0.002, 0.006):
+        say(f"torus fof clustered l={l}")
+        want = oracle.fof_brute(x, l, period=1.0)
+        got, ng = t.fof(l, count_groups=True, period=1.0)
+        np.testing.assert_array_equal(to_host(got), want)
+        assert ng == len(np.unique(want))
+        assert ng <= t.fof(l, count_groups=True)[1]
 
 
 def test_torus_clustered_orders_and_lattice_ties():
@@ -155,6 +187,12 @@ def test_torus_errors():
                                 None, None, 0, None, kdt.C.byref(opts), None)
         kdt._check(st)
     assert e.value.status == kdt.KDT_EUNSUPPORTED
+    with pytest.raises(kdt.KdtError) as e:
+        t.fof(0.01, period=0.5)
+    assert e.value.status == kdt.KDT_EINVAL
+    with pytest.raises(kdt.KdtError) as e:
+        t.fof(-1.0, period=1.0)
+    assert e.value.status == kdt.KDT_EINVAL
     # an empty query set is fine with a period
     gi, gd = t.knn(torch.empty((0, 3), dtype=torch.float32, device="cuda"), 4, period=1.0)
     assert gi.shape == (0, 4)
