@@ -52,8 +52,8 @@ BATCH_SETS = 256
 KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
                 "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
-    "sha256": "b6c5c4b299fbfc3080844f55c4f44436882c2a3aa943b681eaac47964a6faaff",
-    "hbm_bytes": 2.1458e+09,
+    "sha256": "64a60593f33a1813c331e57257d10d29ee3292f2fc1157d9195ed538798a015d",
+    "hbm_bytes": 2.1453e+09,
     "l2_hit_rate": 0.964,
     "valu_issue_frac": 0.71,
 }
@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--no-dsweep", action="store_true")
     ap.add_argument("--no-box", action="store_true")
     ap.add_argument("--no-large-k", action="store_true")
+    ap.add_argument("--no-torus", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of 1 GiB (read once, written once), the "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -353,6 +354,33 @@ def main():
                 del r
             ms = float(np.min(reps))
             out["large_k"][str(kk)] = {"ms": ms, "queries_s": LARGE_K_QUERIES / (ms * 1e-3)}
+        tree.close()
+    if not args.no_torus:
+        # Periodic boundaries (the unit box as a 3-torus, a widening of the
+        # path): kNN k = 32 of the 2^22 queries, r = 0.01 counts and FoF
+        # b = 0.2 of the 2^24 points, one traversal per lane, on the step's
+        # tree built again; best of two calls each, outside the timed steps.
+        tree = kdt.build(xt, leaf_size=LEAF)
+        out["torus"] = {"period": 1.0}
+        calls = {"knn": lambda: tree.knn(qt, K, period=1.0),
+                 "range": lambda: tree.range(qt, RADIUS, period=1.0),
+                 "fof": lambda: tree.fof(l_fof, period=1.0)}
+        for name, call in calls.items():
+            r = call()
+            del r
+            torch.cuda.synchronize()
+            reps = []
+            for _ in range(2):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                r = call()
+                e1.record()
+                torch.cuda.synchronize()
+                reps.append(e0.elapsed_time(e1))
+                del r
+            out["torus"][name + "_ms"] = float(min(reps))
+        out["torus"]["knn_queries_s"] = N_QUERIES / (out["torus"]["knn_ms"] * 1e-3)
         tree.close()
     if not args.no_dsweep:
         out["dsweep"] = dimension_sweep(torch, kdt, workloads, dev)
