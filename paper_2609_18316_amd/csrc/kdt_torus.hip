@@ -415,14 +415,61 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   return KDT_OK;
 }
 
-// Friends-of-friends on the torus (Sec. 4.1 with the periodic metric): one
-// lane per point in tree order searches its ball of radius l and links every
-// friend at a later tree position (nodes ending at or before its own are not
-// entered: the other end of each such pair links it), through the same
-// lock-free union-find as the open grouping, whose roots are the smallest
-// input indices.  Both children are pushed: at most levels + 2 entries.
+// Friends-of-friends on the torus (Sec. 4.1 with the periodic metric).
+//
+// A node whose open-space box diagonal is at most l is a clique: every two of
+// its points are friends (the torus distance never exceeds the open one, and
+// the rounded diagonal bounds every rounded pair distance).  First every
+// point joins the first point of the highest clique node above it; then one
+// lane per point in tree order searches its ball of radius l and links
+// friends at later tree positions (nodes ending at or before its own are not
+// entered: the other end of each such pair links it).  Inside a clique node,
+// already one component, one friend suffices: the whole node when it lies in
+// the ball, else the first friend found.  The union-find is the lock-free one
+// of the open grouping, whose roots are the smallest input indices.
+template <int D>
+__global__ void k_torus_clique_mark(const float* __restrict__ box, int64_t n_nodes, float l2,
+                                    uint8_t* __restrict__ clique) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_nodes) return;
+  float lo[D], hi[D];
+  load_box<D>(box, (uint32_t)v, lo, hi);
+  float s = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float g = hi[a] - lo[a];
+    const float g2 = g * g;
+    s = s + g2;
+  }
+  clique[v] = s <= l2 ? 1 : 0;
+}
+
+template <int D>
+__global__ void k_torus_clique_join(TreeView t, const uint8_t* __restrict__ clique,
+                                    int32_t* __restrict__ parent) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t.n) return;
+  int64_t j = 0;
+  for (int lev = 0; lev <= t.levels; ++lev) {
+    const uint32_t node = (uint32_t)(((int64_t(1) << lev) - 1) + j);
+    if (clique[node]) {
+      const int64_t b = node_begin(t.n, lev, j);
+      if (b != i) {
+        constexpr int S = rec_stride(D);
+        const int32_t me = __float_as_int(t.rec[i * S + D]);
+        const int32_t first = __float_as_int(t.rec[b * S + D]);
+        uf_union(parent, me, first);
+      }
+      return;
+    }
+    if (lev < t.levels) j = i >= node_begin(t.n, lev + 1, 2 * j + 1) ? 2 * j + 1 : 2 * j;
+  }
+}
+
+// Both children are pushed: at most levels + 2 stack entries.
 template <int D>
 __global__ __launch_bounds__(kTBlock) void k_torus_fof_link(TreeView t, float l2, Torus<D> T,
+                                                            const uint8_t* __restrict__ clique,
                                                             int32_t* __restrict__ parent) {
   extern __shared__ uint32_t torus_fcol[];
   uint32_t* col = torus_fcol + threadIdx.x;
@@ -444,12 +491,16 @@ __global__ __launch_bounds__(kTBlock) void k_torus_fof_link(TreeView t, float l2
     load_box<D>(t.box, node, lo, hi);
     if (torus_box_mindist<D>(lo, hi, p, T) > l2) continue;
     const bool whole = box_maxdist<D>(lo, hi, p) <= l2;
-    if (whole || node >= first_leaf) {
+    const bool one = clique[node] != 0;  // one component already
+    if (whole || one || node >= first_leaf) {
       for (int64_t i = b > s ? b : s + 1; i < e; ++i) {
         float x[D];
         int32_t id = 0;
         load_rec<D>(t.rec, i, x, id);
-        if (whole || torus_sq_dist<D>(x, p, T) <= l2) uf_union(parent, me, id);
+        if (whole || torus_sq_dist<D>(x, p, T) <= l2) {
+          uf_union(parent, me, id);
+          if (one) break;
+        }
       }
       continue;
     }
@@ -488,10 +539,19 @@ static kdt_status torus_fof_impl(const kdt_tree* tr, float l, const float* perio
   v.levels = tr->levels;
   const int64_t n = tr->n;
   const unsigned g = (unsigned)((n + 255) / 256);
+  uint8_t* clique = nullptr;
+  if (!buf.get(&clique, (size_t)tr->n_nodes)) {
+    kdt_set_error("kdt_fof_torus: device allocation failed");
+    return KDT_ENOMEM;
+  }
+  const float l2 = l * l;
   k_torus_fof_init<<<g, 256, 0, stream>>>(d_labels, n);
+  k_torus_clique_mark<D><<<(unsigned)((tr->n_nodes + 255) / 256), 256, 0, stream>>>(
+      tr->box, tr->n_nodes, l2, clique);
+  k_torus_clique_join<D><<<g, 256, 0, stream>>>(v, clique, d_labels);
   const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;
   k_torus_fof_link<D><<<(unsigned)((n + kTBlock - 1) / kTBlock), kTBlock, smem, stream>>>(
-      v, l * l, T, d_labels);
+      v, l2, T, clique, d_labels);
   k_torus_fof_final<<<g, 256, 0, stream>>>(d_labels, n);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_fof_torus: kernel launch failed");
