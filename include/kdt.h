@@ -93,8 +93,9 @@ typedef struct {
                              float32 like the open distance.  Every tree point
                              and query must lie in [0, L_a) (KDT_EINVAL
                              otherwise; the call waits on its stream to check).
-                             One traversal per lane (traversal and
-                             split_budget are ignored).  kdt_box, and kdt_knn
+                             kNN and lists take one traversal per lane,
+                             ball counts the wave-shared one (leaf_size <=
+                             64); traversal and split_budget are ignored.  kdt_box, and kdt_knn
                              with k > KDT_MAX_K, return KDT_EUNSUPPORTED. */
 } kdt_query_opts;
 

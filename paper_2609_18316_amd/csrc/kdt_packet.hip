@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kdt_packet.h"
+#include "kdt_torus.h"
 
 namespace kdt {
 
@@ -84,6 +85,20 @@ struct BallQueries {
   __device__ __forceinline__ bool load(const TreeView& t, int64_t nq, const int32_t* order,
                                        int64_t s, Shape& sh, int64_t& row) const {
     sh.r2 = r2;
+    return load_query<D>(t, q, nq, order, s, sh.p, row);
+  }
+};
+
+template <int D>
+struct TorusBallQueries {
+  using Shape = TorusBallShape<D>;
+  const float* q;  // [nq][D], or nullptr: the tree's own points
+  float r2;
+  Torus<D> T;
+  __device__ __forceinline__ bool load(const TreeView& t, int64_t nq, const int32_t* order,
+                                       int64_t s, Shape& sh, int64_t& row) const {
+    sh.r2 = r2;
+    sh.T = T;
     return load_query<D>(t, q, nq, order, s, sh.p, row);
   }
 };
@@ -296,6 +311,15 @@ kdt_status box_packet_launch(const TreeView& v, int leaf, const float* d_lo, con
                                 split_budget, stream, "kdt_box");
 }
 
+template <int D>
+kdt_status torus_range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq,
+                                     float r2, const Torus<D>& T, const int32_t* order,
+                                     int32_t* d_count, uint32_t split_budget,
+                                     hipStream_t stream) {
+  return count_packet_launch<D>(v, leaf, TorusBallQueries<D>{d_q, r2, T}, nq, order, d_count,
+                                split_budget, stream, "kdt_range");
+}
+
 #define KDT_INST(D)                                                                                \
   template kdt_status knn_packet_launch<D>(const TreeView&, int, const float*, int64_t, int,       \
                                            int32_t*, float*, int, const int32_t*, hipStream_t);    \
@@ -305,7 +329,10 @@ kdt_status box_packet_launch(const TreeView& v, int leaf, const float* d_lo, con
                                            int64_t, const int32_t*, int32_t*, uint32_t,          \
                                            hipStream_t);                                         \
   template kdt_status fof_packet_launch<D>(const TreeView&, int, float, int32_t*, uint32_t*,       \
-                                           hipStream_t);
+                                           hipStream_t);                                         \
+  template kdt_status torus_range_packet_launch<D>(const TreeView&, int, const float*, int64_t,    \
+                                                   float, const Torus<D>&, const int32_t*,       \
+                                                   int32_t*, uint32_t, hipStream_t);
 KDT_INST(2)
 KDT_INST(3)
 KDT_INST(4)

@@ -8,67 +8,20 @@
 // oracle's definition.  The tree is the ordinary one: a node is skipped when
 // even the shorter way round to its box is too far, and a node counts whole
 // for a ball when its open-space farthest corner is inside (the torus
-// distance never exceeds the open one).  One traversal per lane.  Also
-// friends-of-friends groups on the torus (kdt_fof_torus).
+// distance never exceeds the open one).  kNN and ball lists take one
+// traversal per lane; ball counts the wave-shared count traversal with a
+// torus ball as its query shape (trees with leaves of at most 64 points).
+// Also friends-of-friends groups on the torus (kdt_fof_torus).
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
 
-#include "kdt_query.h"
+#include "kdt_torus.h"
 
 namespace kdt {
 
 constexpr int kTBlock = 128;
-
-template <int D>
-struct Torus {
-  float L[D];
-};
-
-// Squared torus distance: per axis g = |x - p|, the way round L - g, the
-// shorter of the two squared; summed left to right.
-template <int D>
-__device__ __forceinline__ float torus_sq_dist(const float* __restrict__ x, const float p[D],
-                                               const Torus<D>& T) {
-  float s = 0.0f;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const float g = fabsf(x[a] - p[a]);
-    const float w = T.L[a] - g;
-    const float t = w < g ? w : g;
-    const float t2 = t * t;
-    s = s + t2;
-  }
-  return s;
-}
-
-// Lower bound of torus_sq_dist over the points of the box [lo, hi].  Below
-// the box (lo > p) a point's gap lies between lo - p and hi - p, so its way
-// round is at least L - (hi - p); above it, symmetrically.  Every step is a
-// rounded operation that is monotone in the point's coordinate, so the bound
-// never exceeds the rounded distance of any point inside.
-template <int D>
-__device__ __forceinline__ float torus_box_mindist(const float lo[D], const float hi[D],
-                                                   const float p[D], const Torus<D>& T) {
-  float s = 0.0f;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const float below = lo[a] - p[a];
-    const float above = p[a] - hi[a];
-    float t = 0.0f;
-    if (below > 0.0f) {
-      const float w = T.L[a] - (hi[a] - p[a]);
-      t = w < below ? w : below;
-    } else if (above > 0.0f) {
-      const float w = T.L[a] - (p[a] - lo[a]);
-      t = w < above ? w : above;
-    }
-    const float t2 = t * t;
-    s = s + t2;
-  }
-  return s;
-}
 
 // kNN of one query on the torus: depth-first, nearer child first, a node
 // skipped when its bound exceeds the current k-th candidate (ties kept).
@@ -142,7 +95,7 @@ __global__ __launch_bounds__(kTBlock) void k_torus_knn(TreeView t, const float* 
                                                        int32_t* __restrict__ oidx,
                                                        float* __restrict__ od2) {
   extern __shared__ uint32_t torus_stk[];
-  const int64_t s = (int64_t)blockIdx.x * kTBlock + threadIdx.x;
+  const int64_t s = xcd_block<kXcdRunLane>() * kTBlock + threadIdx.x;
   if (s >= nq) return;
   float p[D];
   const int64_t row = torus_query<D>(t, q, order, s, p);
@@ -171,7 +124,7 @@ __global__ __launch_bounds__(kTBlock) void k_torus_range(TreeView t, const float
                                                          int32_t* __restrict__ out) {
   extern __shared__ uint32_t torus_col[];
   uint32_t* col = torus_col + threadIdx.x;
-  const int64_t s = (int64_t)blockIdx.x * kTBlock + threadIdx.x;
+  const int64_t s = xcd_block<kXcdRunLane>() * kTBlock + threadIdx.x;
   if (s >= nq) return;
   float p[D];
   const int64_t row = torus_query<D>(t, q, order, s, p);
@@ -360,8 +313,13 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   const float r2 = r * r;
   const unsigned grid = (unsigned)((nq + kTBlock - 1) / kTBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;
-  k_torus_range<D, false><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, r2, order, T, d_count,
-                                                            nullptr, nullptr);
+  if (tr->leaf <= 64) {
+    st = torus_range_packet_launch<D>(v, tr->leaf, d_q, nq, r2, T, order, d_count, 0u, stream);
+    if (st != KDT_OK) return st;
+  } else {
+    k_torus_range<D, false><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, r2, order, T, d_count,
+                                                              nullptr, nullptr);
+  }
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_range: torus count kernel launch failed");
     return KDT_EDEVICE;
@@ -473,7 +431,7 @@ __global__ __launch_bounds__(kTBlock) void k_torus_fof_link(TreeView t, float l2
                                                             int32_t* __restrict__ parent) {
   extern __shared__ uint32_t torus_fcol[];
   uint32_t* col = torus_fcol + threadIdx.x;
-  const int64_t s = (int64_t)blockIdx.x * kTBlock + threadIdx.x;
+  const int64_t s = xcd_block<kXcdRunFof>() * kTBlock + threadIdx.x;
   if (s >= t.n) return;
   float p[D];
   int32_t me = 0;
