@@ -586,12 +586,29 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const S
 // point.  Elsewhere each pair within l
 // is linked by the point that comes first in tree order: a lane never enters a
 // node that ends at or before its own position, so the search of a ball costs
-// about half.  Leaves must hold at most 64 points.
+// about half.  Leaves must hold at most 64 points.  The metric supplies the
+// point distance and the node bounds (open space by default).
 template <int D>
+struct OpenMetric {
+  __device__ __forceinline__ float dist(const float x[D], const float p[D]) const {
+    return sq_dist<D>(x, p);
+  }
+  __device__ __forceinline__ float mindist(const float lo[D], const float hi[D],
+                                           const float p[D]) const {
+    return box_mindist<D>(lo, hi, p);
+  }
+  __device__ __forceinline__ float maxdist(const float lo[D], const float hi[D],
+                                           const float p[D]) const {
+    return box_maxdist<D>(lo, hi, p);
+  }
+};
+
+template <int D, class Metric = OpenMetric<D>>
 __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], int64_t pos,
                                            int32_t me, bool active, float l2, int32_t base,
                                            int32_t* __restrict__ parent,
-                                           uint32_t* __restrict__ conn, float* lds) {
+                                           uint32_t* __restrict__ conn, float* lds,
+                                           const Metric& metric = Metric()) {
   constexpr int S = rec_stride(D);
   const int lane = lane_id();
   const uint32_t first_leaf = (1u << t.levels) - 1u;
@@ -614,7 +631,7 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
     const bool mine = active && ((live >> lane) & 1ull) && e > pos;
     float lo[D], hi[D];
     load_box_uniform<D>(t.box, node, lo, hi);
-    bool touch = mine && box_mindist<D>(lo, hi, p) <= l2;
+    bool touch = mine && metric.mindist(lo, hi, p) <= l2;
     if (!__any(touch)) continue;
     const int32_t gfirst = base + __float_as_int(t.rec[b * S + D]);
     const bool one = flag_ld(conn + node) != 0;
@@ -624,7 +641,7 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
       touch = !inside && myroot != uf_find(parent, gfirst);
     }
     if (!__any(touch)) continue;
-    const bool full = touch && box_maxdist<D>(lo, hi, p) <= l2;
+    const bool full = touch && metric.maxdist(lo, hi, p) <= l2;
     if (one) {
       if (full) uf_union_from(parent, myroot, gfirst);
     } else {
@@ -658,7 +675,7 @@ __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], 
       for (int i = 0; i < cnt; ++i) {
         float x[D];
         leaf.point(i, x);
-        fr |= (uint64_t)(sq_dist<D>(x, p) <= l2) << i;
+        fr |= (uint64_t)(metric.dist(x, p) <= l2) << i;
       }
       if (!part) fr = 0;
       while (fr) {

@@ -218,6 +218,43 @@ kdt_status fof_packet_launch(const TreeView& v, int leaf, float l2, int32_t* par
 }
 
 template <int D>
+__global__ __launch_bounds__(64 * kPWaves) void k_fof_torus_packet(TreeView t, float l2,
+                                                                   Torus<D> T,
+                                                                   int32_t* __restrict__ parent,
+                                                                   uint32_t* __restrict__ conn,
+                                                                   int leaf_cap) {
+  extern __shared__ __align__(16) float lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t s0 = (xcd_block<kXcdRunFof>() * kPWaves + wave) * 64;
+  if (s0 >= t.n) return;
+  const int64_t pos = s0 + lane;
+  const bool active = pos < t.n;
+  float p[D];
+  int32_t me = 0;
+  if (active) {
+    load_rec<D>(t.rec, pos, p, me);
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) p[a] = 0.0f;
+  }
+  packet_fof<D>(t, p, pos, me, active, l2, 0, parent, conn, wave_slice<D>(lds, wave, leaf_cap),
+                TorusMetric<D>{T});
+}
+
+template <int D>
+kdt_status torus_fof_packet_launch(const TreeView& v, int leaf, float l2, const Torus<D>& T,
+                                   int32_t* parent, uint32_t* conn, hipStream_t stream) {
+  const unsigned grid = (unsigned)((v.n + 64 * kPWaves - 1) / (64 * kPWaves));
+  k_fof_torus_packet<D><<<grid, 64 * kPWaves, packet_lds_bytes<D>(leaf), stream>>>(
+      v, l2, T, parent, conn, leaf);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_fof_torus: packet kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+template <int D>
 kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, int k,
                              int32_t* d_idx, float* d_d2, int mode, const int32_t* order,
                              hipStream_t stream) {
@@ -332,7 +369,9 @@ kdt_status torus_range_packet_launch(const TreeView& v, int leaf, const float* d
                                            hipStream_t);                                         \
   template kdt_status torus_range_packet_launch<D>(const TreeView&, int, const float*, int64_t,    \
                                                    float, const Torus<D>&, const int32_t*,       \
-                                                   int32_t*, uint32_t, hipStream_t);
+                                                   int32_t*, uint32_t, hipStream_t);     \
+  template kdt_status torus_fof_packet_launch<D>(const TreeView&, int, float, const Torus<D>&,     \
+                                                 int32_t*, uint32_t*, hipStream_t);
 KDT_INST(2)
 KDT_INST(3)
 KDT_INST(4)

@@ -90,6 +90,30 @@ struct TorusBallShape {
   }
 };
 
+// The torus metric for the wave-shared grouping: the point distance, its
+// lower bound over a node, and the open farthest corner as the upper bound.
+template <int D>
+struct TorusMetric {
+  Torus<D> T;
+  __device__ __forceinline__ float dist(const float x[D], const float p[D]) const {
+    return torus_sq_dist<D>(x, p, T);
+  }
+  __device__ __forceinline__ float mindist(const float lo[D], const float hi[D],
+                                           const float p[D]) const {
+    return torus_box_mindist<D>(lo, hi, p, T);
+  }
+  __device__ __forceinline__ float maxdist(const float lo[D], const float hi[D],
+                                           const float p[D]) const {
+    return box_maxdist<D>(lo, hi, p);
+  }
+};
+
+// Torus grouping links through the wave-shared grouping traversal
+// (kdt_packet.hip): conn flags nodes whose points are one component already.
+template <int D>
+kdt_status torus_fof_packet_launch(const TreeView& v, int leaf, float l2, const Torus<D>& T,
+                                   int32_t* parent, uint32_t* conn, hipStream_t stream);
+
 // Torus ball counts through the wave-shared count traversal (kdt_packet.hip);
 // arguments as range_packet_launch.
 template <int D>

@@ -384,10 +384,13 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
 // entered: the other end of each such pair links it).  Inside a clique node,
 // already one component, one friend suffices: the whole node when it lies in
 // the ball, else the first friend found.  The union-find is the lock-free one
-// of the open grouping, whose roots are the smallest input indices.
+// of the open grouping, whose roots are the smallest input indices.  Trees
+// with leaves of at most 64 points link through the wave-shared grouping
+// traversal instead (the open grouping's, with the torus metric), which
+// also takes one link per clique node and flags nodes it joined whole.
 template <int D>
 __global__ void k_torus_clique_mark(const float* __restrict__ box, int64_t n_nodes, float l2,
-                                    uint8_t* __restrict__ clique) {
+                                    uint32_t* __restrict__ clique) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n_nodes) return;
   float lo[D], hi[D];
@@ -403,7 +406,7 @@ __global__ void k_torus_clique_mark(const float* __restrict__ box, int64_t n_nod
 }
 
 template <int D>
-__global__ void k_torus_clique_join(TreeView t, const uint8_t* __restrict__ clique,
+__global__ void k_torus_clique_join(TreeView t, const uint32_t* __restrict__ clique,
                                     int32_t* __restrict__ parent) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= t.n) return;
@@ -427,7 +430,7 @@ __global__ void k_torus_clique_join(TreeView t, const uint8_t* __restrict__ cliq
 // Both children are pushed: at most levels + 2 stack entries.
 template <int D>
 __global__ __launch_bounds__(kTBlock) void k_torus_fof_link(TreeView t, float l2, Torus<D> T,
-                                                            const uint8_t* __restrict__ clique,
+                                                            const uint32_t* __restrict__ clique,
                                                             int32_t* __restrict__ parent) {
   extern __shared__ uint32_t torus_fcol[];
   uint32_t* col = torus_fcol + threadIdx.x;
@@ -497,7 +500,7 @@ static kdt_status torus_fof_impl(const kdt_tree* tr, float l, const float* perio
   v.levels = tr->levels;
   const int64_t n = tr->n;
   const unsigned g = (unsigned)((n + 255) / 256);
-  uint8_t* clique = nullptr;
+  uint32_t* clique = nullptr;
   if (!buf.get(&clique, (size_t)tr->n_nodes)) {
     kdt_set_error("kdt_fof_torus: device allocation failed");
     return KDT_ENOMEM;
@@ -507,9 +510,14 @@ static kdt_status torus_fof_impl(const kdt_tree* tr, float l, const float* perio
   k_torus_clique_mark<D><<<(unsigned)((tr->n_nodes + 255) / 256), 256, 0, stream>>>(
       tr->box, tr->n_nodes, l2, clique);
   k_torus_clique_join<D><<<g, 256, 0, stream>>>(v, clique, d_labels);
-  const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;
-  k_torus_fof_link<D><<<(unsigned)((n + kTBlock - 1) / kTBlock), kTBlock, smem, stream>>>(
-      v, l2, T, clique, d_labels);
+  if (tr->leaf <= 64) {
+    st = torus_fof_packet_launch<D>(v, tr->leaf, l2, T, d_labels, clique, stream);
+    if (st != KDT_OK) return st;
+  } else {
+    const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;
+    k_torus_fof_link<D><<<(unsigned)((n + kTBlock - 1) / kTBlock), kTBlock, smem, stream>>>(
+        v, l2, T, clique, d_labels);
+  }
   k_torus_fof_final<<<g, 256, 0, stream>>>(d_labels, n);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_fof_torus: kernel launch failed");
