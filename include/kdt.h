@@ -85,8 +85,8 @@ typedef struct {
                              it exists for tuning and for testing the
                              hand-off.  Negative: KDT_EINVAL. */
     const float *period;  /* NULL: open boundaries.  Else a host array of d
-                             periods L_a (finite, > 0): kdt_knn (k <= KDT_MAX_K)
-                             and kdt_range measure distances on the D-torus
+                             periods L_a (finite, > 0): kdt_knn and kdt_range
+                             measure distances on the D-torus
                              (the periodic boundary conditions of Sec. 2.1 and
                              Sec. 2.4): per axis the shorter way round,
                              min(|x - q|, L - |x - q|), squared and summed in
@@ -95,8 +95,10 @@ typedef struct {
                              otherwise; the call waits on its stream to check).
                              kNN and lists take one traversal per lane,
                              ball counts the wave-shared one (leaf_size <=
-                             64); traversal and split_budget are ignored.  kdt_box, and kdt_knn
-                             with k > KDT_MAX_K, return KDT_EUNSUPPORTED. */
+                             64), k > KDT_MAX_K the ball-and-sort path
+                             with the torus distance; traversal and
+                             split_budget are ignored.  kdt_box returns
+                             KDT_EUNSUPPORTED. */
 } kdt_query_opts;
 
 /* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side

@@ -8,7 +8,9 @@
 //   3. a segmented sort of the keys: the first k of each row are the answer,
 //      since every point outside the ball is farther than the k-th key.
 // Keys are (d2 bits << 32 | index) with the same float32 distances as the
-// register path, so results are identical to it wherever both apply.  Queries
+// register path, so results are identical to it wherever both apply.  The
+// kernels take the metric as a parameter: open space, or the D-torus of
+// periodic boundaries (the node bound and the point distance change).  Queries
 // are processed in chunks whose keys fit a bounded buffer.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
@@ -16,7 +18,8 @@
 #include <cmath>
 #include <vector>
 
-#include "kdt_query.h"
+#include "kdt_packet.h"
+#include "kdt_torus.h"
 
 namespace kdt {
 
@@ -73,11 +76,11 @@ __global__ void k_start_radius(float* __restrict__ r2, int64_t nq, float scale, 
 // squared radius r2[s] around it.  A node inside the ball counts whole, a
 // leaf that straddles it tests its points.  With `only_marked`, rows whose
 // count is not negative (not grown since they were counted) are skipped.
-template <int D>
+template <int D, class M>
 __global__ __launch_bounds__(kLBlock) void k_ball_count(TreeView t, const float* __restrict__ q,
                                                         int64_t nq, const float* __restrict__ r2v,
                                                         int32_t* __restrict__ count,
-                                                        int only_marked) {
+                                                        int only_marked, M metric) {
   extern __shared__ uint32_t var_stk[];
   uint32_t* col = var_stk + threadIdx.x;
   const int64_t s = (int64_t)blockIdx.x * kLBlock + threadIdx.x;
@@ -94,11 +97,11 @@ __global__ __launch_bounds__(kLBlock) void k_ball_count(TreeView t, const float*
     const uint32_t node = col[kLBlock * --sp];
     float lo[D], hi[D];
     load_box<D>(t.box, node, lo, hi);
-    if (box_mindist<D>(lo, hi, p) > r2) continue;
+    if (metric.mindist(lo, hi, p) > r2) continue;
     const int lev = node_level(node);
     const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
     const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
-    if (box_maxdist<D>(lo, hi, p) <= r2) {
+    if (metric.maxdist(lo, hi, p) <= r2) {
       c += e - b;
       continue;
     }
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(kLBlock) void k_ball_count(TreeView t, const float*
         float x[D];
         int32_t id = 0;
         load_rec<D>(t.rec, i, x, id);
-        c += sq_dist<D>(x, p) <= r2;
+        c += metric.dist(x, p) <= r2;
       }
       continue;
     }
@@ -123,11 +126,11 @@ __global__ __launch_bounds__(kLBlock) void k_ball_count(TreeView t, const float*
 // point append its key at their rank in the wave's ballot.  The node tests
 // are those of k_ball_count, so exactly count[s] keys are written.
 constexpr int kFillWaves = 4;
-template <int D>
+template <int D, class M>
 __global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
     TreeView t, const float* __restrict__ q, int64_t s0, int64_t s1,
     const float* __restrict__ r2v, const int64_t* __restrict__ offsets, int64_t base,
-    uint64_t* __restrict__ keys, int stack_len) {
+    uint64_t* __restrict__ keys, int stack_len, M metric) {
   extern __shared__ uint32_t fill_stk[];
   const int lane = threadIdx.x & 63;
   uint32_t* stk = fill_stk + (threadIdx.x >> 6) * stack_len;
@@ -147,11 +150,11 @@ __global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
     const uint32_t node = stk[--sp];
     float lo[D], hi[D];
     load_box<D>(t.box, node, lo, hi);
-    if (box_mindist<D>(lo, hi, p) > r2) continue;
+    if (metric.mindist(lo, hi, p) > r2) continue;
     const int lev = node_level(node);
     const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
     const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
-    const bool whole = box_maxdist<D>(lo, hi, p) <= r2;
+    const bool whole = metric.maxdist(lo, hi, p) <= r2;
     if (whole || node >= first_leaf) {
       for (int64_t c = b; c < e; c += 64) {
         const int64_t i = c + lane;
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
           float x[D];
           int32_t id = 0;
           load_rec<D>(t.rec, i, x, id);
-          const float d2 = sq_dist<D>(x, p);
+          const float d2 = metric.dist(x, p);
           in = whole || d2 <= r2;
           key = make_key(d2, id);
         }
@@ -233,10 +236,11 @@ __global__ void k_take_first(const uint64_t* __restrict__ keys, const int32_t* _
   }
 }
 
-template <int D>
+template <int D, class M>
 static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t nq, int k,
                                  int32_t* d_idx, float* d_d2, int mode, bool sort_q,
-                                 const int32_t* given, hipStream_t stream) {
+                                 const int32_t* given, const M& metric, const float* period,
+                                 hipStream_t stream) {
   TreeView v;
   v.rec = tr->rec;
   v.box = tr->box;
@@ -282,6 +286,7 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
   // 1. start from the 64th neighbour (the register path), scaled to hold k
   kdt_query_opts in_order{};
   in_order.sort_queries = 0;
+  in_order.period = period;  // the torus kNN also checks the period
   kdt_status st = kdt_knn(tr, q, nq, KDT_MAX_K, nullptr, r2, 1, &in_order, stream);
   if (st != KDT_OK) return st;
   const float scale = kBigMargin * std::pow((float)k / (float)KDT_MAX_K, 2.0f / (float)D);
@@ -303,7 +308,8 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
   const size_t smem = sizeof(uint32_t) * (size_t)stack_len * kLBlock;
   const unsigned gl = (unsigned)((nq + kLBlock - 1) / kLBlock);
   for (int round = 0; round < kBigGrowRounds; ++round) {
-    k_ball_count<D><<<gl, kLBlock, smem, stream>>>(v, q, nq, r2, count, round > 0 ? 1 : 0);
+    k_ball_count<D><<<gl, kLBlock, smem, stream>>>(v, q, nq, r2, count, round > 0 ? 1 : 0,
+                                                   metric);
     k_grow_radius<<<gq, 256, 0, stream>>>(r2, count, prev, stuck, nq, k, 2.0f / (float)D, floor,
                                           round + 2 >= kBigGrowRounds ? 1 : 0, again + round);
     int32_t h_again = 0;
@@ -363,7 +369,7 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
     if (total > 0) {
       k_ball_fill<D><<<(unsigned)((m + kFillWaves - 1) / kFillWaves), 64 * kFillWaves,
                        sizeof(uint32_t) * (size_t)stack_len * kFillWaves, stream>>>(
-          v, q, s0, s1, r2, off, h_off[s0], keys, stack_len);
+          v, q, s0, s1, r2, off, h_off[s0], keys, stack_len, metric);
       size_t sb = 0;
       if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, keys, sorted, (int)total, (int)m,
                                                 rel, rel + 1, stream) != hipSuccess) {
@@ -395,19 +401,32 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
   return KDT_OK;
 }
 
+template <int D>
+static kdt_status knn_large_metric(const kdt_tree* tr, const float* d_q, int64_t nq, int k,
+                                   int32_t* d_idx, float* d_d2, int mode, bool sort_q,
+                                   const int32_t* given, const float* period,
+                                   hipStream_t stream) {
+  if (!period)
+    return knn_large_impl<D>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, OpenMetric<D>{},
+                             nullptr, stream);
+  TorusMetric<D> m;
+  for (int a = 0; a < D; ++a) m.T.L[a] = period[a];
+  return knn_large_impl<D>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, m, period, stream);
+}
+
 kdt_status knn_large(const kdt_tree* tr, const float* d_q, int64_t nq, int k, int32_t* d_idx,
                      float* d_d2, int mode, bool sort_q, const int32_t* given,
-                     hipStream_t stream) {
+                     const float* period, hipStream_t stream) {
   if (nq > INT32_MAX) {
     kdt_set_error("kdt_knn: k above %d supports at most 2^31-1 queries", KDT_MAX_K);
     return KDT_EUNSUPPORTED;
   }
   switch (tr->d) {
-    case 2: return knn_large_impl<2>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
-    case 3: return knn_large_impl<3>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
-    case 4: return knn_large_impl<4>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
-    case 8: return knn_large_impl<8>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
-    case 16: return knn_large_impl<16>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, stream);
+    case 2: return knn_large_metric<2>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+    case 3: return knn_large_metric<3>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+    case 4: return knn_large_metric<4>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+    case 8: return knn_large_metric<8>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
+    case 16: return knn_large_metric<16>(tr, d_q, nq, k, d_idx, d_d2, mode, sort_q, given, period, stream);
   }
   kdt_set_error("kdt_knn: unsupported dimension %d", tr->d);
   return KDT_EUNSUPPORTED;

@@ -547,10 +547,11 @@ kdt_status range_torus(const kdt_tree* tr, const float* d_q, int64_t nq, float r
                        hipStream_t stream);
 
 // k above KDT_MAX_K: exact neighbours from a per-query ball that holds at
-// least k points, its keys sorted per query (arguments as kdt_knn).
+// least k points, its keys sorted per query (arguments as kdt_knn; period
+// NULL for open boundaries).
 kdt_status knn_large(const kdt_tree* tr, const float* d_q, int64_t nq, int k, int32_t* d_idx,
                      float* d_d2, int mode, bool sort_q, const int32_t* given,
-                     hipStream_t stream);
+                     const float* period, hipStream_t stream);
 
 template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,

@@ -491,16 +491,11 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
     kdt_set_error("kdt_knn: traversal must be 0, 1 or 2");
     return KDT_EINVAL;
   }
-  if (opts && opts->period) {
-    if (k > KDT_MAX_K) {
-      kdt_set_error("kdt_knn: k above %d is not supported with periodic boundaries", KDT_MAX_K);
-      return KDT_EUNSUPPORTED;
-    }
-    return knn_torus(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, given, opts->period,
-                     stream);
-  }
+  const float* period = opts ? opts->period : nullptr;
   if (k > KDT_MAX_K)
-    return knn_large(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, given, stream);
+    return knn_large(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, given, period, stream);
+  if (period)
+    return knn_torus(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, given, period, stream);
   switch (tree->d) {
     case 2: return knn_impl<2>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);
     case 3: return knn_impl<3>(tree, d_q, nq, k, d_idx, d_d2, kth_only, sort_q, trav, given, stream);

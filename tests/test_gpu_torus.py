@@ -107,6 +107,32 @@ def test_torus_fof_clustered_joins_across_faces():
         assert ng <= t.fof(l, count_groups=True)[1]
 
 
+@pytest.mark.parametrize("d", kdt.DIMS)
+@pytest.mark.parametrize("kind", ("uniform", "lattice", "normal"))
+def test_torus_large_k_equals_brute_force(kind, d):
+    """k above the register lists on the torus (the ball-and-sort path with
+    the torus distance), all modes, self and external queries."""
+    dev()
+    L = _periods(d)
+    for n in (70, 2500):
+        x = wrap(cases.points(kind, n, d, seed=11 * n + d) * 1.7 - 0.3, L)
+        q = wrap(cases.points(kind, 150, d, seed=13 * n + d) * 1.7 - 0.3, L)
+        t = kdt.build(to_dev(x), leaf_size=16)
+        for k in sorted({65, 300, n + 3}):
+            say(f"torus large k d={d} kind={kind} n={n} k={k}")
+            oi, od = oracle.knn_brute(x, q, k, period=L)
+            gi, gd = t.knn(to_dev(q), k, period=L)
+            np.testing.assert_array_equal(to_host(gi), oi)
+            np.testing.assert_array_equal(to_host(gd), od)
+            np.testing.assert_array_equal(to_host(t.knn(to_dev(q), k, kth_only=2, period=L)),
+                                          np.sqrt(od[:, -1]))
+            rows = np.arange(0, n, max(1, n // 150))
+            oi, od = oracle.knn_brute(x, x[rows], k, period=L)
+            si, sd = t.knn(None, k, period=L)
+            np.testing.assert_array_equal(to_host(si)[rows], oi)
+            np.testing.assert_array_equal(to_host(sd)[rows], od)
+
+
 def test_torus_clustered_orders_and_lattice_ties():
     """Clustered catalogue points across the faces of the unit box, reused and
     unsorted query orders; a coarse lattice where most distances tie."""
@@ -177,8 +203,11 @@ def test_torus_errors():
         t.range(to_dev(qo), 0.1, period=1.0)
     assert e.value.status == kdt.KDT_EINVAL
     with pytest.raises(kdt.KdtError) as e:
-        t.knn(to_dev(q), kdt.MAX_K + 1, period=1.0)
+        t.knn(to_dev(q), kdt.MAX_K_SORTED + 1, kth_only=1, period=1.0)
     assert e.value.status == kdt.KDT_EUNSUPPORTED
+    with pytest.raises(kdt.KdtError) as e:
+        t.knn(to_dev(qo), kdt.MAX_K + 1, period=1.0)
+    assert e.value.status == kdt.KDT_EINVAL
     with pytest.raises(kdt.KdtError) as e:
         opts_lo = torch.zeros((2, 3), dtype=torch.float32, device="cuda")
         opts = kdt.QueryOpts(1, 0, None, 0, kdt._periods(1.0, 3))
