@@ -587,22 +587,7 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const S
 // is linked by the point that comes first in tree order: a lane never enters a
 // node that ends at or before its own position, so the search of a ball costs
 // about half.  Leaves must hold at most 64 points.  The metric supplies the
-// point distance and the node bounds (open space by default).
-template <int D>
-struct OpenMetric {
-  __device__ __forceinline__ float dist(const float x[D], const float p[D]) const {
-    return sq_dist<D>(x, p);
-  }
-  __device__ __forceinline__ float mindist(const float lo[D], const float hi[D],
-                                           const float p[D]) const {
-    return box_mindist<D>(lo, hi, p);
-  }
-  __device__ __forceinline__ float maxdist(const float lo[D], const float hi[D],
-                                           const float p[D]) const {
-    return box_maxdist<D>(lo, hi, p);
-  }
-};
-
+// point distance and the node bounds (OpenMetric by default).
 template <int D, class Metric = OpenMetric<D>>
 __device__ __forceinline__ void packet_fof(const TreeView& t, const float p[D], int64_t pos,
                                            int32_t me, bool active, float l2, int32_t base,

@@ -216,13 +216,31 @@ struct TopD {
   }
 };
 
+// Open-space metric of the traversals: the point distance (Eq. 1, p = 2) and
+// the lower and upper bounds over a node box.  Other metrics (the D-torus of
+// periodic boundaries) supply the same three.
+template <int D>
+struct OpenMetric {
+  __device__ __forceinline__ float dist(const float x[D], const float p[D]) const {
+    return sq_dist<D>(x, p);
+  }
+  __device__ __forceinline__ float mindist(const float lo[D], const float hi[D],
+                                           const float p[D]) const {
+    return box_mindist<D>(lo, hi, p);
+  }
+  __device__ __forceinline__ float maxdist(const float lo[D], const float hi[D],
+                                           const float p[D]) const {
+    return box_maxdist<D>(lo, hi, p);
+  }
+};
+
 // kNN of one query p over tree t (Algorithm 2 semantics): depth-first, nearer
 // child first, a node is skipped when its box is farther than the current
 // k-th candidate.  `stk` is this lane's column of an LDS stack with stride
 // `ld` entries.
-template <int D, class List>
+template <int D, class List, class Metric = OpenMetric<D>>
 __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], List& best,
-                                        uint32_t* stk, int ld) {
+                                        uint32_t* stk, int ld, const Metric& metric = Metric()) {
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   // leaf sizes: floor(n / 2^L) or one more
   const int lmin = (int)(t.n >> t.levels);
@@ -230,7 +248,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
   float lo[D], hi[D];
   load_box<D>(t.box, 0, lo, hi);
   uint32_t node = 0;
-  float nd = box_mindist<D>(lo, hi, p);
+  float nd = metric.mindist(lo, hi, p);
   int sp = 0;
   for (;;) {
     if (nd <= best.worst_d2()) {
@@ -258,13 +276,13 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
               float x[D];
               int32_t id = 0;
               load_rec<D>(t.rec, b + i, x, id);
-              m32 |= (uint32_t)(sq_dist<D>(x, p) <= w) << i;
+              m32 |= (uint32_t)(metric.dist(x, p) <= w) << i;
             }
             if (e - b > lmin) {
               float x[D];
               int32_t id = 0;
               load_rec<D>(t.rec, b + lmin, x, id);
-              m32 |= (uint32_t)(sq_dist<D>(x, p) <= w) << lmin;
+              m32 |= (uint32_t)(metric.dist(x, p) <= w) << lmin;
             }
             mask = m32;
           } else {
@@ -273,7 +291,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
               float x[D];
               int32_t id = 0;
               load_rec<D>(t.rec, c + i, x, id);
-              if (sq_dist<D>(x, p) <= w) mask |= 1ull << i;
+              if (metric.dist(x, p) <= w) mask |= 1ull << i;
             }
           }
           while (mask) {
@@ -282,15 +300,15 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
             float x[D];
             int32_t id = 0;
             load_rec<D>(t.rec, c + i, x, id);
-            best.offer(sq_dist<D>(x, p), id);
+            best.offer(metric.dist(x, p), id);
           }
         }
       } else {
         const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
         load_box<D>(t.box, c0, lo, hi);
-        const float d0 = box_mindist<D>(lo, hi, p);
+        const float d0 = metric.mindist(lo, hi, p);
         load_box<D>(t.box, c1, lo, hi);
-        const float d1 = box_mindist<D>(lo, hi, p);
+        const float d1 = metric.mindist(lo, hi, p);
         const bool first0 = d0 <= d1;
         const uint32_t nn = first0 ? c0 : c1, ff = first0 ? c1 : c0;
         const float dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
@@ -305,7 +323,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
     // (the box is cache-resident), halving the stack's LDS footprint
     node = stk[--sp * ld];
     load_box<D>(t.box, node, lo, hi);
-    nd = box_mindist<D>(lo, hi, p);
+    nd = metric.mindist(lo, hi, p);
   }
 }
 

@@ -23,53 +23,6 @@ namespace kdt {
 
 constexpr int kTBlock = 128;
 
-// kNN of one query on the torus: depth-first, nearer child first, a node
-// skipped when its bound exceeds the current k-th candidate (ties kept).
-// `stk` is this lane's column of an LDS stack with stride `ld`.
-template <int D, class List>
-__device__ __forceinline__ void torus_knn_one(const TreeView& t, const float p[D],
-                                              const Torus<D>& T, List& best, uint32_t* stk,
-                                              int ld) {
-  const uint32_t first_leaf = (1u << t.levels) - 1u;
-  float lo[D], hi[D];
-  load_box<D>(t.box, 0, lo, hi);
-  uint32_t node = 0;
-  float nd = torus_box_mindist<D>(lo, hi, p, T);
-  int sp = 0;
-  for (;;) {
-    if (nd <= best.worst_d2()) {
-      if (node >= first_leaf) {
-        const int64_t j = node - first_leaf;
-        const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
-        for (int64_t i = b; i < e; ++i) {
-          float x[D];
-          int32_t id = 0;
-          load_rec<D>(t.rec, i, x, id);
-          const float d2 = torus_sq_dist<D>(x, p, T);
-          if (d2 <= best.worst_d2()) best.offer(d2, id);
-        }
-      } else {
-        const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
-        load_box<D>(t.box, c0, lo, hi);
-        const float d0 = torus_box_mindist<D>(lo, hi, p, T);
-        load_box<D>(t.box, c1, lo, hi);
-        const float d1 = torus_box_mindist<D>(lo, hi, p, T);
-        const bool first0 = d0 <= d1;
-        const uint32_t nn = first0 ? c0 : c1, ff = first0 ? c1 : c0;
-        const float dn = first0 ? d0 : d1, df = first0 ? d1 : d0;
-        if (df <= best.worst_d2()) stk[sp++ * ld] = ff;
-        node = nn;
-        nd = dn;
-        continue;
-      }
-    }
-    if (sp == 0) break;
-    node = stk[--sp * ld];
-    load_box<D>(t.box, node, lo, hi);
-    nd = torus_box_mindist<D>(lo, hi, p, T);
-  }
-}
-
 // One query per lane: the tree's own points (q == NULL, row = input index)
 // or q[order[s]] (q[s] without an order).
 template <int D>
@@ -102,12 +55,12 @@ __global__ __launch_bounds__(kTBlock) void k_torus_knn(TreeView t, const float* 
   if constexpr (KTH) {
     TopD<KC> best;
     best.init(k);
-    torus_knn_one<D>(t, p, T, best, torus_stk + threadIdx.x, kTBlock);
+    knn_one<D>(t, p, best, torus_stk + threadIdx.x, kTBlock, TorusMetric<D>{T});
     knn_write_kth<KC>(best, mode, row, od2);
   } else {
     TopK<KC> best;
     best.init(k);
-    torus_knn_one<D>(t, p, T, best, torus_stk + threadIdx.x, kTBlock);
+    knn_one<D>(t, p, best, torus_stk + threadIdx.x, kTBlock, TorusMetric<D>{T});
     knn_write<KC>(best, k, mode, row, oidx, od2);
   }
 }
