@@ -52,8 +52,8 @@ BATCH_SETS = 256
 KNN_COUNTERS = {
     "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
                 "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
-    "sha256": "64a60593f33a1813c331e57257d10d29ee3292f2fc1157d9195ed538798a015d",
-    "hbm_bytes": 2.1453e+09,
+    "sha256": "685ecaf95849e47d71f9767899391295a182fde66289de689586d34028cbf7a2",
+    "hbm_bytes": 2.1450e+09,
     "l2_hit_rate": 0.964,
     "valu_issue_frac": 0.71,
 }
