@@ -7,11 +7,12 @@
 //   2. the (d2, index) keys of every point in that ball, one wave per query;
 //   3. a segmented sort of the keys: the first k of each row are the answer,
 //      since every point outside the ball is farther than the k-th key.
-// Keys are (d2 bits << 32 | index) with the same float32 distances as the
-// register path, so results are identical to it wherever both apply.  The
+// Keys are (d2 bits << b | index), b the bits of the largest index, with the
+// same float32 distances as the register path, so results are identical to
+// it wherever both apply; the radix sort passes over 32 + b bits only.  The
 // kernels take the metric as a parameter: open space, or the D-torus of
-// periodic boundaries (the node bound and the point distance change).  Queries
-// are processed in chunks whose keys fit a bounded buffer.
+// periodic boundaries (the node bound and the point distance change).
+// Queries are processed in chunks whose keys fit a bounded buffer.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -130,7 +131,7 @@ template <int D, class M>
 __global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
     TreeView t, const float* __restrict__ q, int64_t s0, int64_t s1,
     const float* __restrict__ r2v, const int64_t* __restrict__ offsets, int64_t base,
-    uint64_t* __restrict__ keys, int stack_len, M metric) {
+    uint64_t* __restrict__ keys, int stack_len, int ib, M metric) {
   extern __shared__ uint32_t fill_stk[];
   const int lane = threadIdx.x & 63;
   uint32_t* stk = fill_stk + (threadIdx.x >> 6) * stack_len;
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
           load_rec<D>(t.rec, i, x, id);
           const float d2 = metric.dist(x, p);
           in = whole || d2 <= r2;
-          key = make_key(d2, id);
+          key = ((uint64_t)__float_as_uint(d2) << ib) | (uint32_t)id;
         }
         const uint64_t m = __ballot(in);
         if (in) keys[pos + __popcll(m & below)] = key;
@@ -217,7 +218,8 @@ __global__ void k_chunk_offsets(const int64_t* __restrict__ off, int64_t s0, int
 // the k-th d2 / distance.  Rows with fewer than k keys are padded (-1, +inf).
 __global__ void k_take_first(const uint64_t* __restrict__ keys, const int32_t* __restrict__ rel,
                              const int32_t* __restrict__ rowof, int64_t s0, int64_t m, int k,
-                             int mode, int32_t* __restrict__ oidx, float* __restrict__ od2) {
+                             int mode, int ib, int32_t* __restrict__ oidx,
+                             float* __restrict__ od2) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = mode == 0 ? k : 1;
   if (t >= m * per) return;
@@ -227,9 +229,9 @@ __global__ void k_take_first(const uint64_t* __restrict__ keys, const int32_t* _
   const int64_t row = rowof ? (int64_t)rowof[s0 + i] : s0 + i;
   const bool empty = j >= have;
   const uint64_t key = empty ? 0ull : keys[rel[i] + j];
-  const float d2 = empty ? INFINITY : __uint_as_float((uint32_t)(key >> 32));
+  const float d2 = empty ? INFINITY : __uint_as_float((uint32_t)(key >> ib));
   if (mode == 0) {
-    if (oidx) oidx[row * k + j] = empty ? -1 : (int32_t)(uint32_t)key;
+    if (oidx) oidx[row * k + j] = empty ? -1 : (int32_t)(key & ((1ull << ib) - 1ull));
     od2[row * k + j] = d2;
   } else {
     od2[row] = mode == 2 ? sqrtf(d2) : d2;
@@ -358,7 +360,11 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
     kdt_set_error("kdt_knn: device allocation failed for the large-k keys");
     return KDT_ENOMEM;
   }
-  // 3. per chunk: keys, segmented sort, first k
+  // 3. per chunk: keys, segmented sort, first k.  A key is (d2 bits << ib |
+  // index) with ib = the bits of the largest index, so the radix sort
+  // passes over 32 + ib bits only.
+  int ib = 1;
+  while (ib < 31 && (int64_t(1) << ib) < tr->n) ++ib;
   void* stmp = nullptr;
   size_t stmp_bytes = 0;
   for (int64_t s0 = 0; s0 < nq;) {
@@ -369,10 +375,11 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
     if (total > 0) {
       k_ball_fill<D><<<(unsigned)((m + kFillWaves - 1) / kFillWaves), 64 * kFillWaves,
                        sizeof(uint32_t) * (size_t)stack_len * kFillWaves, stream>>>(
-          v, q, s0, s1, r2, off, h_off[s0], keys, stack_len, metric);
+          v, q, s0, s1, r2, off, h_off[s0], keys, stack_len, ib, metric);
       size_t sb = 0;
-      if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, keys, sorted, (int)total, (int)m,
-                                                rel, rel + 1, stream) != hipSuccess) {
+      if (hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, sb, keys, sorted, (int)total, (int)m,
+                                                     rel, rel + 1, 0, 32 + ib, stream) !=
+          hipSuccess) {
         kdt_set_error("kdt_knn: large-k sort setup failed");
         return KDT_EDEVICE;
       }
@@ -383,15 +390,16 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
         }
         stmp_bytes = sb;
       }
-      if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, keys, sorted, (int)total, (int)m, rel,
-                                                rel + 1, stream) != hipSuccess) {
+      if (hipcub::DeviceSegmentedRadixSort::SortKeys(stmp, sb, keys, sorted, (int)total, (int)m,
+                                                     rel, rel + 1, 0, 32 + ib, stream) !=
+          hipSuccess) {
         kdt_set_error("kdt_knn: large-k sort failed");
         return KDT_EDEVICE;
       }
     }
     const int64_t outs = m * (mode == 0 ? k : 1);
     k_take_first<<<(unsigned)((outs + 255) / 256), 256, 0, stream>>>(sorted, rel, rowof, s0, m,
-                                                                   k, mode, d_idx, d_d2);
+                                                                   k, mode, ib, d_idx, d_d2);
     s0 = s1;
   }
   if (hipGetLastError() != hipSuccess) {
