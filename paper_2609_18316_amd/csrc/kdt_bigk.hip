@@ -183,14 +183,15 @@ __global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
 // Rows whose ball holds fewer than k points get a larger radius, from the
 // density the count shows: r2 x kBigMargin (k / count)^(2/d), at least
 // x kBigGrowMin (a zero radius restarts from `floor`); the row is marked for
-// recounting.  A row whose count grew by less than an eighth since its last
+// recounting (its index appended to `list`, their number in again[0]).  A
+// row whose count grew by less than an eighth since its last
 // round is stuck (its ball is crossing empty space, e.g. around a small
 // isolated clump): each time, its least growth is multiplied by four, up to
 // kBigGrowCap.  In the last round the radius becomes infinite.
 __global__ void k_grow_radius(float* __restrict__ r2, int32_t* __restrict__ count,
                               int32_t* __restrict__ prev, int32_t* __restrict__ stuck, int64_t nq,
                               int k, float two_over_d, float floor, int last,
-                              int32_t* __restrict__ again) {
+                              int32_t* __restrict__ again, int32_t* __restrict__ list) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq || count[i] >= k || isinf(r2[i])) return;
   const int c = count[i], p = prev[i];
@@ -201,7 +202,7 @@ __global__ void k_grow_radius(float* __restrict__ r2, int32_t* __restrict__ coun
   const float f = c > 0 ? fmaxf(least, kBigMargin * powf((float)k / (float)c, two_over_d)) : least;
   r2[i] = last ? INFINITY : (r2[i] > 0.0f ? r2[i] * f : floor);
   count[i] = -1;
-  again[0] = 1;
+  list[atomicAdd(again, 1)] = (int32_t)i;
 }
 
 struct BigI64 {
@@ -309,12 +310,28 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
   const int stack_len = tr->levels + 2;
   const size_t smem = sizeof(uint32_t) * (size_t)stack_len * kLBlock;
   const unsigned gl = (unsigned)((nq + kLBlock - 1) / kLBlock);
+  // Counts: the wave-shared count traversal (leaves of at most 64 points)
+  // over every query first, then over the list of grown rows; else one
+  // traversal per lane, skipping rows that did not grow.
+  int32_t* list = nullptr;
+  if (!buf.get(&list, (size_t)nq)) {
+    kdt_set_error("kdt_knn: device allocation failed for the large-k row list");
+    return KDT_ENOMEM;
+  }
+  int32_t h_again = (int32_t)nq;
   for (int round = 0; round < kBigGrowRounds; ++round) {
-    k_ball_count<D><<<gl, kLBlock, smem, stream>>>(v, q, nq, r2, count, round > 0 ? 1 : 0,
-                                                   metric);
+    if (tr->leaf <= 64) {
+      st = var_ball_count_launch<D>(v, tr->leaf, q, r2, round == 0 ? nq : (int64_t)h_again,
+                                    round == 0 ? nullptr : list, metric, count, stream);
+      if (st != KDT_OK) return st;
+    } else {
+      k_ball_count<D><<<gl, kLBlock, smem, stream>>>(v, q, nq, r2, count, round > 0 ? 1 : 0,
+                                                     metric);
+    }
     k_grow_radius<<<gq, 256, 0, stream>>>(r2, count, prev, stuck, nq, k, 2.0f / (float)D, floor,
-                                          round + 2 >= kBigGrowRounds ? 1 : 0, again + round);
-    int32_t h_again = 0;
+                                          round + 2 >= kBigGrowRounds ? 1 : 0, again + round,
+                                          list);
+    h_again = 0;
     if (hipMemcpyAsync(&h_again, again + round, sizeof(int32_t), hipMemcpyDeviceToHost,
                        stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {

@@ -418,6 +418,45 @@ struct BallShape {
   }
 };
 
+// A closed ball with its own squared radius (packed with the centre), under
+// a metric (open space or the D-torus): the per-query balls of kNN with k
+// above the register lists.
+template <int D, class Metric>
+struct VarBallShape {
+  static constexpr int kFloats = D + 1;
+  float p[D];
+  float r2;
+  Metric m;
+  __device__ __forceinline__ bool cuts(const float lo[D], const float hi[D]) const {
+    return m.mindist(lo, hi, p) <= r2;
+  }
+  __device__ __forceinline__ bool holds_box(const float lo[D], const float hi[D]) const {
+    return m.maxdist(lo, hi, p) <= r2;
+  }
+  __device__ __forceinline__ bool holds(const float x[D]) const { return m.dist(x, p) <= r2; }
+  __device__ __forceinline__ void pack(float* dst) const {
+#pragma unroll
+    for (int a = 0; a < D; ++a) dst[a] = p[a];
+    dst[D] = r2;
+  }
+  __device__ __forceinline__ VarBallShape unpack(const float* src) const {
+    VarBallShape b;
+#pragma unroll
+    for (int a = 0; a < D; ++a) b.p[a] = src[a];
+    b.r2 = src[D];
+    b.m = m;
+    return b;
+  }
+};
+
+// Counts of per-query balls (centres q[row], squared radii r2v[row]) through
+// the wave-shared count traversal, rows order[s] (or s) for s < nq
+// (kdt_packet.hip; Metric is OpenMetric<D> or TorusMetric<D>).
+template <int D, class Metric>
+kdt_status var_ball_count_launch(const TreeView& v, int leaf, const float* d_q, const float* d_r2,
+                                 int64_t nq, const int32_t* order, const Metric& m,
+                                 int32_t* d_count, hipStream_t stream);
+
 // A closed axis-aligned box [lo, hi] (the rectangular ranges of Sec. 2.3).
 template <int D>
 struct BoxShape {

@@ -103,6 +103,21 @@ struct TorusBallQueries {
   }
 };
 
+template <int D, class Metric>
+struct VarBallQueries {
+  using Shape = VarBallShape<D, Metric>;
+  const float* q;   // [rows][D]
+  const float* r2;  // [rows]
+  Metric m;
+  __device__ __forceinline__ bool load(const TreeView& t, int64_t nq, const int32_t* order,
+                                       int64_t s, Shape& sh, int64_t& row) const {
+    sh.m = m;
+    const bool ok = load_query<D>(t, q, nq, order, s, sh.p, row);
+    sh.r2 = ok ? r2[row] : 0.0f;
+    return ok;
+  }
+};
+
 template <int D>
 struct BoxQueries {
   using Shape = BoxShape<D>;
@@ -357,6 +372,14 @@ kdt_status torus_range_packet_launch(const TreeView& v, int leaf, const float* d
                                 split_budget, stream, "kdt_range");
 }
 
+template <int D, class Metric>
+kdt_status var_ball_count_launch(const TreeView& v, int leaf, const float* d_q, const float* d_r2,
+                                 int64_t nq, const int32_t* order, const Metric& m,
+                                 int32_t* d_count, hipStream_t stream) {
+  return count_packet_launch<D>(v, leaf, VarBallQueries<D, Metric>{d_q, d_r2, m}, nq, order,
+                                d_count, 0u, stream, "kdt_knn");
+}
+
 #define KDT_INST(D)                                                                                \
   template kdt_status knn_packet_launch<D>(const TreeView&, int, const float*, int64_t, int,       \
                                            int32_t*, float*, int, const int32_t*, hipStream_t);    \
@@ -371,7 +394,13 @@ kdt_status torus_range_packet_launch(const TreeView& v, int leaf, const float* d
                                                    float, const Torus<D>&, const int32_t*,       \
                                                    int32_t*, uint32_t, hipStream_t);     \
   template kdt_status torus_fof_packet_launch<D>(const TreeView&, int, float, const Torus<D>&,     \
-                                                 int32_t*, uint32_t*, hipStream_t);
+                                                 int32_t*, uint32_t*, hipStream_t);              \
+  template kdt_status var_ball_count_launch<D, OpenMetric<D>>(                                     \
+      const TreeView&, int, const float*, const float*, int64_t, const int32_t*,                  \
+      const OpenMetric<D>&, int32_t*, hipStream_t);                                               \
+  template kdt_status var_ball_count_launch<D, TorusMetric<D>>(                                    \
+      const TreeView&, int, const float*, const float*, int64_t, const int32_t*,                  \
+      const TorusMetric<D>&, int32_t*, hipStream_t);
 KDT_INST(2)
 KDT_INST(3)
 KDT_INST(4)
