@@ -2,9 +2,10 @@
  * kdt.h -- C ABI of the MI355X (gfx950) k-d tree library.
  *
  * The library builds k-d trees on the GPU and answers batched k-nearest-
- * neighbour and fixed-radius (ball) queries over them, then uses those queries
- * for friends-of-friends grouping and for an adaptive SPH particle-to-mesh
- * deposit with its adjoint.  The method is the one of "cosmokdtree: a flexible
+ * neighbour (any k up to KDT_MAX_K_SORTED), fixed-radius (ball) and
+ * axis-aligned box queries over them, in open space or on the D-torus of
+ * periodic boundaries, then uses those queries for friends-of-friends
+ * grouping and for an adaptive SPH particle-to-mesh deposit with its adjoint.  The method is the one of "cosmokdtree: a flexible
  * OpenMP-parallelized k-d tree for computational astrophysics applications"
  * (tree construction Sec. 2.1 and Algorithm 1, queries Sec. 2.3 and
  * Algorithms 2-3, applications Sec. 4.1-4.2); the GPU design differs from the
@@ -22,7 +23,8 @@
  *   - Indices in results are int32 and refer to the caller's input order.
  *   - Distances are squared Euclidean distances (Eq. 1 with p = 2) in float32,
  *     summed over axes 0..d-1 left to right with every operation rounded on
- *     its own (no fused multiply-add).  Equal distances are ordered by the
+ *     its own (no fused multiply-add); on the torus each axis takes the
+ *     shorter way round first (kdt_query_opts.period).  Equal distances are ordered by the
  *     lower index.  These rules make kNN, ball and grouping results exact and
  *     reproducible, independent of the tree's shape.
  */
