@@ -239,6 +239,72 @@ __global__ void k_take_first(const uint64_t* __restrict__ keys, const int32_t* _
   }
 }
 
+// The k-th smallest squared distance of each row of the chunk (modes 1 and
+// 2), without sorting: one wave per row selects it digit by digit, 8 bits of
+// the distance per pass from highest to lowest, each pass a histogram (in
+// LDS) of the row's keys that match the digits chosen so far.  Only the
+// value is wanted, so the order of equal distances does not matter.  Rows
+// with fewer than k keys give +inf.
+__global__ __launch_bounds__(64) void k_row_kth(const uint64_t* __restrict__ keys,
+                                               const int32_t* __restrict__ rel,
+                                               const int32_t* __restrict__ rowof, int64_t s0,
+                                               int k, int mode, int ib,
+                                               float* __restrict__ od2) {
+  __shared__ uint32_t hist[256];
+  const int lane = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const int64_t row = rowof ? (int64_t)rowof[s0 + i] : s0 + i;
+  const int32_t b = rel[i], have = rel[i + 1] - rel[i];
+  if (have < k) {  // uniform over the block
+    if (lane == 0) od2[row] = INFINITY;
+    return;
+  }
+  uint32_t prefix = 0, mask = 0, rank = (uint32_t)k;  // rank among keys matching prefix
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int j = lane; j < 256; j += 64) hist[j] = 0u;
+    __syncthreads();
+    for (int32_t e = lane; e < have; e += 64) {
+      const uint32_t v = (uint32_t)(keys[b + e] >> ib);
+      if ((v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1];
+    const uint32_t c2 = hist[4 * lane + 2], c3 = hist[4 * lane + 3];
+    const uint32_t mine = c0 + c1 + c2 + c3;
+    uint32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t up = __shfl_up(incl, o);
+      if (lane >= o) incl += up;
+    }
+    // the first lane whose bins reach the rank, then the bin within it
+    const int at = __ffsll((unsigned long long)__ballot(incl >= rank)) - 1;
+    uint32_t acc = __shfl(incl - mine, at);
+    const uint32_t e0 = __shfl(c0, at), e1 = __shfl(c1, at), e2 = __shfl(c2, at);
+    uint32_t bin = 4u * (uint32_t)at;
+    if (acc + e0 < rank) {
+      acc += e0;
+      ++bin;
+      if (acc + e1 < rank) {
+        acc += e1;
+        ++bin;
+        if (acc + e2 < rank) {
+          acc += e2;
+          ++bin;
+        }
+      }
+    }
+    rank -= acc;
+    prefix |= bin << shift;
+    mask |= 255u << shift;
+    __syncthreads();  // every lane has read the histogram before it is cleared
+  }
+  if (lane == 0) {
+    const float d2 = __uint_as_float(prefix);
+    od2[row] = mode == 2 ? sqrtf(d2) : d2;
+  }
+}
+
 template <int D, class M>
 static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t nq, int k,
                                  int32_t* d_idx, float* d_d2, int mode, bool sort_q,
@@ -377,9 +443,10 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
     kdt_set_error("kdt_knn: device allocation failed for the large-k keys");
     return KDT_ENOMEM;
   }
-  // 3. per chunk: keys, segmented sort, first k.  A key is (d2 bits << ib |
-  // index) with ib = the bits of the largest index, so the radix sort
-  // passes over 32 + ib bits only.
+  // 3. per chunk: keys, then a segmented sort and the first k (or, for the
+  // k-th distance alone, a selection).  A key is (d2 bits << ib | index) with
+  // ib = the bits of the largest index, so the radix sort passes over
+  // 32 + ib bits only.
   int ib = 1;
   while (ib < 31 && (int64_t(1) << ib) < tr->n) ++ib;
   void* stmp = nullptr;
@@ -393,6 +460,13 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
       k_ball_fill<D><<<(unsigned)((m + kFillWaves - 1) / kFillWaves), 64 * kFillWaves,
                        sizeof(uint32_t) * (size_t)stack_len * kFillWaves, stream>>>(
           v, q, s0, s1, r2, off, h_off[s0], keys, stack_len, ib, metric);
+    }
+    if (mode != 0) {  // only the k-th distance: selected, not sorted
+      k_row_kth<<<(unsigned)m, 64, 0, stream>>>(keys, rel, rowof, s0, k, mode, ib, d_d2);
+      s0 = s1;
+      continue;
+    }
+    if (total > 0) {
       size_t sb = 0;
       if (hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, sb, keys, sorted, (int)total, (int)m,
                                                      rel, rel + 1, 0, 32 + ib, stream) !=

@@ -136,3 +136,8 @@ def test_large_k_lattice_ties():
         gi, gd = t.knn(to_dev(q), k)
         np.testing.assert_array_equal(to_host(gi), oi)
         np.testing.assert_array_equal(to_host(gd), od)
+        # the k-th distance alone is selected, not sorted: equal distances at
+        # and around the k-th place are the hard case
+        np.testing.assert_array_equal(to_host(t.knn(to_dev(q), k, kth_only=1)), od[:, -1])
+        np.testing.assert_array_equal(to_host(t.knn(to_dev(q), k, kth_only=2)),
+                                      np.sqrt(od[:, -1]))
