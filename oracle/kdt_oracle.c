@@ -706,8 +706,10 @@ int orc_range_tree(const orc_tree *t, const float *q, int64_t nq, float r, int64
                 free(v.buf);
                 return ORC_EINVAL;
             }
-            qsort(v.buf, (size_t)v.n, sizeof(int32_t), idx_cmp);
-            memcpy(out_idx + pos, v.buf, sizeof(int32_t) * (size_t)v.n);
+            if (v.n > 0) { /* an empty ball may have no buffer yet */
+                qsort(v.buf, (size_t)v.n, sizeof(int32_t), idx_cmp);
+                memcpy(out_idx + pos, v.buf, sizeof(int32_t) * (size_t)v.n);
+            }
         }
         pos += v.n;
     }
