@@ -82,7 +82,8 @@ def test_torus_fof_equals_brute_force(kind, d):
     L = _periods(d)
     for n in (1, 33, 2000):
         x = wrap(cases.points(kind, n, d, seed=3 * n + d) * 1.7 - 0.3, L)
-        for leaf in (4, 32):
+        # leaves above 64 points link one lane per point instead of per wave
+        for leaf in (4, 32, 100):
             t = kdt.build(to_dev(x), leaf_size=leaf)
             for l in (0.0, 0.03, 0.1, 0.4):
                 say(f"torus fof d={d} kind={kind} n={n} leaf={leaf} l={l}")
