@@ -151,6 +151,15 @@ def test_torus_clustered_orders_and_lattice_ties():
         np.testing.assert_array_equal(to_host(gd), od)
     np.testing.assert_array_equal(to_host(t.range(qd, 0.02, period=1.0)),
                                   oracle.range_brute(x, q, 0.02, period=1.0))
+    # leaves above 32 points take the traversal's blockwise leaf scan
+    t100 = kdt.build(to_dev(x), leaf_size=100)
+    for k in (8, 64):
+        say(f"torus clustered leaf=100 k={k}")
+        oi, od = oracle.knn_brute(x, q, k, period=1.0)
+        gi, gd = t100.knn(qd, k, period=1.0)
+        np.testing.assert_array_equal(to_host(gi), oi)
+        np.testing.assert_array_equal(to_host(gd), od)
+        np.testing.assert_array_equal(to_host(t100.knn(qd, k, kth_only=1, period=1.0)), od[:, -1])
     rng = np.random.Generator(np.random.PCG64(3))
     xl = (rng.integers(0, 8, (5000, 3)) / 8.0).astype(np.float32)
     ql = (rng.integers(0, 8, (300, 3)) / 8.0).astype(np.float32)
