@@ -47,18 +47,23 @@ __global__ __launch_bounds__(kFBlock) void k_fof_link(TreeView t, float l2,
   fof_point<D>(t, p, s, me, l2, 0, parent, conn, &stk[0][threadIdx.x], kFBlock);
 }
 
+// Returns the status of the launches (the packet launch checks its own and
+// clears the runtime's error, so it is passed on from here).
 template <int D>
-static void fof_launch(const TreeView& v, int leaf, int64_t n_nodes, float l2, int32_t* labels,
-                       uint32_t* conn, hipStream_t stream) {
+static kdt_status fof_launch(const TreeView& v, int leaf, int64_t n_nodes, float l2,
+                             int32_t* labels, uint32_t* conn, hipStream_t stream) {
   const unsigned gn = (unsigned)((n_nodes + 255) / 256);
   const unsigned gp = (unsigned)((v.n + 255) / 256);
   const unsigned gl = (unsigned)((v.n + kFBlock - 1) / kFBlock);
   k_fof_clique_mark<D><<<gn, 256, 0, stream>>>(v.box, n_nodes, l2, conn);
   k_fof_clique_join<D><<<gp, 256, 0, stream>>>(v, labels, conn);
-  if (leaf <= 64)
-    (void)fof_packet_launch<D>(v, leaf, l2, labels, conn, stream);
-  else
-    k_fof_link<D><<<gl, kFBlock, 0, stream>>>(v, l2, labels, conn);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_fof: clique kernel launch failed");
+    return KDT_EDEVICE;
+  }
+  if (leaf <= 64) return fof_packet_launch<D>(v, leaf, l2, labels, conn, stream);
+  k_fof_link<D><<<gl, kFBlock, 0, stream>>>(v, l2, labels, conn);
+  return KDT_OK;
 }
 
 __global__ void k_fof_init(int32_t* __restrict__ parent, int64_t n) {
@@ -111,18 +116,20 @@ extern "C" kdt_status kdt_fof(const kdt_tree* tree, float l, int32_t* d_labels, 
     kdt_set_error("kdt_fof: device allocation failed");
     return KDT_ENOMEM;
   }
+  kdt_status st = KDT_OK;
   switch (tree->d) {
-    case 2: fof_launch<2>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
-    case 3: fof_launch<3>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
-    case 4: fof_launch<4>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
-    case 8: fof_launch<8>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
-    case 16: fof_launch<16>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 2: st = fof_launch<2>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 3: st = fof_launch<3>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 4: st = fof_launch<4>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 8: st = fof_launch<8>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
+    case 16: st = fof_launch<16>(v, tree->leaf, tree->n_nodes, l2, d_labels, conn, stream); break;
     default:
       (void)hipFreeAsync(conn, stream);
       kdt_set_error("kdt_fof: unsupported dimension %d", tree->d);
       return KDT_EUNSUPPORTED;
   }
   (void)hipFreeAsync(conn, stream);
+  if (st != KDT_OK) return st;
   k_fof_final<<<g, 256, 0, stream>>>(d_labels, n);
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_fof: kernel launch failed");

@@ -54,16 +54,30 @@ struct LeafReader {
 // In high dimension almost every leaf is visited and the scan -- 64 queries
 // against up to 64 points -- is a dense contraction.  The filter computes
 // every query-point dot product with fp32 MFMA (v_mfma_f32_16x16x4f32: 16
-// blocks of 16 x 16, d/4 steps each) and marks point i for query q when
-//   (1 - 2^-16) (|q|^2 + |p_i|^2) - 2 q.p_i  <=  (1 + 2^-16) worst_q + 2^-100,
-// worst_q being the query's current k-th squared distance.  Rounding bound:
-// the dot product (d products and sums in fp32), the two norms and the
-// combination stay within (3d + 8) u (|q|^2 + |p|^2) of the real squared
-// distance, and the exact float32 distance of the insertion pass is within
-// (d + 2) u of it (u = 2^-24); the relative margins above are 256 u, and the
-// absolute term covers denormal products the matrix core may flush.  So every
-// point that can enter the list is marked, and the insertion pass, which
-// recomputes the exact distance and key, keeps the results bit-identical.
+// blocks of 16 x 16, d/4 steps each) and marks point i for query q.
+//
+// Everything is first moved to a centre c, the wave's first active query
+// (wave-uniform): q' = fl(q - c), p' = fl(p - c).  With s = |q'|^2 + |p'|^2
+// (computed), point i is marked when
+//   !( (1 - 2^-16) s - 2 q'.p'  >  (1 + 2^-16) worst_q + 2^-100 )  or  !(s < 2^125),
+// worst_q being the query's current k-th squared distance.
+//
+// Why no candidate is lost.  While s < 2^125 no partial sum of the norms or
+// of the dot product can overflow (each is at most s), and the expansion
+// (dot product, norms, combination, d products and sums in fp32 in any
+// order) stays within (3d + 8) u s of |q' - p'|^2, u = 2^-24.  The
+// recentring moves each axis of q' - p' by at most u (|q'_a| + |p'_a|)
+// against q - p, which changes the squared length by at most 4 u s (a little
+// more, by a factor 1 + O(u)).  The exact float32 distance of the insertion
+// pass is within (d + 2) u of |q - p|^2.  The relative margins are 256 u of s
+// and of worst_q, more than (3d + 12) + (d + 2) = 78 u at d = 16, and the
+// absolute term covers denormal products a matrix core may flush.  When s
+// reaches 2^125, or any value is NaN, the point is marked without a test.
+// So every point that can enter the list is marked, and the insertion pass,
+// which recomputes the exact distance from the original coordinates, keeps
+// the results bit-identical.  The centre keeps s near the squared size of
+// the region the wave works in, so far from the origin (coordinates of
+// 1e18 and beyond) the filter still prunes instead of marking everything.
 //
 // MFMA lane layout (16x16x4 f32): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16] and receives D[4 (l / 16) + r][l % 16] in register r.
@@ -75,9 +89,11 @@ template <int D>
 struct DotFilter {
   static constexpr bool kOn = D >= 8 && D % 4 == 0;
   static constexpr int KS = D / 4 > 0 ? D / 4 : 1;  // MFMA k-steps
-  float bq[4][KS];  // B operands: coordinate 4 s + l / 16 of query 16 qj + l % 16
-  float nq[4];      // |q|^2 of query 16 qj + l % 16
-  float* np;        // LDS [64]: |p|^2 of the open leaf's points
+  float bq[4][KS];  // B operands: coordinate 4 s + l / 16 of query 16 qj + l % 16, minus c
+  float nq[4];      // |q - c|^2 of query 16 qj + l % 16
+  float c[D];       // the centre (wave-uniform)
+  float cs[KS];     // c[4 s + l / 16]: the centre on this lane's operand slots
+  float* np;        // LDS [64]: |p - c|^2 of the open leaf's points
   uint64_t* mb;     // LDS [4][4][16]: partial marks on their way to the query's lane
 
   // LDS of one wave: the leaf slice (also the query staging area), then np
@@ -97,18 +113,30 @@ struct DotFilter {
     float* stage = lds;
     np = lds + slice_floats(leaf);
     mb = reinterpret_cast<uint64_t*>(np + 64);
-    float n2 = 0.0f;
-#pragma unroll
-    for (int a = 0; a < D; ++a) n2 += p[a] * p[a];
+    const uint64_t am = __ballot(active);
+    const int first = am ? __ffsll((unsigned long long)am) - 1 : 0;
     wave_sync();
 #pragma unroll
     for (int a = 0; a < D; ++a) stage[l * D + a] = active ? p[a] : 0.0f;
+    wave_sync();
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      c[a] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stage[first * D + a])));
+#pragma unroll
+    for (int s = 0; s < KS; ++s) cs[s] = stage[first * D + 4 * s + (l >> 4)];
+    float n2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const float v = p[a] - c[a];
+      n2 += v * v;
+    }
     np[l] = active ? n2 : 0.0f;
     wave_sync();
 #pragma unroll
     for (int qj = 0; qj < 4; ++qj) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s) bq[qj][s] = stage[(16 * qj + (l & 15)) * D + 4 * s + (l >> 4)];
+      for (int s = 0; s < KS; ++s)
+        bq[qj][s] = stage[(16 * qj + (l & 15)) * D + 4 * s + (l >> 4)] - cs[s];
       nq[qj] = np[16 * qj + (l & 15)];
     }
     wave_sync();
@@ -126,7 +154,10 @@ struct DotFilter {
     float n2 = 0.0f;
     if (l < cnt) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) n2 += leaf[l * S + a] * leaf[l * S + a];
+      for (int a = 0; a < D; ++a) {
+        const float v = leaf[l * S + a] - c[a];
+        n2 += v * v;
+      }
     }
     np[l] = n2;
     wave_sync();
@@ -136,7 +167,7 @@ struct DotFilter {
       if (16 * pi >= cnt) break;
       float ap[KS];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) ap[s] = leaf[(16 * pi + (l & 15)) * S + 4 * s + (l >> 4)];
+      for (int s = 0; s < KS; ++s) ap[s] = leaf[(16 * pi + (l & 15)) * S + 4 * s + (l >> 4)] - cs[s];
       const int row0 = 16 * pi + 4 * (l >> 4);
       float npv[4];
 #pragma unroll
@@ -148,8 +179,11 @@ struct DotFilter {
         for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[s], bq[qj][s], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float lhs = (nq[qj] + npv[r]) * (1.0f - 0x1p-16f) - 2.0f * acc[r];
-          m[qj] |= (uint64_t)(lhs <= thr[qj]) << (row0 + r);
+          const float ns = nq[qj] + npv[r];
+          const float lhs = ns * (1.0f - 0x1p-16f) - 2.0f * acc[r];
+          // unordered compares (NaN) and norms too large to trust mark the point
+          const bool mk = !(lhs > thr[qj]) || !(ns < 0x1p125f);
+          m[qj] |= (uint64_t)mk << (row0 + r);
         }
       }
     }

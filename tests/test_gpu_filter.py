@@ -63,3 +63,93 @@ def test_filter_far_from_the_origin(d, offset):
     oi, od = oracle.knn_brute(x, x, 16)
     np.testing.assert_array_equal(to_host(gi), oi)
     np.testing.assert_array_equal(to_host(gd), od)
+
+
+def _large(kind, n, d, scale, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if kind == "cloud":    # far from the origin, 1 % spread: finite distances
+        return (scale * (1 + 0.01 * rng.random((n, d)))).astype(np.float32)
+    if kind == "spread":   # around the origin at `scale`: many distances overflow to inf
+        return (scale * rng.standard_normal((n, d))).astype(np.float32)
+    # mixed magnitudes 1 .. 1e19 in one set
+    return (rng.standard_normal((n, d)) * 10.0 ** rng.integers(0, 20, (n, 1))).astype(np.float32)
+
+
+@pytest.mark.parametrize("d", (8, 16))
+@pytest.mark.parametrize("scale", (1e18, 4e18, 1e19))
+@pytest.mark.parametrize("kind", ("cloud", "spread", "mixed"))
+def test_filter_large_coordinates(d, scale, kind):
+    """Coordinates where |q|^2 + |p|^2 overflows float32: the filter works
+    around the wave's first query and marks every pair whose norms are too
+    large to trust, so results stay exact."""
+    if kind == "mixed" and scale != 1e19:
+        pytest.skip("one mixed case")
+    dev()
+    x = _large(kind, 3000, d, scale, seed=int(71 + d + np.log10(scale)))
+    q = _large(kind, 400, d, scale, seed=int(91 + d + np.log10(scale)))
+    for k in (1, 16, 64):
+        oi, od = oracle.knn_brute(x, q, k)
+        for leaf in (16, 64):
+            t = kdt.build(to_dev(x), leaf_size=leaf)
+            for sort in (1, 0):
+                say(f"large coordinates d={d} scale={scale:g} kind={kind} k={k} leaf={leaf} sort={sort}")
+                gi, gd = t.knn(to_dev(q), k, traversal=2, sort_queries=sort)
+                np.testing.assert_array_equal(to_host(gi), oi)
+                np.testing.assert_array_equal(to_host(gd), od)
+            t.close()
+    oi, od = oracle.knn_brute(x, x, 16)
+    t = kdt.build(to_dev(x), leaf_size=64)
+    gi, gd = t.knn(None, 16, traversal=2)
+    np.testing.assert_array_equal(to_host(gi), oi)
+    np.testing.assert_array_equal(to_host(gd), od)
+    t.close()
+
+
+@pytest.mark.parametrize("d", (8, 16))
+def test_filter_norms_overflow_dot_product_does_not(d):
+    """Two points whose squared norms sum above FLT_MAX while their dot
+    product stays finite, and whose distance is finite: only the guard on the
+    norm sum keeps the pair.  Queries in input order put a query at the
+    origin first in the wave, so the centre does not help."""
+    dev()
+    a = np.sqrt(1.75e38)
+    cos = 3.3e38 / (2 * 1.75e38)
+    rng = np.random.Generator(np.random.PCG64(5 + d))
+    x = np.zeros((200, d))
+    x[:100] = rng.random((100, d))
+    x[100:, 0] = a * cos * (1 + 1e-3 * rng.random(100))
+    x[100:, 1] = a * np.sqrt(1 - cos * cos) * (1 + 1e-3 * rng.random(100))
+    x = x.astype(np.float32)
+    q = np.zeros((64, d))
+    q[1:, 0] = a * (1 + 1e-3 * rng.random(63))
+    q = q.astype(np.float32)
+    t = kdt.build(to_dev(x), leaf_size=64)
+    for k in (1, 8, 64):
+        say(f"norm-overflow guard d={d} k={k}")
+        oi, od = oracle.knn_brute(x, q, k)
+        assert np.isfinite(od[1:, 0]).all()
+        gi, gd = t.knn(to_dev(q), k, traversal=2, sort_queries=0)
+        np.testing.assert_array_equal(to_host(gi), oi)
+        np.testing.assert_array_equal(to_host(gd), od)
+    t.close()
+
+
+def test_batched_forest_large_coordinates():
+    """The batched forest's wave kNN uses the same filter at d = 8."""
+    dev()
+    sizes = [1, 40, 700, 3001, 64, 1500]
+    sets = [_large(kind, n, 8, sc, seed=300 + i) for i, (n, kind, sc) in enumerate(
+        zip(sizes, ("cloud", "cloud", "spread", "cloud", "mixed", "spread"),
+            (1e18, 4e18, 1e19, 1e19, 1.0, 4e18)))]
+    x = np.concatenate(sets)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    lens = np.zeros(len(sizes), np.float32)
+    plan = kdt.BatchPlan(off, 8, 8, traversal=0)
+    say("batched forest, large coordinates, d=8")
+    idx, d2, lab = (to_host(a) for a in plan.launch(to_dev(x), to_dev(lens), use_graph=2))
+    for s in range(len(sizes)):
+        xs = sets[s]
+        oi, od = oracle.knn_brute(xs, xs, 8)
+        np.testing.assert_array_equal(idx[off[s]:off[s + 1]], oi)
+        np.testing.assert_array_equal(d2[off[s]:off[s + 1]], od)
+    plan.close()
