@@ -384,6 +384,36 @@ kdt_status kdt_batch_launch(kdt_batch_plan *plan, const float *d_pts, const floa
                             hipStream_t stream);
 kdt_status kdt_batch_plan_free(kdt_batch_plan *plan);
 
+/*
+ * kdt_knn_noalloc -- kdt_knn for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  It allocates nothing (no hipMalloc, no stream-ordered pool,
+ * no allocating library routine) and waits on nothing.
+ *
+ * Arguments, results and errors as kdt_knn, restricted to what needs no
+ * allocation: 1 <= k <= KDT_MAX_K and open boundaries (opts->period must be
+ * NULL; otherwise KDT_EUNSUPPORTED).  The tree must live on the current
+ * device (KDT_EINVAL otherwise).
+ *
+ * Its only scratch, the query order of sorted external queries, lives in a
+ * static device array of KDT_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every GPU it runs on until the process ends.  Ordering more than
+ * KDT_NOALLOC_MAX_SORTED queries does not fit: KDT_ECAPACITY, with the limit
+ * in kdt_last_error().  Queries in input order (sort_queries = 0), an order
+ * passed in opts->order, and self queries (d_q NULL) use no scratch and have
+ * no limit.
+ *
+ * All calls on one GPU share that GPU's array: calls that overlap in time on
+ * one GPU (two streams, two threads) race on it and must be ordered by the
+ * caller.  The array keeps the last call's contents; nothing in it has to
+ * start at zero.
+ */
+#define KDT_NOALLOC_MAX_SORTED (1 << 22)
+#define KDT_NOALLOC_SCRATCH_BYTES ((size_t)72 << 20)
+kdt_status kdt_knn_noalloc(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t k,
+                           int32_t *d_idx, float *d_d2, int32_t kth_only,
+                           const kdt_query_opts *opts, hipStream_t stream);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *kdt_last_error(void);
 

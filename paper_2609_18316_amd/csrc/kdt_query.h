@@ -571,6 +571,26 @@ kdt_status knn_large(const kdt_tree* tr, const float* d_q, int64_t nq, int k, in
                      float* d_d2, int mode, bool sort_q, const int32_t* given,
                      const float* period, hipStream_t stream);
 
+// kdt_knn's options after its argument checks.
+struct KnnArgs {
+  bool empty = false;  // nq == 0: nothing to do
+  bool sort_q = true;
+  int traversal = 0;
+  const int32_t* given = nullptr;
+  const float* period = nullptr;
+};
+// Checks kdt_knn's arguments (`who` names the entry point in messages).
+kdt_status knn_check(const kdt_tree* tree, const float* d_q, int64_t nq, int32_t k,
+                     const float* d_d2, int32_t kth_only, const kdt_query_opts* opts,
+                     const char* who, KnnArgs* a);
+// kNN with k <= KDT_MAX_K and open boundaries.  With a workspace (ws_bytes
+// bytes of device memory) the query order, the only scratch of this path,
+// is carved from it and nothing is allocated; KDT_ECAPACITY if it is too
+// small.  ws == NULL: scratch from the stream-ordered pool.
+kdt_status knn_in_workspace(const kdt_tree* t, const float* d_q, int64_t nq, int k,
+                            int32_t* d_idx, float* d_d2, int mode, const KnnArgs& a, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
+
 template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
                                const int32_t* order, int32_t* d_count, uint32_t split_budget,

@@ -26,7 +26,9 @@ DIMS = (2, 3, 4, 8, 16)
 EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt_knn",
            "kdt_range", "kdt_box", "kdt_fof", "kdt_fof_torus", "kdt_p2m", "kdt_p2m_backward",
            "kdt_tree_perm", "kdt_query_order",
-           "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_last_error")
+           "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
+           "kdt_last_error")
+NOALLOC_MAX_SORTED = 1 << 22   # queries kdt_knn_noalloc can order in its static scratch
 
 
 class KdtError(RuntimeError):
@@ -80,6 +82,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_tree_get_info.argtypes = [vp, C.POINTER(TreeInfo)]
     lib.kdt_tree_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.kdt_knn.argtypes = [vp, vp, i64, i32, vp, vp, i32, C.POINTER(QueryOpts), vp]
+    lib.kdt_knn_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, i32, C.POINTER(QueryOpts), vp]
     lib.kdt_range.argtypes = [vp, vp, i64, f32, vp, vp, vp, i64, C.POINTER(C.c_int64),
                               C.POINTER(QueryOpts), vp]
     lib.kdt_box.argtypes = [vp, vp, vp, i64, vp, vp, vp, i64, C.POINTER(C.c_int64),
@@ -211,6 +214,28 @@ class Tree:
         _check(load().kdt_knn(self._h, _ptr(queries), nq, k, _ptr(idx), _ptr(d2), 0,
                               C.byref(opts), _stream(stream)))
         return idx, d2
+
+    def knn_noalloc(self, queries: torch.Tensor | None, k: int, d2: torch.Tensor,
+                    idx: torch.Tensor | None = None, kth_only: int = 0,
+                    sort_queries: bool = True, traversal: int = 0,
+                    order: torch.Tensor | None = None, stream=None) -> None:
+        """kNN into caller-given outputs through ``kdt_knn_noalloc`` (no
+        allocation anywhere: the library's static scratch orders the queries).
+
+        ``d2`` is [nq][k] float32 (or [nq] with ``kth_only``), ``idx`` [nq][k]
+        int32 or None.  k <= 64, open boundaries.
+        """
+        nq = self.n if queries is None else queries.shape[0]
+        if queries is not None:
+            queries = _dev(queries, torch.float32, "queries", (nq, self.d))
+        d2 = _dev(d2, torch.float32, "d2", (nq,) if kth_only else (nq, k))
+        if idx is not None:
+            if kth_only:
+                raise ValueError("idx must be None with kth_only")
+            idx = _dev(idx, torch.int32, "idx", (nq, k))
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), 0, None)
+        _check(load().kdt_knn_noalloc(self._h, _ptr(queries), nq, k, _ptr(idx), _ptr(d2),
+                                      kth_only, C.byref(opts), _stream(stream)))
 
     def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
               sort_queries: bool = True, order: torch.Tensor | None = None, traversal: int = 0,
