@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -74,6 +75,27 @@ def _check(rc: int, what: str):
         raise ValueError(f"oracle {what} failed with status {rc}")
 
 
+def host_threads() -> int:
+    """Threads for slicing oracle queries: the host's cores, at most 16."""
+    return max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                      else (os.cpu_count() or 1)))
+
+
+def _sliced(nq: int, threads: int, call):
+    """Runs call(lo, hi) over contiguous query slices on `threads` host
+    threads.  The C routines take their own buffers and only read the tree,
+    and ctypes releases the interpreter lock while they run, so the slices
+    run in parallel; each slice is the single-threaded oracle as written."""
+    threads = max(1, min(int(threads), nq))
+    if threads == 1:
+        call(0, nq)
+        return
+    bounds = np.linspace(0, nq, threads + 1).astype(np.int64)
+    with ThreadPoolExecutor(threads) as ex:
+        for f in [ex.submit(call, int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:])]:
+            f.result()
+
+
 def _pts(x) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float32)
     if x.ndim == 1:
@@ -95,23 +117,29 @@ def _period(period, d: int):
     return L
 
 
-def knn_brute(pts, queries, k: int, period=None):
+def knn_brute(pts, queries, k: int, period=None, threads: int = 1):
     """k smallest (d2, index) keys of every query, ascending: (idx, d2).
 
     ``period`` (a length or one per axis): distances on the D-torus of those
     periods (Sec. 2.1, Sec. 2.4), every coordinate in [0, period).
+    ``threads``: contiguous query slices on that many host threads.
     """
     pts, queries = _pts(pts), _pts(queries)
     nq = queries.shape[0]
     idx = np.empty((nq, k), np.int32)
     d2 = np.empty((nq, k), np.float32)
     lib = _load()
-    if period is None:
-        rc = lib.orc_knn_brute(pts, pts.shape[0], pts.shape[1], queries, nq, k, idx, d2)
-    else:
-        rc = lib.orc_knn_brute_torus(pts, pts.shape[0], pts.shape[1], queries, nq, k,
-                                     _period(period, pts.shape[1]), idx, d2)
-    _check(rc, "knn_brute")
+
+    def call(a, b):
+        if period is None:
+            rc = lib.orc_knn_brute(pts, pts.shape[0], pts.shape[1], queries[a:b], b - a, k,
+                                   idx[a:b], d2[a:b])
+        else:
+            rc = lib.orc_knn_brute_torus(pts, pts.shape[0], pts.shape[1], queries[a:b], b - a, k,
+                                         _period(period, pts.shape[1]), idx[a:b], d2[a:b])
+        _check(rc, "knn_brute")
+
+    _sliced(nq, threads, call)
     return idx, d2
 
 
@@ -219,21 +247,33 @@ class Tree:
         _check(_load().orc_tree_export(self._h, *[out[k].ctypes.data for k in keys]), "export")
         return out
 
-    def knn(self, queries, k: int):
+    def knn(self, queries, k: int, threads: int = 1):
+        """Algorithm 2 for every query: (idx, d2) ascending by (d2, index).
+        ``threads``: contiguous query slices on that many host threads."""
         q = _pts(queries)
         nq = q.shape[0]
         idx = np.empty((nq, k), np.int32)
         d2 = np.empty((nq, k), np.float32)
-        _check(_load().orc_knn_tree(self._h, q, nq, k, idx, d2), "knn_tree")
+
+        def call(a, b):
+            _check(_load().orc_knn_tree(self._h, q[a:b], b - a, k, idx[a:b], d2[a:b]), "knn_tree")
+
+        _sliced(nq, threads, call)
         return idx, d2
 
-    def range(self, queries, r: float, lists: bool = False):
+    def range(self, queries, r: float, lists: bool = False, threads: int = 1):
+        """Algorithm 3 for every query: counts, and with ``lists`` the CSR lists
+        too (``threads`` applies to counts only)."""
         q = _pts(queries)
         nq = q.shape[0]
         lib = _load()
         count = np.empty(nq, np.int64)
-        _check(lib.orc_range_tree(self._h, q, nq, np.float32(r), count, None, None, 0),
-               "range_tree")
+
+        def call(a, b):
+            _check(lib.orc_range_tree(self._h, q[a:b], b - a, np.float32(r), count[a:b], None,
+                                      None, 0), "range_tree")
+
+        _sliced(nq, threads, call)
         if not lists:
             return count
         total = int(count.sum())

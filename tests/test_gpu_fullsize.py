@@ -1,6 +1,9 @@
 """GPU parity at the full workload sizes, in the launch configuration bench.py
-times, on sampled outputs the oracle computes one by one (and properties that
-hold at any size where the oracle cannot follow)."""
+times: every row the oracle can follow in seconds (its queries run in
+contiguous slices on the host's cores), sampled rows elsewhere, and properties
+that hold at any size where it cannot follow."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 import torch
@@ -13,6 +16,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 N = 1 << 24
 NQ = 1 << 22
+T = oracle.host_threads()
 
 
 @pytest.fixture(scope="module")
@@ -28,17 +32,21 @@ def clustered():
     return x, q, xt, qt, tree, ot
 
 
-def test_knn_and_counts_full_size_sampled(clustered):
+def test_knn_and_counts_full_size_every_row(clustered):
+    """The headline workload: kNN k = 32 and r = 0.01 counts of all 2^22
+    queries against the oracle, row by row."""
     x, q, xt, qt, tree, ot = clustered
     say("kNN k=32 of 2^22 queries + r=0.01 counts")
     order = tree.query_order(qt)
     idx, d2 = tree.knn(qt, 32, order=order)
     cnt = tree.range(qt, 0.01)
-    s = workloads.sample_indices(NQ, 4096, seed=7)
-    oi, od = ot.knn(q[s], 32)
-    np.testing.assert_array_equal(to_host(idx)[s], oi)
-    np.testing.assert_array_equal(to_host(d2)[s], od)
-    np.testing.assert_array_equal(to_host(cnt)[s], ot.range(q[s], 0.01))
+    idx, d2, cnt = to_host(idx), to_host(d2), to_host(cnt)
+    say(f"oracle kNN of all 2^22 queries on {T} threads")
+    oi, od = ot.knn(q, 32, threads=T)
+    np.testing.assert_array_equal(idx, oi)
+    np.testing.assert_array_equal(d2, od)
+    say(f"oracle counts of all 2^22 queries on {T} threads")
+    np.testing.assert_array_equal(cnt, ot.range(q, 0.01, threads=T))
 
 
 def test_box_counts_full_size_sampled(clustered):
@@ -59,8 +67,9 @@ def test_self_knn_and_smoothing_full_size_sampled(clustered):
     x, q, xt, qt, tree, ot = clustered
     say("self kNN k=32 of 2^24 points, k-th distance")
     h = to_host(tree.knn(None, 32, kth_only=2))
-    s = workloads.sample_indices(N, 4096, seed=8)
-    oi, od = ot.knn(x[s], 32)
+    s = workloads.sample_indices(N, 1 << 20, seed=8)
+    say(f"oracle self kNN of 2^20 sampled points on {T} threads")
+    oi, od = ot.knn(x[s], 32, threads=T)
     np.testing.assert_array_equal(h[s], np.sqrt(od[:, -1]))
     assert (od[:, 0] == 0).all()
 
@@ -148,11 +157,9 @@ def test_dimension_sweep_full_size_sampled(d, dist):
     t = kdt.build(xt, leaf_size=c.leaf_size)
     idx, d2 = t.knn(None, 16, traversal=trav)
     idx, d2 = to_host(idx), to_host(d2)
-    s = workloads.sample_indices(n, 48 if d >= 8 else 256, seed=13 + d)
-    if d <= 4:
-        oi, od = oracle.Tree(x, 32).knn(x[s], 16)
-    else:
-        oi, od = oracle.knn_brute(x, x[s], 16)
+    s = workloads.sample_indices(n, 1024 if d >= 8 else 1 << 14, seed=13 + d)
+    say(f"oracle kNN of {len(s)} sampled points on {T} threads")
+    oi, od = oracle.Tree(x, 32).knn(x[s], 16, threads=T)
     np.testing.assert_array_equal(idx[s], oi)
     np.testing.assert_array_equal(d2[s], od)
 
@@ -170,14 +177,21 @@ def test_batched_full_size():
     for u, v in zip(a, b):
         np.testing.assert_array_equal(u, v)
     idx, d2, lab = a
-    rng = np.random.Generator(np.random.PCG64(14))
-    small = [s for s in range(256) if sizes[s] <= 60000]
-    for s in rng.choice(small, size=min(6, len(small)), replace=False):
+    plan.close()
+
+    def one(s):
         xs = x[off[s]:off[s + 1]]
-        say(f"oracle set {s} (n={len(xs)})")
         t = oracle.Tree(xs, 32)
         oi, od = t.knn(xs, 8)
-        np.testing.assert_array_equal(idx[off[s]:off[s + 1]], oi)
-        np.testing.assert_array_equal(d2[off[s]:off[s + 1]], od)
-        np.testing.assert_array_equal(lab[off[s]:off[s + 1]], t.fof(float(lens[s])))
-    plan.close()
+        return s, oi, od, t.fof(float(lens[s]))
+
+    say(f"oracle kNN and FoF of all 256 sets on {T} threads")
+    done = 0
+    with ThreadPoolExecutor(T) as ex:  # largest sets first
+        for f in [ex.submit(one, int(s)) for s in np.argsort(-sizes, kind="stable")]:
+            s, oi, od, ol = f.result()
+            np.testing.assert_array_equal(idx[off[s]:off[s + 1]], oi)
+            np.testing.assert_array_equal(d2[off[s]:off[s + 1]], od)
+            np.testing.assert_array_equal(lab[off[s]:off[s + 1]], ol)
+            done += 1
+    assert done == 256

@@ -112,3 +112,17 @@ def test_large_k_lattice_ties_match_integer_arithmetic():
             np.testing.assert_array_equal(idx[s, :m], order)
             np.testing.assert_array_equal(d2[s, :m].astype(np.float64) * 64.0, di[order])
             assert np.all(idx[s, m:] == -1) and np.all(np.isinf(d2[s, m:]))
+
+
+def test_query_slices_on_threads_change_nothing():
+    """The oracle's queries may run in contiguous slices on host threads (the
+    CPU baseline and the large parity checks do): results are the same."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    x = rng.random((3000, 3), dtype=np.float32)
+    q = rng.random((1001, 3), dtype=np.float32)
+    t = oracle.Tree(x, 8)
+    for a, b in zip(t.knn(q, 9), t.knn(q, 9, threads=7)):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(t.range(q, 0.05), t.range(q, 0.05, threads=5))
+    for a, b in zip(oracle.knn_brute(x, q, 4), oracle.knn_brute(x, q, 4, threads=3)):
+        np.testing.assert_array_equal(a, b)
