@@ -28,7 +28,8 @@ _i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
 
 
 class _Grid(C.Structure):
-    _fields_ = [("lo", C.c_double * 3), ("cell", C.c_double), ("n", C.c_int32 * 3)]
+    _fields_ = [("lo", C.c_double * 3), ("cell", C.c_double), ("n", C.c_int32 * 3),
+                ("periodic", C.c_int32)]
 
 
 def _load():
@@ -301,12 +302,13 @@ def m4_dw(q: float) -> float:
     return float(_load().orc_m4_dw(float(q)))
 
 
-def _grid(lo, cell, shape) -> _Grid:
+def _grid(lo, cell, shape, periodic=False) -> _Grid:
     g = _Grid()
     for a in range(3):
         g.lo[a] = float(lo[a])
         g.n[a] = int(shape[a])
     g.cell = float(cell)
+    g.periodic = 1 if periodic else 0
     return g
 
 
@@ -315,22 +317,26 @@ def _f64(a, shape=None) -> np.ndarray:
     return a if shape is None else a.reshape(shape)
 
 
-def p2m(x, m, h, lo, cell, shape, brute: bool = False) -> np.ndarray:
-    """Mass per cell, float64 ``shape`` (x slowest, z fastest)."""
+def p2m(x, m, h, lo, cell, shape, brute: bool = False, periodic: bool = False) -> np.ndarray:
+    """Mass per cell, float64 ``shape`` (x slowest, z fastest).
+
+    ``periodic``: the mesh box is a 3-torus (every H below half a period).
+    ``brute``: every cell of the mesh, distances the shorter way round on a
+    periodic mesh, instead of the particle's support box."""
     x, m, h = _f64(x, (-1, 3)), _f64(m), _f64(h)
     rho = np.empty(int(np.prod(shape)), np.float64)
     fn = _load().orc_p2m_brute if brute else _load().orc_p2m
-    _check(fn(x, m, h, x.shape[0], C.byref(_grid(lo, cell, shape)), rho), "p2m")
+    _check(fn(x, m, h, x.shape[0], C.byref(_grid(lo, cell, shape, periodic)), rho), "p2m")
     return rho.reshape(shape)
 
 
-def p2m_backward(x, m, h, lo, cell, shape, g):
+def p2m_backward(x, m, h, lo, cell, shape, g, periodic: bool = False):
     """(dL/dm, dL/dx) for L = sum(g * rho), h held fixed, float64."""
     x, m, h = _f64(x, (-1, 3)), _f64(m), _f64(h)
     g = _f64(g).reshape(-1)
     n = x.shape[0]
     dm = np.empty(n, np.float64)
     dx = np.empty((n, 3), np.float64)
-    _check(_load().orc_p2m_backward(x, m, h, n, C.byref(_grid(lo, cell, shape)), g,
+    _check(_load().orc_p2m_backward(x, m, h, n, C.byref(_grid(lo, cell, shape, periodic)), g,
                                     dm.ctypes.data, dx.ctypes.data), "p2m_backward")
     return dm, dx

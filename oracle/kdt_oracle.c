@@ -46,7 +46,12 @@
  *     0 beyond; cells outside the grid are dropped and the weights of each
  *     particle are normalised over the in-grid cells, so mass is conserved;
  *     cell (i, j, k) is centred at lo + (i + 1/2, j + 1/2, k + 1/2) * cell and
- *     the grid is stored x slowest, z fastest.
+ *     the grid is stored x slowest, z fastest;
+ *   - periodic deposit (the periodic boundaries of Sec. 2.4 applied to the
+ *     mesh of Sec. 4.2): the mesh box is a 3-torus of periods n_a * cell; the
+ *     distance from a particle to a cell centre takes per axis the shorter way
+ *     round (as the torus metric of the queries); every H_i must be below half
+ *     of every period, so no cell is reached twice, and no cell is dropped.
  */
 #include <math.h>
 #include <stdint.h>
@@ -784,6 +789,7 @@ typedef struct {
     double lo[3];
     double cell;
     int32_t n[3];
+    int32_t periodic; /* 1: the mesh box is a 3-torus of periods n[a] * cell */
 } orc_grid;
 
 static int grid_ok(const orc_grid *g)
@@ -801,7 +807,9 @@ static int inside_grid(const orc_grid *g, const double *x)
 }
 
 /* Cell index range [c0, c1] per axis that can hold centres within H of x.
-   brute != 0 returns the whole grid instead. */
+   brute != 0 returns the whole grid instead.  On a periodic mesh the range
+   is not clipped: indices below 0 or above n - 1 stand for the cells one
+   period away (an unwrapped index; see wrap_cell). */
 static void cell_box(const orc_grid *g, const double *x, double H, int brute, int32_t *c0,
                      int32_t *c1)
 {
@@ -814,16 +822,58 @@ static void cell_box(const orc_grid *g, const double *x, double H, int brute, in
         double f0 = (x[a] - H - g->lo[a]) / g->cell - 0.5;
         double f1 = (x[a] + H - g->lo[a]) / g->cell - 0.5;
         int64_t i0 = (int64_t)floor(f0) - 1, i1 = (int64_t)ceil(f1) + 1;
-        if (i0 < 0) i0 = 0;
-        if (i1 > g->n[a] - 1) i1 = g->n[a] - 1;
+        if (!g->periodic) {
+            if (i0 < 0) i0 = 0;
+            if (i1 > g->n[a] - 1) i1 = g->n[a] - 1;
+        } else {
+            /* H < period / 2: keep at most one copy of each cell, the n
+               cells whose centres lie within half a period of x (every
+               centre within H is among them, at its nearest copy) */
+            if (i1 - i0 + 1 > g->n[a]) {
+                i0 = (int64_t)ceil((x[a] - g->lo[a]) / g->cell - 0.5 - 0.5 * g->n[a]);
+                i1 = i0 + g->n[a] - 1;
+            }
+        }
         c0[a] = (int32_t)i0;
         c1[a] = (int32_t)i1;
     }
 }
 
+/* Centre of (unwrapped) cell c along axis a. */
 static double cell_centre(const orc_grid *g, int a, int32_t c)
 {
     return g->lo[a] + ((double)c + 0.5) * g->cell;
+}
+
+/* Storage index along axis a of unwrapped cell c (c itself on an open mesh). */
+static int32_t wrap_cell(const orc_grid *g, int a, int32_t c)
+{
+    if (!g->periodic) return c;
+    int32_t w = c % g->n[a];
+    return w < 0 ? w + g->n[a] : w;
+}
+
+/* Per-axis offset from the centre of storage cell c to x on the mesh: on a
+   periodic mesh the shorter way round (used by the whole-mesh form only). */
+static double axis_offset(const orc_grid *g, int a, const double *x, int32_t c)
+{
+    double v = x[a] - cell_centre(g, a, c);
+    if (g->periodic) {
+        double L = g->cell * g->n[a];
+        double u = fabs(v);
+        if (L - u < u) v = v > 0.0 ? v - L : v + L;
+    }
+    return v;
+}
+
+/* The smoothing length must stay below half of every period on a periodic
+   mesh: beyond, a particle's support would reach a cell from both sides. */
+static int support_ok(const orc_grid *g, double H)
+{
+    if (!g->periodic) return 1;
+    for (int a = 0; a < 3; ++a)
+        if (!(2.0 * H < g->cell * g->n[a])) return 0;
+    return 1;
 }
 
 /*
@@ -840,30 +890,40 @@ static int p2m_forward(const double *x, const double *m, const double *h, int64_
         const double *xi = x + 3 * i;
         if (!inside_grid(g, xi) || !(h[i] >= 0.0)) return ORC_EINVAL;
         double H = h[i] > g->cell ? h[i] : g->cell;
+        if (!support_ok(g, H)) return ORC_EINVAL;
         int32_t c0[3], c1[3];
         cell_box(g, xi, H, brute, c0, c1);
+        /* Two passes over the same cells: the normalisation S, then the
+           deposit.  The support-box form measures from the unwrapped cell
+           centre (the nearest copy of the cell, as H < period / 2); the
+           whole-mesh form (brute) takes the shorter way round per axis. */
         double S = 0.0;
-        for (int32_t a = c0[0]; a <= c1[0]; ++a)
-            for (int32_t b = c0[1]; b <= c1[1]; ++b)
-                for (int32_t c = c0[2]; c <= c1[2]; ++c) {
-                    double dx = xi[0] - cell_centre(g, 0, a);
-                    double dy = xi[1] - cell_centre(g, 1, b);
-                    double dz = xi[2] - cell_centre(g, 2, c);
-                    double r = sqrt(dx * dx + dy * dy + dz * dz);
-                    S += orc_m4_w(2.0 * r / H);
-                }
-        if (!(S > 0.0)) return ORC_EINVAL;
-        for (int32_t a = c0[0]; a <= c1[0]; ++a)
-            for (int32_t b = c0[1]; b <= c1[1]; ++b)
-                for (int32_t c = c0[2]; c <= c1[2]; ++c) {
-                    double dx = xi[0] - cell_centre(g, 0, a);
-                    double dy = xi[1] - cell_centre(g, 1, b);
-                    double dz = xi[2] - cell_centre(g, 2, c);
-                    double r = sqrt(dx * dx + dy * dy + dz * dz);
-                    double w = orc_m4_w(2.0 * r / H);
-                    if (w != 0.0)
-                        rho[((int64_t)a * g->n[1] + b) * g->n[2] + c] += m[i] * w / S;
-                }
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1 && !(S > 0.0)) return ORC_EINVAL;
+            for (int32_t a = c0[0]; a <= c1[0]; ++a)
+                for (int32_t b = c0[1]; b <= c1[1]; ++b)
+                    for (int32_t c = c0[2]; c <= c1[2]; ++c) {
+                        double dx, dy, dz;
+                        if (brute) {
+                            dx = axis_offset(g, 0, xi, a);
+                            dy = axis_offset(g, 1, xi, b);
+                            dz = axis_offset(g, 2, xi, c);
+                        } else {
+                            dx = xi[0] - cell_centre(g, 0, a);
+                            dy = xi[1] - cell_centre(g, 1, b);
+                            dz = xi[2] - cell_centre(g, 2, c);
+                        }
+                        double r = sqrt(dx * dx + dy * dy + dz * dz);
+                        double w = orc_m4_w(2.0 * r / H);
+                        if (pass == 0) {
+                            S += w;
+                        } else if (w != 0.0) {
+                            int64_t at = ((int64_t)wrap_cell(g, 0, a) * g->n[1] +
+                                          wrap_cell(g, 1, b)) * g->n[2] + wrap_cell(g, 2, c);
+                            rho[at] += m[i] * w / S;
+                        }
+                    }
+        }
     }
     return ORC_OK;
 }
@@ -895,6 +955,7 @@ int orc_p2m_backward(const double *x, const double *m, const double *h, int64_t 
         const double *xi = x + 3 * i;
         if (!inside_grid(g, xi) || !(h[i] >= 0.0)) return ORC_EINVAL;
         double H = h[i] > g->cell ? h[i] : g->cell;
+        if (!support_ok(g, H)) return ORC_EINVAL;
         int32_t c0[3], c1[3];
         cell_box(g, xi, H, 0, c0, c1);
         double S = 0.0, A = 0.0, B[3] = {0, 0, 0}, C[3] = {0, 0, 0};
@@ -906,7 +967,8 @@ int orc_p2m_backward(const double *x, const double *m, const double *h, int64_t 
                     double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
                     double q = 2.0 * r / H;
                     double w = orc_m4_w(q);
-                    double gc = gg[((int64_t)a * g->n[1] + b) * g->n[2] + c];
+                    double gc = gg[((int64_t)wrap_cell(g, 0, a) * g->n[1] + wrap_cell(g, 1, b)) *
+                                       g->n[2] + wrap_cell(g, 2, c)];
                     S += w;
                     A += gc * w;
                     if (r > 0.0) {
