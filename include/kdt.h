@@ -105,11 +105,15 @@ typedef struct {
 
 /* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side
    `cell`, cell (i,j,k) centred at lo + (i+1/2, j+1/2, k+1/2)*cell, stored with
-   x slowest and z fastest. */
+   x slowest and z fastest.  periodic = 1 makes the mesh box a 3-torus of
+   periods n[a]*cell (the periodic boundaries of Sec. 2.4 applied to the mesh
+   of Sec. 4.2): distances to cell centres take per axis the shorter way
+   round and no support is cut at a face; 0: an open mesh. */
 typedef struct {
     float lo[3];
     float cell;
     int32_t n[3];
+    int32_t periodic;
 } kdt_grid;
 
 /* Shape of a built tree, for diagnostics and the structural tests. */
@@ -294,14 +298,18 @@ kdt_status kdt_fof_torus(const kdt_tree *tree, float l, const float *period, int
  * d_grid [n0*n1*n2] float32: overwritten with the mass per cell.  The sums are
  * accumulated in float64 and rounded once (the float64 summation order
  * follows the scheduling, a difference far below the float32 rounding).
+ * On a periodic mesh (grid->periodic = 1) cells are reached the shorter way
+ * round and nothing is cut at the faces; every H_i must then stay below half
+ * of every period n[a]*cell (KDT_EINVAL otherwise) and n below 2^28.
  * n = 0 writes an all-zero mesh (the particle pointers may then be NULL).
  * The call waits on `stream` once, after the first pass, to read the
  * per-tile particle counts that size its lists (and the validity flag), and
  * again at the end; its buffers come from the stream-ordered pool.
  *
  * Errors: KDT_EINVAL (NULL pointer, bad grid, particle outside the box or an
- * invalid h -- detected on the device), KDT_EUNSUPPORTED (n >= 2^31 or a mesh
- * of more than 2^30 tiles of 16^3 cells), KDT_ENOMEM, KDT_EDEVICE.
+ * invalid h -- detected on the device), KDT_EUNSUPPORTED (n >= 2^31, or
+ * 2^28 on a periodic mesh, or a mesh of more than 2^30 tiles of 16^3 cells),
+ * KDT_ENOMEM, KDT_EDEVICE.
  */
 kdt_status kdt_p2m(const float *d_x, const float *d_m, const float *d_h, int64_t n,
                    const kdt_grid *grid, const int32_t *d_order, float *d_grid,

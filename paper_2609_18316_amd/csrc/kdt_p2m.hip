@@ -6,7 +6,21 @@
 // weights are normalised over the particle's in-grid cells (S_i), so the
 // deposit conserves mass.
 //
+// On a periodic mesh (the periodic boundaries of Sec. 2.4 applied to the
+// mesh) the box is a 3-torus of periods n_a * cell and a cell is reached the
+// shorter way round.  Every H_i is below half of every period, so along each
+// axis a support crosses at most one face: the particle is deposited as up
+// to 8 images (itself, one period away along any subset of the axes whose
+// face its support crosses), each clipped to the mesh like a particle of an
+// open mesh.  An image keeps the particle's own coordinates and moves the
+// cells instead: cell s of the image is measured from the centre of cell
+// s + off (off = -n or +n cells), so no rounding of x + L enters the
+// distances.  S_i sums over all images, so no support is dropped.
+//
 // Forward, as a binned deposit into LDS tiles of 16^3 cells:
+//  0. the particles are gathered once, in visiting order, into compact
+//     arrays (x, y, z, h as one float4, and m), so that every later pass
+//     streams them instead of gathering from the caller's order again;
 //  1. one lane per particle sums S_i over its support, keeps m_i / S_i and
 //     counts, per tile, the particles whose support box overlaps it
 //     (wave-aggregated atomics: the lanes of a wave hold nearby particles);
@@ -41,6 +55,8 @@ struct GridDev {
   float lo[3];
   float cell;
   int32_t n[3];
+  int32_t periodic;  // 1: the mesh box is a 3-torus of periods n[a] * cell
+  float L[3];        // the periods n[a] * cell
 };
 
 __device__ __forceinline__ float m4_w(float q) {
@@ -64,47 +80,103 @@ __device__ __forceinline__ float m4_dw(float q) {
   return 0.0f;
 }
 
-// Cell index range [c0, c1] along one axis whose centres lie within H of x.
-__device__ __forceinline__ void axis_range(float x, float H, float lo, float cell, int n, int& c0,
-                                           int& c1) {
-  const float inv = 1.0f / cell;
-  int a = (int)ceilf((x - H - lo) * inv - 0.5f);
-  int b = (int)floorf((x + H - lo) * inv - 0.5f);
-  c0 = max(a, 0);
-  c1 = min(b, n - 1);
-}
-
+// One image of a particle: its position, H, the cell offset of the image
+// (cell s is measured from the centre of cell s + off; 0 for the particle
+// itself) and its support's cell range clipped to the mesh (c0 > c1 on some
+// axis: no cell).
 struct Particle {
   float x[3];
   float m;
   float H;
+  int off[3];
   int c0[3], c1[3];
   bool ok;
 };
 
-__device__ __forceinline__ void load_particle(const GridDev& g, const float* __restrict__ x,
-                                              const float* __restrict__ m,
-                                              const float* __restrict__ h, int64_t i,
-                                              Particle& p) {
-  p.ok = true;
+// A particle as the gather pass stores it: x, y, z, h; m apart.
+__device__ __forceinline__ float4 load_packed(const float4* __restrict__ P, int64_t t) {
+  return P[t];
+}
+
+// Validity of a particle: inside the mesh box, h finite and >= 0, and on a
+// periodic mesh H below half of every period.
+__device__ __forceinline__ bool particle_ok(const GridDev& g, const float x[3], float h) {
+  bool ok = h >= 0.0f && isfinite(h);
+  const float H = fmaxf(h, g.cell);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    p.x[a] = x[3 * i + a];
-    const float top = g.lo[a] + g.cell * (float)g.n[a];
-    p.ok &= (p.x[a] >= g.lo[a]) && (p.x[a] < top);
+    const float top = g.lo[a] + g.L[a];
+    ok &= (x[a] >= g.lo[a]) && (x[a] < top);
+    if (g.periodic) ok &= 2.0f * H < g.L[a];
   }
-  p.m = m ? m[i] : 0.0f;
-  const float hi = h[i];
-  p.ok &= hi >= 0.0f && isfinite(hi);
-  p.H = fmaxf(hi, g.cell);
+  return ok;
+}
+
+// Per axis, the unclipped cell range [lo_c, hi_c] whose centres can lie
+// within H of x, and the one period offset whose image can reach cells (none
+// if the support crosses no face).
+struct Images {
+  int lo_c[3], hi_c[3];  // unclipped cell range of the support
+  int off[3];            // cell offset of the axis's image: -n, +n, or 0
+  int mask;              // bit a: axis a has an image; images = subsets of mask
+};
+
+__device__ __forceinline__ Images images_of(const GridDev& g, const float x[3], float H) {
+  Images im;
+  im.mask = 0;
+  const float inv = 1.0f / g.cell;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) axis_range(p.x[a], p.H, g.lo[a], g.cell, g.n[a], p.c0[a], p.c1[a]);
+  for (int a = 0; a < 3; ++a) {
+    im.lo_c[a] = (int)ceilf((x[a] - H - g.lo[a]) * inv - 0.5f);
+    im.hi_c[a] = (int)floorf((x[a] + H - g.lo[a]) * inv - 0.5f);
+    im.off[a] = 0;
+    if (!g.periodic) continue;
+    if (im.lo_c[a] < 0) {
+      im.off[a] = -g.n[a];  // cells below the low face, stored one period up
+      im.mask |= 1 << a;
+    } else if (im.hi_c[a] > g.n[a] - 1) {
+      im.off[a] = g.n[a];   // cells above the high face, stored one period down
+      im.mask |= 1 << a;
+    }
+  }
+  return im;
+}
+
+// Image `img` (a subset of im.mask) of the particle at x with smoothing
+// length h: offsets and the clipped cell range (on an open mesh, image 0:
+// the cells whose centres can lie within H, clipped to the mesh).
+__device__ __forceinline__ void make_image(const GridDev& g, const float x[3], float h, float m,
+                                           bool ok, const Images& im, int img, Particle& p) {
+  p.ok = ok;
+  p.m = m;
+  p.H = fmaxf(h, g.cell);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    p.x[a] = x[a];
+    p.off[a] = (img >> a) & 1 ? im.off[a] : 0;
+    p.c0[a] = max(im.lo_c[a] - p.off[a], 0);
+    p.c1[a] = min(im.hi_c[a] - p.off[a], g.n[a] - 1);
+  }
   if (!p.ok) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       p.c0[a] = 0;
       p.c1[a] = -1;
     }
+  }
+}
+
+// Calls f(Particle&, img) for every image of a particle (one on an open
+// mesh or for a support that crosses no face).
+template <typename F>
+__device__ __forceinline__ void for_images(const GridDev& g, const float x[3], float h, float m,
+                                           bool ok, F&& f) {
+  const Images im = images_of(g, x, fmaxf(h, g.cell));
+  for (int img = 0; img < 8; ++img) {
+    if ((img & ~im.mask) != 0) continue;
+    Particle p;
+    make_image(g, x, h, m, ok, im, img, p);
+    f(p, img);
   }
 }
 
@@ -125,18 +197,18 @@ __device__ __forceinline__ void for_cells_in(const GridDev& g, const Particle& p
   const float H2 = p.H * p.H * 1.0002f;
   const float inv = 1.0f / g.cell;
   for (int ix = b0[0]; ix <= b1[0]; ++ix) {
-    const float dx = p.x[0] - (g.lo[0] + ((float)ix + 0.5f) * g.cell);
+    const float dx = p.x[0] - (g.lo[0] + ((float)(ix + p.off[0]) + 0.5f) * g.cell);
     if (dx * dx > H2) continue;
     for (int iy = b0[1]; iy <= b1[1]; ++iy) {
-      const float dy = p.x[1] - (g.lo[1] + ((float)iy + 0.5f) * g.cell);
+      const float dy = p.x[1] - (g.lo[1] + ((float)(iy + p.off[1]) + 0.5f) * g.cell);
       const float dxy = dx * dx + dy * dy;
       if (dxy > H2) continue;
       const float zr = sqrtf(H2 - dxy) + 1e-3f * g.cell;
-      const int z0 = max(b0[2], (int)ceilf((p.x[2] - zr - g.lo[2]) * inv - 0.5f));
-      const int z1 = min(b1[2], (int)floorf((p.x[2] + zr - g.lo[2]) * inv - 0.5f));
+      const int z0 = max(b0[2], (int)ceilf((p.x[2] - zr - g.lo[2]) * inv - 0.5f) - p.off[2]);
+      const int z1 = min(b1[2], (int)floorf((p.x[2] + zr - g.lo[2]) * inv - 0.5f) - p.off[2]);
       const int64_t rowb = ((int64_t)ix * g.n[1] + iy) * g.n[2];
       for (int iz = z0; iz <= z1; ++iz) {
-        const float dz = p.x[2] - (g.lo[2] + ((float)iz + 0.5f) * g.cell);
+        const float dz = p.x[2] - (g.lo[2] + ((float)(iz + p.off[2]) + 0.5f) * g.cell);
         const float r2 = dxy + dz * dz;
         const float r = sqrtf(r2);
         const float q = r * inv2h;
@@ -193,9 +265,9 @@ __device__ __forceinline__ void for_tiles_aggregated(const TileGrid& tg, const i
   }
 }
 
-// Tiles overlapped by a valid particle's support box; false (no tiles) for
-// an invalid particle or an empty box.  The prep and scatter passes decide
-// this identically, so the lists hold exactly the counted entries.
+// Tiles overlapped by one image's support box; false (no tiles) for an
+// invalid particle or an empty box.  The prep and scatter passes decide this
+// identically, so the lists hold exactly the counted entries.
 __device__ __forceinline__ bool tile_range(const Particle& p, int t0[3], int t1[3]) {
   bool has = p.ok;
 #pragma unroll
@@ -207,63 +279,103 @@ __device__ __forceinline__ bool tile_range(const Particle& p, int t0[3], int t1[
   return has;
 }
 
-// Step 1: per particle (visiting position t), f = m / S and the per-tile
-// particle counts.
-__global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
-                                                      const float* __restrict__ x,
-                                                      const float* __restrict__ m,
-                                                      const float* __restrict__ h, int64_t n,
-                                                      const int32_t* __restrict__ order,
-                                                      float* __restrict__ fbuf,
-                                                      uint32_t* __restrict__ tcount,
-                                                      int32_t* __restrict__ bad) {
-  const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
-  int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
-  bool has = false;
-  if (t < n) {
-    const int64_t i = order ? order[t] : t;
-    Particle p;
-    load_particle(g, x, m, h, i, p);
-    if (!p.ok) atomicOr(bad, 1);
-    float S = 0.0f;
-    for_cells(g, p, [&](int64_t, int, int, int, float q, float, float, float, float) {
-      S += m4_w(q);
-    });
-    // a particle inside the mesh has its own cell centre within
-    // sqrt(3)/2 cell <= H, so S > 0
-    has = tile_range(p, t0, t1);
-    fbuf[t] = has ? p.m / S : 0.0f;
-  }
-  for_tiles_aggregated(tg, t0, t1, has, [&](int tile, uint64_t same, int leader, bool) {
-    if (lane_id() == leader) atomicAdd(tcount + tile, (uint32_t)__popcll(same));
-  });
+// Step 0: the particles in visiting order t, packed: P[t] = (x, y, z, h),
+// M[t] = m; the validity flag for any particle outside the box or with an
+// invalid h.
+__global__ __launch_bounds__(kPBlock) void k_p2m_gather(GridDev g, const float* __restrict__ x,
+                                                        const float* __restrict__ m,
+                                                        const float* __restrict__ h, int64_t n,
+                                                        const int32_t* __restrict__ order,
+                                                        float4* __restrict__ P,
+                                                        float* __restrict__ M,
+                                                        int32_t* __restrict__ bad) {
+  const int64_t t = (int64_t)blockIdx.x * kPBlock + threadIdx.x;
+  if (t >= n) return;
+  const int64_t i = order ? order[t] : t;
+  const float xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+  const float hi = h[i];
+  P[t] = make_float4(xi[0], xi[1], xi[2], hi);
+  M[t] = m[i];
+  if (!particle_ok(g, xi, hi)) atomicOr(bad, 1);
 }
 
-// Step 3: every particle appends its visiting position to the lists of the
-// tiles its support box overlaps.
+// Step 1: per particle (visiting position t), f = m / S over all its images
+// and the per-tile entry counts (one per image and overlapped tile).
+__global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
+                                                      const float4* __restrict__ P,
+                                                      const float* __restrict__ M, int64_t n,
+                                                      float* __restrict__ fbuf,
+                                                      uint32_t* __restrict__ tcount) {
+  const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
+  float x[3] = {0.0f, 0.0f, 0.0f}, h = 0.0f, m = 0.0f;
+  bool ok = false;
+  if (t < n) {
+    const float4 v = load_packed(P, t);
+    x[0] = v.x, x[1] = v.y, x[2] = v.z, h = v.w;
+    m = M[t];
+    ok = particle_ok(g, x, h);
+  }
+  // S in float64: a support of 10^5 cells (H near half the mesh) would
+  // drift by 1e-5 in float32
+  double S = 0.0;
+  const Images im = images_of(g, x, fmaxf(h, g.cell));
+  // every lane walks the same image numbers (8 at most), so the tile
+  // aggregation below runs with the whole wave
+  for (int img = 0; img < 8; ++img) {
+    const bool mine = t < n && (img & ~im.mask) == 0;
+    if (!__any(mine)) continue;
+    Particle p;
+    make_image(g, x, h, m, ok && mine, im, img, p);
+    int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
+    bool has = false;
+    if (mine) {
+      for_cells(g, p, [&](int64_t, int, int, int, float q, float, float, float, float) {
+        S += (double)m4_w(q);
+      });
+      has = tile_range(p, t0, t1);
+    }
+    for_tiles_aggregated(tg, t0, t1, has, [&](int tile, uint64_t same, int leader, bool) {
+      if (lane_id() == leader) atomicAdd(tcount + tile, (uint32_t)__popcll(same));
+    });
+  }
+  // a particle inside the mesh has its own cell centre within
+  // sqrt(3)/2 cell <= H, so S > 0
+  if (t < n) fbuf[t] = ok ? (float)((double)m / S) : 0.0f;
+}
+
+// Step 3: every image appends its entry (visiting position, and on a
+// periodic mesh the image in the low three bits) to the lists of the tiles
+// its support box overlaps.
 __global__ __launch_bounds__(kPBlock) void k_p2m_scatter(GridDev g, TileGrid tg,
-                                                         const float* __restrict__ x,
-                                                         const float* __restrict__ h, int64_t n,
-                                                         const int32_t* __restrict__ order,
+                                                         const float4* __restrict__ P, int64_t n,
                                                          const int64_t* __restrict__ toff,
                                                          uint32_t* __restrict__ tfill,
                                                          int32_t* __restrict__ pairs) {
   const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
-  int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
-  bool has = false;
+  float x[3] = {0.0f, 0.0f, 0.0f}, h = 0.0f;
+  bool ok = false;
   if (t < n) {
-    const int64_t i = order ? order[t] : t;
-    Particle p;
-    load_particle(g, x, nullptr, h, i, p);
-    has = tile_range(p, t0, t1);
+    const float4 v = load_packed(P, t);
+    x[0] = v.x, x[1] = v.y, x[2] = v.z, h = v.w;
+    ok = particle_ok(g, x, h);
   }
-  for_tiles_aggregated(tg, t0, t1, has, [&](int tile, uint64_t same, int leader, bool mine) {
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(tfill + tile, (uint32_t)__popcll(same));
-    base = (uint32_t)__shfl((int)base, leader);
-    const int64_t at = toff[tile] + base + lanes_below(same);
-    if (mine && at < toff[tile + 1]) pairs[at] = (int32_t)t;
-  });
+  const Images im = images_of(g, x, fmaxf(h, g.cell));
+  for (int img = 0; img < 8; ++img) {
+    const bool mine = t < n && (img & ~im.mask) == 0;
+    if (!__any(mine)) continue;
+    Particle p;
+    make_image(g, x, h, 0.0f, ok && mine, im, img, p);
+    int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
+    const bool has = mine && tile_range(p, t0, t1);
+    const int32_t code = g.periodic ? (int32_t)(t * 8 + img) : (int32_t)t;
+    for_tiles_aggregated(tg, t0, t1, has, [&](int tile, uint64_t same, int leader, bool on) {
+      uint32_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(tfill + tile, (uint32_t)__popcll(same));
+      base = (uint32_t)__shfl((int)base, leader);
+      const int64_t at = toff[tile] + base + lanes_below(same);
+      if (on && at < toff[tile + 1]) pairs[at] = code;
+    });
+  }
 }
 
 struct DepositChunk {
@@ -272,12 +384,10 @@ struct DepositChunk {
   int64_t begin, end;
 };
 
-// Step 4: one workgroup per chunk of one tile's particle list.
+// Step 4: one workgroup per chunk of one tile's entry list.
 __global__ __launch_bounds__(kPBlock) void k_p2m_tile(GridDev g, TileGrid tg,
-                                                      const float* __restrict__ x,
-                                                      const float* __restrict__ h,
-                                                      const int32_t* __restrict__ order,
-                                                      int64_t n, const float* __restrict__ fbuf,
+                                                      const float4* __restrict__ P, int64_t n,
+                                                      const float* __restrict__ fbuf,
                                                       const int32_t* __restrict__ pairs,
                                                       const DepositChunk* __restrict__ chunks,
                                                       float* __restrict__ mesh,
@@ -292,11 +402,15 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_tile(GridDev g, TileGrid tg,
   for (int c = threadIdx.x; c < kTileCells; c += kPBlock) tile[c] = 0.0;
   __syncthreads();
   for (int64_t e = ck.begin + threadIdx.x; e < ck.end; e += kPBlock) {
-    const int64_t t = pairs[e];
+    const int32_t code = pairs[e];
+    const int64_t t = g.periodic ? (int64_t)((uint32_t)code >> 3) : (int64_t)code;
+    const int img = g.periodic ? (code & 7) : 0;
     if ((uint64_t)t >= (uint64_t)n) continue;
-    const int64_t i = order ? order[t] : t;
+    const float4 v = load_packed(P, t);
+    const float x[3] = {v.x, v.y, v.z};
+    const Images im = images_of(g, x, fmaxf(v.w, g.cell));
     Particle p;
-    load_particle(g, x, nullptr, h, i, p);
+    make_image(g, x, v.w, 0.0f, true, im, img, p);
     const float f = fbuf[t];
     int b0[3], b1[3];
 #pragma unroll
@@ -356,34 +470,37 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_bwd(GridDev g, const float* __r
   const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
   if (t >= n) return;
   const int64_t i = order ? order[t] : t;
-  Particle p;
-  load_particle(g, x, m, h, i, p);
-  if (!p.ok) {
+  const float xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+  const float hi = h[i], mi = m[i];
+  if (!particle_ok(g, xi, hi)) {
     atomicOr(bad, 1);
     return;
   }
-  const float inv2h = 2.0f / p.H;
+  const float inv2h = 2.0f / fmaxf(hi, g.cell);
   double S = 0.0, A = 0.0, B[3] = {0.0, 0.0, 0.0}, C[3] = {0.0, 0.0, 0.0};
-  for_cells(g, p, [&](int64_t cidx, int, int, int, float q, float dx, float dy, float dz, float r) {
-    const float w = m4_w(q);
-    const double gc = (double)gg[cidx];
-    S += (double)w;
-    A += gc * (double)w;
-    if (r > 0.0f) {
-      const float fct = m4_dw(q) * inv2h / r;
-      const double bx = (double)(fct * dx), by = (double)(fct * dy), bz = (double)(fct * dz);
-      B[0] += bx;
-      B[1] += by;
-      B[2] += bz;
-      C[0] += gc * bx;
-      C[1] += gc * by;
-      C[2] += gc * bz;
-    }
+  for_images(g, xi, hi, mi, true, [&](const Particle& p, int) {
+    for_cells(g, p, [&](int64_t cidx, int, int, int, float q, float dx, float dy, float dz,
+                        float r) {
+      const float w = m4_w(q);
+      const double gc = (double)gg[cidx];
+      S += (double)w;
+      A += gc * (double)w;
+      if (r > 0.0f) {
+        const float fct = m4_dw(q) * inv2h / r;
+        const double bx = (double)(fct * dx), by = (double)(fct * dy), bz = (double)(fct * dz);
+        B[0] += bx;
+        B[1] += by;
+        B[2] += bz;
+        C[0] += gc * bx;
+        C[1] += gc * by;
+        C[2] += gc * bz;
+      }
+    });
   });
   const double G = A / S;
   if (gm) gm[i] = (float)G;
   if (gx) {
-    const double f = (double)p.m / S;
+    const double f = (double)mi / S;
 #pragma unroll
     for (int a = 0; a < 3; ++a) gx[3 * i + a] = (float)(f * (C[a] - G * B[a]));
   }
@@ -392,7 +509,7 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_bwd(GridDev g, const float* __r
 static bool grid_ok(const kdt_grid* g) {
   return g && g->cell > 0.0f && std::isfinite(g->cell) && g->n[0] > 0 && g->n[1] > 0 &&
          g->n[2] > 0 && std::isfinite(g->lo[0]) && std::isfinite(g->lo[1]) &&
-         std::isfinite(g->lo[2]);
+         std::isfinite(g->lo[2]) && (g->periodic == 0 || g->periodic == 1);
 }
 
 static GridDev to_dev(const kdt_grid* g) {
@@ -400,8 +517,10 @@ static GridDev to_dev(const kdt_grid* g) {
   for (int a = 0; a < 3; ++a) {
     d.lo[a] = g->lo[a];
     d.n[a] = g->n[a];
+    d.L[a] = g->cell * (float)g->n[a];
   }
   d.cell = g->cell;
+  d.periodic = g->periodic;
   return d;
 }
 
@@ -419,7 +538,8 @@ static kdt_status read_bad_flag(const int32_t* d_bad, hipStream_t stream, const 
     return KDT_EDEVICE;
   }
   if (bad) {
-    kdt_set_error("%s: a particle lies outside the grid or has an invalid smoothing length", who);
+    kdt_set_error("%s: a particle lies outside the grid or has an invalid smoothing length "
+                  "(on a periodic mesh H must stay below half of every period)", who);
     return KDT_EINVAL;
   }
   return KDT_OK;
@@ -442,8 +562,9 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
     kdt_set_error("kdt_p2m: NULL pointer, negative n or invalid grid");
     return KDT_EINVAL;
   }
-  if (n > INT32_MAX) {
-    kdt_set_error("kdt_p2m: n = %lld above 2^31 - 1", (long long)n);
+  if (n > INT32_MAX || (grid->periodic && n >= (int64_t(1) << 28))) {
+    kdt_set_error("kdt_p2m: n = %lld above %s", (long long)n,
+                  grid->periodic ? "2^28 - 1 (periodic mesh)" : "2^31 - 1");
     return KDT_EUNSUPPORTED;
   }
   const GridDev g = to_dev(grid);
@@ -459,9 +580,12 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
   }
   PoolBuffers buf(stream);
   float* fbuf = nullptr;
+  float* M = nullptr;
+  float4* P = nullptr;
   uint32_t* tcount = nullptr;
   int32_t* bad = nullptr;
-  if (!buf.get(&fbuf, (size_t)n) || !buf.get(&tcount, (size_t)n_tiles + 64)) {
+  if (!buf.get(&fbuf, (size_t)n) || !buf.get(&M, (size_t)n) || !buf.get(&P, (size_t)n) ||
+      !buf.get(&tcount, (size_t)n_tiles + 64)) {
     kdt_set_error("kdt_p2m: device allocation failed");
     return KDT_ENOMEM;
   }
@@ -469,8 +593,10 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
   const unsigned gt = (unsigned)((n_tiles + 64 + 255) / 256);
   k_fill_u32<<<gt, 256, 0, stream>>>(tcount, n_tiles + 64, 0u);
   const unsigned gp = (unsigned)((n + kPBlock - 1) / kPBlock);
-  if (n > 0)
-    k_p2m_prep<<<gp, kPBlock, 0, stream>>>(g, tg, d_x, d_m, d_h, n, d_order, fbuf, tcount, bad);
+  if (n > 0) {
+    k_p2m_gather<<<gp, kPBlock, 0, stream>>>(g, d_x, d_m, d_h, n, d_order, P, M, bad);
+    k_p2m_prep<<<gp, kPBlock, 0, stream>>>(g, tg, P, M, n, fbuf, tcount);
+  }
   // the per-tile counts size the lists: read them back (with the check flag)
   std::vector<uint32_t> cnt((size_t)n_tiles + 1);
   hipError_t e = hipMemcpyAsync(cnt.data(), tcount, sizeof(uint32_t) * (n_tiles + 1),
@@ -481,7 +607,8 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
     return KDT_EDEVICE;
   }
   if (cnt[n_tiles] != 0) {
-    kdt_set_error("kdt_p2m: a particle lies outside the grid or has an invalid smoothing length");
+    kdt_set_error("kdt_p2m: a particle lies outside the grid or has an invalid smoothing "
+                  "length (on a periodic mesh H must stay below half of every period)");
     return KDT_EINVAL;
   }
   // lay out the lists and cut them into chunks; tiles of several chunks get
@@ -549,9 +676,9 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
   }
   k_fill_u32<<<gt, 256, 0, stream>>>(tcount, n_tiles, 0u);  // reused as list fill counters
   if (n > 0)
-    k_p2m_scatter<<<gp, kPBlock, 0, stream>>>(g, tg, d_x, d_h, n, d_order, d_toff, tcount, pairs);
-  k_p2m_tile<<<(unsigned)chunks.size(), kPBlock, 0, stream>>>(g, tg, d_x, d_h, d_order, n, fbuf,
-                                                              pairs, d_chunks, d_grid, partial);
+    k_p2m_scatter<<<gp, kPBlock, 0, stream>>>(g, tg, P, n, d_toff, tcount, pairs);
+  k_p2m_tile<<<(unsigned)chunks.size(), kPBlock, 0, stream>>>(g, tg, P, n, fbuf, pairs, d_chunks,
+                                                              d_grid, partial);
   if (!split.empty())
     k_p2m_reduce<<<dim3((unsigned)split.size(), kTileCells / kPBlock), kPBlock, 0, stream>>>(
         g, tg, d_split, partial, d_grid);

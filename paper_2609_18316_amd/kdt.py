@@ -57,7 +57,8 @@ class QueryOpts(C.Structure):
 
 
 class Grid(C.Structure):
-    _fields_ = [("lo", C.c_float * 3), ("cell", C.c_float), ("n", C.c_int32 * 3)]
+    _fields_ = [("lo", C.c_float * 3), ("cell", C.c_float), ("n", C.c_int32 * 3),
+                ("periodic", C.c_int32)]
 
 
 class TreeInfo(C.Structure):
@@ -329,32 +330,35 @@ def build(points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
     return Tree(points, leaf_size, check_finite, stream)
 
 
-def make_grid(lo, cell: float, shape) -> Grid:
+def make_grid(lo, cell: float, shape, periodic: bool = False) -> Grid:
     g = Grid()
     for a in range(3):
         g.lo[a] = float(lo[a])
         g.n[a] = int(shape[a])
     g.cell = float(cell)
+    g.periodic = 1 if periodic else 0
     return g
 
 
 def p2m(x: torch.Tensor, m: torch.Tensor, h: torch.Tensor, lo, cell: float, shape,
-        order_ptr: int | None = None, out: torch.Tensor | None = None, stream=None):
-    """Adaptive SPH deposit: float32 mass per cell, shape ``shape``."""
+        order_ptr: int | None = None, out: torch.Tensor | None = None, stream=None,
+        periodic: bool = False):
+    """Adaptive SPH deposit: float32 mass per cell, shape ``shape``.
+    ``periodic``: the mesh box is a 3-torus (every H below half a period)."""
     n = x.shape[0]
     x = _dev(x, torch.float32, "x", (n, 3))
     m = _dev(m, torch.float32, "m", (n,))
     h = _dev(h, torch.float32, "h", (n,))
     if out is None:
         out = torch.empty(tuple(shape), dtype=torch.float32, device=x.device)
-    g = make_grid(lo, cell, shape)
+    g = make_grid(lo, cell, shape, periodic)
     _check(load().kdt_p2m(_ptr(x), _ptr(m), _ptr(h), n, C.byref(g), order_ptr, _ptr(out),
                           _stream(stream)))
     return out
 
 
 def p2m_backward(x, m, h, lo, cell, shape, grad, order_ptr=None, need_m=True, need_x=True,
-                 stream=None):
+                 stream=None, periodic: bool = False):
     """(dL/dm, dL/dx) of L = sum(grad * p2m(x, m, h)), h held fixed."""
     n = x.shape[0]
     x = _dev(x, torch.float32, "x", (n, 3))
@@ -363,7 +367,7 @@ def p2m_backward(x, m, h, lo, cell, shape, grad, order_ptr=None, need_m=True, ne
     grad = _dev(grad.contiguous(), torch.float32, "grad")
     gm = torch.empty(n, dtype=torch.float32, device=x.device) if need_m else None
     gx = torch.empty((n, 3), dtype=torch.float32, device=x.device) if need_x else None
-    g = make_grid(lo, cell, shape)
+    g = make_grid(lo, cell, shape, periodic)
     _check(load().kdt_p2m_backward(_ptr(x), _ptr(m), _ptr(h), n, C.byref(g), order_ptr,
                                    _ptr(grad), _ptr(gm), _ptr(gx), _stream(stream)))
     return gm, gx
@@ -374,18 +378,21 @@ class P2M(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, m, h, grid):
-        lo, cell, shape, order_ptr = grid
+        """grid: (lo, cell, shape, order_ptr) or (lo, cell, shape, order_ptr, periodic)."""
+        lo, cell, shape, order_ptr = grid[:4]
+        periodic = bool(grid[4]) if len(grid) > 4 else False
         ctx.save_for_backward(x, m, h)
-        ctx.grid = grid
-        return p2m(x.detach(), m.detach(), h.detach(), lo, cell, shape, order_ptr)
+        ctx.grid = (lo, cell, shape, order_ptr, periodic)
+        return p2m(x.detach(), m.detach(), h.detach(), lo, cell, shape, order_ptr,
+                   periodic=periodic)
 
     @staticmethod
     def backward(ctx, g):
         x, m, h = ctx.saved_tensors
-        lo, cell, shape, order_ptr = ctx.grid
+        lo, cell, shape, order_ptr, periodic = ctx.grid
         gm, gx = p2m_backward(x.detach(), m.detach(), h.detach(), lo, cell, shape, g,
                               order_ptr, need_m=ctx.needs_input_grad[1],
-                              need_x=ctx.needs_input_grad[0])
+                              need_x=ctx.needs_input_grad[0], periodic=periodic)
         return gx, gm, None, None
 
 

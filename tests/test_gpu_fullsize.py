@@ -141,6 +141,53 @@ def test_deposit_full_size_subvolume_and_adjoint_sample(clustered):
     assert np.linalg.norm(gx_s - ox) <= 1e-4 * np.linalg.norm(ox)
 
 
+def test_periodic_deposit_full_size_corner_and_faces(clustered):
+    """The 256^3 deposit on the periodic mesh: sub-volumes at a corner and on
+    faces, where supports wrap, against the oracle over the particles within
+    reach the shorter way round; total mass exact; the adjoint on a sample."""
+    x, q, xt, qt, tree, ot = clustered
+    g = 256
+    cell = 1.0 / g
+    m = workloads.masses(N, seed=5)
+    mt = to_dev(m)
+    h = tree.knn(None, 32, kth_only=2)
+    say("periodic P2M forward 2^24 particles on 256^3")
+    rho = to_host(kdt.p2m(xt, mt, h, (0, 0, 0), cell, (g, g, g), order_ptr=tree.perm_ptr,
+                          periodic=True))
+    hh = to_host(h)
+    total = float(m.astype(np.float64).sum())
+    assert abs(float(rho.astype(np.float64).sum()) - total) <= 1e-5 * total
+    mean = total / rho.size
+    H = np.maximum(hh, np.float32(cell)).astype(np.float64)
+    for lo_c in ((0, 0, 0), (248, 120, 0), (250, 250, 250), (7, 255, 100)):
+        lo = np.array(lo_c) * cell
+        hi = (np.array(lo_c) + 16) * cell
+        gap = np.zeros_like(x, dtype=np.float64)
+        for a in range(3):  # distance to the slab [lo, hi), the shorter way round
+            d = np.maximum(np.maximum(lo[a] - x[:, a], x[:, a] - hi[a]), 0.0)
+            d = np.minimum(d, np.maximum(np.maximum(lo[a] - (x[:, a] - 1.0), (x[:, a] - 1.0) - hi[a]), 0.0))
+            d = np.minimum(d, np.maximum(np.maximum(lo[a] - (x[:, a] + 1.0), (x[:, a] + 1.0) - hi[a]), 0.0))
+            gap[:, a] = d
+        sel = np.nonzero(np.all(gap < H[:, None] + cell, axis=1))[0]
+        say(f"oracle periodic deposit of {len(sel)} particles around cells {lo_c}")
+        o = oracle.p2m(x[sel], m[sel], hh[sel], (0, 0, 0), cell, (g, g, g), periodic=True)
+        cx = [np.arange(c, c + 16) % g for c in lo_c]
+        og = o[np.ix_(*cx)]
+        gg = rho[np.ix_(*cx)].astype(np.float64)
+        assert (np.abs(gg - og) <= 1e-5 * np.maximum(np.abs(og), mean)).all()
+    say("periodic P2M adjoint 2^24 particles")
+    gen = torch.Generator(device=xt.device).manual_seed(13)
+    up = torch.randn((g, g, g), device=xt.device, generator=gen)
+    gm, gx = kdt.p2m_backward(xt, mt, h, (0, 0, 0), cell, (g, g, g), up, order_ptr=tree.perm_ptr,
+                              periodic=True)
+    s = workloads.sample_indices(N, 2048, seed=14)
+    om, ox = oracle.p2m_backward(x[s], m[s], hh[s], (0, 0, 0), cell, (g, g, g), to_host(up),
+                                 periodic=True)
+    gm_s, gx_s = to_host(gm)[s].astype(np.float64), to_host(gx)[s].astype(np.float64)
+    assert (np.abs(gm_s - om) <= 1e-5 * np.maximum(np.abs(om), np.abs(om).mean())).all()
+    assert np.linalg.norm(gx_s - ox) <= 1e-4 * np.linalg.norm(ox)
+
+
 @pytest.mark.parametrize("d", (2, 4, 8, 16))
 @pytest.mark.parametrize("dist", ("uniform", "normal"))
 def test_dimension_sweep_full_size_sampled(d, dist):

@@ -92,3 +92,95 @@ def test_rejects_particle_outside_grid():
         kdt.p2m(to_dev(x), to_dev(np.ones(1, np.float32)), to_dev(np.ones(1, np.float32) * 0.1),
                 (0, 0, 0), 1.0 / 16, (16, 16, 16))
     assert e.value.status == kdt.KDT_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# periodic mesh: the box is a 3-torus of periods n_a * cell
+# ---------------------------------------------------------------------------
+
+def _periodic_setup(n, shape, cell, seed):
+    """Clustered points scaled into the box of `shape` cells, h = distance to
+    the 32nd neighbour (capped below half the smallest period)."""
+    L = np.array(shape, np.float64) * cell
+    x = (workloads.clustered(n, seed).astype(np.float64) * L).astype(np.float32)
+    x = np.minimum(x, np.nextafter(L.astype(np.float32), 0))
+    m = workloads.masses(n, seed + 1)
+    t = kdt.build(to_dev(x))
+    h = t.knn(None, min(32, n), kth_only=2)
+    h = torch.clamp(h, max=float(0.45 * L.min()))
+    return x, m, t, h
+
+
+SHAPES = [((16, 16, 16), 1.0 / 16), ((32, 24, 40), 1.0 / 32), ((64, 64, 64), 1.0 / 64)]
+
+
+@pytest.mark.parametrize("n,shape,cell", [(n,) + sc for n in (1, 777, 20000) for sc in SHAPES]
+                         + [(300000,) + SHAPES[2]])
+def test_periodic_forward_matches_float64_oracle(n, shape, cell):
+    dev()
+    say(f"periodic p2m forward n={n} shape={shape}")
+    x, m, t, h = _periodic_setup(n, shape, cell, seed=400 + n)
+    lo = (0.0, 0.0, 0.0)
+    o = oracle.p2m(x, m, to_host(h), lo, cell, shape, periodic=True)
+    g = kdt.p2m(to_dev(x), to_dev(m), h, lo, cell, shape, order_ptr=t.perm_ptr, periodic=True)
+    _close_rho(to_host(g), o, float(m.astype(np.float64).sum()))
+    g2 = kdt.p2m(to_dev(x), to_dev(m), h, lo, cell, shape, periodic=True)  # input order
+    _close_rho(to_host(g2), o, float(m.astype(np.float64).sum()))
+
+
+@pytest.mark.parametrize("shape,cell", SHAPES[:2])
+def test_periodic_backward_matches_float64_oracle(shape, cell):
+    dev()
+    n = 20000
+    say(f"periodic p2m backward n={n} shape={shape}")
+    x, m, t, h = _periodic_setup(n, shape, cell, seed=500)
+    lo = (0.0, 0.0, 0.0)
+    rng = np.random.Generator(np.random.PCG64(9))
+    g = rng.standard_normal(shape).astype(np.float32)
+    gm, gx = kdt.p2m_backward(to_dev(x), to_dev(m), h, lo, cell, shape, to_dev(g),
+                              order_ptr=t.perm_ptr, periodic=True)
+    om, ox = oracle.p2m_backward(x, m, to_host(h), lo, cell, shape, g, periodic=True)
+    gm, gx = to_host(gm).astype(np.float64), to_host(gx).astype(np.float64)
+    scale = np.abs(om).mean()
+    assert (np.abs(gm - om) <= 1e-5 * np.maximum(np.abs(om), scale)).all()
+    assert np.linalg.norm(gx - ox) <= 1e-4 * np.linalg.norm(ox)
+
+
+def test_periodic_autograd_identities():
+    """On the torus nothing is cut at a face: a constant upstream gradient
+    gives dm = 1 and no force on any particle."""
+    dev()
+    shape, cell = (32, 24, 40), 1.0 / 32
+    x, m, t, h = _periodic_setup(5000, shape, cell, seed=600)
+    grid = ((0.0, 0.0, 0.0), cell, shape, t.perm_ptr, True)
+    xt = to_dev(x).requires_grad_(True)
+    mt = to_dev(m).requires_grad_(True)
+    rho = kdt.P2M.apply(xt, mt, h, grid)
+    assert abs(float(rho.double().sum()) - float(m.astype(np.float64).sum())) <= 1e-5 * m.sum()
+    gg = torch.randn(shape, device=xt.device, generator=torch.Generator(xt.device).manual_seed(4))
+    (rho * gg).sum().backward()
+    lhs = float((gg.double() * rho.double()).sum())
+    rhs = float((mt.grad.double() * mt.double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    xt.grad = None
+    mt.grad = None
+    rho = kdt.P2M.apply(xt, mt, h, grid)
+    rho.sum().backward()
+    np.testing.assert_allclose(to_host(mt.grad), 1.0, rtol=1e-5)
+    assert float(xt.grad.abs().max()) < 1e-3 * float(mt.detach().max()) * max(shape)
+
+
+def test_periodic_rejects_support_of_half_a_period():
+    dev()
+    shape, cell = (16, 12, 20), 1.0 / 16
+    x = np.array([[0.5, 0.3, 0.6]], np.float32)
+    m = np.ones(1, np.float32)
+    for call in (lambda h: kdt.p2m(to_dev(x), to_dev(m), to_dev(h), (0, 0, 0), cell, shape,
+                                   periodic=True),
+                 lambda h: kdt.p2m_backward(to_dev(x), to_dev(m), to_dev(h), (0, 0, 0), cell,
+                                            shape, torch.ones(shape, device=dev()),
+                                            periodic=True)):
+        with pytest.raises(kdt.KdtError) as e:
+            call(np.array([0.5 * 12 * cell], np.float32))
+        assert e.value.status == kdt.KDT_EINVAL
+        call(np.array([0.49 * 12 * cell], np.float32))
