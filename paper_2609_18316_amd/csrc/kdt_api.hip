@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <list>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -28,6 +30,46 @@ void kdt_clear_error() { g_error.clear(); }
 extern "C" const char* kdt_last_error(void) { return g_error.c_str(); }
 
 namespace kdt {
+
+namespace {
+struct ScratchKey {
+  int device;
+  hipStream_t stream;
+  int slot;
+  bool operator<(const ScratchKey& o) const {
+    if (device != o.device) return device < o.device;
+    if (stream != o.stream) return stream < o.stream;
+    return slot < o.slot;
+  }
+};
+struct ScratchBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_scratch_mu;
+// never destroyed: device memory is not released from static destructors
+std::map<ScratchKey, ScratchBuf>* g_scratch = new std::map<ScratchKey, ScratchBuf>();
+}  // namespace
+
+void* stream_scratch(hipStream_t stream, int slot, size_t bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  ScratchBuf& b = (*g_scratch)[ScratchKey{dev, stream, slot}];
+  if (b.ptr && b.bytes >= bytes) return b.ptr;
+  if (b.ptr) (void)hipFreeAsync(b.ptr, stream);
+  b.ptr = nullptr;
+  b.bytes = 0;
+  // grow by a quarter beyond the request, so slowly growing calls settle
+  const size_t want = std::max<size_t>(256, bytes + bytes / 4);
+  if (dev_alloc(&b.ptr, want, stream) != hipSuccess) {
+    b.ptr = nullptr;
+    return nullptr;
+  }
+  b.bytes = want;
+  return b.ptr;
+}
+
 
 // Build schedules depend only on (device, n, d, leaf); repeated builds of the
 // same shape reuse the uploaded tables.

@@ -213,6 +213,16 @@ kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
 // Stream-ordered device allocation from the default pool (kept cached).
 hipError_t dev_alloc(void** ptr, size_t bytes, hipStream_t stream);
 
+// Scratch that an entry point keeps on its stream from one call to the next:
+// slot `slot` of (current device, stream) holds at least `bytes` bytes,
+// grown (stream-ordered free and allocation) when a call needs more, never
+// shrunk, held until the process ends.  The deposit uses it: its host part
+// waits on the stream anyway, and freeing its large buffers back to the
+// pool on every call cost milliseconds of host time.  Calls that share a
+// stream must not run their host parts concurrently (they already share the
+// stream's order).  NULL if the allocation fails.
+void* stream_scratch(hipStream_t stream, int slot, size_t bytes);
+
 // Stream-ordered scratch buffers of one call, released in stream order when
 // the holder goes out of scope -- on every return path, errors included.
 class PoolBuffers {
@@ -220,9 +230,17 @@ class PoolBuffers {
   explicit PoolBuffers(hipStream_t s) : stream_(s) {}
   PoolBuffers(const PoolBuffers&) = delete;
   PoolBuffers& operator=(const PoolBuffers&) = delete;
-  ~PoolBuffers() {
-    for (void* q : held_)
-      if (q) (void)hipFreeAsync(q, stream_);
+  ~PoolBuffers() { release(); }
+  // Returns every held buffer to the pool now, in stream order (work queued
+  // before this call still sees them).  A call that waits on its stream at
+  // the end releases first: a free can block the host for milliseconds, and
+  // queued behind the stream's work it costs no GPU time.
+  void release() {
+    for (void*& q : held_)
+      if (q) {
+        (void)hipFreeAsync(q, stream_);
+        q = nullptr;
+      }
   }
   // count elements of T (at least one); false if the pool is exhausted
   template <typename T>

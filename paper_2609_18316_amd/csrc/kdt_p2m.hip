@@ -18,12 +18,12 @@
 // distances.  S_i sums over all images, so no support is dropped.
 //
 // Forward, as a binned deposit into LDS tiles of 16^3 cells:
-//  0. the particles are gathered once, in visiting order, into compact
-//     arrays (x, y, z, h as one float4, and m), so that every later pass
-//     streams them instead of gathering from the caller's order again;
-//  1. one lane per particle sums S_i over its support, keeps m_i / S_i and
-//     counts, per tile, the particles whose support box overlaps it
-//     (wave-aggregated atomics: the lanes of a wave hold nearby particles);
+//  1. one lane per particle (in visiting order) gathers it from the caller's
+//     arrays, stores it packed for the later passes (x, y, z, h as one
+//     float4, and m), sums S_i over its support, keeps m_i / S_i and counts,
+//     per tile, the particles whose support box overlaps it (wave-aggregated
+//     atomics: the lanes of a wave hold nearby particles); the later passes
+//     stream the packed copy instead of gathering again;
 //  2. the host reads the per-tile counts, lays out the (tile, particle) lists
 //     and cuts them into chunks of at most kChunk particles;
 //  3. the particles are scattered into their tiles' lists;
@@ -50,6 +50,11 @@ constexpr int kPBlock = 256;
 constexpr int kT = 16;                      // tile edge in cells
 constexpr int kTileCells = kT * kT * kT;    // float64 LDS tile: 32 KiB
 constexpr int64_t kChunk = 4096;            // particles per deposit work item
+
+// Scratch slots the deposit keeps on its stream between calls.
+enum : int { kSlotParticles = 100, kSlotLists = 101, kSlotPartial = 102, kSlotFlag = 103 };
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct GridDev {
   float lo[3];
@@ -279,41 +284,33 @@ __device__ __forceinline__ bool tile_range(const Particle& p, int t0[3], int t1[
   return has;
 }
 
-// Step 0: the particles in visiting order t, packed: P[t] = (x, y, z, h),
-// M[t] = m; the validity flag for any particle outside the box or with an
-// invalid h.
-__global__ __launch_bounds__(kPBlock) void k_p2m_gather(GridDev g, const float* __restrict__ x,
-                                                        const float* __restrict__ m,
-                                                        const float* __restrict__ h, int64_t n,
-                                                        const int32_t* __restrict__ order,
-                                                        float4* __restrict__ P,
-                                                        float* __restrict__ M,
-                                                        int32_t* __restrict__ bad) {
-  const int64_t t = (int64_t)blockIdx.x * kPBlock + threadIdx.x;
-  if (t >= n) return;
-  const int64_t i = order ? order[t] : t;
-  const float xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
-  const float hi = h[i];
-  P[t] = make_float4(xi[0], xi[1], xi[2], hi);
-  M[t] = m[i];
-  if (!particle_ok(g, xi, hi)) atomicOr(bad, 1);
-}
-
-// Step 1: per particle (visiting position t), f = m / S over all its images
-// and the per-tile entry counts (one per image and overlapped tile).
+// Step 1: per particle (visiting position t): gathered from the caller's
+// arrays and stored packed, P[t] = (x, y, z, h), M[t] = m; f = m / S over
+// all its images; the per-tile entry counts (one per image and overlapped
+// tile); the validity flag for a particle outside the box or with an invalid
+// h.  The gather's scattered reads overlap the support sums.
 __global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
-                                                      const float4* __restrict__ P,
-                                                      const float* __restrict__ M, int64_t n,
+                                                      const float* __restrict__ xin,
+                                                      const float* __restrict__ min_,
+                                                      const float* __restrict__ hin, int64_t n,
+                                                      const int32_t* __restrict__ order,
+                                                      float4* __restrict__ P,
+                                                      float* __restrict__ M,
                                                       float* __restrict__ fbuf,
-                                                      uint32_t* __restrict__ tcount) {
+                                                      uint32_t* __restrict__ tcount,
+                                                      int32_t* __restrict__ bad) {
   const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
   float x[3] = {0.0f, 0.0f, 0.0f}, h = 0.0f, m = 0.0f;
   bool ok = false;
   if (t < n) {
-    const float4 v = load_packed(P, t);
-    x[0] = v.x, x[1] = v.y, x[2] = v.z, h = v.w;
-    m = M[t];
+    const int64_t i = order ? order[t] : t;
+    x[0] = xin[3 * i], x[1] = xin[3 * i + 1], x[2] = xin[3 * i + 2];
+    h = hin[i];
+    m = min_[i];
+    P[t] = make_float4(x[0], x[1], x[2], h);
+    M[t] = m;
     ok = particle_ok(g, x, h);
+    if (!ok) atomicOr(bad, 1);
   }
   // S in float64: a support of 10^5 cells (H near half the mesh) would
   // drift by 1e-5 in float32
@@ -528,7 +525,8 @@ static GridDev to_dev(const kdt_grid* g) {
 
 using namespace kdt;
 
-// Waits for the stream and reports the device-side validity flag.
+// Reads the device-side validity flag back, waits for the stream and
+// reports the flag.
 static kdt_status read_bad_flag(const int32_t* d_bad, hipStream_t stream, const char* who) {
   int32_t bad = 0;
   hipError_t e = hipMemcpyAsync(&bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, stream);
@@ -578,25 +576,28 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
     kdt_set_error("kdt_p2m: mesh too large (%lld tiles of %d^3 cells)", (long long)n_tiles, kT);
     return KDT_EUNSUPPORTED;
   }
-  PoolBuffers buf(stream);
-  float* fbuf = nullptr;
-  float* M = nullptr;
-  float4* P = nullptr;
-  uint32_t* tcount = nullptr;
-  int32_t* bad = nullptr;
-  if (!buf.get(&fbuf, (size_t)n) || !buf.get(&M, (size_t)n) || !buf.get(&P, (size_t)n) ||
-      !buf.get(&tcount, (size_t)n_tiles + 64)) {
+  // scratch kept on the stream between calls: the packed particles, m / S
+  // and the tile counters (+ the validity flag) in one slot; the lists and
+  // chunk tables in a second; float64 partial tiles in a third
+  const size_t a_p = align256(sizeof(float4) * (size_t)n);
+  const size_t a_n = align256(sizeof(float) * (size_t)n);
+  const size_t a_t = align256(sizeof(uint32_t) * ((size_t)n_tiles + 64));
+  char* s0 = static_cast<char*>(stream_scratch(stream, kSlotParticles, a_p + 2 * a_n + a_t));
+  if (!s0) {
     kdt_set_error("kdt_p2m: device allocation failed");
     return KDT_ENOMEM;
   }
-  bad = reinterpret_cast<int32_t*>(tcount + n_tiles);
+  float4* P = reinterpret_cast<float4*>(s0);
+  float* M = reinterpret_cast<float*>(s0 + a_p);
+  float* fbuf = reinterpret_cast<float*>(s0 + a_p + a_n);
+  uint32_t* tcount = reinterpret_cast<uint32_t*>(s0 + a_p + 2 * a_n);
+  int32_t* bad = reinterpret_cast<int32_t*>(tcount + n_tiles);
   const unsigned gt = (unsigned)((n_tiles + 64 + 255) / 256);
   k_fill_u32<<<gt, 256, 0, stream>>>(tcount, n_tiles + 64, 0u);
   const unsigned gp = (unsigned)((n + kPBlock - 1) / kPBlock);
-  if (n > 0) {
-    k_p2m_gather<<<gp, kPBlock, 0, stream>>>(g, d_x, d_m, d_h, n, d_order, P, M, bad);
-    k_p2m_prep<<<gp, kPBlock, 0, stream>>>(g, tg, P, M, n, fbuf, tcount);
-  }
+  if (n > 0)
+    k_p2m_prep<<<gp, kPBlock, 0, stream>>>(g, tg, d_x, d_m, d_h, n, d_order, P, M, fbuf, tcount,
+                                           bad);
   // the per-tile counts size the lists: read them back (with the check flag)
   std::vector<uint32_t> cnt((size_t)n_tiles + 1);
   hipError_t e = hipMemcpyAsync(cnt.data(), tcount, sizeof(uint32_t) * (n_tiles + 1),
@@ -651,17 +652,22 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
   std::stable_sort(chunks.begin(), chunks.end(), [](const DepositChunk& a, const DepositChunk& b) {
     return a.end - a.begin > b.end - b.begin;
   });
-  int32_t* pairs = nullptr;
-  int64_t* d_toff = nullptr;
-  DepositChunk* d_chunks = nullptr;
-  SplitTile* d_split = nullptr;
-  double* partial = nullptr;
-  if (!buf.get(&pairs, (size_t)total) || !buf.get(&d_toff, (size_t)n_tiles + 1) ||
-      !buf.get(&d_chunks, chunks.size()) || !buf.get(&d_split, split.size()) ||
-      !buf.get(&partial, (size_t)slots * kTileCells)) {
+  const size_t a_pairs = align256(sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1));
+  const size_t a_toff = align256(sizeof(int64_t) * ((size_t)n_tiles + 1));
+  const size_t a_chunks = align256(sizeof(DepositChunk) * std::max<size_t>(chunks.size(), 1));
+  const size_t a_split = align256(sizeof(SplitTile) * std::max<size_t>(split.size(), 1));
+  char* s1 = static_cast<char*>(
+      stream_scratch(stream, kSlotLists, a_pairs + a_toff + a_chunks + a_split));
+  double* partial = static_cast<double*>(
+      stream_scratch(stream, kSlotPartial, sizeof(double) * kTileCells * std::max(slots, 1)));
+  if (!s1 || !partial) {
     kdt_set_error("kdt_p2m: device allocation failed (%lld particle-tile pairs)", (long long)total);
     return KDT_ENOMEM;
   }
+  int32_t* pairs = reinterpret_cast<int32_t*>(s1);
+  int64_t* d_toff = reinterpret_cast<int64_t*>(s1 + a_pairs);
+  DepositChunk* d_chunks = reinterpret_cast<DepositChunk*>(s1 + a_pairs + a_toff);
+  SplitTile* d_split = reinterpret_cast<SplitTile*>(s1 + a_pairs + a_toff + a_chunks);
   e = hipMemcpyAsync(d_toff, toff.data(), sizeof(int64_t) * (n_tiles + 1), hipMemcpyHostToDevice,
                      stream);
   if (e == hipSuccess)
@@ -705,9 +711,8 @@ extern "C" kdt_status kdt_p2m_backward(const float* d_x, const float* d_m, const
     return KDT_EINVAL;
   }
   if (n == 0 || (!d_gm && !d_gx)) return KDT_OK;
-  PoolBuffers buf(stream);
-  int32_t* bad = nullptr;
-  if (!buf.get(&bad, 64)) {
+  int32_t* bad = static_cast<int32_t*>(stream_scratch(stream, kSlotFlag, 256));
+  if (!bad) {
     kdt_set_error("kdt_p2m_backward: allocation failed");
     return KDT_ENOMEM;
   }
