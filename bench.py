@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-box", action="store_true")
     ap.add_argument("--no-large-k", action="store_true")
     ap.add_argument("--no-torus", action="store_true")
+    ap.add_argument("--no-midpoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of 1 GiB (read once, written once), the "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -412,6 +413,49 @@ def main():
             out["torus"][name + "_ms"] = float(min(reps))
         out["torus"]["knn_queries_s"] = N_QUERIES / (out["torus"]["knn_ms"] * 1e-3)
         tree.close()
+    if not args.no_midpoint:
+        # The paper's sliding-midpoint split rule (outside the timed step):
+        # build, kNN k = 32 of the 2^22 queries and r = 0.01 counts on that
+        # tree, best of three calls each, beside the median tree of the step.
+        def timed(call, reps=3):
+            r = call()
+            del r
+            torch.cuda.synchronize()
+            best = None
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                r = call()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                best = ms if best is None else min(best, ms)
+                del r
+            return best
+        b_ms = timed(lambda: kdt.build(xt, leaf_size=LEAF, check_finite=False,
+                                       split_rule=kdt.SPLIT_MIDPOINT))
+        mtree = kdt.build(xt, leaf_size=LEAF, split_rule=kdt.SPLIT_MIDPOINT)
+        k_ms = timed(lambda: mtree.knn(qt, K))
+        r_ms = timed(lambda: mtree.range(qt, RADIUS))
+        out["midpoint"] = {"leaf_size": LEAF, "depth": mtree.info.levels,
+                           "n_nodes": mtree.info.n_nodes, "build_ms": b_ms,
+                           "build_mpts_s": N_POINTS / (b_ms * 1e-3) / 1e6, "knn_ms": k_ms,
+                           "knn_queries_s": N_QUERIES / (k_ms * 1e-3), "range_ms": r_ms,
+                           "range_queries_s": N_QUERIES / (r_ms * 1e-3),
+                           "median_tree": {"build_ms": avg["build"],
+                                           "knn_ms": avg["knn_order"] + avg["knn"],
+                                           "range_ms": avg["range"]}}
+        mtree.close()
+        # the like-for-like comparison: the median tree with one traversal per
+        # lane for the counts as well (the sliding-midpoint tree has no
+        # wave-shared count)
+        mt2 = kdt.build(xt, leaf_size=LEAF)
+        out["midpoint"]["median_tree"]["range_lane_ms"] = timed(
+            lambda: mt2.range(qt, RADIUS, traversal=1))
+        mt2.close()
+        print(f"[bench] sliding midpoint: build {b_ms:.2f} ms, kNN {k_ms:.2f} ms, "
+              f"counts {r_ms:.2f} ms", file=sys.stderr, flush=True)
     if not args.no_dsweep:
         out["dsweep"] = dimension_sweep(torch, kdt, workloads, dev)
     if not args.no_cpu_baseline:

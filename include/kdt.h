@@ -63,6 +63,21 @@ typedef struct {
     int32_t check_finite; /* 1 (default when opts is NULL): kdt_build waits for its
                              first pass and rejects NaN/Inf coordinates with
                              KDT_EINVAL.  0: no wait, no check. */
+    int32_t split_rule;   /* 0 (default): balanced median splits (see kdt_build).
+                             1: the paper's sliding-midpoint rule (Sec. 2.1,
+                             Algorithm 1): split the longest side of the
+                             node's tight box at its midpoint, sliding to the
+                             nearest point when a side would be empty.  The
+                             depth then depends on the data (at most 96
+                             levels, KDT_EUNSUPPORTED beyond) and the build
+                             waits on its stream once per level.  Such a tree
+                             answers kdt_knn (k <= KDT_MAX_K, open
+                             boundaries; one traversal per lane),
+                             kdt_knn_noalloc, kdt_range (open boundaries;
+                             one traversal per lane), kdt_fof and
+                             kdt_query_order; kdt_box, kdt_fof_torus, larger
+                             k and periods return KDT_EUNSUPPORTED.  Results
+                             are the same as on a median tree. */
 } kdt_build_opts;
 
 typedef struct {
@@ -160,12 +175,24 @@ kdt_status kdt_tree_get_info(const kdt_tree *tree, kdt_tree_info *info);
 /*
  * Copies the tree to host memory for inspection (waits on `stream`).
  * h_pts [n][d] tree-ordered positions, h_perm [n] original index of each,
- * h_lo / h_hi [n_nodes][d] tight bounding box of each node in heap order
- * (node (l, j) at 2^l - 1 + j), h_axis [n_nodes] split axis (-1 for leaves),
- * h_split [n_nodes] split coordinate.  Any pointer may be NULL.
+ * h_lo / h_hi [n_nodes][d] tight bounding box of each node in the numbering
+ * of kdt_tree_nodes (heap order, node (l, j) at 2^l - 1 + j, for a median
+ * tree), h_axis [n_nodes] split axis (-1 for leaves), h_split [n_nodes] split
+ * coordinate (after any slide).  Any pointer may be NULL.
  */
 kdt_status kdt_tree_export(const kdt_tree *tree, float *h_pts, int32_t *h_perm, float *h_lo,
                            float *h_hi, int32_t *h_axis, float *h_split, hipStream_t stream);
+
+/*
+ * Copies the node records to host memory (waits on `stream`): for each of
+ * the n_nodes nodes, h_left the left child (-1 for a leaf; the right child is
+ * h_left + 1), [h_begin, h_end) its points in tree order, h_level its depth.
+ * Median trees report their implicit layout (node (l, j) at 2^l - 1 + j);
+ * sliding-midpoint trees number their nodes level by level.  Any pointer may
+ * be NULL.
+ */
+kdt_status kdt_tree_nodes(const kdt_tree *tree, int32_t *h_left, int32_t *h_begin,
+                          int32_t *h_end, int32_t *h_level, hipStream_t stream);
 
 /*
  * kdt_knn -- k nearest neighbours of nq query points (Sec. 2.3, Algorithm 2).

@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "kdt_internal.h"
 
@@ -147,19 +148,45 @@ extern "C" kdt_status kdt_build(const float* d_pts, int64_t n, int32_t d,
     kdt_set_error("kdt_build: dimension %d is not one of 2, 3, 4, 8, 16", d);
     return KDT_EUNSUPPORTED;
   }
-  int leaf = 32, check = 1;
+  int leaf = 32, check = 1, rule = 0;
   if (opts) {
     if (opts->leaf_size) leaf = opts->leaf_size;
     check = opts->check_finite;
+    rule = opts->split_rule;
   }
   if (leaf < 2 || leaf > 256) {
     kdt_set_error("kdt_build: leaf_size %d outside [2, 256]", leaf);
+    return KDT_EINVAL;
+  }
+  if (rule != 0 && rule != 1) {
+    kdt_set_error("kdt_build: split_rule %d is not 0 (median) or 1 (sliding midpoint)", rule);
     return KDT_EINVAL;
   }
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) {
     kdt_set_error("kdt_build: no HIP device");
     return KDT_EDEVICE;
+  }
+  if (rule == 1) {
+    kdt_tree* t = new (std::nothrow) kdt_tree();
+    if (!t) {
+      kdt_set_error("kdt_build: out of host memory");
+      return KDT_ENOMEM;
+    }
+    t->device = device;
+    t->stream = stream;
+    t->n = n;
+    t->d = d;
+    t->leaf = leaf;
+    t->stride = rec_stride(d);
+    const kdt_status st = build_midpoint(d_pts, n, d, leaf, check != 0, stream, t);
+    if (st != KDT_OK) {
+      if (t->rec) (void)hipFreeAsync(t->rec, stream);
+      delete t;
+      return st;
+    }
+    *out = t;
+    return KDT_OK;
   }
   std::shared_ptr<CachedPlan> cp;
   kdt_status st = get_plan(device, n, d, leaf, stream, cp);
@@ -259,6 +286,43 @@ extern "C" kdt_status kdt_tree_get_info(const kdt_tree* tree, kdt_tree_info* inf
 }
 
 extern "C" const int32_t* kdt_tree_perm(const kdt_tree* tree) { return tree ? tree->perm : nullptr; }
+
+extern "C" kdt_status kdt_tree_nodes(const kdt_tree* tree, int32_t* h_left, int32_t* h_begin,
+                                     int32_t* h_end, int32_t* h_level, hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree) {
+    kdt_set_error("kdt_tree_nodes: NULL tree");
+    return KDT_EINVAL;
+  }
+  const int64_t m = tree->n_nodes;
+  std::vector<int4> rec((size_t)m);
+  if (tree->nodes) {
+    hipError_t e = hipMemcpyAsync(rec.data(), tree->nodes, sizeof(int4) * (size_t)m,
+                                  hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      kdt_set_error("kdt_tree_nodes: copy failed: %s", hipGetErrorString(e));
+      return KDT_EDEVICE;
+    }
+  } else {
+    // the implicit median layout, written out
+    for (int64_t v = 0; v < m; ++v) {
+      int lev = 0;
+      while ((int64_t(2) << lev) - 1 <= v) ++lev;
+      const int64_t j = v - ((int64_t(1) << lev) - 1);
+      const bool leaf = lev == tree->levels;
+      rec[(size_t)v] = make_int4(leaf ? -1 : (int)(2 * v + 1), (int)node_begin(tree->n, lev, j),
+                                 (int)node_begin(tree->n, lev, j + 1), lev);
+    }
+  }
+  for (int64_t v = 0; v < m; ++v) {
+    if (h_left) h_left[v] = rec[(size_t)v].x;
+    if (h_begin) h_begin[v] = rec[(size_t)v].y;
+    if (h_end) h_end[v] = rec[(size_t)v].z;
+    if (h_level) h_level[v] = rec[(size_t)v].w;
+  }
+  return KDT_OK;
+}
 
 extern "C" kdt_status kdt_tree_export(const kdt_tree* tree, float* h_pts, int32_t* h_perm,
                                       float* h_lo, float* h_hi, int32_t* h_axis, float* h_split,

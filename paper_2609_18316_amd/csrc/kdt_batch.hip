@@ -402,6 +402,10 @@ extern "C" kdt_status kdt_batch_plan_create(const int64_t* h_offsets, int32_t n_
     kdt_set_error("kdt_batch_plan_create: k=%d outside [1, %d]", k, KDT_MAX_K);
     return k < 1 ? KDT_EINVAL : KDT_EUNSUPPORTED;
   }
+  if (bopts && bopts->split_rule != 0) {
+    kdt_set_error("kdt_batch_plan_create: the batched forest is built with median splits only");
+    return KDT_EUNSUPPORTED;
+  }
   if (h_offsets[0] != 0 || h_offsets[n_sets] > INT32_MAX) {
     kdt_set_error("kdt_batch_plan_create: offsets must start at 0 and total below 2^31");
     return KDT_EINVAL;

@@ -47,6 +47,26 @@ __global__ __launch_bounds__(kFBlock) void k_fof_link(TreeView t, float l2,
   fof_point<D>(t, p, s, me, l2, 0, parent, conn, &stk[0][threadIdx.x], kFBlock);
 }
 
+// The same links over a sliding-midpoint tree: its depth is data-dependent,
+// so the stack (levels + 2 entries per lane) is sized at launch.
+template <int D>
+__global__ __launch_bounds__(kFBlock) void k_fof_link_stored(TreeView t, float l2,
+                                                             int32_t* __restrict__ parent,
+                                                             uint32_t* __restrict__ conn) {
+  extern __shared__ uint32_t stk_fof[];
+  const int64_t s = xcd_block<kXcdRunFof>() * kFBlock + threadIdx.x;
+  if (s >= t.n) return;
+  float p[D];
+  int32_t me = 0;
+  load_rec<D>(t.rec, s, p, me);
+  fof_point<D, StoredShape>(t, p, s, me, l2, 0, parent, conn, stk_fof + threadIdx.x, kFBlock);
+}
+
+__global__ void k_fill_conn(uint32_t* __restrict__ conn, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) conn[i] = 0u;
+}
+
 // Returns the status of the launches (the packet launch checks its own and
 // clears the runtime's error, so it is passed on from here).
 template <int D>
@@ -55,6 +75,14 @@ static kdt_status fof_launch(const TreeView& v, int leaf, int64_t n_nodes, float
   const unsigned gn = (unsigned)((n_nodes + 255) / 256);
   const unsigned gp = (unsigned)((v.n + 255) / 256);
   const unsigned gl = (unsigned)((v.n + kFBlock - 1) / kFBlock);
+  if (v.nodes) {
+    // a sliding-midpoint tree: every friend pair is linked by the search (no
+    // one-component node flags, which join through the implicit layout)
+    k_fill_conn<<<gn, 256, 0, stream>>>(conn, n_nodes);
+    const size_t smem = sizeof(uint32_t) * (size_t)(v.levels + 2) * kFBlock;
+    k_fof_link_stored<D><<<gl, kFBlock, smem, stream>>>(v, l2, labels, conn);
+    return KDT_OK;
+  }
   k_fof_clique_mark<D><<<gn, 256, 0, stream>>>(v.box, n_nodes, l2, conn);
   k_fof_clique_join<D><<<gp, 256, 0, stream>>>(v, labels, conn);
   if (hipGetLastError() != hipSuccess) {
@@ -92,6 +120,7 @@ static TreeView view_of(const kdt_tree* t) {
   v.box = t->box;
   v.n = t->n;
   v.levels = t->levels;
+  v.nodes = t->nodes;
   return v;
 }
 

@@ -276,8 +276,29 @@ struct kdt_tree {
   int32_t* perm = nullptr;   // [n]
   int32_t* axis = nullptr;   // [n_nodes]
   float* split = nullptr;    // [n_nodes]
+  // sliding-midpoint trees (split_rule 1): [n_nodes] (left child or -1, first
+  // point, end point, level), nodes numbered level by level; NULL for the
+  // implicit median layout
+  int4* nodes = nullptr;
 };
+
+namespace kdt {
+// The sliding-midpoint build (Sec. 2.1); fills t (levels, n_nodes and the
+// arrays, one allocation starting at t->rec) from d_pts [n][d].
+kdt_status build_midpoint(const float* d_pts, int64_t n, int d, int leaf, bool check,
+                          hipStream_t stream, kdt_tree* t);
+}  // namespace kdt
 
 // Error reporting shared by every entry point.
 void kdt_set_error(const char* fmt, ...);
 void kdt_clear_error();
+
+// Entry points whose kernels use the median tree's implicit layout refuse a
+// sliding-midpoint tree: true (and the error set) if t is one.
+inline bool refuse_stored(const kdt_tree* t, const char* who) {
+  if (t && t->nodes) {
+    kdt_set_error("%s: not available on a sliding-midpoint tree (split_rule 1)", who);
+    return true;
+  }
+  return false;
+}

@@ -12,7 +12,44 @@ struct TreeView {
   const float* rec;  // [n][rec_stride(D)] tree-ordered records
   const float* box;  // [n_nodes][2 * pad4(D)]
   int64_t n;
-  int32_t levels;
+  int32_t levels;    // depth of the deepest leaf
+  const int4* nodes = nullptr;  // stored node records (sliding-midpoint trees), else NULL
+};
+
+// Node layout of a tree, as the traversals see it.  A median tree is
+// implicit: node (l, j) sits at 2^l - 1 + j, its children at 2v + 1 and
+// 2v + 2, and it owns points [floor(j n / 2^l), floor((j + 1) n / 2^l)), so
+// every leaf holds floor(n / 2^L) or one more.  A sliding-midpoint tree
+// (Sec. 2.1, data-dependent depth) stores per node (left child or -1 for a
+// leaf, first point, end point, level); its right child follows the left.
+struct MedianShape {
+  static constexpr bool kUniformLeaves = true;
+  int64_t n;
+  int levels;
+  uint32_t first_leaf;
+  __device__ __forceinline__ explicit MedianShape(const TreeView& t)
+      : n(t.n), levels(t.levels), first_leaf((1u << t.levels) - 1u) {}
+  __device__ __forceinline__ bool is_leaf(uint32_t v) const { return v >= first_leaf; }
+  __device__ __forceinline__ uint32_t left(uint32_t v) const { return 2 * v + 1; }
+  __device__ __forceinline__ void range(uint32_t v, int64_t& b, int64_t& e) const {
+    const int lev = 31 - __clz(v + 1);
+    const int64_t j = (int64_t)v - ((int64_t(1) << lev) - 1);
+    b = (j * n) >> lev;
+    e = ((j + 1) * n) >> lev;
+  }
+};
+
+struct StoredShape {
+  static constexpr bool kUniformLeaves = false;
+  const int4* node;
+  __device__ __forceinline__ explicit StoredShape(const TreeView& t) : node(t.nodes) {}
+  __device__ __forceinline__ bool is_leaf(uint32_t v) const { return node[v].x < 0; }
+  __device__ __forceinline__ uint32_t left(uint32_t v) const { return (uint32_t)node[v].x; }
+  __device__ __forceinline__ void range(uint32_t v, int64_t& b, int64_t& e) const {
+    const int4 r = node[v];
+    b = r.y;
+    e = r.z;
+  }
 };
 
 template <int D>
@@ -238,11 +275,11 @@ struct OpenMetric {
 // child first, a node is skipped when its box is farther than the current
 // k-th candidate.  `stk` is this lane's column of an LDS stack with stride
 // `ld` entries.
-template <int D, class List, class Metric = OpenMetric<D>>
+template <int D, class List, class Metric = OpenMetric<D>, class Shape = MedianShape>
 __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], List& best,
                                         uint32_t* stk, int ld, const Metric& metric = Metric()) {
-  const uint32_t first_leaf = (1u << t.levels) - 1u;
-  // leaf sizes: floor(n / 2^L) or one more
+  const Shape sh(t);
+  // median trees: every leaf holds floor(n / 2^L) or one more points
   const int lmin = (int)(t.n >> t.levels);
   const int lmax = (int)((t.n + (int64_t(1) << t.levels) - 1) >> t.levels);
   float lo[D], hi[D];
@@ -252,9 +289,9 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
   int sp = 0;
   for (;;) {
     if (nd <= best.worst_d2()) {
-      if (node >= first_leaf) {
-        const int64_t j = node - first_leaf;
-        const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
+      if (sh.is_leaf(node)) {
+        int64_t b, e;
+        sh.range(node, b, e);
         // Two passes per block of up to 64 leaf points.  The first computes
         // every distance and marks the points that can enter the list (float
         // test against the current k-th distance, ties kept); the second
@@ -266,7 +303,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
         for (int64_t c = b; c < e; c += 64) {
           const float w = best.worst_d2();
           uint64_t mask = 0;
-          if (lmax <= 32) {
+          if (Shape::kUniformLeaves && lmax <= 32) {
             // Every leaf holds lmin or lmin + 1 points: the first lmin are
             // scanned with a wave-uniform trip count, the possible last one
             // on its own (one block: e - b <= 32).
@@ -304,7 +341,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
           }
         }
       } else {
-        const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
+        const uint32_t c0 = sh.left(node), c1 = c0 + 1;
         load_box<D>(t.box, c0, lo, hi);
         const float d0 = metric.mindist(lo, hi, p);
         load_box<D>(t.box, c1, lo, hi);
@@ -444,13 +481,13 @@ __device__ __forceinline__ void flag_st(uint32_t* p, uint32_t v) {
 // every point of node v is already (or will be, once the running unions land)
 // in one component; such a node needs a single link to p, and once one friend
 // is found inside it the rest of its subtree is skipped.
-template <int D>
+template <int D, class Shape = MedianShape>
 __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], int64_t pos,
                                           int32_t me, float l2, int32_t base,
                                           int32_t* __restrict__ parent,
                                           uint32_t* __restrict__ conn, uint32_t* stk, int ld) {
   constexpr int S = rec_stride(D);
-  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  const Shape sh(t);
   int sp = 1;
   stk[0] = 0;
   int32_t myroot = base + me;  // an ancestor of p's set root (see uf_union_from)
@@ -459,9 +496,8 @@ __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], i
     --sp;
     if (guard >= 0 && sp < guard) guard = -1;
     const uint32_t node = stk[sp * ld];
-    const int lev = node_level(node);
-    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
-    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    int64_t b, e;
+    sh.range(node, b, e);
     // links go towards later tree positions only: a node that ends at or
     // before p's position is left to the points inside it
     if (e <= pos) continue;
@@ -485,7 +521,7 @@ __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], i
       }
       continue;
     }
-    if (node >= first_leaf) {
+    if (sh.is_leaf(node)) {
       for (int64_t i = b; i < e; ++i) {
         float x[D];
         int32_t id = 0;
@@ -504,8 +540,9 @@ __device__ __forceinline__ void fof_point(const TreeView& t, const float p[D], i
       continue;
     }
     if (one && !in_region) guard = sp;
-    stk[sp++ * ld] = 2 * node + 2;
-    stk[sp++ * ld] = 2 * node + 1;
+    const uint32_t c0 = sh.left(node);
+    stk[sp++ * ld] = c0 + 1;
+    stk[sp++ * ld] = c0;
   }
 }
 

@@ -27,7 +27,7 @@ constexpr int kQBlock = 128;
 // The per-lane stack lives in LDS, (levels + 1) entries per lane (the tree
 // depth bounds it: one pending sibling per level), sized at launch.  KTH:
 // only the k-th distance is written (modes 1 and 2), kept in a TopD list.
-template <int D, int KC, bool KTH>
+template <int D, int KC, bool KTH, class Shape = MedianShape>
 __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* __restrict__ q,
                                                       int64_t nq, int k,
                                                       const int32_t* __restrict__ order, int mode,
@@ -50,12 +50,12 @@ __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* _
   if constexpr (KTH) {
     TopD<KC> best;
     best.init(k);
-    knn_one<D>(t, p, best, stk_dyn + threadIdx.x, kQBlock);
+    knn_one<D, TopD<KC>, OpenMetric<D>, Shape>(t, p, best, stk_dyn + threadIdx.x, kQBlock);
     knn_write_kth<KC>(best, mode, row, od2);
   } else {
     TopK<KC> best;
     best.init(k);
-    knn_one<D>(t, p, best, stk_dyn + threadIdx.x, kQBlock);
+    knn_one<D, TopK<KC>, OpenMetric<D>, Shape>(t, p, best, stk_dyn + threadIdx.x, kQBlock);
     knn_write<KC>(best, k, mode, row, oidx, od2);
   }
 }
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* _
 // Ball queries: counts, then CSR lists
 // ---------------------------------------------------------------------------
 
-template <int D, bool FILL>
+template <int D, bool FILL, class Shape = MedianShape>
 __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __restrict__ q,
                                                    int64_t nq, float r2,
                                                    const int32_t* __restrict__ order,
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
 #pragma unroll
     for (int a = 0; a < D; ++a) p[a] = q[row * D + a];
   }
-  const uint32_t first_leaf = (1u << t.levels) - 1u;
+  const Shape sh(t);
   int64_t c = 0;
   int64_t pos = FILL ? offsets[row] : 0;
   int sp = 0;
@@ -96,9 +96,8 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
     float lo[D], hi[D];
     load_box<D>(t.box, node, lo, hi);
     if (box_mindist<D>(lo, hi, p) > r2) continue;
-    const int lev = node_level(node);
-    const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
-    const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
+    int64_t b, e;
+    sh.range(node, b, e);
     if (box_maxdist<D>(lo, hi, p) <= r2) {
       if (FILL) {
         for (int64_t i = b; i < e; ++i) {
@@ -111,7 +110,7 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
       c += e - b;
       continue;
     }
-    if (node >= first_leaf) {
+    if (sh.is_leaf(node)) {
       for (int64_t i = b; i < e; ++i) {
         float x[D];
         int32_t id = 0;
@@ -123,8 +122,9 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
       }
       continue;
     }
-    col[kQBlock * sp++] = 2 * node + 2;
-    col[kQBlock * sp++] = 2 * node + 1;
+    const uint32_t c0 = sh.left(node);
+    col[kQBlock * sp++] = c0 + 1;
+    col[kQBlock * sp++] = c0;
   }
   if (!FILL) count[row] = (int32_t)c;
 }
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
 // descending towards the nearer child.
 // ---------------------------------------------------------------------------
 
-template <int D>
+template <int D, class Shape = MedianShape>
 __global__ void k_query_leaf(TreeView t, const float* __restrict__ q, int64_t nq,
                              uint32_t* __restrict__ key, int32_t* __restrict__ val) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,14 +142,16 @@ __global__ void k_query_leaf(TreeView t, const float* __restrict__ q, int64_t nq
   float p[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) p[a] = q[s * D + a];
+  const Shape sh(t);
   uint32_t node = 0;
-  for (int l = 0; l < t.levels; ++l) {
+  while (!sh.is_leaf(node)) {
+    const uint32_t c0 = sh.left(node);
     float lo[D], hi[D];
-    load_box<D>(t.box, 2 * node + 1, lo, hi);
+    load_box<D>(t.box, c0, lo, hi);
     const float d0 = box_mindist<D>(lo, hi, p);
-    load_box<D>(t.box, 2 * node + 2, lo, hi);
+    load_box<D>(t.box, c0 + 1, lo, hi);
     const float d1 = box_mindist<D>(lo, hi, p);
-    node = d0 <= d1 ? 2 * node + 1 : 2 * node + 2;
+    node = d0 <= d1 ? c0 : c0 + 1;
   }
   key[s] = node;
   val[s] = (int32_t)s;
@@ -232,6 +234,7 @@ static TreeView view_of(const kdt_tree* t) {
   v.box = t->box;
   v.n = t->n;
   v.levels = t->levels;
+  v.nodes = t->nodes;
   return v;
 }
 
@@ -265,7 +268,10 @@ static kdt_status order_queries(const kdt_tree* t, const float* d_q, int64_t nq,
   // up to 4 dimensions a Hilbert key over the root box; above, the leaf
   // reached by descending towards the nearer child
   const bool hilbert = D <= 4 && kind == 0;
-  const int end_bit = hilbert ? (30 / D) * D : std::max(1, t->levels + 1);
+  // leaf keys are node ids: below 2^(L+1) in a median tree, n_nodes in a stored one
+  int node_bits = 1;
+  while (node_bits < 31 && (int64_t(1) << node_bits) < t->n_nodes) ++node_bits;
+  const int end_bit = hilbert ? (30 / D) * D : t->nodes ? node_bits : std::max(1, t->levels + 1);
   // The double-buffer form of the sort ping-pongs between the two key and
   // the two index arrays, so its temporary storage holds only histograms and
   // look-back state (about 2 MB at 2^22 queries, against 34 MB for the form
@@ -295,6 +301,9 @@ static kdt_status order_queries(const kdt_tree* t, const float* d_q, int64_t nq,
   }
   if (hilbert)
     k_query_hilbert<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq, k0, v0);
+  else if (t->nodes)
+    k_query_leaf<D, StoredShape><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q,
+                                                                                   nq, k0, v0);
   else
     k_query_leaf<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq, k0, v0);
   KDT_HIP(hipGetLastError());
@@ -324,13 +333,19 @@ static kdt_status knn_dispatch(const kdt_tree* t, const float* d_q, int64_t nq, 
   const TreeView v = view_of(t);
   const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(t->levels + 1) * kQBlock;
-#define KDT_LANE(KC)                                                                      \
-  if (mode == 0)                                                                          \
-    k_knn_lane<D, KC, false><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, \
-                                                              d_idx, d_d2);               \
-  else                                                                                    \
-    k_knn_lane<D, KC, true><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode,  \
-                                                             d_idx, d_d2);
+#define KDT_LANE_S(KC, SH)                                                                    \
+  if (mode == 0)                                                                              \
+    k_knn_lane<D, KC, false, SH><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode, \
+                                                                  d_idx, d_d2);               \
+  else                                                                                        \
+    k_knn_lane<D, KC, true, SH><<<grid, kQBlock, smem, stream>>>(v, d_q, nq, k, order, mode,  \
+                                                                 d_idx, d_d2);
+#define KDT_LANE(KC)            \
+  if (t->nodes) {               \
+    KDT_LANE_S(KC, StoredShape) \
+  } else {                      \
+    KDT_LANE_S(KC, MedianShape) \
+  }
   if (k <= 8) {
     KDT_LANE(8)
   } else if (k <= 16) {
@@ -341,6 +356,7 @@ static kdt_status knn_dispatch(const kdt_tree* t, const float* d_q, int64_t nq, 
     KDT_LANE(64)
   }
 #undef KDT_LANE
+#undef KDT_LANE_S
   KDT_HIP(hipGetLastError());
   return KDT_OK;
 }
@@ -353,6 +369,7 @@ static kdt_status knn_impl(const kdt_tree* t, const float* d_q, int64_t nq, int 
                            size_t ws_bytes = 0) {
   if (traversal == 0) traversal = D <= 8 ? 1 : 2;  // measured defaults
   if (t->leaf > 64) traversal = 1;  // the wave kernel marks at most 64 points per leaf
+  if (t->nodes) traversal = 1;      // stored trees: one traversal per lane
   int32_t* order = nullptr;
   if (d_q && !given && sort_q && nq > 1) {
     kdt_status st = order_queries<D>(t, d_q, nq, traversal == 1 ? 0 : 1, &order, stream, nullptr,
@@ -385,7 +402,10 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
   // both children are pushed: at most levels + 2 entries
   const size_t rsmem = sizeof(uint32_t) * (size_t)(t->levels + 2) * kQBlock;
   kdt_status st = KDT_OK;
-  if (t->leaf <= 64 && traversal != 1)
+  if (t->nodes)
+    k_range<D, false, StoredShape><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order,
+                                                                     d_count, nullptr, nullptr);
+  else if (t->leaf <= 64 && traversal != 1)
     st = range_packet_launch<D>(v, t->leaf, d_q, nq, r2, order, d_count, split_budget, stream);
   else
     k_range<D, false><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
@@ -435,8 +455,12 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
           kdt_set_error("device allocation failed for the lists");
           st = KDT_ENOMEM;
         } else {
-          k_range<D, true><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count,
-                                                             d_off, unsorted);
+          if (t->nodes)
+            k_range<D, true, StoredShape><<<grid, kQBlock, rsmem, stream>>>(
+                v, d_q, nq, r2, order, d_count, d_off, unsorted);
+          else
+            k_range<D, true><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count,
+                                                               d_off, unsorted);
           if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total,
                                                     (int)nq, d_off, d_off + 1, stream) !=
               hipSuccess) {
@@ -560,6 +584,8 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
   KnnArgs a;
   const kdt_status chk = knn_check(tree, d_q, nq, k, d_d2, kth_only, opts, "kdt_knn", &a);
   if (chk != KDT_OK || a.empty) return chk;
+  if ((k > KDT_MAX_K || a.period) && refuse_stored(tree, "kdt_knn with k > 64 or a period"))
+    return KDT_EUNSUPPORTED;
   if (k > KDT_MAX_K)
     return knn_large(tree, d_q, nq, k, d_idx, d_d2, kth_only, a.sort_q, a.given, a.period, stream);
   if (a.period)
@@ -610,6 +636,8 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
     return KDT_OK;
   }
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
+  if (opts && opts->period && refuse_stored(tree, "kdt_range with a period"))
+    return KDT_EUNSUPPORTED;
   if (opts && opts->period)
     return range_torus(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q,
                        opts->order, opts->period, stream);

@@ -23,7 +23,8 @@ MAX_K_SORTED = 1 << 20  # kdt_knn above MAX_K: ball and sort
 DIMS = (2, 3, 4, 8, 16)
 
 # Every exported entry point of include/kdt.h.
-EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt_knn",
+EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt_tree_nodes",
+           "kdt_knn",
            "kdt_range", "kdt_box", "kdt_fof", "kdt_fof_torus", "kdt_p2m", "kdt_p2m_backward",
            "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
@@ -38,7 +39,9 @@ class KdtError(RuntimeError):
 
 
 class BuildOpts(C.Structure):
-    _fields_ = [("leaf_size", C.c_int32), ("check_finite", C.c_int32)]
+    _fields_ = [("leaf_size", C.c_int32), ("check_finite", C.c_int32), ("split_rule", C.c_int32)]
+
+SPLIT_MEDIAN, SPLIT_MIDPOINT = 0, 1
 
 
 def _periods(period, d: int):
@@ -82,6 +85,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_free.argtypes = [vp]
     lib.kdt_tree_get_info.argtypes = [vp, C.POINTER(TreeInfo)]
     lib.kdt_tree_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.kdt_tree_nodes.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.kdt_knn.argtypes = [vp, vp, i64, i32, vp, vp, i32, C.POINTER(QueryOpts), vp]
     lib.kdt_knn_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, i32, C.POINTER(QueryOpts), vp]
     lib.kdt_range.argtypes = [vp, vp, i64, f32, vp, vp, vp, i64, C.POINTER(C.c_int64),
@@ -148,13 +152,15 @@ class Tree:
     """A device-resident k-d tree (library-owned; freed with the object)."""
 
     def __init__(self, points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
-                 stream=None):
+                 stream=None, split_rule: int = SPLIT_MEDIAN):
+        """split_rule: SPLIT_MEDIAN (balanced) or SPLIT_MIDPOINT (the paper's
+        sliding midpoint, data-dependent depth)."""
         lib = load()
         points = _dev(points, torch.float32, "points")
         if points.dim() != 2:
             raise ValueError("points must be [n][d]")
         self._h = C.c_void_p()
-        opts = BuildOpts(leaf_size, 1 if check_finite else 0)
+        opts = BuildOpts(leaf_size, 1 if check_finite else 0, int(split_rule))
         _check(lib.kdt_build(_ptr(points), points.shape[0], points.shape[1], C.byref(opts),
                              _stream(stream), C.byref(self._h)))
         info = TreeInfo()
@@ -322,12 +328,17 @@ class Tree:
                                       out["lo"].ctypes.data, out["hi"].ctypes.data,
                                       out["axis"].ctypes.data, out["split"].ctypes.data,
                                       _stream(stream)))
+        for key in ("left", "begin", "end", "level"):
+            out[key] = np.empty(i.n_nodes, np.int32)
+        _check(load().kdt_tree_nodes(self._h, out["left"].ctypes.data, out["begin"].ctypes.data,
+                                     out["end"].ctypes.data, out["level"].ctypes.data,
+                                     _stream(stream)))
         return out
 
 
 def build(points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
-          stream=None) -> Tree:
-    return Tree(points, leaf_size, check_finite, stream)
+          stream=None, split_rule: int = SPLIT_MEDIAN) -> Tree:
+    return Tree(points, leaf_size, check_finite, stream, split_rule)
 
 
 def make_grid(lo, cell: float, shape, periodic: bool = False) -> Grid:

@@ -49,6 +49,28 @@ def test_knn_and_counts_full_size_every_row(clustered):
     np.testing.assert_array_equal(cnt, ot.range(q, 0.01, threads=T))
 
 
+def test_midpoint_tree_full_size(clustered):
+    """The paper's split rule on the GPU at 2^24 clustered points: the whole
+    tree equals the oracle's (which builds with that rule), and kNN k = 32 and
+    r = 0.01 counts of all 2^22 queries over it equal the oracle's."""
+    from tests.test_gpu_midpoint import assert_same_tree
+    x, q, xt, qt, tree, ot = clustered
+    say("sliding-midpoint tree over 2^24 points")
+    mt = kdt.build(xt, leaf_size=32, split_rule=kdt.SPLIT_MIDPOINT)
+    say(f"{mt.info.n_nodes} nodes, depth {mt.info.levels}; comparing with the oracle's tree")
+    assert mt.info.levels == ot.depth
+    assert_same_tree(mt.export(), ot.export())
+    idx, d2 = mt.knn(qt, 32)
+    cnt = mt.range(qt, 0.01)
+    idx, d2, cnt = to_host(idx), to_host(d2), to_host(cnt)
+    say(f"oracle kNN and counts of all 2^22 queries on {T} threads")
+    oi, od = ot.knn(q, 32, threads=T)
+    np.testing.assert_array_equal(idx, oi)
+    np.testing.assert_array_equal(d2, od)
+    np.testing.assert_array_equal(cnt, ot.range(q, 0.01, threads=T))
+    mt.close()
+
+
 def test_box_counts_full_size_sampled(clustered):
     """2^16 boxes of side 0.002-0.04 on the 2^24-point tree; 48 sampled rows
     checked against the oracle's definition."""
