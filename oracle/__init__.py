@@ -67,6 +67,9 @@ def _load():
     for name in ("orc_p2m", "orc_p2m_brute"):
         getattr(lib, name).argtypes = [_f64p, _f64p, _f64p, i64, C.POINTER(_Grid), _f64p]
     lib.orc_p2m_backward.argtypes = [_f64p, _f64p, _f64p, i64, C.POINTER(_Grid), _f64p, vp, vp]
+    lib.orc_p2m_cloud.argtypes = [_f64p, _f64p, i64, C.POINTER(_Grid), i32, _f64p, i32]
+    lib.orc_cloud_shape.argtypes = [i32, C.c_double]
+    lib.orc_cloud_shape.restype = C.c_double
     _lib = lib
     return lib
 
@@ -328,6 +331,24 @@ def p2m(x, m, h, lo, cell, shape, brute: bool = False, periodic: bool = False) -
     fn = _load().orc_p2m_brute if brute else _load().orc_p2m
     _check(fn(x, m, h, x.shape[0], C.byref(_grid(lo, cell, shape, periodic)), rho), "p2m")
     return rho.reshape(shape)
+
+
+CLOUD_SCHEMES = {"ngp": 1, "cic": 2, "tsc": 3}
+
+
+def p2m_cloud(x, m, lo, cell, shape, scheme: str, periodic: bool = False,
+              brute: bool = False) -> np.ndarray:
+    """Fixed-cloud deposit (NGP, CIC or TSC): mass per cell, float64 ``shape``.
+    ``brute``: every cell of the mesh through the scheme's shape function."""
+    x, m = _f64(x, (-1, 3)), _f64(m)
+    rho = np.empty(int(np.prod(shape)), np.float64)
+    _check(_load().orc_p2m_cloud(x, m, x.shape[0], C.byref(_grid(lo, cell, shape, periodic)),
+                                 CLOUD_SCHEMES[scheme], rho, 1 if brute else 0), "p2m_cloud")
+    return rho.reshape(shape)
+
+
+def cloud_shape(scheme: str, v: float) -> float:
+    return float(_load().orc_cloud_shape(CLOUD_SCHEMES[scheme], float(v)))
 
 
 def p2m_backward(x, m, h, lo, cell, shape, g, periodic: bool = False):

@@ -51,7 +51,16 @@
  *     mesh of Sec. 4.2): the mesh box is a 3-torus of periods n_a * cell; the
  *     distance from a particle to a cell centre takes per axis the shorter way
  *     round (as the torus metric of the queries); every H_i must be below half
- *     of every period, so no cell is reached twice, and no cell is dropped.
+ *     of every period, so no cell is reached twice, and no cell is dropped;
+ *   - fixed-cloud deposits (the NGP, CIC and TSC schemes Sec. 4.2 compares
+ *     against, after Hockney and Eastwood): per axis, with s the position in
+ *     units of cells from the first cell centre, NGP puts weight 1 on the
+ *     nearest centre, CIC weights 1 - f and f on the two centres around s,
+ *     TSC 0.5 (0.5 - u)^2, 0.75 - u^2, 0.5 (0.5 + u)^2 on the nearest centre
+ *     and its neighbours (u = s - nearest); the weight of a cell is the
+ *     product over the axes.  On an open mesh the weights of cells outside are
+ *     dropped and the rest renormalised (the paper calls the schemes
+ *     conservative); on a periodic mesh indices wrap (n_a >= 3 cells).
  */
 #include <math.h>
 #include <stdint.h>
@@ -938,6 +947,122 @@ int orc_p2m_brute(const double *x, const double *m, const double *h, int64_t n,
                   const orc_grid *g, double *rho)
 {
     return p2m_forward(x, m, h, n, g, rho, 1);
+}
+
+/* Per-axis weights of the fixed-cloud schemes (1 NGP, 2 CIC, 3 TSC) for a
+   particle at s (cells, from the first centre): w[0 .. order-1] on cells
+   base, base + 1, ...  Returns the number of cells. */
+static int cloud_axis(int scheme, double s, int64_t *base, double *w)
+{
+    if (scheme == 1) {
+        *base = (int64_t)floor(s + 0.5);
+        w[0] = 1.0;
+        return 1;
+    }
+    if (scheme == 2) {
+        double i0 = floor(s), f = s - i0;
+        *base = (int64_t)i0;
+        w[0] = 1.0 - f;
+        w[1] = f;
+        return 2;
+    }
+    double c = floor(s + 0.5), u = s - c;
+    *base = (int64_t)c - 1;
+    w[0] = 0.5 * (0.5 - u) * (0.5 - u);
+    w[1] = 0.75 - u * u;
+    w[2] = 0.5 * (0.5 + u) * (0.5 + u);
+    return 3;
+}
+
+/* The same weights from the shape function of the scheme, W(v) for a cell
+   whose centre is v cells from the particle (v = i - s):
+   NGP 1 for -1/2 <= v < 1/2; CIC max(0, 1 - |v|); TSC 3/4 - v^2 for
+   |v| <= 1/2, (3/2 - |v|)^2 / 2 for 1/2 < |v| < 3/2, else 0. */
+double orc_cloud_shape(int scheme, double v)
+{
+    double a = fabs(v);
+    if (scheme == 1) return (v >= -0.5 && v < 0.5) ? 1.0 : 0.0;
+    if (scheme == 2) return a < 1.0 ? 1.0 - a : 0.0;
+    if (a <= 0.5) return 0.75 - v * v;
+    if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+    return 0.0;
+}
+
+/*
+ * Fixed-cloud deposit rho[c] = sum_i m_i W_ic / S_i (S_i = the particle's
+ * in-mesh weight; 1 unless cells fall outside an open mesh).  brute != 0
+ * visits every cell of the mesh with the shape function (offsets the
+ * shorter way round on a periodic mesh) instead of the per-axis stencil.
+ */
+static int cloud_forward(const double *x, const double *m, int64_t n, const orc_grid *g,
+                         int scheme, double *rho, int brute)
+{
+    if (!x || !m || !rho || n < 0 || !grid_ok(g) || scheme < 1 || scheme > 3) return ORC_EINVAL;
+    if (g->periodic)
+        for (int a = 0; a < 3; ++a)
+            if (g->n[a] < scheme) return ORC_EINVAL;
+    int64_t ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    for (int64_t c = 0; c < ncell; ++c) rho[c] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *xi = x + 3 * i;
+        if (!inside_grid(g, xi)) return ORC_EINVAL;
+        int64_t base[3];
+        double w[3][3];
+        int cnt[3];
+        for (int a = 0; a < 3; ++a) {
+            if (brute) {
+                base[a] = 0;
+                cnt[a] = g->n[a];
+            } else {
+                cnt[a] = cloud_axis(scheme, (xi[a] - g->lo[a]) / g->cell - 0.5, &base[a], w[a]);
+            }
+        }
+        double S = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1 && !(S > 0.0)) return ORC_EINVAL;
+            for (int p = 0; p < cnt[0]; ++p)
+                for (int q = 0; q < cnt[1]; ++q)
+                    for (int r = 0; r < cnt[2]; ++r) {
+                        int64_t idx[3] = {base[0] + p, base[1] + q, base[2] + r};
+                        double wt = 1.0;
+                        int in = 1;
+                        for (int a = 0; a < 3; ++a) {
+                            int k = a == 0 ? p : a == 1 ? q : r;
+                            if (brute) {
+                                double v = (double)idx[a] - ((xi[a] - g->lo[a]) / g->cell - 0.5);
+                                if (g->periodic) {
+                                    double L = g->n[a];
+                                    double u = fabs(v);
+                                    if (L - u < u) v = v > 0.0 ? v - L : v + L;
+                                }
+                                wt *= orc_cloud_shape(scheme, v);
+                            } else {
+                                wt *= w[a][k];
+                                if (g->periodic) {
+                                    idx[a] %= g->n[a];
+                                    if (idx[a] < 0) idx[a] += g->n[a];
+                                } else if (idx[a] < 0 || idx[a] >= g->n[a]) {
+                                    in = 0;
+                                }
+                            }
+                        }
+                        if (!in || wt == 0.0) continue;
+                        if (pass == 0) {
+                            S += wt;
+                        } else {
+                            int64_t at = (idx[0] * g->n[1] + idx[1]) * g->n[2] + idx[2];
+                            rho[at] += m[i] * wt / S;
+                        }
+                    }
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_p2m_cloud(const double *x, const double *m, int64_t n, const orc_grid *g, int scheme,
+                  double *rho, int brute)
+{
+    return cloud_forward(x, m, n, g, scheme, rho, brute);
 }
 
 /*

@@ -12,6 +12,9 @@ side L, §3.1; a clustered mock of Gaussian groups plus a uniform background,
 * ``normal``    -- standard-normal points in d dimensions.
 * ``clustered`` -- 2000 isotropic Gaussian halos (80 % of the points) plus a
   20 % uniform background in [0, 1)^3, the §4.1 style of clustered mock.
+* ``grf``       -- the §3.1 inhomogeneous mock: particles placed in proportion
+  to a Gaussian-random-field density (spectral index -2) on a grid of about
+  N^(1/3) cells per side.
 * ``masses``    -- particle masses for the particle-to-mesh deposit (§4.2).
 * ``batch_sizes`` -- log-uniform sizes for many independent point sets.
 
@@ -90,6 +93,56 @@ def clustered(n: int, seed: int) -> np.ndarray:
     pts = np.concatenate([x32, bg], axis=0)
     perm = rng.permutation(n)
     return np.ascontiguousarray(pts[perm])
+
+
+GRF_INDEX = -2.0
+
+
+def grf_density(nx: int, seed: int, index: float = GRF_INDEX) -> np.ndarray:
+    """Density on an ``nx``^3 periodic grid from a Gaussian random field with
+    power spectrum P(k) ~ |k|^index (the §3.1 mock uses index -2).
+
+    White noise is drawn on the grid, filtered in Fourier space by
+    sqrt(P(k)) (the k = 0 mode removed), and transformed back, giving a field
+    delta with zero mean.  The paper does not say how delta becomes a
+    (non-negative) density; the reading here is the lognormal map
+    rho = exp(delta / std(delta)), float64, mean not normalised.
+    """
+    rng = _rng(seed)
+    white = rng.standard_normal((nx, nx, nx))
+    f = np.fft.rfftn(white)
+    k = np.fft.fftfreq(nx) * nx
+    kz = np.fft.rfftfreq(nx) * nx
+    k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + kz[None, None, :] ** 2
+    amp = np.zeros_like(k2)
+    nz = k2 > 0
+    amp[nz] = k2[nz] ** (index / 4.0)  # sqrt(P) = |k|^(index / 2)
+    delta = np.fft.irfftn(f * amp, s=(nx, nx, nx), axes=(0, 1, 2))
+    sd = delta.std()
+    return np.exp(delta / sd) if sd > 0 else np.ones_like(delta)  # a 1^3 grid has no field
+
+
+def grf(n: int, seed: int, index: float = GRF_INDEX) -> np.ndarray:
+    """The §3.1 inhomogeneous mock: ``n`` points in [0, 1)^3, float32.
+
+    * density from ``grf_density`` on nx = floor(n^(1/3)) cells per side, so
+      the mean spacing of the points is about one cell;
+    * per cell, a share of the n points proportional to its density (largest
+      remainder, ties to the lower cell index);
+    * each point at its cell's corner plus a uniform shift inside the cell,
+      in float64, rounded to float32 (a value that rounds to 1.0 becomes 0.0);
+    * finally a seeded random permutation.
+    """
+    nx = max(1, int(np.floor(n ** (1.0 / 3.0) + 1e-9)))
+    rho = grf_density(nx, seed, index).reshape(-1)
+    counts = _hamilton_split(n, rho)
+    rng = _rng(seed + 1)
+    cell = np.repeat(np.arange(nx ** 3), counts)
+    ijk = np.stack(np.unravel_index(cell, (nx, nx, nx)), axis=1).astype(np.float64)
+    x = (ijk + rng.random((n, 3))) / nx
+    x32 = x.astype(np.float32)
+    x32[x32 >= np.float32(1.0)] = np.float32(0.0)
+    return np.ascontiguousarray(x32[rng.permutation(n)])
 
 
 def masses(n: int, seed: int) -> np.ndarray:
