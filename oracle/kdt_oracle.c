@@ -955,6 +955,8 @@ int orc_p2m_brute(const double *x, const double *m, const double *h, int64_t n,
 static int cloud_axis(int scheme, double s, int64_t *base, double *w)
 {
     if (scheme == 1) {
+        /* the cell holding the particle, floor((x - lo) / cell); the caller
+           passes that index, decided in float32 (see cloud_forward) */
         *base = (int64_t)floor(s + 0.5);
         w[0] = 1.0;
         return 1;
@@ -976,12 +978,13 @@ static int cloud_axis(int scheme, double s, int64_t *base, double *w)
 
 /* The same weights from the shape function of the scheme, W(v) for a cell
    whose centre is v cells from the particle (v = i - s):
-   NGP 1 for -1/2 <= v < 1/2; CIC max(0, 1 - |v|); TSC 3/4 - v^2 for
-   |v| <= 1/2, (3/2 - |v|)^2 / 2 for 1/2 < |v| < 3/2, else 0. */
+   NGP 1 for -1/2 < v <= 1/2 (a particle on a cell face belongs to the cell
+   above it); CIC max(0, 1 - |v|); TSC 3/4 - v^2 for |v| <= 1/2,
+   (3/2 - |v|)^2 / 2 for 1/2 < |v| < 3/2, else 0. */
 double orc_cloud_shape(int scheme, double v)
 {
     double a = fabs(v);
-    if (scheme == 1) return (v >= -0.5 && v < 0.5) ? 1.0 : 0.0;
+    if (scheme == 1) return (v > -0.5 && v <= 0.5) ? 1.0 : 0.0;
     if (scheme == 2) return a < 1.0 ? 1.0 - a : 0.0;
     if (a <= 0.5) return 0.75 - v * v;
     if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
@@ -1013,6 +1016,12 @@ static int cloud_forward(const double *x, const double *m, int64_t n, const orc_
             if (brute) {
                 base[a] = 0;
                 cnt[a] = g->n[a];
+            } else if (scheme == 1) {
+                /* NGP decides an integer from the position: the cell index
+                   floor((x - lo) / cell) is taken in float32, as the GPU
+                   takes it (the other schemes' weights are continuous) */
+                float t = ((float)xi[a] - (float)g->lo[a]) / (float)g->cell;
+                cnt[a] = cloud_axis(scheme, (double)floorf(t), &base[a], w[a]);
             } else {
                 cnt[a] = cloud_axis(scheme, (xi[a] - g->lo[a]) / g->cell - 0.5, &base[a], w[a]);
             }

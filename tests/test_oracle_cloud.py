@@ -37,8 +37,11 @@ def test_shape_functions_partition_unity_and_moments(scheme):
     c = {"ngp": 1.0, "cic": 1.0, "tsc": 0.75}[scheme]
     assert oracle.cloud_shape(scheme, 0.0) == c
     edge = {"ngp": 0.5, "cic": 1.0, "tsc": 1.5}[scheme]
-    assert oracle.cloud_shape(scheme, edge) == 0.0
-    assert oracle.cloud_shape(scheme, -edge - 1e-9) == 0.0
+    assert oracle.cloud_shape(scheme, -edge) == 0.0
+    assert oracle.cloud_shape(scheme, edge + 1e-9) == 0.0
+    # NGP: a particle on a cell face belongs to the cell above it (the cell
+    # whose centre is half a cell above: v = +1/2)
+    assert oracle.cloud_shape(scheme, edge) == (1.0 if scheme == "ngp" else 0.0)
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
@@ -54,6 +57,14 @@ def test_stencil_equals_the_shape_function_over_the_whole_mesh(scheme, periodic)
     b = oracle.p2m_cloud(x, m, (0, 0, 0), CELL, shape, scheme, periodic=periodic, brute=True)
     np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
     assert abs(a.sum() - m.sum()) < 1e-12 * m.sum()
+
+
+def test_ngp_particle_on_a_face_goes_to_the_cell_above():
+    shape = (16, 16, 16)
+    x = np.array([[5.0, 7.5, 0.0]]) * CELL
+    for brute in (False, True):
+        rho = oracle.p2m_cloud(x, np.ones(1), (0, 0, 0), CELL, shape, "ngp", brute=brute)
+        assert rho[5, 7, 0] == 1.0
 
 
 def test_particle_at_a_cell_centre():
