@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--no-large-k", action="store_true")
     ap.add_argument("--no-torus", action="store_true")
     ap.add_argument("--no-midpoint", action="store_true")
+    ap.add_argument("--no-cloud", action="store_true")
+    ap.add_argument("--no-grf", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of 1 GiB (read once, written once), the "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -456,6 +458,62 @@ def main():
         mt2.close()
         print(f"[bench] sliding midpoint: build {b_ms:.2f} ms, kNN {k_ms:.2f} ms, "
               f"counts {r_ms:.2f} ms", file=sys.stderr, flush=True)
+    if not args.no_cloud:
+        # The fixed-cloud deposits the paper compares the adaptive one with
+        # (Table 3): the same 2^24 particles and 256^3 mesh, best of three.
+        out["cloud"] = {"p2m_sph_fwd_ms": avg["p2m_fwd"]}
+        for scheme in ("ngp", "cic", "tsc"):
+            best = None
+            for _ in range(4):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                r = kdt.p2m_cloud(xt, mt, lo, cell, shape, scheme)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                best = ms if best is None else min(best, ms)
+                del r
+            out["cloud"][scheme + "_ms"] = best
+        out["cloud"]["sph_over_tsc"] = avg["p2m_fwd"] / out["cloud"]["tsc_ms"]
+    if not args.no_grf:
+        # The paper's inhomogeneous mock (Sec. 3.1): 2^24 points from a
+        # Gaussian random field of spectral index -2; build, kNN k = 32 of the
+        # 2^22 uniform queries, r = 0.01 counts and FoF b = 0.2 on it.
+        t_g = time.perf_counter()
+        xg = torch.from_numpy(workloads.grf(N_POINTS, seed=7)).to(dev)
+        gen_s = time.perf_counter() - t_g
+
+        def best_of(call, reps=3):
+            r = call()
+            del r
+            torch.cuda.synchronize()
+            best = None
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                r = call()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                best = ms if best is None else min(best, ms)
+                del r
+            return best
+        gtree = kdt.build(xg, leaf_size=LEAF)
+        out["grf"] = {
+            "n_points": N_POINTS, "generation_s": gen_s,
+            "build_ms": best_of(lambda: kdt.build(xg, leaf_size=LEAF, check_finite=False)),
+            "knn_ms": best_of(lambda: gtree.knn(qt, K)),
+            "range_ms": best_of(lambda: gtree.range(qt, RADIUS)),
+            "fof_ms": best_of(lambda: gtree.fof(l_fof)),
+            "midpoint_build_ms": best_of(lambda: kdt.build(
+                xg, leaf_size=LEAF, check_finite=False, split_rule=kdt.SPLIT_MIDPOINT), reps=2),
+        }
+        out["grf"]["knn_queries_s"] = N_QUERIES / (out["grf"]["knn_ms"] * 1e-3)
+        gtree.close()
+        del xg
+        print(f"[bench] GRF mock: {out['grf']}", file=sys.stderr, flush=True)
     if not args.no_dsweep:
         out["dsweep"] = dimension_sweep(torch, kdt, workloads, dev)
     if not args.no_cpu_baseline:

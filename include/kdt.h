@@ -343,6 +343,23 @@ kdt_status kdt_p2m(const float *d_x, const float *d_m, const float *d_h, int64_t
                    hipStream_t stream);
 
 /*
+ * kdt_p2m_cloud -- fixed-cloud particle-to-mesh deposit, the comparison the
+ * paper draws against the adaptive kernel (Sec. 4.2, Table 3): scheme 1 NGP
+ * (the cell holding the particle, floor((x - lo) / cell) in float32), 2 CIC
+ * (weights 1 - f and f on the two cell centres around the particle per axis),
+ * 3 TSC (0.5 (0.5 - u)^2, 0.75 - u^2, 0.5 (0.5 + u)^2 on the nearest centre
+ * and its two neighbours, u the offset from the nearest centre in cells); a
+ * cell's weight is the product over the axes.  On an open mesh cells outside
+ * are dropped and the particle's weights renormalised, so mass is conserved;
+ * a periodic mesh wraps (at least `scheme` cells per axis).  Arguments,
+ * waits, accumulation and errors as kdt_p2m, without smoothing lengths.
+ * Errors also: KDT_EINVAL for another scheme.
+ */
+kdt_status kdt_p2m_cloud(const float *d_x, const float *d_m, int64_t n, const kdt_grid *grid,
+                         int32_t scheme, const int32_t *d_order, float *d_grid,
+                         hipStream_t stream);
+
+/*
  * kdt_p2m_backward -- adjoint of kdt_p2m for a loss L = sum_c g_c rho_c with
  * the smoothing lengths held fixed:
  *   dL/dm_i = A_i / S_i,   dL/dx_i = (m_i / S_i) (C_i - (A_i / S_i) B_i),

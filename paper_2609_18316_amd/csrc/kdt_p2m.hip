@@ -40,6 +40,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "kdt_internal.h"
@@ -63,6 +64,11 @@ struct GridDev {
   int32_t periodic;  // 1: the mesh box is a 3-torus of periods n[a] * cell
   float L[3];        // the periods n[a] * cell
 };
+
+// Deposit schemes: the adaptive SPH kernel (M4, Sec. 4.2) and the fixed
+// clouds the paper compares it with (Table 3; after Hockney and Eastwood):
+// NGP, CIC and TSC spread a particle over 1, 2 and 3 cells per axis.
+enum : int { kSph = 0, kNgp = 1, kCic = 2, kTsc = 3 };
 
 __device__ __forceinline__ float m4_w(float q) {
   if (q < 1.0f) {
@@ -103,37 +109,62 @@ __device__ __forceinline__ float4 load_packed(const float4* __restrict__ P, int6
   return P[t];
 }
 
-// Validity of a particle: inside the mesh box, h finite and >= 0, and on a
-// periodic mesh H below half of every period.
+// Validity of a particle: inside the mesh box; for the adaptive kernel also
+// h finite and >= 0, and on a periodic mesh H below half of every period.
+template <int SCH = kSph>
 __device__ __forceinline__ bool particle_ok(const GridDev& g, const float x[3], float h) {
-  bool ok = h >= 0.0f && isfinite(h);
+  bool ok = SCH != kSph || (h >= 0.0f && isfinite(h));
   const float H = fmaxf(h, g.cell);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float top = g.lo[a] + g.L[a];
     ok &= (x[a] >= g.lo[a]) && (x[a] < top);
-    if (g.periodic) ok &= 2.0f * H < g.L[a];
+    if (SCH == kSph && g.periodic) ok &= 2.0f * H < g.L[a];
   }
   return ok;
 }
 
-// Per axis, the unclipped cell range [lo_c, hi_c] whose centres can lie
-// within H of x, and the one period offset whose image can reach cells (none
-// if the support crosses no face).
+// Per axis, the unclipped cell range [lo_c, hi_c] the particle can reach, and
+// the one period offset whose image can reach cells (none if the support
+// crosses no face).  For the fixed clouds also the stencil: cell base + j
+// has weight cw[a][j] along axis a.
 struct Images {
   int lo_c[3], hi_c[3];  // unclipped cell range of the support
   int off[3];            // cell offset of the axis's image: -n, +n, or 0
   int mask;              // bit a: axis a has an image; images = subsets of mask
+  float cw[3][3];        // fixed clouds: per-axis weights from lo_c
 };
 
+template <int SCH>
 __device__ __forceinline__ Images images_of(const GridDev& g, const float x[3], float H) {
   Images im;
   im.mask = 0;
   const float inv = 1.0f / g.cell;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    im.lo_c[a] = (int)ceilf((x[a] - H - g.lo[a]) * inv - 0.5f);
-    im.hi_c[a] = (int)floorf((x[a] + H - g.lo[a]) * inv - 0.5f);
+    if constexpr (SCH == kSph) {
+      im.lo_c[a] = (int)ceilf((x[a] - H - g.lo[a]) * inv - 0.5f);
+      im.hi_c[a] = (int)floorf((x[a] + H - g.lo[a]) * inv - 0.5f);
+    } else if constexpr (SCH == kNgp) {
+      // the cell holding the particle (decided in float32, as the oracle does)
+      im.lo_c[a] = im.hi_c[a] = (int)floorf((x[a] - g.lo[a]) / g.cell);
+      im.cw[a][0] = 1.0f;
+    } else if constexpr (SCH == kCic) {
+      const float sc = (x[a] - g.lo[a]) * inv - 0.5f;  // in cells from the first centre
+      const float i0 = floorf(sc), f = sc - i0;
+      im.lo_c[a] = (int)i0;
+      im.hi_c[a] = im.lo_c[a] + 1;
+      im.cw[a][0] = 1.0f - f;
+      im.cw[a][1] = f;
+    } else {
+      const float sc = (x[a] - g.lo[a]) * inv - 0.5f;
+      const float c = floorf(sc + 0.5f), u = sc - c;  // nearest centre, offset in [-1/2, 1/2)
+      im.lo_c[a] = (int)c - 1;
+      im.hi_c[a] = im.lo_c[a] + 2;
+      im.cw[a][0] = 0.5f * (0.5f - u) * (0.5f - u);
+      im.cw[a][1] = 0.75f - u * u;
+      im.cw[a][2] = 0.5f * (0.5f + u) * (0.5f + u);
+    }
     im.off[a] = 0;
     if (!g.periodic) continue;
     if (im.lo_c[a] < 0) {
@@ -176,7 +207,7 @@ __device__ __forceinline__ void make_image(const GridDev& g, const float x[3], f
 template <typename F>
 __device__ __forceinline__ void for_images(const GridDev& g, const float x[3], float h, float m,
                                            bool ok, F&& f) {
-  const Images im = images_of(g, x, fmaxf(h, g.cell));
+  const Images im = images_of<kSph>(g, x, fmaxf(h, g.cell));
   for (int img = 0; img < 8; ++img) {
     if ((img & ~im.mask) != 0) continue;
     Particle p;
@@ -226,6 +257,28 @@ __device__ __forceinline__ void for_cells_in(const GridDev& g, const Particle& p
 template <typename F>
 __device__ __forceinline__ void for_cells(const GridDev& g, const Particle& p, F&& f) {
   for_cells_in(g, p, p.c0, p.c1, f);
+}
+
+// Visits the cells of [b0, b1] that an image reaches with (flat index, ix,
+// iy, iz, weight): the M4 profile w(q) for the adaptive kernel, the product
+// of the per-axis stencil weights for the fixed clouds.
+template <int SCH, typename F>
+__device__ __forceinline__ void for_weights(const GridDev& g, const Particle& p, const Images& im,
+                                            const int b0[3], const int b1[3], F&& f) {
+  if constexpr (SCH == kSph) {
+    for_cells_in(g, p, b0, b1, [&](int64_t c, int ix, int iy, int iz, float q, float, float,
+                                   float, float) { f(c, ix, iy, iz, m4_w(q)); });
+  } else {
+    for (int ix = b0[0]; ix <= b1[0]; ++ix) {
+      const float wx = im.cw[0][ix + p.off[0] - im.lo_c[0]];
+      for (int iy = b0[1]; iy <= b1[1]; ++iy) {
+        const float wxy = wx * im.cw[1][iy + p.off[1] - im.lo_c[1]];
+        const int64_t rowb = ((int64_t)ix * g.n[1] + iy) * g.n[2];
+        for (int iz = b0[2]; iz <= b1[2]; ++iz)
+          f(rowb + iz, ix, iy, iz, wxy * im.cw[2][iz + p.off[2] - im.lo_c[2]]);
+      }
+    }
+  }
 }
 
 __global__ void k_zero_f64(double* p, int64_t n) {
@@ -289,6 +342,7 @@ __device__ __forceinline__ bool tile_range(const Particle& p, int t0[3], int t1[
 // all its images; the per-tile entry counts (one per image and overlapped
 // tile); the validity flag for a particle outside the box or with an invalid
 // h.  The gather's scattered reads overlap the support sums.
+template <int SCH>
 __global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
                                                       const float* __restrict__ xin,
                                                       const float* __restrict__ min_,
@@ -305,17 +359,17 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
   if (t < n) {
     const int64_t i = order ? order[t] : t;
     x[0] = xin[3 * i], x[1] = xin[3 * i + 1], x[2] = xin[3 * i + 2];
-    h = hin[i];
+    h = hin ? hin[i] : 0.0f;
     m = min_[i];
     P[t] = make_float4(x[0], x[1], x[2], h);
     M[t] = m;
-    ok = particle_ok(g, x, h);
+    ok = particle_ok<SCH>(g, x, h);
     if (!ok) atomicOr(bad, 1);
   }
   // S in float64: a support of 10^5 cells (H near half the mesh) would
   // drift by 1e-5 in float32
   double S = 0.0;
-  const Images im = images_of(g, x, fmaxf(h, g.cell));
+  const Images im = images_of<SCH>(g, x, fmaxf(h, g.cell));
   // every lane walks the same image numbers (8 at most), so the tile
   // aggregation below runs with the whole wave
   for (int img = 0; img < 8; ++img) {
@@ -326,9 +380,8 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
     int t0[3] = {0, 0, 0}, t1[3] = {-1, -1, -1};
     bool has = false;
     if (mine) {
-      for_cells(g, p, [&](int64_t, int, int, int, float q, float, float, float, float) {
-        S += (double)m4_w(q);
-      });
+      for_weights<SCH>(g, p, im, p.c0, p.c1,
+                       [&](int64_t, int, int, int, float w) { S += (double)w; });
       has = tile_range(p, t0, t1);
     }
     for_tiles_aggregated(tg, t0, t1, has, [&](int tile, uint64_t same, int leader, bool) {
@@ -343,6 +396,7 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
 // Step 3: every image appends its entry (visiting position, and on a
 // periodic mesh the image in the low three bits) to the lists of the tiles
 // its support box overlaps.
+template <int SCH>
 __global__ __launch_bounds__(kPBlock) void k_p2m_scatter(GridDev g, TileGrid tg,
                                                          const float4* __restrict__ P, int64_t n,
                                                          const int64_t* __restrict__ toff,
@@ -354,9 +408,9 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_scatter(GridDev g, TileGrid tg,
   if (t < n) {
     const float4 v = load_packed(P, t);
     x[0] = v.x, x[1] = v.y, x[2] = v.z, h = v.w;
-    ok = particle_ok(g, x, h);
+    ok = particle_ok<SCH>(g, x, h);
   }
-  const Images im = images_of(g, x, fmaxf(h, g.cell));
+  const Images im = images_of<SCH>(g, x, fmaxf(h, g.cell));
   for (int img = 0; img < 8; ++img) {
     const bool mine = t < n && (img & ~im.mask) == 0;
     if (!__any(mine)) continue;
@@ -382,6 +436,7 @@ struct DepositChunk {
 };
 
 // Step 4: one workgroup per chunk of one tile's entry list.
+template <int SCH>
 __global__ __launch_bounds__(kPBlock) void k_p2m_tile(GridDev g, TileGrid tg,
                                                       const float4* __restrict__ P, int64_t n,
                                                       const float* __restrict__ fbuf,
@@ -405,7 +460,7 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_tile(GridDev g, TileGrid tg,
     if ((uint64_t)t >= (uint64_t)n) continue;
     const float4 v = load_packed(P, t);
     const float x[3] = {v.x, v.y, v.z};
-    const Images im = images_of(g, x, fmaxf(v.w, g.cell));
+    const Images im = images_of<SCH>(g, x, fmaxf(v.w, g.cell));
     Particle p;
     make_image(g, x, v.w, 0.0f, true, im, img, p);
     const float f = fbuf[t];
@@ -415,8 +470,7 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_tile(GridDev g, TileGrid tg,
       b0[a] = max(p.c0[a], lo[a]);
       b1[a] = min(p.c1[a], hi[a]);
     }
-    for_cells_in(g, p, b0, b1, [&](int64_t, int ix, int iy, int iz, float q, float, float, float, float) {
-      const float w = m4_w(q);
+    for_weights<SCH>(g, p, im, b0, b1, [&](int64_t, int ix, int iy, int iz, float w) {
       if (w > 0.0f)
         atomicAdd(&tile[((ix - lo[0]) * kT + (iy - lo[1])) * kT + (iz - lo[2])], (double)(f * w));
     });
@@ -552,16 +606,30 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 
 }  // namespace
 
-extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d_h, int64_t n,
-                              const kdt_grid* grid, const int32_t* d_order, float* d_grid,
-                              hipStream_t stream) {
-  kdt_clear_error();
-  if (!d_grid || n < 0 || !grid_ok(grid) || (n > 0 && (!d_x || !d_m || !d_h))) {
-    kdt_set_error("kdt_p2m: NULL pointer, negative n or invalid grid");
+namespace {
+// Calls f with the scheme as a compile-time constant.
+template <typename F>
+void by_scheme(int sch, F&& f) {
+  switch (sch) {
+    case kNgp: f(std::integral_constant<int, kNgp>()); break;
+    case kCic: f(std::integral_constant<int, kCic>()); break;
+    case kTsc: f(std::integral_constant<int, kTsc>()); break;
+    default: f(std::integral_constant<int, kSph>()); break;
+  }
+}
+}  // namespace
+
+// The binned deposit of either scheme (d_h NULL for the fixed clouds); `who`
+// names the entry point in messages.
+static kdt_status p2m_forward(int sch, const char* who, const float* d_x, const float* d_m,
+                              const float* d_h, int64_t n, const kdt_grid* grid,
+                              const int32_t* d_order, float* d_grid, hipStream_t stream) {
+  if (!d_grid || n < 0 || !grid_ok(grid) || (n > 0 && (!d_x || !d_m || (sch == kSph && !d_h)))) {
+    kdt_set_error("%s: NULL pointer, negative n or invalid grid", who);
     return KDT_EINVAL;
   }
   if (n > INT32_MAX || (grid->periodic && n >= (int64_t(1) << 28))) {
-    kdt_set_error("kdt_p2m: n = %lld above %s", (long long)n,
+    kdt_set_error("%s: n = %lld above %s", who, (long long)n,
                   grid->periodic ? "2^28 - 1 (periodic mesh)" : "2^31 - 1");
     return KDT_EUNSUPPORTED;
   }
@@ -573,7 +641,7 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
     n_tiles *= tg.nt[a];
   }
   if (n_tiles > INT32_MAX / 2) {
-    kdt_set_error("kdt_p2m: mesh too large (%lld tiles of %d^3 cells)", (long long)n_tiles, kT);
+    kdt_set_error("%s: mesh too large (%lld tiles of %d^3 cells)", who, (long long)n_tiles, kT);
     return KDT_EUNSUPPORTED;
   }
   // scratch kept on the stream between calls: the packed particles, m / S
@@ -584,7 +652,7 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
   const size_t a_t = align256(sizeof(uint32_t) * ((size_t)n_tiles + 64));
   char* s0 = static_cast<char*>(stream_scratch(stream, kSlotParticles, a_p + 2 * a_n + a_t));
   if (!s0) {
-    kdt_set_error("kdt_p2m: device allocation failed");
+    kdt_set_error("%s: device allocation failed", who);
     return KDT_ENOMEM;
   }
   float4* P = reinterpret_cast<float4*>(s0);
@@ -596,20 +664,22 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
   k_fill_u32<<<gt, 256, 0, stream>>>(tcount, n_tiles + 64, 0u);
   const unsigned gp = (unsigned)((n + kPBlock - 1) / kPBlock);
   if (n > 0)
-    k_p2m_prep<<<gp, kPBlock, 0, stream>>>(g, tg, d_x, d_m, d_h, n, d_order, P, M, fbuf, tcount,
-                                           bad);
+    by_scheme(sch, [&](auto c) {
+      k_p2m_prep<decltype(c)::value><<<gp, kPBlock, 0, stream>>>(g, tg, d_x, d_m, d_h, n, d_order,
+                                                                 P, M, fbuf, tcount, bad);
+    });
   // the per-tile counts size the lists: read them back (with the check flag)
   std::vector<uint32_t> cnt((size_t)n_tiles + 1);
   hipError_t e = hipMemcpyAsync(cnt.data(), tcount, sizeof(uint32_t) * (n_tiles + 1),
                                 hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
-    kdt_set_error("kdt_p2m: %s", hipGetErrorString(e));
+    kdt_set_error("%s: %s", who, hipGetErrorString(e));
     return KDT_EDEVICE;
   }
   if (cnt[n_tiles] != 0) {
-    kdt_set_error("kdt_p2m: a particle lies outside the grid or has an invalid smoothing "
-                  "length (on a periodic mesh H must stay below half of every period)");
+    kdt_set_error("%s: a particle lies outside the grid or has an invalid smoothing "
+                  "length (on a periodic mesh H must stay below half of every period)", who);
     return KDT_EINVAL;
   }
   // lay out the lists and cut them into chunks; tiles of several chunks get
@@ -661,7 +731,7 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
   double* partial = static_cast<double*>(
       stream_scratch(stream, kSlotPartial, sizeof(double) * kTileCells * std::max(slots, 1)));
   if (!s1 || !partial) {
-    kdt_set_error("kdt_p2m: device allocation failed (%lld particle-tile pairs)", (long long)total);
+    kdt_set_error("%s: device allocation failed (%lld particle-tile pairs)", who, (long long)total);
     return KDT_ENOMEM;
   }
   int32_t* pairs = reinterpret_cast<int32_t*>(s1);
@@ -677,28 +747,55 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
     e = hipMemcpyAsync(d_split, split.data(), sizeof(SplitTile) * split.size(),
                        hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) {
-    kdt_set_error("kdt_p2m: %s", hipGetErrorString(e));
+    kdt_set_error("%s: %s", who, hipGetErrorString(e));
     return KDT_EDEVICE;
   }
   k_fill_u32<<<gt, 256, 0, stream>>>(tcount, n_tiles, 0u);  // reused as list fill counters
-  if (n > 0)
-    k_p2m_scatter<<<gp, kPBlock, 0, stream>>>(g, tg, P, n, d_toff, tcount, pairs);
-  k_p2m_tile<<<(unsigned)chunks.size(), kPBlock, 0, stream>>>(g, tg, P, n, fbuf, pairs, d_chunks,
-                                                              d_grid, partial);
+  by_scheme(sch, [&](auto c) {
+    constexpr int S = decltype(c)::value;
+    if (n > 0) k_p2m_scatter<S><<<gp, kPBlock, 0, stream>>>(g, tg, P, n, d_toff, tcount, pairs);
+    k_p2m_tile<S><<<(unsigned)chunks.size(), kPBlock, 0, stream>>>(g, tg, P, n, fbuf, pairs,
+                                                                   d_chunks, d_grid, partial);
+  });
   if (!split.empty())
     k_p2m_reduce<<<dim3((unsigned)split.size(), kTileCells / kPBlock), kPBlock, 0, stream>>>(
         g, tg, d_split, partial, d_grid);
   if (hipGetLastError() != hipSuccess) {
-    kdt_set_error("kdt_p2m: kernel launch failed");
+    kdt_set_error("%s: kernel launch failed", who);
     return KDT_EDEVICE;
   }
   // the host tables above must outlive their copies
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
-    kdt_set_error("kdt_p2m: %s", hipGetErrorString(e));
+    kdt_set_error("%s: %s", who, hipGetErrorString(e));
     return KDT_EDEVICE;
   }
   return KDT_OK;
+}
+
+extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d_h, int64_t n,
+                              const kdt_grid* grid, const int32_t* d_order, float* d_grid,
+                              hipStream_t stream) {
+  kdt_clear_error();
+  return p2m_forward(kSph, "kdt_p2m", d_x, d_m, d_h, n, grid, d_order, d_grid, stream);
+}
+
+extern "C" kdt_status kdt_p2m_cloud(const float* d_x, const float* d_m, int64_t n,
+                                    const kdt_grid* grid, int32_t scheme, const int32_t* d_order,
+                                    float* d_grid, hipStream_t stream) {
+  kdt_clear_error();
+  if (scheme < kNgp || scheme > kTsc) {
+    kdt_set_error("kdt_p2m_cloud: scheme %d is not 1 (NGP), 2 (CIC) or 3 (TSC)", scheme);
+    return KDT_EINVAL;
+  }
+  if (grid && grid->periodic)
+    for (int a = 0; a < 3; ++a)
+      if (grid->n[a] < scheme) {
+        kdt_set_error("kdt_p2m_cloud: a periodic mesh needs at least %d cells per axis", scheme);
+        return KDT_EINVAL;
+      }
+  return p2m_forward(scheme, "kdt_p2m_cloud", d_x, d_m, nullptr, n, grid, d_order, d_grid,
+                     stream);
 }
 
 extern "C" kdt_status kdt_p2m_backward(const float* d_x, const float* d_m, const float* d_h,

@@ -25,7 +25,7 @@ DIMS = (2, 3, 4, 8, 16)
 # Every exported entry point of include/kdt.h.
 EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt_tree_nodes",
            "kdt_knn",
-           "kdt_range", "kdt_box", "kdt_fof", "kdt_fof_torus", "kdt_p2m", "kdt_p2m_backward",
+           "kdt_range", "kdt_box", "kdt_fof", "kdt_fof_torus", "kdt_p2m", "kdt_p2m_cloud", "kdt_p2m_backward",
            "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
            "kdt_last_error")
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_fof.argtypes = [vp, f32, vp, C.POINTER(C.c_int64), vp]
     lib.kdt_fof_torus.argtypes = [vp, f32, C.POINTER(C.c_float), vp, C.POINTER(C.c_int64), vp]
     lib.kdt_p2m.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp]
+    lib.kdt_p2m_cloud.argtypes = [vp, vp, i64, C.POINTER(Grid), i32, vp, vp, vp]
     lib.kdt_p2m_backward.argtypes = [vp, vp, vp, i64, C.POINTER(Grid), vp, vp, vp, vp, vp]
     lib.kdt_query_order.argtypes = [vp, vp, i64, C.c_int32, vp, vp]
     lib.kdt_tree_perm.argtypes = [vp]
@@ -365,6 +366,24 @@ def p2m(x: torch.Tensor, m: torch.Tensor, h: torch.Tensor, lo, cell: float, shap
     g = make_grid(lo, cell, shape, periodic)
     _check(load().kdt_p2m(_ptr(x), _ptr(m), _ptr(h), n, C.byref(g), order_ptr, _ptr(out),
                           _stream(stream)))
+    return out
+
+
+CLOUD_SCHEMES = {"ngp": 1, "cic": 2, "tsc": 3}
+
+
+def p2m_cloud(x: torch.Tensor, m: torch.Tensor, lo, cell: float, shape, scheme: str,
+              order_ptr: int | None = None, out: torch.Tensor | None = None, stream=None,
+              periodic: bool = False):
+    """Fixed-cloud deposit ("ngp", "cic" or "tsc"): float32 mass per cell."""
+    n = x.shape[0]
+    x = _dev(x, torch.float32, "x", (n, 3))
+    m = _dev(m, torch.float32, "m", (n,))
+    if out is None:
+        out = torch.empty(tuple(shape), dtype=torch.float32, device=x.device)
+    g = make_grid(lo, cell, shape, periodic)
+    _check(load().kdt_p2m_cloud(_ptr(x), _ptr(m), n, C.byref(g), CLOUD_SCHEMES[scheme],
+                                order_ptr, _ptr(out), _stream(stream)))
     return out
 
 

@@ -210,6 +210,45 @@ def test_periodic_deposit_full_size_corner_and_faces(clustered):
     assert np.linalg.norm(gx_s - ox) <= 1e-4 * np.linalg.norm(ox)
 
 
+@pytest.mark.parametrize("scheme", ("cic", "tsc"))
+def test_cloud_deposit_full_size(clustered, scheme):
+    """The fixed-cloud comparison of Table 3 at the full size: 2^24 particles
+    on 256^3, periodic and open, total mass and sub-volumes against the
+    oracle over the particles within reach."""
+    x, q, xt, qt, tree, ot = clustered
+    g = 256
+    cell = 1.0 / g
+    m = workloads.masses(N, seed=5)
+    total = float(m.astype(np.float64).sum())
+    mean = total / g ** 3
+    for periodic in (False, True):
+        say(f"{scheme} deposit of 2^24 particles on 256^3, periodic={periodic}")
+        rho = to_host(kdt.p2m_cloud(xt, to_dev(m), (0, 0, 0), cell, (g, g, g), scheme,
+                                    order_ptr=tree.perm_ptr, periodic=periodic))
+        assert abs(float(rho.astype(np.float64).sum()) - total) <= 1e-5 * total
+        # sub-volumes at a corner and across the z faces (periodic) or inside
+        for lo_c in ((0, 0, 0), (100, 37, 250) if periodic else (100, 37, 240)):
+            reach = 2 * cell
+            cx = [np.arange(c, c + 16) % g for c in lo_c]
+            lo = np.array(lo_c) * cell
+            hi = (np.array(lo_c) + 16) * cell
+            near = np.ones(N, bool)
+            for a in range(3):
+                d = np.maximum(np.maximum(lo[a] - x[:, a], x[:, a] - hi[a]), 0.0)
+                if periodic:
+                    d = np.minimum(d, np.maximum(lo[a] - (x[:, a] - 1.0), 0.0))
+                    d = np.minimum(d, np.maximum((x[:, a] + 1.0) - hi[a], 0.0))
+                near &= d < reach
+            sel = np.nonzero(near)[0]
+            o = oracle.p2m_cloud(x[sel], m[sel], (0, 0, 0), cell, (g, g, g), scheme,
+                                 periodic=periodic)
+            og, gg = o[np.ix_(*cx)], rho[np.ix_(*cx)].astype(np.float64)
+            ratio = np.abs(gg - og) / (1e-5 * np.maximum(np.abs(og), mean))
+            worst = np.unravel_index(np.argmax(ratio), ratio.shape)
+            assert (ratio <= 1).all(), (periodic, lo_c, float(ratio.max()), worst,
+                                        float(gg[worst]), float(og[worst]), len(sel))
+
+
 @pytest.mark.parametrize("d", (2, 4, 8, 16))
 @pytest.mark.parametrize("dist", ("uniform", "normal"))
 def test_dimension_sweep_full_size_sampled(d, dist):
