@@ -86,6 +86,10 @@ def parse():
     ap.add_argument("--no-midpoint", action="store_true")
     ap.add_argument("--no-cloud", action="store_true")
     ap.add_argument("--no-grf", action="store_true")
+    ap.add_argument("--no-workcount", action="store_true")
+    ap.add_argument("--valu-calibration", action="store_true",
+                    help="only run the VALU-only probe kernel, the reference the counted "
+                         "VALU instructions of the other kernels are read against")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of 1 GiB (read once, written once), the "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -94,6 +98,22 @@ def parse():
 
 def linking_length(n: int) -> float:
     return float(np.float32(FOF_B * (1.0 / n) ** (1.0 / 3.0)))
+
+
+def workcount():
+    """Counts of the instrumented library for the benchmarked launches (a
+    child process: it loads libkdt_counts.so), or None if it is not built."""
+    import subprocess
+    from paper_2609_18316_amd import kdt
+    if not os.path.exists(kdt.LIB_COUNTS_PATH):
+        return None
+    print("[bench] counting traversal work (instrumented library)", file=sys.stderr, flush=True)
+    r = subprocess.run([sys.executable, "-m", "paper_2609_18316_amd.workcount"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=600)
+    sys.stderr.write(r.stderr[-2000:])
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def host_cpu():
@@ -190,6 +210,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.valu_calibration:
+        kdt.load()
+        kdt.valu_probe()
+        torch.cuda.synchronize()
+        print(json.dumps({"valu_probe": {"blocks": 8192, "threads": 256, "iters": 20000,
+                                         "valu_per_iter": 16}}))
+        return
     if args.copy_calibration:
         a = torch.ones(1 << 28, device="cuda:0")
         b = torch.empty_like(a)
@@ -516,6 +543,26 @@ def main():
         print(f"[bench] GRF mock: {out['grf']}", file=sys.stderr, flush=True)
     if not args.no_dsweep:
         out["dsweep"] = dimension_sweep(torch, kdt, workloads, dev)
+    if not args.no_workcount:
+        # Algorithmic bytes of the kNN launch: the compulsory term (queries
+        # in, results out) plus the traversal term, leaf points scanned x
+        # record bytes + node boxes read x box bytes, counted by the
+        # instrumented library in a child process on the same launch.
+        wc = workcount()
+        if wc:
+            out["workcount"] = wc
+            kc = wc["knn_c2"]
+            trav = kc["lane_points"] * kc["record_bytes"] + kc["lane_nodes"] * kc["box_bytes"]
+            rf = out["roofline"]
+            rf["algorithmic_bytes"] = {
+                "compulsory": knn_bytes, "traversal": trav,
+                "leaf_points_per_query": kc["lane_points"] / N_QUERIES,
+                "nodes_per_query": kc["lane_nodes"] / N_QUERIES,
+                "reloads_per_query": kc["lane_inserts"] / N_QUERIES}
+            rf["compulsory_frac"] = rf["frac"]
+            rf["achieved"] = (knn_bytes + trav) / (avg["knn"] * 1e-3) / 1e9
+            rf["frac"] = rf["achieved"] / HBM_PEAK_GBS
+            rf["kernel"] += "; traversal bytes: leaf points x 16 + node boxes x 32"
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(x, q, args.cpu_queries, args.cpu_queries_threaded)

@@ -1,0 +1,51 @@
+/*
+ * kdt_debug.h -- test and measurement hooks of the k-d tree library.  Not
+ * for production use; every call is cheap and allocates nothing.
+ */
+#ifndef KDT_DEBUG_H
+#define KDT_DEBUG_H
+
+#include "kdt.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * Makes the `after`-th next device allocation of the library (counting
+ * from 1, process-wide) fail as if the device were out of memory, so that
+ * tests can check the KDT_ENOMEM paths; after <= 0 disarms the hook.
+ * Allocations of batched plans (plain hipMalloc at plan creation) are not
+ * covered.
+ */
+kdt_status kdt_debug_fail_alloc(int64_t after);
+
+/*
+ * Work counters of the instrumented build of the library (compiled with
+ * KDT_COUNT_VISITS; the product build returns KDT_EUNSUPPORTED): waits for
+ * the device, then writes 8 uint64 totals to h_counts (host, may be NULL)
+ * and zeroes the counters if `reset`.  Slots: 0 nodes visited (node boxes
+ * tested) and 1 leaf point records scanned by the traversals with one query
+ * per lane, 2 records read again to insert a kNN candidate, 3 node boxes and
+ * 4 leaf points read by the wave-shared traversals (once per wave), 5 boxes
+ * read again when a node leaves a per-lane stack; 6-7 unused.  They give the traversal term of the algorithmic bytes of a call:
+ * points x record bytes + nodes x box bytes.
+ */
+kdt_status kdt_debug_visits(uint64_t *h_counts, int32_t reset);
+
+/*
+ * Launches a kernel of `blocks` workgroups of 256 threads that only issues
+ * VALU instructions (eight independent multiply-add chains per lane, `iters`
+ * rounds, 16 float32 instructions per round), asynchronously on `stream`.
+ * Profiled with the same counters as the library's kernels, it gives the
+ * chip's VALU issue rate that their instruction counts are read against.
+ * d_out [blocks] float32 (device) is never written in practice.
+ */
+kdt_status kdt_debug_valu_probe(float *d_out, int32_t blocks, int32_t iters,
+                                hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDT_DEBUG_H */

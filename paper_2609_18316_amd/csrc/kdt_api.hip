@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <list>
 #include <map>
 #include <memory>
@@ -13,7 +14,8 @@
 #include <string>
 #include <vector>
 
-#include "kdt_internal.h"
+#include "kdt_debug.h"
+#include "kdt_query.h"
 
 static thread_local std::string g_error;
 
@@ -51,6 +53,33 @@ std::mutex g_scratch_mu;
 // never destroyed: device memory is not released from static destructors
 std::map<ScratchKey, ScratchBuf>* g_scratch = new std::map<ScratchKey, ScratchBuf>();
 }  // namespace
+
+namespace {
+std::atomic<int64_t> g_fail_after{-1};
+}  // namespace
+
+bool alloc_should_fail() {
+  int64_t v = g_fail_after.load();
+  while (v > 0) {
+    if (g_fail_after.compare_exchange_weak(v, v - 1)) return v == 1;
+  }
+  return false;
+}
+
+unsigned long long* visit_counters() {
+#ifdef KDT_COUNT_VISITS
+  static unsigned long long* buf = nullptr;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const size_t bytes = sizeof(unsigned long long) * kVisitSlots * kVisitShards;
+    if (hipMalloc((void**)&buf, bytes) != hipSuccess || hipMemset(buf, 0, bytes) != hipSuccess)
+      buf = nullptr;
+  });
+  return buf;
+#else
+  return nullptr;
+#endif
+}
 
 void* stream_scratch(hipStream_t stream, int slot, size_t bytes) {
   int dev = 0;
@@ -361,5 +390,69 @@ extern "C" kdt_status kdt_tree_export(const kdt_tree* tree, float* h_pts, int32_
       if (h_lo) h_lo[v * d + a] = box[(size_t)v * 2 * P + a];
       if (h_hi) h_hi[v * d + a] = box[(size_t)v * 2 * P + P + a];
     }
+  return KDT_OK;
+}
+
+extern "C" kdt_status kdt_debug_fail_alloc(int64_t after) {
+  kdt_clear_error();
+  g_fail_after.store(after > 0 ? after : -1);
+  return KDT_OK;
+}
+
+extern "C" kdt_status kdt_debug_visits(uint64_t* h_counts, int32_t reset) {
+  kdt_clear_error();
+  unsigned long long* d = visit_counters();
+  if (!d) {
+    kdt_set_error("kdt_debug_visits: this library was built without work counters");
+    return KDT_EUNSUPPORTED;
+  }
+  unsigned long long h[kVisitSlots * kVisitShards];
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+      (reset && hipMemset(d, 0, sizeof(h)) != hipSuccess)) {
+    kdt_set_error("kdt_debug_visits: reading the counters failed");
+    return KDT_EDEVICE;
+  }
+  if (h_counts)
+    for (int s = 0; s < kVisitSlots; ++s) {
+      uint64_t sum = 0;
+      for (int k = 0; k < kVisitShards; ++k) sum += h[s * kVisitShards + k];
+      h_counts[s] = sum;
+    }
+  return KDT_OK;
+}
+
+namespace {
+// Eight independent multiply-add chains per lane (each a separate multiply and
+// add: the library is built without contraction or packed float32): a kernel
+// that does nothing but issue VALU instructions, for calibrating the VALU
+// issue rate that the counters of the other kernels are read against.
+__global__ __launch_bounds__(256) void k_valu_probe(float* out, int iters) {
+  float a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = (float)(threadIdx.x + j) * 1e-3f;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = a[j] * 0.9999f + 1e-4f;
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s += a[j];
+  if (s == 12345.678f) out[blockIdx.x] = s;  // keeps the chains live; never true
+}
+}  // namespace
+
+extern "C" kdt_status kdt_debug_valu_probe(float* d_out, int32_t blocks, int32_t iters,
+                                           hipStream_t stream) {
+  kdt_clear_error();
+  if (!d_out || blocks < 1 || iters < 1) {
+    kdt_set_error("kdt_debug_valu_probe: NULL output or non-positive size");
+    return KDT_EINVAL;
+  }
+  k_valu_probe<<<blocks, 256, 0, stream>>>(d_out, iters);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_debug_valu_probe: launch failed");
+    return KDT_EDEVICE;
+  }
   return KDT_OK;
 }

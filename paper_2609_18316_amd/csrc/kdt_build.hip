@@ -978,6 +978,7 @@ static void set_smem_attr(int cap) {
 }
 
 hipError_t dev_alloc(void** ptr, size_t bytes, hipStream_t stream) {
+  if (alloc_should_fail()) return hipErrorOutOfMemory;
   static std::once_flag once;
   std::call_once(once, [] {
     int dev = 0;

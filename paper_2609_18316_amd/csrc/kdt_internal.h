@@ -211,7 +211,14 @@ void build_scratch_free(BuildScratch& w, hipStream_t stream);
 kdt_status build_launch(const Plan& p, const PlanDev& pd, const float* d_pts,
                         const BuildScratch& w, const BuildOut& o, int phase, hipStream_t stream);
 // Stream-ordered device allocation from the default pool (kept cached).
+// Fails on purpose when the allocation-failure hook (kdt_debug_fail_alloc)
+// says so.
 hipError_t dev_alloc(void** ptr, size_t bytes, hipStream_t stream);
+// True if the allocation-failure hook wants this allocation to fail.
+bool alloc_should_fail();
+// The device counters of the instrumented build (KDT_COUNT_VISITS), else
+// NULL; traversal views carry them.
+unsigned long long* visit_counters();
 
 // Scratch that an entry point keeps on its stream from one call to the next:
 // slot `slot` of (current device, stream) holds at least `bytes` bytes,

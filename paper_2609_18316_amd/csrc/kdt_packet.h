@@ -249,6 +249,7 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
     const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)stackv, sp);
     float lo[D], hi[D];
     load_box_uniform<D>(t.box, node, lo, hi);
+    KDT_WAVE_VISIT(t, kVisitWaveNodes, 1);
     const bool need = active && box_mindist<D>(lo, hi, p) <= best.worst_d2();
     if (!__any(need)) continue;
     if (node >= first_leaf) {
@@ -256,6 +257,7 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       const int64_t b = node_begin(t.n, t.levels, j), e = node_begin(t.n, t.levels, j + 1);
       const int cnt = (int)(e - b);
       leaf.open(b, cnt);
+      KDT_WAVE_VISIT(t, kVisitWavePoints, cnt);
       // Mark the leaf points (at most 64) that beat this lane's current k-th
       // candidate; the rounds above then insert them, so the wave pays for
       // the largest per-lane count of insertions rather than for every point
@@ -315,6 +317,7 @@ __device__ __forceinline__ void packet_knn(const TreeView& t, const float p[D], 
       }
     } else {
       const uint32_t c0 = 2 * node + 1, c1 = c0 + 1;
+      KDT_WAVE_VISIT(t, kVisitWaveNodes, 2);
       load_box_uniform<D>(t.box, c0, lo, hi);
       const float d0 = box_mindist<D>(lo, hi, p);
       load_box_uniform<D>(t.box, c1, lo, hi);
@@ -590,6 +593,7 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const S
     const bool mine = active && ((live >> lane) & 1ull);
     float lo[D], hi[D];
     load_box_uniform<D>(t.box, node, lo, hi);
+    KDT_WAVE_VISIT(t, kVisitWaveNodes, 1);
     const bool touch = mine && sh.cuts(lo, hi);
     if (!__any(touch)) continue;
     const bool full = touch && sh.holds_box(lo, hi);
@@ -603,6 +607,7 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const S
     if (node >= first_leaf) {
       const int cnt = (int)(e - b);
       leaf.open(b, cnt);
+      KDT_WAVE_VISIT(t, kVisitWavePoints, cnt);
       const int na = __popcll(pm);
       const int W = cnt <= 8 ? 8 : cnt <= 16 ? 16 : cnt <= 32 ? 32 : 64;
       const int G = 64 / W;

@@ -14,7 +14,39 @@ struct TreeView {
   int64_t n;
   int32_t levels;    // depth of the deepest leaf
   const int4* nodes = nullptr;  // stored node records (sliding-midpoint trees), else NULL
+  unsigned long long* visits = nullptr;  // work counters of the instrumented build, else NULL
 };
+
+// Work counters of the instrumented build (compiled with KDT_COUNT_VISITS):
+// how many node boxes and point records the traversals read, for the
+// algorithmic bytes of the roofline.  Slots: kVisitNodes / kVisitPoints /
+// kVisitInsert for one traversal per lane (nodes visited, i.e. node boxes
+// tested -- the root and both children of every expanded node --, leaf
+// records scanned, records read again to insert a candidate), kVisitReload
+// for a box read again when its node leaves the stack (the stack keeps node
+// ids only), kVisitWaveNodes / kVisitWavePoints for the wave-shared
+// traversals (one box read and one leaf staged into LDS count once per
+// wave).  Each slot has kVisitShards
+// counters (workgroup b adds to shard b % kVisitShards).  In the product
+// build the macros compile to nothing.
+enum : int { kVisitNodes = 0, kVisitPoints = 1, kVisitInsert = 2, kVisitWaveNodes = 3,
+             kVisitWavePoints = 4, kVisitReload = 5, kVisitSlots = 8 };
+constexpr int kVisitShards = 64;
+#ifdef KDT_COUNT_VISITS
+__device__ __forceinline__ void count_visit(const TreeView& t, int slot, uint32_t n) {
+  if (t.visits)
+    atomicAdd(t.visits + slot * kVisitShards + (blockIdx.x % kVisitShards),
+              (unsigned long long)n);
+}
+#define KDT_LANE_VISIT(t, slot, n) count_visit((t), (slot), (uint32_t)(n))
+#define KDT_WAVE_VISIT(t, slot, n)                                  \
+  do {                                                              \
+    if (lane_id() == 0) count_visit((t), (slot), (uint32_t)(n));    \
+  } while (0)
+#else
+#define KDT_LANE_VISIT(t, slot, n) ((void)0)
+#define KDT_WAVE_VISIT(t, slot, n) ((void)0)
+#endif
 
 // Node layout of a tree, as the traversals see it.  A median tree is
 // implicit: node (l, j) sits at 2^l - 1 + j, its children at 2v + 1 and
@@ -284,6 +316,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
   const int lmax = (int)((t.n + (int64_t(1) << t.levels) - 1) >> t.levels);
   float lo[D], hi[D];
   load_box<D>(t.box, 0, lo, hi);
+  KDT_LANE_VISIT(t, kVisitNodes, 1);
   uint32_t node = 0;
   float nd = metric.mindist(lo, hi, p);
   int sp = 0;
@@ -292,6 +325,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
       if (sh.is_leaf(node)) {
         int64_t b, e;
         sh.range(node, b, e);
+        KDT_LANE_VISIT(t, kVisitPoints, e - b);
         // Two passes per block of up to 64 leaf points.  The first computes
         // every distance and marks the points that can enter the list (float
         // test against the current k-th distance, ties kept); the second
@@ -331,6 +365,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
               if (metric.dist(x, p) <= w) mask |= 1ull << i;
             }
           }
+          KDT_LANE_VISIT(t, kVisitInsert, __popcll(mask));
           while (mask) {
             const int i = __builtin_ctzll(mask);
             mask &= mask - 1;
@@ -342,6 +377,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
         }
       } else {
         const uint32_t c0 = sh.left(node), c1 = c0 + 1;
+        KDT_LANE_VISIT(t, kVisitNodes, 2);
         load_box<D>(t.box, c0, lo, hi);
         const float d0 = metric.mindist(lo, hi, p);
         load_box<D>(t.box, c1, lo, hi);
@@ -359,6 +395,7 @@ __device__ __forceinline__ void knn_one(const TreeView& t, const float p[D], Lis
     // only the node id is kept on the stack; its box distance is recomputed
     // (the box is cache-resident), halving the stack's LDS footprint
     node = stk[--sp * ld];
+    KDT_LANE_VISIT(t, kVisitReload, 1);
     load_box<D>(t.box, node, lo, hi);
     nd = metric.mindist(lo, hi, p);
   }

@@ -235,6 +235,7 @@ static TreeView view_of(const kdt_tree* t) {
   v.n = t->n;
   v.levels = t->levels;
   v.nodes = t->nodes;
+  v.visits = visit_counters();
   return v;
 }
 

@@ -29,6 +29,9 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
            "kdt_last_error")
+# The test and measurement hooks of include/kdt_debug.h.
+DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe")
+LIB_COUNTS_PATH = os.path.join(HERE, "libkdt_counts.so")
 NOALLOC_MAX_SORTED = 1 << 22   # queries kdt_knn_noalloc can order in its static scratch
 
 
@@ -105,12 +108,40 @@ def load(path: str = LIB_PATH):
                                               C.POINTER(QueryOpts), C.POINTER(vp)]
         lib.kdt_batch_launch.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp]
         lib.kdt_batch_plan_free.argtypes = [vp]
+    lib.kdt_debug_fail_alloc.argtypes = [i64]
+    lib.kdt_debug_visits.argtypes = [vp, i32]
+    lib.kdt_debug_valu_probe.argtypes = [vp, i32, i32, vp]
     lib.kdt_last_error.restype = C.c_char_p
-    for name in EXPORTS:
+    for name in EXPORTS + DEBUG_EXPORTS:
         if name not in ("kdt_last_error", "kdt_tree_perm") and hasattr(lib, name):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+def fail_alloc(after: int) -> None:
+    """Test hook: the after-th next device allocation fails (<= 0 disarms)."""
+    _check(load().kdt_debug_fail_alloc(int(after)))
+
+
+VISIT_SLOTS = ("lane_nodes", "lane_points", "lane_inserts", "wave_nodes", "wave_points",
+               "lane_node_reloads")
+
+
+def visits(reset: bool = True) -> dict:
+    """Work counters of the instrumented library (load it with
+    ``load(LIB_COUNTS_PATH)`` first): node boxes and point records read by
+    the traversals since the last reset."""
+    import numpy as np
+    out = np.zeros(8, np.uint64)
+    _check(load().kdt_debug_visits(out.ctypes.data, 1 if reset else 0))
+    return {k: int(out[i]) for i, k in enumerate(VISIT_SLOTS)}
+
+
+def valu_probe(blocks: int = 8192, iters: int = 20000, stream=None) -> None:
+    """Runs the VALU-only calibration kernel (see include/kdt_debug.h)."""
+    out = torch.empty(blocks, dtype=torch.float32, device="cuda")
+    _check(load().kdt_debug_valu_probe(_ptr(out), int(blocks), int(iters), _stream(stream)))
 
 
 def _check(rc: int):

@@ -10,22 +10,28 @@ from paper_2609_18316_amd import kdt
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    src = open(os.path.join(ROOT, "include", "kdt.h")).read()
+def declared_symbols(header="kdt.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(kdt_[a-z_0-9]+)\s*\(", src)))
+
+
+def all_declared_symbols():
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    return sorted(set(sum((declared_symbols(h) for h in headers), [])))
 
 
 def test_header_declares_the_binding_surface():
     names = declared_symbols()
     assert set(names) == set(kdt.EXPORTS), names
+    assert set(declared_symbols("kdt_debug.h")) == set(kdt.DEBUG_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(kdt.LIB_PATH):
         pytest.fail("libkdt.so is not built (run __graft_entry__.build())")
     lib = kdt.load()
-    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    missing = [n for n in all_declared_symbols() if not hasattr(lib, n)]
     assert not missing, missing
 
 
