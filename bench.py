@@ -42,30 +42,17 @@ HBM_PEAK_GBS = 8000.0
 BATCH_SETS = 256
 
 
-# Hardware counters of the kNN traversal kernel (k_knn_lane<3,32,false>, one launch
-# over the 2^22 queries), taken with rocprofv3 --pmc on MI355X: FETCH_SIZE
-# and WRITE_SIZE (KiB per dispatch) in two runs, FETCH_SIZE scaled by 2.0 and
-# WRITE_SIZE by 1.0 -- the factors that turn the same counters of a plain
-# 1 GiB read + 1 GiB write kernel into its bytes -- and TCC_HIT / TCC_MISS,
-# SQ_INSTS_VALU.  They describe the kernel built from the sources whose hash
-# is given; for any other source they are not reported.
-KNN_COUNTERS = {
-    "sources": ["paper_2609_18316_amd/csrc/kdt_query.h", "paper_2609_18316_amd/csrc/kdt_query.hip",
-                "paper_2609_18316_amd/csrc/kdt_internal.h", "paper_2609_18316_amd/build_lib.py"],
-    "sha256": "685ecaf95849e47d71f9767899391295a182fde66289de689586d34028cbf7a2",
-    "hbm_bytes": 2.1450e+09,
-    "l2_hit_rate": 0.964,
-    "valu_issue_frac": 0.71,
-}
-
-
-def sources_hash(paths) -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+# Hardware counter passes, each a child run of this script under
+# rocprofv3 --pmc (counters are read by the profiler around the program, so
+# they cannot be taken from inside it).  The child replays three launches:
+# the VALU-only probe (known instruction count: the issue-rate reference),
+# a plain 1 GiB copy (the reference that scales FETCH_SIZE and WRITE_SIZE,
+# in KiB per dispatch, to bytes) and the kNN traversal of the timed step.
+COUNTER_PASSES = (("FETCH_SIZE",), ("WRITE_SIZE",), ("TCC_HIT_sum", "TCC_MISS_sum"),
+                  ("SQ_WAVES", "SQ_INSTS_VALU", "GRBM_GUI_ACTIVE"))
+KNN_KERNEL = "k_knn_lane<3, 32, false"
+COPY_BYTES = 1 << 30
+N_XCD = 8  # GRBM_GUI_ACTIVE is summed over the chip's 8 XCDs
 
 
 def parse():
@@ -87,13 +74,106 @@ def parse():
     ap.add_argument("--no-cloud", action="store_true")
     ap.add_argument("--no-grf", action="store_true")
     ap.add_argument("--no-workcount", action="store_true")
-    ap.add_argument("--valu-calibration", action="store_true",
-                    help="only run the VALU-only probe kernel, the reference the counted "
-                         "VALU instructions of the other kernels are read against")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain copy of 1 GiB (read once, written once), the "
-                         "reference that scales FETCH_SIZE / WRITE_SIZE counters to bytes")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the rocprofv3 counter passes over the kNN launch")
+    ap.add_argument("--counter-child", action="store_true",
+                    help="(run by the counter passes) only run the VALU probe, a 1 GiB copy "
+                         "and the kNN launch of the step, once each")
     return ap.parse_args()
+
+
+def counter_child(torch, kdt, workloads) -> None:
+    """The launches the counter passes read: the VALU probe, a plain copy of
+    COPY_BYTES, and the step's kNN launch (same inputs, tree and order)."""
+    kdt.load()
+    dev = torch.device("cuda:0")
+    kdt.valu_probe()
+    a = torch.ones(COPY_BYTES // 4, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    xt = torch.from_numpy(workloads.clustered(N_POINTS, seed=2)).to(dev)
+    qt = torch.from_numpy(workloads.uniform(N_QUERIES, 3, seed=102)).to(dev)
+    tree = kdt.build(xt, leaf_size=LEAF, check_finite=True)
+    order = tree.query_order(qt)
+    tree.knn(qt, K, order=order)
+    torch.cuda.synchronize()
+    tree.close()
+
+
+def counter_passes():
+    """Runs the COUNTER_PASSES (a child of this script under rocprofv3 each)
+    and returns the kNN launch's counters, scaled by the references, or a
+    dict with an "error" entry."""
+    import csv
+    import shutil
+    import signal
+    import subprocess
+    import tempfile
+    prof = shutil.which("rocprofv3")
+    if prof is None:
+        return {"error": "rocprofv3 not found"}
+    got = {}
+    env = dict(os.environ, TMPDIR="/tmp")
+    for i, counters in enumerate(COUNTER_PASSES):
+        d = tempfile.mkdtemp(prefix="kdt_pmc_", dir="/tmp")
+        cmd = [prof, "--pmc", *counters, "--output-format", "csv", "-d", d, "-o", "c", "--",
+               sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--counter-child"]
+        print(f"[bench] counter pass {i + 1}/{len(COUNTER_PASSES)}: {' '.join(counters)}",
+              file=sys.stderr, flush=True)
+        p = subprocess.Popen(cmd, cwd="/tmp", env=env, stdout=subprocess.PIPE,
+                             stderr=subprocess.STDOUT, start_new_session=True)
+        try:
+            log, _ = p.communicate(timeout=180)
+        except subprocess.TimeoutExpired:
+            os.killpg(p.pid, signal.SIGKILL)
+            p.communicate()
+            return {"error": f"counter pass {counters} timed out"}
+        path = os.path.join(d, "c_counter_collection.csv")
+        if p.returncode != 0 and not os.path.exists(path):
+            return {"error": f"counter pass {counters} exited {p.returncode}: "
+                             + log.decode(errors="replace")[-300:]}
+        per = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"]
+                who = ("probe" if "k_valu_probe" in name else
+                       "copy" if "copyBuffer" in name else
+                       "knn" if KNN_KERNEL in name else None)
+                if who is None:
+                    continue
+                e = per.setdefault((who, r["Dispatch_Id"]), {
+                    "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+                e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        shutil.rmtree(d, ignore_errors=True)
+        # one dispatch each: the longest (the library's own small copies are
+        # copy dispatches too; the reference copy is the 1 GiB one)
+        for who in ("probe", "copy", "knn"):
+            runs = [e for (w, _), e in per.items() if w == who]
+            if runs:
+                got.setdefault(who, {}).update(max(runs, key=lambda e: e["ns"]))
+    if set(got) != {"probe", "copy", "knn"}:
+        return {"error": f"counter passes found {sorted(got)} of probe, copy, knn"}
+    kib = 1024.0
+    fetch_scale = COPY_BYTES / (got["copy"]["FETCH_SIZE"] * kib)
+    write_scale = COPY_BYTES / (got["copy"]["WRITE_SIZE"] * kib)
+    k, pr = got["knn"], got["probe"]
+    fetch = k["FETCH_SIZE"] * kib * fetch_scale
+    write = k["WRITE_SIZE"] * kib * write_scale
+    probe_rate = pr["SQ_INSTS_VALU"] / (pr["GRBM_GUI_ACTIVE"] / N_XCD)
+    knn_rate = k["SQ_INSTS_VALU"] / (k["GRBM_GUI_ACTIVE"] / N_XCD)
+    hit, miss = k["TCC_HIT_sum"], k["TCC_MISS_sum"]
+    return {
+        "hbm_fetch_bytes": fetch, "hbm_write_bytes": write, "hbm_bytes": fetch + write,
+        "fetch_scale": fetch_scale, "write_scale": write_scale,
+        "l2_hit_rate": hit / (hit + miss),
+        "valu_per_wave": k["SQ_INSTS_VALU"] / k["SQ_WAVES"],
+        "valu_per_cycle": knn_rate, "probe_valu_per_cycle": probe_rate,
+        "valu_issue_frac": knn_rate / probe_rate,
+        "clock_ghz": k["GRBM_GUI_ACTIVE"] / N_XCD / k["ns"],
+    }
 
 
 def linking_length(n: int) -> float:
@@ -210,20 +290,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    if args.valu_calibration:
-        kdt.load()
-        kdt.valu_probe()
-        torch.cuda.synchronize()
-        print(json.dumps({"valu_probe": {"blocks": 8192, "threads": 256, "iters": 20000,
-                                         "valu_per_iter": 16}}))
-        return
-    if args.copy_calibration:
-        a = torch.ones(1 << 28, device="cuda:0")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
+    if args.counter_child:
+        counter_child(torch, kdt, workloads)
         return
     kdt.load()
     dev = torch.device("cuda:0")
@@ -350,12 +418,6 @@ def main():
                      "kernel": "k_knn_lane<3,32,false> (kNN traversal, k=32, one query per lane): "
                                "compulsory bytes 4d + 8k = 268 per query"},
     }
-    if KNN_COUNTERS["sha256"] and sources_hash(KNN_COUNTERS["sources"]) == KNN_COUNTERS["sha256"]:
-        rf = out["roofline"]
-        rf["traffic"] = KNN_COUNTERS["hbm_bytes"]
-        rf["traffic_gbs"] = KNN_COUNTERS["hbm_bytes"] / (avg["knn"] * 1e-3) / 1e9
-        rf["l2_hit_rate"] = KNN_COUNTERS["l2_hit_rate"]
-        rf["valu_issue_frac"] = KNN_COUNTERS["valu_issue_frac"]
     if batch:
         # The baseline (the single-tree entry points once per set, eager) is
         # timed outside the timed steps: it is a comparison, not the path.
@@ -558,11 +620,24 @@ def main():
                 "compulsory": knn_bytes, "traversal": trav,
                 "leaf_points_per_query": kc["lane_points"] / N_QUERIES,
                 "nodes_per_query": kc["lane_nodes"] / N_QUERIES,
-                "reloads_per_query": kc["lane_inserts"] / N_QUERIES}
+                "list_inserts_per_query": kc["lane_inserts"] / N_QUERIES,
+                "box_reloads_per_query": kc["lane_node_reloads"] / N_QUERIES}
             rf["compulsory_frac"] = rf["frac"]
             rf["achieved"] = (knn_bytes + trav) / (avg["knn"] * 1e-3) / 1e9
             rf["frac"] = rf["achieved"] / HBM_PEAK_GBS
             rf["kernel"] += "; traversal bytes: leaf points x 16 + node boxes x 32"
+    if not args.no_counters:
+        # HBM traffic, L2 hit rate and VALU issue of the kNN launch, from
+        # counter passes over the same launch (children of this script).
+        c = counter_passes()
+        rf = out["roofline"]
+        rf["counters"] = c
+        if "error" not in c:
+            rf["traffic"] = c["hbm_bytes"]
+            rf["traffic_gbs"] = c["hbm_bytes"] / (avg["knn"] * 1e-3) / 1e9
+            rf["l2_hit_rate"] = c["l2_hit_rate"]
+            rf["valu_issue_frac"] = c["valu_issue_frac"]
+        print(f"[bench] counters: {c}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(x, q, args.cpu_queries, args.cpu_queries_threaded)
