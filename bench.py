@@ -68,6 +68,8 @@ def parse():
                     help="queries of the oracle timing over the host's threads")
     ap.add_argument("--no-dsweep", action="store_true")
     ap.add_argument("--no-box", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small uniform workload (65536 points)")
     ap.add_argument("--no-large-k", action="store_true")
     ap.add_argument("--no-torus", action="store_true")
     ap.add_argument("--no-midpoint", action="store_true")
@@ -174,6 +176,43 @@ def counter_passes():
         "valu_issue_frac": knn_rate / probe_rate,
         "clock_ghz": k["GRBM_GUI_ACTIVE"] / N_XCD / k["ns"],
     }
+
+
+def small_uniform(torch, kdt, workloads, dev) -> dict:
+    """The small uniform workload: 65536 points uniform in [0, 1)^3 (seed 1),
+    leaf 32, every point a query: build, kNN k = 8 and closed-ball counts
+    r = 0.02.  Each stage runs 20 times after 3 warm-ups; the median of the
+    HIP-event times on the current stream is reported."""
+    n = 1 << 16
+    xt = torch.from_numpy(workloads.uniform(n, 3, seed=1)).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def med(call, reps=20):
+        for _ in range(3):
+            keep = call()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            keep = call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+            del keep
+        return float(np.median(ts))
+
+    build_ms = med(lambda: kdt.build(xt, leaf_size=LEAF, check_finite=True))
+    tree = kdt.build(xt, leaf_size=LEAF)
+    knn_ms = med(lambda: tree.knn(None, 8))
+    range_ms = med(lambda: tree.range(None, 0.02))
+    tree.close()
+    res = {"n_points": n, "leaf_size": LEAF, "build_ms": build_ms,
+           "build_mpts_s": n / (build_ms * 1e-3) / 1e6,
+           "knn_k8_ms": knn_ms, "knn_queries_s": n / (knn_ms * 1e-3),
+           "range_r002_ms": range_ms, "range_queries_s": n / (range_ms * 1e-3)}
+    print(f"[bench] small uniform (65536): {res}", file=sys.stderr, flush=True)
+    return res
 
 
 def linking_length(n: int) -> float:
@@ -433,6 +472,8 @@ def main():
         out["batch_per_set_eager_ms"] = float(np.mean(reps))
         out["batched_speedup"] = out["batch_per_set_eager_ms"] / avg["batch_graph"]
         out["batched_points"] = batch[4]
+    if not args.no_small:
+        out["small_uniform"] = small_uniform(torch, kdt, workloads, dev)
     if not args.no_box:
         # Box queries (the rectangular ranges, a widening of the path): cubes of
         # the ball's volume (side 0.0161 for r = 0.01) centred on the 2^22
@@ -453,8 +494,24 @@ def main():
         box_ms = float(np.median(reps))
         out["box"] = {"ms": box_ms, "queries_s": N_QUERIES / (box_ms * 1e-3),
                       "side": 2 * half, "n_boxes": N_QUERIES}
-        tree.close()
         del blo, bhi
+        # Ball lists (CSR) of the same r = 0.01 balls of the 2^22 queries: the
+        # whole call (counts and offsets, a host read of the total, the fill
+        # and the per-row sort), timed on the host around a synchronised call.
+        tree.range(qt, RADIUS, lists=True)
+        torch.cuda.synchronize()
+        reps = []
+        for _ in range(3):
+            t_l = time.perf_counter()
+            lc, loff, lidx = tree.range(qt, RADIUS, lists=True)
+            torch.cuda.synchronize()
+            reps.append((time.perf_counter() - t_l) * 1e3)
+        lists_ms = float(np.median(reps))
+        out["ball_lists"] = {"ms": lists_ms, "queries_s": N_QUERIES / (lists_ms * 1e-3),
+                             "pairs": int(lidx.numel()),
+                             "pairs_s": lidx.numel() / (lists_ms * 1e-3)}
+        del lc, loff, lidx
+        tree.close()
     if not args.no_large_k:
         # kNN with k above the 64 register entries (the ball-and-sort path, a
         # widening of the path): 10^5 of the queries, k = 100 (the paper's

@@ -136,9 +136,12 @@ typedef struct {
     int64_t n;          /* points */
     int32_t d;          /* dimension */
     int32_t leaf_size;  /* N_leaf used */
-    int32_t levels;     /* L: splits on every root-to-leaf path; leaves = 2^L */
+    int32_t levels;     /* median tree: L, splits on every root-to-leaf path
+                           (2^L leaves); sliding-midpoint tree: the depth of
+                           the deepest leaf */
     int32_t stride;     /* floats per point record in tree order */
-    int64_t n_nodes;    /* 2^(L+1) - 1 */
+    int64_t n_nodes;    /* median tree: 2^(L+1) - 1; sliding-midpoint tree: the
+                           nodes it has (2 x leaves - 1) */
 } kdt_tree_info;
 
 /*
@@ -151,12 +154,15 @@ typedef struct {
  * opts   may be NULL (leaf_size 32, finiteness check on).
  * out    receives the tree handle; release it with kdt_free.
  *
- * Splits are balanced: node (l, j) owns points [floor(j n / 2^l),
- * floor((j+1) n / 2^l)) of the tree order and is split along the longest side
- * of its tight bounding box (lowest axis on ties) at the median, so that the
- * depth is L = ceil(log2(ceil(n / leaf_size))) for every leaf.  The paper's
- * sliding-midpoint rule (Sec. 2.1 step 1) is not used: the median rule gives a
- * depth known from n alone, which fixes the launch schedule.  Query results do
+ * With split_rule 0 (the default) splits are balanced: node (l, j) owns
+ * points [floor(j n / 2^l), floor((j+1) n / 2^l)) of the tree order and is
+ * split along the longest side of its tight bounding box (lowest axis on
+ * ties) at the median, so that the depth is L = ceil(log2(ceil(n /
+ * leaf_size))) for every leaf; the depth is known from n alone, which fixes
+ * the launch schedule and lets the build run without host waits (other than
+ * the finiteness check).  With split_rule 1 the paper's sliding-midpoint rule
+ * (Sec. 2.1 steps 1-4) is used: the depth depends on the data, so the build
+ * waits on `stream` once per level to size the next one.  Query results do
  * not depend on the split rule.
  *
  * Errors: KDT_EINVAL (NULL pointer, n out of range, non-finite coordinate when
@@ -168,6 +174,16 @@ kdt_status kdt_build(const float *d_pts, int64_t n, int32_t d, const kdt_build_o
 /* Releases a tree.  Waits for the tree's build stream; the caller must have
    finished (or ordered before this call) every query that uses the tree. */
 kdt_status kdt_free(kdt_tree *tree);
+
+/*
+ * Releases the device scratch the library keeps for `stream` between calls
+ * (the particle-to-mesh deposits keep theirs, sized by the largest call so
+ * far, so that repeated calls allocate nothing).  The memory is returned in
+ * stream order (work already queued on `stream` finishes first).  Call it
+ * before destroying a stream that ran deposits, or to give the memory back;
+ * the next deposit on the stream allocates again.  Errors: KDT_EDEVICE.
+ */
+kdt_status kdt_stream_release(hipStream_t stream);
 
 /* Fills *info (host). */
 kdt_status kdt_tree_get_info(const kdt_tree *tree, kdt_tree_info *info);

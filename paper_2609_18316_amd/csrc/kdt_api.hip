@@ -100,6 +100,29 @@ void* stream_scratch(hipStream_t stream, int slot, size_t bytes) {
   return b.ptr;
 }
 
+extern "C" kdt_status kdt_stream_release(hipStream_t stream) {
+  kdt_clear_error();
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    kdt_set_error("kdt_stream_release: no current device");
+    return KDT_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  kdt_status st = KDT_OK;
+  for (auto it = g_scratch->begin(); it != g_scratch->end();) {
+    if (it->first.device == dev && it->first.stream == stream) {
+      if (it->second.ptr && hipFreeAsync(it->second.ptr, stream) != hipSuccess) {
+        kdt_set_error("kdt_stream_release: hipFreeAsync failed");
+        st = KDT_EDEVICE;
+      }
+      it = g_scratch->erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return st;
+}
+
 
 // Build schedules depend only on (device, n, d, leaf); repeated builds of the
 // same shape reuse the uploaded tables.

@@ -412,9 +412,15 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
     size_t tb = 0;
     hipcub::TransformInputIterator<int64_t, BigI64, const int32_t*> c64(count, BigI64());
     if (hipcub::DeviceScan::InclusiveSum(nullptr, tb, c64, off + 1, (int)nq, stream) !=
-            hipSuccess ||
-        !buf.get((char**)&tmp, tb) ||
-        hipcub::DeviceScan::InclusiveSum(tmp, tb, c64, off + 1, (int)nq, stream) != hipSuccess) {
+        hipSuccess) {
+      kdt_set_error("kdt_knn: large-k offsets failed");
+      return KDT_EDEVICE;
+    }
+    if (!buf.get((char**)&tmp, tb)) {
+      kdt_set_error("kdt_knn: device allocation failed for the large-k offsets");
+      return KDT_ENOMEM;
+    }
+    if (hipcub::DeviceScan::InclusiveSum(tmp, tb, c64, off + 1, (int)nq, stream) != hipSuccess) {
       kdt_set_error("kdt_knn: large-k offsets failed");
       return KDT_EDEVICE;
     }

@@ -281,9 +281,15 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   void* tmp = nullptr;
   size_t tb = 0;
   hipcub::TransformInputIterator<int64_t, TorusI64, const int32_t*> c64(d_count, TorusI64());
-  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, c64, d_off, (int)nq, stream) != hipSuccess ||
-      !buf.get((char**)&tmp, tb) ||
-      hipcub::DeviceScan::ExclusiveSum(tmp, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
+    kdt_set_error("kdt_range: torus offset scan failed");
+    return KDT_EDEVICE;
+  }
+  if (!buf.get((char**)&tmp, tb)) {
+    kdt_set_error("kdt_range: device allocation failed for the list offsets");
+    return KDT_ENOMEM;
+  }
+  if (hipcub::DeviceScan::ExclusiveSum(tmp, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
     kdt_set_error("kdt_range: torus offset scan failed");
     return KDT_EDEVICE;
   }
@@ -316,9 +322,15 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   void* stmp = nullptr;
   size_t sb = 0;
   if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total, (int)nq,
-                                            d_off, d_off + 1, stream) != hipSuccess ||
-      !buf.get((char**)&stmp, sb) ||
-      hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total, (int)nq, d_off,
+                                            d_off, d_off + 1, stream) != hipSuccess) {
+    kdt_set_error("kdt_range: torus list sort failed");
+    return KDT_EDEVICE;
+  }
+  if (!buf.get((char**)&stmp, sb)) {
+    kdt_set_error("kdt_range: device allocation failed for sorting the lists");
+    return KDT_ENOMEM;
+  }
+  if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total, (int)nq, d_off,
                                             d_off + 1, stream) != hipSuccess) {
     kdt_set_error("kdt_range: torus list sort failed");
     return KDT_EDEVICE;
@@ -484,9 +496,15 @@ static kdt_status torus_fof_impl(const kdt_tree* tr, float l, const float* perio
   char* tmp = nullptr;
   size_t tb = 0;
   int64_t h = 0;
-  if (hipcub::DeviceReduce::Sum(nullptr, tb, roots, d_out, (int)n, stream) != hipSuccess ||
-      !buf.get(&d_out, 1) || !buf.get(&tmp, tb) ||
-      hipcub::DeviceReduce::Sum(tmp, tb, roots, d_out, (int)n, stream) != hipSuccess ||
+  if (hipcub::DeviceReduce::Sum(nullptr, tb, roots, d_out, (int)n, stream) != hipSuccess) {
+    kdt_set_error("kdt_fof_torus: counting groups failed");
+    return KDT_EDEVICE;
+  }
+  if (!buf.get(&d_out, 1) || !buf.get(&tmp, tb)) {
+    kdt_set_error("kdt_fof_torus: device allocation failed");
+    return KDT_ENOMEM;
+  }
+  if (hipcub::DeviceReduce::Sum(tmp, tb, roots, d_out, (int)n, stream) != hipSuccess ||
       hipMemcpyAsync(&h, d_out, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
     kdt_set_error("kdt_fof_torus: counting groups failed");

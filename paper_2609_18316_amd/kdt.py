@@ -28,7 +28,7 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_range", "kdt_box", "kdt_fof", "kdt_fof_torus", "kdt_p2m", "kdt_p2m_cloud", "kdt_p2m_backward",
            "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
-           "kdt_last_error")
+           "kdt_stream_release", "kdt_last_error")
 # The test and measurement hooks of include/kdt_debug.h.
 DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe")
 LIB_COUNTS_PATH = os.path.join(HERE, "libkdt_counts.so")
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_query_order.argtypes = [vp, vp, i64, C.c_int32, vp, vp]
     lib.kdt_tree_perm.argtypes = [vp]
     lib.kdt_tree_perm.restype = vp
+    lib.kdt_stream_release.argtypes = [vp]
     if hasattr(lib, "kdt_batch_plan_create"):
         lib.kdt_batch_plan_create.argtypes = [vp, i32, i32, i32, C.POINTER(BuildOpts),
                                               C.POINTER(QueryOpts), C.POINTER(vp)]
@@ -117,6 +118,11 @@ def load(path: str = LIB_PATH):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+def stream_release(stream=None) -> None:
+    """Frees the deposit scratch the library keeps for ``stream`` (stream-ordered)."""
+    _check(load().kdt_stream_release(_stream(stream)))
 
 
 def fail_alloc(after: int) -> None:

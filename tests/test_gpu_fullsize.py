@@ -71,6 +71,43 @@ def test_midpoint_tree_full_size(clustered):
     mt.close()
 
 
+def test_ball_lists_full_size(clustered):
+    """CSR lists of the r = 0.01 balls of all 2^22 queries on the 2^24-point
+    tree (Algorithm 3 with lists): offsets equal the running sum of the
+    oracle's counts on every row; on every row the listed indices ascend, are
+    distinct and lie in the closed ball (d2 <= r2, float32 in the oracle's
+    summation order), which with the counts makes each list the exact ball;
+    2^14 sampled rows also equal the oracle's lists."""
+    x, q, xt, qt, tree, ot = clustered
+    r = 0.01
+    say("ball lists r=0.01 of 2^22 queries")
+    cnt, off, idx = tree.range(qt, r, lists=True)
+    cnt, off, idx = to_host(cnt), to_host(off), to_host(idx)
+    say(f"{len(idx)} pairs; oracle counts of all 2^22 queries on {T} threads")
+    oc = ot.range(q, r, threads=T)
+    np.testing.assert_array_equal(cnt, oc)
+    assert off[0] == 0
+    np.testing.assert_array_equal(np.diff(off), oc.astype(np.int64))
+    assert off[-1] == len(idx)
+    r2 = np.float32(r) * np.float32(r)
+    row = np.repeat(np.arange(NQ, dtype=np.int64), oc)
+    step = 1 << 24
+    for s in range(0, len(idx), step):
+        i, w = idx[s:s + step], row[s:s + step]
+        assert i.min() >= 0 and i.max() < N
+        dx = x[i] - q[w]
+        d2 = (dx[:, 0] * dx[:, 0] + dx[:, 1] * dx[:, 1]) + dx[:, 2] * dx[:, 2]
+        assert (d2 <= r2).all()
+        # ascending and distinct within each row
+        same_row = w[1:] == w[:-1]
+        assert (i[1:][same_row] > i[:-1][same_row]).all()
+    sample = workloads.sample_indices(NQ, 1 << 14, seed=61)
+    say("oracle lists of 2^14 sampled rows")
+    sc, soff, sidx = ot.range(q[sample], r, lists=True)
+    for j, row_id in enumerate(sample):
+        np.testing.assert_array_equal(idx[off[row_id]:off[row_id + 1]], sidx[soff[j]:soff[j + 1]])
+
+
 def test_box_counts_full_size_sampled(clustered):
     """2^16 boxes of side 0.002-0.04 on the 2^24-point tree; 48 sampled rows
     checked against the oracle's definition."""
