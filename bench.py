@@ -35,7 +35,8 @@ K = 32
 RADIUS = 0.01
 FOF_B = 0.2
 GRID = 256
-LEAF = 32
+LEAF = 0         # the clustered workload's tree: the tuned leaf size (kdt_build picks it)
+LEAF_FIXED = 32  # the small uniform workload, the batched sets and the oracle's tree
 LARGE_K_QUERIES = 100_000
 LARGE_KS = (100, 1000, 10_000)
 HBM_PEAK_GBS = 8000.0
@@ -98,7 +99,7 @@ def counter_child(torch, kdt, workloads) -> None:
     del a, b
     xt = torch.from_numpy(workloads.clustered(N_POINTS, seed=2)).to(dev)
     qt = torch.from_numpy(workloads.uniform(N_QUERIES, 3, seed=102)).to(dev)
-    tree = kdt.build(xt, leaf_size=LEAF, check_finite=True)
+    tree = kdt.build(xt, leaf_size=LEAF, tune_k=K, check_finite=True)
     order = tree.query_order(qt)
     tree.knn(qt, K, order=order)
     torch.cuda.synchronize()
@@ -202,12 +203,12 @@ def small_uniform(torch, kdt, workloads, dev) -> dict:
             del keep
         return float(np.median(ts))
 
-    build_ms = med(lambda: kdt.build(xt, leaf_size=LEAF, check_finite=True))
-    tree = kdt.build(xt, leaf_size=LEAF)
+    build_ms = med(lambda: kdt.build(xt, leaf_size=LEAF_FIXED, check_finite=True))
+    tree = kdt.build(xt, leaf_size=LEAF_FIXED)
     knn_ms = med(lambda: tree.knn(None, 8))
     range_ms = med(lambda: tree.range(None, 0.02))
     tree.close()
-    res = {"n_points": n, "leaf_size": LEAF, "build_ms": build_ms,
+    res = {"n_points": n, "leaf_size": LEAF_FIXED, "build_ms": build_ms,
            "build_mpts_s": n / (build_ms * 1e-3) / 1e6,
            "knn_k8_ms": knn_ms, "knn_queries_s": n / (knn_ms * 1e-3),
            "range_r002_ms": range_ms, "range_queries_s": n / (range_ms * 1e-3)}
@@ -261,7 +262,7 @@ def cpu_baseline(x, q, n_q1, n_qt):
     model, nproc, usable = host_cpu()
     threads = oracle.host_threads()
     t0 = time.perf_counter()
-    tree = oracle.Tree(x, LEAF)
+    tree = oracle.Tree(x, LEAF_FIXED)
     t1 = time.perf_counter()
     tree.knn(q[:n_q1], K)
     t2 = time.perf_counter()
@@ -355,7 +356,7 @@ def main():
         sizes = workloads.batch_sizes(BATCH_SETS, 3.0, 6.0, seed=4)
         bx, boff = workloads.batched_clustered(sizes, seed_base=40000)
         bl = np.array([linking_length(int(s)) for s in sizes], np.float32)
-        plan = kdt.BatchPlan(boff, 3, 8, LEAF)
+        plan = kdt.BatchPlan(boff, 3, 8, LEAF_FIXED)
         bxt = torch.from_numpy(bx).to(dev)
         blt = torch.from_numpy(bl).to(dev)
         bout = (torch.empty((int(boff[-1]), 8), dtype=torch.int32, device=dev),
@@ -378,7 +379,7 @@ def main():
             marks[name] = e
 
         mark("start")
-        tree = kdt.build(xt, leaf_size=LEAF, check_finite=True)
+        tree = kdt.build(xt, leaf_size=LEAF, tune_k=K, check_finite=True)
         mark("build")
         order = tree.query_order(qt)
         mark("knn_order")
@@ -444,7 +445,8 @@ def main():
                         "2^22 uniform queries, kNN k=32, ball r=0.01, FoF b=0.2, "
                         "SPH P2M 256^3 with adjoint, batched 256 clustered sets",
             "n_points": N_POINTS, "n_queries": N_QUERIES, "k": K, "radius": RADIUS,
-            "leaf_size": LEAF, "grid": GRID, "fof_linking_length": l_fof,
+            "leaf_size": kdt.tuning_get(3, N_POINTS, K)[0], "grid": GRID,
+            "fof_linking_length": l_fof,
         },
         "phases_ms": avg,
         "build_mpts_s": N_POINTS / (avg["build"] * 1e-3) / 1e6,
@@ -480,7 +482,7 @@ def main():
         # queries, counts on the step's tree, built again; outside the timed steps.
         half = 0.5 * (4.0 / 3.0 * np.pi) ** (1.0 / 3.0) * RADIUS
         blo, bhi = (qt - half).contiguous(), (qt + half).contiguous()
-        tree = kdt.build(xt, leaf_size=LEAF)
+        tree = kdt.build(xt, leaf_size=LEAF, tune_k=K)
         tree.box(blo, bhi)
         torch.cuda.synchronize()
         reps = []
@@ -517,7 +519,7 @@ def main():
         # widening of the path): 10^5 of the queries, k = 100 (the paper's
         # parallel test), 1000 and 10^4 (the top of its k sweep), full lists,
         # on the step's tree built again; outside the timed steps.
-        tree = kdt.build(xt, leaf_size=LEAF)
+        tree = kdt.build(xt, leaf_size=LEAF, tune_k=K)
         qk = qt[:LARGE_K_QUERIES].contiguous()
         out["large_k"] = {"n_queries": LARGE_K_QUERIES}
         for kk in LARGE_KS:
@@ -539,7 +541,7 @@ def main():
         # path): kNN k = 32 of the 2^22 queries, r = 0.01 counts and FoF
         # b = 0.2 of the 2^24 points, one traversal per lane, on the step's
         # tree built again; best of two calls each, outside the timed steps.
-        tree = kdt.build(xt, leaf_size=LEAF)
+        tree = kdt.build(xt, leaf_size=LEAF, tune_k=K)
         out["torus"] = {"period": 1.0}
         calls = {"knn": lambda: tree.knn(qt, K, period=1.0),
                  "range": lambda: tree.range(qt, RADIUS, period=1.0),
@@ -581,12 +583,12 @@ def main():
                 best = ms if best is None else min(best, ms)
                 del r
             return best
-        b_ms = timed(lambda: kdt.build(xt, leaf_size=LEAF, check_finite=False,
+        b_ms = timed(lambda: kdt.build(xt, leaf_size=LEAF, tune_k=K, check_finite=False,
                                        split_rule=kdt.SPLIT_MIDPOINT))
-        mtree = kdt.build(xt, leaf_size=LEAF, split_rule=kdt.SPLIT_MIDPOINT)
+        mtree = kdt.build(xt, leaf_size=LEAF, tune_k=K, split_rule=kdt.SPLIT_MIDPOINT)
         k_ms = timed(lambda: mtree.knn(qt, K))
         r_ms = timed(lambda: mtree.range(qt, RADIUS))
-        out["midpoint"] = {"leaf_size": LEAF, "depth": mtree.info.levels,
+        out["midpoint"] = {"leaf_size": mtree.info.leaf_size, "depth": mtree.info.levels,
                            "n_nodes": mtree.info.n_nodes, "build_ms": b_ms,
                            "build_mpts_s": N_POINTS / (b_ms * 1e-3) / 1e6, "knn_ms": k_ms,
                            "knn_queries_s": N_QUERIES / (k_ms * 1e-3), "range_ms": r_ms,
@@ -598,7 +600,7 @@ def main():
         # the like-for-like comparison: the median tree with one traversal per
         # lane for the counts as well (the sliding-midpoint tree has no
         # wave-shared count)
-        mt2 = kdt.build(xt, leaf_size=LEAF)
+        mt2 = kdt.build(xt, leaf_size=LEAF, tune_k=K)
         out["midpoint"]["median_tree"]["range_lane_ms"] = timed(
             lambda: mt2.range(qt, RADIUS, traversal=1))
         mt2.close()
@@ -606,21 +608,32 @@ def main():
               f"counts {r_ms:.2f} ms", file=sys.stderr, flush=True)
     if not args.no_cloud:
         # The fixed-cloud deposits the paper compares the adaptive one with
-        # (Table 3): the same 2^24 particles and 256^3 mesh, best of three.
+        # (Table 3): the same 2^24 particles and 256^3 mesh, visited in the
+        # same tree order as the adaptive deposit of the step, best of three
+        # after one warm-up; the input-order figures (no order given) follow.
         out["cloud"] = {"p2m_sph_fwd_ms": avg["p2m_fwd"]}
-        for scheme in ("ngp", "cic", "tsc"):
+        ctree = kdt.build(xt, leaf_size=LEAF, tune_k=K)
+        h_c = ctree.knn(None, K, kth_only=2)
+        for scheme, order_ptr, tag in (("ngp", ctree.perm_ptr, ""), ("cic", ctree.perm_ptr, ""),
+                                       ("tsc", ctree.perm_ptr, ""), ("tsc", None, "_input_order"),
+                                       ("sph", None, "_input_order")):
             best = None
             for _ in range(4):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
-                r = kdt.p2m_cloud(xt, mt, lo, cell, shape, scheme)
+                if scheme == "sph":
+                    r = kdt.p2m(xt, mt, h_c, lo, cell, shape, order_ptr=order_ptr)
+                else:
+                    r = kdt.p2m_cloud(xt, mt, lo, cell, shape, scheme, order_ptr=order_ptr)
                 e1.record()
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1)
-                best = ms if best is None else min(best, ms)
+                if _ > 0:  # the first call warms up
+                    best = ms if best is None else min(best, ms)
                 del r
-            out["cloud"][scheme + "_ms"] = best
+            out["cloud"][scheme + tag + "_ms"] = best
+        ctree.close()
         out["cloud"]["sph_over_tsc"] = avg["p2m_fwd"] / out["cloud"]["tsc_ms"]
     if not args.no_grf:
         # The paper's inhomogeneous mock (Sec. 3.1): 2^24 points from a
@@ -646,15 +659,15 @@ def main():
                 best = ms if best is None else min(best, ms)
                 del r
             return best
-        gtree = kdt.build(xg, leaf_size=LEAF)
+        gtree = kdt.build(xg, leaf_size=LEAF, tune_k=K)
         out["grf"] = {
             "n_points": N_POINTS, "generation_s": gen_s,
-            "build_ms": best_of(lambda: kdt.build(xg, leaf_size=LEAF, check_finite=False)),
+            "build_ms": best_of(lambda: kdt.build(xg, leaf_size=LEAF, tune_k=K, check_finite=False)),
             "knn_ms": best_of(lambda: gtree.knn(qt, K)),
             "range_ms": best_of(lambda: gtree.range(qt, RADIUS)),
             "fof_ms": best_of(lambda: gtree.fof(l_fof)),
             "midpoint_build_ms": best_of(lambda: kdt.build(
-                xg, leaf_size=LEAF, check_finite=False, split_rule=kdt.SPLIT_MIDPOINT), reps=2),
+                xg, leaf_size=LEAF, tune_k=K, check_finite=False, split_rule=kdt.SPLIT_MIDPOINT), reps=2),
         }
         out["grf"]["knn_queries_s"] = N_QUERIES / (out["grf"]["knn_ms"] * 1e-3)
         gtree.close()

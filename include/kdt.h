@@ -59,7 +59,9 @@ typedef struct kdt_batch_plan kdt_batch_plan; /* many trees, fixed shapes, libra
 
 typedef struct {
     int32_t leaf_size;    /* N_leaf: a node with <= leaf_size points is a leaf
-                             (Sec. 2.1 step 4).  0 selects the default, 32. */
+                             (Sec. 2.1 step 4), 2..256.  0: the autotuned
+                             choice for (d, n, tune_k) from the library's
+                             tuning table (kdt_tuning_get). */
     int32_t check_finite; /* 1 (default when opts is NULL): kdt_build waits for its
                              first pass and rejects NaN/Inf coordinates with
                              KDT_EINVAL.  0: no wait, no check. */
@@ -78,6 +80,8 @@ typedef struct {
                              kdt_query_order; kdt_box, kdt_fof_torus, larger
                              k and periods return KDT_EUNSUPPORTED.  Results
                              are the same as on a median tree. */
+    int32_t tune_k;       /* With leaf_size 0: the k of the kNN queries the tree
+                             is built for, to pick its N_leaf (0: 32). */
 } kdt_build_opts;
 
 typedef struct {
@@ -88,9 +92,12 @@ typedef struct {
                              independent traversal per lane.  2: one traversal
                              shared by the 64 queries of a wave, leaves staged
                              in LDS (trees with leaf_size <= 64; larger leaves
-                             use 1).  The default is 1 for kNN in d <= 8 and 2
-                             otherwise, and 2 for ball counts.  Results are
-                             identical either way. */
+                             use 1).  0 picks, for kNN, the queries per
+                             traversal the tuning table gives for (d, the
+                             tree's n, k) (kdt_tuning_get: 1 -> 1, 64 -> 2;
+                             as measured, 1 up to d = 8 and 2 for d = 16),
+                             and 2 for ball counts.  Results are identical
+                             either way. */
     const int32_t *order; /* NULL, or a device permutation [nq] from
                              kdt_query_order to use instead of sorting again. */
     int32_t split_budget; /* Ball counts with traversal 2.  0: default (a wave
@@ -151,7 +158,8 @@ typedef struct {
  *        the work queued on `stream` by this call has run: the tree keeps its own
  *        copy of positions and indices (the tree is self-contained, Sec. 3.4).
  * n      1 <= n <= 2^31 - 1.     d in {2, 3, 4, 8, 16}.
- * opts   may be NULL (leaf_size 32, finiteness check on).
+ * opts   may be NULL (every field 0 except check_finite = 1: autotuned leaf
+ *        size, finiteness check on, median splits).
  * out    receives the tree handle; release it with kdt_free.
  *
  * With split_rule 0 (the default) splits are balanced: node (l, j) owns
@@ -411,6 +419,32 @@ kdt_status kdt_p2m_backward(const float *d_x, const float *d_m, const float *d_h
 kdt_status kdt_query_order(const kdt_tree *tree, const float *d_q, int64_t nq, int32_t kind,
                            int32_t *d_order, hipStream_t stream);
 
+/*
+ * The tuning table behind leaf_size = 0 and traversal = 0 (the paper tunes
+ * N_leaf by hand, Sec. 2.1 and App. A; here it is measured).  An entry gives,
+ * for a shape (d, n, k), the leaf size and the queries per traversal (1: one
+ * per lane, 64: one shared by a wave) that the autotuner
+ * (paper_2609_18316_amd/autotune.py) measured fastest.  The library holds
+ * the table that tool last wrote; kdt_tuning_set adds or replaces an entry
+ * for the rest of the process (thread-safe; keyed by d, log2 n rounded and
+ * k; leaf_size = queries_per_wave = 0 removes the run-time entry of the
+ * shape again).  A lookup takes the entry of dimension d nearest in
+ * (log2 n, log2 k).
+ *
+ * kdt_tuning_get writes (host pointers, each may be NULL) the looked-up
+ * leaf size and queries per traversal, and the traversal stack depth a
+ * median tree of that shape needs: its depth L + 1 with
+ * L = ceil(log2(ceil(n / leaf))) -- fixed by n and the leaf size, so it is
+ * derived rather than tuned.
+ *
+ * Errors: KDT_EINVAL (d not in {2,3,4,8,16}, n < 1, k < 1; for _set also
+ * leaf_size outside [2, 256] or queries_per_wave not 1 or 64).
+ */
+kdt_status kdt_tuning_set(int32_t d, int64_t n, int32_t k, int32_t leaf_size,
+                          int32_t queries_per_wave);
+kdt_status kdt_tuning_get(int32_t d, int64_t n, int32_t k, int32_t *leaf_size,
+                          int32_t *queries_per_wave, int32_t *stack_depth);
+
 /* Device pointer to the tree order: perm[t] is the input index of the point at
    tree position t (n int32, owned by the tree).  NULL on error. */
 const int32_t *kdt_tree_perm(const kdt_tree *tree);
@@ -436,7 +470,9 @@ const int32_t *kdt_tree_perm(const kdt_tree *tree);
  * use_graph = 2: the same batched kernels launched eagerly (no graph).
  * use_graph = 0: the per-set baseline -- kdt_build, kdt_knn and kdt_fof called
  *   once per set, eagerly (waits on `stream` to read d_l).
- * bopts->leaf_size sets N_leaf for every set (0 or NULL: 32); qopts->traversal
+ * bopts->leaf_size sets N_leaf for every set; 0 (or NULL bopts) gives each
+ * set the tuned N_leaf of its own size (kdt_tuning_get(d, n_s, k));
+ * qopts->traversal
  * picks the batched kNN kernel (0 and 2: wave packets, the measured default
  * for all-points queries; 1: one query per lane; leaf_size > 64 always uses
  * 1); qopts may be NULL and its other fields are unused.  Results are

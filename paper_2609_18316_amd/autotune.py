@@ -10,9 +10,15 @@ is measured on the GPU for a given workload shape:
 * traversal stack depth -- not tuned: with median splits it is exactly the
   tree depth L = ceil(log2(ceil(n / N_leaf))), known from n.
 
-`tune()` times build + query for every candidate and returns the fastest;
-`lookup()` reads results stored by earlier tuning runs (a JSON table next to
-this file, keyed by workload shape), falling back to the paper's regime.
+`tune()` times build + query for every candidate, returns the fastest and
+installs it in the running library (kdt_tuning_set), so that leaf_size = 0
+and traversal = 0 pick it for the rest of the process; `lookup()` reads
+results stored by earlier tuning runs (a JSON table next to this file, keyed
+by workload shape), falling back to the paper's regime.  `write_inc()` turns
+that table into csrc/kdt_tuning.inc, the table compiled into the library:
+run this module on a GPU (``python -m paper_2609_18316_amd.autotune``) to
+measure the standard shapes, store them and regenerate it; the library picks
+the new table up at its next build.
 """
 from __future__ import annotations
 
@@ -26,6 +32,10 @@ import torch
 from . import kdt
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table.json")
+INC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kdt_tuning.inc")
+# Query kinds in the order the compiled-in table prefers them when several
+# kinds were measured for one (d, log2 n, k): the library cannot tell them apart.
+KIND_ORDER = ("uniform-queries", "self", "self-uniform", "batch-clustered", "self-normal")
 LEAF_CANDIDATES = (8, 12, 16, 24, 32, 48, 64)
 
 
@@ -82,6 +92,7 @@ def tune(points: torch.Tensor, k: int, queries: torch.Tensor | None = None,
                 best = c
         tree.close()
     assert best is not None
+    kdt.tuning_set(d, n, k, best.leaf_size, best.queries_per_wave)
     return best
 
 
@@ -111,6 +122,30 @@ def lookup(n: int, d: int, k: int, kind: str, path: str = TABLE) -> Choice:
     return Choice(leaf, 64, levels + 1, float("nan"), float("nan"))
 
 
+def _parse_key(name: str):
+    """(d, log2 n, k, kind) of a table key."""
+    n_part, d_part, k_part, kind = name.split("-", 3)
+    return int(d_part[1:]), int(n_part[3:]), int(k_part[1:]), kind
+
+
+def write_inc(table: dict | None = None, path: str = INC) -> None:
+    """Writes the compiled-in tuning table: one initializer {d, log2 n, k,
+    leaf, queries per wave} per shape, the preferred kind first."""
+    table = load_table() if table is None else table
+    rows = []
+    for name, e in table.items():
+        d, l2, k, kind = _parse_key(name)
+        rank = KIND_ORDER.index(kind) if kind in KIND_ORDER else len(KIND_ORDER)
+        rows.append((d, l2, k, rank, name, e["leaf_size"], e["queries_per_wave"]))
+    rows.sort()
+    lines = ["// Generated by paper_2609_18316_amd/autotune.py (write_inc) from",
+             "// autotune_table.json: {d, log2 n, k, leaf size, queries per traversal}."]
+    for d, l2, k, _, name, leaf, qpw in rows:
+        lines.append(f"{{{d}, {l2}, {k}, {leaf}, {qpw}}},  // {name}")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def _standard_workloads():
     """The workload shapes the benchmark and the parity configurations use."""
     from . import workloads
@@ -128,15 +163,36 @@ def _standard_workloads():
             xt = torch.from_numpy(pts).to(dev)
             sel = torch.randperm(xt.shape[0], generator=gen)[: 1 << 16].to(dev)
             yield key(1 << 22, d, 16, f"self-{dist}"), xt, xt[sel].contiguous(), 16
+    # set sizes of the batched mode (clustered sets, k = 8, every point a query)
+    for e in (10, 12, 14, 16, 18, 20):
+        xs = torch.from_numpy(workloads.clustered(1 << e, seed=500 + e)).to(dev)
+        yield key(1 << e, 3, 8, "batch-clustered"), xs, None, 8
 
 
-if __name__ == "__main__":
-    import sys
-    out = sys.argv[1] if len(sys.argv) > 1 else TABLE
+def main(argv=None) -> None:
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", default="", help="substring of the shapes to measure")
+    ap.add_argument("--out-dir", default="",
+                    help="write autotune_table.json and kdt_tuning.inc there instead of in place")
+    args = ap.parse_args(argv)
     results = {}
     for name, pts, qs, kk in _standard_workloads():
+        if args.only and args.only not in name:
+            continue
         print(name, flush=True)
         c = tune(pts, kk, qs, verbose=True)
         results[name] = c
         print(name, asdict(c), flush=True)
-    store(results, out)
+    table_path = os.path.join(args.out_dir, "autotune_table.json") if args.out_dir else TABLE
+    if args.out_dir:
+        os.makedirs(args.out_dir, exist_ok=True)
+        with open(table_path, "w") as f:
+            json.dump(load_table(), f, indent=1, sort_keys=True)
+    store(results, table_path)
+    write_inc(load_table(table_path),
+              os.path.join(args.out_dir, "kdt_tuning.inc") if args.out_dir else INC)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,7 +164,7 @@ static kdt_status get_plan(int device, int64_t n, int d, int leaf, hipStream_t s
   cp->leaf = leaf;
   int64_t offs[2] = {0, n};
   std::string err;
-  if (!make_plan(offs, 1, d, leaf, cp->plan, err)) {
+  if (!make_plan(offs, 1, d, &leaf, cp->plan, err)) {
     kdt_set_error("%s", err.c_str());
     return KDT_EINVAL;
   }
@@ -200,12 +200,18 @@ extern "C" kdt_status kdt_build(const float* d_pts, int64_t n, int32_t d,
     kdt_set_error("kdt_build: dimension %d is not one of 2, 3, 4, 8, 16", d);
     return KDT_EUNSUPPORTED;
   }
-  int leaf = 32, check = 1, rule = 0;
+  int leaf = 0, check = 1, rule = 0, tune_k = 0;
   if (opts) {
-    if (opts->leaf_size) leaf = opts->leaf_size;
+    leaf = opts->leaf_size;
     check = opts->check_finite;
     rule = opts->split_rule;
+    tune_k = opts->tune_k;
   }
+  if (tune_k < 0) {
+    kdt_set_error("kdt_build: tune_k %d is negative", tune_k);
+    return KDT_EINVAL;
+  }
+  if (leaf == 0) leaf = tuned(d, n, tune_k ? tune_k : 32).leaf;
   if (leaf < 2 || leaf > 256) {
     kdt_set_error("kdt_build: leaf_size %d outside [2, 256]", leaf);
     return KDT_EINVAL;

@@ -247,7 +247,8 @@ using namespace kdt;
 struct kdt_batch_plan {
   Plan plan;
   PlanDev dev;
-  int d = 0, k = 0, leaf = 0;
+  int d = 0, k = 0, leaf = 0;  // leaf: the largest N_leaf of the sets
+  std::vector<int> leaves;     // N_leaf of each set
   bool knn_packets = false;  // wave-packet kNN instead of one query per lane
   std::vector<int64_t> offsets;
   BuildScratch w;
@@ -410,11 +411,16 @@ extern "C" kdt_status kdt_batch_plan_create(const int64_t* h_offsets, int32_t n_
     kdt_set_error("kdt_batch_plan_create: offsets must start at 0 and total below 2^31");
     return KDT_EINVAL;
   }
-  int leaf = bopts && bopts->leaf_size ? bopts->leaf_size : 32;
-  if (leaf < 2 || leaf > 256) {
-    kdt_set_error("kdt_batch_plan_create: leaf_size %d outside [2, 256]", leaf);
+  const int given_leaf = bopts ? bopts->leaf_size : 0;
+  if (given_leaf != 0 && (given_leaf < 2 || given_leaf > 256)) {
+    kdt_set_error("kdt_batch_plan_create: leaf_size %d outside [2, 256]", given_leaf);
     return KDT_EINVAL;
   }
+  // leaf_size 0: each set takes the tuned N_leaf of its own size
+  std::vector<int> leaves((size_t)n_sets);
+  for (int s = 0; s < n_sets; ++s)
+    leaves[s] = given_leaf ? given_leaf : tuned(d, h_offsets[s + 1] - h_offsets[s], k).leaf;
+  const int leaf = *std::max_element(leaves.begin(), leaves.end());
   kdt_batch_plan* bp = new (std::nothrow) kdt_batch_plan();
   if (!bp) {
     kdt_set_error("kdt_batch_plan_create: out of host memory");
@@ -423,6 +429,7 @@ extern "C" kdt_status kdt_batch_plan_create(const int64_t* h_offsets, int32_t n_
   bp->d = d;
   bp->k = k;
   bp->leaf = leaf;
+  bp->leaves = leaves;
   // traversal 0 picks the measured default: wave packets (for the batch's
   // all-points kNN they beat one query per lane: the whole 256-set clustered
   // pipeline at k = 8 takes 57.1 ms with them, 65.4 ms without)
@@ -430,7 +437,7 @@ extern "C" kdt_status kdt_batch_plan_create(const int64_t* h_offsets, int32_t n_
   bp->knn_packets = leaf <= 64 && trav != 1;
   bp->offsets.assign(h_offsets, h_offsets + n_sets + 1);
   std::string err;
-  if (!make_plan(h_offsets, n_sets, d, leaf, bp->plan, err)) {
+  if (!make_plan(h_offsets, n_sets, d, leaves.data(), bp->plan, err)) {
     delete bp;
     kdt_set_error("kdt_batch_plan_create: %s", err.c_str());
     return KDT_EINVAL;
@@ -500,11 +507,11 @@ static kdt_status eager_per_set(kdt_batch_plan* bp, const float* d_pts, const fl
     kdt_set_error("kdt_batch_launch: reading linking lengths failed");
     return KDT_EDEVICE;
   }
-  kdt_build_opts bo{bp->leaf, 0};
   std::vector<kdt_tree*> trees(ns, nullptr);
   kdt_status st = KDT_OK;
   for (int i = 0; i < ns && st == KDT_OK; ++i) {
     const int64_t off = bp->offsets[i], n = bp->offsets[i + 1] - off;
+    kdt_build_opts bo{bp->leaves[i], 0, 0, 0};
     st = kdt_build(d_pts + off * bp->d, n, bp->d, &bo, s, &trees[i]);
     if (st == KDT_OK)
       st = kdt_knn(trees[i], nullptr, n, bp->k, d_idx + off * bp->k, d_d2 + off * bp->k, 0, nullptr, s);

@@ -53,10 +53,11 @@ static size_t lds_bytes(int d, int cap) {
   return (size_t)cap * 4 * d + 4 * 256 * 4 + (size_t)cap * 2 * 2;
 }
 
-bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std::string& err) {
+bool make_plan(const int64_t* offsets, int n_sets, int d, const int* leaves, Plan& p,
+               std::string& err) {
   p = Plan();
   p.d = d;
-  p.leaf = leaf;
+  p.leaf = 0;
   p.lds_cap = lds_capacity(d);
   p.total = offsets[n_sets] - offsets[0];
   int64_t nb = 0;
@@ -68,7 +69,8 @@ bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& p, std
       err = "every set must hold between 1 and 2^31-1 points";
       return false;
     }
-    sd.levels = levels_for(sd.n, leaf);
+    sd.levels = levels_for(sd.n, leaves[s]);
+    p.leaf = std::max(p.leaf, leaves[s]);
     int g = 0;
     while (g < sd.levels && ((sd.n + (int64_t(1) << g) - 1) >> g) > p.lds_cap) ++g;
     sd.glevels = g;

@@ -160,9 +160,19 @@ struct Plan {
 };
 
 // Builds the static schedule of a forest from host-known sizes.
-bool make_plan(const int64_t* offsets, int n_sets, int d, int leaf, Plan& plan, std::string& err);
+// leaves: N_leaf of each set (n_sets entries); plan.leaf is the largest.
+bool make_plan(const int64_t* offsets, int n_sets, int d, const int* leaves, Plan& plan,
+               std::string& err);
 
 int levels_for(int64_t n, int leaf);
+
+// The tuning table (kdt_tuning.hip): N_leaf and queries per traversal (1 or
+// 64) measured fastest for the nearest shape of dimension d.
+struct Tuning {
+  int leaf;
+  int qpw;
+};
+Tuning tuned(int d, int64_t n, int k);
 int lds_capacity(int d);
 
 // Device copies of a plan's tables (one allocation).

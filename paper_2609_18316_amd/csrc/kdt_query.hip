@@ -368,7 +368,7 @@ static kdt_status knn_impl(const kdt_tree* t, const float* d_q, int64_t nq, int 
                            float* d_d2, int mode, bool sort_q, int traversal,
                            const int32_t* given, hipStream_t stream, void* ws = nullptr,
                            size_t ws_bytes = 0) {
-  if (traversal == 0) traversal = D <= 8 ? 1 : 2;  // measured defaults
+  if (traversal == 0) traversal = tuned(D, t->n, k).qpw == 64 ? 2 : 1;  // the tuning table
   if (t->leaf > 64) traversal = 1;  // the wave kernel marks at most 64 points per leaf
   if (t->nodes) traversal = 1;      // stored trees: one traversal per lane
   int32_t* order = nullptr;

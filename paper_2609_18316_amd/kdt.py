@@ -28,7 +28,7 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_range", "kdt_box", "kdt_fof", "kdt_fof_torus", "kdt_p2m", "kdt_p2m_cloud", "kdt_p2m_backward",
            "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
-           "kdt_stream_release", "kdt_last_error")
+           "kdt_stream_release", "kdt_tuning_set", "kdt_tuning_get", "kdt_last_error")
 # The test and measurement hooks of include/kdt_debug.h.
 DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe")
 LIB_COUNTS_PATH = os.path.join(HERE, "libkdt_counts.so")
@@ -42,7 +42,8 @@ class KdtError(RuntimeError):
 
 
 class BuildOpts(C.Structure):
-    _fields_ = [("leaf_size", C.c_int32), ("check_finite", C.c_int32), ("split_rule", C.c_int32)]
+    _fields_ = [("leaf_size", C.c_int32), ("check_finite", C.c_int32), ("split_rule", C.c_int32),
+                ("tune_k", C.c_int32)]
 
 SPLIT_MEDIAN, SPLIT_MIDPOINT = 0, 1
 
@@ -104,6 +105,8 @@ def load(path: str = LIB_PATH):
     lib.kdt_tree_perm.argtypes = [vp]
     lib.kdt_tree_perm.restype = vp
     lib.kdt_stream_release.argtypes = [vp]
+    lib.kdt_tuning_set.argtypes = [i32, i64, i32, i32, i32]
+    lib.kdt_tuning_get.argtypes = [i32, i64, i32, vp, vp, vp]
     if hasattr(lib, "kdt_batch_plan_create"):
         lib.kdt_batch_plan_create.argtypes = [vp, i32, i32, i32, C.POINTER(BuildOpts),
                                               C.POINTER(QueryOpts), C.POINTER(vp)]
@@ -118,6 +121,21 @@ def load(path: str = LIB_PATH):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+def tuning_set(d: int, n: int, k: int, leaf_size: int, queries_per_wave: int) -> None:
+    """Installs a tuning entry (leaf size, 1 or 64 queries per traversal) for
+    the shape (d, n, k) for the rest of the process (0, 0 removes it)."""
+    _check(load().kdt_tuning_set(int(d), int(n), int(k), int(leaf_size), int(queries_per_wave)))
+
+
+def tuning_get(d: int, n: int, k: int) -> tuple[int, int, int]:
+    """(leaf size, queries per traversal, stack depth) the library uses for
+    leaf_size = 0 and traversal = 0 at the shape (d, n, k)."""
+    leaf, qpw, depth = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    _check(load().kdt_tuning_get(int(d), int(n), int(k), C.byref(leaf), C.byref(qpw),
+                                 C.byref(depth)))
+    return leaf.value, qpw.value, depth.value
 
 
 def stream_release(stream=None) -> None:
@@ -190,15 +208,16 @@ class Tree:
     """A device-resident k-d tree (library-owned; freed with the object)."""
 
     def __init__(self, points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
-                 stream=None, split_rule: int = SPLIT_MEDIAN):
+                 stream=None, split_rule: int = SPLIT_MEDIAN, tune_k: int = 0):
         """split_rule: SPLIT_MEDIAN (balanced) or SPLIT_MIDPOINT (the paper's
-        sliding midpoint, data-dependent depth)."""
+        sliding midpoint, data-dependent depth).  leaf_size 0: the tuned
+        leaf size for the shape and the kNN k ``tune_k`` (0: 32)."""
         lib = load()
         points = _dev(points, torch.float32, "points")
         if points.dim() != 2:
             raise ValueError("points must be [n][d]")
         self._h = C.c_void_p()
-        opts = BuildOpts(leaf_size, 1 if check_finite else 0, int(split_rule))
+        opts = BuildOpts(leaf_size, 1 if check_finite else 0, int(split_rule), int(tune_k))
         _check(lib.kdt_build(_ptr(points), points.shape[0], points.shape[1], C.byref(opts),
                              _stream(stream), C.byref(self._h)))
         info = TreeInfo()
@@ -375,8 +394,8 @@ class Tree:
 
 
 def build(points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
-          stream=None, split_rule: int = SPLIT_MEDIAN) -> Tree:
-    return Tree(points, leaf_size, check_finite, stream, split_rule)
+          stream=None, split_rule: int = SPLIT_MEDIAN, tune_k: int = 0) -> Tree:
+    return Tree(points, leaf_size, check_finite, stream, split_rule, tune_k)
 
 
 def make_grid(lo, cell: float, shape, periodic: bool = False) -> Grid:
@@ -467,7 +486,8 @@ class BatchPlan:
     """Many point sets of uneven size: fixed shapes, one launch per batch."""
 
     def __init__(self, offsets, d: int, k: int, leaf_size: int = 32, traversal: int = 0):
-        """traversal: 0 measured default, 1 one query per lane, 2 wave packets."""
+        """traversal: 0 measured default, 1 one query per lane, 2 wave packets.
+        leaf_size 0: each set takes the tuned leaf size of its own size."""
         import numpy as np
         lib = load()
         off = np.ascontiguousarray(offsets, dtype=np.int64)

@@ -10,7 +10,7 @@ of its own: the product library and the instrumented one cannot share one.
 
 Launches (the bench's configurations):
   knn_c2     kNN k = 32 of 2^22 uniform queries (Hilbert order, one query
-             per lane) on the 2^24-point clustered tree, leaf 32;
+             per lane) on the 2^24-point clustered tree, tuned leaf size;
   range_c2   closed-ball counts r = 0.01 of the same queries (wave-shared);
   knn_d8 / knn_d16   kNN k = 16 of every point of 2^22 uniform points in
              d = 8 and 16, leaf size and traversal from the tuning table.
@@ -44,7 +44,7 @@ def main() -> None:
 
     x = torch.from_numpy(workloads.clustered(1 << 24, seed=2)).to(dev)
     q = torch.from_numpy(workloads.uniform(1 << 22, 3, seed=102)).to(dev)
-    tree = kdt.build(x, leaf_size=32)
+    tree = kdt.build(x, leaf_size=0, tune_k=32)  # the tuned leaf size, as the bench
     order = tree.query_order(q)
     kdt.visits(reset=True)
     tree.knn(q, 32, order=order)

@@ -26,7 +26,7 @@ def clustered():
     x = workloads.clustered(N, seed=2)
     q = workloads.uniform(NQ, 3, seed=102)
     xt, qt = to_dev(x), to_dev(q)
-    tree = kdt.build(xt, leaf_size=32)
+    tree = kdt.build(xt, leaf_size=0, tune_k=32)  # the tuned leaf size, as the bench
     say("oracle tree over 2^24 points")
     ot = oracle.Tree(x, 32)
     return x, q, xt, qt, tree, ot
@@ -55,11 +55,14 @@ def test_midpoint_tree_full_size(clustered):
     r = 0.01 counts of all 2^22 queries over it equal the oracle's."""
     from tests.test_gpu_midpoint import assert_same_tree
     x, q, xt, qt, tree, ot = clustered
-    say("sliding-midpoint tree over 2^24 points")
-    mt = kdt.build(xt, leaf_size=32, split_rule=kdt.SPLIT_MIDPOINT)
+    leaf = kdt.tuning_get(3, N, 32)[0]
+    say(f"sliding-midpoint tree over 2^24 points, leaf {leaf} (the bench's)")
+    mt = kdt.build(xt, leaf_size=leaf, split_rule=kdt.SPLIT_MIDPOINT)
+    omt = ot if leaf == 32 else oracle.Tree(x, leaf)
     say(f"{mt.info.n_nodes} nodes, depth {mt.info.levels}; comparing with the oracle's tree")
-    assert mt.info.levels == ot.depth
-    assert_same_tree(mt.export(), ot.export())
+    assert mt.info.levels == omt.depth
+    assert_same_tree(mt.export(), omt.export())
+    del omt
     idx, d2 = mt.knn(qt, 32)
     cnt = mt.range(qt, 0.01)
     idx, d2, cnt = to_host(idx), to_host(d2), to_host(cnt)
