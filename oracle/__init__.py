@@ -47,6 +47,8 @@ def _load():
     lib.orc_range_brute.argtypes = [_f32p, i64, i32, _f32p, i64, f32, _i64p, vp, vp]
     lib.orc_knn_brute_torus.argtypes = [_f32p, i64, i32, _f32p, i64, i32, _f32p, _i32p, _f32p]
     lib.orc_range_brute_torus.argtypes = [_f32p, i64, i32, _f32p, i64, f32, _f32p, _i64p, vp, vp]
+    lib.orc_knn_brute_f64.argtypes = [_f64p, i64, i32, _f64p, i64, i32, _i32p, _f64p]
+    lib.orc_range_brute_f64.argtypes = [_f64p, i64, i32, _f64p, i64, C.c_double, _i64p, vp, vp]
     lib.orc_fof_brute.argtypes = [_f32p, i64, i32, f32, _i32p]
     lib.orc_fof_brute_torus.argtypes = [_f32p, i64, i32, f32, _f32p, _i32p]
     lib.orc_tree_build.argtypes = [_f32p, i64, i32, i32, C.POINTER(vp)]
@@ -170,6 +172,50 @@ def range_brute(pts, queries, r: float, lists: bool = False, period=None):
     offsets = np.empty(nq + 1, np.int64)
     idx = np.empty(max(int(count.sum()), 1), np.int32)
     _check(call(count, offsets.ctypes.data, idx.ctypes.data), "range_brute")
+    return count, offsets, idx[:int(count.sum())]
+
+
+def _pts64(x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    return x
+
+
+def knn_brute_f64(pts, queries, k: int, threads: int = 1):
+    """kNN on float64 coordinates (the double-precision real kind of
+    Sec. 2.4): the k smallest (d2, index) keys with d2 in float64, ascending,
+    padded with (-1, +inf): (idx int32, d2 float64)."""
+    pts, queries = _pts64(pts), _pts64(queries)
+    nq = queries.shape[0]
+    idx = np.empty((nq, k), np.int32)
+    d2 = np.empty((nq, k), np.float64)
+    lib = _load()
+
+    def call(a, b):
+        _check(lib.orc_knn_brute_f64(pts, pts.shape[0], pts.shape[1], queries[a:b], b - a, k,
+                                     idx[a:b], d2[a:b]), "knn_brute_f64")
+
+    _sliced(nq, threads, call)
+    return idx, d2
+
+
+def range_brute_f64(pts, queries, r: float, lists: bool = False):
+    """Ball counts (d2 <= fl64(r*r)) on float64 coordinates; with ``lists``
+    also CSR (offsets int64, ascending indices int32)."""
+    pts, queries = _pts64(pts), _pts64(queries)
+    n, d = pts.shape
+    nq = queries.shape[0]
+    lib = _load()
+    count = np.empty(nq, np.int64)
+    _check(lib.orc_range_brute_f64(pts, n, d, queries, nq, float(r), count, None, None),
+           "range_brute_f64")
+    if not lists:
+        return count
+    offsets = np.empty(nq + 1, np.int64)
+    idx = np.empty(max(int(count.sum()), 1), np.int32)
+    _check(lib.orc_range_brute_f64(pts, n, d, queries, nq, float(r), count,
+                                   offsets.ctypes.data, idx.ctypes.data), "range_brute_f64")
     return count, offsets, idx[:int(count.sum())]
 
 

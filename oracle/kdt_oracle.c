@@ -21,7 +21,10 @@
  *   - recursive ball query with whole-node acceptance (Algorithm 3);
  *   - friends-of-friends grouping by union-find over ball queries (Sec. 4.1);
  *   - adaptive SPH particle-to-mesh deposit with the M4 cubic spline and
- *     per-particle normalisation (Sec. 4.2), and its adjoint, in float64.
+ *     per-particle normalisation (Sec. 4.2), and its adjoint, in float64;
+ *   - brute-force kNN and ball counts/lists on float64 coordinates (the
+ *     double-precision real kind of Sec. 2.4): the same definitions with the
+ *     squared distance in IEEE float64, summed left to right over the axes.
  *
  * Readings of the paper taken here (it is silent or self-contradictory):
  *   - ties in squared distance are broken by the lower point index, so a kNN
@@ -277,6 +280,90 @@ int orc_range_brute_torus(const float *pts, int64_t n, int d, const float *q, in
 {
     if (!L) return ORC_EINVAL;
     return range_brute(pts, n, d, q, nq, r, L, out_count, offsets, out_idx);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Float64 coordinates (Sec. 2.4, double-precision real kind): brute force.  */
+/* ------------------------------------------------------------------------ */
+
+static double sq_dist64(const double *p, const double *q, int d)
+{
+    double s = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double t = p[a] - q[a];
+        s += t * t;
+    }
+    return s;
+}
+
+typedef struct {
+    double d2;
+    int32_t idx;
+} key64_t;
+
+static int key64_less(key64_t a, key64_t b)
+{
+    return a.d2 < b.d2 || (a.d2 == b.d2 && a.idx < b.idx);
+}
+
+/* The k smallest (d2, idx) keys over all n points, ascending; rows padded
+ * with (-1, +inf) when k > n. */
+int orc_knn_brute_f64(const double *pts, int64_t n, int d, const double *q, int64_t nq, int k,
+                      int32_t *out_idx, double *out_d2)
+{
+    if (!pts || !q || !out_idx || !out_d2 || n < 0 || nq < 0 || k < 1 || d < 1)
+        return ORC_EINVAL;
+    key64_t *best = (key64_t *)malloc(sizeof(key64_t) * (size_t)k);
+    if (!best) return ORC_ENOMEM;
+    for (int64_t t = 0; t < nq; ++t) {
+        const double *qt = q + t * d;
+        for (int j = 0; j < k; ++j) {
+            best[j].d2 = INFINITY;
+            best[j].idx = INT32_MAX;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            key64_t c = {sq_dist64(pts + i * d, qt, d), (int32_t)i};
+            if (!key64_less(c, best[k - 1])) continue;
+            int j = k - 1;
+            while (j > 0 && key64_less(c, best[j - 1])) {
+                best[j] = best[j - 1];
+                --j;
+            }
+            best[j] = c;
+        }
+        for (int j = 0; j < k; ++j) {
+            const int pad = best[j].idx == INT32_MAX;
+            out_idx[t * k + j] = pad ? -1 : best[j].idx;
+            out_d2[t * k + j] = pad ? INFINITY : best[j].d2;
+        }
+    }
+    free(best);
+    return ORC_OK;
+}
+
+/* Number of points with d2 <= fl64(r*r), and optionally their indices
+ * (ascending). */
+int orc_range_brute_f64(const double *pts, int64_t n, int d, const double *q, int64_t nq,
+                        double r, int64_t *out_count, int64_t *offsets, int32_t *out_idx)
+{
+    if (!pts || !q || !out_count || n < 0 || nq < 0 || d < 1 || !(r >= 0.0)) return ORC_EINVAL;
+    const double r2 = r * r;
+    int64_t pos = 0;
+    for (int64_t t = 0; t < nq; ++t) {
+        const double *qt = q + t * d;
+        int64_t c = 0;
+        if (offsets) offsets[t] = pos;
+        for (int64_t i = 0; i < n; ++i) {
+            if (sq_dist64(pts + i * d, qt, d) <= r2) {
+                if (out_idx) out_idx[pos] = (int32_t)i;
+                ++pos;
+                ++c;
+            }
+        }
+        out_count[t] = c;
+    }
+    if (offsets) offsets[nq] = pos;
+    return ORC_OK;
 }
 
 /* Friends-of-friends by breadth-first search over all pairs; on the torus of
