@@ -420,6 +420,51 @@ kdt_status kdt_query_order(const kdt_tree *tree, const float *d_q, int64_t nq, i
                            int32_t *d_order, hipStream_t stream);
 
 /*
+ * Float64 coordinates (the double-precision real kind of Sec. 2.4).
+ *
+ * kdt_build_f64 builds a tree over d_pts [n][d] float64 (device; n, d, opts
+ * as for kdt_build, split_rule 0 or 1).  The tree's shape comes from the
+ * float32 build over the coordinates rounded to float32 (clamped to the
+ * float32 range, so coordinates beyond it are fine); the tree then stores
+ * the float64 coordinates in tree order and the tight float64 box of every
+ * node, and its queries compute in float64 only.  With check_finite (the
+ * default) NaN/Inf coordinates give KDT_EINVAL (the call waits on `stream`).
+ * Such a tree answers kdt_knn_f64, kdt_range_f64, kdt_query_order (from
+ * float32 queries: the order only steers the work), kdt_tree_get_info,
+ * kdt_tree_perm and kdt_tree_export (which exports the float32 rounding of
+ * the coordinates); the float32 query calls return KDT_EUNSUPPORTED.
+ * Release it with kdt_free.
+ *
+ * kdt_knn_f64: the k (1..KDT_MAX_K) smallest (d2, index) keys of each query
+ * d_q [nq][d] float64 (NULL: every tree point, nq = n, row i = input point i), with
+ * d2 the float64 squared distance summed over the axes in order (each
+ * operation rounded on its own), ties by lower index, ascending; rows padded
+ * with (-1, +inf) when k > n.  d_idx [nq][k] int32 (may be NULL), d_d2
+ * [nq][k] float64.  opts: sort_queries and order as for kdt_knn (the order
+ * may come from kdt_query_order); traversal and split_budget are ignored
+ * (one traversal per lane); a period gives KDT_EUNSUPPORTED.
+ *
+ * kdt_range_f64: closed-ball counts (d2 <= fl64(r * r)) into d_count [nq]
+ * int32, and with d_offsets [nq + 1] int64 the CSR lists as in kdt_range
+ * (the call waits on `stream` to read the total; *required gets it;
+ * d_idx may be NULL to size first; capacity below the total gives
+ * KDT_ECAPACITY; every row ascending by input index).
+ *
+ * nq = 0 does nothing (pointers may be NULL).
+ * Errors: KDT_EINVAL (NULL pointers, a tree not built by kdt_build_f64,
+ * sizes out of range, r < 0 or NaN, k < 1), KDT_EUNSUPPORTED (d, k above
+ * KDT_MAX_K, a period), KDT_ENOMEM, KDT_ECAPACITY, KDT_EDEVICE.
+ */
+kdt_status kdt_build_f64(const double *d_pts, int64_t n, int32_t d, const kdt_build_opts *opts,
+                         hipStream_t stream, kdt_tree **out);
+kdt_status kdt_knn_f64(const kdt_tree *tree, const double *d_q, int64_t nq, int32_t k,
+                       int32_t *d_idx, double *d_d2, const kdt_query_opts *opts,
+                       hipStream_t stream);
+kdt_status kdt_range_f64(const kdt_tree *tree, const double *d_q, int64_t nq, double r,
+                         int32_t *d_count, int64_t *d_offsets, int32_t *d_idx, int64_t capacity,
+                         int64_t *required, const kdt_query_opts *opts, hipStream_t stream);
+
+/*
  * The tuning table behind leaf_size = 0 and traversal = 0 (the paper tunes
  * N_leaf by hand, Sec. 2.1 and App. A; here it is measured).  An entry gives,
  * for a shape (d, n, k), the leaf size and the queries per traversal (1: one

@@ -320,6 +320,7 @@ extern "C" kdt_status kdt_free(kdt_tree* tree) {
   if (!tree) return KDT_OK;
   hipError_t e = hipStreamSynchronize(tree->stream);
   if (tree->rec) (void)hipFreeAsync(tree->rec, tree->stream);
+  if (tree->f64_block) (void)hipFreeAsync(tree->f64_block, tree->stream);
   delete tree;
   if (e != hipSuccess) {
     kdt_set_error("kdt_free: waiting for the tree's stream failed");

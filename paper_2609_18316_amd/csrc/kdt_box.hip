@@ -224,7 +224,7 @@ extern "C" kdt_status kdt_box(const kdt_tree* tree, const float* d_lo, const flo
                               int64_t capacity, int64_t* required, const kdt_query_opts* opts,
                               hipStream_t stream) {
   kdt_clear_error();
-  if (refuse_stored(tree, "kdt_box")) return KDT_EUNSUPPORTED;
+  if (refuse_stored(tree, "kdt_box") || refuse_f64(tree, "kdt_box")) return KDT_EUNSUPPORTED;
   if (!tree || nq < 0) {
     kdt_set_error("kdt_box: NULL tree or negative nq");
     return KDT_EINVAL;

@@ -131,6 +131,7 @@ using namespace kdt;
 extern "C" kdt_status kdt_fof(const kdt_tree* tree, float l, int32_t* d_labels, int64_t* n_groups,
                               hipStream_t stream) {
   kdt_clear_error();
+  if (refuse_f64(tree, "kdt_fof")) return KDT_EUNSUPPORTED;
   if (!tree || !d_labels || !(l >= 0.0f) || !std::isfinite(l)) {
     kdt_set_error("kdt_fof: NULL tree or labels, or linking length not finite and >= 0");
     return KDT_EINVAL;

@@ -297,6 +297,12 @@ struct kdt_tree {
   // point, end point, level), nodes numbered level by level; NULL for the
   // implicit median layout
   int4* nodes = nullptr;
+  // float64 trees (kdt_build_f64): coordinates in tree order [n][d] and the
+  // tight float64 node boxes [n_nodes][2][d], one allocation (f64_block);
+  // NULL for float32 trees
+  double* rec64 = nullptr;
+  double* box64 = nullptr;
+  void* f64_block = nullptr;
 };
 
 namespace kdt {
@@ -309,6 +315,17 @@ kdt_status build_midpoint(const float* d_pts, int64_t n, int d, int leaf, bool c
 // Error reporting shared by every entry point.
 void kdt_set_error(const char* fmt, ...);
 void kdt_clear_error();
+
+// The float32 query entry points refuse a tree built from float64
+// coordinates (its float32 copy only steers the shape): true (and the error
+// set) if t is one.
+inline bool refuse_f64(const kdt_tree* t, const char* who) {
+  if (t && t->rec64) {
+    kdt_set_error("%s: the tree holds float64 coordinates; use the _f64 entry points", who);
+    return true;
+  }
+  return false;
+}
 
 // Entry points whose kernels use the median tree's implicit layout refuse a
 // sliding-midpoint tree: true (and the error set) if t is one.

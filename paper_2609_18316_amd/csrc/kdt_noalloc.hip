@@ -63,6 +63,7 @@ extern "C" kdt_status kdt_knn_noalloc(const kdt_tree* tree, const float* d_q, in
                                       int32_t k, int32_t* d_idx, float* d_d2, int32_t kth_only,
                                       const kdt_query_opts* opts, hipStream_t stream) {
   kdt_clear_error();
+  if (refuse_f64(tree, "kdt_knn_noalloc")) return KDT_EUNSUPPORTED;
   KnnArgs a;
   const kdt_status chk = knn_check(tree, d_q, nq, k, d_d2, kth_only, opts, "kdt_knn_noalloc", &a);
   if (chk != KDT_OK || a.empty) return chk;

@@ -582,6 +582,7 @@ extern "C" kdt_status kdt_knn(const kdt_tree* tree, const float* d_q, int64_t nq
                               int32_t* d_idx, float* d_d2, int32_t kth_only,
                               const kdt_query_opts* opts, hipStream_t stream) {
   kdt_clear_error();
+  if (refuse_f64(tree, "kdt_knn")) return KDT_EUNSUPPORTED;
   KnnArgs a;
   const kdt_status chk = knn_check(tree, d_q, nq, k, d_d2, kth_only, opts, "kdt_knn", &a);
   if (chk != KDT_OK || a.empty) return chk;
@@ -599,6 +600,7 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
                                 int64_t capacity, int64_t* required, const kdt_query_opts* opts,
                                 hipStream_t stream) {
   kdt_clear_error();
+  if (refuse_f64(tree, "kdt_range")) return KDT_EUNSUPPORTED;
   if (!tree || nq < 0 || !(r >= 0.0f) || !std::isfinite(r)) {
     kdt_set_error("kdt_range: NULL tree, negative nq, or r not finite and >= 0");
     return KDT_EINVAL;

@@ -550,7 +550,8 @@ using namespace kdt;
 extern "C" kdt_status kdt_fof_torus(const kdt_tree* tree, float l, const float* period,
                                     int32_t* d_labels, int64_t* n_groups, hipStream_t stream) {
   kdt_clear_error();
-  if (refuse_stored(tree, "kdt_fof_torus")) return KDT_EUNSUPPORTED;
+  if (refuse_stored(tree, "kdt_fof_torus") || refuse_f64(tree, "kdt_fof_torus"))
+    return KDT_EUNSUPPORTED;
   if (!tree || !d_labels || !period || !(l >= 0.0f) || !std::isfinite(l)) {
     kdt_set_error("kdt_fof_torus: NULL tree, labels or period, or l not finite and >= 0");
     return KDT_EINVAL;

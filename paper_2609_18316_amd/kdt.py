@@ -28,7 +28,8 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_range", "kdt_box", "kdt_fof", "kdt_fof_torus", "kdt_p2m", "kdt_p2m_cloud", "kdt_p2m_backward",
            "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
-           "kdt_stream_release", "kdt_tuning_set", "kdt_tuning_get", "kdt_last_error")
+           "kdt_stream_release", "kdt_tuning_set", "kdt_tuning_get",
+           "kdt_build_f64", "kdt_knn_f64", "kdt_range_f64", "kdt_last_error")
 # The test and measurement hooks of include/kdt_debug.h.
 DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe")
 LIB_COUNTS_PATH = os.path.join(HERE, "libkdt_counts.so")
@@ -106,6 +107,10 @@ def load(path: str = LIB_PATH):
     lib.kdt_tree_perm.restype = vp
     lib.kdt_stream_release.argtypes = [vp]
     lib.kdt_tuning_set.argtypes = [i32, i64, i32, i32, i32]
+    lib.kdt_build_f64.argtypes = [vp, i64, i32, C.POINTER(BuildOpts), vp, C.POINTER(vp)]
+    lib.kdt_knn_f64.argtypes = [vp, vp, i64, i32, vp, vp, C.POINTER(QueryOpts), vp]
+    lib.kdt_range_f64.argtypes = [vp, vp, i64, C.c_double, vp, vp, vp, i64, C.POINTER(C.c_int64),
+                                  C.POINTER(QueryOpts), vp]
     lib.kdt_tuning_get.argtypes = [i32, i64, i32, vp, vp, vp]
     if hasattr(lib, "kdt_batch_plan_create"):
         lib.kdt_batch_plan_create.argtypes = [vp, i32, i32, i32, C.POINTER(BuildOpts),
@@ -391,6 +396,70 @@ class Tree:
                                      out["end"].ctypes.data, out["level"].ctypes.data,
                                      _stream(stream)))
         return out
+
+
+class TreeF64(Tree):
+    """A tree over float64 coordinates (kdt_build_f64): its queries compute in
+    float64 (``knn``, ``range``); the float32 queries are refused."""
+
+    def __init__(self, points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
+                 stream=None, split_rule: int = SPLIT_MEDIAN, tune_k: int = 0):
+        lib = load()
+        points = _dev(points, torch.float64, "points")
+        if points.dim() != 2:
+            raise ValueError("points must be [n][d]")
+        self._h = C.c_void_p()
+        opts = BuildOpts(leaf_size, 1 if check_finite else 0, int(split_rule), int(tune_k))
+        _check(lib.kdt_build_f64(_ptr(points), points.shape[0], points.shape[1], C.byref(opts),
+                                 _stream(stream), C.byref(self._h)))
+        info = TreeInfo()
+        _check(lib.kdt_tree_get_info(self._h, C.byref(info)))
+        self.info = Info(info.n, info.d, info.leaf_size, info.levels, info.stride, info.n_nodes)
+        self.n, self.d = info.n, info.d
+        self.device = points.device
+
+    def knn(self, queries: torch.Tensor | None, k: int, sort_queries: bool = True,
+            order: torch.Tensor | None = None, stream=None, **unused):
+        """(idx int32 [nq][k], d2 float64 [nq][k]), ascending by (d2, index)."""
+        nq = self.n if queries is None else queries.shape[0]
+        if queries is not None:
+            queries = _dev(queries, torch.float64, "queries", (nq, self.d))
+        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order), 0, None)
+        idx = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((nq, k), dtype=torch.float64, device=self.device)
+        _check(load().kdt_knn_f64(self._h, _ptr(queries), nq, k, _ptr(idx), _ptr(d2),
+                                  C.byref(opts), _stream(stream)))
+        return idx, d2
+
+    def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
+              sort_queries: bool = True, order: torch.Tensor | None = None, stream=None,
+              **unused):
+        """Closed-ball counts in float64; with ``lists`` also CSR."""
+        nq = self.n if queries is None else queries.shape[0]
+        if queries is not None:
+            queries = _dev(queries, torch.float64, "queries", (nq, self.d))
+        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order), 0, None)
+        count = torch.empty(nq, dtype=torch.int32, device=self.device)
+        lib = load()
+        if not lists:
+            _check(lib.kdt_range_f64(self._h, _ptr(queries), nq, float(r), _ptr(count), None,
+                                     None, 0, None, C.byref(opts), _stream(stream)))
+            return count
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
+        req = C.c_int64(0)
+        _check(lib.kdt_range_f64(self._h, _ptr(queries), nq, float(r), _ptr(count),
+                                 _ptr(offsets), None, 0, C.byref(req), C.byref(opts),
+                                 _stream(stream)))
+        idx = torch.empty(max(req.value, 1), dtype=torch.int32, device=self.device)
+        _check(lib.kdt_range_f64(self._h, _ptr(queries), nq, float(r), _ptr(count),
+                                 _ptr(offsets), _ptr(idx), idx.numel(), C.byref(req),
+                                 C.byref(opts), _stream(stream)))
+        return count, offsets, idx[:req.value]
+
+
+def build_f64(points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
+              stream=None, split_rule: int = SPLIT_MEDIAN, tune_k: int = 0) -> TreeF64:
+    return TreeF64(points, leaf_size, check_finite, stream, split_rule, tune_k)
 
 
 def build(points: torch.Tensor, leaf_size: int = 32, check_finite: bool = True,
