@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--no-midpoint", action="store_true")
     ap.add_argument("--no-cloud", action="store_true")
     ap.add_argument("--no-grf", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-workcount", action="store_true")
     ap.add_argument("--no-counters", action="store_true",
                     help="skip the rocprofv3 counter passes over the kNN launch")
@@ -635,6 +636,39 @@ def main():
             out["cloud"][scheme + tag + "_ms"] = best
         ctree.close()
         out["cloud"]["sph_over_tsc"] = avg["p2m_fwd"] / out["cloud"]["tsc_ms"]
+    if not args.no_f64:
+        # Float64 coordinates (the double-precision real kind of Sec. 2.4):
+        # the same 2^24 points and 2^22 queries widened to float64, tuned
+        # leaf; build, kNN k = 32 and r = 0.01 counts, best of three.
+        x64 = xt.double()
+        q64 = qt.double()
+
+        def best3(call):
+            call()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                keep = call()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+                del keep
+            return float(min(ts))
+
+        f_build = best3(lambda: kdt.build_f64(x64, leaf_size=LEAF, tune_k=K, check_finite=False))
+        ft = kdt.build_f64(x64, leaf_size=LEAF, tune_k=K)
+        f_knn = best3(lambda: ft.knn(q64, K))
+        f_rng = best3(lambda: ft.range(q64, RADIUS))
+        out["f64"] = {"build_ms": f_build, "knn_ms": f_knn, "range_ms": f_rng,
+                      "build_mpts_s": N_POINTS / (f_build * 1e-3) / 1e6,
+                      "knn_queries_s": N_QUERIES / (f_knn * 1e-3),
+                      "range_queries_s": N_QUERIES / (f_rng * 1e-3),
+                      "leaf_size": ft.info.leaf_size}
+        ft.close()
+        del x64, q64
+        print(f"[bench] float64 coordinates: {out['f64']}", file=sys.stderr, flush=True)
     if not args.no_grf:
         # The paper's inhomogeneous mock (Sec. 3.1): 2^24 points from a
         # Gaussian random field of spectral index -2; build, kNN k = 32 of the
