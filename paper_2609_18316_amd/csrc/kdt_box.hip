@@ -190,8 +190,21 @@ static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d
     kdt_set_error("device allocation failed for the box lists");
     return KDT_ENOMEM;
   }
-  k_box<D, true><<<grid, kBoxBlock, smem, stream>>>(v, d_lo, d_hi, nq, order, d_count, d_off,
-                                                     unsorted);
+  if (tr->leaf <= 64 && traversal != 1) {
+    // the wave-shared traversal of the counts, writing the lists
+    int32_t* cur = nullptr;
+    if (!buf.get(&cur, (size_t)nq)) {
+      kdt_set_error("device allocation failed for the box list cursors");
+      return KDT_ENOMEM;
+    }
+    const FillOut fo{unsorted, d_off, cur};
+    const kdt_status st = box_packet_launch<D>(v, tr->leaf, d_lo, d_hi, nq, order, d_count,
+                                               split_budget, stream, &fo);
+    if (st != KDT_OK) return st;
+  } else {
+    k_box<D, true><<<grid, kBoxBlock, smem, stream>>>(v, d_lo, d_hi, nq, order, d_count, d_off,
+                                                       unsorted);
+  }
   void* stmp = nullptr;
   size_t sb = 0;
   if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total, (int)nq,

@@ -39,6 +39,8 @@ struct LeafReader {
 #pragma unroll
     for (int a = 0; a < D; ++a) x[a] = lds[i * S + a];
   }
+  // The input index of point i of the open leaf.
+  __device__ __forceinline__ int32_t index(int i) const { return __float_as_int(lds[i * S + D]); }
   // Point i of the open leaf and its index, i per lane.
   __device__ __forceinline__ void lane_point(int i, float x[D], int32_t& id) const {
 #pragma unroll
@@ -422,7 +424,8 @@ __device__ __forceinline__ bool hand_off(const PacketSpill& spill, int levels, u
 template <int D>
 kdt_status box_packet_launch(const TreeView& v, int leaf, const float* d_lo, const float* d_hi,
                              int64_t nq, const int32_t* order, int32_t* d_count,
-                             uint32_t split_budget, hipStream_t stream);
+                             uint32_t split_budget, hipStream_t stream,
+                             const FillOut* fill = nullptr);
 
 // Query shapes of the wave-shared counts.  Each says whether it cuts a node
 // box, holds a node box whole, and holds a point, and packs into kFloats
@@ -536,10 +539,29 @@ struct BoxShape {
 };
 
 // LDS floats of one wave of a count: the open leaf, then the packed queries
-// [64][K] (K floats per query shape) and their counts [64].
+// [64][K] (K floats per query shape), their counts [64] and, for the fill,
+// their hit masks [64] (uint64).
 template <int D, int K = D>
 __host__ __device__ constexpr size_t range_wave_floats(int leaf) {
-  return (size_t)leaf * rec_stride(D) + 64 * (K + 1);
+  return (size_t)leaf * rec_stride(D) + 64 * (K + 1) + 128;
+}
+
+// Fill mode: a lane appends n indices to its row; returns the first slot.
+__device__ __forceinline__ int64_t fill_reserve(const FillOut& fo, int64_t row, int n) {
+  return fo.off[row] + atomicAdd(fo.cur + row, n);
+}
+
+// Fill mode: a lane's leaf hits (bit i: point i of the open leaf) into its row.
+template <class Leaf>
+__device__ __forceinline__ void fill_hits(const FillOut& fo, int64_t row, uint64_t hits,
+                                          const Leaf& leaf) {
+  if (!hits) return;
+  int64_t at = fill_reserve(fo, row, __popcll(hits));
+  while (hits) {
+    const int i = __ffsll((unsigned long long)hits) - 1;
+    hits &= hits - 1;
+    fo.out[at++] = leaf.index(i);
+  }
 }
 
 // Counts of the 64 query shapes of a wave (closed balls: Algorithm 3
@@ -563,18 +585,26 @@ __host__ __device__ constexpr size_t range_wave_floats(int leaf) {
 // writes its remaining stack entries (entry i sits in lane i) as tasks for a
 // later pass and returns its partial counts; the later passes add theirs, so
 // every count is the same integer sum.
-template <int D, class Shape>
+//
+// FILL: the same traversal writes the CSR lists (FillOut) of the lanes'
+// rows instead of only counting: a whole node is written for each lane that
+// holds it by the whole wave (64 entries per step, its rows' slots reserved
+// by that lane), a leaf's hits by each lane from its hit mask.
+template <int D, class Shape, bool FILL = false>
 __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const Shape& sh,
                                                       bool active, float* lds,
                                                       int leaf_cap, uint32_t start,
                                                       uint64_t start_mask, uint32_t group,
-                                                      const PacketSpill& spill) {
+                                                      const PacketSpill& spill,
+                                                      int64_t row = 0,
+                                                      const FillOut& fo = FillOut{}) {
   constexpr int S = rec_stride(D);
   constexpr int K = Shape::kFloats;
   const int lane = lane_id();
   LeafReader<D> leaf(t.rec, lds);
   float* cq = lds + (size_t)leaf_cap * S;                  // packed queries [64][K]
   int32_t* cc = reinterpret_cast<int32_t*>(cq + 64 * K);  // their counts [64]
+  uint64_t* cm = reinterpret_cast<uint64_t*>(cc + 64);    // their hit masks [64] (fill)
   const uint32_t first_leaf = (1u << t.levels) - 1u;
   int64_t count = 0;
   uint32_t stackv = start;                         // lane i: node of entry i
@@ -601,6 +631,21 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const S
     const int64_t j = (int64_t)node - ((int64_t(1) << lev) - 1);
     const int64_t b = node_begin(t.n, lev, j), e = node_begin(t.n, lev, j + 1);
     if (full) count += e - b;
+    if (FILL) {
+      uint64_t fm = __ballot(full);
+      if (fm) {
+        constexpr int S2 = rec_stride(D);
+        const int64_t at = full ? fill_reserve(fo, row, (int)(e - b)) : 0;
+        while (fm) {
+          const int l = __ffsll((unsigned long long)fm) - 1;
+          fm &= fm - 1;
+          const int64_t dst = ((int64_t)__builtin_amdgcn_readlane((int)(at >> 32), l) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)at, l);
+          for (int64_t i = b + lane; i < e; i += 64)
+            fo.out[dst + (i - b)] = __float_as_int(t.rec[i * S2 + D]);
+        }
+      }
+    }
     const bool part = touch && !full;
     const uint64_t pm = __ballot(part);
     if (pm == 0) continue;
@@ -626,19 +671,27 @@ __device__ __forceinline__ int64_t packet_range_count(const TreeView& t, const S
           const Shape qs = sh.unpack(cq + ac * K);
           const bool hit = i < cnt && a < na && qs.holds(x);
           const uint64_t hm = __ballot(hit);
-          if (i == 0 && a < na) cc[a] = __popcll((hm >> (slot * W)) & wmask);
+          if (i == 0 && a < na) {
+            cc[a] = __popcll((hm >> (slot * W)) & wmask);
+            if (FILL) cm[a] = (hm >> (slot * W)) & wmask;
+          }
         }
         wave_sync();
         if (part) count += cc[me];
+        if (FILL && part) fill_hits(fo, row, cm[me], leaf);
       } else {
         int c = 0;
+        uint64_t hits = 0;
 #pragma unroll uniform_batch<D>()
         for (int i = 0; i < cnt; ++i) {
           float x[D];
           leaf.point(i, x);
-          c += sh.holds(x);
+          const bool h = sh.holds(x);
+          c += h;
+          if (FILL) hits |= (uint64_t)h << i;
         }
         if (part) count += c;
+        if (FILL && part) fill_hits(fo, row, hits, leaf);
       }
     } else {
       const uint32_t mlo = (uint32_t)pm, mhi = (uint32_t)(pm >> 32);

@@ -149,12 +149,14 @@ __host__ __device__ constexpr size_t count_wave_floats(int leaf) {
 }
 
 // First pass of the counts: one 64-query group per wave from the root; writes
-// each count (partial if the wave handed subtrees on).
-template <int D, class Q>
+// each count (partial if the wave handed subtrees on), or with FILL the
+// lists.
+template <int D, class Q, bool FILL>
 __global__ __launch_bounds__(64 * kPWaves) void k_count_packet(TreeView t, Q src, int64_t nq,
                                                                const int32_t* __restrict__ order,
                                                                int32_t* __restrict__ count,
-                                                               int leaf_cap, PacketSpill spill) {
+                                                               int leaf_cap, PacketSpill spill,
+                                                               FillOut fo) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t s0 = (xcd_block<kXcdRunPacket>() * kPWaves + wave) * 64;
@@ -162,20 +164,20 @@ __global__ __launch_bounds__(64 * kPWaves) void k_count_packet(TreeView t, Q src
   typename Q::Shape sh;
   int64_t row = 0;
   const bool active = src.load(t, nq, order, s0 + lane, sh, row);
-  const int64_t c = packet_range_count<D>(t, sh, active,
-                                          lds + (size_t)wave * count_wave_floats<D, Q>(leaf_cap),
-                                          leaf_cap, 0u, ~0ull, (uint32_t)(s0 / 64), spill);
-  if (active) count[row] = (int32_t)c;
+  const int64_t c = packet_range_count<D, typename Q::Shape, FILL>(
+      t, sh, active, lds + (size_t)wave * count_wave_floats<D, Q>(leaf_cap), leaf_cap, 0u, ~0ull,
+      (uint32_t)(s0 / 64), spill, row, fo);
+  if (!FILL && active) count[row] = (int32_t)c;
   wave_done(spill);
 }
 
 // A later pass: each wave takes tasks left by the previous pass (a fixed
 // count, read at start, so every wave's loop ends) and adds its counts.
-template <int D, class Q>
+template <int D, class Q, bool FILL>
 __global__ __launch_bounds__(64 * kPWaves) void k_count_tasks(
     TreeView t, Q src, int64_t nq, const int32_t* __restrict__ order,
     int32_t* __restrict__ count, int leaf_cap, const PacketTask* __restrict__ in,
-    const uint32_t* __restrict__ in_count, uint32_t in_cap, PacketSpill spill) {
+    const uint32_t* __restrict__ in_count, uint32_t in_cap, PacketSpill spill, FillOut fo) {
   extern __shared__ __align__(16) float lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t n = min(*in_count, in_cap);
@@ -187,14 +189,19 @@ __global__ __launch_bounds__(64 * kPWaves) void k_count_tasks(
     int64_t row = 0;
     const bool active = src.load(t, nq, order, (int64_t)task.group * 64 + lane, sh, row);
     const uint64_t mask = ((uint64_t)task.hi << 32) | task.lo;
-    const int64_t c = packet_range_count<D>(t, sh, active, slice, leaf_cap, task.node, mask,
-                                            task.group, spill);
-    if (active && c != 0) atomicAdd(count + row, (int32_t)c);
+    const int64_t c = packet_range_count<D, typename Q::Shape, FILL>(
+        t, sh, active, slice, leaf_cap, task.node, mask, task.group, spill, row, fo);
+    if (!FILL && active && c != 0) atomicAdd(count + row, (int32_t)c);
   }
 }
 
 __global__ void k_zero_tasks(uint32_t* c, int n) {
   if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 template <int D>
@@ -303,11 +310,14 @@ kdt_status knn_packet_launch(const TreeView& v, int leaf, const float* d_q, int6
 // The wave-shared counts (balls or boxes), with heavy traversals split over
 // kRangePasses launches: the first kRangePasses - 1 hand off what exceeds their
 // budget of node visits, the last finishes everything.
+//
+// With `fill` the same launches write the CSR lists instead (fill->cur zeroed
+// here first); d_count is then not written.
 template <int D, class Q>
 static kdt_status count_packet_launch(const TreeView& v, int leaf, Q src, int64_t nq,
                                       const int32_t* order, int32_t* d_count,
                                       uint32_t split_budget, hipStream_t stream,
-                                      const char* who) {
+                                      const char* who, const FillOut* fill = nullptr) {
   const unsigned grid = (unsigned)((nq + 64 * kPWaves - 1) / (64 * kPWaves));
   const size_t smem = sizeof(float) * count_wave_floats<D, Q>(leaf) * kPWaves;
   PoolBuffers buf(stream);
@@ -328,17 +338,27 @@ static kdt_status count_packet_launch(const TreeView& v, int leaf, Q src, int64_
   const uint32_t tail_from = split_budget                ? 0u
                              : waves > kRangeTailWaves ? (uint32_t)(waves - kRangeTailWaves)
                                                        : 0u;
-  k_count_packet<D, Q><<<grid, 64 * kPWaves, smem, stream>>>(
-      v, src, nq, order, d_count, leaf,
-      PacketSpill{tasks, counts, kRangeTaskCap, first, counts + kRangePasses, tail_from});
+  const FillOut fo = fill ? *fill : FillOut{nullptr, nullptr, nullptr};
+  if (fill) k_zero_i32<<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(fill->cur, nq);
+  const PacketSpill sp0{tasks, counts, kRangeTaskCap, first, counts + kRangePasses, tail_from};
+  if (fill)
+    k_count_packet<D, Q, true><<<grid, 64 * kPWaves, smem, stream>>>(v, src, nq, order, d_count,
+                                                                     leaf, sp0, fo);
+  else
+    k_count_packet<D, Q, false><<<grid, 64 * kPWaves, smem, stream>>>(v, src, nq, order, d_count,
+                                                                      leaf, sp0, fo);
   for (int pass = 1; pass < kRangePasses; ++pass) {
     const bool last = pass == kRangePasses - 1;
     const PacketSpill out = last ? PacketSpill{nullptr, nullptr, 0u, 0u, nullptr, 0u}
                                 : PacketSpill{tasks + (size_t)pass * kRangeTaskCap, counts + pass,
                                              kRangeTaskCap, later, nullptr, 0u};
-    k_count_tasks<D, Q><<<kRangeTaskBlocks, 64 * kPWaves, smem, stream>>>(
-        v, src, nq, order, d_count, leaf, tasks + (size_t)(pass - 1) * kRangeTaskCap,
-        counts + pass - 1, kRangeTaskCap, out);
+    const PacketTask* in = tasks + (size_t)(pass - 1) * kRangeTaskCap;
+    if (fill)
+      k_count_tasks<D, Q, true><<<kRangeTaskBlocks, 64 * kPWaves, smem, stream>>>(
+          v, src, nq, order, d_count, leaf, in, counts + pass - 1, kRangeTaskCap, out, fo);
+    else
+      k_count_tasks<D, Q, false><<<kRangeTaskBlocks, 64 * kPWaves, smem, stream>>>(
+          v, src, nq, order, d_count, leaf, in, counts + pass - 1, kRangeTaskCap, out, fo);
   }
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("%s: packet kernel launch failed", who);
@@ -350,26 +370,26 @@ static kdt_status count_packet_launch(const TreeView& v, int leaf, Q src, int64_
 template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
                                const int32_t* order, int32_t* d_count, uint32_t split_budget,
-                               hipStream_t stream) {
+                               hipStream_t stream, const FillOut* fill) {
   return count_packet_launch<D>(v, leaf, BallQueries<D>{d_q, r2}, nq, order, d_count,
-                                split_budget, stream, "kdt_range");
+                                split_budget, stream, "kdt_range", fill);
 }
 
 template <int D>
 kdt_status box_packet_launch(const TreeView& v, int leaf, const float* d_lo, const float* d_hi,
                              int64_t nq, const int32_t* order, int32_t* d_count,
-                             uint32_t split_budget, hipStream_t stream) {
+                             uint32_t split_budget, hipStream_t stream, const FillOut* fill) {
   return count_packet_launch<D>(v, leaf, BoxQueries<D>{d_lo, d_hi}, nq, order, d_count,
-                                split_budget, stream, "kdt_box");
+                                split_budget, stream, "kdt_box", fill);
 }
 
 template <int D>
 kdt_status torus_range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq,
                                      float r2, const Torus<D>& T, const int32_t* order,
                                      int32_t* d_count, uint32_t split_budget,
-                                     hipStream_t stream) {
+                                     hipStream_t stream, const FillOut* fill) {
   return count_packet_launch<D>(v, leaf, TorusBallQueries<D>{d_q, r2, T}, nq, order, d_count,
-                                split_budget, stream, "kdt_range");
+                                split_budget, stream, "kdt_range", fill);
 }
 
 template <int D, class Metric>
@@ -384,15 +404,17 @@ kdt_status var_ball_count_launch(const TreeView& v, int leaf, const float* d_q, 
   template kdt_status knn_packet_launch<D>(const TreeView&, int, const float*, int64_t, int,       \
                                            int32_t*, float*, int, const int32_t*, hipStream_t);    \
   template kdt_status range_packet_launch<D>(const TreeView&, int, const float*, int64_t, float,   \
-                                             const int32_t*, int32_t*, uint32_t, hipStream_t);   \
+                                             const int32_t*, int32_t*, uint32_t, hipStream_t,    \
+                                             const FillOut*);                                    \
   template kdt_status box_packet_launch<D>(const TreeView&, int, const float*, const float*,       \
                                            int64_t, const int32_t*, int32_t*, uint32_t,          \
-                                           hipStream_t);                                         \
+                                           hipStream_t, const FillOut*);                         \
   template kdt_status fof_packet_launch<D>(const TreeView&, int, float, int32_t*, uint32_t*,       \
                                            hipStream_t);                                         \
   template kdt_status torus_range_packet_launch<D>(const TreeView&, int, const float*, int64_t,    \
                                                    float, const Torus<D>&, const int32_t*,       \
-                                                   int32_t*, uint32_t, hipStream_t);     \
+                                                   int32_t*, uint32_t, hipStream_t,              \
+                                                   const FillOut*);                              \
   template kdt_status torus_fof_packet_launch<D>(const TreeView&, int, float, const Torus<D>&,     \
                                                  int32_t*, uint32_t*, hipStream_t);              \
   template kdt_status var_ball_count_launch<D, OpenMetric<D>>(                                     \

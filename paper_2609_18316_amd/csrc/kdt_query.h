@@ -17,6 +17,17 @@ struct TreeView {
   unsigned long long* visits = nullptr;  // work counters of the instrumented build, else NULL
 };
 
+// Where the wave-shared counts write CSR lists in fill mode: the indices of
+// row r go to out[off[r] ..], a slot at a time reserved with an atomic on the
+// row's cursor cur[r] (zero before the first pass), so the subtrees a wave
+// hands on to later passes append the same way.  The order within a row
+// depends on the schedule; callers sort each row afterwards.
+struct FillOut {
+  int32_t* out;
+  const int64_t* off;
+  int32_t* cur;
+};
+
 // Work counters of the instrumented build (compiled with KDT_COUNT_VISITS):
 // how many node boxes and point records the traversals read, for the
 // algorithmic bytes of the roofline.  Slots: kVisitNodes / kVisitPoints /
@@ -668,7 +679,7 @@ kdt_status knn_in_workspace(const kdt_tree* t, const float* d_q, int64_t nq, int
 template <int D>
 kdt_status range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq, float r2,
                                const int32_t* order, int32_t* d_count, uint32_t split_budget,
-                               hipStream_t stream);
+                               hipStream_t stream, const FillOut* fill = nullptr);
 template <int D>
 kdt_status fof_packet_launch(const TreeView& v, int leaf, float l2, int32_t* parent, uint32_t* conn,
                              hipStream_t stream);

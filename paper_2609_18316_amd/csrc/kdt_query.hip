@@ -456,13 +456,27 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
           kdt_set_error("device allocation failed for the lists");
           st = KDT_ENOMEM;
         } else {
-          if (t->nodes)
+          int32_t* cur = nullptr;
+          if (t->nodes) {
             k_range<D, true, StoredShape><<<grid, kQBlock, rsmem, stream>>>(
                 v, d_q, nq, r2, order, d_count, d_off, unsorted);
-          else
+          } else if (t->leaf <= 64 && traversal != 1) {
+            // the wave-shared traversal of the counts, writing the lists
+            if (!buf.get(&cur, (size_t)nq)) {
+              kdt_set_error("device allocation failed for the list cursors");
+              st = KDT_ENOMEM;
+            } else {
+              const FillOut fo{unsorted, d_off, cur};
+              st = range_packet_launch<D>(v, t->leaf, d_q, nq, r2, order, d_count, split_budget,
+                                          stream, &fo);
+            }
+          } else {
             k_range<D, true><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count,
                                                                d_off, unsorted);
-          if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total,
+          }
+          if (st != KDT_OK) {
+            // reported above
+          } else if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total,
                                                     (int)nq, d_off, d_off + 1, stream) !=
               hipSuccess) {
             kdt_set_error("kdt_range: list sort setup failed");

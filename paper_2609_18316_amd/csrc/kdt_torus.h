@@ -115,11 +115,11 @@ kdt_status torus_fof_packet_launch(const TreeView& v, int leaf, float l2, const 
                                    int32_t* parent, uint32_t* conn, hipStream_t stream);
 
 // Torus ball counts through the wave-shared count traversal (kdt_packet.hip);
-// arguments as range_packet_launch.
+// arguments as range_packet_launch (fill: CSR lists instead of counts).
 template <int D>
 kdt_status torus_range_packet_launch(const TreeView& v, int leaf, const float* d_q, int64_t nq,
                                      float r2, const Torus<D>& T, const int32_t* order,
                                      int32_t* d_count, uint32_t split_budget,
-                                     hipStream_t stream);
+                                     hipStream_t stream, const FillOut* fill = nullptr);
 
 }  // namespace kdt

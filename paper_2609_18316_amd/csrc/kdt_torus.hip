@@ -317,8 +317,21 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
     kdt_set_error("device allocation failed for the lists");
     return KDT_ENOMEM;
   }
-  k_torus_range<D, true><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, r2, order, T, d_count, d_off,
-                                                           unsorted);
+  if (tr->leaf <= 64) {
+    // the wave-shared traversal of the counts, writing the lists
+    int32_t* cur = nullptr;
+    if (!buf.get(&cur, (size_t)nq)) {
+      kdt_set_error("device allocation failed for the list cursors");
+      return KDT_ENOMEM;
+    }
+    const FillOut fo{unsorted, d_off, cur};
+    st = torus_range_packet_launch<D>(v, tr->leaf, d_q, nq, r2, T, order, d_count, 0u, stream,
+                                      &fo);
+    if (st != KDT_OK) return st;
+  } else {
+    k_torus_range<D, true><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, r2, order, T, d_count,
+                                                             d_off, unsorted);
+  }
   void* stmp = nullptr;
   size_t sb = 0;
   if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total, (int)nq,

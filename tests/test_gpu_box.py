@@ -50,6 +50,10 @@ def test_box_counts_and_lists(d):
             for trav, budget in ((1, 0), (2, 0), (2, 3)):  # per lane; wave-shared; handed on
                 got = t.box(to_dev(lo), to_dev(hi), traversal=trav, split_budget=budget)
                 np.testing.assert_array_equal(to_host(got), oc)
+                c, off, lst = t.box(to_dev(lo), to_dev(hi), lists=True, traversal=trav,
+                                    split_budget=budget)
+                np.testing.assert_array_equal(to_host(off), ooff)
+                np.testing.assert_array_equal(to_host(lst), olst)
 
 
 @pytest.mark.parametrize("leaf", (8, 32, 64))
