@@ -27,6 +27,9 @@ namespace kdt {
 constexpr int kLBlock = 128;
 constexpr int64_t kBigKeysPerChunk = int64_t(1) << 27;  // 1 GiB of keys
 constexpr int kBigGrowRounds = 24;  // then the radius becomes infinite
+// Largest k sorted in LDS (128 KiB of keys per workgroup; gfx950 gives a
+// workgroup up to 160 KiB); larger k takes the segmented radix sort.
+constexpr int kTopkMax = 16384;
 // Margin on estimated squared radii (x 1.1^(d/2) expected points), the least
 // growth of a radius that fell short, and the cap of that least growth for
 // stuck rows.
@@ -236,6 +239,101 @@ __global__ void k_take_first(const uint64_t* __restrict__ keys, const int32_t* _
     od2[row * k + j] = d2;
   } else {
     od2[row] = mode == 2 ? sqrtf(d2) : d2;
+  }
+}
+
+// The k smallest keys of each row of the chunk, sorted and written as
+// (index, d2) pairs (mode 0), one workgroup per row.  The row's keys go to
+// LDS -- all of them when they fit in P, else only the k smallest, found
+// first by a radix select over the key bits, 8 bits per pass from the top
+// (keys are distinct: they end in the point index, so exactly k keys are at
+// or below the k-th) -- and are sorted there by a bitonic network over the
+// next power of two, padded with all-ones keys.  Needs k <= P.
+template <int P>
+constexpr int topk_threads() {
+  return P <= 1024 ? 128 : P <= 4096 ? 256 : 1024;
+}
+
+template <int P>
+__global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
+    const uint64_t* __restrict__ keys, const int32_t* __restrict__ rel,
+    const int32_t* __restrict__ rowof, int64_t s0, int k, int ib, int32_t* __restrict__ oidx,
+    float* __restrict__ od2) {
+  constexpr int T = topk_threads<P>();
+  __shared__ uint64_t s[P];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sh_digit, sh_rank, sh_fill;
+  const int tid = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const int64_t row = rowof ? (int64_t)rowof[s0 + i] : s0 + i;
+  const int32_t have = rel[i + 1] - rel[i];
+  const uint64_t* __restrict__ src = keys + rel[i];
+  int n = have;
+  if (have > P) {
+    const int bits = 32 + ib;
+    uint64_t prefix = 0ull, mask = 0ull;
+    uint32_t rank = (uint32_t)k;  // rank of the wanted key among those matching prefix
+    for (int shift = (bits - 1) / 8 * 8; shift >= 0; shift -= 8) {
+      for (int j = tid; j < 256; j += T) hist[j] = 0u;
+      __syncthreads();
+      for (int32_t e = tid; e < have; e += T) {
+        const uint64_t key = src[e];
+        if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t acc = 0u;
+        int dsel = 255;
+        for (int dg = 0; dg < 256; ++dg) {
+          if (acc + hist[dg] >= rank) {
+            dsel = dg;
+            break;
+          }
+          acc += hist[dg];
+        }
+        sh_digit = (uint32_t)dsel;
+        sh_rank = rank - acc;
+      }
+      __syncthreads();
+      prefix |= (uint64_t)sh_digit << shift;
+      mask |= 255ull << shift;
+      rank = sh_rank;
+      __syncthreads();  // every thread has read sh_digit before the next pass
+    }
+    // prefix is the k-th smallest key: the keys at or below it are exactly k
+    if (tid == 0) sh_fill = 0u;
+    __syncthreads();
+    for (int32_t e = tid; e < have; e += T) {
+      const uint64_t key = src[e];
+      if (key <= prefix) s[atomicAdd(&sh_fill, 1u)] = key;
+    }
+    n = k;
+  } else {
+    for (int32_t e = tid; e < have; e += T) s[e] = src[e];
+  }
+  int pn = 1;
+  while (pn < n) pn <<= 1;
+  for (int e = n + tid; e < pn; e += T) s[e] = ~0ull;
+  __syncthreads();
+  for (int size = 2; size <= pn; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < pn / 2; t += T) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const uint64_t a = s[lo], c = s[hi];
+        if ((a > c) == ((lo & size) == 0)) {
+          s[lo] = c;
+          s[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = tid; j < k; j += T) {
+    const bool empty = j >= n;
+    const uint64_t key = empty ? 0ull : s[j];
+    if (oidx) oidx[row * k + j] = empty ? -1 : (int32_t)(key & ((1ull << ib) - 1ull));
+    od2[row * k + j] = empty ? INFINITY : __uint_as_float((uint32_t)(key >> ib));
   }
 }
 
@@ -469,6 +567,22 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
     }
     if (mode != 0) {  // only the k-th distance: selected, not sorted
       k_row_kth<<<(unsigned)m, 64, 0, stream>>>(keys, rel, rowof, s0, k, mode, ib, d_d2);
+      s0 = s1;
+      continue;
+    }
+    if (k <= kTopkMax) {  // rows sorted in LDS, the k smallest written directly
+      int64_t widest = 0;
+      for (int64_t r = s0; r < s1; ++r) widest = std::max(widest, h_off[r + 1] - h_off[r]);
+      const int64_t want = std::max<int64_t>(k, std::min<int64_t>(widest, kTopkMax));
+      if (want <= 1024)
+        k_row_topk<1024><<<(unsigned)m, topk_threads<1024>(), 0, stream>>>(keys, rel, rowof, s0, k,
+                                                                            ib, d_idx, d_d2);
+      else if (want <= 4096)
+        k_row_topk<4096><<<(unsigned)m, topk_threads<4096>(), 0, stream>>>(keys, rel, rowof, s0, k,
+                                                                            ib, d_idx, d_d2);
+      else
+        k_row_topk<kTopkMax><<<(unsigned)m, topk_threads<kTopkMax>(), 0, stream>>>(
+            keys, rel, rowof, s0, k, ib, d_idx, d_d2);
       s0 = s1;
       continue;
     }

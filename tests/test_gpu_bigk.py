@@ -141,3 +141,25 @@ def test_large_k_lattice_ties():
         np.testing.assert_array_equal(to_host(t.knn(to_dev(q), k, kth_only=1)), od[:, -1])
         np.testing.assert_array_equal(to_host(t.knn(to_dev(q), k, kth_only=2)),
                                       np.sqrt(od[:, -1]))
+
+
+def test_large_k_rows_beyond_the_lds_sort():
+    """Rows whose candidate ball holds more keys than one workgroup sorts in
+    LDS (16384): the k smallest are selected first.  Coincident points (the
+    ball of every query holds them all) and a 1/32 lattice (masses of equal
+    distances, ties by index) at k = 1000 and 9000; also k = 16384 itself."""
+    dev()
+    rng = np.random.Generator(np.random.PCG64(77))
+    same = np.full((20000, 3), 0.5, np.float32)
+    lat = (rng.integers(0, 8, size=(40000, 3)) / 32.0).astype(np.float32)
+    for x, ks in ((same, (1000, 9000, 16384)), (lat, (1000, 9000))):
+        q = np.concatenate([x[:20], (rng.integers(0, 8, size=(20, 3)) / 32.0 + 1 / 64.0)
+                            .astype(np.float32)])
+        t = kdt.build(to_dev(x), leaf_size=32)
+        for k in ks:
+            say(f"large k={k} on {len(x)} points with wide candidate rows")
+            oi, od = oracle.knn_brute(x, q, k)
+            gi, gd = t.knn(to_dev(q), k)
+            np.testing.assert_array_equal(to_host(gi), oi)
+            np.testing.assert_array_equal(to_host(gd), od)
+        t.close()
