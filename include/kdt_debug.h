@@ -44,6 +44,15 @@ kdt_status kdt_debug_visits(uint64_t *h_counts, int32_t reset);
 kdt_status kdt_debug_valu_probe(float *d_out, int32_t blocks, int32_t iters,
                                 hipStream_t stream);
 
+/*
+ * The library's radix sort (the one that orders queries): sorts n pairs
+ * (d_keys [n] uint32, d_vals [n] int32, device, in place) by the key bits
+ * [begin_bit, end_bit), stably, asynchronously on `stream`.  For testing the
+ * sort against a reference.  Errors: KDT_EINVAL, KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_debug_radix_sort(uint32_t *d_keys, int32_t *d_vals, int64_t n, int32_t begin_bit,
+                                int32_t end_bit, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

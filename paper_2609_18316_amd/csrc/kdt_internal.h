@@ -166,6 +166,14 @@ bool make_plan(const int64_t* offsets, int n_sets, int d, const int* leaves, Pla
 
 int levels_for(int64_t n, int leaf);
 
+// Stable LSD radix sort of (key, value) pairs on key bits [begin_bit, end_bit)
+// (kdt_sort.hip), 8 bits per pass, ping-ponging between keys[0]/keys[1] and
+// vals[0]/vals[1] (input in [0]); returns the index of the pair of arrays
+// holding the result.  scratch: radix_sort_scratch_bytes(n) device bytes.
+size_t radix_sort_scratch_bytes(int64_t n);
+int radix_sort_pairs(uint32_t* keys[2], int32_t* vals[2], int64_t n, int begin_bit, int end_bit,
+                     void* scratch, hipStream_t stream);
+
 // The tuning table (kdt_tuning.hip): N_leaf and queries per traversal (1 or
 // 64) measured fastest for the nearest shape of dimension d.
 struct Tuning {

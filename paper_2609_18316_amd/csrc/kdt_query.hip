@@ -263,9 +263,7 @@ static kdt_status order_queries(const kdt_tree* t, const float* d_q, int64_t nq,
   }
   PoolBuffers buf(stream);
   uint32_t *k0 = nullptr, *k1 = nullptr;
-  int32_t *v0 = nullptr, *v1 = dst;
-  void* tmp = nullptr;
-  size_t tmp_bytes = 0;
+  int32_t *v0 = nullptr, *v1 = nullptr;
   // up to 4 dimensions a Hilbert key over the root box; above, the leaf
   // reached by descending towards the nearer child
   const bool hilbert = D <= 4 && kind == 0;
@@ -273,14 +271,13 @@ static kdt_status order_queries(const kdt_tree* t, const float* d_q, int64_t nq,
   int node_bits = 1;
   while (node_bits < 31 && (int64_t(1) << node_bits) < t->n_nodes) ++node_bits;
   const int end_bit = hilbert ? (30 / D) * D : t->nodes ? node_bits : std::max(1, t->levels + 1);
-  // The double-buffer form of the sort ping-pongs between the two key and
-  // the two index arrays, so its temporary storage holds only histograms and
-  // look-back state (about 2 MB at 2^22 queries, against 34 MB for the form
-  // that copies its input).
-  hipcub::DoubleBuffer<uint32_t> keys(k0, k1);
-  hipcub::DoubleBuffer<int32_t> vals(v0, v1);
-  KDT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys, vals, (int)nq, 0, end_bit,
-                                             stream));
+  // The sort (kdt_sort.hip) ping-pongs between two key and two index arrays,
+  // one pass per 8 key bits; the keys are written into the buffer that makes
+  // the last pass land in the caller's array, so nothing is copied.
+  const int passes = nq > 1 ? (end_bit + 7) / 8 : 0;
+  const int last = passes & 1;
+  const size_t tmp_bytes = radix_sort_scratch_bytes(nq);
+  void* tmp = nullptr;
   if (ws) {
     const size_t a = ((size_t)nq * 4 + 255) / 256 * 256;  // one key or index array
     const size_t need = 4 * a + tmp_bytes;
@@ -293,32 +290,31 @@ static kdt_status order_queries(const kdt_tree* t, const float* d_q, int64_t nq,
     k0 = reinterpret_cast<uint32_t*>(w);
     k1 = reinterpret_cast<uint32_t*>(w + a);
     v0 = reinterpret_cast<int32_t*>(w + 2 * a);
-    if (!dst) v1 = reinterpret_cast<int32_t*>(w + 3 * a);
+    v1 = reinterpret_cast<int32_t*>(w + 3 * a);
     tmp = w + 4 * a;
-  } else if (!buf.get(&k0, (size_t)nq) || !buf.get(&k1, (size_t)nq) || !buf.get(&v0, (size_t)nq) ||
-             (!dst && !buf.get(&v1, (size_t)nq)) || !buf.get((char**)&tmp, tmp_bytes)) {
+  } else if (!buf.get(&k0, (size_t)nq) || !buf.get(&k1, (size_t)nq) ||
+             !buf.get(&v0, (size_t)nq) || (!dst && !buf.get(&v1, (size_t)nq)) ||
+             !buf.get((char**)&tmp, tmp_bytes)) {
     kdt_set_error("device allocation failed for query ordering");
     return KDT_ENOMEM;
   }
+  int32_t* vals[2] = {v0, v1};
+  if (dst) vals[last] = dst, vals[last ^ 1] = v0;
+  uint32_t* keys[2] = {k0, k1};
   if (hilbert)
-    k_query_hilbert<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq, k0, v0);
+    k_query_hilbert<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq,
+                                                                         keys[0], vals[0]);
   else if (t->nodes)
-    k_query_leaf<D, StoredShape><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q,
-                                                                                   nq, k0, v0);
+    k_query_leaf<D, StoredShape><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(
+        view_of(t), d_q, nq, keys[0], vals[0]);
   else
-    k_query_leaf<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq, k0, v0);
+    k_query_leaf<D><<<(unsigned)((nq + 255) / 256), 256, 0, stream>>>(view_of(t), d_q, nq,
+                                                                      keys[0], vals[0]);
   KDT_HIP(hipGetLastError());
-  keys = hipcub::DoubleBuffer<uint32_t>(k0, k1);
-  vals = hipcub::DoubleBuffer<int32_t>(v0, v1);
-  KDT_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, vals, (int)nq, 0, end_bit,
-                                             stream));
-  int32_t* sorted = vals.Current();
-  if (dst) {
-    if (sorted != dst)
-      KDT_HIP(hipMemcpyAsync(dst, sorted, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToDevice,
-                             stream));
-    return KDT_OK;
-  }
+  const int cur = radix_sort_pairs(keys, vals, nq, 0, end_bit, tmp, stream);
+  KDT_HIP(hipGetLastError());
+  int32_t* sorted = vals[cur];
+  if (dst) return KDT_OK;  // the last pass wrote dst (vals[last])
   if (!ws) {
     // the other index array goes back to the pool; the sorted one is the caller's
     buf.keep(sorted);

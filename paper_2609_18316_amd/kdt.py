@@ -31,7 +31,8 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_stream_release", "kdt_tuning_set", "kdt_tuning_get",
            "kdt_build_f64", "kdt_knn_f64", "kdt_range_f64", "kdt_last_error")
 # The test and measurement hooks of include/kdt_debug.h.
-DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe")
+DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe",
+                 "kdt_debug_radix_sort")
 LIB_COUNTS_PATH = os.path.join(HERE, "libkdt_counts.so")
 NOALLOC_MAX_SORTED = 1 << 22   # queries kdt_knn_noalloc can order in its static scratch
 
@@ -120,6 +121,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_debug_fail_alloc.argtypes = [i64]
     lib.kdt_debug_visits.argtypes = [vp, i32]
     lib.kdt_debug_valu_probe.argtypes = [vp, i32, i32, vp]
+    lib.kdt_debug_radix_sort.argtypes = [vp, vp, i64, i32, i32, vp]
     lib.kdt_last_error.restype = C.c_char_p
     for name in EXPORTS + DEBUG_EXPORTS:
         if name not in ("kdt_last_error", "kdt_tree_perm") and hasattr(lib, name):
@@ -146,6 +148,17 @@ def tuning_get(d: int, n: int, k: int) -> tuple[int, int, int]:
 def stream_release(stream=None) -> None:
     """Frees the deposit scratch the library keeps for ``stream`` (stream-ordered)."""
     _check(load().kdt_stream_release(_stream(stream)))
+
+
+def radix_sort(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, end_bit: int = 32,
+               stream=None) -> None:
+    """Test hook: the library's stable radix sort of (uint32 key as int32
+    bits, int32 value) pairs in place, on key bits [begin_bit, end_bit)."""
+    n = keys.numel()
+    keys = _dev(keys, torch.int32, "keys", (n,))
+    vals = _dev(vals, torch.int32, "vals", (n,))
+    _check(load().kdt_debug_radix_sort(_ptr(keys), _ptr(vals), n, int(begin_bit), int(end_bit),
+                                       _stream(stream)))
 
 
 def fail_alloc(after: int) -> None:

@@ -1,0 +1,49 @@
+"""The library's radix sort (it orders the queries along the tree and the
+deposit's particles): bit-identical to numpy's stable sort on the same key
+bits, for sizes spanning several tiles and a ragged tail, full and partial
+bit ranges, heavy ties, and every digit value."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_18316_amd import kdt
+from tests.gpu_util import dev, say, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _reference(keys, vals, lo, hi):
+    sel = (keys.astype(np.uint64) >> lo) & ((1 << (hi - lo)) - 1)
+    order = np.argsort(sel, kind="stable")
+    return keys[order], vals[order]
+
+
+@pytest.mark.parametrize("n", (0, 1, 2, 7, 4095, 4096, 4097, 100003, 1 << 20))
+def test_sort_equals_stable_numpy_sort(n):
+    dev()
+    rng = np.random.Generator(np.random.PCG64(n + 3))
+    cases = {
+        "full": rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32),
+        "ties": rng.integers(0, 5, size=n, dtype=np.uint64).astype(np.uint32) * 0x01010101,
+        "sorted": np.arange(n, dtype=np.uint32),
+        "reversed": np.arange(n, dtype=np.uint32)[::-1].copy(),
+    }
+    for name, keys in cases.items():
+        for lo, hi in ((0, 32), (0, 30), (0, 13), (8, 24), (5, 6), (0, 0)):
+            vals = np.arange(n, dtype=np.int32)
+            say(f"radix sort n={n} {name} bits [{lo}, {hi})")
+            kt = torch.from_numpy(keys.view(np.int32).copy()).to(dev())
+            vt = torch.from_numpy(vals).to(dev())
+            kdt.radix_sort(kt, vt, lo, hi)
+            ek, ev = _reference(keys, vals, lo, hi)
+            np.testing.assert_array_equal(to_host(kt).view(np.uint32), ek)
+            np.testing.assert_array_equal(to_host(vt), ev)
+
+
+def test_sort_rejects_bad_bits():
+    dev()
+    k = torch.zeros(4, dtype=torch.int32, device=dev())
+    v = torch.zeros(4, dtype=torch.int32, device=dev())
+    for lo, hi in ((3, 2), (-1, 4), (0, 33)):
+        with pytest.raises(kdt.KdtError):
+            kdt.radix_sort(k, v, lo, hi)
