@@ -53,7 +53,16 @@ constexpr int kTileCells = kT * kT * kT;    // float64 LDS tile: 32 KiB
 constexpr int64_t kChunk = 4096;            // particles per deposit work item
 
 // Scratch slots the deposit keeps on its stream between calls.
-enum : int { kSlotParticles = 100, kSlotLists = 101, kSlotPartial = 102, kSlotFlag = 103 };
+enum : int {
+  kSlotParticles = 100,
+  kSlotLists = 101,
+  kSlotPartial = 102,
+  kSlotFlag = 103,
+  kSlotOrder = 104
+};
+// Calls without a particle order and at least this many particles order
+// them by home tile first.
+constexpr int64_t kSelfOrderMin = 1 << 16;
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -393,6 +402,28 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
   if (t < n) fbuf[t] = ok ? (float)((double)m / S) : 0.0f;
 }
 
+// The key of the self-ordering of an unordered call: the tile of the cell
+// that holds each particle (wrapped on a periodic mesh); a particle outside
+// the mesh of an open grid, or with a non-finite coordinate, gets the key
+// n_tiles.  Only the speed depends on this order, never the deposit.
+__global__ void k_p2m_tilekey(GridDev g, TileGrid tg, const float* __restrict__ x, int64_t n,
+                              uint32_t n_tiles, uint32_t* __restrict__ keys,
+                              int32_t* __restrict__ vals) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  int c[3];
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float s = floorf((x[3 * t + a] - g.lo[a]) / g.cell);
+    if (g.periodic && s == s) s -= floorf(s / (float)g.n[a]) * (float)g.n[a];
+    in &= s >= 0.0f && s < (float)g.n[a];
+    c[a] = in ? (int)s : 0;
+  }
+  keys[t] = in ? (uint32_t)(((c[0] / kT) * tg.nt[1] + c[1] / kT) * tg.nt[2] + c[2] / kT) : n_tiles;
+  vals[t] = (int32_t)t;
+}
+
 // Step 3: every image appends its entry (visiting position, and on a
 // periodic mesh the image in the low three bits) to the lists of the tiles
 // its support box overlaps.
@@ -619,6 +650,42 @@ void by_scheme(int sch, F&& f) {
 }
 }  // namespace
 
+// An unordered call's particles in home-tile order (k_p2m_tilekey, then the
+// library's radix sort), so that a wave's particles share their tiles: the
+// per-tile counters are then updated once per wave, not once per lane.  The
+// order lives in the stream's scratch (slot kSlotOrder).
+static kdt_status self_order(const GridDev& g, const int32_t gn[3], const float* d_x, int64_t n,
+                             hipStream_t stream, const char* who, const int32_t** order) {
+  TileGrid tg;
+  int64_t n_tiles = 1;
+  for (int a = 0; a < 3; ++a) {
+    tg.nt[a] = (gn[a] + kT - 1) / kT;
+    n_tiles *= tg.nt[a];
+  }
+  int bits = 1;
+  while (bits < 31 && (int64_t(1) << bits) <= n_tiles) ++bits;
+  const size_t a4 = align256(sizeof(uint32_t) * (size_t)n);
+  char* s = static_cast<char*>(
+      stream_scratch(stream, kSlotOrder, 4 * a4 + radix_sort_scratch_bytes(n)));
+  if (!s) {
+    kdt_set_error("%s: device allocation failed for the particle order", who);
+    return KDT_ENOMEM;
+  }
+  uint32_t* keys[2] = {reinterpret_cast<uint32_t*>(s), reinterpret_cast<uint32_t*>(s + a4)};
+  int32_t* vals[2] = {reinterpret_cast<int32_t*>(s + 2 * a4),
+                      reinterpret_cast<int32_t*>(s + 3 * a4)};
+  k_p2m_tilekey<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(g, tg, d_x, n,
+                                                                 (uint32_t)n_tiles, keys[0],
+                                                                 vals[0]);
+  const int cur = radix_sort_pairs(keys, vals, n, 0, bits, s + 4 * a4, stream);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("%s: ordering the particles failed", who);
+    return KDT_EDEVICE;
+  }
+  *order = vals[cur];
+  return KDT_OK;
+}
+
 // The binned deposit of either scheme (d_h NULL for the fixed clouds); `who`
 // names the entry point in messages.
 static kdt_status p2m_forward(int sch, const char* who, const float* d_x, const float* d_m,
@@ -643,6 +710,10 @@ static kdt_status p2m_forward(int sch, const char* who, const float* d_x, const 
   if (n_tiles > INT32_MAX / 2) {
     kdt_set_error("%s: mesh too large (%lld tiles of %d^3 cells)", who, (long long)n_tiles, kT);
     return KDT_EUNSUPPORTED;
+  }
+  if (!d_order && n >= kSelfOrderMin) {
+    const kdt_status st = self_order(g, grid->n, d_x, n, stream, who, &d_order);
+    if (st != KDT_OK) return st;
   }
   // scratch kept on the stream between calls: the packed particles, m / S
   // and the tile counters (+ the validity flag) in one slot; the lists and
@@ -814,6 +885,11 @@ extern "C" kdt_status kdt_p2m_backward(const float* d_x, const float* d_m, const
     return KDT_ENOMEM;
   }
   k_zero_f64<<<1, 32, 0, stream>>>(reinterpret_cast<double*>(bad), 1);
+  if (!d_order && n >= kSelfOrderMin) {
+    const kdt_status st =
+        self_order(to_dev(grid), grid->n, d_x, n, stream, "kdt_p2m_backward", &d_order);
+    if (st != KDT_OK) return st;
+  }
   k_p2m_bwd<<<(unsigned)((n + kPBlock - 1) / kPBlock), kPBlock, 0, stream>>>(
       to_dev(grid), d_x, d_m, d_h, n, d_order, d_ggrid, d_gm, d_gx, bad);
   if (hipGetLastError() != hipSuccess) {

@@ -184,3 +184,32 @@ def test_periodic_rejects_support_of_half_a_period():
             call(np.array([0.5 * 12 * cell], np.float32))
         assert e.value.status == kdt.KDT_EINVAL
         call(np.array([0.49 * 12 * cell], np.float32))
+
+
+def test_unordered_calls_above_the_self_ordering_size():
+    """Calls with no particle order and at least 2^16 particles sort the
+    particles by home tile first: SPH (open and periodic), TSC and the
+    adjoint in input order against the float64 oracle."""
+    dev()
+    n, cells = 100000, 32
+    x, m, t, h = _setup(n, cells, seed=901)
+    shape = (cells,) * 3
+    lo, cell = (0.0, 0.0, 0.0), 1.0 / cells
+    hh = to_host(h)
+    total = float(m.astype(np.float64).sum())
+    for periodic in (False, True):
+        say(f"unordered SPH deposit n={n} periodic={periodic}")
+        g = kdt.p2m(to_dev(x), to_dev(m), h, lo, cell, shape, periodic=periodic)
+        _close_rho(to_host(g), oracle.p2m(x, m, hh, lo, cell, shape, periodic=periodic), total)
+        say(f"unordered TSC deposit n={n} periodic={periodic}")
+        g = kdt.p2m_cloud(to_dev(x), to_dev(m), lo, cell, shape, "tsc", periodic=periodic)
+        _close_rho(to_host(g), oracle.p2m_cloud(x, m, lo, cell, shape, "tsc", periodic=periodic),
+                   total)
+    say(f"unordered adjoint n={n}")
+    rng = np.random.Generator(np.random.PCG64(17))
+    up = rng.standard_normal(shape).astype(np.float32)
+    gm, gx = kdt.p2m_backward(to_dev(x), to_dev(m), h, lo, cell, shape, to_dev(up))
+    om, ox = oracle.p2m_backward(x, m, hh, lo, cell, shape, up)
+    gm, gx = to_host(gm).astype(np.float64), to_host(gx).astype(np.float64)
+    assert (np.abs(gm - om) <= 1e-5 * np.maximum(np.abs(om), np.abs(om).mean())).all()
+    assert np.linalg.norm(gx - ox) <= 1e-4 * np.linalg.norm(ox)
