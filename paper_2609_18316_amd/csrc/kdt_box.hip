@@ -139,8 +139,10 @@ static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d
   const unsigned grid = (unsigned)((nq + kBoxBlock - 1) / kBoxBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kBoxBlock;
   if (tr->leaf <= 64 && traversal != 1) {
+    int cap = 0;
+    const TreeView vc = count_view(v, tr->leaf, &cap);
     const kdt_status st =
-        box_packet_launch<D>(v, tr->leaf, d_lo, d_hi, nq, order, d_count, split_budget, stream);
+        box_packet_launch<D>(vc, cap, d_lo, d_hi, nq, order, d_count, split_budget, stream);
     if (st != KDT_OK) return st;
   } else {
     k_box<D, false><<<grid, kBoxBlock, smem, stream>>>(v, d_lo, d_hi, nq, order, d_count,
@@ -198,7 +200,9 @@ static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d
       return KDT_ENOMEM;
     }
     const FillOut fo{unsorted, d_off, cur};
-    const kdt_status st = box_packet_launch<D>(v, tr->leaf, d_lo, d_hi, nq, order, d_count,
+    int cap = 0;
+    const TreeView vc = count_view(v, tr->leaf, &cap);
+    const kdt_status st = box_packet_launch<D>(vc, cap, d_lo, d_hi, nq, order, d_count,
                                                split_budget, stream, &fo);
     if (st != KDT_OK) return st;
   } else {

@@ -17,6 +17,23 @@ struct TreeView {
   unsigned long long* visits = nullptr;  // work counters of the instrumented build, else NULL
 };
 
+// The wave-shared counts (and their list fill) over a median tree treat the
+// nodes of one level as their leaves: the coarsest level whose nodes hold at
+// most kCountLeaf points, never below the tree's own leaves.  Node ranges
+// and tight boxes exist at every level, so the counts are the same; only
+// the cost differs -- ball counts at r = 0.01 on 2^24 clustered points took
+// 3.6 ms with 32-point leaves and 4.8 ms with 16-point ones.  Returns that
+// view and, in *cap, its largest node (the LDS slices' leaf capacity).
+constexpr int kCountLeaf = 32;
+inline TreeView count_view(TreeView v, int leaf, int* cap) {
+  int l = v.levels;
+  while (l > 0 && ((v.n + (int64_t(1) << (l - 1)) - 1) >> (l - 1)) <= kCountLeaf) --l;
+  const int64_t big = (v.n + (int64_t(1) << l) - 1) >> l;
+  *cap = big > leaf ? (int)big : leaf;
+  v.levels = l;
+  return v;
+}
+
 // Where the wave-shared counts write CSR lists in fill mode: the indices of
 // row r go to out[off[r] ..], a slot at a time reserved with an atomic on the
 // row's cursor cur[r] (zero before the first pass), so the subtrees a wave

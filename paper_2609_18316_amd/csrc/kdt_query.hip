@@ -403,7 +403,11 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
     k_range<D, false, StoredShape><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order,
                                                                      d_count, nullptr, nullptr);
   else if (t->leaf <= 64 && traversal != 1)
-    st = range_packet_launch<D>(v, t->leaf, d_q, nq, r2, order, d_count, split_budget, stream);
+  {
+    int cap = 0;
+    const TreeView vc = count_view(v, t->leaf, &cap);
+    st = range_packet_launch<D>(vc, cap, d_q, nq, r2, order, d_count, split_budget, stream);
+  }
   else
     k_range<D, false><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
   if (st != KDT_OK) {
@@ -463,7 +467,9 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
               st = KDT_ENOMEM;
             } else {
               const FillOut fo{unsorted, d_off, cur};
-              st = range_packet_launch<D>(v, t->leaf, d_q, nq, r2, order, d_count, split_budget,
+              int cap = 0;
+              const TreeView vc = count_view(v, t->leaf, &cap);
+              st = range_packet_launch<D>(vc, cap, d_q, nq, r2, order, d_count, split_budget,
                                           stream, &fo);
             }
           } else {

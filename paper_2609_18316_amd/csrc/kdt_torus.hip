@@ -267,7 +267,9 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   const unsigned grid = (unsigned)((nq + kTBlock - 1) / kTBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;
   if (tr->leaf <= 64) {
-    st = torus_range_packet_launch<D>(v, tr->leaf, d_q, nq, r2, T, order, d_count, 0u, stream);
+    int cap = 0;
+    const TreeView vc = count_view(v, tr->leaf, &cap);
+    st = torus_range_packet_launch<D>(vc, cap, d_q, nq, r2, T, order, d_count, 0u, stream);
     if (st != KDT_OK) return st;
   } else {
     k_torus_range<D, false><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, r2, order, T, d_count,
@@ -325,7 +327,9 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
       return KDT_ENOMEM;
     }
     const FillOut fo{unsorted, d_off, cur};
-    st = torus_range_packet_launch<D>(v, tr->leaf, d_q, nq, r2, T, order, d_count, 0u, stream,
+    int cap = 0;
+    const TreeView vc = count_view(v, tr->leaf, &cap);
+    st = torus_range_packet_launch<D>(vc, cap, d_q, nq, r2, T, order, d_count, 0u, stream,
                                       &fo);
     if (st != KDT_OK) return st;
   } else {
