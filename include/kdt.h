@@ -64,7 +64,13 @@ typedef struct {
                              tuning table (kdt_tuning_get). */
     int32_t check_finite; /* 1 (default when opts is NULL): kdt_build waits for its
                              first pass and rejects NaN/Inf coordinates with
-                             KDT_EINVAL.  0: no wait, no check. */
+                             KDT_EINVAL.  2: deferred -- no wait; the check's
+                             result stays with the tree and kdt_tree_check
+                             reports it (a tree of non-finite points is
+                             built but its query results are meaningless).
+                             Sliding-midpoint builds wait in any case and
+                             treat 2 as 1.  0: no check.  With 0 or 2 a
+                             non-finite coordinate is built as 0. */
     int32_t split_rule;   /* 0 (default): balanced median splits (see kdt_build).
                              1: the paper's sliding-midpoint rule (Sec. 2.1,
                              Algorithm 1): split the longest side of the
@@ -195,6 +201,11 @@ kdt_status kdt_stream_release(hipStream_t stream);
 
 /* Fills *info (host). */
 kdt_status kdt_tree_get_info(const kdt_tree *tree, kdt_tree_info *info);
+
+/* The deferred finiteness check of a tree built with check_finite = 2: waits
+   on `stream` and returns KDT_EINVAL if a coordinate was NaN or infinite,
+   KDT_OK otherwise (also for trees built with check_finite 0 or 1). */
+kdt_status kdt_tree_check(const kdt_tree *tree, hipStream_t stream);
 
 /*
  * Copies the tree to host memory for inspection (waits on `stream`).

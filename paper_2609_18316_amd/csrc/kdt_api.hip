@@ -200,7 +200,7 @@ extern "C" kdt_status kdt_build(const float* d_pts, int64_t n, int32_t d,
     kdt_set_error("kdt_build: dimension %d is not one of 2, 3, 4, 8, 16", d);
     return KDT_EUNSUPPORTED;
   }
-  int leaf = 0, check = 1, rule = 0, tune_k = 0;
+  int leaf = 0, check = 1, rule = 0, tune_k = 0;  // check: 0 none, 1 wait, 2 deferred
   if (opts) {
     leaf = opts->leaf_size;
     check = opts->check_finite;
@@ -214,6 +214,10 @@ extern "C" kdt_status kdt_build(const float* d_pts, int64_t n, int32_t d,
   if (leaf == 0) leaf = tuned(d, n, tune_k ? tune_k : 32).leaf;
   if (leaf < 2 || leaf > 256) {
     kdt_set_error("kdt_build: leaf_size %d outside [2, 256]", leaf);
+    return KDT_EINVAL;
+  }
+  if (check < 0 || check > 2) {
+    kdt_set_error("kdt_build: check_finite %d is not 0, 1 or 2", check);
     return KDT_EINVAL;
   }
   if (rule != 0 && rule != 1) {
@@ -271,8 +275,9 @@ extern "C" kdt_status kdt_build(const float* d_pts, int64_t n, int32_t d,
   const size_t b_split = sizeof(float) * (size_t)t->n_nodes;
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
   void* block = nullptr;
-  if (dev_alloc(&block, up(b_rec) + up(b_box) + up(b_perm) + up(b_axis) + up(b_split), stream) !=
-      hipSuccess) {
+  // + 256 B for the deferred finiteness flag
+  if (dev_alloc(&block, up(b_rec) + up(b_box) + up(b_perm) + up(b_axis) + up(b_split) + 256,
+                stream) != hipSuccess) {
     delete t;
     kdt_set_error("kdt_build: cannot allocate the tree (%lld points)", (long long)n);
     return KDT_ENOMEM;
@@ -293,7 +298,16 @@ extern "C" kdt_status kdt_build(const float* d_pts, int64_t n, int32_t d,
   }
   BuildOut o{t->rec, t->box, t->perm, t->axis, t->split};
   st = build_launch(plan, cp->dev, d_pts, w, o, 0, stream);
-  if (st == KDT_OK && check) {
+  if (st == KDT_OK && check == 2) {
+    // deferred: the flag moves into the tree, kdt_tree_check reads it later
+    t->flag = reinterpret_cast<int32_t*>(bp + up(b_rec) + up(b_box) + up(b_perm) + up(b_axis) +
+                                         up(b_split));
+    if (hipMemcpyAsync(t->flag, w.bad, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) !=
+        hipSuccess) {
+      kdt_set_error("kdt_build: keeping the input check failed");
+      st = KDT_EDEVICE;
+    }
+  } else if (st == KDT_OK && check) {
     int32_t bad = 0;
     if (hipMemcpyAsync(&bad, w.bad, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {
@@ -325,6 +339,27 @@ extern "C" kdt_status kdt_free(kdt_tree* tree) {
   if (e != hipSuccess) {
     kdt_set_error("kdt_free: waiting for the tree's stream failed");
     return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+
+extern "C" kdt_status kdt_tree_check(const kdt_tree* tree, hipStream_t stream) {
+  kdt_clear_error();
+  if (!tree) {
+    kdt_set_error("kdt_tree_check: NULL tree");
+    return KDT_EINVAL;
+  }
+  if (!tree->flag) return KDT_OK;  // checked while building, or not asked for
+  int32_t bad = 0;
+  if (hipMemcpyAsync(&bad, tree->flag, sizeof(bad), hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    kdt_set_error("kdt_tree_check: reading the input check failed");
+    return KDT_EDEVICE;
+  }
+  if (bad) {
+    kdt_set_error("kdt_tree_check: the points contain NaN or infinite coordinates");
+    return KDT_EINVAL;
   }
   return KDT_OK;
 }

@@ -261,8 +261,13 @@ __global__ __launch_bounds__(kBuildBlock) void k_ingest(const ChunkEntry* __rest
   for (int64_t i = ch.b + threadIdx.x; i < ch.e; i += kBuildBlock) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const float v = in[i * D + a];
-      nonfinite |= !isfinite(v);
+      // a non-finite coordinate is flagged and enters the build's copy as 0,
+      // so that the later passes only ever see finite keys (a deferred or
+      // skipped check builds a well-formed tree of meaningless points)
+      const float raw = in[i * D + a];
+      const bool fin = isfinite(raw);
+      nonfinite |= !fin;
+      const float v = fin ? raw : 0.0f;
       x[a * tot + i] = v;
       const uint32_t k = fkey(v);
       lo[a] = min(lo[a], k);

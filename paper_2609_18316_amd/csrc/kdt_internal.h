@@ -311,6 +311,9 @@ struct kdt_tree {
   double* rec64 = nullptr;
   double* box64 = nullptr;
   void* f64_block = nullptr;
+  // deferred finiteness check (check_finite 2): nonzero if a coordinate was
+  // NaN or infinite; inside the tree's allocation.  NULL otherwise.
+  int32_t* flag = nullptr;
 };
 
 namespace kdt {

@@ -29,7 +29,8 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_tree_perm", "kdt_query_order",
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
            "kdt_stream_release", "kdt_tuning_set", "kdt_tuning_get",
-           "kdt_build_f64", "kdt_knn_f64", "kdt_range_f64", "kdt_last_error")
+           "kdt_build_f64", "kdt_knn_f64", "kdt_range_f64", "kdt_tree_check",
+           "kdt_last_error")
 # The test and measurement hooks of include/kdt_debug.h.
 DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe",
                  "kdt_debug_radix_sort")
@@ -108,6 +109,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_tree_perm.restype = vp
     lib.kdt_stream_release.argtypes = [vp]
     lib.kdt_tuning_set.argtypes = [i32, i64, i32, i32, i32]
+    lib.kdt_tree_check.argtypes = [vp, vp]
     lib.kdt_build_f64.argtypes = [vp, i64, i32, C.POINTER(BuildOpts), vp, C.POINTER(vp)]
     lib.kdt_knn_f64.argtypes = [vp, vp, i64, i32, vp, vp, C.POINTER(QueryOpts), vp]
     lib.kdt_range_f64.argtypes = [vp, vp, i64, C.c_double, vp, vp, vp, i64, C.POINTER(C.c_int64),
@@ -191,6 +193,14 @@ def _check(rc: int):
         raise KdtError(rc, load().kdt_last_error().decode())
 
 
+def _check_mode(check_finite) -> int:
+    """check_finite: True (wait and reject), False (no check) or "deferred"
+    (no wait; Tree.check() reports it later)."""
+    if check_finite == "deferred":
+        return 2
+    return 1 if check_finite else 0
+
+
 def _stream(stream=None) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
@@ -235,7 +245,7 @@ class Tree:
         if points.dim() != 2:
             raise ValueError("points must be [n][d]")
         self._h = C.c_void_p()
-        opts = BuildOpts(leaf_size, 1 if check_finite else 0, int(split_rule), int(tune_k))
+        opts = BuildOpts(leaf_size, _check_mode(check_finite), int(split_rule), int(tune_k))
         _check(lib.kdt_build(_ptr(points), points.shape[0], points.shape[1], C.byref(opts),
                              _stream(stream), C.byref(self._h)))
         info = TreeInfo()
@@ -243,6 +253,11 @@ class Tree:
         self.info = Info(info.n, info.d, info.leaf_size, info.levels, info.stride, info.n_nodes)
         self.n, self.d = info.n, info.d
         self.device = points.device
+
+    def check(self, stream=None) -> None:
+        """Raises KdtError (KDT_EINVAL) if a deferred finiteness check
+        (check_finite="deferred") found a NaN or infinite coordinate."""
+        _check(load().kdt_tree_check(self._h, _stream(stream)))
 
     def close(self):
         h = getattr(self, "_h", None)

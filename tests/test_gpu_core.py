@@ -252,6 +252,20 @@ def test_error_paths():
     with pytest.raises(kdt.KdtError) as e:
         kdt.build(to_dev(bad))
     assert e.value.status == kdt.KDT_EINVAL
+    # the deferred check: the build returns, kdt_tree_check reports
+    for n in (100, 70000):  # one and several ingest chunks
+        xs = cases.points("uniform", n, 3, seed=n)
+        t = kdt.build(to_dev(xs), check_finite="deferred")
+        t.check()
+        t.close()
+        bs = xs.copy()
+        bs[n // 2, 2] = np.nan if n == 100 else -np.inf
+        t = kdt.build(to_dev(bs), check_finite="deferred")
+        with pytest.raises(kdt.KdtError) as e:
+            t.check()
+        assert e.value.status == kdt.KDT_EINVAL
+        t.close()
+    kdt.build(to_dev(x), check_finite=False).check()
     with pytest.raises(kdt.KdtError) as e:
         kdt.build(to_dev(cases.points("uniform", 100, 5, seed=1)))
     assert e.value.status == kdt.KDT_EUNSUPPORTED
