@@ -53,6 +53,18 @@ kdt_status kdt_debug_valu_probe(float *d_out, int32_t blocks, int32_t iters,
 kdt_status kdt_debug_radix_sort(uint32_t *d_keys, int32_t *d_vals, int64_t n, int32_t begin_bit,
                                 int32_t end_bit, hipStream_t stream);
 
+/*
+ * Exclusive running sum of the n int32 values d_in (device) into d_out
+ * (device), the library's scan of the CSR list offsets and of the sliding
+ * midpoint build's ranks.  out_bits = 64: d_out holds n + 1 int64 values,
+ * the last the total; out_bits = 32: d_out holds n int32 values (NULL
+ * allowed when n = 0; sums below 2^31 assumed).  Asynchronous on `stream`.
+ * For testing the scan against a reference.  Errors: KDT_EINVAL,
+ * KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_debug_exclusive_scan(const int32_t *d_in, void *d_out, int64_t n, int32_t out_bits,
+                                    hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

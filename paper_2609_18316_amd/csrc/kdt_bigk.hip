@@ -208,10 +208,6 @@ __global__ void k_grow_radius(float* __restrict__ r2, int32_t* __restrict__ coun
   list[atomicAdd(again, 1)] = (int32_t)i;
 }
 
-struct BigI64 {
-  __host__ __device__ int64_t operator()(int32_t v) const { return v; }
-};
-
 __global__ void k_chunk_offsets(const int64_t* __restrict__ off, int64_t s0, int64_t m,
                                 int32_t* __restrict__ rel) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -507,18 +503,11 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
   // 2. offsets of each query's keys; chunks of at most kBigKeysPerChunk keys
   {
     void* tmp = nullptr;
-    size_t tb = 0;
-    hipcub::TransformInputIterator<int64_t, BigI64, const int32_t*> c64(count, BigI64());
-    if (hipcub::DeviceScan::InclusiveSum(nullptr, tb, c64, off + 1, (int)nq, stream) !=
-        hipSuccess) {
-      kdt_set_error("kdt_knn: large-k offsets failed");
-      return KDT_EDEVICE;
-    }
-    if (!buf.get((char**)&tmp, tb)) {
+    if (!buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
       kdt_set_error("kdt_knn: device allocation failed for the large-k offsets");
       return KDT_ENOMEM;
     }
-    if (hipcub::DeviceScan::InclusiveSum(tmp, tb, c64, off + 1, (int)nq, stream) != hipSuccess) {
+    if (exclusive_scan<int64_t>(count, off, nq, off + nq, tmp, stream) != KDT_OK) {
       kdt_set_error("kdt_knn: large-k offsets failed");
       return KDT_EDEVICE;
     }

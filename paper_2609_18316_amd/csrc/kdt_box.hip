@@ -103,15 +103,6 @@ __global__ void k_box_centres(const float* __restrict__ lo, const float* __restr
   c[i] = isfinite(m) ? m : 0.0f;
 }
 
-__global__ void k_box_offsets_last(int64_t* off, const int32_t* count, int64_t nq) {
-  // off holds the exclusive scan of count over [0, nq); writes off[nq]
-  if (blockIdx.x == 0 && threadIdx.x == 0) off[nq] = off[nq - 1] + count[nq - 1];
-}
-
-struct BoxI64 {
-  __host__ __device__ int64_t operator()(int32_t v) const { return v; }
-};
-
 template <int D>
 static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d_hi, int64_t nq,
                            int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
@@ -154,22 +145,15 @@ static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d
   }
   if (!d_off) return KDT_OK;
   void* tmp = nullptr;
-  size_t tb = 0;
-  hipcub::TransformInputIterator<int64_t, BoxI64, const int32_t*> c64(d_count, BoxI64());
-  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
-    kdt_set_error("kdt_box: offset scan setup failed");
-    return KDT_EDEVICE;
-  }
-  if (!buf.get((char**)&tmp, tb)) {
+  if (!buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
     kdt_set_error("device allocation failed for the box list offsets");
     return KDT_ENOMEM;
   }
   int64_t total = 0;
-  if (hipcub::DeviceScan::ExclusiveSum(tmp, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
+  if (exclusive_scan<int64_t>(d_count, d_off, nq, d_off + nq, tmp, stream) != KDT_OK) {
     kdt_set_error("kdt_box: offset scan failed");
     return KDT_EDEVICE;
   }
-  k_box_offsets_last<<<1, 1, 0, stream>>>(d_off, d_count, nq);
   if (hipMemcpyAsync(&total, d_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, stream) !=
           hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {

@@ -313,14 +313,6 @@ __global__ void k_zero64(int32_t* p, int64_t* q) {
   if (q) *q = 0;
 }
 
-__global__ void k_last_offset64(int64_t* off, const int32_t* count, int64_t nq) {
-  off[nq] = off[nq - 1] + count[nq - 1];
-}
-
-struct I64Of {
-  __host__ __device__ int64_t operator()(int32_t x) const { return x; }
-};
-
 bool dim_ok64(int d) { return d == 2 || d == 3 || d == 4 || d == 8 || d == 16; }
 
 template <typename F>
@@ -575,23 +567,15 @@ extern "C" kdt_status kdt_range_f64(const kdt_tree* tree, const double* d_q, int
   }
   if (!d_offsets) return KDT_OK;
   // offsets: exclusive running sum of the counts, then the total
-  hipcub::TransformInputIterator<int64_t, I64Of, const int32_t*> c64(d_count, I64Of());
-  size_t tb = 0;
-  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, c64, d_offsets, (int)nq, stream) !=
-      hipSuccess) {
-    kdt_set_error("kdt_range_f64: offset scan setup failed");
-    return KDT_EDEVICE;
-  }
   void* tmp = nullptr;
-  if (!buf.get((char**)&tmp, tb)) {
+  if (!buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
     kdt_set_error("kdt_range_f64: device allocation failed for the list offsets");
     return KDT_ENOMEM;
   }
-  if (hipcub::DeviceScan::ExclusiveSum(tmp, tb, c64, d_offsets, (int)nq, stream) != hipSuccess) {
+  if (exclusive_scan<int64_t>(d_count, d_offsets, nq, d_offsets + nq, tmp, stream) != KDT_OK) {
     kdt_set_error("kdt_range_f64: offset scan failed");
     return KDT_EDEVICE;
   }
-  k_last_offset64<<<1, 1, 0, stream>>>(d_offsets, d_count, nq);
   int64_t total = 0;
   if (hipMemcpyAsync(&total, d_offsets + nq, sizeof(total), hipMemcpyDeviceToHost, stream) !=
           hipSuccess ||

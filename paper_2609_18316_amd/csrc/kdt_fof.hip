@@ -10,7 +10,6 @@
 // it goes.  A final pass points every element at its root, which is the
 // canonical group label.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include "kdt_query.h"
 
@@ -109,11 +108,6 @@ __global__ void k_fof_final(int32_t* __restrict__ parent, int64_t n) {
   }
 }
 
-struct IsRoot {
-  const int32_t* lab;
-  __host__ __device__ int64_t operator()(int64_t i) const { return lab[i] == (int32_t)i ? 1 : 0; }
-};
-
 static TreeView view_of(const kdt_tree* t) {
   TreeView v;
   v.rec = t->rec;
@@ -166,23 +160,15 @@ extern "C" kdt_status kdt_fof(const kdt_tree* tree, float l, int32_t* d_labels, 
     return KDT_EDEVICE;
   }
   if (n_groups) {
-    hipcub::CountingInputIterator<int64_t> ci(0);
-    hipcub::TransformInputIterator<int64_t, IsRoot, hipcub::CountingInputIterator<int64_t>> roots(
-        ci, IsRoot{d_labels});
     PoolBuffers buf(stream);
     int64_t* d_out = nullptr;
     char* tmp = nullptr;
-    size_t tb = 0;
-    if (hipcub::DeviceReduce::Sum(nullptr, tb, roots, d_out, (int)n, stream) != hipSuccess) {
-      kdt_set_error("kdt_fof: group count setup failed");
-      return KDT_EDEVICE;
-    }
-    if (!buf.get(&d_out, 1) || !buf.get(&tmp, tb)) {
+    if (!buf.get(&d_out, 1) || !buf.get(&tmp, scan_scratch_bytes(n))) {
       kdt_set_error("kdt_fof: device allocation failed");
       return KDT_ENOMEM;
     }
     int64_t h = 0;
-    if (hipcub::DeviceReduce::Sum(tmp, tb, roots, d_out, (int)n, stream) != hipSuccess ||
+    if (count_roots(d_labels, n, d_out, tmp, stream) != KDT_OK ||
         hipMemcpyAsync(&h, d_out, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {
       kdt_set_error("kdt_fof: counting groups failed");

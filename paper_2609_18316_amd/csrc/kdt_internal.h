@@ -174,6 +174,21 @@ size_t radix_sort_scratch_bytes(int64_t n);
 int radix_sort_pairs(uint32_t* keys[2], int32_t* vals[2], int64_t n, int begin_bit, int end_bit,
                      void* scratch, hipStream_t stream);
 
+// Exclusive running sum of n int32 values into out (kdt_sort.hip), 64-bit
+// sums; the total is written to *total_at (device) when total_at is not
+// NULL (for CSR offsets: total_at = out + n).  scratch: scan_scratch_bytes(n)
+// device bytes.
+size_t scan_scratch_bytes(int64_t n);
+template <typename Out>
+kdt_status exclusive_scan(const int32_t* in, Out* out, int64_t n, int64_t* total_at,
+                          void* scratch, hipStream_t stream);
+
+// *out (device) <- the number of i in [0, n) with labels[i] == i: the groups
+// of a friends-of-friends labelling (kdt_sort.hip).  scratch:
+// scan_scratch_bytes(n) device bytes.
+kdt_status count_roots(const int32_t* labels, int64_t n, int64_t* out, void* scratch,
+                       hipStream_t stream);
+
 // The tuning table (kdt_tuning.hip): N_leaf and queries per traversal (1 or
 // 64) measured fastest for the nearest shape of dimension d.
 struct Tuning {

@@ -31,7 +31,6 @@
 //   compact  the next level's segments, whose count the host reads back (the
 //            one wait per level).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 
@@ -546,9 +545,8 @@ kdt_status build_midpoint_d(const float* d_pts, int64_t n, int leaf, bool check,
   int32_t *sid = nullptr, *mark = nullptr, *rank = nullptr, *cid = nullptr, *flags = nullptr;
   uint32_t* rootkeys = nullptr;
   void* scan_tmp = nullptr;
-  size_t scan_bytes = 0;
   // the marks and their scan have n + 1 entries: rank[n] is the total
-  KDT_M(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, mark, rank, (int)(n + 1), stream));
+  const size_t scan_bytes = scan_scratch_bytes(n + 1);
   if (!buf.get(&X[0], (size_t)D * n) || !buf.get(&X[1], (size_t)D * n) ||
       !buf.get(&Pm[0], (size_t)n) || !buf.get(&Pm[1], (size_t)n) || !buf.get(&sid, (size_t)n) ||
       !buf.get(&mark, (size_t)n + 1) || !buf.get(&rank, (size_t)n + 1) ||
@@ -585,7 +583,6 @@ kdt_status build_midpoint_d(const float* d_pts, int64_t n, int leaf, bool check,
   uint32_t* ckeys = nullptr;
   int32_t *act = nullptr, *pos = nullptr;
   void* cscan_tmp = nullptr;
-  size_t cscan_bytes = 0;
   // capacity for c segments (and 2 c children); the buffers' contents are lost
   auto ensure = [&](int64_t m) -> bool {
     if (m <= mcap) return true;
@@ -594,12 +591,8 @@ kdt_status build_midpoint_d(const float* d_pts, int64_t n, int leaf, bool check,
     if (!lvl.get(&seg, (size_t)c) || !lvl.get(&nseg, (size_t)c) || !lvl.get(&res, (size_t)c) ||
         !lvl.get(&seg_split, (size_t)c) || !lvl.get(&ckeys, (size_t)c * 4 * D) ||
         !lvl.get(&act, (size_t)2 * c) ||
-        !lvl.get(&pos, (size_t)2 * c))
-      return false;
-    cscan_bytes = 0;
-    if (hipcub::DeviceScan::ExclusiveSum(nullptr, cscan_bytes, act, pos, (int)(2 * c), stream) !=
-            hipSuccess ||
-        !lvl.get((char**)&cscan_tmp, cscan_bytes))
+        !lvl.get(&pos, (size_t)2 * c) ||
+        !lvl.get((char**)&cscan_tmp, scan_scratch_bytes(2 * c)))
       return false;
     mcap = c;
     return true;
@@ -656,7 +649,10 @@ kdt_status build_midpoint_d(const float* d_pts, int64_t n, int leaf, bool check,
     const unsigned gb = (unsigned)((n + kBoxBlock - 1) / kBoxBlock);
     k_mid_plan<D><<<gm, kMBlock, 0, stream>>>((int)m, seg, seg_split, na.box);
     k_mid_mark<<<gn1, kMBlock, 0, stream>>>(n, X[cur], sid, seg, seg_split, mark);
-    KDT_M(hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, mark, rank, (int)(n + 1), stream));
+    if (exclusive_scan<int32_t>(mark, rank, n + 1, nullptr, scan_tmp, stream) != KDT_OK) {
+      kdt_set_error("kdt_build (sliding midpoint): the scan of the marks failed");
+      return KDT_EDEVICE;
+    }
     k_mid_resolve<<<gm, kMBlock, 0, stream>>>((int)m, seg, seg_split, rank, res, node_base, level,
                                               na.node, na.axis, na.split);
     k_mid_slide<<<gs, kMBlock, 0, stream>>>((int)m, X[cur], Pm[cur], n, seg, seg_split, res,
@@ -668,8 +664,10 @@ kdt_status build_midpoint_d(const float* d_pts, int64_t n, int leaf, bool check,
     k_mid_boxes<D><<<gb, kBoxBlock, 0, stream>>>(n, X[cur], cid, ckeys);
     k_mid_children<D><<<gc, kMBlock, 0, stream>>>((int)(2 * m), ckeys, node_base, leaf, na.node,
                                                   na.box, act);
-    KDT_M(hipcub::DeviceScan::ExclusiveSum(cscan_tmp, cscan_bytes, act, pos, (int)(2 * m),
-                                           stream));
+    if (exclusive_scan<int32_t>(act, pos, 2 * m, nullptr, cscan_tmp, stream) != KDT_OK) {
+      kdt_set_error("kdt_build (sliding midpoint): the scan of the children failed");
+      return KDT_EDEVICE;
+    }
     k_mid_compact<<<gc, kMBlock, 0, stream>>>((int)(2 * m), act, pos, node_base, na.node, nseg,
                                               d_count);
     k_mid_sid<<<gn, kMBlock, 0, stream>>>(n, cid, act, pos, sid);

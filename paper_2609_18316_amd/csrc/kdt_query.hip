@@ -210,15 +210,6 @@ __global__ void k_query_hilbert(TreeView t, const float* __restrict__ q, int64_t
 }
 
 
-struct ToI64 {
-  __host__ __device__ int64_t operator()(int32_t v) const { return v; }
-};
-
-__global__ void k_range_offsets_fix(int64_t* off, const int32_t* count, int64_t nq) {
-  // off holds the exclusive scan of count over [0, nq); write off[nq]
-  if (blockIdx.x == 0 && threadIdx.x == 0) off[nq] = nq > 0 ? off[nq - 1] + count[nq - 1] : 0;
-}
-
 #define KDT_HIP(call)                                                        \
   do {                                                                       \
     hipError_t e_ = (call);                                                  \
@@ -424,21 +415,14 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
   if (d_off) {
     PoolBuffers buf(stream);
     void* tmp = nullptr;
-    size_t tb = 0;
-    hipcub::TransformInputIterator<int64_t, ToI64, const int32_t*> cnt64(d_count, ToI64());
     int64_t total = 0;
-    if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt64, d_off, (int)nq, stream) != hipSuccess) {
-      kdt_set_error("kdt_range: offset scan setup failed");
-      st = KDT_EDEVICE;
-    } else if (!buf.get((char**)&tmp, tb)) {
+    if (!buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
       kdt_set_error("device allocation failed for the list offsets");
       st = KDT_ENOMEM;
-    } else if (hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt64, d_off, (int)nq, stream) !=
-               hipSuccess) {
+    } else if (exclusive_scan<int64_t>(d_count, d_off, nq, d_off + nq, tmp, stream) != KDT_OK) {
       kdt_set_error("kdt_range: offset scan failed");
       st = KDT_EDEVICE;
     } else {
-      k_range_offsets_fix<<<1, 1, 0, stream>>>(d_off, d_count, nq);
       if (hipMemcpyAsync(&total, d_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, stream) !=
               hipSuccess ||
           hipStreamSynchronize(stream) != hipSuccess) {

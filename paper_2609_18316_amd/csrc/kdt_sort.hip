@@ -181,7 +181,152 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
   }
 }
 
+// --- exclusive scan of int32 values (CSR offsets, the midpoint build's ranks)
+//
+// Three kernels: the sum of each tile of kTile values; one workgroup turning
+// the tile sums into tile offsets (and the total); per tile, the running sum
+// of its values from its offset.  Loads and stores go through LDS so that
+// both are coalesced; sums are 64-bit.
+
+// Per tile of kTile values: their sum (ROOTS: the number of i with in[i] == i).
+template <bool ROOTS>
+__global__ __launch_bounds__(kThreads) void k_scan_tiles(const int32_t* __restrict__ in, int64_t n,
+                                                         int64_t* __restrict__ tsum) {
+  __shared__ int64_t part[kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  int64_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + r * kThreads + threadIdx.x;
+    if (i < n) s += ROOTS ? (int64_t)(in[i] == (int32_t)i) : (int64_t)in[i];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < kWaves; ++w) t += part[w];
+    tsum[blockIdx.x] = t;
+  }
+}
+
+// Exclusive running sum of a block of values (64-bit), the block total in *total.
+__device__ __forceinline__ int64_t block_exclusive64(int64_t v, int64_t* wsum, int64_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int64_t carry = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    if (w < wave) carry += wsum[w];
+    all += wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return carry + incl - v;
+}
+
+// One workgroup: tile sums -> tile offsets, in steps of kThreads; tsum[tiles]
+// gets the total.
+__global__ __launch_bounds__(kThreads) void k_scan_top(int64_t* __restrict__ tsum, int64_t tiles) {
+  __shared__ int64_t wsum[kWaves];
+  int64_t run = 0;
+  for (int64_t b = 0; b < tiles; b += kThreads) {
+    const int64_t i = b + threadIdx.x;
+    const int64_t v = i < tiles ? tsum[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive64(v, wsum, &tot);
+    if (i < tiles) tsum[i] = run + ex;
+    run += tot;
+  }
+  if (threadIdx.x == 0) tsum[tiles] = run;
+}
+
+// Per tile: out[i] = offset of the tile + the sum of the tile's values before i.
+template <typename Out>
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const int32_t* __restrict__ in, int64_t n,
+                                                         const int64_t* __restrict__ tsum,
+                                                         Out* __restrict__ out) {
+  __shared__ int64_t buf[kTile];
+  __shared__ int64_t wsum[kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + r * kThreads + tid;
+    buf[r * kThreads + tid] = i < n ? (int64_t)in[i] : 0;
+  }
+  __syncthreads();
+  // thread t owns values [t * kItems, (t + 1) * kItems) of the tile
+  int64_t mine = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) mine += buf[tid * kItems + j];
+  int64_t tot;
+  int64_t run = tsum[blockIdx.x] + block_exclusive64(mine, wsum, &tot);
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    const int64_t v = buf[tid * kItems + j];
+    buf[tid * kItems + j] = run;
+    run += v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + r * kThreads + tid;
+    if (i < n) out[i] = (Out)buf[r * kThreads + tid];
+  }
+}
+
+__global__ void k_scan_total(const int64_t* __restrict__ tsum, int64_t tiles, int64_t* out_n) {
+  *out_n = tsum[tiles];
+}
+
 }  // namespace
+
+size_t scan_scratch_bytes(int64_t n) {
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  return sizeof(int64_t) * (size_t)(tiles + 1);
+}
+
+template <typename Out>
+kdt_status exclusive_scan(const int32_t* in, Out* out, int64_t n, int64_t* total_at,
+                          void* scratch, hipStream_t stream) {
+  if (n <= 0) {
+    if (total_at) {
+      int64_t* z = static_cast<int64_t*>(scratch);
+      k_scan_top<<<1, kThreads, 0, stream>>>(z, 0);
+      k_scan_total<<<1, 1, 0, stream>>>(z, 0, total_at);
+    }
+    return hipGetLastError() == hipSuccess ? KDT_OK : KDT_EDEVICE;
+  }
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  int64_t* tsum = static_cast<int64_t*>(scratch);
+  k_scan_tiles<false><<<(unsigned)tiles, kThreads, 0, stream>>>(in, n, tsum);
+  k_scan_top<<<1, kThreads, 0, stream>>>(tsum, tiles);
+  k_scan_apply<Out><<<(unsigned)tiles, kThreads, 0, stream>>>(in, n, tsum, out);
+  if (total_at) k_scan_total<<<1, 1, 0, stream>>>(tsum, tiles, total_at);
+  return hipGetLastError() == hipSuccess ? KDT_OK : KDT_EDEVICE;
+}
+
+kdt_status count_roots(const int32_t* labels, int64_t n, int64_t* out, void* scratch,
+                       hipStream_t stream) {
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  int64_t* tsum = static_cast<int64_t*>(scratch);
+  if (tiles > 0) k_scan_tiles<true><<<(unsigned)tiles, kThreads, 0, stream>>>(labels, n, tsum);
+  k_scan_top<<<1, kThreads, 0, stream>>>(tsum, tiles);
+  k_scan_total<<<1, 1, 0, stream>>>(tsum, tiles, out);
+  return hipGetLastError() == hipSuccess ? KDT_OK : KDT_EDEVICE;
+}
+
+template kdt_status exclusive_scan<int32_t>(const int32_t*, int32_t*, int64_t, int64_t*, void*,
+                                            hipStream_t);
+template kdt_status exclusive_scan<int64_t>(const int32_t*, int64_t*, int64_t, int64_t*, void*,
+                                            hipStream_t);
 
 size_t radix_sort_scratch_bytes(int64_t n) {
   const int64_t tiles = (n + kTile - 1) / kTile;
@@ -247,4 +392,32 @@ extern "C" kdt_status kdt_debug_radix_sort(uint32_t* d_keys, int32_t* d_vals, in
     return KDT_EDEVICE;
   }
   return KDT_OK;
+}
+
+extern "C" kdt_status kdt_debug_exclusive_scan(const int32_t* d_in, void* d_out, int64_t n,
+                                               int32_t out_bits, hipStream_t stream) {
+  kdt_clear_error();
+  if (n < 0 || n > INT32_MAX || (n > 0 && !d_in) || ((n > 0 || out_bits == 64) && !d_out) ||
+      (out_bits != 32 && out_bits != 64)) {
+    kdt_set_error("kdt_debug_exclusive_scan: NULL arrays, n outside [0, 2^31-1] or out_bits "
+                  "not 32 or 64");
+    return KDT_EINVAL;
+  }
+  kdt::PoolBuffers buf(stream);
+  void* scratch = nullptr;
+  if (!buf.get((char**)&scratch, kdt::scan_scratch_bytes(n))) {
+    kdt_set_error("kdt_debug_exclusive_scan: device allocation failed");
+    return KDT_ENOMEM;
+  }
+  kdt_status st;
+  if (out_bits == 64) {
+    int64_t* out = static_cast<int64_t*>(d_out);
+    st = kdt::exclusive_scan<int64_t>(d_in, out, n, out + n, scratch, stream);
+  } else {
+    st = n > 0 ? kdt::exclusive_scan<int32_t>(d_in, static_cast<int32_t*>(d_out), n, nullptr,
+                                              scratch, stream)
+               : KDT_OK;
+  }
+  if (st != KDT_OK) kdt_set_error("kdt_debug_exclusive_scan: launch failed");
+  return st;
 }

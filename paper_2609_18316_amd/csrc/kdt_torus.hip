@@ -134,14 +134,6 @@ __global__ void k_torus_check(const float* __restrict__ q, int64_t nq, Torus<D> 
 
 __global__ void k_torus_flag_clear(int32_t* flag) { flag[0] = 0; }
 
-__global__ void k_torus_offsets_last(int64_t* off, const int32_t* count, int64_t nq) {
-  off[nq] = off[nq - 1] + count[nq - 1];
-}
-
-struct TorusI64 {
-  __host__ __device__ int64_t operator()(int32_t v) const { return v; }
-};
-
 // Periods finite and positive, every tree point (its root box) and every
 // query inside [0, L).  Waits on the stream.
 template <int D>
@@ -281,21 +273,14 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   }
   if (!d_off) return KDT_OK;
   void* tmp = nullptr;
-  size_t tb = 0;
-  hipcub::TransformInputIterator<int64_t, TorusI64, const int32_t*> c64(d_count, TorusI64());
-  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
-    kdt_set_error("kdt_range: torus offset scan failed");
-    return KDT_EDEVICE;
-  }
-  if (!buf.get((char**)&tmp, tb)) {
+  if (!buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
     kdt_set_error("kdt_range: device allocation failed for the list offsets");
     return KDT_ENOMEM;
   }
-  if (hipcub::DeviceScan::ExclusiveSum(tmp, tb, c64, d_off, (int)nq, stream) != hipSuccess) {
+  if (exclusive_scan<int64_t>(d_count, d_off, nq, d_off + nq, tmp, stream) != KDT_OK) {
     kdt_set_error("kdt_range: torus offset scan failed");
     return KDT_EDEVICE;
   }
-  k_torus_offsets_last<<<1, 1, 0, stream>>>(d_off, d_count, nq);
   int64_t total = 0;
   if (hipMemcpyAsync(&total, d_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, stream) !=
           hipSuccess ||
@@ -463,11 +448,6 @@ __global__ void k_torus_fof_final(int32_t* __restrict__ parent, int64_t n) {
   if (i < n) uf_st(parent + i, uf_root(parent, (int32_t)i));
 }
 
-struct TorusIsRoot {
-  const int32_t* lab;
-  __host__ __device__ int64_t operator()(int64_t i) const { return lab[i] == (int32_t)i ? 1 : 0; }
-};
-
 template <int D>
 static kdt_status torus_fof_impl(const kdt_tree* tr, float l, const float* period,
                                  int32_t* d_labels, int64_t* n_groups, hipStream_t stream) {
@@ -506,22 +486,14 @@ static kdt_status torus_fof_impl(const kdt_tree* tr, float l, const float* perio
     return KDT_EDEVICE;
   }
   if (!n_groups) return KDT_OK;
-  hipcub::CountingInputIterator<int64_t> ci(0);
-  hipcub::TransformInputIterator<int64_t, TorusIsRoot, hipcub::CountingInputIterator<int64_t>>
-      roots(ci, TorusIsRoot{d_labels});
   int64_t* d_out = nullptr;
   char* tmp = nullptr;
-  size_t tb = 0;
   int64_t h = 0;
-  if (hipcub::DeviceReduce::Sum(nullptr, tb, roots, d_out, (int)n, stream) != hipSuccess) {
-    kdt_set_error("kdt_fof_torus: counting groups failed");
-    return KDT_EDEVICE;
-  }
-  if (!buf.get(&d_out, 1) || !buf.get(&tmp, tb)) {
+  if (!buf.get(&d_out, 1) || !buf.get(&tmp, scan_scratch_bytes(n))) {
     kdt_set_error("kdt_fof_torus: device allocation failed");
     return KDT_ENOMEM;
   }
-  if (hipcub::DeviceReduce::Sum(tmp, tb, roots, d_out, (int)n, stream) != hipSuccess ||
+  if (count_roots(d_labels, n, d_out, tmp, stream) != KDT_OK ||
       hipMemcpyAsync(&h, d_out, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
     kdt_set_error("kdt_fof_torus: counting groups failed");

@@ -33,7 +33,7 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_last_error")
 # The test and measurement hooks of include/kdt_debug.h.
 DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe",
-                 "kdt_debug_radix_sort")
+                 "kdt_debug_radix_sort", "kdt_debug_exclusive_scan")
 LIB_COUNTS_PATH = os.path.join(HERE, "libkdt_counts.so")
 NOALLOC_MAX_SORTED = 1 << 22   # queries kdt_knn_noalloc can order in its static scratch
 
@@ -124,6 +124,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_debug_visits.argtypes = [vp, i32]
     lib.kdt_debug_valu_probe.argtypes = [vp, i32, i32, vp]
     lib.kdt_debug_radix_sort.argtypes = [vp, vp, i64, i32, i32, vp]
+    lib.kdt_debug_exclusive_scan.argtypes = [vp, vp, i64, i32, vp]
     lib.kdt_last_error.restype = C.c_char_p
     for name in EXPORTS + DEBUG_EXPORTS:
         if name not in ("kdt_last_error", "kdt_tree_perm") and hasattr(lib, name):
@@ -161,6 +162,21 @@ def radix_sort(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, end_b
     vals = _dev(vals, torch.int32, "vals", (n,))
     _check(load().kdt_debug_radix_sort(_ptr(keys), _ptr(vals), n, int(begin_bit), int(end_bit),
                                        _stream(stream)))
+
+
+def exclusive_scan(values: torch.Tensor, out_bits: int = 64, stream=None) -> torch.Tensor:
+    """Test hook: the library's exclusive running sum of int32 values;
+    out_bits 64 gives n + 1 int64 sums (the last the total), 32 gives n
+    int32 sums."""
+    n = values.numel()
+    values = _dev(values, torch.int32, "values", (n,))
+    if out_bits == 64:
+        out = torch.empty(n + 1, dtype=torch.int64, device=values.device)
+    else:
+        out = torch.empty(n, dtype=torch.int32, device=values.device)
+    _check(load().kdt_debug_exclusive_scan(_ptr(values), out.data_ptr(), n, int(out_bits),
+                                           _stream(stream)))
+    return out
 
 
 def fail_alloc(after: int) -> None:

@@ -1,7 +1,9 @@
 """The library's radix sort (it orders the queries along the tree and the
 deposit's particles): bit-identical to numpy's stable sort on the same key
 bits, for sizes spanning several tiles and a ragged tail, full and partial
-bit ranges, heavy ties, and every digit value."""
+bit ranges, heavy ties, and every digit value.  Its exclusive scan (the CSR
+offsets of the ball lists, the sliding midpoint build's ranks): equal to
+numpy's cumulative sum, with totals past 2^31 in the 64-bit form."""
 import numpy as np
 import pytest
 import torch
@@ -47,3 +49,28 @@ def test_sort_rejects_bad_bits():
     for lo, hi in ((3, 2), (-1, 4), (0, 33)):
         with pytest.raises(kdt.KdtError):
             kdt.radix_sort(k, v, lo, hi)
+
+
+@pytest.mark.parametrize("n", (0, 1, 2, 255, 256, 4095, 4096, 4097, 1 << 20, 4096 * 300 + 17))
+def test_scan_equals_cumulative_sum(n):
+    dev()
+    rng = np.random.Generator(np.random.PCG64(n + 11))
+    cases = {
+        "small": rng.integers(0, 8, size=n).astype(np.int32),
+        "zeros": np.zeros(n, np.int32),
+        "wide": rng.integers(0, 1 << 30, size=n).astype(np.int32),  # totals past 2^31
+    }
+    for name, v in cases.items():
+        say(f"exclusive scan n={n} {name}")
+        want = np.concatenate([[0], np.cumsum(v.astype(np.int64))])
+        got = to_host(kdt.exclusive_scan(torch.from_numpy(v).to(dev()), 64))
+        np.testing.assert_array_equal(got, want)
+        if want[-1] < 2 ** 31:
+            got = to_host(kdt.exclusive_scan(torch.from_numpy(v).to(dev()), 32))
+            np.testing.assert_array_equal(got, want[:-1].astype(np.int32))
+
+
+def test_scan_rejects_bad_width():
+    dev()
+    with pytest.raises(kdt.KdtError):
+        kdt.exclusive_scan(torch.zeros(4, dtype=torch.int32, device=dev()), 16)
