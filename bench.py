@@ -392,11 +392,16 @@ def main():
         mark("range")
         lab = tree.fof(l_fof)
         mark("fof")
-        h = tree.knn(None, K, kth_only=2)
+        # smoothing lengths, masses and gradients in tree order: every pass of
+        # the deposit streams contiguous arrays; the gradients go back to
+        # input order at the end
+        h = tree.knn(None, K, kth_only=2, tree_rows=True)
         mark("hsml")
-        rho = kdt.p2m(xt, mt, h, lo, cell, shape, order_ptr=tree.perm_ptr)
+        m_t = tree.gather(mt)
+        rho = kdt.p2m_tree(tree, m_t, h, lo, cell, shape)
         mark("p2m_fwd")
-        gm, gx = kdt.p2m_backward(xt, mt, h, lo, cell, shape, gg, order_ptr=tree.perm_ptr)
+        gm_t, gx_t = kdt.p2m_tree_backward(tree, m_t, h, lo, cell, shape, gg)
+        gm, gx = tree.scatter(gm_t), tree.scatter(gx_t)
         mark("p2m_bwd")
         if batch:
             plan, bxt, blt, bout, _ = batch
@@ -614,21 +619,27 @@ def main():
               f"counts {r_ms:.2f} ms", file=sys.stderr, flush=True)
     if not args.no_cloud:
         # The fixed-cloud deposits the paper compares the adaptive one with
-        # (Table 3): the same 2^24 particles and 256^3 mesh, visited in the
-        # same tree order as the adaptive deposit of the step, best of three
-        # after one warm-up; the input-order figures (no order given) follow.
+        # (Table 3): the same 2^24 particles and 256^3 mesh in tree order as
+        # the adaptive deposit of the step (masses gathered into tree order
+        # inside the timed call, as there), best of three after one warm-up;
+        # then the caller's arrays visited through the tree order
+        # ("perm_order") and in input order (no order given).
         out["cloud"] = {"p2m_sph_fwd_ms": avg["p2m_fwd"]}
         ctree = kdt.build(xt, leaf_size=LEAF, tune_k=K)
         h_c = ctree.knn(None, K, kth_only=2)
-        for scheme, order_ptr, tag in (("ngp", ctree.perm_ptr, ""), ("cic", ctree.perm_ptr, ""),
-                                       ("tsc", ctree.perm_ptr, ""), ("tsc", None, "_input_order"),
-                                       ("sph", None, "_input_order")):
+        for scheme, how in (("ngp", "tree"), ("cic", "tree"), ("tsc", "tree"),
+                            ("tsc", "perm_order"), ("tsc", "input_order"),
+                            ("sph", "perm_order"), ("sph", "input_order")):
             best = None
+            order_ptr = ctree.perm_ptr if how == "perm_order" else None
             for _ in range(4):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
-                if scheme == "sph":
+                if how == "tree":
+                    r = kdt.p2m_tree(ctree, ctree.gather(mt), None, lo, cell, shape,
+                                     scheme=scheme)
+                elif scheme == "sph":
                     r = kdt.p2m(xt, mt, h_c, lo, cell, shape, order_ptr=order_ptr)
                 else:
                     r = kdt.p2m_cloud(xt, mt, lo, cell, shape, scheme, order_ptr=order_ptr)
@@ -638,7 +649,7 @@ def main():
                 if _ > 0:  # the first call warms up
                     best = ms if best is None else min(best, ms)
                 del r
-            out["cloud"][scheme + tag + "_ms"] = best
+            out["cloud"][scheme + ("" if how == "tree" else "_" + how) + "_ms"] = best
         ctree.close()
         out["cloud"]["sph_over_tsc"] = avg["p2m_fwd"] / out["cloud"]["tsc_ms"]
     if not args.no_f64:

@@ -129,6 +129,16 @@ typedef struct {
                              with the torus distance; traversal and
                              split_budget are ignored.  kdt_box returns
                              KDT_EUNSUPPORTED. */
+    int32_t tree_rows;    /* Self queries (d_q NULL) of kdt_knn, kdt_range and
+                             their _f64 and _noalloc forms.  0: row i of every
+                             output belongs to input point i.  1: row t
+                             belongs to the tree's t-th point in tree order
+                             (input point kdt_tree_perm[t]), so the rows are
+                             written in the order the traversal visits them,
+                             as contiguous runs, and they line up with the
+                             tree-ordered deposit (kdt_p2m_tree).  Results
+                             are otherwise identical.  1 with external
+                             queries, or another value: KDT_EINVAL. */
 } kdt_query_opts;
 
 /* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side
@@ -206,6 +216,21 @@ kdt_status kdt_tree_get_info(const kdt_tree *tree, kdt_tree_info *info);
    on `stream` and returns KDT_EINVAL if a coordinate was NaN or infinite,
    KDT_OK otherwise (also for trees built with check_finite 0 or 1). */
 kdt_status kdt_tree_check(const kdt_tree *tree, hipStream_t stream);
+
+/*
+ * kdt_tree_gather, kdt_tree_scatter -- per-point arrays between input order
+ * and the tree's order: rows of `width` 4-byte elements (float32 or int32;
+ * 1 <= width <= 4096), d_in and d_out [n][width] device, not the same
+ * array.  Gather: d_out[t] = d_in[kdt_tree_perm[t]] (input -> tree order);
+ * scatter: d_out[kdt_tree_perm[t]] = d_in[t] (tree -> input order).
+ * Asynchronous on `stream`; n = 0 does nothing.
+ * Errors: KDT_EINVAL (NULL tree or arrays, width, d_in == d_out),
+ * KDT_EDEVICE.
+ */
+kdt_status kdt_tree_gather(const kdt_tree *tree, const void *d_in, int32_t width, void *d_out,
+                           hipStream_t stream);
+kdt_status kdt_tree_scatter(const kdt_tree *tree, const void *d_in, int32_t width, void *d_out,
+                            hipStream_t stream);
 
 /*
  * Copies the tree to host memory for inspection (waits on `stream`).
@@ -411,6 +436,33 @@ kdt_status kdt_p2m_backward(const float *d_x, const float *d_m, const float *d_h
                             const kdt_grid *grid, const int32_t *d_order,
                             const float *d_ggrid, float *d_gm, float *d_gx,
                             hipStream_t stream);
+
+/*
+ * kdt_p2m_tree, kdt_p2m_tree_backward -- the deposit and its adjoint over
+ * the points of a tree (Sec. 4.2 with the particles held in the tree's
+ * order, the order every pass of the deposit visits them in): positions
+ * come from the tree's own records, and d_m [n], d_h [n] and the outputs
+ * d_gm [n], d_gx [n][3] are in tree order (row t belongs to input point
+ * kdt_tree_perm[t]; kdt_tree_gather and kdt_tree_scatter convert, and
+ * kdt_knn with tree_rows = 1 writes smoothing lengths in this order).  Every
+ * pass then streams contiguous arrays instead of gathering through an
+ * order.  scheme 0: the adaptive SPH kernel (d_h required); 1, 2, 3: the
+ * fixed clouds NGP, CIC, TSC of kdt_p2m_cloud (d_h ignored).  The backward
+ * is the adjoint of scheme 0.  Results are those of kdt_p2m /
+ * kdt_p2m_cloud / kdt_p2m_backward with the tree order as d_order and the
+ * per-particle arrays permuted accordingly.  A tree built with the deferred
+ * finiteness check that found a NaN or infinite coordinate gives
+ * KDT_EINVAL (read on the device with the validity flag); a tree built
+ * without any check must not hold one (such a coordinate enters the tree as
+ * 0).  Waits, accumulation, grid and other errors as kdt_p2m.
+ * Errors also: KDT_EINVAL (NULL tree, scheme outside 0..3),
+ * KDT_EUNSUPPORTED (d != 3, or a tree of float64 coordinates).
+ */
+kdt_status kdt_p2m_tree(const kdt_tree *tree, const float *d_m, const float *d_h,
+                        const kdt_grid *grid, int32_t scheme, float *d_grid, hipStream_t stream);
+kdt_status kdt_p2m_tree_backward(const kdt_tree *tree, const float *d_m, const float *d_h,
+                                 const kdt_grid *grid, const float *d_ggrid, float *d_gm,
+                                 float *d_gx, hipStream_t stream);
 
 /*
  * kdt_query_order -- writes into d_order [nq] (int32, device) a deterministic

@@ -364,6 +364,71 @@ extern "C" kdt_status kdt_tree_check(const kdt_tree* tree, hipStream_t stream) {
   return KDT_OK;
 }
 
+namespace {
+// Rows of W 4-byte elements (W = 0: the runtime width w) between input and
+// tree order: gather out[t] = in[perm[t]], scatter out[perm[t]] = in[t].  One
+// thread per element, consecutive threads on consecutive tree-order
+// elements, so the tree-order side is read or written as whole lines.
+template <int W, bool SCATTER>
+__global__ void k_tree_permute(const int32_t* __restrict__ perm, int64_t n, int w,
+                               const uint32_t* __restrict__ in, uint32_t* __restrict__ out) {
+  const int64_t width = W > 0 ? W : w;
+  const int64_t total = n * width;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += step) {
+    const int64_t t = e / width, c = e - t * width;
+    const int64_t i = perm[t];
+    if (SCATTER)
+      out[i * width + c] = in[e];
+    else
+      out[e] = in[i * width + c];
+  }
+}
+
+kdt_status tree_permute(const kdt_tree* tree, const void* d_in, int32_t width, void* d_out,
+                        hipStream_t stream, bool scatter, const char* who) {
+  if (!tree || width < 1 || width > 4096 || (tree->n > 0 && (!d_in || !d_out)) ||
+      (tree->n > 0 && d_in == d_out)) {
+    kdt_set_error("%s: NULL tree or arrays, width outside [1, 4096], or in == out", who);
+    return KDT_EINVAL;
+  }
+  if (tree->n == 0) return KDT_OK;
+  const int64_t total = tree->n * (int64_t)width;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  const auto* in = static_cast<const uint32_t*>(d_in);
+  auto* out = static_cast<uint32_t*>(d_out);
+#define KDT_PERMUTE(WW)                                                                  \
+  (scatter ? (k_tree_permute<WW, true><<<grid, 256, 0, stream>>>(tree->perm, tree->n, width, \
+                                                                 in, out))               \
+           : (k_tree_permute<WW, false><<<grid, 256, 0, stream>>>(tree->perm, tree->n, width, \
+                                                                  in, out)))
+  if (width == 1)
+    KDT_PERMUTE(1);
+  else if (width == 3)
+    KDT_PERMUTE(3);
+  else
+    KDT_PERMUTE(0);
+#undef KDT_PERMUTE
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("%s: kernel launch failed", who);
+    return KDT_EDEVICE;
+  }
+  return KDT_OK;
+}
+}  // namespace
+
+extern "C" kdt_status kdt_tree_gather(const kdt_tree* tree, const void* d_in, int32_t width,
+                                      void* d_out, hipStream_t stream) {
+  kdt_clear_error();
+  return tree_permute(tree, d_in, width, d_out, stream, false, "kdt_tree_gather");
+}
+
+extern "C" kdt_status kdt_tree_scatter(const kdt_tree* tree, const void* d_in, int32_t width,
+                                       void* d_out, hipStream_t stream) {
+  kdt_clear_error();
+  return tree_permute(tree, d_in, width, d_out, stream, true, "kdt_tree_scatter");
+}
+
 extern "C" kdt_status kdt_tree_get_info(const kdt_tree* tree, kdt_tree_info* info) {
   kdt_clear_error();
   if (!tree || !info) {

@@ -38,7 +38,8 @@ constexpr float kBigGrowMin = 1.1f;
 constexpr float kBigGrowCap = 64.0f;
 
 // Queries in a spatially coherent order, pos -> row: the tree's own points
-// in tree order (self queries) or the given queries gathered through `order`.
+// in tree order (self queries; rowof NULL: the rows stay in tree order) or
+// the given queries gathered through `order`.
 template <int D>
 __global__ void k_gather_self(const float* __restrict__ rec, int64_t n, float* __restrict__ qs,
                               int32_t* __restrict__ rowof) {
@@ -47,7 +48,7 @@ __global__ void k_gather_self(const float* __restrict__ rec, int64_t n, float* _
   if (i >= n) return;
 #pragma unroll
   for (int a = 0; a < D; ++a) qs[i * D + a] = rec[i * S + a];
-  rowof[i] = __float_as_int(rec[i * S + D]);
+  if (rowof) rowof[i] = __float_as_int(rec[i * S + D]);
 }
 
 template <int D>
@@ -422,8 +423,9 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
       return KDT_ENOMEM;
     }
     if (!d_q) {
-      k_gather_self<D><<<gq, 256, 0, stream>>>(tr->rec, nq, qs, rows);
-      rowof = rows;
+      // `given` set: the tree-order row marker -- row = position
+      k_gather_self<D><<<gq, 256, 0, stream>>>(tr->rec, nq, qs, given ? nullptr : rows);
+      rowof = given ? nullptr : rows;
     } else {
       if (!given) {
         const kdt_status st = kdt_query_order(tr, d_q, nq, 0, rows, stream);

@@ -185,7 +185,7 @@ __device__ __forceinline__ int64_t load_query64(const View64& v, const double* _
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) qq[a] = v.rec[i * D + a];
-  return v.perm[i];
+  return order ? i : v.perm[i];  // self queries: tree order when order is set
 }
 
 template <int D, int KC, typename Shape>
@@ -463,8 +463,12 @@ extern "C" kdt_status kdt_knn_f64(const kdt_tree* tree, const double* d_q, int64
     kdt_set_error("kdt_knn_f64: self queries need nq == n (%lld)", (long long)tree->n);
     return KDT_EINVAL;
   }
+  const int32_t* rows = nullptr;
+  const kdt_status rs = self_rows(tree, d_q, opts, "kdt_knn_f64", &rows);
+  if (rs != KDT_OK) return rs;
   PoolBuffers buf(stream);
-  const int32_t* order = opts ? opts->order : nullptr;
+  // self queries: the tree-order row marker (or NULL)
+  const int32_t* order = d_q ? (opts ? opts->order : nullptr) : rows;
   int32_t* own = nullptr;
   if (d_q && !order && (!opts || opts->sort_queries) && nq > 1) {
     const kdt_status st = order64(tree, d_q, nq, buf, &own, stream);
@@ -481,10 +485,10 @@ extern "C" kdt_status kdt_knn_f64(const kdt_tree* tree, const double* d_q, int64
       constexpr int KC = decltype(kc)::value;
       if (tree->nodes)
         k_knn64<D, KC, StoredShape><<<g, kF64Block, smem, stream>>>(
-            v, d_q, nq, k, d_q ? order : nullptr, d_idx, d_d2, depth);
+            v, d_q, nq, k, order, d_idx, d_d2, depth);
       else
         k_knn64<D, KC, MedianShape><<<g, kF64Block, smem, stream>>>(
-            v, d_q, nq, k, d_q ? order : nullptr, d_idx, d_d2, depth);
+            v, d_q, nq, k, order, d_idx, d_d2, depth);
     };
     if (k <= 8)
       go(std::integral_constant<int, 8>());
@@ -524,6 +528,9 @@ extern "C" kdt_status kdt_range_f64(const kdt_tree* tree, const double* d_q, int
     kdt_set_error("kdt_range_f64: self queries need nq == n (%lld)", (long long)tree->n);
     return KDT_EINVAL;
   }
+  const int32_t* rows = nullptr;
+  const kdt_status rs = self_rows(tree, d_q, opts, "kdt_range_f64", &rows);
+  if (rs != KDT_OK) return rs;
   if (required) *required = 0;
   PoolBuffers buf(stream);
   const int32_t* order = opts ? opts->order : nullptr;
@@ -533,7 +540,7 @@ extern "C" kdt_status kdt_range_f64(const kdt_tree* tree, const double* d_q, int
     if (st != KDT_OK) return st;
     order = own;
   }
-  if (!d_q) order = nullptr;
+  if (!d_q) order = rows;  // self queries: the tree-order row marker (or NULL)
   const View64 v = view64(tree);
   const double r2 = r * r;
   const int depth = stack_depth(tree);

@@ -353,6 +353,28 @@ inline bool refuse_f64(const kdt_tree* t, const char* who) {
   return false;
 }
 
+// The rows of self queries (d_q NULL).  opts->tree_rows 0: row i belongs to
+// input point i; 1: row t belongs to the tree's t-th point (tree order).
+// The query kernels take, for self queries, a non-NULL order argument as the
+// request for tree-order rows (it is never read): *rows gets t->perm then,
+// else NULL.  KDT_EINVAL (error set) for another value, or tree_rows with
+// external queries.
+inline kdt_status self_rows(const kdt_tree* t, const void* d_q, const kdt_query_opts* opts,
+                            const char* who, const int32_t** rows) {
+  const int32_t tr = opts ? opts->tree_rows : 0;
+  *rows = nullptr;
+  if (tr != 0 && tr != 1) {
+    kdt_set_error("%s: tree_rows must be 0 or 1", who);
+    return KDT_EINVAL;
+  }
+  if (tr && d_q) {
+    kdt_set_error("%s: tree_rows applies to self queries (NULL queries) only", who);
+    return KDT_EINVAL;
+  }
+  if (tr) *rows = t->perm;
+  return KDT_OK;
+}
+
 // Entry points whose kernels use the median tree's implicit layout refuse a
 // sliding-midpoint tree: true (and the error set) if t is one.
 inline bool refuse_stored(const kdt_tree* t, const char* who) {

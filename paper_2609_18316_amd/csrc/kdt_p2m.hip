@@ -20,10 +20,12 @@
 // Forward, as a binned deposit into LDS tiles of 16^3 cells:
 //  1. one lane per particle (in visiting order) gathers it from the caller's
 //     arrays, stores it packed for the later passes (x, y, z, h as one
-//     float4, and m), sums S_i over its support, keeps m_i / S_i and counts,
-//     per tile, the particles whose support box overlaps it (wave-aggregated
+//     float4), sums S_i over its support, keeps m_i / S_i and counts, per
+//     tile, the particles whose support box overlaps it (wave-aggregated
 //     atomics: the lanes of a wave hold nearby particles); the later passes
-//     stream the packed copy instead of gathering again;
+//     stream the packed copy instead of gathering again.  The tree entry
+//     points read the positions from a tree's records and m, h in tree
+//     order, so every pass streams contiguous arrays;
 //  2. the host reads the per-tile counts, lays out the (tile, particle) lists
 //     and cuts them into chunks of at most kChunk particles;
 //  3. the particles are scattered into their tiles' lists;
@@ -113,9 +115,21 @@ struct Particle {
   bool ok;
 };
 
-// A particle as the gather pass stores it: x, y, z, h; m apart.
+// A particle as the gather pass stores it: x, y, z, h.
 __device__ __forceinline__ float4 load_packed(const float4* __restrict__ P, int64_t t) {
   return P[t];
+}
+
+// Position i of the caller's [n][3] array (XS = 3) or of a 3-d tree's
+// records [n][4] (XS = 4: x, y, z and the point's index).
+template <int XS>
+__device__ __forceinline__ void load_position(const float* __restrict__ x, int64_t i, float p[3]) {
+  if constexpr (XS == 4) {
+    const float4 r = reinterpret_cast<const float4*>(x)[i];
+    p[0] = r.x, p[1] = r.y, p[2] = r.z;
+  } else {
+    p[0] = x[3 * i], p[1] = x[3 * i + 1], p[2] = x[3 * i + 2];
+  }
 }
 
 // Validity of a particle: inside the mesh box; for the adaptive kernel also
@@ -347,31 +361,33 @@ __device__ __forceinline__ bool tile_range(const Particle& p, int t0[3], int t1[
 }
 
 // Step 1: per particle (visiting position t): gathered from the caller's
-// arrays and stored packed, P[t] = (x, y, z, h), M[t] = m; f = m / S over
-// all its images; the per-tile entry counts (one per image and overlapped
-// tile); the validity flag for a particle outside the box or with an invalid
-// h.  The gather's scattered reads overlap the support sums.
-template <int SCH>
+// arrays (positions with XS floats per row) and stored packed,
+// P[t] = (x, y, z, h); f = m / S over all its images; the per-tile entry
+// counts (one per image and overlapped tile); the validity flag for a
+// particle outside the box or with an invalid h, or for a tree whose
+// deferred finiteness check failed (tree_bad).  The gather's scattered
+// reads, if any, overlap the support sums.
+template <int SCH, int XS>
 __global__ __launch_bounds__(kPBlock) void k_p2m_prep(GridDev g, TileGrid tg,
                                                       const float* __restrict__ xin,
                                                       const float* __restrict__ min_,
                                                       const float* __restrict__ hin, int64_t n,
                                                       const int32_t* __restrict__ order,
+                                                      const int32_t* __restrict__ tree_bad,
                                                       float4* __restrict__ P,
-                                                      float* __restrict__ M,
                                                       float* __restrict__ fbuf,
                                                       uint32_t* __restrict__ tcount,
                                                       int32_t* __restrict__ bad) {
   const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
   float x[3] = {0.0f, 0.0f, 0.0f}, h = 0.0f, m = 0.0f;
   bool ok = false;
+  if (t == 0 && tree_bad && *tree_bad) atomicOr(bad, 1);
   if (t < n) {
     const int64_t i = order ? order[t] : t;
-    x[0] = xin[3 * i], x[1] = xin[3 * i + 1], x[2] = xin[3 * i + 2];
+    load_position<XS>(xin, i, x);
     h = hin ? hin[i] : 0.0f;
     m = min_[i];
     P[t] = make_float4(x[0], x[1], x[2], h);
-    M[t] = m;
     ok = particle_ok<SCH>(g, x, h);
     if (!ok) atomicOr(bad, 1);
   }
@@ -541,18 +557,24 @@ __global__ __launch_bounds__(kPBlock) void k_p2m_reduce(GridDev g, TileGrid tg,
   mesh[((int64_t)ix * g.n[1] + iy) * g.n[2] + iz] = (float)v;
 }
 
+// The adjoint: one lane per particle (visiting position t, row order[t] or
+// t of every per-particle array; positions with XS floats per row).
+template <int XS>
 __global__ __launch_bounds__(kPBlock) void k_p2m_bwd(GridDev g, const float* __restrict__ x,
                                                      const float* __restrict__ m,
                                                      const float* __restrict__ h, int64_t n,
                                                      const int32_t* __restrict__ order,
+                                                     const int32_t* __restrict__ tree_bad,
                                                      const float* __restrict__ gg,
                                                      float* __restrict__ gm,
                                                      float* __restrict__ gx,
                                                      int32_t* __restrict__ bad) {
   const int64_t t = xcd_block<kXcdRunP2M>() * kPBlock + threadIdx.x;
+  if (t == 0 && tree_bad && *tree_bad) atomicOr(bad, 1);
   if (t >= n) return;
   const int64_t i = order ? order[t] : t;
-  const float xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+  float xi[3];
+  load_position<XS>(x, i, xi);
   const float hi = h[i], mi = m[i];
   if (!particle_ok(g, xi, hi)) {
     atomicOr(bad, 1);
@@ -612,7 +634,8 @@ using namespace kdt;
 
 // Reads the device-side validity flag back, waits for the stream and
 // reports the flag.
-static kdt_status read_bad_flag(const int32_t* d_bad, hipStream_t stream, const char* who) {
+static kdt_status read_bad_flag(const int32_t* d_bad, hipStream_t stream, const char* who,
+                                bool tree) {
   int32_t bad = 0;
   hipError_t e = hipMemcpyAsync(&bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -622,7 +645,8 @@ static kdt_status read_bad_flag(const int32_t* d_bad, hipStream_t stream, const 
   }
   if (bad) {
     kdt_set_error("%s: a particle lies outside the grid or has an invalid smoothing length "
-                  "(on a periodic mesh H must stay below half of every period)", who);
+                  "(on a periodic mesh H must stay below half of every period)%s", who,
+                  tree ? ", or the tree's points hold a non-finite coordinate" : "");
     return KDT_EINVAL;
   }
   return KDT_OK;
@@ -686,12 +710,25 @@ static kdt_status self_order(const GridDev& g, const int32_t gn[3], const float*
   return KDT_OK;
 }
 
-// The binned deposit of either scheme (d_h NULL for the fixed clouds); `who`
-// names the entry point in messages.
-static kdt_status p2m_forward(int sch, const char* who, const float* d_x, const float* d_m,
-                              const float* d_h, int64_t n, const kdt_grid* grid,
-                              const int32_t* d_order, float* d_grid, hipStream_t stream) {
-  if (!d_grid || n < 0 || !grid_ok(grid) || (n > 0 && (!d_x || !d_m || (sch == kSph && !d_h)))) {
+// Where a deposit's particles come from: the caller's arrays (positions
+// [n][3]; row order[t], or t, of every array for visiting position t), or a
+// 3-d tree's records [n][4] with m and h in tree order (xs = 4, no order).
+struct Source {
+  const float* x;
+  const float* m;
+  const float* h;             // NULL for the fixed clouds
+  const int32_t* order;
+  int xs;                     // floats per position row: 3 or 4
+  const int32_t* tree_bad;    // the tree's deferred finiteness flag, or NULL
+  bool may_self_order;        // an unordered call of the caller's arrays
+};
+
+// The binned deposit of either scheme; `who` names the entry point in
+// messages.
+static kdt_status p2m_forward(int sch, const char* who, Source src, int64_t n,
+                              const kdt_grid* grid, float* d_grid, hipStream_t stream) {
+  if (!d_grid || n < 0 || !grid_ok(grid) ||
+      (n > 0 && (!src.x || !src.m || (sch == kSph && !src.h)))) {
     kdt_set_error("%s: NULL pointer, negative n or invalid grid", who);
     return KDT_EINVAL;
   }
@@ -711,8 +748,8 @@ static kdt_status p2m_forward(int sch, const char* who, const float* d_x, const 
     kdt_set_error("%s: mesh too large (%lld tiles of %d^3 cells)", who, (long long)n_tiles, kT);
     return KDT_EUNSUPPORTED;
   }
-  if (!d_order && n >= kSelfOrderMin) {
-    const kdt_status st = self_order(g, grid->n, d_x, n, stream, who, &d_order);
+  if (src.may_self_order && !src.order && n >= kSelfOrderMin) {
+    const kdt_status st = self_order(g, grid->n, src.x, n, stream, who, &src.order);
     if (st != KDT_OK) return st;
   }
   // scratch kept on the stream between calls: the packed particles, m / S
@@ -721,23 +758,27 @@ static kdt_status p2m_forward(int sch, const char* who, const float* d_x, const 
   const size_t a_p = align256(sizeof(float4) * (size_t)n);
   const size_t a_n = align256(sizeof(float) * (size_t)n);
   const size_t a_t = align256(sizeof(uint32_t) * ((size_t)n_tiles + 64));
-  char* s0 = static_cast<char*>(stream_scratch(stream, kSlotParticles, a_p + 2 * a_n + a_t));
+  char* s0 = static_cast<char*>(stream_scratch(stream, kSlotParticles, a_p + a_n + a_t));
   if (!s0) {
     kdt_set_error("%s: device allocation failed", who);
     return KDT_ENOMEM;
   }
   float4* P = reinterpret_cast<float4*>(s0);
-  float* M = reinterpret_cast<float*>(s0 + a_p);
-  float* fbuf = reinterpret_cast<float*>(s0 + a_p + a_n);
-  uint32_t* tcount = reinterpret_cast<uint32_t*>(s0 + a_p + 2 * a_n);
+  float* fbuf = reinterpret_cast<float*>(s0 + a_p);
+  uint32_t* tcount = reinterpret_cast<uint32_t*>(s0 + a_p + a_n);
   int32_t* bad = reinterpret_cast<int32_t*>(tcount + n_tiles);
   const unsigned gt = (unsigned)((n_tiles + 64 + 255) / 256);
   k_fill_u32<<<gt, 256, 0, stream>>>(tcount, n_tiles + 64, 0u);
   const unsigned gp = (unsigned)((n + kPBlock - 1) / kPBlock);
   if (n > 0)
     by_scheme(sch, [&](auto c) {
-      k_p2m_prep<decltype(c)::value><<<gp, kPBlock, 0, stream>>>(g, tg, d_x, d_m, d_h, n, d_order,
-                                                                 P, M, fbuf, tcount, bad);
+      constexpr int S = decltype(c)::value;
+      if (src.xs == 4)
+        k_p2m_prep<S, 4><<<gp, kPBlock, 0, stream>>>(g, tg, src.x, src.m, src.h, n, src.order,
+                                                     src.tree_bad, P, fbuf, tcount, bad);
+      else
+        k_p2m_prep<S, 3><<<gp, kPBlock, 0, stream>>>(g, tg, src.x, src.m, src.h, n, src.order,
+                                                     src.tree_bad, P, fbuf, tcount, bad);
     });
   // the per-tile counts size the lists: read them back (with the check flag)
   std::vector<uint32_t> cnt((size_t)n_tiles + 1);
@@ -750,7 +791,8 @@ static kdt_status p2m_forward(int sch, const char* who, const float* d_x, const 
   }
   if (cnt[n_tiles] != 0) {
     kdt_set_error("%s: a particle lies outside the grid or has an invalid smoothing "
-                  "length (on a periodic mesh H must stay below half of every period)", who);
+                  "length (on a periodic mesh H must stay below half of every period)%s", who,
+                  src.tree_bad ? ", or the tree's points hold a non-finite coordinate" : "");
     return KDT_EINVAL;
   }
   // lay out the lists and cut them into chunks; tiles of several chunks get
@@ -848,25 +890,65 @@ extern "C" kdt_status kdt_p2m(const float* d_x, const float* d_m, const float* d
                               const kdt_grid* grid, const int32_t* d_order, float* d_grid,
                               hipStream_t stream) {
   kdt_clear_error();
-  return p2m_forward(kSph, "kdt_p2m", d_x, d_m, d_h, n, grid, d_order, d_grid, stream);
+  return p2m_forward(kSph, "kdt_p2m", Source{d_x, d_m, d_h, d_order, 3, nullptr, true}, n, grid,
+                     d_grid, stream);
+}
+
+// A fixed cloud's scheme and, on a periodic mesh, the cells per axis it
+// needs; false (and the error set) otherwise.
+static bool cloud_ok(const char* who, const kdt_grid* grid, int32_t scheme) {
+  if (scheme < kNgp || scheme > kTsc) {
+    kdt_set_error("%s: scheme %d is not 1 (NGP), 2 (CIC) or 3 (TSC)", who, scheme);
+    return false;
+  }
+  if (grid && grid->periodic)
+    for (int a = 0; a < 3; ++a)
+      if (grid->n[a] < scheme) {
+        kdt_set_error("%s: a periodic mesh needs at least %d cells per axis", who, scheme);
+        return false;
+      }
+  return true;
 }
 
 extern "C" kdt_status kdt_p2m_cloud(const float* d_x, const float* d_m, int64_t n,
                                     const kdt_grid* grid, int32_t scheme, const int32_t* d_order,
                                     float* d_grid, hipStream_t stream) {
   kdt_clear_error();
-  if (scheme < kNgp || scheme > kTsc) {
-    kdt_set_error("kdt_p2m_cloud: scheme %d is not 1 (NGP), 2 (CIC) or 3 (TSC)", scheme);
+  if (!cloud_ok("kdt_p2m_cloud", grid, scheme)) return KDT_EINVAL;
+  return p2m_forward(scheme, "kdt_p2m_cloud", Source{d_x, d_m, nullptr, d_order, 3, nullptr, true},
+                     n, grid, d_grid, stream);
+}
+
+static kdt_status p2m_backward(const char* who, Source src, int64_t n, const kdt_grid* grid,
+                               const float* d_ggrid, float* d_gm, float* d_gx,
+                               hipStream_t stream) {
+  if (n < 0 || !grid_ok(grid) || (n > 0 && (!src.x || !src.m || !src.h || !d_ggrid))) {
+    kdt_set_error("%s: NULL pointer, negative n or invalid grid", who);
     return KDT_EINVAL;
   }
-  if (grid && grid->periodic)
-    for (int a = 0; a < 3; ++a)
-      if (grid->n[a] < scheme) {
-        kdt_set_error("kdt_p2m_cloud: a periodic mesh needs at least %d cells per axis", scheme);
-        return KDT_EINVAL;
-      }
-  return p2m_forward(scheme, "kdt_p2m_cloud", d_x, d_m, nullptr, n, grid, d_order, d_grid,
-                     stream);
+  if (n == 0 || (!d_gm && !d_gx)) return KDT_OK;
+  int32_t* bad = static_cast<int32_t*>(stream_scratch(stream, kSlotFlag, 256));
+  if (!bad) {
+    kdt_set_error("%s: allocation failed", who);
+    return KDT_ENOMEM;
+  }
+  k_zero_f64<<<1, 32, 0, stream>>>(reinterpret_cast<double*>(bad), 1);
+  if (src.may_self_order && !src.order && n >= kSelfOrderMin) {
+    const kdt_status st = self_order(to_dev(grid), grid->n, src.x, n, stream, who, &src.order);
+    if (st != KDT_OK) return st;
+  }
+  const unsigned gp = (unsigned)((n + kPBlock - 1) / kPBlock);
+  if (src.xs == 4)
+    k_p2m_bwd<4><<<gp, kPBlock, 0, stream>>>(to_dev(grid), src.x, src.m, src.h, n, src.order,
+                                             src.tree_bad, d_ggrid, d_gm, d_gx, bad);
+  else
+    k_p2m_bwd<3><<<gp, kPBlock, 0, stream>>>(to_dev(grid), src.x, src.m, src.h, n, src.order,
+                                             src.tree_bad, d_ggrid, d_gm, d_gx, bad);
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("%s: kernel launch failed", who);
+    return KDT_EDEVICE;
+  }
+  return read_bad_flag(bad, stream, who, src.tree_bad != nullptr);
 }
 
 extern "C" kdt_status kdt_p2m_backward(const float* d_x, const float* d_m, const float* d_h,
@@ -874,27 +956,45 @@ extern "C" kdt_status kdt_p2m_backward(const float* d_x, const float* d_m, const
                                        const float* d_ggrid, float* d_gm, float* d_gx,
                                        hipStream_t stream) {
   kdt_clear_error();
-  if (n < 0 || !grid_ok(grid) || (n > 0 && (!d_x || !d_m || !d_h || !d_ggrid))) {
-    kdt_set_error("kdt_p2m_backward: NULL pointer, negative n or invalid grid");
-    return KDT_EINVAL;
+  return p2m_backward("kdt_p2m_backward", Source{d_x, d_m, d_h, d_order, 3, nullptr, true}, n,
+                      grid, d_ggrid, d_gm, d_gx, stream);
+}
+
+// A tree the tree-ordered deposit can read: 3-d float32 coordinates, records
+// of 4 floats; false (and the error set) otherwise.
+static bool p2m_tree_ok(const kdt_tree* tree, const char* who) {
+  if (!tree) {
+    kdt_set_error("%s: NULL tree", who);
+    return false;
   }
-  if (n == 0 || (!d_gm && !d_gx)) return KDT_OK;
-  int32_t* bad = static_cast<int32_t*>(stream_scratch(stream, kSlotFlag, 256));
-  if (!bad) {
-    kdt_set_error("kdt_p2m_backward: allocation failed");
-    return KDT_ENOMEM;
+  if (refuse_f64(tree, who)) return false;
+  if (tree->d != 3 || tree->stride != 4) {
+    kdt_set_error("%s: the deposit needs a tree of 3-d points (this one has d = %d)", who,
+                  tree->d);
+    return false;
   }
-  k_zero_f64<<<1, 32, 0, stream>>>(reinterpret_cast<double*>(bad), 1);
-  if (!d_order && n >= kSelfOrderMin) {
-    const kdt_status st =
-        self_order(to_dev(grid), grid->n, d_x, n, stream, "kdt_p2m_backward", &d_order);
-    if (st != KDT_OK) return st;
-  }
-  k_p2m_bwd<<<(unsigned)((n + kPBlock - 1) / kPBlock), kPBlock, 0, stream>>>(
-      to_dev(grid), d_x, d_m, d_h, n, d_order, d_ggrid, d_gm, d_gx, bad);
-  if (hipGetLastError() != hipSuccess) {
-    kdt_set_error("kdt_p2m_backward: kernel launch failed");
-    return KDT_EDEVICE;
-  }
-  return read_bad_flag(bad, stream, "kdt_p2m_backward");
+  return true;
+}
+
+extern "C" kdt_status kdt_p2m_tree(const kdt_tree* tree, const float* d_m, const float* d_h,
+                                   const kdt_grid* grid, int32_t scheme, float* d_grid,
+                                   hipStream_t stream) {
+  kdt_clear_error();
+  if (!p2m_tree_ok(tree, "kdt_p2m_tree")) return tree ? KDT_EUNSUPPORTED : KDT_EINVAL;
+  if (scheme != kSph && !cloud_ok("kdt_p2m_tree", grid, scheme)) return KDT_EINVAL;
+  return p2m_forward(scheme, "kdt_p2m_tree",
+                     Source{tree->rec, d_m, scheme == kSph ? d_h : nullptr, nullptr, 4,
+                            tree->flag, false},
+                     tree->n, grid, d_grid, stream);
+}
+
+extern "C" kdt_status kdt_p2m_tree_backward(const kdt_tree* tree, const float* d_m,
+                                            const float* d_h, const kdt_grid* grid,
+                                            const float* d_ggrid, float* d_gm, float* d_gx,
+                                            hipStream_t stream) {
+  kdt_clear_error();
+  if (!p2m_tree_ok(tree, "kdt_p2m_tree_backward")) return tree ? KDT_EUNSUPPORTED : KDT_EINVAL;
+  return p2m_backward("kdt_p2m_tree_backward",
+                      Source{tree->rec, d_m, d_h, nullptr, 4, tree->flag, false}, tree->n, grid,
+                      d_ggrid, d_gm, d_gx, stream);
 }

@@ -42,9 +42,10 @@ __device__ __forceinline__ bool load_query(const TreeView& t, const float* __res
     return false;
   }
   if (q == nullptr) {
+    // self queries: row = input index, or s (tree order) when order is set
     int32_t id = 0;
     load_rec<D>(t.rec, s, p, id);
-    row = id;
+    row = order ? s : id;
   } else {
     row = order ? order[s] : s;
 #pragma unroll

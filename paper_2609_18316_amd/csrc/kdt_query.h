@@ -678,6 +678,8 @@ struct KnnArgs {
   bool empty = false;  // nq == 0: nothing to do
   bool sort_q = true;
   int traversal = 0;
+  // external queries: the caller's order or NULL; self queries: the
+  // tree-order row marker (self_rows) or NULL
   const int32_t* given = nullptr;
   const float* period = nullptr;
 };

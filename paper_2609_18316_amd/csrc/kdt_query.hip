@@ -39,9 +39,10 @@ __global__ __launch_bounds__(kQBlock) void k_knn_lane(TreeView t, const float* _
   float p[D];
   int64_t row;
   if (q == nullptr) {
+    // self queries: row = input index, or s (tree order) when order is set
     int32_t id = 0;
     load_rec<D>(t.rec, s, p, id);
-    row = id;
+    row = order ? s : id;
   } else {
     row = order ? order[s] : s;
 #pragma unroll
@@ -78,9 +79,10 @@ __global__ __launch_bounds__(kQBlock) void k_range(TreeView t, const float* __re
   float p[D];
   int64_t row;
   if (q == nullptr) {
+    // self queries: row = input index, or s (tree order) when order is set
     int32_t id = 0;
     load_rec<D>(t.rec, s, p, id);
-    row = id;
+    row = order ? s : id;
   } else {
     row = order ? order[s] : s;
 #pragma unroll
@@ -371,7 +373,8 @@ static kdt_status knn_impl(const kdt_tree* t, const float* d_q, int64_t nq, int 
                                      ws, ws_bytes);
     if (st != KDT_OK) return st;
   }
-  const int32_t* use = d_q ? (given ? given : order) : nullptr;
+  // self queries: `given` is the tree-order row marker (or NULL)
+  const int32_t* use = d_q ? (given ? given : order) : given;
   kdt_status st = traversal == 1
                       ? knn_dispatch<D>(t, d_q, nq, k, d_idx, d_d2, mode, use, stream)
                       : knn_packet_launch<D>(view_of(t), t->leaf, d_q, nq, k, d_idx, d_d2, mode,
@@ -390,7 +393,8 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
     kdt_status st = order_queries<D>(t, d_q, nq, 0, &own, stream);
     if (st != KDT_OK) return st;
   }
-  const int32_t* order = d_q ? (given ? given : own) : nullptr;
+  // self queries: `given` is the tree-order row marker (or NULL)
+  const int32_t* order = d_q ? (given ? given : own) : given;
   const TreeView v = view_of(t);
   const float r2 = r * r;
   const unsigned grid = (unsigned)((nq + kQBlock - 1) / kQBlock);
@@ -556,7 +560,10 @@ kdt_status knn_check(const kdt_tree* tree, const float* d_q, int64_t nq, int32_t
   }
   a->sort_q = opts ? opts->sort_queries != 0 : true;
   a->traversal = opts ? opts->traversal : 0;
-  a->given = opts ? opts->order : nullptr;
+  const int32_t* rows = nullptr;
+  const kdt_status rs = self_rows(tree, d_q, opts, who, &rows);
+  if (rs != KDT_OK) return rs;
+  a->given = d_q ? (opts ? opts->order : nullptr) : rows;
   a->period = opts ? opts->period : nullptr;
   if (a->traversal < 0 || a->traversal > 2) {
     kdt_set_error("%s: traversal must be 0, 1 or 2", who);
@@ -646,17 +653,22 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
     return KDT_OK;
   }
   const bool sort_q = opts ? opts->sort_queries != 0 : true;
+  const int32_t* rows = nullptr;
+  const kdt_status rs = self_rows(tree, d_q, opts, "kdt_range", &rows);
+  if (rs != KDT_OK) return rs;
+  const int32_t* given = d_q ? (opts ? opts->order : nullptr) : rows;
   if (opts && opts->period && refuse_stored(tree, "kdt_range with a period"))
     return KDT_EUNSUPPORTED;
   if (opts && opts->period)
     return range_torus(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q,
-                       opts->order, opts->period, stream);
+                       given, opts->period, stream);
+  const int trav = opts ? opts->traversal : 0;
   switch (tree->d) {
-    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
-    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
-    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
-    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
-    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, opts ? opts->order : nullptr, opts ? opts->traversal : 0, budget, stream);
+    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
   }
   kdt_set_error("kdt_range: unsupported dimension %d", tree->d);
   return KDT_EUNSUPPORTED;

@@ -23,8 +23,9 @@ namespace kdt {
 
 constexpr int kTBlock = 128;
 
-// One query per lane: the tree's own points (q == NULL, row = input index)
-// or q[order[s]] (q[s] without an order).
+// One query per lane: the tree's own points (q == NULL; row = input index,
+// or s -- tree order -- when order is set) or q[order[s]] (q[s] without an
+// order).
 template <int D>
 __device__ __forceinline__ int64_t torus_query(const TreeView& t, const float* __restrict__ q,
                                                const int32_t* __restrict__ order, int64_t s,
@@ -32,7 +33,7 @@ __device__ __forceinline__ int64_t torus_query(const TreeView& t, const float* _
   if (q == nullptr) {
     int32_t id = 0;
     load_rec<D>(t.rec, s, p, id);
-    return id;
+    return order ? s : id;
   }
   const int64_t row = order ? order[s] : s;
 #pragma unroll
@@ -201,7 +202,7 @@ static kdt_status torus_knn_impl(const kdt_tree* tr, const float* d_q, int64_t n
     if (st != KDT_OK) return st;
     order = own;
   }
-  if (!d_q) order = nullptr;
+  if (!d_q) order = given;  // self queries: the tree-order row marker (or NULL)
   const unsigned grid = (unsigned)((nq + kTBlock - 1) / kTBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 1) * kTBlock;
 #define KDT_TORUS(KC)                                                                          \
@@ -254,7 +255,7 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
     if (st != KDT_OK) return st;
     order = own;
   }
-  if (!d_q) order = nullptr;
+  if (!d_q) order = given;  // self queries: the tree-order row marker (or NULL)
   const float r2 = r * r;
   const unsigned grid = (unsigned)((nq + kTBlock - 1) / kTBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;

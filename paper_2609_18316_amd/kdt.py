@@ -30,6 +30,7 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_batch_plan_create", "kdt_batch_launch", "kdt_batch_plan_free", "kdt_knn_noalloc",
            "kdt_stream_release", "kdt_tuning_set", "kdt_tuning_get",
            "kdt_build_f64", "kdt_knn_f64", "kdt_range_f64", "kdt_tree_check",
+           "kdt_tree_gather", "kdt_tree_scatter", "kdt_p2m_tree", "kdt_p2m_tree_backward",
            "kdt_last_error")
 # The test and measurement hooks of include/kdt_debug.h.
 DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe",
@@ -63,7 +64,8 @@ def _periods(period, d: int):
 
 class QueryOpts(C.Structure):
     _fields_ = [("sort_queries", C.c_int32), ("traversal", C.c_int32), ("order", C.c_void_p),
-                ("split_budget", C.c_int32), ("period", C.POINTER(C.c_float))]
+                ("split_budget", C.c_int32), ("period", C.POINTER(C.c_float)),
+                ("tree_rows", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -110,6 +112,10 @@ def load(path: str = LIB_PATH):
     lib.kdt_stream_release.argtypes = [vp]
     lib.kdt_tuning_set.argtypes = [i32, i64, i32, i32, i32]
     lib.kdt_tree_check.argtypes = [vp, vp]
+    lib.kdt_tree_gather.argtypes = [vp, vp, i32, vp, vp]
+    lib.kdt_tree_scatter.argtypes = [vp, vp, i32, vp, vp]
+    lib.kdt_p2m_tree.argtypes = [vp, vp, vp, C.POINTER(Grid), i32, vp, vp]
+    lib.kdt_p2m_tree_backward.argtypes = [vp, vp, vp, C.POINTER(Grid), vp, vp, vp, vp]
     lib.kdt_build_f64.argtypes = [vp, i64, i32, C.POINTER(BuildOpts), vp, C.POINTER(vp)]
     lib.kdt_knn_f64.argtypes = [vp, vp, i64, i32, vp, vp, C.POINTER(QueryOpts), vp]
     lib.kdt_range_f64.argtypes = [vp, vp, i64, C.c_double, vp, vp, vp, i64, C.POINTER(C.c_int64),
@@ -289,6 +295,28 @@ class Tree:
         """Device address of the tree order (n int32, owned by the tree)."""
         return int(load().kdt_tree_perm(self._h))
 
+    def gather(self, values: torch.Tensor, stream=None) -> torch.Tensor:
+        """Per-point values (rows of 4-byte elements, input order) in tree
+        order: out[t] = values[perm[t]]."""
+        return self._permute(values, "kdt_tree_gather", stream)
+
+    def scatter(self, values: torch.Tensor, stream=None) -> torch.Tensor:
+        """Per-point values in tree order back in input order:
+        out[perm[t]] = values[t]."""
+        return self._permute(values, "kdt_tree_scatter", stream)
+
+    def _permute(self, values, fn, stream):
+        if values.dtype not in (torch.float32, torch.int32):
+            raise TypeError("values must be float32 or int32")
+        if values.shape[0] != self.n:
+            raise ValueError(f"values need {self.n} rows")
+        values = _dev(values.contiguous(), values.dtype, "values")
+        width = values.numel() // max(self.n, 1)
+        out = torch.empty_like(values)
+        _check(getattr(load(), fn)(self._h, _ptr(values), int(width), _ptr(out),
+                                   _stream(stream)))
+        return out
+
     def query_order(self, queries: torch.Tensor, kind: int = 0, stream=None) -> torch.Tensor:
         """Permutation of the queries along the tree (reusable through ``order=``).
 
@@ -304,10 +332,11 @@ class Tree:
 
     def knn(self, queries: torch.Tensor | None, k: int, kth_only: int = 0,
             sort_queries: bool = True, traversal: int = 0, order: torch.Tensor | None = None,
-            period=None, stream=None):
+            period=None, stream=None, tree_rows: bool = False):
         """k nearest neighbours, ascending by (d2, index): (idx [nq][k], d2 [nq][k]).
 
-        ``queries=None`` queries every point of the tree (row i = input point i).
+        ``queries=None`` queries every point of the tree (row i = input point i;
+        with ``tree_rows`` row t = the tree's t-th point, input point perm[t]).
         ``kth_only=1`` returns only d2 of the k-th neighbour, ``2`` its distance.
         ``period`` (one value or one per axis): distances on the D-torus, every
         point and query in [0, period).
@@ -316,7 +345,8 @@ class Tree:
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
         per = _periods(period, self.d)
-        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), 0, per)
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), 0, per,
+                         1 if tree_rows else 0)
         if kth_only:
             d2 = torch.empty(nq, dtype=torch.float32, device=self.device)
             _check(load().kdt_knn(self._h, _ptr(queries), nq, k, None, _ptr(d2), kth_only,
@@ -331,7 +361,8 @@ class Tree:
     def knn_noalloc(self, queries: torch.Tensor | None, k: int, d2: torch.Tensor,
                     idx: torch.Tensor | None = None, kth_only: int = 0,
                     sort_queries: bool = True, traversal: int = 0,
-                    order: torch.Tensor | None = None, stream=None) -> None:
+                    order: torch.Tensor | None = None, stream=None,
+                    tree_rows: bool = False) -> None:
         """kNN into caller-given outputs through ``kdt_knn_noalloc`` (no
         allocation anywhere: the library's static scratch orders the queries).
 
@@ -346,26 +377,27 @@ class Tree:
             if kth_only:
                 raise ValueError("idx must be None with kth_only")
             idx = _dev(idx, torch.int32, "idx", (nq, k))
-        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), 0, None)
+        opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), 0, None,
+                         1 if tree_rows else 0)
         _check(load().kdt_knn_noalloc(self._h, _ptr(queries), nq, k, _ptr(idx), _ptr(d2),
                                       kth_only, C.byref(opts), _stream(stream)))
 
     def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
               sort_queries: bool = True, order: torch.Tensor | None = None, traversal: int = 0,
-              split_budget: int = 0, period=None, stream=None):
+              split_budget: int = 0, period=None, stream=None, tree_rows: bool = False):
         """Closed-ball counts; with ``lists`` also CSR (offsets int64, idx int32).
 
         ``split_budget`` > 0 makes every wave of the wave-shared count hand
         subtrees on to later launches after that many node visits (results are
         identical; 0 keeps the default schedule).  ``period``: balls on the
-        D-torus, as in ``knn``.
+        D-torus, as in ``knn``.  ``tree_rows``: self-query rows in tree order.
         """
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float32, "queries", (nq, self.d))
         per = _periods(period, self.d)
         opts = QueryOpts(1 if sort_queries else 0, int(traversal), _ptr(order), int(split_budget),
-                         per)
+                         per, 1 if tree_rows else 0)
         count = torch.empty(nq, dtype=torch.int32, device=self.device)
         lib = load()
         if not lists:
@@ -463,12 +495,13 @@ class TreeF64(Tree):
         self.device = points.device
 
     def knn(self, queries: torch.Tensor | None, k: int, sort_queries: bool = True,
-            order: torch.Tensor | None = None, stream=None, **unused):
+            order: torch.Tensor | None = None, stream=None, tree_rows: bool = False, **unused):
         """(idx int32 [nq][k], d2 float64 [nq][k]), ascending by (d2, index)."""
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float64, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order), 0, None)
+        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order), 0, None,
+                         1 if tree_rows else 0)
         idx = torch.empty((nq, k), dtype=torch.int32, device=self.device)
         d2 = torch.empty((nq, k), dtype=torch.float64, device=self.device)
         _check(load().kdt_knn_f64(self._h, _ptr(queries), nq, k, _ptr(idx), _ptr(d2),
@@ -477,12 +510,13 @@ class TreeF64(Tree):
 
     def range(self, queries: torch.Tensor | None, r: float, lists: bool = False,
               sort_queries: bool = True, order: torch.Tensor | None = None, stream=None,
-              **unused):
+              tree_rows: bool = False, **unused):
         """Closed-ball counts in float64; with ``lists`` also CSR."""
         nq = self.n if queries is None else queries.shape[0]
         if queries is not None:
             queries = _dev(queries, torch.float64, "queries", (nq, self.d))
-        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order), 0, None)
+        opts = QueryOpts(1 if sort_queries else 0, 0, _ptr(order), 0, None,
+                         1 if tree_rows else 0)
         count = torch.empty(nq, dtype=torch.int32, device=self.device)
         lib = load()
         if not lists:
@@ -569,6 +603,37 @@ def p2m_backward(x, m, h, lo, cell, shape, grad, order_ptr=None, need_m=True, ne
     g = make_grid(lo, cell, shape, periodic)
     _check(load().kdt_p2m_backward(_ptr(x), _ptr(m), _ptr(h), n, C.byref(g), order_ptr,
                                    _ptr(grad), _ptr(gm), _ptr(gx), _stream(stream)))
+    return gm, gx
+
+
+def p2m_tree(tree: "Tree", m: torch.Tensor, h: torch.Tensor | None, lo, cell: float, shape,
+             scheme: str = "sph", out: torch.Tensor | None = None, stream=None,
+             periodic: bool = False):
+    """Deposit of the tree's points (positions from its records) with m and
+    h (None for the fixed clouds) in tree order: float32 mass per cell."""
+    m = _dev(m, torch.float32, "m", (tree.n,))
+    if h is not None:
+        h = _dev(h, torch.float32, "h", (tree.n,))
+    if out is None:
+        out = torch.empty(tuple(shape), dtype=torch.float32, device=tree.device)
+    g = make_grid(lo, cell, shape, periodic)
+    code = 0 if scheme == "sph" else CLOUD_SCHEMES[scheme]
+    _check(load().kdt_p2m_tree(tree._h, _ptr(m), _ptr(h), C.byref(g), code, _ptr(out),
+                               _stream(stream)))
+    return out
+
+
+def p2m_tree_backward(tree: "Tree", m, h, lo, cell, shape, grad, need_m=True, need_x=True,
+                      stream=None, periodic: bool = False):
+    """(dL/dm, dL/dx) in tree order for L = sum(grad * p2m_tree(tree, m, h))."""
+    m = _dev(m, torch.float32, "m", (tree.n,))
+    h = _dev(h, torch.float32, "h", (tree.n,))
+    grad = _dev(grad.contiguous(), torch.float32, "grad")
+    gm = torch.empty(tree.n, dtype=torch.float32, device=tree.device) if need_m else None
+    gx = torch.empty((tree.n, 3), dtype=torch.float32, device=tree.device) if need_x else None
+    g = make_grid(lo, cell, shape, periodic)
+    _check(load().kdt_p2m_tree_backward(tree._h, _ptr(m), _ptr(h), C.byref(g), _ptr(grad),
+                                        _ptr(gm), _ptr(gx), _stream(stream)))
     return gm, gx
 
 

@@ -177,8 +177,16 @@ def test_deposit_full_size_subvolume_and_adjoint_sample(clustered):
     say("P2M forward 2^24 particles on 256^3")
     rho = to_host(kdt.p2m(xt, mt, h, (0, 0, 0), cell, (g, g, g), order_ptr=tree.perm_ptr))
     hh = to_host(h)
+    # the same deposit in tree order, as the step runs it: smoothing lengths
+    # written in tree order, masses gathered, positions from the tree
+    say("P2M forward in tree order")
+    h_t = tree.knn(None, 32, kth_only=2, tree_rows=True)
+    np.testing.assert_array_equal(to_host(tree.scatter(h_t)), hh)
+    m_t = tree.gather(mt)
+    rho_t = to_host(kdt.p2m_tree(tree, m_t, h_t, (0, 0, 0), cell, (g, g, g)))
     total = float(m.astype(np.float64).sum())
-    assert abs(float(rho.astype(np.float64).sum()) - total) <= 1e-5 * total
+    for r in (rho, rho_t):
+        assert abs(float(r.astype(np.float64).sum()) - total) <= 1e-5 * total
     mean = total / rho.size
     for lo_c in ((100, 100, 100), (3, 250, 17), (128, 64, 200)):
         lo = np.array(lo_c) * cell
@@ -190,6 +198,8 @@ def test_deposit_full_size_subvolume_and_adjoint_sample(clustered):
         o = oracle.p2m(x[sel], m[sel], hh[sel], (0, 0, 0), cell, (g, g, g))
         a, b, c = lo_c
         og = o[a:a + 16, b:b + 16, c:c + 16]
+        gt = rho_t[a:a + 16, b:b + 16, c:c + 16].astype(np.float64)
+        assert (np.abs(gt - og) <= 1e-5 * np.maximum(np.abs(og), mean)).all()
         gg = rho[a:a + 16, b:b + 16, c:c + 16].astype(np.float64)
         err = np.abs(gg - og)
         assert (err <= 1e-5 * np.maximum(np.abs(og), mean)).all()
@@ -206,6 +216,12 @@ def test_deposit_full_size_subvolume_and_adjoint_sample(clustered):
     s = workloads.sample_indices(N, 2048, seed=12)
     om, ox = oracle.p2m_backward(x[s], m[s], hh[s], (0, 0, 0), cell, (g, g, g), to_host(up))
     gm_s, gx_s = to_host(gm)[s].astype(np.float64), to_host(gx)[s].astype(np.float64)
+    assert (np.abs(gm_s - om) <= 1e-5 * np.maximum(np.abs(om), np.abs(om).mean())).all()
+    assert np.linalg.norm(gx_s - ox) <= 1e-4 * np.linalg.norm(ox)
+    say("P2M adjoint in tree order")
+    gm_t, gx_t = kdt.p2m_tree_backward(tree, m_t, h_t, (0, 0, 0), cell, (g, g, g), up)
+    gm_s = to_host(tree.scatter(gm_t))[s].astype(np.float64)
+    gx_s = to_host(tree.scatter(gx_t))[s].astype(np.float64)
     assert (np.abs(gm_s - om) <= 1e-5 * np.maximum(np.abs(om), np.abs(om).mean())).all()
     assert np.linalg.norm(gx_s - ox) <= 1e-4 * np.linalg.norm(ox)
 
