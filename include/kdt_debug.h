@@ -65,6 +65,16 @@ kdt_status kdt_debug_radix_sort(uint32_t *d_keys, int32_t *d_vals, int64_t n, in
 kdt_status kdt_debug_exclusive_scan(const int32_t *d_in, void *d_out, int64_t n, int32_t out_bits,
                                     hipStream_t stream);
 
+/*
+ * Sorts every row of a CSR list ascending, as the ball and box lists are:
+ * row r of d_in [total] int32 (device) is [d_off[r], d_off[r + 1]) (d_off
+ * [nq + 1] int64, device, d_off[nq] = total) and goes to the same range of
+ * d_out (not d_in).  Waits on `stream`.  For testing the row sort against a
+ * reference.  Errors: KDT_EINVAL, KDT_ENOMEM, KDT_EDEVICE.
+ */
+kdt_status kdt_debug_sort_rows(const int32_t *d_in, int32_t *d_out, const int64_t *d_off,
+                               int64_t nq, int64_t total, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

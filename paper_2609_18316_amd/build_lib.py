@@ -30,7 +30,7 @@ ARCH = os.environ.get("KDT_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["kdt_api.hip", "kdt_build.hip", "kdt_query.hip", "kdt_fof.hip", "kdt_p2m.hip",
            "kdt_batch.hip", "kdt_packet.hip", "kdt_box.hip", "kdt_bigk.hip",
            "kdt_torus.hip", "kdt_noalloc.hip", "kdt_midpoint.hip", "kdt_tuning.hip",
-           "kdt_f64.hip", "kdt_sort.hip"]
+           "kdt_f64.hip", "kdt_sort.hip", "kdt_rowsort.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

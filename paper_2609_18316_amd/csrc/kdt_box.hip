@@ -9,7 +9,6 @@
 // 64 points, one traversal per lane.  Only comparisons are involved, so the
 // result is exact.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <cmath>
 
@@ -193,22 +192,12 @@ static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d
     k_box<D, true><<<grid, kBoxBlock, smem, stream>>>(v, d_lo, d_hi, nq, order, d_count, d_off,
                                                        unsorted);
   }
-  void* stmp = nullptr;
-  size_t sb = 0;
-  if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total, (int)nq,
-                                            d_off, d_off + 1, stream) != hipSuccess) {
-    kdt_set_error("kdt_box: list sort setup failed");
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_box: list kernel launch failed");
     return KDT_EDEVICE;
   }
-  if (!buf.get((char**)&stmp, sb)) {
-    kdt_set_error("device allocation failed for sorting the box lists");
-    return KDT_ENOMEM;
-  }
-  if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total, (int)nq,
-                                            d_off, d_off + 1, stream) != hipSuccess) {
-    kdt_set_error("kdt_box: list sort failed");
-    return KDT_EDEVICE;
-  }
+  const kdt_status ss = sort_list_rows(unsorted, d_idx, d_off, nq, total, stream);
+  if (ss != KDT_OK) return ss;
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_box: list kernel launch failed");
     return KDT_EDEVICE;

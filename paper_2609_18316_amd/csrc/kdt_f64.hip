@@ -23,7 +23,6 @@
 // as in the float32 path; the candidate list is a sorted register array.
 
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cfloat>
@@ -609,22 +608,8 @@ extern "C" kdt_status kdt_range_f64(const kdt_tree* tree, const double* d_q, int
     return st;
   }
   // every row ascending by input index
-  size_t sb = 0;
-  if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total, (int)nq,
-                                            d_offsets, d_offsets + 1, stream) != hipSuccess) {
-    kdt_set_error("kdt_range_f64: list sort setup failed");
-    return KDT_EDEVICE;
-  }
-  void* stmp = nullptr;
-  if (!buf.get((char**)&stmp, sb)) {
-    kdt_set_error("kdt_range_f64: device allocation failed for sorting the lists");
-    return KDT_ENOMEM;
-  }
-  if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total, (int)nq,
-                                            d_offsets, d_offsets + 1, stream) != hipSuccess) {
-    kdt_set_error("kdt_range_f64: list sort failed");
-    return KDT_EDEVICE;
-  }
+  st = sort_list_rows(unsorted, d_idx, d_offsets, nq, total, stream);
+  if (st != KDT_OK) return st;
   // the scratch goes back to the pool in stream order; the caller's arrays
   // are complete when the stream reaches this point
   return KDT_OK;

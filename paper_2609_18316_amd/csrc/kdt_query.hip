@@ -10,7 +10,6 @@
 // in tree order (self queries) or by sorting external queries by the leaf
 // they fall in.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 
@@ -445,8 +444,6 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
         st = KDT_EUNSUPPORTED;
       } else if (d_idx && total > 0) {
         int32_t* unsorted = nullptr;
-        void* stmp = nullptr;
-        size_t sb = 0;
         if (!buf.get(&unsorted, (size_t)total)) {
           kdt_set_error("device allocation failed for the lists");
           st = KDT_ENOMEM;
@@ -471,22 +468,11 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
             k_range<D, true><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count,
                                                                d_off, unsorted);
           }
-          if (st != KDT_OK) {
-            // reported above
-          } else if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total,
-                                                    (int)nq, d_off, d_off + 1, stream) !=
-              hipSuccess) {
-            kdt_set_error("kdt_range: list sort setup failed");
-            st = KDT_EDEVICE;
-          } else if (!buf.get((char**)&stmp, sb)) {
-            kdt_set_error("device allocation failed for sorting the lists");
-            st = KDT_ENOMEM;
-          } else if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total,
-                                                           (int)nq, d_off, d_off + 1, stream) !=
-                     hipSuccess) {
-            kdt_set_error("kdt_range: list sort failed");
+          if (st == KDT_OK && hipGetLastError() != hipSuccess) {
+            kdt_set_error("kdt_range: list kernel launch failed");
             st = KDT_EDEVICE;
           }
+          if (st == KDT_OK) st = sort_list_rows(unsorted, d_idx, d_off, nq, total, stream);
         }
       }
     }

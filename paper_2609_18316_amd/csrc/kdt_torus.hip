@@ -13,7 +13,6 @@
 // torus ball as its query shape (trees with leaves of at most 64 points).
 // Also friends-of-friends groups on the torus (kdt_fof_torus).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <cmath>
 
@@ -322,23 +321,11 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
     k_torus_range<D, true><<<grid, kTBlock, smem, stream>>>(v, d_q, nq, r2, order, T, d_count,
                                                              d_off, unsorted);
   }
-  void* stmp = nullptr;
-  size_t sb = 0;
-  if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, sb, unsorted, d_idx, (int)total, (int)nq,
-                                            d_off, d_off + 1, stream) != hipSuccess) {
-    kdt_set_error("kdt_range: torus list sort failed");
+  if (hipGetLastError() != hipSuccess) {
+    kdt_set_error("kdt_range: torus list kernel launch failed");
     return KDT_EDEVICE;
   }
-  if (!buf.get((char**)&stmp, sb)) {
-    kdt_set_error("kdt_range: device allocation failed for sorting the lists");
-    return KDT_ENOMEM;
-  }
-  if (hipcub::DeviceSegmentedSort::SortKeys(stmp, sb, unsorted, d_idx, (int)total, (int)nq, d_off,
-                                            d_off + 1, stream) != hipSuccess) {
-    kdt_set_error("kdt_range: torus list sort failed");
-    return KDT_EDEVICE;
-  }
-  return KDT_OK;
+  return sort_list_rows(unsorted, d_idx, d_off, nq, total, stream);
 }
 
 // Friends-of-friends on the torus (Sec. 4.1 with the periodic metric).

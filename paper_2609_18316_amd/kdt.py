@@ -34,7 +34,7 @@ EXPORTS = ("kdt_build", "kdt_free", "kdt_tree_get_info", "kdt_tree_export", "kdt
            "kdt_last_error")
 # The test and measurement hooks of include/kdt_debug.h.
 DEBUG_EXPORTS = ("kdt_debug_fail_alloc", "kdt_debug_visits", "kdt_debug_valu_probe",
-                 "kdt_debug_radix_sort", "kdt_debug_exclusive_scan")
+                 "kdt_debug_radix_sort", "kdt_debug_exclusive_scan", "kdt_debug_sort_rows")
 LIB_COUNTS_PATH = os.path.join(HERE, "libkdt_counts.so")
 NOALLOC_MAX_SORTED = 1 << 22   # queries kdt_knn_noalloc can order in its static scratch
 
@@ -131,6 +131,7 @@ def load(path: str = LIB_PATH):
     lib.kdt_debug_valu_probe.argtypes = [vp, i32, i32, vp]
     lib.kdt_debug_radix_sort.argtypes = [vp, vp, i64, i32, i32, vp]
     lib.kdt_debug_exclusive_scan.argtypes = [vp, vp, i64, i32, vp]
+    lib.kdt_debug_sort_rows.argtypes = [vp, vp, vp, i64, i64, vp]
     lib.kdt_last_error.restype = C.c_char_p
     for name in EXPORTS + DEBUG_EXPORTS:
         if name not in ("kdt_last_error", "kdt_tree_perm") and hasattr(lib, name):
@@ -182,6 +183,18 @@ def exclusive_scan(values: torch.Tensor, out_bits: int = 64, stream=None) -> tor
         out = torch.empty(n, dtype=torch.int32, device=values.device)
     _check(load().kdt_debug_exclusive_scan(_ptr(values), out.data_ptr(), n, int(out_bits),
                                            _stream(stream)))
+    return out
+
+
+def sort_rows(values: torch.Tensor, offsets: torch.Tensor, stream=None) -> torch.Tensor:
+    """Test hook: the library's per-row sort of a CSR list (int32 values,
+    int64 offsets of nq + 1 entries), every row ascending."""
+    total = values.numel()
+    values = _dev(values, torch.int32, "values", (total,))
+    offsets = _dev(offsets, torch.int64, "offsets")
+    out = torch.empty(total, dtype=torch.int32, device=values.device)
+    _check(load().kdt_debug_sort_rows(_ptr(values), _ptr(out), _ptr(offsets),
+                                      offsets.numel() - 1, total, _stream(stream)))
     return out
 
 

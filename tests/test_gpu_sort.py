@@ -74,3 +74,49 @@ def test_scan_rejects_bad_width():
     dev()
     with pytest.raises(kdt.KdtError):
         kdt.exclusive_scan(torch.zeros(4, dtype=torch.int32, device=dev()), 16)
+
+
+def _rows_case(lengths, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    vals = np.empty(int(off[-1]), np.int32)
+    for r, L in enumerate(lengths):  # distinct indices per row, shuffled
+        vals[off[r]:off[r + 1]] = rng.permutation(rng.choice(1 << 24, size=L, replace=False))
+    return vals, off
+
+
+@pytest.mark.parametrize("case", ("every_size", "random_mix", "all_small", "long_rows"))
+def test_row_sort_equals_numpy(case):
+    """Every row of a CSR list ascending: the lengths span the register path
+    (<= 64), both LDS paths (<= 1024, <= 16384) and the long-row fallback,
+    with empty rows and rows of one entry in between."""
+    dev()
+    rng = np.random.Generator(np.random.PCG64(len(case)))
+    if case == "every_size":
+        lengths = [0, 1, 2, 3, 63, 64, 65, 127, 128, 129, 1023, 1024, 1025, 4096, 16383, 16384,
+                   16385, 40000, 0, 1]
+    elif case == "random_mix":
+        lengths = list(rng.geometric(1 / 60, size=20000) - 1) + [3000, 20000, 0, 900]
+    elif case == "all_small":
+        lengths = list(rng.integers(0, 65, size=100003))
+    else:
+        lengths = [70000, 5, 17000, 0, 33000]
+    vals, off = _rows_case(lengths, 5)
+    say(f"row sort {case}: {len(lengths)} rows, {len(vals)} entries")
+    got = to_host(kdt.sort_rows(torch.from_numpy(vals).to(dev()), torch.from_numpy(off).to(dev())))
+    want = vals.copy()
+    for r in range(len(lengths)):
+        want[off[r]:off[r + 1]].sort()
+    np.testing.assert_array_equal(got, want)
+
+
+def test_row_sort_empty_and_errors():
+    dev()
+    got = kdt.sort_rows(torch.zeros(0, dtype=torch.int32, device=dev()),
+                        torch.zeros(4, dtype=torch.int64, device=dev()))
+    assert got.numel() == 0
+    with pytest.raises(kdt.KdtError):  # in place
+        v = torch.zeros(4, dtype=torch.int32, device=dev())
+        o = torch.tensor([0, 4], dtype=torch.int64, device=dev())
+        kdt._check(kdt.load().kdt_debug_sort_rows(kdt._ptr(v), kdt._ptr(v), kdt._ptr(o), 1, 4,
+                                                  kdt._stream()))
