@@ -139,6 +139,16 @@ typedef struct {
                              tree-ordered deposit (kdt_p2m_tree).  Results
                              are otherwise identical.  1 with external
                              queries, or another value: KDT_EINVAL. */
+    int32_t counts_given; /* kdt_range lists (d_idx and d_offsets set), open or
+                             periodic: 1 = d_count and d_offsets already hold
+                             what the sizing call (d_idx NULL) of the same
+                             tree, queries, radius and options wrote, so the
+                             call skips the counting pass and the offset scan
+                             and only fills and sorts the lists (it still
+                             reads the total back).  Other values of d_count
+                             and d_offsets give undefined lists.  0: count
+                             again.  1 without lists, or another value:
+                             KDT_EINVAL.  Ignored by the other calls. */
 } kdt_query_opts;
 
 /* Uniform mesh for the particle-to-mesh deposit: n[0]*n[1]*n[2] cells of side

@@ -196,7 +196,7 @@ static kdt_status box_impl(const kdt_tree* tr, const float* d_lo, const float* d
     kdt_set_error("kdt_box: list kernel launch failed");
     return KDT_EDEVICE;
   }
-  const kdt_status ss = sort_list_rows(unsorted, d_idx, d_off, nq, total, stream);
+  const kdt_status ss = sort_list_rows(unsorted, d_idx, d_off, nq, total, tr->n, stream);
   if (ss != KDT_OK) return ss;
   if (hipGetLastError() != hipSuccess) {
     kdt_set_error("kdt_box: list kernel launch failed");

@@ -608,7 +608,7 @@ extern "C" kdt_status kdt_range_f64(const kdt_tree* tree, const double* d_q, int
     return st;
   }
   // every row ascending by input index
-  st = sort_list_rows(unsorted, d_idx, d_offsets, nq, total, stream);
+  st = sort_list_rows(unsorted, d_idx, d_offsets, nq, total, tree->n, stream);
   if (st != KDT_OK) return st;
   // the scratch goes back to the pool in stream order; the caller's arrays
   // are complete when the stream reaches this point

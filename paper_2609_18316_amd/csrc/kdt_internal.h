@@ -185,11 +185,12 @@ kdt_status exclusive_scan(const int32_t* in, Out* out, int64_t n, int64_t* total
 
 // Sorts every row of a CSR list ascending (kdt_rowsort.hip): row r is
 // in[off[r], off[r + 1]) and goes to the same range of out (in != out; off
-// device, nq + 1 entries, total = off[nq]).  Scratch from the stream-ordered
-// pool; waits on `stream` once.  KDT_ENOMEM, KDT_EUNSUPPORTED (total above
-// 2^31 - 1), KDT_EDEVICE, with the error set.
+// device, nq + 1 entries, total = off[nq]; every entry in [0, key_limit)).
+// Scratch from the stream-ordered pool; waits on `stream` once, twice when
+// rows above 16384 entries occur.  KDT_ENOMEM, KDT_EUNSUPPORTED (total
+// above 2^31 - 1), KDT_EDEVICE, with the error set.
 kdt_status sort_list_rows(const int32_t* in, int32_t* out, const int64_t* off, int64_t nq,
-                          int64_t total, hipStream_t stream);
+                          int64_t total, int64_t key_limit, hipStream_t stream);
 
 // *out (device) <- the number of i in [0, n) with labels[i] == i: the groups
 // of a friends-of-friends labelling (kdt_sort.hip).  scratch:

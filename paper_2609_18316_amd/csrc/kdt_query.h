@@ -664,7 +664,7 @@ kdt_status knn_torus(const kdt_tree* tr, const float* d_q, int64_t nq, int k, in
 kdt_status range_torus(const kdt_tree* tr, const float* d_q, int64_t nq, float r,
                        int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
                        int64_t* required, bool sort_q, const int32_t* given, const float* period,
-                       hipStream_t stream);
+                       bool counts_given, hipStream_t stream);
 
 // k above KDT_MAX_K: exact neighbours from a per-query ball that holds at
 // least k points, its keys sorted per query (arguments as kdt_knn; period

@@ -386,7 +386,8 @@ template <int D>
 static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, float r,
                              int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
                              int64_t* required, bool sort_q, const int32_t* given,
-                             int traversal, uint32_t split_budget, hipStream_t stream) {
+                             int traversal, uint32_t split_budget, bool counts_given,
+                             hipStream_t stream) {
   int32_t* own = nullptr;
   if (d_q && !given && sort_q && nq > 1) {
     kdt_status st = order_queries<D>(t, d_q, nq, 0, &own, stream);
@@ -400,17 +401,19 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
   // both children are pushed: at most levels + 2 entries
   const size_t rsmem = sizeof(uint32_t) * (size_t)(t->levels + 2) * kQBlock;
   kdt_status st = KDT_OK;
-  if (t->nodes)
+  if (counts_given) {
+    // the counts and offsets of the sizing call are in d_count and d_off
+  } else if (t->nodes) {
     k_range<D, false, StoredShape><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order,
                                                                      d_count, nullptr, nullptr);
-  else if (t->leaf <= 64 && traversal != 1)
-  {
+  } else if (t->leaf <= 64 && traversal != 1) {
     int cap = 0;
     const TreeView vc = count_view(v, t->leaf, &cap);
     st = range_packet_launch<D>(vc, cap, d_q, nq, r2, order, d_count, split_budget, stream);
+  } else {
+    k_range<D, false><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count, nullptr,
+                                                        nullptr);
   }
-  else
-    k_range<D, false><<<grid, kQBlock, rsmem, stream>>>(v, d_q, nq, r2, order, d_count, nullptr, nullptr);
   if (st != KDT_OK) {
     if (own) (void)hipFreeAsync(own, stream);
     return st;
@@ -419,10 +422,11 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
     PoolBuffers buf(stream);
     void* tmp = nullptr;
     int64_t total = 0;
-    if (!buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
+    if (!counts_given && !buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
       kdt_set_error("device allocation failed for the list offsets");
       st = KDT_ENOMEM;
-    } else if (exclusive_scan<int64_t>(d_count, d_off, nq, d_off + nq, tmp, stream) != KDT_OK) {
+    } else if (!counts_given &&
+               exclusive_scan<int64_t>(d_count, d_off, nq, d_off + nq, tmp, stream) != KDT_OK) {
       kdt_set_error("kdt_range: offset scan failed");
       st = KDT_EDEVICE;
     } else {
@@ -472,7 +476,7 @@ static kdt_status range_impl(const kdt_tree* t, const float* d_q, int64_t nq, fl
             kdt_set_error("kdt_range: list kernel launch failed");
             st = KDT_EDEVICE;
           }
-          if (st == KDT_OK) st = sort_list_rows(unsorted, d_idx, d_off, nq, total, stream);
+          if (st == KDT_OK) st = sort_list_rows(unsorted, d_idx, d_off, nq, total, t->n, stream);
         }
       }
     }
@@ -621,6 +625,12 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
     kdt_set_error("kdt_range: split_budget must be >= 0");
     return KDT_EINVAL;
   }
+  const bool counts_given = opts && opts->counts_given;
+  if (opts && (opts->counts_given < 0 || opts->counts_given > 1 ||
+               (counts_given && (!d_idx || !d_offsets)))) {
+    kdt_set_error("kdt_range: counts_given must be 0 or 1, and 1 needs lists (d_idx, d_offsets)");
+    return KDT_EINVAL;
+  }
   const uint32_t budget = opts ? (uint32_t)opts->split_budget : 0u;
   if (nq > INT32_MAX && d_offsets) {
     kdt_set_error("kdt_range: list mode supports at most 2^31-1 queries");
@@ -647,14 +657,14 @@ extern "C" kdt_status kdt_range(const kdt_tree* tree, const float* d_q, int64_t 
     return KDT_EUNSUPPORTED;
   if (opts && opts->period)
     return range_torus(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q,
-                       given, opts->period, stream);
+                       given, opts->period, counts_given, stream);
   const int trav = opts ? opts->traversal : 0;
   switch (tree->d) {
-    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
-    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
-    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
-    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
-    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, stream);
+    case 2: return range_impl<2>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, counts_given, stream);
+    case 3: return range_impl<3>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, counts_given, stream);
+    case 4: return range_impl<4>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, counts_given, stream);
+    case 8: return range_impl<8>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, counts_given, stream);
+    case 16: return range_impl<16>(tree, d_q, nq, r, d_count, d_offsets, d_idx, capacity, required, sort_q, given, trav, budget, counts_given, stream);
   }
   kdt_set_error("kdt_range: unsupported dimension %d", tree->d);
   return KDT_EUNSUPPORTED;

@@ -6,14 +6,17 @@
 //                     a bitonic network over the lanes (shuffles), sized to
 //                     the next power of two of the row;
 //   <= kSmallMax      in LDS by the same 64-lane workgroup (bitonic);
-//   <= kMidMax        in LDS by a 1024-lane workgroup (bitonic; 64 KiB);
-//   longer            hipCUB's segmented sort over those rows only.
+//   <= kMidMax        by a 1024-lane workgroup: runs of 16 in registers,
+//                     then LDS (bitonic; 64 KiB);
+//   longer            the library's LSD radix sort over the concatenation of
+//                     those rows, ordered by (row, entry): with one composite
+//                     key (row rank above the entry's bits) when both fit in
+//                     32 bits, else by the entry, then stably by the row.
 // A 64-lane workgroup walks chunks of 64 consecutive rows: one coalesced load
 // gives the chunk's offsets, and the next row's entries are loaded while the
 // current one is sorted.  Rows of the two larger classes are collected (by
 // row id, through counters) for the later passes.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <climits>
@@ -107,6 +110,9 @@ __global__ __launch_bounds__(64) void k_rows_small(const int32_t* __restrict__ i
   }
 }
 
+// A mid row per workgroup: each thread first sorts a run of 16 entries in
+// registers (the bitonic stages up to 16, directions taken from the entries'
+// positions), then the stages from 32 on run in LDS.
 __global__ __launch_bounds__(kMidThreads) void k_rows_mid(const int32_t* __restrict__ in,
                                                           int32_t* __restrict__ out,
                                                           const int64_t* __restrict__ off,
@@ -114,31 +120,128 @@ __global__ __launch_bounds__(kMidThreads) void k_rows_mid(const int32_t* __restr
                                                           const int32_t* __restrict__ rows) {
   __shared__ int32_t s[kMidMax];
   const uint32_t m = ctr[0];
+  const int t = threadIdx.x;
   for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
     const int64_t r = rows[i];
     const int64_t b = off[r], L = off[r + 1] - b;
-    const int P = pow2_at_least(L);
-    for (int e = threadIdx.x; e < P; e += kMidThreads) s[e] = e < L ? in[b + e] : INT_MAX;
+    const int P = max(pow2_at_least(L), 32);  // mid rows hold more than kSmallMax entries
+    if (t < P / 16) {
+      int32_t v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t e = (int64_t)t * 16 + q;
+        v[q] = e < L ? in[b + e] : INT_MAX;
+      }
+#pragma unroll
+      for (int k = 2; k <= 16; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int p = q ^ j;
+            if (p > q) {
+              const bool up = ((t * 16 + q) & k) == 0;
+              const int32_t a = v[q], c = v[p];
+              const bool sw = (a > c) == up;
+              v[q] = sw ? c : a;
+              v[p] = sw ? a : c;
+            }
+          }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) s[t * 16 + q] = v[q];
+    }
     __syncthreads();
-    lds_bitonic(s, P, threadIdx.x, kMidThreads);
-    for (int e = threadIdx.x; e < L; e += kMidThreads) out[b + e] = s[e];
+    for (int k = 32; k <= P; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int x = t; x < (P >> 1); x += kMidThreads) {
+          const int lo = ((x & ~(j - 1)) << 1) | (x & (j - 1));
+          const int hi = lo + j;
+          const int32_t a = s[lo], c = s[hi];
+          if ((a > c) == ((lo & k) == 0)) {
+            s[lo] = c;
+            s[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
+    for (int e = t; e < L; e += kMidThreads) out[b + e] = s[e];
     __syncthreads();
   }
 }
 
-__global__ void k_big_bounds(const int32_t* __restrict__ rows, uint32_t nbig,
-                             const int64_t* __restrict__ off, int64_t* __restrict__ begin,
-                             int64_t* __restrict__ end) {
+__global__ void k_big_len(const int32_t* __restrict__ rows, uint32_t nbig,
+                          const int64_t* __restrict__ off, int32_t* __restrict__ len) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbig) return;
-  begin[i] = off[rows[i]];
-  end[i] = off[rows[i] + 1];
+  if (i < nbig) len[i] = (int32_t)(off[rows[i] + 1] - off[rows[i]]);
+}
+
+// The long rows' entries are handled in chunks of kBigChunk of their
+// concatenation (row rank i owns [boff[i], boff[i+1])): every row is longer
+// than a chunk, so a chunk meets at most two rows -- the one holding its
+// first entry (a binary search over boff) and the next.
+constexpr int kBigChunk = 4096;
+
+__device__ __forceinline__ uint32_t chunk_row(const int64_t* __restrict__ boff, uint32_t nbig,
+                                              int64_t e0) {
+  __shared__ uint32_t row0;
+  if (threadIdx.x == 0) {
+    uint32_t lo = 0, hi = nbig - 1;  // the last i with boff[i] <= e0
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= e0) lo = mid; else hi = mid - 1;
+    }
+    row0 = lo;
+  }
+  __syncthreads();
+  return row0;
+}
+
+// Entries into the sort's arrays; composite: key = i << shift | entry,
+// value = entry; else key = entry, value = i.
+__global__ __launch_bounds__(256) void k_big_gather(const int32_t* __restrict__ rows,
+                                                    uint32_t nbig,
+                                                    const int64_t* __restrict__ off,
+                                                    const int64_t* __restrict__ boff, int64_t tb,
+                                                    const int32_t* __restrict__ in, int shift,
+                                                    int composite, uint32_t* __restrict__ keys,
+                                                    int32_t* __restrict__ vals) {
+  const int64_t e0 = (int64_t)blockIdx.x * kBigChunk;
+  const uint32_t i0 = chunk_row(boff, nbig, e0);
+  const int64_t split = i0 + 1 < nbig ? boff[i0 + 1] : tb;
+  for (int64_t e = e0 + threadIdx.x; e < e0 + kBigChunk && e < tb; e += 256) {
+    const uint32_t i = e < split ? i0 : i0 + 1;
+    const int32_t v = in[off[rows[i]] + (e - boff[i])];
+    keys[e] = composite ? (i << shift) | (uint32_t)v : (uint32_t)v;
+    vals[e] = composite ? v : (int32_t)i;
+  }
+}
+
+// The sorted concatenation back into each long row's range of out.
+__global__ __launch_bounds__(256) void k_big_place(const int32_t* __restrict__ rows,
+                                                   uint32_t nbig,
+                                                   const int64_t* __restrict__ off,
+                                                   const int64_t* __restrict__ boff, int64_t tb,
+                                                   const int32_t* __restrict__ sorted,
+                                                   int32_t* __restrict__ out) {
+  const int64_t e0 = (int64_t)blockIdx.x * kBigChunk;
+  const uint32_t i0 = chunk_row(boff, nbig, e0);
+  const int64_t split = i0 + 1 < nbig ? boff[i0 + 1] : tb;
+  for (int64_t e = e0 + threadIdx.x; e < e0 + kBigChunk && e < tb; e += 256) {
+    const uint32_t i = e < split ? i0 : i0 + 1;
+    out[off[rows[i]] + (e - boff[i])] = sorted[e];
+  }
+}
+
+int bits_below(int64_t limit) {  // bits of limit - 1 (at least 1)
+  int b = 1;
+  while (b < 32 && (int64_t(1) << b) < limit) ++b;
+  return b;
 }
 
 }  // namespace
 
 kdt_status sort_list_rows(const int32_t* in, int32_t* out, const int64_t* off, int64_t nq,
-                          int64_t total, hipStream_t stream) {
+                          int64_t total, int64_t key_limit, hipStream_t stream) {
   if (nq <= 0 || total <= 0) return KDT_OK;
   if (total > INT32_MAX || nq > INT32_MAX) {
     kdt_set_error("lists above 2^31-1 entries or rows are not supported");
@@ -152,7 +255,8 @@ kdt_status sort_list_rows(const int32_t* in, int32_t* out, const int64_t* off, i
     return KDT_ENOMEM;
   }
   k_zero_ctr<<<1, 64, 0, stream>>>(ctr);
-  const unsigned gs = (unsigned)std::min<int64_t>((nq + 63) / 64, 256 * 32);
+  // twice the resident waves: the short rows wait on memory, not on the ALUs
+  const unsigned gs = (unsigned)std::min<int64_t>((nq + 63) / 64, 256 * 64);
   k_rows_small<<<gs, 64, 0, stream>>>(in, out, off, nq, ctr, mid, big);
   k_rows_mid<<<512, kMidThreads, 0, stream>>>(in, out, off, ctr, mid);
   uint32_t h[2] = {0u, 0u};
@@ -164,26 +268,53 @@ kdt_status sort_list_rows(const int32_t* in, int32_t* out, const int64_t* off, i
   }
   const uint32_t nbig = h[1];
   if (nbig == 0) return KDT_OK;
-  // rows above kMidMax entries: hipCUB's segmented sort over those rows
-  int64_t *bb = nullptr, *be = nullptr;
-  void* tmp = nullptr;
-  size_t tb = 0;
-  if (!buf.get(&bb, nbig) || !buf.get(&be, nbig)) {
+  // rows above kMidMax entries: their concatenation through the radix sort
+  int32_t* len = nullptr;
+  int64_t* boff = nullptr;
+  void* scan_tmp = nullptr;
+  if (!buf.get(&len, nbig) || !buf.get(&boff, (size_t)nbig + 1) ||
+      !buf.get((char**)&scan_tmp, scan_scratch_bytes(nbig))) {
     kdt_set_error("device allocation failed for sorting the lists");
     return KDT_ENOMEM;
   }
-  k_big_bounds<<<(nbig + 255) / 256, 256, 0, stream>>>(big, nbig, off, bb, be);
-  if (hipcub::DeviceSegmentedSort::SortKeys(nullptr, tb, in, out, (int)total, (int)nbig, bb, be,
-                                            stream) != hipSuccess) {
+  k_big_len<<<(nbig + 255) / 256, 256, 0, stream>>>(big, nbig, off, len);
+  int64_t tb = 0;
+  if (exclusive_scan<int64_t>(len, boff, nbig, boff + nbig, scan_tmp, stream) != KDT_OK ||
+      hipMemcpyAsync(&tb, boff + nbig, sizeof(tb), hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
     kdt_set_error("sorting the long list rows failed");
     return KDT_EDEVICE;
   }
-  if (!buf.get((char**)&tmp, tb)) {
-    kdt_set_error("device allocation failed for sorting the lists");
+  uint32_t* keys[2] = {nullptr, nullptr};
+  int32_t* vals[2] = {nullptr, nullptr};
+  void* rs_tmp = nullptr;
+  if (!buf.get(&keys[0], (size_t)tb) || !buf.get(&keys[1], (size_t)tb) ||
+      !buf.get(&vals[0], (size_t)tb) || !buf.get(&vals[1], (size_t)tb) ||
+      !buf.get((char**)&rs_tmp, radix_sort_scratch_bytes(tb))) {
+    kdt_set_error("device allocation failed for sorting the long list rows");
     return KDT_ENOMEM;
   }
-  if (hipcub::DeviceSegmentedSort::SortKeys(tmp, tb, in, out, (int)total, (int)nbig, bb, be,
-                                            stream) != hipSuccess) {
+  const int kb = bits_below(key_limit), rb = bits_below(nbig);
+  const bool composite = kb + rb <= 32;
+  const unsigned gc = (unsigned)((tb + kBigChunk - 1) / kBigChunk);
+  k_big_gather<<<gc, 256, 0, stream>>>(big, nbig, off, boff, tb, in, kb, composite ? 1 : 0,
+                                       keys[0], vals[0]);
+  const int32_t* sorted = nullptr;
+  if (composite) {
+    const int c = radix_sort_pairs(keys, vals, tb, 0, kb + rb, rs_tmp, stream);
+    sorted = vals[c];
+  } else {
+    // by the entry, then stably by the row (the arrays swap roles)
+    const int a = radix_sort_pairs(keys, vals, tb, 0, kb, rs_tmp, stream);
+    uint32_t* k2[2] = {reinterpret_cast<uint32_t*>(vals[a]),
+                       reinterpret_cast<uint32_t*>(vals[a ^ 1])};
+    int32_t* v2[2] = {reinterpret_cast<int32_t*>(keys[a]), reinterpret_cast<int32_t*>(keys[a ^ 1])};
+    const int c = radix_sort_pairs(k2, v2, tb, 0, rb, rs_tmp, stream);
+    sorted = v2[c];
+  }
+  k_big_place<<<gc, 256, 0, stream>>>(big, nbig, off, boff, tb, sorted, out);
+  if (hipGetLastError() != hipSuccess) {
     kdt_set_error("sorting the long list rows failed");
     return KDT_EDEVICE;
   }
@@ -202,5 +333,5 @@ extern "C" kdt_status kdt_debug_sort_rows(const int32_t* d_in, int32_t* d_out,
                   "[0, 2^31-1]");
     return KDT_EINVAL;
   }
-  return kdt::sort_list_rows(d_in, d_out, d_off, nq, total, stream);
+  return kdt::sort_list_rows(d_in, d_out, d_off, nq, total, int64_t(1) << 31, stream);
 }

@@ -233,7 +233,7 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
                                    int32_t* d_count, int64_t* d_off, int32_t* d_idx,
                                    int64_t capacity, int64_t* required, bool sort_q,
                                    const int32_t* given, const float* period,
-                                   hipStream_t stream) {
+                                   bool counts_given, hipStream_t stream) {
   PoolBuffers buf(stream);
   Torus<D> T;
   kdt_status st = torus_setup<D>(tr, d_q, nq, period, buf, &T, stream, "kdt_range");
@@ -258,7 +258,9 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   const float r2 = r * r;
   const unsigned grid = (unsigned)((nq + kTBlock - 1) / kTBlock);
   const size_t smem = sizeof(uint32_t) * (size_t)(tr->levels + 2) * kTBlock;
-  if (tr->leaf <= 64) {
+  if (counts_given) {
+    // the counts and offsets of the sizing call are in d_count and d_off
+  } else if (tr->leaf <= 64) {
     int cap = 0;
     const TreeView vc = count_view(v, tr->leaf, &cap);
     st = torus_range_packet_launch<D>(vc, cap, d_q, nq, r2, T, order, d_count, 0u, stream);
@@ -273,11 +275,12 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
   }
   if (!d_off) return KDT_OK;
   void* tmp = nullptr;
-  if (!buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
+  if (!counts_given && !buf.get((char**)&tmp, scan_scratch_bytes(nq))) {
     kdt_set_error("kdt_range: device allocation failed for the list offsets");
     return KDT_ENOMEM;
   }
-  if (exclusive_scan<int64_t>(d_count, d_off, nq, d_off + nq, tmp, stream) != KDT_OK) {
+  if (!counts_given &&
+      exclusive_scan<int64_t>(d_count, d_off, nq, d_off + nq, tmp, stream) != KDT_OK) {
     kdt_set_error("kdt_range: torus offset scan failed");
     return KDT_EDEVICE;
   }
@@ -325,7 +328,7 @@ static kdt_status torus_range_impl(const kdt_tree* tr, const float* d_q, int64_t
     kdt_set_error("kdt_range: torus list kernel launch failed");
     return KDT_EDEVICE;
   }
-  return sort_list_rows(unsorted, d_idx, d_off, nq, total, stream);
+  return sort_list_rows(unsorted, d_idx, d_off, nq, total, tr->n, stream);
 }
 
 // Friends-of-friends on the torus (Sec. 4.1 with the periodic metric).
@@ -508,13 +511,13 @@ kdt_status knn_torus(const kdt_tree* tr, const float* d_q, int64_t nq, int k, in
 kdt_status range_torus(const kdt_tree* tr, const float* d_q, int64_t nq, float r,
                        int32_t* d_count, int64_t* d_off, int32_t* d_idx, int64_t capacity,
                        int64_t* required, bool sort_q, const int32_t* given, const float* period,
-                       hipStream_t stream) {
+                       bool counts_given, hipStream_t stream) {
   switch (tr->d) {
-    case 2: return torus_range_impl<2>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
-    case 3: return torus_range_impl<3>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
-    case 4: return torus_range_impl<4>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
-    case 8: return torus_range_impl<8>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
-    case 16: return torus_range_impl<16>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, stream);
+    case 2: return torus_range_impl<2>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, counts_given, stream);
+    case 3: return torus_range_impl<3>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, counts_given, stream);
+    case 4: return torus_range_impl<4>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, counts_given, stream);
+    case 8: return torus_range_impl<8>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, counts_given, stream);
+    case 16: return torus_range_impl<16>(tr, d_q, nq, r, d_count, d_off, d_idx, capacity, required, sort_q, given, period, counts_given, stream);
   }
   kdt_set_error("kdt_range: unsupported dimension %d", tr->d);
   return KDT_EUNSUPPORTED;

@@ -65,7 +65,7 @@ def _periods(period, d: int):
 class QueryOpts(C.Structure):
     _fields_ = [("sort_queries", C.c_int32), ("traversal", C.c_int32), ("order", C.c_void_p),
                 ("split_budget", C.c_int32), ("period", C.POINTER(C.c_float)),
-                ("tree_rows", C.c_int32)]
+                ("tree_rows", C.c_int32), ("counts_given", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -422,6 +422,7 @@ class Tree:
         _check(lib.kdt_range(self._h, _ptr(queries), nq, float(r), _ptr(count), _ptr(offsets),
                              None, 0, C.byref(req), C.byref(opts), _stream(stream)))
         idx = torch.empty(max(req.value, 1), dtype=torch.int32, device=self.device)
+        opts.counts_given = 1  # the sizing call above wrote count and offsets
         _check(lib.kdt_range(self._h, _ptr(queries), nq, float(r), _ptr(count), _ptr(offsets),
                              _ptr(idx), idx.numel(), C.byref(req), C.byref(opts),
                              _stream(stream)))

@@ -200,6 +200,48 @@ def test_range_capacity_error_reports_required():
     assert req.value == int(oracle.Tree(x, 16).range(x[:100], 0.1).sum())
 
 
+def test_range_lists_with_and_without_given_counts():
+    """The list call after a sizing call (counts_given = 1, what Tree.range
+    does) and a call that counts again give the oracle's lists; counts_given
+    without lists is refused."""
+    dev()
+    import ctypes as C
+    x = cases.points("uniform", 20011, 3, seed=3)
+    q = cases.points("uniform", 3001, 3, seed=4)
+    t = kdt.build(to_dev(x), leaf_size=16)
+    oc, ooff, olst = oracle.Tree(x, 16).range(q, 0.05, lists=True)
+    qd = to_dev(q)
+    for given, period in ((0, None), (1, None), (0, 1.0), (1, 1.0)):
+        say(f"lists counts_given={given} period={period}")
+        count = to_dev(np.zeros(3001, np.int32))
+        off = to_dev(np.zeros(3002, np.int64))
+        req = C.c_int64(0)
+        per = kdt._periods(period, 3)
+        opts = kdt.QueryOpts(1, 0, None, 0, per, 0, 0)
+        kdt._check(kdt.load().kdt_range(t._h, qd.data_ptr(), 3001, 0.05, count.data_ptr(),
+                                        off.data_ptr(), None, 0, C.byref(req), C.byref(opts),
+                                        kdt._stream()))
+        idx = to_dev(np.zeros(req.value, np.int32))
+        opts.counts_given = given
+        kdt._check(kdt.load().kdt_range(t._h, qd.data_ptr(), 3001, 0.05, count.data_ptr(),
+                                        off.data_ptr(), idx.data_ptr(), req.value, C.byref(req),
+                                        C.byref(opts), kdt._stream()))
+        if period is None:
+            np.testing.assert_array_equal(to_host(count), oc)
+            np.testing.assert_array_equal(to_host(off), ooff)
+            np.testing.assert_array_equal(to_host(idx), olst)
+        else:
+            pc, poff, plst = oracle.range_brute(x, q, 0.05, lists=True, period=1.0)
+            np.testing.assert_array_equal(to_host(off), poff)
+            np.testing.assert_array_equal(to_host(idx), plst)
+    opts = kdt.QueryOpts(1, 0, None, 0, None, 0, 1)
+    count = to_dev(np.zeros(3001, np.int32))
+    with pytest.raises(kdt.KdtError) as e:
+        kdt._check(kdt.load().kdt_range(t._h, qd.data_ptr(), 3001, 0.05, count.data_ptr(), None,
+                                        None, 0, None, C.byref(opts), kdt._stream()))
+    assert e.value.status == kdt.KDT_EINVAL
+
+
 @pytest.mark.parametrize("d", (2, 3, 8))
 @pytest.mark.parametrize("leaf", (16, 100))  # wave packets / one traversal per lane
 def test_fof_matches_oracle(d, leaf):
