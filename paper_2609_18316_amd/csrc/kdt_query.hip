@@ -321,9 +321,11 @@ static kdt_status knn_dispatch(const kdt_tree* t, const float* d_q, int64_t nq, 
                                hipStream_t stream) {
   TreeView v = view_of(t);
   // the k-th distance alone (smoothing lengths) reads the tree at 32-point
-  // nodes, as the counts do: 2^24 self queries at k = 32 took 19.0 ms on
-  // 16-point leaves, 18.6 ms on 32-point nodes of the same tree
-  if (mode != 0 && !t->nodes) {
+  // nodes, as the counts do, when k is above 16: 2^24 self queries at k = 32
+  // took 19.0 ms on 16-point leaves, 18.6 ms on 32-point nodes of the same
+  // tree; at k = 8 the tree's own 24-point leaves are faster (8.7 against
+  // 9.9 ms)
+  if (mode != 0 && !t->nodes && k > 16) {
     int cap = 0;
     v = count_view(v, t->leaf, &cap);
   }
