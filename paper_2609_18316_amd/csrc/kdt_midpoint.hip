@@ -129,33 +129,57 @@ __device__ __forceinline__ int longest_axis(const float lo[D], const float hi[D]
 }  // namespace
 
 // AoS -> SoA copy, identity order, finiteness flag and the root's box keys.
+// Grid-stride: each workgroup folds its points' keys in registers, then in
+// LDS, and adds one atomic per key and workgroup (one per wave and key made
+// 2^24 points take 18 ms, the atomics on the 2d keys serialising).
 template <int D>
 __global__ __launch_bounds__(kMBlock) void k_mid_ingest(const float* __restrict__ pts, int64_t n,
                                                         float* __restrict__ x,
                                                         int32_t* __restrict__ perm,
                                                         uint32_t* __restrict__ rootkeys,
                                                         int32_t* __restrict__ bad) {
-  const int64_t i = (int64_t)blockIdx.x * kMBlock + threadIdx.x;
-  const bool in = i < n;
-  bool fin = true;
-  float v[D];
+  constexpr int kW = kMBlock / 64;
+  __shared__ uint32_t red[2 * D][kW];
+  uint32_t mn[D], mx[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    v[a] = in ? pts[i * D + a] : 0.0f;
-    fin &= isfinite(v[a]);
-    if (in) x[(int64_t)a * n + i] = v[a];
+    mn[a] = 0xFFFFFFFFu;
+    mx[a] = 0u;
   }
-  if (in) perm[i] = (int32_t)i;
-  if (in && !fin) atomicOr(bad, 1);
-  const bool any = __any(in);
+  bool fin = true;
+  for (int64_t i = (int64_t)blockIdx.x * kMBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kMBlock) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const float v = pts[i * D + a];
+      fin &= isfinite(v);
+      x[(int64_t)a * n + i] = v;
+      const uint32_t k = fkey(v);
+      mn[a] = min(mn[a], k);
+      mx[a] = max(mx[a], k);
+    }
+    perm[i] = (int32_t)i;
+  }
+  if (!fin) atomicOr(bad, 1);
+  const int w = threadIdx.x >> 6;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const uint32_t mn = wave_min32(in ? fkey(v[a]) : 0xFFFFFFFFu);
-    const uint32_t mx = wave_max32(in ? fkey(v[a]) : 0u);
-    if (lane_id() == 0 && any) {
-      atomicMin(rootkeys + a, mn);
-      atomicMax(rootkeys + D + a, mx);
+    const uint32_t wmn = wave_min32(mn[a]);
+    const uint32_t wmx = wave_max32(mx[a]);
+    if (lane_id() == 0) {
+      red[a][w] = wmn;
+      red[D + a][w] = wmx;
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * D) {
+    const int j = threadIdx.x;
+    uint32_t v = red[j][0];
+    for (int q = 1; q < kW; ++q) v = j < D ? min(v, red[j][q]) : max(v, red[j][q]);
+    if (j < D)
+      atomicMin(rootkeys + j, v);
+    else
+      atomicMax(rootkeys + j, v);
   }
 }
 
@@ -563,7 +587,8 @@ kdt_status build_midpoint_d(const float* d_pts, int64_t n, int leaf, bool check,
   k_mid_fill_i32<<<1, kMBlock, 0, stream>>>(flags, 64, 0);
   k_mid_fill_i32<<<1, kMBlock, 0, stream>>>(reinterpret_cast<int32_t*>(rootkeys), D, -1);
   k_mid_fill_i32<<<1, kMBlock, 0, stream>>>(reinterpret_cast<int32_t*>(rootkeys) + D, D, 0);
-  k_mid_ingest<D><<<gn, kMBlock, 0, stream>>>(d_pts, n, X[0], Pm[0], rootkeys, bad);
+  k_mid_ingest<D><<<std::min(gn, 2048u), kMBlock, 0, stream>>>(d_pts, n, X[0], Pm[0], rootkeys,
+                                                               bad);
 
   NodeArrays na;
   struct Guard {
