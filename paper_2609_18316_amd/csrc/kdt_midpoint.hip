@@ -357,6 +357,10 @@ __global__ __launch_bounds__(kMBlock) void k_mid_scatter(
 }
 
 constexpr int kBoxBlock = 1024;
+// Levels of at most kRunBoxChildren children take their boxes from the
+// children's runs, with about kRunBoxBlocks workgroups in all.
+constexpr int64_t kRunBoxChildren = 2048;
+constexpr int64_t kRunBoxBlocks = 4096;
 
 // Per point of the new order: the children's tight boxes.  A child is one run
 // of positions, so a wave's points fall in one or two children; partial
@@ -438,6 +442,61 @@ __global__ void k_mid_reset_keys(int64_t mc, uint32_t* __restrict__ ckeys) {
   const int64_t j = (int64_t)blockIdx.x * kMBlock + threadIdx.x;
   if (j >= mc * 2 * D) return;
   ckeys[j] = (j % (2 * D)) < D ? 0xFFFFFFFFu : 0u;
+}
+
+// The children's boxes at the top levels (few children, long runs): the
+// runs are known from the children's node records, so G workgroups take a
+// slice of each child's run, fold it in registers and LDS, and add one
+// atomic per key; with one atomic per workgroup and child in k_mid_boxes,
+// the 16 384 workgroups of a 2^24-point level queued on the same few keys.
+template <int D>
+__global__ __launch_bounds__(kBoxBlock) void k_mid_boxes_runs(int64_t n,
+                                                              const float* __restrict__ x,
+                                                              const int4* __restrict__ node,
+                                                              int64_t node_base,
+                                                              uint32_t* __restrict__ ckeys) {
+  constexpr int W = kBoxBlock / 64;
+  __shared__ uint32_t red[2 * D][W];
+  const int c = blockIdx.y;
+  const int4 r = node[node_base + c];
+  const int64_t len = (int64_t)r.z - r.y;
+  const int64_t s0 = r.y + len * blockIdx.x / gridDim.x;
+  const int64_t s1 = r.y + len * (blockIdx.x + 1) / gridDim.x;
+  uint32_t mn[D], mx[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    mn[a] = 0xFFFFFFFFu;
+    mx[a] = 0u;
+  }
+  for (int64_t i = s0 + threadIdx.x; i < s1; i += kBoxBlock) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const uint32_t k = fkey(x[(int64_t)a * n + i]);
+      mn[a] = min(mn[a], k);
+      mx[a] = max(mx[a], k);
+    }
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const uint32_t wmn = wave_min32(mn[a]);
+    const uint32_t wmx = wave_max32(mx[a]);
+    if (lane_id() == 0) {
+      red[a][w] = wmn;
+      red[D + a][w] = wmx;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * D && s1 > s0) {
+    const int j = threadIdx.x;
+    uint32_t v = red[j][0];
+    for (int q = 1; q < W; ++q) v = j < D ? min(v, red[j][q]) : max(v, red[j][q]);
+    uint32_t* k = ckeys + (int64_t)c * 2 * D;
+    if (j < D)
+      atomicMin(k + j, v);
+    else
+      atomicMax(k + j, v);
+  }
 }
 
 // Per child slot: its box; 1 in act[] if it is split at the next level.
@@ -686,7 +745,13 @@ kdt_status build_midpoint_d(const float* d_pts, int64_t n, int leaf, bool check,
                                                  X[1 - cur], Pm[1 - cur], cid);
     cur = 1 - cur;
     k_mid_reset_keys<D><<<gk, kMBlock, 0, stream>>>(2 * m, ckeys);
-    k_mid_boxes<D><<<gb, kBoxBlock, 0, stream>>>(n, X[cur], cid, ckeys);
+    if (2 * m <= kRunBoxChildren) {
+      const unsigned G = (unsigned)std::max<int64_t>(1, kRunBoxBlocks / (2 * m));
+      k_mid_boxes_runs<D><<<dim3(G, (unsigned)(2 * m)), kBoxBlock, 0, stream>>>(
+          n, X[cur], na.node, node_base, ckeys);
+    } else {
+      k_mid_boxes<D><<<gb, kBoxBlock, 0, stream>>>(n, X[cur], cid, ckeys);
+    }
     k_mid_children<D><<<gc, kMBlock, 0, stream>>>((int)(2 * m), ckeys, node_base, leaf, na.node,
                                                   na.box, act);
     if (exclusive_scan<int32_t>(act, pos, 2 * m, nullptr, cscan_tmp, stream) != KDT_OK) {
