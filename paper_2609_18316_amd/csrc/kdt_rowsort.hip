@@ -188,7 +188,10 @@ __device__ __forceinline__ uint32_t chunk_row(const int64_t* __restrict__ boff, 
     uint32_t lo = 0, hi = nbig - 1;  // the last i with boff[i] <= e0
     while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) >> 1;
-      if (boff[mid] <= e0) lo = mid; else hi = mid - 1;
+      if (boff[mid] <= e0)
+        lo = mid;
+      else
+        hi = mid - 1;
     }
     row0 = lo;
   }
