@@ -213,3 +213,46 @@ def test_unordered_calls_above_the_self_ordering_size():
     gm, gx = to_host(gm).astype(np.float64), to_host(gx).astype(np.float64)
     assert (np.abs(gm - om) <= 1e-5 * np.maximum(np.abs(om), np.abs(om).mean())).all()
     assert np.linalg.norm(gx - ox) <= 1e-4 * np.linalg.norm(ox)
+
+
+def test_adjoint_against_central_differences_of_the_forward():
+    """dL/dx and dL/dm of the autograd function against central differences
+    of the GPU forward itself (L = sum g rho, h held fixed), for particles
+    away from the mesh faces: the M4 weights are twice differentiable, and
+    cells entering or leaving a support do so at zero weight and slope, so
+    the differences converge; the float32 mesh limits them to about 1e-6 of
+    L, far below the 1e-2 relative tolerance used here."""
+    dev()
+    cells, n = 32, 64
+    rng = np.random.Generator(np.random.PCG64(21))
+    x = (0.3 + 0.4 * rng.random((n, 3))).astype(np.float32)
+    m = (0.5 + rng.random(n)).astype(np.float32)
+    h = (rng.random(n) * 3.0 / cells).astype(np.float32)  # H from one to three cells
+    shape, lo, cell = (cells,) * 3, (0.0, 0.0, 0.0), 1.0 / cells
+    g = to_dev(rng.standard_normal(shape).astype(np.float32))
+    hd = to_dev(h)
+
+    def loss(xa, ma):
+        rho = kdt.p2m(to_dev(xa), to_dev(ma), hd, lo, cell, shape)
+        return float((g.double() * rho.double()).sum())
+
+    xt = to_dev(x).requires_grad_(True)
+    mt = to_dev(m).requires_grad_(True)
+    rho = kdt.P2M.apply(xt, mt, hd, (lo, cell, shape, None))
+    (g * rho).sum().backward()
+    gx, gm = to_host(xt.grad).astype(np.float64), to_host(mt.grad).astype(np.float64)
+    eps = np.float32(2e-3 * cell)
+    for i in (0, 7, 23, 41, 63):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, a] += eps
+            xm[i, a] -= eps
+            fd = (loss(xp, m) - loss(xm, m)) / (float(xp[i, a]) - float(xm[i, a]))
+            say(f"particle {i} axis {a}: adjoint {gx[i, a]:.6g}, central difference {fd:.6g}")
+            assert abs(fd - gx[i, a]) <= 1e-2 * max(abs(gx[i, a]), 1e-2 * np.abs(gx).max())
+        # L is linear in the masses: the difference is exact up to rounding
+        mp, mm = m.copy(), m.copy()
+        mp[i] += np.float32(0.25)
+        mm[i] -= np.float32(0.25)
+        fd = (loss(x, mp) - loss(x, mm)) / (float(mp[i]) - float(mm[i]))
+        assert abs(fd - gm[i]) <= 1e-4 * max(abs(gm[i]), np.abs(gm).max())
