@@ -55,48 +55,75 @@ struct LeafReader {
 //
 // In high dimension almost every leaf is visited and the scan -- 64 queries
 // against up to 64 points -- is a dense contraction.  The filter computes
-// every query-point dot product with fp32 MFMA (v_mfma_f32_16x16x4f32: 16
-// blocks of 16 x 16, d/4 steps each) and marks point i for query q.
+// every query-point dot product on the matrix cores and marks point i for
+// query q.
 //
 // Everything is first moved to a centre c, the wave's first active query
-// (wave-uniform): q' = fl(q - c), p' = fl(p - c).  With s = |q'|^2 + |p'|^2
-// (computed), point i is marked when
-//   !( (1 - 2^-16) s - 2 q'.p'  >  (1 + 2^-16) worst_q + 2^-100 )  or  !(s < 2^125),
+// (wave-uniform): q' = fl(q - c), p' = fl(p - c), in float32.  Each operand
+// value v is then split into two bf16 values, v_hi = bf16(v) (round to
+// nearest even) and v_lo = bf16(v - v_hi) (v - v_hi is exact in float32),
+// and the dot product is taken as three bf16 products accumulated in float32
+// (v_mfma_f32_16x16x16_bf16: q_hi.p_hi + q_hi.p_lo + q_lo.p_hi, the 16
+// coordinates of a block in one step; d = 8 pads with zeros).  With
+// s = |q'|^2 + |p'|^2 (computed in float32), point i is marked when
+//   !( (1 - 2^-13) s - 2 q'.p'  >  (1 + 2^-16) worst_q + 2^-100 )  or  !(s < 2^125),
 // worst_q being the query's current k-th squared distance.
 //
-// Why no candidate is lost.  While s < 2^125 no partial sum of the norms or
-// of the dot product can overflow (each is at most s), and the expansion
-// (dot product, norms, combination, d products and sums in fp32 in any
-// order) stays within (3d + 8) u s of |q' - p'|^2, u = 2^-24.  The
-// recentring moves each axis of q' - p' by at most u (|q'_a| + |p'_a|)
-// against q - p, which changes the squared length by at most 4 u s (a little
-// more, by a factor 1 + O(u)).  The exact float32 distance of the insertion
-// pass is within (d + 2) u of |q - p|^2.  The relative margins are 256 u of s
-// and of worst_q, more than (3d + 12) + (d + 2) = 78 u at d = 16, and the
-// absolute term covers denormal products a matrix core may flush.  When s
-// reaches 2^125, or any value is NaN, the point is marked without a test.
-// So every point that can enter the list is marked, and the insertion pass,
+// Why no candidate is lost.  With u_b = 2^-8 (bf16) the split leaves
+// |v - v_hi - v_lo| <= u_b^2 |v| and |v_lo| <= u_b (1 + u_b) |v|, so per axis
+// |q'p' - (q_hi p_hi + q_hi p_lo + q_lo p_hi)| <= 3.01 * 2^-16 |q'||p'|, and
+// over the axes 3.01 * 2^-16 |q'||p'| <= 1.51 * 2^-16 s.  The 48 products are
+// exact in float32; their accumulation in any order adds at most 48 u of
+// their absolute sum, 0.1 * 2^-16 s (u = 2^-24).  So 2 q'.p' is within
+// 3.22 * 2^-16 s.  The rest of the test (norms, combination, the recentring
+// that moves each axis of q' - p' by at most u (|q'_a| + |p'_a|), and the
+// exact float32 distance of the insertion pass) stays within (3d + 14) u s
+// and (d + 2) u worst, below 0.25 * 2^-16 s at d = 16.  The relative
+// margins are 8 * 2^-16 of s and 2^-16 of worst, so more than twice the
+// total.  Operands a matrix core flushes to zero (bf16 or float32 values
+// below 2^-126) change the dot product by at most 2^-123 max(1, s), covered
+// by the 2^-100 absolute term and the relative margin.  While s < 2^125 no
+// partial sum overflows; at or above it, or with any value NaN (a split of
+// an infinite value gives one), the point is marked without a test.  So
+// every point that can enter the list is marked, and the insertion pass,
 // which recomputes the exact distance from the original coordinates, keeps
 // the results bit-identical.  The centre keeps s near the squared size of
 // the region the wave works in, so far from the origin (coordinates of
 // 1e18 and beyond) the filter still prunes instead of marking everything.
 //
-// MFMA lane layout (16x16x4 f32): lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16] and receives D[4 (l / 16) + r][l % 16] in register r.
-// Rows are leaf points, columns queries.
+// MFMA lane layout (16x16x16 bf16, checked on the device): lane l supplies
+// A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16] for j = 0..3 and
+// receives D[4 (l / 16) + r][l % 16] in register r.  Rows are leaf points,
+// columns queries.
 
 typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef short v4s_t __attribute__((ext_vector_type(4)));
+
+// The bf16 bits of v rounded to nearest even (NaN to a quiet NaN, values
+// past the bf16 range to infinity), as the high half of a float32.
+__device__ __forceinline__ uint32_t bf16_rne_bits(float v) {
+  const uint32_t u = __float_as_uint(v);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC00000u;
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+}
+
+// v = hi + lo + e with hi = bf16(v), lo = bf16(v - hi), |e| <= 2^-16 |v|.
+__device__ __forceinline__ void split_bf16(float v, short& hi, short& lo) {
+  const uint32_t h = bf16_rne_bits(v);
+  const uint32_t l = bf16_rne_bits(v - __uint_as_float(h));
+  hi = (short)(h >> 16);
+  lo = (short)(l >> 16);
+}
 
 template <int D>
 struct DotFilter {
-  static constexpr bool kOn = D >= 8 && D % 4 == 0;
-  static constexpr int KS = D / 4 > 0 ? D / 4 : 1;  // MFMA k-steps
-  float bq[4][KS];  // B operands: coordinate 4 s + l / 16 of query 16 qj + l % 16, minus c
-  float nq[4];      // |q - c|^2 of query 16 qj + l % 16
-  float c[D];       // the centre (wave-uniform)
-  float cs[KS];     // c[4 s + l / 16]: the centre on this lane's operand slots
-  float* np;        // LDS [64]: |p - c|^2 of the open leaf's points
-  uint64_t* mb;     // LDS [4][4][16]: partial marks on their way to the query's lane
+  static constexpr bool kOn = D == 8 || D == 16;
+  v4s_t bhi[4], blo[4];  // B operands: coordinates 4 (l / 16) + j of query 16 qj + l % 16, minus c
+  float nq[4];           // |q - c|^2 of query 16 qj + l % 16
+  float c[D];            // the centre (wave-uniform)
+  float cs[4];           // c[4 (l / 16) + j]: the centre on this lane's operand slots (0 past d)
+  float* np;             // LDS [64]: |p - c|^2 of the open leaf's points
+  uint64_t* mb;          // LDS [4][4][16]: partial marks on their way to the query's lane
 
   // LDS of one wave: the leaf slice (also the query staging area), then np
   // and mb.  `leaf` is the tree's leaf size.
@@ -125,7 +152,10 @@ struct DotFilter {
     for (int a = 0; a < D; ++a)
       c[a] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stage[first * D + a])));
 #pragma unroll
-    for (int s = 0; s < KS; ++s) cs[s] = stage[first * D + 4 * s + (l >> 4)];
+    for (int j = 0; j < 4; ++j) {
+      const int k = 4 * (l >> 4) + j;
+      cs[j] = k < D ? stage[first * D + k] : 0.0f;
+    }
     float n2 = 0.0f;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -137,8 +167,14 @@ struct DotFilter {
 #pragma unroll
     for (int qj = 0; qj < 4; ++qj) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s)
-        bq[qj][s] = stage[(16 * qj + (l & 15)) * D + 4 * s + (l >> 4)] - cs[s];
+      for (int j = 0; j < 4; ++j) {
+        const int k = 4 * (l >> 4) + j;
+        const float v = k < D ? stage[(16 * qj + (l & 15)) * D + k] - cs[j] : 0.0f;
+        short h, lo;
+        split_bf16(v, h, lo);
+        bhi[qj][j] = h;
+        blo[qj][j] = lo;
+      }
       nq[qj] = np[16 * qj + (l & 15)];
     }
     wave_sync();
@@ -167,9 +203,16 @@ struct DotFilter {
 #pragma unroll
     for (int pi = 0; pi < 4; ++pi) {
       if (16 * pi >= cnt) break;
-      float ap[KS];
+      v4s_t ahi, alo;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) ap[s] = leaf[(16 * pi + (l & 15)) * S + 4 * s + (l >> 4)] - cs[s];
+      for (int j = 0; j < 4; ++j) {
+        const int k = 4 * (l >> 4) + j;
+        const float v = k < D ? leaf[(16 * pi + (l & 15)) * S + k] - cs[j] : 0.0f;
+        short h, lo;
+        split_bf16(v, h, lo);
+        ahi[j] = h;
+        alo[j] = lo;
+      }
       const int row0 = 16 * pi + 4 * (l >> 4);
       float npv[4];
 #pragma unroll
@@ -177,12 +220,13 @@ struct DotFilter {
 #pragma unroll
       for (int qj = 0; qj < 4; ++qj) {
         v4f_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[s], bq[qj][s], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo[qj], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi[qj], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi[qj], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const float ns = nq[qj] + npv[r];
-          const float lhs = ns * (1.0f - 0x1p-16f) - 2.0f * acc[r];
+          const float lhs = ns * (1.0f - 0x1p-13f) - 2.0f * acc[r];
           // unordered compares (NaN) and norms too large to trust mark the point
           const bool mk = !(lhs > thr[qj]) || !(ns < 0x1p125f);
           m[qj] |= (uint64_t)mk << (row0 + r);

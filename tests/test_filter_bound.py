@@ -1,23 +1,25 @@
 """The candidate filter of the wave kNN in d = 8 and 16 (matrix-core dot
-products, a rounding margin) emulated on the host in float32: no point whose
-exact float32 squared distance is within a query's current k-th distance may
-go unmarked, at any magnitude of the coordinates.
+products of bf16 hi/lo splits, a rounding margin) emulated on the host: no
+point whose exact float32 squared distance is within a query's current k-th
+distance may go unmarked, at any magnitude of the coordinates.
 
 The emulation follows the kernel's arithmetic step by step (centre = the
-wave's first active query, recentred operands, norms, dot product, the margin
-test and the overflow guard).  The dot product of a matrix core has no fixed
-summation order, so three orders are tried: left to right in float32, pairs
-within blocks of four, and exact then rounded once.  Marks only grow with the
-threshold, so testing every pair at worst = its own exact distance covers
-every list state.  Copies of the filter without the centre, and without the
-guard, are checked to fail on the same inputs, so the test can tell them
-apart.
+wave's first active query, recentred float32 operands, norms, each operand
+split into v_hi = bf16(v) and v_lo = bf16(v - v_hi) by round to nearest
+even, the three products q_hi.p_hi + q_hi.p_lo + q_lo.p_hi accumulated in
+float32, the margin test and the overflow guard).  The accumulation of a
+matrix core has no fixed order, so three orders are tried: left to right in
+float32, pairs within blocks of four, and exact then rounded once.  Marks
+only grow with the threshold, so testing every pair at worst = its own exact
+distance covers every list state.  Copies of the filter without the centre,
+without the guard, and without the low halves (one bf16 product) are checked
+to fail on the same inputs, so the test can tell them apart.
 """
 import numpy as np
 import pytest
 
 F = np.float32
-MARGIN_LO = F(1.0 - 2.0 ** -16)
+MARGIN_LO = F(1.0 - 2.0 ** -13)
 MARGIN_HI = F(1.0 + 2.0 ** -16)
 ABS = F(2.0 ** -100)
 GUARD = F(2.0 ** 125)
@@ -42,10 +44,35 @@ def _norms(v):
     return n
 
 
-def _dots(qc, pc, order):
-    """q'.p' [nq][np] in float32 with the given summation order."""
+def bf16(v):
+    """float32 -> the float32 value of its bf16 rounding (nearest even; NaN
+    to a quiet NaN, past the range to infinity), as the kernel rounds."""
+    v = np.asarray(v, F)
+    u = v.view(np.uint32).astype(np.uint64)
+    h = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    nan = (u & 0x7FFFFFFF) > 0x7F800000
+    h = np.where(nan, np.uint32(0x7FC00000), h)
+    return h.view(F)
+
+
+def split(v):
     with np.errstate(over="ignore", invalid="ignore"):
-        prod = (qc[:, None, :] * pc[None, :, :]).astype(F)  # rounded products
+        hi = bf16(v)
+        lo = bf16((v - hi).astype(F))
+    return hi, lo
+
+
+def _dots(qc, pc, order, halves=True):
+    """q'.p' [nq][np] from the bf16 splits, accumulated in float32 with the
+    given order (halves False: the high halves alone)."""
+    qh, ql = split(qc)
+    ph, pl = split(pc)
+    with np.errstate(over="ignore", invalid="ignore"):
+        terms = [(qh[:, None, :].astype(np.float64) * ph[None, :, :]).astype(F)]
+        if halves:  # products of bf16 values are exact in float32
+            terms = [(qh[:, None, :].astype(np.float64) * pl[None, :, :]).astype(F),
+                     (ql[:, None, :].astype(np.float64) * ph[None, :, :]).astype(F)] + terms
+        prod = np.concatenate(terms, axis=2)
         if order == "seq":
             acc = np.zeros(prod.shape[:2], F)
             for a in range(prod.shape[2]):
@@ -59,14 +86,14 @@ def _dots(qc, pc, order):
                 acc = (acc + (s01 + s23).astype(F)).astype(F)
             return acc
         if order == "exact":
-            e = qc.astype(np.float64) @ pc.astype(np.float64).T
-            return e.astype(F)
+            return prod.astype(np.float64).sum(axis=2).astype(F)
     raise ValueError(order)
 
 
-def marks(q, p, worst, order, centre=True, guard=True):
+def marks(q, p, worst, order, centre=True, guard=True, halves=True):
     """The filter's decision for every (query, point) pair at threshold
-    worst [nq][np] (centre / guard False: the filter without that part)."""
+    worst [nq][np] (centre / guard / halves False: the filter without that
+    part)."""
     with np.errstate(over="ignore", invalid="ignore"):
         if centre:
             c = q[0]
@@ -75,7 +102,7 @@ def marks(q, p, worst, order, centre=True, guard=True):
         else:
             qc, pc = q, p
         ns = (_norms(qc)[:, None] + _norms(pc)[None, :]).astype(F)
-        acc = _dots(qc, pc, order)
+        acc = _dots(qc, pc, order, halves)
         lhs = ((ns * MARGIN_LO).astype(F) - (F(2.0) * acc).astype(F)).astype(F)
         thr = ((worst * MARGIN_HI).astype(F) + ABS).astype(F)
         if guard:
@@ -142,3 +169,18 @@ def test_filter_without_centre_or_guard_fails_these_inputs(d):
     assert old["cloud@1"] == 0 and no_guard["cloud@1"] == 0
     assert old["cloud@1e+19"] > 0 and no_guard["cloud@1e+19"] == 0
     assert old["guard"] > 0 and no_guard["guard"] > 0
+
+
+@pytest.mark.parametrize("d", (8, 16))
+def test_filter_needs_the_low_halves(d):
+    """One bf16 product (the high halves alone, 2^-8 per operand) is far
+    outside the margin: the same inputs lose true neighbours without the
+    low halves, and lose none with them."""
+    lost = 0
+    for name, pts in _cases(d):
+        q = pts[: len(pts) // 2] if len(pts) > 8 else pts
+        p = pts[len(pts) // 2:] if len(pts) > 8 else pts
+        ex = exact_d2(q, p)
+        lost += int((~marks(q, p, ex, "seq", halves=False)).sum())
+        assert not (~marks(q, p, ex, "seq")).any()
+    assert lost > 0
