@@ -1,6 +1,7 @@
 """The matrix-core filter of the wave kNN (d = 8, 16) must never drop a
-point that belongs in the answer: it marks candidates with fp32 MFMA dot
-products and a rounding margin, and the exact float32 distances decide.
+point that belongs in the answer: it marks candidates with matrix-core dot
+products of split bf16 operands and a rounding margin, and the exact float32
+distances decide.
 These cases put the decision within a few ulps or make the norm expansion
 cancel badly; results must stay bit-identical to the oracle."""
 import numpy as np
