@@ -544,6 +544,12 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
   // 32 + ib bits only.
   int ib = 1;
   while (ib < 31 && (int64_t(1) << ib) < tr->n) ++ib;
+  // the fill reads the tree at its nodes of at most 64 points: a wave scans
+  // such a node in one step, and a ball of 10^4 points takes a quarter of
+  // the steps of 16-point leaves (whole-node and per-point tests decide the
+  // same points at any level, so the keys are the ones counted)
+  int fill_cap = 0;
+  const TreeView vfill = coarse_view(v, tr->leaf, 64, &fill_cap);
   void* stmp = nullptr;
   size_t stmp_bytes = 0;
   for (int64_t s0 = 0; s0 < nq;) {
@@ -554,7 +560,7 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
     if (total > 0) {
       k_ball_fill<D><<<(unsigned)((m + kFillWaves - 1) / kFillWaves), 64 * kFillWaves,
                        sizeof(uint32_t) * (size_t)stack_len * kFillWaves, stream>>>(
-          v, q, s0, s1, r2, off, h_off[s0], keys, stack_len, ib, metric);
+          vfill, q, s0, s1, r2, off, h_off[s0], keys, stack_len, ib, metric);
     }
     if (mode != 0) {  // only the k-th distance: selected, not sorted
       k_row_kth<<<(unsigned)m, 64, 0, stream>>>(keys, rel, rowof, s0, k, mode, ib, d_d2);

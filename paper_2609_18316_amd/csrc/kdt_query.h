@@ -25,13 +25,17 @@ struct TreeView {
 // 3.6 ms with 32-point leaves and 4.8 ms with 16-point ones.  Returns that
 // view and, in *cap, its largest node (the LDS slices' leaf capacity).
 constexpr int kCountLeaf = 32;
-inline TreeView count_view(TreeView v, int leaf, int* cap) {
+// The view at the coarsest level whose nodes hold at most `most` points.
+inline TreeView coarse_view(TreeView v, int leaf, int most, int* cap) {
   int l = v.levels;
-  while (l > 0 && ((v.n + (int64_t(1) << (l - 1)) - 1) >> (l - 1)) <= kCountLeaf) --l;
+  while (l > 0 && ((v.n + (int64_t(1) << (l - 1)) - 1) >> (l - 1)) <= most) --l;
   const int64_t big = (v.n + (int64_t(1) << l) - 1) >> l;
   *cap = big > leaf ? (int)big : leaf;
   v.levels = l;
   return v;
+}
+inline TreeView count_view(TreeView v, int leaf, int* cap) {
+  return coarse_view(v, leaf, kCountLeaf, cap);
 }
 
 // Where the wave-shared counts write CSR lists in fill mode: the indices of
