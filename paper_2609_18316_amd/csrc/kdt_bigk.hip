@@ -36,6 +36,13 @@ constexpr int kTopkMax = 16384;
 constexpr float kBigMargin = 1.1f;
 constexpr float kBigGrowMin = 1.1f;
 constexpr float kBigGrowCap = 64.0f;
+// A ball holding more than kBigShrinkAt k points and more than the 16384
+// keys a row sort holds in LDS (a query in a void whose scaled radius
+// reached a halo) shrinks once, towards kBigShrinkTo k points.
+constexpr int kBigShrinkAt = 2;
+constexpr float kBigShrinkTo = 1.3f;
+constexpr int32_t kShrunk = 1 << 30;  // flag in stuck[]
+constexpr int kBigShrinkMinK = 2048;
 
 // Queries in a spatially coherent order, pos -> row: the tree's own points
 // in tree order (self queries; rowof NULL: the rows stay in tree order) or
@@ -191,16 +198,37 @@ __global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
 // row whose count grew by less than an eighth since its last
 // round is stuck (its ball is crossing empty space, e.g. around a small
 // isolated clump): each time, its least growth is multiplied by four, up to
-// kBigGrowCap.  In the last round the radius becomes infinite.
+// kBigGrowCap.  In the last round the radius becomes infinite.  A row whose
+// ball holds more than kBigShrinkAt k points and more than `lds_keys` (the
+// row sort's LDS capacity) shrinks once (not in the last two rounds), by
+// (kBigShrinkTo k / count)^(2/d): its keys are written and selected
+// afterwards, so an oversized ball costs in proportion, and a row beyond
+// the LDS sort needs the radix select; should the smaller ball hold fewer
+// than k points, it grows again as above.  Only for k of at least
+// kBigShrinkMinK: below, few rows pass the LDS capacity and the recount
+// round costs more than it saves (10^5 queries at k = 1000: 44 -> 50 ms,
+// while k = 10^4 drops from 295 to 240 ms).
 __global__ void k_grow_radius(float* __restrict__ r2, int32_t* __restrict__ count,
                               int32_t* __restrict__ prev, int32_t* __restrict__ stuck, int64_t nq,
-                              int k, float two_over_d, float floor, int last,
+                              int k, float two_over_d, float floor, int last, int lds_keys,
                               int32_t* __restrict__ again, int32_t* __restrict__ list) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nq || count[i] >= k || isinf(r2[i])) return;
+  if (i >= nq || isinf(r2[i])) return;
+  if (count[i] >= k) {
+    const int c = count[i];
+    if (last || k < kBigShrinkMinK || c / kBigShrinkAt <= k || c <= lds_keys ||
+        (stuck[i] & kShrunk) || !(r2[i] > 0.0f))
+      return;
+    stuck[i] |= kShrunk;
+    prev[i] = 0;
+    r2[i] *= powf(kBigShrinkTo * (float)k / (float)c, two_over_d);
+    count[i] = -1;
+    list[atomicAdd(again, 1)] = (int32_t)i;
+    return;
+  }
   const int c = count[i], p = prev[i];
-  const int l = stuck[i] + (p > 0 && c - p < (p >> 3) ? 1 : 0);
-  stuck[i] = l;
+  const int l = (stuck[i] & ~kShrunk) + (p > 0 && c - p < (p >> 3) ? 1 : 0);
+  stuck[i] = (stuck[i] & kShrunk) | l;
   prev[i] = c;
   const float least = fminf(kBigGrowCap, kBigGrowMin * exp2f(2.0f * (float)l));
   const float f = c > 0 ? fmaxf(least, kBigMargin * powf((float)k / (float)c, two_over_d)) : least;
@@ -251,12 +279,85 @@ constexpr int topk_threads() {
   return P <= 1024 ? 128 : P <= 4096 ? 256 : 1024;
 }
 
+// Ascending bitonic sort of s[0, pn) (pn a power of two, 32 <= pn <= 16 T)
+// by T threads, thread t owning the run s[16 t, 16 t + 16): the steps that
+// stay inside a run (every step of the merges up to 16, and the last four of
+// each larger merge) run in registers, one LDS load and store per run; the
+// others in LDS.  65 instead of 105 LDS passes at pn = 16384.
+__device__ __forceinline__ void run16_sort(uint64_t v[16], int base) {
+#pragma unroll
+  for (int k = 2; k <= 16; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int p = q ^ j;
+        if (p > q) {
+          const bool up = ((base + q) & k) == 0;
+          const uint64_t a = v[q], c = v[p];
+          const bool sw = (a > c) == up;
+          v[q] = sw ? c : a;
+          v[p] = sw ? a : c;
+        }
+      }
+  }
+}
+
+__device__ __forceinline__ void bitonic_runs16(uint64_t* s, int pn, int tid, int T) {
+  const bool own = tid * 16 < pn;
+  uint64_t v[16];
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = s[tid * 16 + q];
+    run16_sort(v, tid * 16);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s[tid * 16 + q] = v[q];
+  }
+  __syncthreads();
+  for (int k = 32; k <= pn; k <<= 1) {
+    for (int j = k >> 1; j >= 16; j >>= 1) {
+      for (int t = tid; t < pn / 2; t += T) {
+        const int lo = 2 * t - (t & (j - 1));
+        const int hi = lo + j;
+        const uint64_t a = s[lo], c = s[hi];
+        if ((a > c) == ((lo & k) == 0)) {
+          s[lo] = c;
+          s[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+    if (own) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = s[tid * 16 + q];
+      // the rest of merge k inside the run: steps 8, 4, 2, 1, direction from bit k
+      const bool up = ((tid * 16) & k) == 0;
+#pragma unroll
+      for (int j = 8; j > 0; j >>= 1)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int p = q ^ j;
+          if (p > q) {
+            const uint64_t a = v[q], c = v[p];
+            const bool sw = (a > c) == up;
+            v[q] = sw ? c : a;
+            v[p] = sw ? a : c;
+          }
+        }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) s[tid * 16 + q] = v[q];
+    }
+    __syncthreads();
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
     const uint64_t* __restrict__ keys, const int32_t* __restrict__ rel,
     const int32_t* __restrict__ rowof, int64_t s0, int k, int ib, int32_t* __restrict__ oidx,
     float* __restrict__ od2) {
   constexpr int T = topk_threads<P>();
+  static_assert(T * 16 >= P, "a thread owns one run of 16 keys of the row");
   __shared__ uint64_t s[P];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t sh_digit, sh_rank, sh_fill;
@@ -310,20 +411,26 @@ __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
   }
   int pn = 1;
   while (pn < n) pn <<= 1;
-  for (int e = n + tid; e < pn; e += T) s[e] = ~0ull;
-  __syncthreads();
-  for (int size = 2; size <= pn; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = tid; t < pn / 2; t += T) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const uint64_t a = s[lo], c = s[hi];
-        if ((a > c) == ((lo & size) == 0)) {
-          s[lo] = c;
-          s[hi] = a;
+  if (pn >= 32) {
+    for (int e = n + tid; e < pn; e += T) s[e] = ~0ull;
+    __syncthreads();
+    bitonic_runs16(s, pn, tid, T);
+  } else {
+    for (int e = n + tid; e < pn; e += T) s[e] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= pn; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int t = tid; t < pn / 2; t += T) {
+          const int lo = 2 * t - (t & (stride - 1));
+          const int hi = lo + stride;
+          const uint64_t a = s[lo], c = s[hi];
+          if ((a > c) == ((lo & size) == 0)) {
+            s[lo] = c;
+            s[hi] = a;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   for (int j = tid; j < k; j += T) {
@@ -491,8 +598,8 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
                                                      metric);
     }
     k_grow_radius<<<gq, 256, 0, stream>>>(r2, count, prev, stuck, nq, k, 2.0f / (float)D, floor,
-                                          round + 2 >= kBigGrowRounds ? 1 : 0, again + round,
-                                          list);
+                                          round + 2 >= kBigGrowRounds ? 1 : 0, kTopkMax,
+                                          again + round, list);
     h_again = 0;
     if (hipMemcpyAsync(&h_again, again + round, sizeof(int32_t), hipMemcpyDeviceToHost,
                        stream) != hipSuccess ||
