@@ -38,10 +38,12 @@ constexpr float kBigGrowMin = 1.1f;
 constexpr float kBigGrowCap = 64.0f;
 // A ball holding more than kBigShrinkAt k points and more than the 16384
 // keys a row sort holds in LDS (a query in a void whose scaled radius
-// reached a halo) shrinks once, towards kBigShrinkTo k points.
+// reached a halo) shrinks, at most kBigShrinks times, towards kBigShrinkTo k
+// points.
 constexpr int kBigShrinkAt = 2;
 constexpr float kBigShrinkTo = 1.3f;
-constexpr int32_t kShrunk = 1 << 30;  // flag in stuck[]
+constexpr int kBigShrinks = 1;  // a second shrink cost more than it saved (k = 10^4: 239 -> 254 ms)
+constexpr int kShrinkShift = 29;  // stuck[]: shrinks done above this bit, stuck rounds below
 constexpr int kBigShrinkMinK = 2048;
 
 // Queries in a spatially coherent order, pos -> row: the tree's own points
@@ -200,7 +202,8 @@ __global__ __launch_bounds__(64 * kFillWaves) void k_ball_fill(
 // isolated clump): each time, its least growth is multiplied by four, up to
 // kBigGrowCap.  In the last round the radius becomes infinite.  A row whose
 // ball holds more than kBigShrinkAt k points and more than `lds_keys` (the
-// row sort's LDS capacity) shrinks once (not in the last two rounds), by
+// row sort's LDS capacity) shrinks, up to kBigShrinks times (not in the last
+// two rounds), by
 // (kBigShrinkTo k / count)^(2/d): its keys are written and selected
 // afterwards, so an oversized ball costs in proportion, and a row beyond
 // the LDS sort needs the radix select; should the smaller ball hold fewer
@@ -217,9 +220,9 @@ __global__ void k_grow_radius(float* __restrict__ r2, int32_t* __restrict__ coun
   if (count[i] >= k) {
     const int c = count[i];
     if (last || k < kBigShrinkMinK || c / kBigShrinkAt <= k || c <= lds_keys ||
-        (stuck[i] & kShrunk) || !(r2[i] > 0.0f))
+        (stuck[i] >> kShrinkShift) >= kBigShrinks || !(r2[i] > 0.0f))
       return;
-    stuck[i] |= kShrunk;
+    stuck[i] += 1 << kShrinkShift;
     prev[i] = 0;
     r2[i] *= powf(kBigShrinkTo * (float)k / (float)c, two_over_d);
     count[i] = -1;
@@ -227,8 +230,9 @@ __global__ void k_grow_radius(float* __restrict__ r2, int32_t* __restrict__ coun
     return;
   }
   const int c = count[i], p = prev[i];
-  const int l = (stuck[i] & ~kShrunk) + (p > 0 && c - p < (p >> 3) ? 1 : 0);
-  stuck[i] = (stuck[i] & kShrunk) | l;
+  const int32_t shrinks = stuck[i] & ~((1 << kShrinkShift) - 1);
+  const int l = (stuck[i] & ((1 << kShrinkShift) - 1)) + (p > 0 && c - p < (p >> 3) ? 1 : 0);
+  stuck[i] = shrinks | l;
   prev[i] = c;
   const float least = fminf(kBigGrowCap, kBigGrowMin * exp2f(2.0f * (float)l));
   const float f = c > 0 ? fmaxf(least, kBigMargin * powf((float)k / (float)c, two_over_d)) : least;
