@@ -136,6 +136,27 @@ def test_self_knn_and_smoothing_full_size_sampled(clustered):
     assert (od[:, 0] == 0).all()
 
 
+@pytest.mark.parametrize("k", [1000, 10_000])
+def test_large_k_full_size_sampled(clustered, k):
+    """kNN with k in the ball-and-sort range on the 2^24 clustered points: the
+    first 10^5 uniform queries (as timed) and 2000 queries on cluster points,
+    whose first candidate balls hold far more than k points and shrink once
+    before the sort; full sorted rows compared on 200 sampled queries."""
+    x, q, xt, qt, tree, ot = clustered
+    on = x[workloads.sample_indices(N, 2000, seed=9)]
+    for name, qs in (("uniform", q[:100_000]), ("in clusters", on)):
+        say(f"large k={k} of {len(qs)} {name} queries on 2^24 points")
+        gi, gd = tree.knn(to_dev(qs), k)
+        s = workloads.sample_indices(len(qs), 200, seed=10)
+        st = torch.from_numpy(s).to(gi.device)
+        hi, hd = to_host(gi[st]), to_host(gd[st])
+        del gi, gd
+        say(f"oracle tree kNN k={k} of the 200 sampled rows on {T} threads")
+        oi, od = ot.knn(qs[s], k, threads=T)
+        np.testing.assert_array_equal(hi, oi)
+        np.testing.assert_array_equal(hd, od)
+
+
 def test_fof_full_size_properties_and_sampled_components(clustered):
     x, q, xt, qt, tree, ot = clustered
     l = float(np.float32(0.2 * (1.0 / N) ** (1.0 / 3.0)))
