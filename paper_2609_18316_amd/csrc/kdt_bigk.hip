@@ -242,9 +242,42 @@ __global__ void k_grow_radius(float* __restrict__ r2, int32_t* __restrict__ coun
 }
 
 __global__ void k_chunk_offsets(const int64_t* __restrict__ off, int64_t s0, int64_t m,
-                                int32_t* __restrict__ rel) {
+                                int32_t* __restrict__ rel, uint32_t* __restrict__ ctr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i <= m) rel[i] = (int32_t)(off[s0 + i] - off[s0]);
+  if (i < 3) ctr[i] = 0u;
+}
+
+// The LDS sort a row of `have` keys takes: the smallest of the 1024, 4096
+// and 16384-key workgroup sorts holding max(k, min(have, 16384)) keys (rows
+// wider than 16384 select their k smallest first).  Classes 0, 1, 2; the
+// host and the device classify alike.
+__host__ __device__ __forceinline__ int topk_class(int64_t have, int k) {
+  const int64_t want = have < 16384 ? (have > k ? have : k) : (k > 16384 ? k : 16384);
+  return want <= 1024 ? 0 : want <= 4096 ? 1 : 2;
+}
+
+// Chunk rows listed by class: row i of class c goes to
+// rows[base[c] + slot], slots taken in any order (each row is sorted on its
+// own, so the order of a class list does not change any result), one atomic
+// per wave and class.  ctr holds three zeroed counters.
+__global__ void k_topk_classes(const int32_t* __restrict__ rel, int64_t m, int k, int64_t base1,
+                               int64_t base2, uint32_t* __restrict__ ctr,
+                               int32_t* __restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int c = i < m ? topk_class(rel[i + 1] - rel[i], k) : -1;
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const uint64_t mk = __ballot(c == cc);
+    if (!mk) continue;
+    const int lead = __ffsll((unsigned long long)mk) - 1;
+    uint32_t at = 0u;
+    if (lane == lead) at = atomicAdd(ctr + cc, (uint32_t)__popcll(mk));
+    at = __shfl(at, lead);
+    const int64_t base = cc == 0 ? 0 : cc == 1 ? base1 : base2;
+    if (c == cc) rows[base + at + __popcll(mk & ((1ull << lane) - 1ull))] = (int32_t)i;
+  }
 }
 
 // The first k sorted keys of each query of the chunk: (index, d2) pairs, or
@@ -271,8 +304,46 @@ __global__ void k_take_first(const uint64_t* __restrict__ keys, const int32_t* _
   }
 }
 
+// One wave picks the digit of a radix-select pass: given the 256-bin
+// histogram of the keys that match the digits chosen so far and the rank
+// (from 1) of the wanted key among them, the bin that holds it and the
+// number of matching keys in lower bins.  Each lane sums four bins, a
+// prefix sum over the lanes finds the first lane that reaches the rank, and
+// that lane's bins are walked.  Every lane of the wave gets the result.
+__device__ __forceinline__ void wave_pick_digit(const uint32_t* hist, int lane, uint32_t rank,
+                                                uint32_t& bin, uint32_t& below) {
+  const uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1];
+  const uint32_t c2 = hist[4 * lane + 2], c3 = hist[4 * lane + 3];
+  const uint32_t mine = c0 + c1 + c2 + c3;
+  uint32_t incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t up = __shfl_up(incl, o);
+    if (lane >= o) incl += up;
+  }
+  const int at = __ffsll((unsigned long long)__ballot(incl >= rank)) - 1;
+  uint32_t acc = __shfl(incl - mine, at);
+  const uint32_t e0 = __shfl(c0, at), e1 = __shfl(c1, at), e2 = __shfl(c2, at);
+  uint32_t b = 4u * (uint32_t)at;
+  if (acc + e0 < rank) {
+    acc += e0;
+    ++b;
+    if (acc + e1 < rank) {
+      acc += e1;
+      ++b;
+      if (acc + e2 < rank) {
+        acc += e2;
+        ++b;
+      }
+    }
+  }
+  bin = b;
+  below = acc;
+}
+
 // The k smallest keys of each row of the chunk, sorted and written as
-// (index, d2) pairs (mode 0), one workgroup per row.  The row's keys go to
+// (index, d2) pairs (mode 0), one workgroup per row: row rows[b] of the
+// chunk for workgroup b, or row b when rows is null.  The row's keys go to
 // LDS -- all of them when they fit in P, else only the k smallest, found
 // first by a radix select over the key bits, 8 bits per pass from the top
 // (keys are distinct: they end in the point index, so exactly k keys are at
@@ -358,21 +429,24 @@ __device__ __forceinline__ void bitonic_runs16(uint64_t* s, int pn, int tid, int
 template <int P>
 __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
     const uint64_t* __restrict__ keys, const int32_t* __restrict__ rel,
-    const int32_t* __restrict__ rowof, int64_t s0, int k, int ib, int32_t* __restrict__ oidx,
-    float* __restrict__ od2) {
+    const int32_t* __restrict__ rowof, const int32_t* __restrict__ rows, int64_t s0, int k,
+    int ib, int32_t* __restrict__ oidx, float* __restrict__ od2) {
   constexpr int T = topk_threads<P>();
   static_assert(T * 16 >= P, "a thread owns one run of 16 keys of the row");
   __shared__ uint64_t s[P];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t sh_digit, sh_rank, sh_fill;
   const int tid = threadIdx.x;
-  const int64_t i = blockIdx.x;
+  const int64_t i = rows ? (int64_t)rows[blockIdx.x] : (int64_t)blockIdx.x;
   const int64_t row = rowof ? (int64_t)rowof[s0 + i] : s0 + i;
   const int32_t have = rel[i + 1] - rel[i];
   const uint64_t* __restrict__ src = keys + rel[i];
+  const int lane = tid & 63;
+  const int bits = 32 + ib;
+  int kp = 32;  // the sort size k keys need
+  while (kp < k) kp <<= 1;
   int n = have;
   if (have > P) {
-    const int bits = 32 + ib;
     uint64_t prefix = 0ull, mask = 0ull;
     uint32_t rank = (uint32_t)k;  // rank of the wanted key among those matching prefix
     for (int shift = (bits - 1) / 8 * 8; shift >= 0; shift -= 8) {
@@ -383,18 +457,13 @@ __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
         if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
       }
       __syncthreads();
-      if (tid == 0) {
-        uint32_t acc = 0u;
-        int dsel = 255;
-        for (int dg = 0; dg < 256; ++dg) {
-          if (acc + hist[dg] >= rank) {
-            dsel = dg;
-            break;
-          }
-          acc += hist[dg];
+      if (tid < 64) {
+        uint32_t bin, below;
+        wave_pick_digit(hist, tid, rank, bin, below);
+        if (tid == 0) {
+          sh_digit = bin;
+          sh_rank = rank - below;
         }
-        sh_digit = (uint32_t)dsel;
-        sh_rank = rank - acc;
       }
       __syncthreads();
       prefix |= (uint64_t)sh_digit << shift;
@@ -410,6 +479,65 @@ __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
       if (key <= prefix) s[atomicAdd(&sh_fill, 1u)] = key;
     }
     n = k;
+  } else if (have > kp) {
+    // More keys than the sort of k needs: the same digit passes over the
+    // keys held in registers, stopped as soon as the keys at or below the
+    // chosen digits' range number at most kp (all of them after the last
+    // pass, when that range is the k-th key alone); only those are sorted.
+    constexpr int R = P / T;
+    uint64_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int e = tid + j * T;
+      v[j] = e < have ? src[e] : ~0ull;  // ~0 is no key: its d2 bits would be a NaN
+    }
+    uint64_t prefix = 0ull, mask = 0ull, bound = 0ull;
+    uint32_t rank = (uint32_t)k, base = 0u;  // base: keys below the chosen range
+    for (int shift = (bits - 1) / 8 * 8; shift >= 0; shift -= 8) {
+      for (int j = tid; j < 256; j += T) hist[j] = 0u;
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if (v[j] != ~0ull && (v[j] & mask) == prefix)
+          atomicAdd(&hist[(uint32_t)(v[j] >> shift) & 255u], 1u);
+      __syncthreads();
+      if (tid < 64) {
+        uint32_t bin, below;
+        wave_pick_digit(hist, tid, rank, bin, below);
+        if (tid == 0) {
+          sh_digit = bin;
+          sh_rank = rank - below;
+          sh_fill = below + hist[bin];
+        }
+      }
+      __syncthreads();
+      const uint32_t kept = base + sh_fill;  // keys at or below the range's top
+      base += rank - sh_rank;
+      rank = sh_rank;
+      prefix |= (uint64_t)sh_digit << shift;
+      mask |= 255ull << shift;
+      __syncthreads();  // every thread has read sh_* and hist before they change
+      if (kept <= (uint32_t)kp || shift == 0) {  // uniform over the workgroup
+        bound = prefix | ((1ull << shift) - 1ull);
+        n = (int)kept;
+        break;
+      }
+    }
+    if (tid == 0) sh_fill = 0u;
+    __syncthreads();
+    // the kept keys to s[0, n), one LDS atomic per wave and register slot
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const bool keep = v[j] != ~0ull && v[j] <= bound;
+      const uint64_t m = __ballot(keep);
+      if (m) {
+        const int lead = __ffsll((unsigned long long)m) - 1;
+        uint32_t at = 0u;
+        if (lane == lead) at = atomicAdd(&sh_fill, (uint32_t)__popcll(m));
+        at = __shfl(at, lead);
+        if (keep) s[at + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = v[j];
+      }
+    }
   } else {
     for (int32_t e = tid; e < have; e += T) s[e] = src[e];
   }
@@ -474,32 +602,8 @@ __global__ __launch_bounds__(64) void k_row_kth(const uint64_t* __restrict__ key
       if ((v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
     }
     __syncthreads();
-    const uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1];
-    const uint32_t c2 = hist[4 * lane + 2], c3 = hist[4 * lane + 3];
-    const uint32_t mine = c0 + c1 + c2 + c3;
-    uint32_t incl = mine;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t up = __shfl_up(incl, o);
-      if (lane >= o) incl += up;
-    }
-    // the first lane whose bins reach the rank, then the bin within it
-    const int at = __ffsll((unsigned long long)__ballot(incl >= rank)) - 1;
-    uint32_t acc = __shfl(incl - mine, at);
-    const uint32_t e0 = __shfl(c0, at), e1 = __shfl(c1, at), e2 = __shfl(c2, at);
-    uint32_t bin = 4u * (uint32_t)at;
-    if (acc + e0 < rank) {
-      acc += e0;
-      ++bin;
-      if (acc + e1 < rank) {
-        acc += e1;
-        ++bin;
-        if (acc + e2 < rank) {
-          acc += e2;
-          ++bin;
-        }
-      }
-    }
+    uint32_t bin, acc;
+    wave_pick_digit(hist, lane, rank, bin, acc);
     rank -= acc;
     prefix |= bin << shift;
     mask |= 255u << shift;
@@ -642,10 +746,11 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
   uint64_t* keys = nullptr;
   uint64_t* sorted = nullptr;
   int32_t* rel = nullptr;
+  uint32_t* cls_ctr = nullptr;
   const int64_t biggest = std::min(cap, h_off[nq]);
   if (!buf.get(&keys, (size_t)std::max<int64_t>(biggest, 1)) ||
       !buf.get(&sorted, (size_t)std::max<int64_t>(biggest, 1)) ||
-      !buf.get(&rel, (size_t)nq + 1)) {
+      !buf.get(&rel, (size_t)nq + 1) || !buf.get(&cls_ctr, 4)) {
     kdt_set_error("kdt_knn: device allocation failed for the large-k keys");
     return KDT_ENOMEM;
   }
@@ -667,7 +772,7 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
     int64_t s1 = s0 + 1;
     while (s1 < nq && h_off[s1 + 1] - h_off[s0] <= cap) ++s1;
     const int64_t m = s1 - s0, total = h_off[s1] - h_off[s0];
-    k_chunk_offsets<<<(unsigned)((m + 256) / 256), 256, 0, stream>>>(off, s0, m, rel);
+    k_chunk_offsets<<<(unsigned)((m + 256) / 256), 256, 0, stream>>>(off, s0, m, rel, cls_ctr);
     if (total > 0) {
       k_ball_fill<D><<<(unsigned)((m + kFillWaves - 1) / kFillWaves), 64 * kFillWaves,
                        sizeof(uint32_t) * (size_t)stack_len * kFillWaves, stream>>>(
@@ -679,18 +784,28 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
       continue;
     }
     if (k <= kTopkMax) {  // rows sorted in LDS, the k smallest written directly
-      int64_t widest = 0;
-      for (int64_t r = s0; r < s1; ++r) widest = std::max(widest, h_off[r + 1] - h_off[r]);
-      const int64_t want = std::max<int64_t>(k, std::min<int64_t>(widest, kTopkMax));
-      if (want <= 1024)
-        k_row_topk<1024><<<(unsigned)m, topk_threads<1024>(), 0, stream>>>(keys, rel, rowof, s0, k,
-                                                                            ib, d_idx, d_d2);
-      else if (want <= 4096)
-        k_row_topk<4096><<<(unsigned)m, topk_threads<4096>(), 0, stream>>>(keys, rel, rowof, s0, k,
-                                                                            ib, d_idx, d_d2);
-      else
-        k_row_topk<kTopkMax><<<(unsigned)m, topk_threads<kTopkMax>(), 0, stream>>>(
-            keys, rel, rowof, s0, k, ib, d_idx, d_d2);
+      // Each row takes the smallest workgroup sort that holds it: a few wide
+      // rows no longer move every row of the chunk to the 1024-thread sort,
+      // whose 128 KiB of LDS leave one workgroup per CU.
+      int64_t cnt[3] = {0, 0, 0};
+      for (int64_t r = s0; r < s1; ++r) ++cnt[topk_class(h_off[r + 1] - h_off[r], k)];
+      const int used = (cnt[0] > 0) + (cnt[1] > 0) + (cnt[2] > 0);
+      int32_t* cls_rows = list;  // the grown-row list is no longer needed
+      if (used > 1)
+        k_topk_classes<<<(unsigned)((m + 255) / 256), 256, 0, stream>>>(
+            rel, m, k, cnt[0], cnt[0] + cnt[1], cls_ctr, cls_rows);
+      const int32_t* r0 = used > 1 ? cls_rows : nullptr;
+      const int32_t* r1 = used > 1 ? cls_rows + cnt[0] : nullptr;
+      const int32_t* r2l = used > 1 ? cls_rows + cnt[0] + cnt[1] : nullptr;
+      if (cnt[0] > 0)
+        k_row_topk<1024><<<(unsigned)cnt[0], topk_threads<1024>(), 0, stream>>>(
+            keys, rel, rowof, r0, s0, k, ib, d_idx, d_d2);
+      if (cnt[1] > 0)
+        k_row_topk<4096><<<(unsigned)cnt[1], topk_threads<4096>(), 0, stream>>>(
+            keys, rel, rowof, r1, s0, k, ib, d_idx, d_d2);
+      if (cnt[2] > 0)
+        k_row_topk<kTopkMax><<<(unsigned)cnt[2], topk_threads<kTopkMax>(), 0, stream>>>(
+            keys, rel, rowof, r2l, s0, k, ib, d_idx, d_d2);
       s0 = s1;
       continue;
     }
