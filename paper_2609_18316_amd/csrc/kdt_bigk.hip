@@ -343,22 +343,34 @@ __device__ __forceinline__ void wave_pick_digit(const uint32_t* hist, int lane, 
 
 // The k smallest keys of each row of the chunk, sorted and written as
 // (index, d2) pairs (mode 0), one workgroup per row: row rows[b] of the
-// chunk for workgroup b, or row b when rows is null.  The row's keys go to
-// LDS -- all of them when they fit in P, else only the k smallest, found
-// first by a radix select over the key bits, 8 bits per pass from the top
-// (keys are distinct: they end in the point index, so exactly k keys are at
-// or below the k-th) -- and are sorted there by a bitonic network over the
-// next power of two, padded with all-ones keys.  Needs k <= P.
+// chunk for workgroup b, or row b when rows is null.  A row of at most kp
+// keys (kp: the power of two at or above k, at least 32) goes to LDS whole.
+// A longer row first bounds its k smallest by a radix select over the key
+// bits, 8 bits per pass from the top, each pass a histogram of the keys that
+// match the digits chosen so far; the passes stop once the keys at or below
+// the chosen range number at most kp (after the last pass that range is the
+// k-th key alone: keys are distinct, they end in the point index).  Rows of
+// up to R T keys hold them in registers for this; longer rows read them from
+// global memory each pass.  The kept keys go to LDS, and are sorted there by
+// a bitonic network over the next power of two, padded with all-ones keys.
+// Needs k <= P.
 template <int P>
 constexpr int topk_threads() {
   return P <= 1024 ? 128 : P <= 4096 ? 256 : 1024;
 }
 
-// Ascending bitonic sort of s[0, pn) (pn a power of two, 32 <= pn <= 16 T)
-// by T threads, thread t owning the run s[16 t, 16 t + 16): the steps that
-// stay inside a run (every step of the merges up to 16, and the last four of
-// each larger merge) run in registers, one LDS load and store per run; the
-// others in LDS.  65 instead of 105 LDS passes at pn = 16384.
+// Key i of a row sort lives at LDS slot pad16(i): one unused slot after
+// every 16 keys, so the runs of 16 that neighbouring lanes load start 17
+// keys (34 banks) apart and a wave's run loads spread over all the banks,
+// where unpadded they would all fall on the same few.
+__host__ __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
+// Ascending bitonic sort of keys [0, pn) (pn a power of two, 32 <= pn <= 16
+// T; key i at s[pad16(i)]) by T threads, thread t owning the run of keys
+// [16 t, 16 t + 16): the steps that stay inside a run (every step of the
+// merges up to 16, and the last four of each larger merge) run in registers,
+// one LDS load and store per run; the others in LDS.  65 instead of 105 LDS
+// passes at pn = 16384.
 __device__ __forceinline__ void run16_sort(uint64_t v[16], int base) {
 #pragma unroll
   for (int k = 2; k <= 16; k <<= 1) {
@@ -383,10 +395,10 @@ __device__ __forceinline__ void bitonic_runs16(uint64_t* s, int pn, int tid, int
   uint64_t v[16];
   if (own) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = s[tid * 16 + q];
+    for (int q = 0; q < 16; ++q) v[q] = s[tid * 17 + q];
     run16_sort(v, tid * 16);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s[tid * 16 + q] = v[q];
+    for (int q = 0; q < 16; ++q) s[tid * 17 + q] = v[q];
   }
   __syncthreads();
   for (int k = 32; k <= pn; k <<= 1) {
@@ -394,17 +406,17 @@ __device__ __forceinline__ void bitonic_runs16(uint64_t* s, int pn, int tid, int
       for (int t = tid; t < pn / 2; t += T) {
         const int lo = 2 * t - (t & (j - 1));
         const int hi = lo + j;
-        const uint64_t a = s[lo], c = s[hi];
+        const uint64_t a = s[pad16(lo)], c = s[pad16(hi)];
         if ((a > c) == ((lo & k) == 0)) {
-          s[lo] = c;
-          s[hi] = a;
+          s[pad16(lo)] = c;
+          s[pad16(hi)] = a;
         }
       }
       __syncthreads();
     }
     if (own) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = s[tid * 16 + q];
+      for (int q = 0; q < 16; ++q) v[q] = s[tid * 17 + q];
       // the rest of merge k inside the run: steps 8, 4, 2, 1, direction from bit k
       const bool up = ((tid * 16) & k) == 0;
 #pragma unroll
@@ -420,7 +432,7 @@ __device__ __forceinline__ void bitonic_runs16(uint64_t* s, int pn, int tid, int
           }
         }
 #pragma unroll
-      for (int q = 0; q < 16; ++q) s[tid * 16 + q] = v[q];
+      for (int q = 0; q < 16; ++q) s[tid * 17 + q] = v[q];
     }
     __syncthreads();
   }
@@ -433,7 +445,7 @@ __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
     int ib, int32_t* __restrict__ oidx, float* __restrict__ od2) {
   constexpr int T = topk_threads<P>();
   static_assert(T * 16 >= P, "a thread owns one run of 16 keys of the row");
-  __shared__ uint64_t s[P];
+  __shared__ uint64_t s[P + P / 16];  // key i at s[pad16(i)]
   __shared__ uint32_t hist[256];
   __shared__ uint32_t sh_digit, sh_rank, sh_fill;
   const int tid = threadIdx.x;
@@ -445,61 +457,37 @@ __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
   const int bits = 32 + ib;
   int kp = 32;  // the sort size k keys need
   while (kp < k) kp <<= 1;
+  // keys per thread in registers: the 16384-key sort (1024 threads, one
+  // workgroup per CU) holds rows of up to 32768
+  constexpr int R = P >= 16384 ? 32 : P / T;
   int n = have;
-  if (have > P) {
-    uint64_t prefix = 0ull, mask = 0ull;
-    uint32_t rank = (uint32_t)k;  // rank of the wanted key among those matching prefix
-    for (int shift = (bits - 1) / 8 * 8; shift >= 0; shift -= 8) {
-      for (int j = tid; j < 256; j += T) hist[j] = 0u;
-      __syncthreads();
-      for (int32_t e = tid; e < have; e += T) {
-        const uint64_t key = src[e];
-        if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
-      }
-      __syncthreads();
-      if (tid < 64) {
-        uint32_t bin, below;
-        wave_pick_digit(hist, tid, rank, bin, below);
-        if (tid == 0) {
-          sh_digit = bin;
-          sh_rank = rank - below;
-        }
-      }
-      __syncthreads();
-      prefix |= (uint64_t)sh_digit << shift;
-      mask |= 255ull << shift;
-      rank = sh_rank;
-      __syncthreads();  // every thread has read sh_digit before the next pass
-    }
-    // prefix is the k-th smallest key: the keys at or below it are exactly k
-    if (tid == 0) sh_fill = 0u;
-    __syncthreads();
-    for (int32_t e = tid; e < have; e += T) {
-      const uint64_t key = src[e];
-      if (key <= prefix) s[atomicAdd(&sh_fill, 1u)] = key;
-    }
-    n = k;
-  } else if (have > kp) {
-    // More keys than the sort of k needs: the same digit passes over the
-    // keys held in registers, stopped as soon as the keys at or below the
-    // chosen digits' range number at most kp (all of them after the last
-    // pass, when that range is the k-th key alone); only those are sorted.
-    constexpr int R = P / T;
+  uint64_t bound = 0ull;  // the kept keys are those at or below it
+  if (have > kp) {
+    const bool in_regs = have <= R * T;
     uint64_t v[R];
+    if (in_regs) {
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int e = tid + j * T;
-      v[j] = e < have ? src[e] : ~0ull;  // ~0 is no key: its d2 bits would be a NaN
+      for (int j = 0; j < R; ++j) {
+        const int e = tid + j * T;
+        v[j] = e < have ? src[e] : ~0ull;  // ~0 is no key: its d2 bits would be a NaN
+      }
     }
-    uint64_t prefix = 0ull, mask = 0ull, bound = 0ull;
+    uint64_t prefix = 0ull, mask = 0ull;
     uint32_t rank = (uint32_t)k, base = 0u;  // base: keys below the chosen range
     for (int shift = (bits - 1) / 8 * 8; shift >= 0; shift -= 8) {
       for (int j = tid; j < 256; j += T) hist[j] = 0u;
       __syncthreads();
+      if (in_regs) {
 #pragma unroll
-      for (int j = 0; j < R; ++j)
-        if (v[j] != ~0ull && (v[j] & mask) == prefix)
-          atomicAdd(&hist[(uint32_t)(v[j] >> shift) & 255u], 1u);
+        for (int j = 0; j < R; ++j)
+          if (v[j] != ~0ull && (v[j] & mask) == prefix)
+            atomicAdd(&hist[(uint32_t)(v[j] >> shift) & 255u], 1u);
+      } else {
+        for (int32_t e = tid; e < have; e += T) {
+          const uint64_t key = src[e];
+          if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+        }
+      }
       __syncthreads();
       if (tid < 64) {
         uint32_t bin, below;
@@ -525,40 +513,48 @@ __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
     }
     if (tid == 0) sh_fill = 0u;
     __syncthreads();
-    // the kept keys to s[0, n), one LDS atomic per wave and register slot
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const bool keep = v[j] != ~0ull && v[j] <= bound;
+    // the kept keys to s[0, n), one LDS atomic per wave and step
+    const auto put = [&](uint64_t key) {
+      const bool keep = key != ~0ull && key <= bound;
       const uint64_t m = __ballot(keep);
       if (m) {
         const int lead = __ffsll((unsigned long long)m) - 1;
         uint32_t at = 0u;
         if (lane == lead) at = atomicAdd(&sh_fill, (uint32_t)__popcll(m));
         at = __shfl(at, lead);
-        if (keep) s[at + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = v[j];
+        if (keep) s[pad16((int)(at + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))))] = key;
+      }
+    };
+    if (in_regs) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) put(v[j]);
+    } else {
+      for (int32_t j = 0; j < (have + T - 1) / T; ++j) {  // the same trip count on every lane
+        const int32_t e = tid + j * T;
+        put(e < have ? src[e] : ~0ull);
       }
     }
   } else {
-    for (int32_t e = tid; e < have; e += T) s[e] = src[e];
+    for (int32_t e = tid; e < have; e += T) s[pad16(e)] = src[e];
   }
   int pn = 1;
   while (pn < n) pn <<= 1;
   if (pn >= 32) {
-    for (int e = n + tid; e < pn; e += T) s[e] = ~0ull;
+    for (int e = n + tid; e < pn; e += T) s[pad16(e)] = ~0ull;
     __syncthreads();
     bitonic_runs16(s, pn, tid, T);
   } else {
-    for (int e = n + tid; e < pn; e += T) s[e] = ~0ull;
+    for (int e = n + tid; e < pn; e += T) s[pad16(e)] = ~0ull;
     __syncthreads();
     for (int size = 2; size <= pn; size <<= 1) {
       for (int stride = size >> 1; stride > 0; stride >>= 1) {
         for (int t = tid; t < pn / 2; t += T) {
           const int lo = 2 * t - (t & (stride - 1));
           const int hi = lo + stride;
-          const uint64_t a = s[lo], c = s[hi];
+          const uint64_t a = s[pad16(lo)], c = s[pad16(hi)];
           if ((a > c) == ((lo & size) == 0)) {
-            s[lo] = c;
-            s[hi] = a;
+            s[pad16(lo)] = c;
+            s[pad16(hi)] = a;
           }
         }
         __syncthreads();
@@ -567,7 +563,7 @@ __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
   }
   for (int j = tid; j < k; j += T) {
     const bool empty = j >= n;
-    const uint64_t key = empty ? 0ull : s[j];
+    const uint64_t key = empty ? 0ull : s[pad16(j)];
     if (oidx) oidx[row * k + j] = empty ? -1 : (int32_t)(key & ((1ull << ib) - 1ull));
     od2[row * k + j] = empty ? INFINITY : __uint_as_float((uint32_t)(key >> ib));
   }
