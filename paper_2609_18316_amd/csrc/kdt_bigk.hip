@@ -19,6 +19,7 @@
 #include <cmath>
 #include <vector>
 
+#include "kdt_bitonic.h"
 #include "kdt_packet.h"
 #include "kdt_torus.h"
 
@@ -359,85 +360,6 @@ constexpr int topk_threads() {
   return P <= 1024 ? 128 : P <= 4096 ? 256 : 1024;
 }
 
-// Key i of a row sort lives at LDS slot pad16(i): one unused slot after
-// every 16 keys, so the runs of 16 that neighbouring lanes load start 17
-// keys (34 banks) apart and a wave's run loads spread over all the banks,
-// where unpadded they would all fall on the same few.
-__host__ __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
-
-// Ascending bitonic sort of keys [0, pn) (pn a power of two, 32 <= pn <= 16
-// T; key i at s[pad16(i)]) by T threads, thread t owning the run of keys
-// [16 t, 16 t + 16): the steps that stay inside a run (every step of the
-// merges up to 16, and the last four of each larger merge) run in registers,
-// one LDS load and store per run; the others in LDS.  65 instead of 105 LDS
-// passes at pn = 16384.
-__device__ __forceinline__ void run16_sort(uint64_t v[16], int base) {
-#pragma unroll
-  for (int k = 2; k <= 16; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int p = q ^ j;
-        if (p > q) {
-          const bool up = ((base + q) & k) == 0;
-          const uint64_t a = v[q], c = v[p];
-          const bool sw = (a > c) == up;
-          v[q] = sw ? c : a;
-          v[p] = sw ? a : c;
-        }
-      }
-  }
-}
-
-__device__ __forceinline__ void bitonic_runs16(uint64_t* s, int pn, int tid, int T) {
-  const bool own = tid * 16 < pn;
-  uint64_t v[16];
-  if (own) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = s[tid * 17 + q];
-    run16_sort(v, tid * 16);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) s[tid * 17 + q] = v[q];
-  }
-  __syncthreads();
-  for (int k = 32; k <= pn; k <<= 1) {
-    for (int j = k >> 1; j >= 16; j >>= 1) {
-      for (int t = tid; t < pn / 2; t += T) {
-        const int lo = 2 * t - (t & (j - 1));
-        const int hi = lo + j;
-        const uint64_t a = s[pad16(lo)], c = s[pad16(hi)];
-        if ((a > c) == ((lo & k) == 0)) {
-          s[pad16(lo)] = c;
-          s[pad16(hi)] = a;
-        }
-      }
-      __syncthreads();
-    }
-    if (own) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = s[tid * 17 + q];
-      // the rest of merge k inside the run: steps 8, 4, 2, 1, direction from bit k
-      const bool up = ((tid * 16) & k) == 0;
-#pragma unroll
-      for (int j = 8; j > 0; j >>= 1)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int p = q ^ j;
-          if (p > q) {
-            const uint64_t a = v[q], c = v[p];
-            const bool sw = (a > c) == up;
-            v[q] = sw ? c : a;
-            v[p] = sw ? a : c;
-          }
-        }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) s[tid * 17 + q] = v[q];
-    }
-    __syncthreads();
-  }
-}
-
 template <int P>
 __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
     const uint64_t* __restrict__ keys, const int32_t* __restrict__ rel,
@@ -541,7 +463,6 @@ __global__ __launch_bounds__(topk_threads<P>()) void k_row_topk(
   while (pn < n) pn <<= 1;
   if (pn >= 32) {
     for (int e = n + tid; e < pn; e += T) s[pad16(e)] = ~0ull;
-    __syncthreads();
     bitonic_runs16(s, pn, tid, T);
   } else {
     for (int e = n + tid; e < pn; e += T) s[pad16(e)] = ~0ull;

@@ -6,8 +6,8 @@
 //                     a bitonic network over the lanes (shuffles), sized to
 //                     the next power of two of the row;
 //   <= kSmallMax      in LDS by the same 64-lane workgroup (bitonic);
-//   <= kMidMax        by a 1024-lane workgroup: runs of 16 in registers,
-//                     then LDS (bitonic; 64 KiB);
+//   <= kMidMax        by a 1024-lane workgroup: bitonic over LDS (68 KiB),
+//                     the steps inside each lane's run of 16 in registers;
 //   longer            the library's LSD radix sort over the concatenation of
 //                     those rows, ordered by (row, entry): with one composite
 //                     key (row rank above the entry's bits) when both fit in
@@ -23,6 +23,7 @@
 #include <cstdint>
 
 #include "kdt.h"
+#include "kdt_bitonic.h"
 #include "kdt_debug.h"
 #include "kdt_internal.h"
 
@@ -110,61 +111,25 @@ __global__ __launch_bounds__(64) void k_rows_small(const int32_t* __restrict__ i
   }
 }
 
-// A mid row per workgroup: each thread first sorts a run of 16 entries in
-// registers (the bitonic stages up to 16, directions taken from the entries'
-// positions), then the stages from 32 on run in LDS.
+// A mid row per workgroup: the entries go to LDS (padded, one slot after
+// every 16), then the workgroup bitonic sort whose steps inside a thread's
+// run of 16 run in registers.
 __global__ __launch_bounds__(kMidThreads) void k_rows_mid(const int32_t* __restrict__ in,
                                                           int32_t* __restrict__ out,
                                                           const int64_t* __restrict__ off,
                                                           const uint32_t* __restrict__ ctr,
                                                           const int32_t* __restrict__ rows) {
-  __shared__ int32_t s[kMidMax];
+  static_assert(kMidMax <= 16 * kMidThreads, "a thread owns one run of 16 entries of a row");
+  __shared__ int32_t s[kMidMax + kMidMax / 16];  // entry i at s[pad16(i)]
   const uint32_t m = ctr[0];
   const int t = threadIdx.x;
   for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
     const int64_t r = rows[i];
     const int64_t b = off[r], L = off[r + 1] - b;
     const int P = max(pow2_at_least(L), 32);  // mid rows hold more than kSmallMax entries
-    if (t < P / 16) {
-      int32_t v[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int64_t e = (int64_t)t * 16 + q;
-        v[q] = e < L ? in[b + e] : INT_MAX;
-      }
-#pragma unroll
-      for (int k = 2; k <= 16; k <<= 1)
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1)
-#pragma unroll
-          for (int q = 0; q < 16; ++q) {
-            const int p = q ^ j;
-            if (p > q) {
-              const bool up = ((t * 16 + q) & k) == 0;
-              const int32_t a = v[q], c = v[p];
-              const bool sw = (a > c) == up;
-              v[q] = sw ? c : a;
-              v[p] = sw ? a : c;
-            }
-          }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) s[t * 16 + q] = v[q];
-    }
-    __syncthreads();
-    for (int k = 32; k <= P; k <<= 1)
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int x = t; x < (P >> 1); x += kMidThreads) {
-          const int lo = ((x & ~(j - 1)) << 1) | (x & (j - 1));
-          const int hi = lo + j;
-          const int32_t a = s[lo], c = s[hi];
-          if ((a > c) == ((lo & k) == 0)) {
-            s[lo] = c;
-            s[hi] = a;
-          }
-        }
-        __syncthreads();
-      }
-    for (int e = t; e < L; e += kMidThreads) out[b + e] = s[e];
+    for (int e = t; e < P; e += kMidThreads) s[pad16(e)] = e < L ? in[b + e] : INT_MAX;
+    bitonic_runs16(s, P, t, kMidThreads);
+    for (int e = t; e < L; e += kMidThreads) out[b + e] = s[pad16(e)];
     __syncthreads();
   }
 }
