@@ -26,9 +26,12 @@
 namespace kdt {
 
 constexpr int kLBlock = 128;
-constexpr int64_t kBigKeysPerChunk = int64_t(1) << 27;  // 1 GiB of keys
+// Keys per chunk (8 GiB): each chunk's fill and sort launches wait for their
+// widest rows, so fewer, larger chunks keep more rows in flight (at k = 10^4
+// the balls average about 28 000 keys: 4800 rows per chunk of 2^27 keys)
+constexpr int64_t kBigKeysPerChunk = int64_t(1) << 30;
 constexpr int kBigGrowRounds = 24;  // then the radius becomes infinite
-// Largest k sorted in LDS (128 KiB of keys per workgroup; gfx950 gives a
+// Largest k sorted in LDS (16384 keys, 136 KiB with the padding slots, per workgroup; gfx950 gives a
 // workgroup up to 160 KiB); larger k takes the segmented radix sort.
 constexpr int kTopkMax = 16384;
 // Margin on estimated squared radii (x 1.1^(d/2) expected points), the least
@@ -665,8 +668,9 @@ static kdt_status knn_large_impl(const kdt_tree* tr, const float* d_q, int64_t n
   int32_t* rel = nullptr;
   uint32_t* cls_ctr = nullptr;
   const int64_t biggest = std::min(cap, h_off[nq]);
+  const bool radix_rows = mode == 0 && k > kTopkMax;  // the segmented radix sort's output
   if (!buf.get(&keys, (size_t)std::max<int64_t>(biggest, 1)) ||
-      !buf.get(&sorted, (size_t)std::max<int64_t>(biggest, 1)) ||
+      (radix_rows && !buf.get(&sorted, (size_t)std::max<int64_t>(biggest, 1))) ||
       !buf.get(&rel, (size_t)nq + 1) || !buf.get(&cls_ctr, 4)) {
     kdt_set_error("kdt_knn: device allocation failed for the large-k keys");
     return KDT_ENOMEM;
