@@ -163,3 +163,26 @@ def test_large_k_rows_beyond_the_lds_sort():
             np.testing.assert_array_equal(to_host(gi), oi)
             np.testing.assert_array_equal(to_host(gd), od)
         t.close()
+
+
+def test_large_k_rows_beyond_the_register_select():
+    """Rows of more than 32768 candidate keys, more than the widest row sort
+    holds in registers: the select reads them from global memory each digit
+    pass and stops once the kept keys fit the sort.  40000 coincident points
+    (every key ties on distance: the passes go down into the index bits) and
+    a tight cluster of 40000 seen from afar (the whole cluster is in every
+    ball, distinct distances); k = 1000, 9000 and 16384."""
+    dev()
+    rng = np.random.Generator(np.random.PCG64(78))
+    same = np.full((40000, 3), 0.25, np.float32)
+    tight = (0.5 + 1e-3 * rng.standard_normal((40000, 3))).astype(np.float32)
+    far = np.array([[0.9, 0.1, 0.2], [0.05, 0.95, 0.5], [0.5, 0.5, 0.98]], np.float32)
+    for x, q in ((same, np.concatenate([same[:4], far])), (tight, far)):
+        t = kdt.build(to_dev(x), leaf_size=32)
+        for k in (1000, 9000, 16384):
+            say(f"large k={k} on {len(x)} points, every ball holding all of them")
+            oi, od = oracle.knn_brute(x, q, k)
+            gi, gd = t.knn(to_dev(q), k)
+            np.testing.assert_array_equal(to_host(gi), oi)
+            np.testing.assert_array_equal(to_host(gd), od)
+        t.close()
